@@ -61,6 +61,10 @@ def lib():
     L.oracle_angle_cdf.restype = d
     L.oracle_angle_icdf.argtypes = [d, d]
     L.oracle_angle_icdf.restype = d
+    L.oracle_angle_icdf_v.argtypes = [d, d]
+    L.oracle_angle_icdf_v.restype = d
+    L.oracle_angle_cdf_v.argtypes = [d, d]
+    L.oracle_angle_cdf_v.restype = d
     L.oracle_sample_plain.argtypes = [dp, dp, i64, dp, dp]
     L.oracle_sample_plain.restype = None
     L.oracle_pair_invariants.argtypes = [dp, dp, dp, dp]
@@ -135,6 +139,15 @@ def angle_cdf(mu, x):
 
 def angle_icdf(u, x):
     return lib().oracle_angle_icdf(float(u), float(x))
+
+
+def angle_icdf_v(u, x):
+    """v = 1 - mu solving F(1 - v; x) = u (relative precision for forward scatters)."""
+    return lib().oracle_angle_icdf_v(float(u), float(x))
+
+
+def angle_cdf_v(v, x):
+    return lib().oracle_angle_cdf_v(float(v), float(x))
 
 
 def sample_plain(x, u):

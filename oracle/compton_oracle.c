@@ -173,6 +173,27 @@ static double series_partial_integral(double x, double v0)
     return sum;
 }
 
+/* int_{1-v}^{1} f dmu by the same series, integrated term by term over
+ * w = 1 - mu in [0, v]:
+ *   sum_k (-x)^k [ A_k v^{k+1}/(k+1) - 2(k+1) v^{k+2}/(k+2) + (k+1) v^{k+3}/(k+3) ];
+ * every term is small with v, so the upper tail keeps relative precision for
+ * forward scatters (mu -> 1). */
+static double series_upper_integral(double x, double v)
+{
+    double sum = 0.0, xk = 1.0, v_k1 = v;
+    for (int k = 0; k < SERIES_TERMS; ++k) {
+        double A = (double)(k + 1) * (double)(k + 2) / 2.0 + 1.0;
+        double v_k2 = v_k1 * v, v_k3 = v_k2 * v;
+        double term = xk * (A * v_k1 / (double)(k + 1) - 2.0 * (double)(k + 1) * v_k2 / (double)(k + 2) +
+                            (double)(k + 1) * v_k3 / (double)(k + 3));
+        sum += term;
+        if (k > 2 && fabs(term) <= 1e-20 * fabs(sum)) break;
+        xk *= -x;
+        v_k1 *= v;
+    }
+    return sum;
+}
+
 /* G(a) with dG/da = f expressed in a (closed form antiderivative). */
 static quad closed_G(quad a, quad x)
 {
@@ -201,45 +222,83 @@ double oracle_angle_pdf(double mu, double x)
     return f / (8.0 / 3.0 * oracle_sigma_ratio(x));
 }
 
-/* CDF F(mu; x) of the rest-frame scattering cosine. */
-double oracle_angle_cdf(double mu, double x)
+/* CDF of the rest-frame scattering cosine written in v = 1 - mu:
+ * F(1 - v; x) = int_{-1}^{1-v} f / int_{-1}^{1} f, decreasing in v. */
+double oracle_angle_cdf_v(double v, double x)
 {
-    if (mu <= -1.0) return 0.0;
-    if (mu >= 1.0) return 1.0;
+    if (v >= 2.0) return 0.0;
+    if (v <= 0.0) return 1.0;
     if (x < 0.2) {
         double total = series_partial_integral(x, 0.0);
-        return series_partial_integral(x, 1.0 - mu) / total;
+        return series_partial_integral(x, v) / total;
     }
-    quad X = x, a = 1 + X * (1 - (quad)mu), amax = 1 + 2 * X;
+    quad X = x, a = 1 + X * (quad)v, amax = 1 + 2 * X;
     quad num = closed_G(amax, X) - closed_G(a, X);
     quad den = closed_G(amax, X) - closed_G((quad)1, X);
     return (double)(num / den);
 }
 
-/* Inverse CDF by plain bisection on [-1, 1] down to adjacent doubles. */
-double oracle_angle_icdf(double u, double x)
+/* CDF F(mu; x) of the rest-frame scattering cosine. */
+double oracle_angle_cdf(double mu, double x)
 {
-    double lo = -1.0, hi = 1.0;
-    for (int it = 0; it < 2000; ++it) {
+    if (mu <= -1.0) return 0.0;
+    if (mu >= 1.0) return 1.0;
+    return oracle_angle_cdf_v(1.0 - mu, x);
+}
+
+/* Upper tail 1 - F(1 - v; x), increasing in v, with relative precision at
+ * small v. */
+double oracle_angle_upper_v(double v, double x)
+{
+    if (v <= 0.0) return 0.0;
+    if (v >= 2.0) return 1.0;
+    if (x < 0.2) return series_upper_integral(x, v) / series_partial_integral(x, 0.0);
+    quad X = x, a = 1 + X * (quad)v, amax = 1 + 2 * X;
+    quad num = closed_G(a, X) - closed_G((quad)1, X);
+    quad den = closed_G(amax, X) - closed_G((quad)1, X);
+    return (double)(num / den);
+}
+
+/* Inverse CDF solved for v = 1 - mu (the scattering angle's natural variable:
+ * forward scatters, mu -> 1, keep full relative precision in v and hence in
+ * sin(theta) = sqrt(v (2 - v))), by plain bisection on [0, 2] down to
+ * adjacent doubles.  For u >= 1/2 the bisection compares the upper tail with
+ * 1 - u (exact for 53-bit uniforms), otherwise F with u. */
+double oracle_angle_icdf_v(double u, double x)
+{
+    double lo = 0.0, hi = 2.0;
+    const int upper = u >= 0.5;
+    const double one_minus_u = 1.0 - u;
+    for (int it = 0; it < 4000; ++it) {
         double mid = 0.5 * (lo + hi);
-        if (mid <= lo || mid >= hi || hi - lo <= 1e-17) break;
-        if (oracle_angle_cdf(mid, x) < u)
+        if (mid <= lo || mid >= hi || hi - lo <= 1e-17 * hi) break;
+        int v_too_small = upper ? oracle_angle_upper_v(mid, x) < one_minus_u : oracle_angle_cdf_v(mid, x) > u;
+        if (v_too_small)
             lo = mid;
         else
             hi = mid;
     }
-    double flo = oracle_angle_cdf(lo, x), fhi = oracle_angle_cdf(hi, x);
-    return (u - flo <= fhi - u) ? lo : hi;
+    double elo, ehi;
+    if (upper) {
+        elo = one_minus_u - oracle_angle_upper_v(lo, x);
+        ehi = oracle_angle_upper_v(hi, x) - one_minus_u;
+    } else {
+        elo = oracle_angle_cdf_v(lo, x) - u;
+        ehi = u - oracle_angle_cdf_v(hi, x);
+    }
+    return (elo <= ehi) ? lo : hi;
 }
+
+double oracle_angle_icdf(double u, double x) { return 1.0 - oracle_angle_icdf_v(u, x); }
 
 /* Plain sampler over arrays: mu = F^-1(u; x), r = eps'/eps = 1/(1 + x(1 - mu)). */
 void oracle_sample_plain(const double* x, const double* u, int64_t n, double* mu_out, double* ratio_out)
 {
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) {
-        double mu = oracle_angle_icdf(u[i], x[i]);
-        mu_out[i] = mu;
-        ratio_out[i] = 1.0 / (1.0 + x[i] * (1.0 - mu));
+        double v = oracle_angle_icdf_v(u[i], x[i]);
+        mu_out[i] = 1.0 - v;
+        ratio_out[i] = 1.0 / (1.0 + x[i] * v);
     }
 }
 
@@ -302,15 +361,15 @@ void oracle_pair_invariants(const double p_in[3], const double k_in[3], double* 
 }
 
 /* One resolved collision: given the pre-collision electron p and photon k,
- * the rest-frame scattering cosine mu and azimuth phi, compute the outgoing
- * electron p1 and photon k1 (lab frame):
+ * the rest-frame scattering angle through v = 1 - cos(theta) and the azimuth
+ * phi = 2 pi u_phi, compute the outgoing electron p1 and photon k1 (lab):
  *   1. boost the photon to the electron rest frame: energy x, direction n;
- *   2. scatter about n by (mu, phi) with the Compton shift x1 = x/(1+x(1-mu));
+ *   2. scatter about n by (theta, phi) with the Compton shift x1 = x/(1+x v);
  *   3. boost the scattered photon back with the same (pre-collision) p;
  *   4. the electron takes p + k - k1 (momentum conservation).
  * Energies before/after are returned for the conservation check. */
-void oracle_scatter_event(const double p_in[3], const double k_in[3], double mu, double u_phi,
-                          double p_out[3], double k_out[3], double* e_before, double* e_after)
+static void scatter_event_v(const double p_in[3], const double k_in[3], quad V, double u_phi, double p_out[3],
+                            double k_out[3], double* e_before, double* e_after)
 {
     quad p[3] = {p_in[0], p_in[1], p_in[2]}, k[3] = {k_in[0], k_in[1], k_in[2]};
     quad gamma = sqrtq(1 + dot3(p, p));
@@ -320,12 +379,12 @@ void oracle_scatter_event(const double p_in[3], const double k_in[3], double mu,
     quad kr_norm = sqrtq(dot3(kr, kr));
     for (int i = 0; i < 3; ++i) n[i] = kr[i] / kr_norm;
     onb(n, e1, e2);
-    quad Mu = mu;
-    quad sin_theta = sqrtq((1 - Mu) * (1 + Mu));
+    quad Mu = 1 - V;
+    quad sin_theta = sqrtq(V * (2 - V));
     quad phi = 2 * M_PIq * (quad)u_phi;
     quad cphi = cosq(phi), sphi = sinq(phi);
     for (int i = 0; i < 3; ++i) d[i] = Mu * n[i] + sin_theta * (cphi * e1[i] + sphi * e2[i]);
-    quad x1 = x / (1 + x * (1 - Mu));
+    quad x1 = x / (1 + x * V);
     for (int i = 0; i < 3; ++i) q1[i] = x1 * d[i];
     quad eps1 = boost_to_lab(p, gamma, q1, x1, k1);
     for (int i = 0; i < 3; ++i) p1[i] = p[i] + k[i] - k1[i];
@@ -335,6 +394,13 @@ void oracle_scatter_event(const double p_in[3], const double k_in[3], double mu,
     }
     if (e_before) *e_before = (double)(gamma + eps);
     if (e_after) *e_after = (double)(sqrtq(1 + dot3(p1, p1)) + eps1);
+}
+
+/* The same with the scattering cosine mu given directly. */
+void oracle_scatter_event(const double p_in[3], const double k_in[3], double mu, double u_phi,
+                          double p_out[3], double k_out[3], double* e_before, double* e_after)
+{
+    scatter_event_v(p_in, k_in, 1 - (quad)mu, u_phi, p_out, k_out, e_before, e_after);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -431,9 +497,9 @@ static void process_cell(int dtype, void* const E[4], void* const G[4], int64_t 
         draw(seed, (uint64_t)ie, step, PURPOSE_SCATTER, s);
         double u_mu = oracle_uniform53(s[0], s[1]);
         double u_phi = oracle_uniform53(s[2], s[3]);
-        double mu = oracle_angle_icdf(u_mu, x);
+        double v = oracle_angle_icdf_v(u_mu, x);
         double p1[3], k1[3], eb, ea;
-        oracle_scatter_event(p, k, mu, u_phi, p1, k1, &eb, &ea);
+        scatter_event_v(p, k, (quad)v, u_phi, p1, k1, &eb, &ea);
         t->energy_before += eb;
         t->energy_after += ea;
         /* Weight rule: the lighter macro-particle always scatters, the heavier
