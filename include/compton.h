@@ -1,0 +1,189 @@
+/*
+ * compton.h -- C ABI of libcompton.so: the per-pair Compton-scattering
+ * Monte-Carlo step of a particle-in-cell code and the small network that
+ * stands in for its inverse-CDF angle/energy sampler, on AMD MI355X (gfx950).
+ *
+ * Method (Badiali, Bilbao, Cruz, Silva, "Machine Learning-based models in
+ * particle-in-cell codes for advanced physics extensions"):
+ *   Sec. 3.1  particles are binned into collision cells and paired inside each
+ *             cell; for every pair the interaction probability is compared
+ *             with a random number; accepted collisions are resolved and both
+ *             momenta updated.
+ *   Sec. 3.2  the probability is a function of the macro-particle weights,
+ *             momenta and a normalisation factor: the photon is boosted into
+ *             the lepton rest frame, the Klein-Nishina cross-section is
+ *             evaluated there and the rate is carried back to the lab frame;
+ *             P_max = 2 sigma_T c dt max[w_e, w_gamma] bounds it.
+ *   Sec. 2    a network object is loaded once and then run on any batch of
+ *             inputs; Sec. 4: it can also be trained inside the simulation.
+ *
+ * Units: momenta in m_e c, energies in m_e c^2.  Cross-sections enter as
+ * s(x) = sigma_KN(x) / sigma_T with x the rest-frame photon energy.
+ *
+ * Conventions shared by every call:
+ *   - Every pointer to particle, offset, input or output data is DEVICE memory
+ *     owned by the caller; it must stay valid until the work queued on
+ *     `stream` has completed.  Particle arrays are updated in place.
+ *   - Calls only queue work on `stream` (a hipStream_t passed as void*; NULL
+ *     is the default stream) and return without synchronising, except the
+ *     calls documented as synchronous.
+ *   - Every call returns a cs_status; on failure nothing is queued and
+ *     cs_last_error() describes the reason.  No C++ exception crosses the ABI.
+ *   - Physical anomalies are not errors: they are counted in cs_stats.
+ *   - One context per host thread and stream; contexts are not thread-safe.
+ */
+#ifndef COMPTON_H
+#define COMPTON_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CS_OK = 0,
+    CS_ERR_INVALID_ARG = 1, /* null pointer, bad size, dt <= 0, bad enum ...      */
+    CS_ERR_LAYOUT = 2,      /* cell offsets not a valid layout (cs_check_layout) */
+    CS_ERR_UNSUPPORTED = 3, /* valid request this build does not handle         */
+    CS_ERR_HIP = 4,         /* the HIP runtime reported an error                */
+    CS_ERR_IO = 5,          /* file missing, unreadable or corrupt              */
+    CS_ERR_NOT_READY = 6    /* MLP sampler requested without a usable network   */
+} cs_status;
+
+/* Storage type of particle and sampler arrays.  Arithmetic is FP64 either way. */
+typedef enum { CS_F32 = 0, CS_F64 = 1 } cs_dtype;
+
+/* Angle/energy sampler used for accepted collisions. */
+typedef enum {
+    CS_SAMPLER_PLAIN = 0,    /* inverse CDF of the Klein-Nishina angular law, FP64 */
+    CS_SAMPLER_MLP_F32 = 1,  /* network, FP32 arithmetic                          */
+    CS_SAMPLER_MLP_BF16 = 2, /* network, BF16 MFMA hidden layers, FP32 accumulate */
+    CS_SAMPLER_MLP_FP8 = 3   /* network, FP8 E4M3 MFMA, per-layer scales          */
+} cs_sampler;
+
+typedef enum { CS_LOSS_MSE = 0, CS_LOSS_MAE = 1 } cs_loss;
+
+typedef struct cs_ctx cs_ctx;
+typedef struct cs_mlp cs_mlp;
+
+/* One particle species as structure of arrays: x, y, z momentum components
+ * (m_e c) and macro-particle weight w, each n elements of the call's dtype. */
+typedef struct {
+    void* x;
+    void* y;
+    void* z;
+    void* w;
+    int64_t n;
+} cs_species;
+
+/* Per-step counters and sums, written to device memory by cs_compton_step.
+ * 128 bytes. */
+typedef struct {
+    int64_t n_pairs;      /* candidate pairs formed                              */
+    int64_t n_collided;   /* pairs with u < P                                    */
+    int64_t n_clipped;    /* pairs whose P exceeded 1 and was clipped to 1       */
+    int64_t n_invalid;    /* pairs skipped: non-finite input or negative weight  */
+    int64_t n_fallback;   /* MLP sampler only: samples outside the network's x   */
+                          /* range, resolved by the plain sampler                */
+    int64_t layout_error; /* 1 when the offsets were not a valid layout; then    */
+                          /* no particle was touched                             */
+    int64_t reserved_i[2];
+    double sum_prob;      /* sum of P over valid pairs (fixed summation order)   */
+    double energy_before; /* sum over collided pairs of gamma + eps before       */
+    double energy_after;  /* ... and gamma' + eps' after (pre-storage rounding)  */
+    double reserved_d[5];
+} cs_stats;
+
+/* ---------------------------------------------------------------- lifecycle */
+
+/* Create a context on HIP device `device` (its workspace grows on demand). */
+cs_status cs_create(cs_ctx** out, int device);
+cs_status cs_destroy(cs_ctx* ctx);
+/* Text of the last failure on this context (never NULL; "" after success).
+ * With ctx == NULL: the last failure of cs_create. */
+const char* cs_last_error(const cs_ctx* ctx);
+/* Synchronous: wait for `stream` and report any asynchronous HIP error. */
+cs_status cs_sync(cs_ctx* ctx, void* stream);
+
+/* ------------------------------------------------------------ the step ---- */
+
+/*
+ * cs_compton_step -- one Monte-Carlo Compton step over every collision cell.
+ *
+ * Particles are sorted by cell: cell c owns electrons [off_e[c], off_e[c+1])
+ * and photons [off_g[c], off_g[c+1]).  off_e / off_g are int64 device arrays
+ * of n_cells + 1 entries; a valid layout starts at 0, never decreases and ends
+ * at the species count.  An invalid layout is detected on the device: the step
+ * then touches no particle and sets stats->layout_error (use cs_check_layout
+ * for a synchronous check).
+ *
+ * Per cell with N_e electrons and N_g photons, min(N_e, N_g) pairs are formed:
+ * the smaller species in storage order, the larger one through a keyed
+ * pseudo-random bijection of its [0, N) drawn per (seed, cell, step), so no
+ * particle is in two pairs.  With N_max = max(N_e, N_g), each pair collides
+ * with probability
+ *     P = dt * density_norm * N_max * max(w_e, w_g) * s(x) * (1 - beta . k_hat)
+ * (clipped to 1), where density_norm = sigma_T c / V_cell in the caller's
+ * units; P <= 2 dt density_norm N_max max(w) is the paper's P_max.
+ * An accepted pair takes its rest-frame scattering cosine from `sampler`
+ * (PLAIN: the inverse Klein-Nishina CDF), conserves momentum exactly
+ * (p' = p + k - k'), and is written back in place; with unequal weights the
+ * lighter particle always moves and the heavier with probability
+ * w_min / w_max.  Random numbers come from Philox4x32-10 keyed by `seed`,
+ * with counters built from (particle or cell index, step, purpose), so a
+ * step is a pure function of (state, seed, step).
+ *
+ * dtype:   storage type of all eight particle arrays.
+ * sampler: CS_SAMPLER_PLAIN with mlp == NULL, or an MLP sampler with a
+ *          network prepared by cs_mlp_quantize for that precision.
+ * stats:   nullable device pointer to one cs_stats, overwritten.
+ * Errors:  CS_ERR_INVALID_ARG (null arrays with n > 0, n_cells < 0,
+ *          dt <= 0 or non-finite, density_norm < 0, bad enums),
+ *          CS_ERR_UNSUPPORTED (a species count >= 2^31),
+ *          CS_ERR_NOT_READY (MLP sampler without prepared weights).
+ */
+cs_status cs_compton_step(cs_ctx* ctx, cs_dtype dtype, cs_species electrons, cs_species photons,
+                          const int64_t* off_e, const int64_t* off_g, int64_t n_cells, double dt,
+                          double density_norm, uint64_t seed, uint64_t step, cs_sampler sampler,
+                          const cs_mlp* mlp, cs_stats* stats, void* stream);
+
+/* Synchronous layout check of device offsets: CS_OK or CS_ERR_LAYOUT. */
+cs_status cs_check_layout(cs_ctx* ctx, const int64_t* off, int64_t n_cells, int64_t n_particles,
+                          void* stream);
+
+/*
+ * cs_sample_plain -- the conventional sampler on its own: for each i,
+ * mu[i] = F^-1(u[i]; x[i]) with F the CDF of the rest-frame scattering cosine
+ * under the Klein-Nishina law, and ratio[i] = eps'/eps = 1/(1 + x(1 - mu)).
+ * Arrays of n elements of `dtype` (FP64 arithmetic either way); x >= 0,
+ * u in [0, 1).  Used for training targets and the sampler-stage benchmark.
+ */
+cs_status cs_sample_plain(cs_ctx* ctx, cs_dtype dtype, const void* x, const void* u, int64_t n,
+                          void* mu_out, void* ratio_out, void* stream);
+
+/* ------------------------------------------------------- measurement ---- */
+
+/* Stages of cs_compton_step, in order. */
+typedef enum {
+    CS_STAGE_PREP = 0,     /* offsets check, pairs per cell, scans, chunk map   */
+    CS_STAGE_PAIR = 1,     /* pairing, x, s(x), P, accept, compaction           */
+    CS_STAGE_COMPACT = 2,  /* offsets of the accepted pairs                     */
+    CS_STAGE_COLLIDE = 3,  /* sampling, scattering, write-back                  */
+    CS_STAGE_FINALIZE = 4, /* stats reduction                                   */
+    CS_STAGE_COUNT = 5
+} cs_stage;
+
+/* Enable (1) or disable (0) per-stage timing: while enabled, every
+ * cs_compton_step records HIP events between its stages on its stream
+ * (the Sec. 3.3 stage breakdown of the paper, measured on the device). */
+cs_status cs_set_stage_timing(cs_ctx* ctx, int enable);
+/* Synchronous: wait for the last timed step and write up to n stage
+ * durations in milliseconds (index = cs_stage); *n_written gets the count. */
+cs_status cs_stage_times(cs_ctx* ctx, float* ms_out, int32_t n, int32_t* n_written);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* COMPTON_H */

@@ -1,0 +1,358 @@
+// cs_device.h -- device-side arithmetic of the Compton step for gfx950.
+//
+// Counter-based random numbers, the in-cell pairing bijection, the
+// Klein-Nishina cross-section and angular CDF, the inverse-CDF sampler and
+// the rest-frame/lab kinematics.  All physics arithmetic is FP64 and written
+// in forms free of catastrophic cancellation for gamma >> 1 (the Lorentz
+// boosts and back-transforms), so that a FP32-stored plasma loses nothing
+// beyond its storage rounding.
+//
+// Units: momenta in m_e c, energies in m_e c^2, s(x) = sigma_KN / sigma_T.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cs {
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of the 4x32
+// S-box, key advanced by the Weyl constants between rounds.
+// ---------------------------------------------------------------------------
+struct u32x4 {
+    uint32_t a, b, c, d;
+};
+
+__device__ __forceinline__ u32x4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                          uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t m0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t m1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = (uint32_t)(m1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(m0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)m1;
+        c3 = (uint32_t)m0;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return {c0, c1, c2, c3};
+}
+
+// Stream purposes (fourth counter word, low byte).
+enum : uint32_t { kPair = 1, kCollide = 2, kScatter = 3 };
+
+// counter = (index lo, index hi, step lo, step hi << 8 | purpose), key = seed.
+__device__ __forceinline__ u32x4 draw(uint64_t seed, uint64_t index, uint64_t step, uint32_t purpose) {
+    return philox10((uint32_t)index, (uint32_t)(index >> 32), (uint32_t)step,
+                    ((uint32_t)(step >> 32) << 8) | purpose, (uint32_t)seed, (uint32_t)(seed >> 32));
+}
+
+// 53-bit uniform in [0, 1): top 27 bits of a, top 26 bits of b.
+__device__ __forceinline__ double uniform53(uint32_t a, uint32_t b) {
+    return ((double)(a >> 5) * 67108864.0 + (double)(b >> 6)) * 0x1p-53;
+}
+
+// ---------------------------------------------------------------------------
+// In-cell pairing: 4-round balanced Feistel network over 2h bits
+// (2h >= ceil(log2 M)) with cycle-walking into [0, M) (Black & Rogaway 2002).
+// Round function: MurmurHash3's 32-bit finaliser of (right half ^ key word).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t fmix32(uint32_t h) {
+    h ^= h >> 16;
+    h *= 0x85EBCA6Bu;
+    h ^= h >> 13;
+    h *= 0xC2B2AE35u;
+    h ^= h >> 16;
+    return h;
+}
+
+struct FeistelKey {
+    uint32_t k[4];
+    uint32_t half_bits;  // h
+};
+
+__device__ __forceinline__ uint32_t ceil_log2(uint32_t M) { return M <= 1 ? 0u : 32u - __clz(M - 1u); }
+
+// The cycle-walk always ends: i lies on a cycle of the permutation of
+// [0, 2^{2h}), and that cycle returns to i, which is < M.
+__device__ __forceinline__ uint32_t shuffle_index(uint32_t i, uint32_t M, const FeistelKey& key) {
+    if (M <= 1u) return 0u;
+    const uint32_t h = key.half_bits;
+    const uint32_t mask = (1u << h) - 1u;
+    uint32_t v = i;
+    do {
+        uint32_t L = v >> h, R = v & mask;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const uint32_t f = fmix32(R ^ key.k[r]) & mask;
+            const uint32_t nR = L ^ f;
+            L = R;
+            R = nR;
+        }
+        v = (L << h) | R;
+    } while (v >= M);
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// Klein-Nishina.  With a = 1 + x(1 - mu) the rest-frame angular density is
+// f(mu) = a^-3 + a^-1 - (1 - mu^2) a^-2 (unnormalised), and
+// s(x) = (3/8) int_{-1}^{1} f dmu.
+// ---------------------------------------------------------------------------
+
+// Taylor coefficients of s(x) about 0, from integrating the binomial series
+// of a^-n term by term:
+//   c_k = (3/8) (-1)^k 2^{k+1} [ (k+2)/2 + 1/(k+1) - 4(k+1)/((k+2)(k+3)) ].
+// Radius of convergence 1/2; |c_k| x^k ~ (3/8) k (2x)^k, so 48 terms reach
+// round-off for x < 0.2.
+constexpr int kSeriesTerms = 48;
+constexpr double kSeriesSwitch = 0.2;
+
+struct Coeffs {
+    double c[kSeriesTerms];
+};
+
+constexpr Coeffs sigma_series_coeffs() {
+    Coeffs r{};
+    double two = 2.0;  // 2^{k+1}
+    for (int k = 0; k < kSeriesTerms; ++k) {
+        const double kk = (double)k;
+        const double br = (kk + 2.0) / 2.0 + 1.0 / (kk + 1.0) - 4.0 * (kk + 1.0) / ((kk + 2.0) * (kk + 3.0));
+        r.c[k] = 0.375 * ((k & 1) ? -two : two) * br;
+        two *= 2.0;
+    }
+    return r;
+}
+
+// Series of the upper tail of the angular integral (v = 1 - mu, t = x v):
+//   int_{mu}^{1} f = v [ P1(t) - 2 v P2(t) + v^2 P3(t) ],
+//   P1 = sum (-t)^k ((k+1)(k+2)/2 + 1)/(k+1),  P2 = sum (-t)^k (k+1)/(k+2),
+//   P3 = sum (-t)^k (k+1)/(k+3).
+// t <= 2x < 0.4 in the series branch; 48 terms reach round-off.
+struct TailCoeffs {
+    double p1[kSeriesTerms], p2[kSeriesTerms], p3[kSeriesTerms];
+};
+
+constexpr TailCoeffs tail_series_coeffs() {
+    TailCoeffs r{};
+    for (int k = 0; k < kSeriesTerms; ++k) {
+        const double kk = (double)k;
+        const double sgn = (k & 1) ? -1.0 : 1.0;
+        r.p1[k] = sgn * (((kk + 1.0) * (kk + 2.0) / 2.0 + 1.0) / (kk + 1.0));
+        r.p2[k] = sgn * ((kk + 1.0) / (kk + 2.0));
+        r.p3[k] = sgn * ((kk + 1.0) / (kk + 3.0));
+    }
+    return r;
+}
+
+__constant__ constexpr Coeffs kSigma = sigma_series_coeffs();
+__constant__ constexpr TailCoeffs kTail = tail_series_coeffs();
+
+// The table pointer is passed through an empty asm so that the compiler
+// re-reads the coefficients (scalar loads) on every call instead of hoisting
+// a whole table into vector registers across the sampler's Newton loop.
+__device__ __forceinline__ double horner(const double* c, double x) {
+    asm volatile("" : "+s"(c));
+    double acc = c[kSeriesTerms - 1];
+#pragma unroll
+    for (int k = kSeriesTerms - 2; k >= 0; --k) acc = fma(acc, x, c[k]);
+    return acc;
+}
+
+// s(x) = sigma_KN(x) / sigma_T.
+__device__ __forceinline__ double sigma_ratio(double x) {
+    if (x < kSeriesSwitch) return horner(kSigma.c, x);
+    const double l = log1p(2.0 * x);
+    const double opx = 1.0 + x, o2x = 1.0 + 2.0 * x;
+    return 0.75 * (opx / (x * x * x) * (2.0 * x * opx / o2x - l) + l / (2.0 * x) - (1.0 + 3.0 * x) / (o2x * o2x));
+}
+
+// Unnormalised angular density f at mu = 1 - v, for x >= 0.
+__device__ __forceinline__ double angle_density_v(double v, double x) {
+    const double a = 1.0 + x * v;
+    const double ia = 1.0 / a;
+    return ia * ia * ia + ia - v * (2.0 - v) * ia * ia;
+}
+
+// int_{1 - v}^{1} f dmu (upper tail), for 0 <= v <= 2.
+//   series branch (x < 0.2): as above;
+//   closed branch: with a = 1 + x v and G' = f in a,
+//   (1/x)[G(a) - G(1)] = (1/x)[ x v (2 + x v) / (2 a^2) + log1p(x v)
+//                        - (-(x v) + (2x+2) log1p(x v) - (2x+1) x v / a) / x^2 ].
+__device__ __forceinline__ double angle_tail(double v, double x) {
+    if (x < kSeriesSwitch) {
+        const double t = x * v;
+        const double P1 = horner(kTail.p1, t);
+        const double P2 = horner(kTail.p2, t);
+        const double P3 = horner(kTail.p3, t);
+        return v * (P1 - 2.0 * v * P2 + v * v * P3);
+    }
+    const double xv = x * v;
+    const double a = 1.0 + xv;
+    const double L = log1p(xv);
+    const double g = xv * (2.0 + xv) / (2.0 * a * a) + L -
+                     (-xv + (2.0 * x + 2.0) * L - (2.0 * x + 1.0) * xv / a) / (x * x);
+    return g / x;
+}
+
+// Thomson-limit inverse (x -> 0): root of (mu^3 + 3 mu + 4)/8 = u by Cardano.
+__device__ __forceinline__ double thomson_root(double u) {
+    const double q = 4.0 * u - 2.0;
+    const double r = sqrt(q * q + 1.0);
+    return cbrt(q + r) + cbrt(q - r);
+}
+
+// Inverse CDF of the rest-frame scattering angle, returned as v = 1 - mu so
+// that forward scatters (mu -> 1) keep relative precision: the v with
+// tail(v) = (1 - u) tail(2).  Newton in v, safeguarded by a bisection bracket,
+// from the Thomson root (x < 1/2) or, for x >= 1/2, from the inverse of the
+// large-x approximation F ~ ln((1+2x)/a) / ln(1+2x), a = 1 + x v.  A step
+// below 1e-10 v is accepted and ends the iteration (quadratic convergence
+// leaves the error at the tail's round-off); an exact zero residual ends it
+// too.  At most 4 steps are needed for x in [0, 1e3].
+__device__ __forceinline__ double angle_icdf_v(double u, double x) {
+    const double Z = angle_tail(2.0, x);
+    const double target = (1.0 - u) * Z;  // 1 - u is exact for u = k 2^-53
+    double lo = 0.0, hi = 2.0;
+    double v = x < 0.5 ? 1.0 - thomson_root(u) : expm1((1.0 - u) * log1p(2.0 * x)) / x;
+    v = fmin(fmax(v, 0.0), 2.0);
+    for (int it = 0; it < 60; ++it) {
+        const double R = angle_tail(v, x) - target;  // > 0: v too large
+        if (R == 0.0) break;
+        if (R > 0.0)
+            hi = v;
+        else
+            lo = v;
+        double next = v - R / angle_density_v(v, x);
+        if (fabs(next - v) <= 1e-10 * next) {
+            v = next;
+            break;
+        }
+        if (!(next > lo && next < hi)) next = 0.5 * (lo + hi);
+        v = next;
+        if (hi - lo <= 1e-16 * hi) break;
+    }
+    return fmin(fmax(v, 0.0), 2.0);
+}
+
+// ---------------------------------------------------------------------------
+// Kinematics (FP64, cancellation-free forms)
+// ---------------------------------------------------------------------------
+struct d3 {
+    double x, y, z;
+};
+
+__device__ __forceinline__ double dot(d3 a, d3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ d3 cross(d3 a, d3 b) {
+    return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+__device__ __forceinline__ d3 axpy(double a, d3 x, d3 y) { return {fma(a, x.x, y.x), fma(a, x.y, y.y), fma(a, x.z, y.z)}; }
+__device__ __forceinline__ d3 scale(double a, d3 x) { return {a * x.x, a * x.y, a * x.z}; }
+
+struct PairInv {
+    double gamma, eps, x, flux;  // x = gamma eps - p.k (rest-frame photon energy)
+};
+
+// x = gamma eps - p.k; for p.k > 0 use x = (eps^2 + |p x k|^2)/(gamma eps + p.k)
+// (gamma^2 eps^2 - (p.k)^2 = eps^2 + |p x k|^2), which has no cancellation.
+// flux = 1 - beta . k_hat = x / (gamma eps).
+__device__ __forceinline__ PairInv pair_invariants(d3 p, d3 k) {
+    PairInv r;
+    r.gamma = sqrt(1.0 + dot(p, p));
+    r.eps = sqrt(dot(k, k));
+    if (r.eps == 0.0) {
+        r.x = 0.0;
+        r.flux = 0.0;
+        return r;
+    }
+    const double pk = dot(p, k);
+    const double ge = r.gamma * r.eps;
+    if (pk <= 0.0) {
+        r.x = ge - pk;
+    } else {
+        const d3 c = cross(p, k);
+        r.x = (r.eps * r.eps + dot(c, c)) / (ge + pk);
+    }
+    r.flux = r.x / ge;
+    return r;
+}
+
+struct Scattered {
+    d3 p1, k1;
+    double e_before, e_after;
+};
+
+// Resolve one collision.  Rest frame of the electron (velocity p/gamma):
+// photon direction n from the decomposition of k along p_hat (perpendicular
+// part unchanged, parallel part gamma k_par - |p| eps written without
+// cancellation); scattered direction d = mu n + sin(theta)(cos(phi) e1 +
+// sin(phi) e2) about the Duff et al. (JCGT 2017) orthonormal basis of n,
+// with v = 1 - mu and sin(theta) = sqrt(v (2 - v));
+// Compton shift x1 = x / (1 + x v); back-boost with the pre-collision
+// p (parallel part x1 (gamma c + |p|), again cancellation-free); the
+// electron takes p + k - k1.
+__device__ __forceinline__ Scattered scatter(d3 p, d3 k, const PairInv& inv, double v, double u_phi) {
+    const double gamma = inv.gamma, eps = inv.eps, x = inv.x;
+    const double pp2 = dot(p, p);
+    const double pp = sqrt(pp2);
+    d3 n, ph;
+    const bool moving = pp > 0.0;
+    if (moving) {
+        ph = scale(1.0 / pp, p);
+        const double kpar = dot(k, ph);
+        const d3 kperp = axpy(-kpar, ph, k);
+        double kpar_r;
+        if (kpar <= 0.0) {
+            kpar_r = gamma * kpar - pp * eps;
+        } else {
+            const d3 c = cross(ph, k);
+            kpar_r = (eps * eps - gamma * gamma * dot(c, c)) / (gamma * kpar + pp * eps);
+        }
+        n = axpy(kpar_r, ph, kperp);
+    } else {
+        ph = {0.0, 0.0, 0.0};
+        n = k;
+    }
+    const double nn = 1.0 / sqrt(dot(n, n));
+    n = scale(nn, n);
+    // orthonormal basis (Duff et al. 2017)
+    const double s = n.z >= 0.0 ? 1.0 : -1.0;
+    const double a = -1.0 / (s + n.z);
+    const double b = n.x * n.y * a;
+    const d3 e1 = {1.0 + s * n.x * n.x * a, s * b, -s * n.x};
+    const d3 e2 = {b, s + n.y * n.y * a, -n.y};
+    double sphi, cphi;
+    sincospi(2.0 * u_phi, &sphi, &cphi);
+    const double mu = 1.0 - v;
+    const double st = sqrt(v * (2.0 - v));
+    d3 d = scale(mu, n);
+    d = axpy(st * cphi, e1, d);
+    d = axpy(st * sphi, e2, d);
+    const double x1 = x / (1.0 + x * v);
+    d3 k1;
+    if (moving) {
+        const double c = dot(d, ph);
+        const d3 dperp = axpy(-c, ph, d);
+        double par;
+        if (c >= 0.0) {
+            par = x1 * (gamma * c + pp);
+        } else {
+            const d3 cr = cross(ph, d);
+            par = x1 * (1.0 - gamma * gamma * dot(cr, cr)) / (gamma * c - pp);
+        }
+        k1 = axpy(par, ph, scale(x1, dperp));
+    } else {
+        k1 = scale(x1, d);
+    }
+    Scattered r;
+    r.k1 = k1;
+    r.p1 = {(p.x + k.x) - k1.x, (p.y + k.y) - k1.y, (p.z + k.z) - k1.z};
+    r.e_before = gamma + eps;
+    r.e_after = sqrt(1.0 + dot(r.p1, r.p1)) + sqrt(dot(k1, k1));
+    return r;
+}
+
+}  // namespace cs
