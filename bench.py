@@ -30,6 +30,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="grid", choices=["grid", "single_cell", "uneven", "power_law", "grid_large"])
     ap.add_argument("--sampler", default="plain")
+    ap.add_argument("--strategy", default="fused", choices=["fused", "compact", "multi_kernel"])
+    ap.add_argument("--chunks-per-block", type=int, default=0, help="fused strategy; 0 = automatic")
+    ap.add_argument("--sweep", action="store_true", help="time every strategy / chunks-per-block candidate")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     return ap.parse_args()
@@ -72,6 +75,34 @@ def cpu_baseline(p, seconds):
                       f"plasma, {elapsed:.1f} s"}
 
 
+def sweep(ctx, p, args):
+    """Time each kernel strategy on the same initial state (printed as JSON
+    lines tagged "sweep"); the measured line that follows uses the options
+    given on the command line."""
+    import torch
+
+    from paper_2206_02937_amd import compton
+
+    cands = [("compact", 0), ("multi_kernel", 0)] + [("fused", g) for g in (2, 4, 8, 16)]
+    for strategy, gpb in cands:
+        ctx.set_strategy(strategy)
+        ctx.set_chunks_per_block(gpb)
+        e, g, oe, og = compton.to_device(p)
+        for s in range(3):
+            ctx.step(e, g, oe, og, p.dt, p.density_norm, p.seed, s, sampler=args.sampler)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        n = 50
+        for s in range(3, 3 + n):
+            ctx.step(e, g, oe, og, p.dt, p.density_norm, p.seed, s, sampler=args.sampler)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / n
+        print(json.dumps({"sweep": True, "strategy": strategy, "chunks_per_block": gpb, "ms_per_step": dt * 1e3,
+                          "pairs_per_s": p.n_pairs / dt}), flush=True)
+    ctx.set_strategy(args.strategy)
+    ctx.set_chunks_per_block(args.chunks_per_block)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -86,6 +117,10 @@ def main():
     p = plasma.make(args.workload, seed=0)
     n_pairs = p.n_pairs
     ctx = compton.Context(0)
+    ctx.set_strategy(args.strategy)
+    ctx.set_chunks_per_block(args.chunks_per_block)
+    if args.sweep:
+        sweep(ctx, p, args)
     e, g, oe, og = compton.to_device(p)
     stats = ctx.stats_buffer()
     step = 0
@@ -128,8 +163,21 @@ def main():
     # entry and both particles and writes 6 values per accepted pair
     pair_bytes = n_pairs * 8 * sb + acc_per_step * 8
     collide_bytes = acc_per_step * (8 + 8 * sb + 6 * sb)
-    dominant = max(["pair", "collide"], key=lambda k: stage_ms[k])
-    if dominant == "pair":
+    if args.strategy == "multi_kernel":
+        dominant = max(["pair", "collide"], key=lambda k: stage_ms[k])
+    elif args.strategy == "compact":
+        dominant = max(["pair", "collide"], key=lambda k: stage_ms[k])
+    else:
+        dominant = "fused"
+    if dominant == "fused":
+        # fused strategy: k_step does the whole per-pair work; bytes as both
+        # stages together (reads of every pair + write-back of accepted pairs)
+        step_bytes = n_pairs * 8 * sb + acc_per_step * 6 * sb
+        achieved = step_bytes / (stage_ms["pair"] * 1e-3) / 1e9
+        roof = {"kernel": "k_step", "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+                "bytes_per_launch": step_bytes, "avg_ms": stage_ms["pair"]}
+    elif dominant == "pair":
         achieved = pair_bytes / (stage_ms["pair"] * 1e-3) / 1e9
         roof = {"kernel": "k_pair", "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": achieved / PEAK_HBM_GBS, "traffic": None,
@@ -158,7 +206,8 @@ def main():
         "dtype": "f64" if sb == 8 else "f32 storage, f64 arithmetic",
         "data": "synthetic",
         "config": {"workload": p.name, "cells": p.n_cells, "pairs_per_step": n_pairs, "sampler": args.sampler,
-                   "collisions_per_step": acc_per_step},
+                   "collisions_per_step": acc_per_step, "strategy": args.strategy,
+                   "chunks_per_block": args.chunks_per_block},
         "gpu_ms_per_step": gpu_ms / args.steps,
         "stage_ms": stage_ms,
         "roofline": roof,

@@ -162,6 +162,27 @@ cs_status cs_check_layout(cs_ctx* ctx, const int64_t* off, int64_t n_cells, int6
 cs_status cs_sample_plain(cs_ctx* ctx, cs_dtype dtype, const void* x, const void* u, int64_t n,
                           void* mu_out, void* ratio_out, void* stream);
 
+/* --------------------------------------------------------- options ------ */
+
+/* Kernel strategies of cs_compton_step; all give bitwise-identical results. */
+typedef enum {
+    CS_STRATEGY_FUSED = 0,        /* scan + persistent step kernel with an LDS queue of    */
+                                  /* accepted pairs drained in place (default)             */
+    CS_STRATEGY_MULTI_KERNEL = 1, /* one kernel per stage (baseline)                       */
+    CS_STRATEGY_COMPACT = 2       /* scan + pair kernel compacting accepted pairs by       */
+                                  /* decoupled look-back + dense collide kernel            */
+} cs_strategy;
+
+typedef enum {
+    CS_OPT_STRATEGY = 0,         /* a cs_strategy                                        */
+    CS_OPT_CHUNKS_PER_BLOCK = 1  /* fused: 256-pair chunks per workgroup, 0 = automatic  */
+} cs_option;
+
+/* Set / read a context option.  CS_ERR_INVALID_ARG for unknown options or
+ * out-of-range values (chunks per block in [0, 4096]). */
+cs_status cs_set_option(cs_ctx* ctx, cs_option opt, int64_t value);
+cs_status cs_get_option(const cs_ctx* ctx, cs_option opt, int64_t* value);
+
 /* ------------------------------------------------------- measurement ---- */
 
 /* Stages of cs_compton_step, in order. */

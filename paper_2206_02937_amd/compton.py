@@ -18,6 +18,8 @@ STATUS_NAMES = {0: "CS_OK", 1: "CS_ERR_INVALID_ARG", 2: "CS_ERR_LAYOUT", 3: "CS_
                 4: "CS_ERR_HIP", 5: "CS_ERR_IO", 6: "CS_ERR_NOT_READY"}
 CS_F32, CS_F64 = 0, 1
 SAMPLERS = {"plain": 0, "mlp_f32": 1, "mlp_bf16": 2, "mlp_fp8": 3}
+STRATEGIES = {"fused": 0, "multi_kernel": 1, "compact": 2}
+OPT_STRATEGY, OPT_CHUNKS_PER_BLOCK = 0, 1
 LOSSES = {"mse": 0, "mae": 1}
 
 
@@ -63,6 +65,10 @@ def lib():
     L.cs_check_layout.restype = st
     L.cs_sample_plain.argtypes = [vp, C.c_int, vp, vp, i64, vp, vp, vp]
     L.cs_sample_plain.restype = st
+    L.cs_set_option.argtypes = [vp, C.c_int, i64]
+    L.cs_set_option.restype = st
+    L.cs_get_option.argtypes = [vp, C.c_int, C.POINTER(i64)]
+    L.cs_get_option.restype = st
     L.cs_set_stage_timing.argtypes = [vp, C.c_int]
     L.cs_set_stage_timing.restype = st
     L.cs_stage_times.argtypes = [vp, C.POINTER(C.c_float), i32, C.POINTER(i32)]
@@ -187,6 +193,20 @@ class Context:
             return False
         self._check(rc)
         return True
+
+    def set_option(self, opt, value):
+        self._check(lib().cs_set_option(self._h, int(opt), int(value)))
+
+    def get_option(self, opt):
+        v = C.c_int64()
+        self._check(lib().cs_get_option(self._h, int(opt), C.byref(v)))
+        return v.value
+
+    def set_strategy(self, name):
+        self.set_option(OPT_STRATEGY, STRATEGIES[name])
+
+    def set_chunks_per_block(self, g):
+        self.set_option(OPT_CHUNKS_PER_BLOCK, g)
 
     def set_stage_timing(self, enable):
         self._check(lib().cs_set_stage_timing(self._h, 1 if enable else 0))

@@ -29,25 +29,39 @@ cs_status hip_fail(cs_ctx* ctx, hipError_t e, const char* where) {
     return fail(ctx, CS_ERR_HIP, m);
 }
 
-// Ensure the context workspace holds `bytes`; growth waits for `stream` first
-// so that no queued kernel still uses the old buffer.
-cs_status ensure_workspace(cs_ctx* ctx, size_t bytes, hipStream_t stream) {
-    if (ctx->ws.bytes >= bytes) return CS_OK;
+// Ensure the context workspace holds `step_bytes` of per-step area and
+// `status_words` look-back status words.  Growth waits for `stream` first so
+// that no queued kernel still uses the old buffer, then re-initialises the
+// control block (epoch 1) and zeroes the status words (synchronous; never
+// inside a captured graph, since a captured step never grows).
+cs_status ensure_workspace(cs_ctx* ctx, size_t step_bytes, int64_t status_words, hipStream_t stream) {
+    cs::Workspace& w = ctx->ws;
+    if (w.base && w.status_cap >= status_words && w.bytes >= cs::ws_fixed_bytes(w.status_cap) + step_bytes)
+        return CS_OK;
     hipError_t e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "workspace growth: stream synchronize");
-    if (ctx->ws.base) {
-        e = hipFree(ctx->ws.base);
-        ctx->ws.base = nullptr;
-        ctx->ws.bytes = 0;
+    if (w.base) {
+        e = hipFree(w.base);
+        w.base = nullptr;
+        w.bytes = 0;
+        w.status_cap = 0;
         if (e != hipSuccess) return hip_fail(ctx, e, "workspace growth: hipFree");
     }
-    size_t want = bytes + bytes / 4 + 4096;
-    e = hipMalloc(&ctx->ws.base, want);
+    const int64_t cap = status_words + status_words / 4 + 64;
+    const size_t fixed = cs::ws_fixed_bytes(cap);
+    const size_t want = fixed + step_bytes + step_bytes / 4 + 4096;
+    e = hipMalloc(&w.base, want);
     if (e != hipSuccess) {
-        ctx->ws.base = nullptr;
+        w.base = nullptr;
         return hip_fail(ctx, e, "workspace growth: hipMalloc");
     }
-    ctx->ws.bytes = want;
+    e = hipMemset(w.base, 0, fixed);
+    cs::StepControl init = {};
+    init.epoch = 1;
+    if (e == hipSuccess) e = hipMemcpy(w.base, &init, sizeof(init), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(ctx, e, "workspace growth: initialisation");
+    w.bytes = want;
+    w.status_cap = cap;
     return CS_OK;
 }
 
@@ -167,10 +181,33 @@ cs_status cs_compton_step(cs_ctx* ctx, cs_dtype dtype, cs_species electrons, cs_
     sh.n_chunks = (nmin + cs::kChunk - 1) / cs::kChunk;
     sh.n_collide_blocks = sh.n_chunks < 1024 ? (sh.n_chunks > 0 ? sh.n_chunks : 1) : 1024;
     sh.scan_tmp_len = cs::step_scan_tmp_len(n_cells, sh.n_chunks);
-    cs_status s = ensure_workspace(ctx, cs::step_workspace_bytes(sh), st);
+    int64_t G = ctx->chunks_per_block;
+    if (G <= 0) {
+        // automatic: about 512 workgroups (2 per compute unit at the fused
+        // kernel's occupancy), at most 16 chunks each
+        G = sh.n_chunks / 512;
+        if (G > 16) G = 16;
+    }
+    if (G < 1) G = 1;
+    sh.chunks_per_block = G;
+    sh.n_step_blocks = sh.n_chunks > 0 ? (sh.n_chunks + G - 1) / G : 1;
+    sh.n_prep_blocks = cs::fused_prep_blocks(n_cells);
+    int64_t nd = (nmin + 63) / 64;
+    sh.n_dense_blocks = nd < 1 ? 1 : (nd > 2048 ? 2048 : nd);
+    const int64_t strategy = ctx->strategy;
+    size_t bytes;
+    int64_t status_words = sh.n_prep_blocks;
+    if (strategy == CS_STRATEGY_FUSED) {
+        bytes = cs::fused_workspace_bytes(sh);
+    } else if (strategy == CS_STRATEGY_COMPACT) {
+        sh.n_collide_blocks = sh.n_dense_blocks;
+        bytes = cs::compact_workspace_bytes(sh);
+        status_words += sh.n_chunks;
+    } else {
+        bytes = cs::step_workspace_bytes(sh);
+    }
+    cs_status s = ensure_workspace(ctx, bytes, status_words, st);
     if (s != CS_OK) return s;
-    cs::StepBuffers b;
-    cs::carve_step_buffers(ctx->ws.base, sh, &b);
     cs::StepParams p;
     p.dtype = dtype;
     p.e = electrons;
@@ -185,11 +222,58 @@ cs_status cs_compton_step(cs_ctx* ctx, cs_dtype dtype, cs_species electrons, cs_
     p.mlp = mlp;
     p.stats = stats;
     p.events = ctx->timing ? ctx->events : nullptr;
-    hipError_t e = cs::launch_step(sh, b, p, st);
+    p.use_device_step = 0;
+    hipError_t e;
+    if (strategy == CS_STRATEGY_FUSED) {
+        cs::FusedBuffers fb;
+        cs::carve_fused_buffers(ctx->ws, sh, &fb);
+        e = cs::launch_fused(sh, fb, p, st);
+    } else if (strategy == CS_STRATEGY_COMPACT) {
+        cs::CompactBuffers cb;
+        cs::carve_compact_buffers(ctx->ws, sh, &cb);
+        e = cs::launch_compact(sh, cb, p, st);
+    } else {
+        cs::StepBuffers b;
+        cs::carve_step_buffers(cs::ws_step_area(ctx->ws), sh, &b);
+        e = cs::launch_step(sh, b, p, st);
+    }
     if (e != hipSuccess) return hip_fail(ctx, e, "cs_compton_step: launch");
     if (ctx->timing) ctx->timed_step_pending = true;
     ctx->last_error.clear();
     return CS_OK;
+}
+
+cs_status cs_set_option(cs_ctx* ctx, cs_option opt, int64_t value) {
+    if (!ctx) return CS_ERR_INVALID_ARG;
+    switch (opt) {
+        case CS_OPT_STRATEGY:
+            if (value != CS_STRATEGY_FUSED && value != CS_STRATEGY_MULTI_KERNEL && value != CS_STRATEGY_COMPACT)
+                return fail(ctx, CS_ERR_INVALID_ARG, "cs_set_option: unknown strategy");
+            ctx->strategy = value;
+            break;
+        case CS_OPT_CHUNKS_PER_BLOCK:
+            if (value < 0 || value > 4096) return fail(ctx, CS_ERR_INVALID_ARG, "cs_set_option: chunks per block");
+            ctx->chunks_per_block = value;
+            break;
+        default:
+            return fail(ctx, CS_ERR_INVALID_ARG, "cs_set_option: unknown option");
+    }
+    ctx->last_error.clear();
+    return CS_OK;
+}
+
+cs_status cs_get_option(const cs_ctx* ctx, cs_option opt, int64_t* value) {
+    if (!ctx || !value) return CS_ERR_INVALID_ARG;
+    switch (opt) {
+        case CS_OPT_STRATEGY:
+            *value = ctx->strategy;
+            return CS_OK;
+        case CS_OPT_CHUNKS_PER_BLOCK:
+            *value = ctx->chunks_per_block;
+            return CS_OK;
+        default:
+            return CS_ERR_INVALID_ARG;
+    }
 }
 
 cs_status cs_check_layout(cs_ctx* ctx, const int64_t* off, int64_t n_cells, int64_t n_particles, void* stream) {
@@ -197,9 +281,9 @@ cs_status cs_check_layout(cs_ctx* ctx, const int64_t* off, int64_t n_cells, int6
     if (!off || n_cells < 0 || n_particles < 0) return fail(ctx, CS_ERR_INVALID_ARG, "cs_check_layout: bad argument");
     DeviceGuard g(ctx->device);
     hipStream_t st = (hipStream_t)stream;
-    cs_status s = ensure_workspace(ctx, 256, st);
+    cs_status s = ensure_workspace(ctx, 256, 0, st);
     if (s != CS_OK) return s;
-    int32_t* flag = (int32_t*)ctx->ws.base;
+    int32_t* flag = (int32_t*)cs::ws_step_area(ctx->ws);
     hipError_t e = cs::launch_check_layout(off, n_cells, n_particles, flag, st);
     if (e != hipSuccess) return hip_fail(ctx, e, "cs_check_layout: launch");
     int32_t h = 0;

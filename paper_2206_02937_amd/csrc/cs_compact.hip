@@ -1,0 +1,239 @@
+// cs_compact.hip -- the step as four kernels (default strategy):
+//
+//   k_prep_scan       (cs_fused.hip) cells -> pair offsets, keys, chunk map
+//   k_pair_compact    one lane per pair, one workgroup per 256-pair chunk:
+//                     pairing, x, s(x), P, accept; the accepted pairs of the
+//                     chunk get their global position by decoupled look-back
+//                     over the chunks, so the list of accepted pairs is dense
+//                     and in pair order with no atomics.  Lean (no sampler),
+//                     so it runs at full occupancy.
+//   k_collide_dense   one-wave workgroups stride over the dense list: sample
+//                     the angle, scatter, write back.
+//   k_finalize_step   (cs_fused.hip) fixed-order reduction of the partial sums.
+#include <hip/hip_runtime.h>
+
+#include "cs_block.h"
+#include "cs_device.h"
+#include "cs_internal.h"
+#include "cs_lookback.h"
+#include "cs_pair.h"
+
+namespace cs {
+
+constexpr int kDenseThreads = 64;
+
+template <typename T>
+struct CompactArgs {
+    Particles<T> pt;
+    const int64_t *off_e, *off_g;
+    int64_t n_cells, n_chunks;
+    const int32_t* pair_off;
+    const uint32_t* keys;
+    const int32_t* chunk_cell;
+    double dt, density_norm;
+    uint64_t seed;
+    StepControl* ctrl;
+    uint64_t* status;  // one word per chunk
+    int2* list;
+    double* chunk_prob;
+    int64_t* chunk_clip;
+    int64_t* chunk_inv;
+    double* coll_eb;
+    double* coll_ea;
+    cs_stats* stats;
+};
+
+template <typename T>
+__global__ __launch_bounds__(kChunk) void k_pair_compact(const CompactArgs<T> a) {
+    __shared__ int s_wcnt[kChunk / 64];
+    __shared__ int s_prefix;
+    __shared__ double s_rd[kChunk / 64];
+    __shared__ long long s_ri[2 * (kChunk / 64)];
+    const int tid = threadIdx.x;
+    const int lane = lane_id();
+    const int wave = tid >> 6;
+    const int64_t j = blockIdx.x;
+    StepControl* ctrl = a.ctrl;
+    const uint32_t E = ctrl->epoch;
+    const uint64_t step = ctrl->step;
+    const bool layout_ok = ctrl->layout_epoch != E && ctrl->scan_fault_epoch != E;
+    const int32_t T_total = layout_ok ? a.pair_off[a.n_cells] : 0;
+    const int32_t t = (int32_t)(j * kChunk) + tid;
+    const bool active = t < T_total;
+    int c = 0;
+    if (active) {
+        int lo = a.chunk_cell[j], hi = a.chunk_cell[j + 1];
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (a.pair_off[mid] <= t)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        c = lo;
+    }
+    PairOutcome o;
+    o.accept = false;
+    o.P = 0.0;
+    o.clipped = false;
+    o.invalid = false;
+    o.ie = o.ig = 0;
+    if (__any(active))
+        o = pair_eval<T>(a.pt, active, a.off_e[c], a.off_e[c + 1], a.off_g[c], a.off_g[c + 1], a.keys + 4 * c,
+                         (uint32_t)(t - (active ? a.pair_off[c] : 0)), a.dt, a.density_norm, a.seed, step);
+    const uint64_t mask = __ballot(o.accept);
+    const int before = __popcll(mask & ((1ull << lane) - 1ull));
+    if (lane == 0) s_wcnt[wave] = __popcll(mask);
+    const double wp = wave_sum(o.P);
+    const long long wc = wave_sum_i(o.clipped ? 1 : 0), wi = wave_sum_i(o.invalid ? 1 : 0);
+    if (lane == 0) {
+        s_rd[wave] = wp;
+        s_ri[2 * wave] = wc;
+        s_ri[2 * wave + 1] = wi;
+    }
+    __syncthreads();
+    int wbase = 0, total = 0;
+#pragma unroll
+    for (int w = 0; w < kChunk / 64; ++w) {
+        wbase += w < wave ? s_wcnt[w] : 0;
+        total += s_wcnt[w];
+    }
+    if (tid < 64) {
+        const uint32_t ex = lookback_exclusive_wave(a.status, j, E, (uint32_t)total, &ctrl->scan_fault_epoch);
+        if (tid == 0) s_prefix = (int)ex;
+    }
+    if (tid == 0) {
+        double p = 0.0;
+        long long cl = 0, in = 0;
+        for (int w = 0; w < kChunk / 64; ++w) {
+            p += s_rd[w];
+            cl += s_ri[2 * w];
+            in += s_ri[2 * w + 1];
+        }
+        a.chunk_prob[j] = p;
+        a.chunk_clip[j] = cl;
+        a.chunk_inv[j] = in;
+    }
+    __syncthreads();
+    if (o.accept) a.list[s_prefix + wbase + before] = make_int2(o.ie, o.ig);
+    if (tid == 0 && j == (int64_t)gridDim.x - 1) ctrl->n_accepted = (uint32_t)(s_prefix + total);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kDenseThreads) void k_collide_dense(const CompactArgs<T> a) {
+    StepControl* ctrl = a.ctrl;
+    const uint32_t E = ctrl->epoch;
+    const uint64_t step = ctrl->step;
+    const bool layout_ok = ctrl->layout_epoch != E && ctrl->scan_fault_epoch != E;
+    const int64_t A = layout_ok ? (int64_t)ctrl->n_accepted : 0;
+    const int64_t stride = (int64_t)gridDim.x * kDenseThreads;
+    const int64_t n_iter = (A + stride - 1) / stride;  // uniform over the grid
+    CollideSums sums;
+    for (int64_t it = 0; it < n_iter; ++it) {
+        const int64_t q = it * stride + (int64_t)blockIdx.x * kDenseThreads + threadIdx.x;
+        if (!__any(q < A)) break;
+        const bool active = q < A;
+        const int2 pr = active ? a.list[q] : make_int2(0, 0);
+        collide_plain<T>(a.pt, active, pr.x, pr.y, a.seed, step, sums);
+    }
+    const double eb = wave_sum(sums.e_before), ea = wave_sum(sums.e_after);
+    if (threadIdx.x == 0) {
+        a.coll_eb[blockIdx.x] = eb;
+        a.coll_ea[blockIdx.x] = ea;
+    }
+}
+
+static size_t al(size_t v) { return (v + 255) & ~(size_t)255; }
+
+size_t compact_workspace_bytes(const StepShape& s) {
+    size_t b = 0;
+    b += al(sizeof(int32_t) * (s.n_cells + 1));
+    b += al(sizeof(uint32_t) * 4 * (s.n_cells > 0 ? s.n_cells : 1));
+    b += al(sizeof(int32_t) * (s.n_chunks + 1));
+    b += al(sizeof(int2) * s.n_chunks * kChunk + 8);
+    b += 3 * al(8 * (s.n_chunks > 0 ? s.n_chunks : 1));
+    b += 2 * al(8 * s.n_collide_blocks);
+    return b;
+}
+
+void carve_compact_buffers(const Workspace& w, const StepShape& s, CompactBuffers* b) {
+    b->ctrl = ws_control(w);
+    b->status = ws_status(w);
+    char* p = (char*)ws_step_area(w);
+    auto take = [&](size_t n) {
+        char* r = p;
+        p += al(n);
+        return (void*)r;
+    };
+    b->pair_off = (int32_t*)take(sizeof(int32_t) * (s.n_cells + 1));
+    b->cell_keys = (uint32_t*)take(sizeof(uint32_t) * 4 * (s.n_cells > 0 ? s.n_cells : 1));
+    b->chunk_cell = (int32_t*)take(sizeof(int32_t) * (s.n_chunks + 1));
+    b->list = (int2*)take(sizeof(int2) * s.n_chunks * kChunk + 8);
+    b->chunk_prob = (double*)take(8 * (s.n_chunks > 0 ? s.n_chunks : 1));
+    b->chunk_clip = (int64_t*)take(8 * (s.n_chunks > 0 ? s.n_chunks : 1));
+    b->chunk_inv = (int64_t*)take(8 * (s.n_chunks > 0 ? s.n_chunks : 1));
+    b->coll_eb = (double*)take(8 * s.n_collide_blocks);
+    b->coll_ea = (double*)take(8 * s.n_collide_blocks);
+}
+
+template <typename T>
+static hipError_t launch_compact_t(const StepShape& sh, const CompactBuffers& b, const StepParams& p, hipStream_t st) {
+    auto mark = [&](int i) {
+        if (p.events) (void)hipEventRecord(p.events[i], st);
+    };
+    mark(0);
+    // prep status words first, then one per chunk
+    hipError_t e = launch_prep(sh, b.ctrl, b.status, b.pair_off, b.cell_keys, b.chunk_cell, p, st);
+    if (e != hipSuccess) return e;
+    mark(1);
+    CompactArgs<T> a;
+    a.pt = {(T*)p.e.x, (T*)p.e.y, (T*)p.e.z, (T*)p.e.w, (T*)p.g.x, (T*)p.g.y, (T*)p.g.z, (T*)p.g.w};
+    a.off_e = p.off_e;
+    a.off_g = p.off_g;
+    a.n_cells = sh.n_cells;
+    a.n_chunks = sh.n_chunks;
+    a.pair_off = b.pair_off;
+    a.keys = b.cell_keys;
+    a.chunk_cell = b.chunk_cell;
+    a.dt = p.dt;
+    a.density_norm = p.density_norm;
+    a.seed = p.seed;
+    a.ctrl = b.ctrl;
+    a.status = b.status + sh.n_prep_blocks;
+    a.list = b.list;
+    a.chunk_prob = b.chunk_prob;
+    a.chunk_clip = b.chunk_clip;
+    a.chunk_inv = b.chunk_inv;
+    a.coll_eb = b.coll_eb;
+    a.coll_ea = b.coll_ea;
+    a.stats = p.stats;
+    if (sh.n_chunks > 0) k_pair_compact<T><<<(unsigned)sh.n_chunks, kChunk, 0, st>>>(a);
+    mark(2);
+    mark(3);
+    k_collide_dense<T><<<(unsigned)sh.n_collide_blocks, kDenseThreads, 0, st>>>(a);
+    mark(4);
+    FinalArgs f = {};
+    f.ctrl = b.ctrl;
+    f.pair_off = b.pair_off;
+    f.n_cells = sh.n_cells;
+    f.a_prob = b.chunk_prob;
+    f.a_clip = b.chunk_clip;
+    f.a_inv = b.chunk_inv;
+    f.a_coll = nullptr;
+    f.n_a = sh.n_chunks;
+    f.b_eb = b.coll_eb;
+    f.b_ea = b.coll_ea;
+    f.b_fb = nullptr;
+    f.n_b = sh.n_collide_blocks;
+    f.stats = p.stats;
+    e = launch_finalize(f, st);
+    mark(5);
+    return e == hipSuccess ? hipGetLastError() : e;
+}
+
+hipError_t launch_compact(const StepShape& sh, const CompactBuffers& b, const StepParams& p, hipStream_t st) {
+    if (p.dtype == CS_F64) return launch_compact_t<double>(sh, b, p, st);
+    return launch_compact_t<float>(sh, b, p, st);
+}
+
+}  // namespace cs

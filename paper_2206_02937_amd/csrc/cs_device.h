@@ -128,12 +128,14 @@ constexpr Coeffs sigma_series_coeffs() {
 }
 
 // Series of the upper tail of the angular integral (v = 1 - mu, t = x v):
-//   int_{mu}^{1} f = v [ P1(t) - 2 v P2(t) + v^2 P3(t) ],
-//   P1 = sum (-t)^k ((k+1)(k+2)/2 + 1)/(k+1),  P2 = sum (-t)^k (k+1)/(k+2),
-//   P3 = sum (-t)^k (k+1)/(k+3).
+//   int_{mu}^{1} f = v sum_k (-t)^k [ A_k/(k+1) - 2 v (k+1)/(k+2) + v^2 (k+1)/(k+3) ],
+//   A_k = (k+1)(k+2)/2 + 1,
+// from integrating the binomial series of a^-n term by term.  Stored per k as
+// the signed coefficients of 1, v and v^2, so that one Horner pass in t with
+// coefficient e_k(v) = a_k + v (b_k + v c_k) evaluates it.
 // t <= 2x < 0.4 in the series branch; 48 terms reach round-off.
 struct TailCoeffs {
-    double p1[kSeriesTerms], p2[kSeriesTerms], p3[kSeriesTerms];
+    double a[kSeriesTerms], b[kSeriesTerms], c[kSeriesTerms];
 };
 
 constexpr TailCoeffs tail_series_coeffs() {
@@ -141,9 +143,9 @@ constexpr TailCoeffs tail_series_coeffs() {
     for (int k = 0; k < kSeriesTerms; ++k) {
         const double kk = (double)k;
         const double sgn = (k & 1) ? -1.0 : 1.0;
-        r.p1[k] = sgn * (((kk + 1.0) * (kk + 2.0) / 2.0 + 1.0) / (kk + 1.0));
-        r.p2[k] = sgn * ((kk + 1.0) / (kk + 2.0));
-        r.p3[k] = sgn * ((kk + 1.0) / (kk + 3.0));
+        r.a[k] = sgn * (((kk + 1.0) * (kk + 2.0) / 2.0 + 1.0) / (kk + 1.0));
+        r.b[k] = sgn * (-2.0 * (kk + 1.0) / (kk + 2.0));
+        r.c[k] = sgn * ((kk + 1.0) / (kk + 3.0));
     }
     return r;
 }
@@ -151,20 +153,65 @@ constexpr TailCoeffs tail_series_coeffs() {
 __constant__ constexpr Coeffs kSigma = sigma_series_coeffs();
 __constant__ constexpr TailCoeffs kTail = tail_series_coeffs();
 
-// The table pointer is passed through an empty asm so that the compiler
-// re-reads the coefficients (scalar loads) on every call instead of hoisting
-// a whole table into vector registers across the sampler's Newton loop.
-__device__ __forceinline__ double horner(const double* c, double x) {
+// Horner over coefficients [N0, N1) of a table.  The table pointer is passed
+// through an empty asm so that the compiler re-reads the coefficients (scalar
+// loads) on every call instead of hoisting a whole table into vector
+// registers across the sampler's Newton loop.
+typedef const __attribute__((address_space(4))) double* cdptr;  // constant (scalar-load) space
+
+template <int N0, int N1>
+__device__ __forceinline__ double horner_range(const double* c_generic, double x) {
+    cdptr c = (cdptr)c_generic;
     asm volatile("" : "+s"(c));
-    double acc = c[kSeriesTerms - 1];
+    double acc = c[N1 - 1];
 #pragma unroll
-    for (int k = kSeriesTerms - 2; k >= 0; --k) acc = fma(acc, x, c[k]);
+    for (int k = N1 - 2; k >= N0; --k) acc = fma(acc, x, c[k]);
     return acc;
 }
 
-// s(x) = sigma_KN(x) / sigma_T.
+// A 48-term series split at 14 terms: below `low_switch` the value is defined
+// as the 14-term sum (the dropped tail is below 2e-19 relative for the tables
+// here), above it as L + x^14 H.  The value depends on x alone; the wave
+// skips H when none of its active lanes needs it.
+constexpr int kLowTerms = 14;
+
+__device__ __forceinline__ double series_split(const double* c, double x, double low_switch) {
+    const double L = horner_range<0, kLowTerms>(c, x);
+    if (__all(x < low_switch)) return L;
+    const double H = horner_range<kLowTerms, kSeriesTerms>(c, x);
+    if (x < low_switch) return L;
+    const double x2 = x * x, x4 = x2 * x2, x8 = x4 * x4;
+    const double x14 = x8 * x4 * x2;
+    return fma(x14, H, L);
+}
+
+// Horner in t over terms [N0, N1) of the tail series, coefficient
+// e_k(v) = a_k + v (b_k + v c_k).
+template <int N0, int N1>
+__device__ __forceinline__ double tail_horner(const TailCoeffs* T_generic, double t, double v) {
+    cdptr A = (cdptr)T_generic->a, B = (cdptr)T_generic->b, C = (cdptr)T_generic->c;
+    asm volatile("" : "+s"(A), "+s"(B), "+s"(C));
+    double acc = fma(v, fma(v, C[N1 - 1], B[N1 - 1]), A[N1 - 1]);
+#pragma unroll
+    for (int k = N1 - 2; k >= N0; --k) acc = fma(acc, t, fma(v, fma(v, C[k], B[k]), A[k]));
+    return acc;
+}
+
+// The same 14-term split as series_split, with the switch at t = 0.04.
+__device__ __forceinline__ double tail_series(const TailCoeffs* T, double t, double v) {
+    const double L = tail_horner<0, kLowTerms>(T, t, v);
+    if (__all(t < 0.04)) return L;
+    const double H = tail_horner<kLowTerms, kSeriesTerms>(T, t, v);
+    if (t < 0.04) return L;
+    const double t2 = t * t, t4 = t2 * t2, t8 = t4 * t4;
+    const double t14 = t8 * t4 * t2;
+    return fma(t14, H, L);
+}
+
+// s(x) = sigma_KN(x) / sigma_T: series below 0.2 (14 terms below 0.02),
+// closed form with log1p above.
 __device__ __forceinline__ double sigma_ratio(double x) {
-    if (x < kSeriesSwitch) return horner(kSigma.c, x);
+    if (x < kSeriesSwitch) return series_split(kSigma.c, x, 0.02);
     const double l = log1p(2.0 * x);
     const double opx = 1.0 + x, o2x = 1.0 + 2.0 * x;
     return 0.75 * (opx / (x * x * x) * (2.0 * x * opx / o2x - l) + l / (2.0 * x) - (1.0 + 3.0 * x) / (o2x * o2x));
@@ -184,11 +231,8 @@ __device__ __forceinline__ double angle_density_v(double v, double x) {
 //                        - (-(x v) + (2x+2) log1p(x v) - (2x+1) x v / a) / x^2 ].
 __device__ __forceinline__ double angle_tail(double v, double x) {
     if (x < kSeriesSwitch) {
-        const double t = x * v;
-        const double P1 = horner(kTail.p1, t);
-        const double P2 = horner(kTail.p2, t);
-        const double P3 = horner(kTail.p3, t);
-        return v * (P1 - 2.0 * v * P2 + v * v * P3);
+        const double t = x * v;  // <= 2x < 0.4; 14 terms suffice below 0.04
+        return v * tail_series(&kTail, t, v);
     }
     const double xv = x * v;
     const double a = 1.0 + xv;
@@ -198,26 +242,40 @@ __device__ __forceinline__ double angle_tail(double v, double x) {
     return g / x;
 }
 
-// Thomson-limit inverse (x -> 0): root of (mu^3 + 3 mu + 4)/8 = u by Cardano.
+// Thomson-limit inverse (x -> 0): root of (mu^3 + 3 mu + 4)/8 = u by Cardano;
+// with q = 4u - 2 and A = cbrt(q + sqrt(q^2 + 1)) the root is A - 1/A.
 __device__ __forceinline__ double thomson_root(double u) {
     const double q = 4.0 * u - 2.0;
-    const double r = sqrt(q * q + 1.0);
-    return cbrt(q + r) + cbrt(q - r);
+    const double A = cbrt(q + sqrt(q * q + 1.0));
+    return A - 1.0 / A;
 }
 
 // Inverse CDF of the rest-frame scattering angle, returned as v = 1 - mu so
 // that forward scatters (mu -> 1) keep relative precision: the v with
-// tail(v) = (1 - u) tail(2).  Newton in v, safeguarded by a bisection bracket,
-// from the Thomson root (x < 1/2) or, for x >= 1/2, from the inverse of the
-// large-x approximation F ~ ln((1+2x)/a) / ln(1+2x), a = 1 + x v.  A step
-// below 1e-10 v is accepted and ends the iteration (quadratic convergence
-// leaves the error at the tail's round-off); an exact zero residual ends it
-// too.  At most 4 steps are needed for x in [0, 1e3].
+// tail(v) = (1 - u) Z, Z = tail(2) = (8/3) s(x).
+//
+// Start: for x < 1/2 the Thomson root v0 = 1 - mu0 corrected to first order
+// in x: with tail = v(2 - v + v^2/3) - x v^2 (2 - 4v/3 + v^2/2) + O(x^2) and
+// Z = 8/3 - 16x/3 + O(x^2), v1 = [v0^2 (2 - 4 v0/3 + v0^2/2) - 16(1 - u)/3]
+// / (2 - 2 v0 + v0^2); for x >= 1/2 the inverse of the large-x law
+// F ~ ln((1+2x)/a) / ln(1+2x), a = 1 + x v.  Then Newton in v, safeguarded
+// by a bisection bracket.  A step below 1e-8 v is accepted and ends the
+// iteration: the error after it is C v (1e-8)^2 with C = |f'/2f| v <= O(1)
+// for the Klein-Nishina density, i.e. at round-off.  An exact zero residual
+// ends it too.
 __device__ __forceinline__ double angle_icdf_v(double u, double x) {
-    const double Z = angle_tail(2.0, x);
+    const double Z = (8.0 / 3.0) * sigma_ratio(x);
     const double target = (1.0 - u) * Z;  // 1 - u is exact for u = k 2^-53
     double lo = 0.0, hi = 2.0;
-    double v = x < 0.5 ? 1.0 - thomson_root(u) : expm1((1.0 - u) * log1p(2.0 * x)) / x;
+    double v;
+    if (x < 0.5) {
+        const double v0 = 1.0 - thomson_root(u);
+        const double v1 = (v0 * v0 * (2.0 - 4.0 / 3.0 * v0 + 0.5 * v0 * v0) - 16.0 / 3.0 * (1.0 - u)) /
+                          (2.0 - 2.0 * v0 + v0 * v0);
+        v = v0 + x * v1;
+    } else {
+        v = expm1((1.0 - u) * log1p(2.0 * x)) / x;
+    }
     v = fmin(fmax(v, 0.0), 2.0);
     for (int it = 0; it < 60; ++it) {
         const double R = angle_tail(v, x) - target;  // > 0: v too large
@@ -227,7 +285,7 @@ __device__ __forceinline__ double angle_icdf_v(double u, double x) {
         else
             lo = v;
         double next = v - R / angle_density_v(v, x);
-        if (fabs(next - v) <= 1e-10 * next) {
+        if (fabs(next - v) <= 1e-8 * next) {
             v = next;
             break;
         }

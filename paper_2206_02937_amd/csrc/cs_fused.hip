@@ -1,0 +1,468 @@
+// cs_fused.hip -- the step as a scan kernel, a persistent step kernel and a
+// finalize kernel.
+//
+//   k_prep_scan  one pass over the cells: validate offsets, pairs per cell
+//                (min(N_e, N_g)), pairing keys, exclusive scan of the pair
+//                counts by decoupled look-back, and the first cell of every
+//                256-pair chunk.
+//   k_step       persistent over chunks: each workgroup evaluates `chunks`
+//                consecutive 256-pair chunks (pairing, x, s(x), P, accept),
+//                appends accepted pairs in pair order to a queue in LDS, and
+//                drains the queue densely (all lanes busy) whenever it holds
+//                a full workgroup of pairs and at the end; per-workgroup partial
+//                sums go to the workspace.
+//   k_finalize_step  one workgroup reduces the partial sums in a fixed order
+//                into cs_stats and advances the step epoch and device step.
+//
+// Step-to-step state lives in a small control block of the workspace (epoch,
+// done counter, layout flag, device step).  The look-back status words and
+// the layout flag carry the epoch of the step that wrote them, so nothing
+// needs clearing between steps.
+#include <hip/hip_runtime.h>
+
+#include "cs_block.h"
+#include "cs_device.h"
+#include "cs_internal.h"
+#include "cs_lookback.h"
+#include "cs_pair.h"
+
+namespace cs {
+
+// ---------------------------------------------------------------------------
+// k_prep_scan
+// ---------------------------------------------------------------------------
+constexpr int kPrepThreads = 256;
+constexpr int kPrepPerThread = 4;
+constexpr int kPrepCells = kPrepThreads * kPrepPerThread;
+
+struct PrepArgs {
+    const int64_t *off_e, *off_g;
+    int64_t n_cells, ne, ng, n_chunks;
+    uint64_t seed, step;
+    int use_device_step;  // 1: take the step from ctrl (graph replay)
+    int32_t* pair_off;    // [n_cells + 1]
+    uint32_t* keys;       // [4 n_cells]
+    int32_t* chunk_cell;  // [n_chunks + 1]
+    uint64_t* status;     // [n_prep_blocks]
+    StepControl* ctrl;
+};
+
+__global__ __launch_bounds__(kPrepThreads) void k_prep_scan(const PrepArgs a) {
+    __shared__ int s_scan[kPrepThreads / 64 + 1];
+    __shared__ int s_prefix;
+    const uint32_t E = a.ctrl->epoch;
+    const uint64_t step = a.use_device_step ? a.ctrl->step : a.step;
+    const int64_t base = (int64_t)blockIdx.x * kPrepCells + (int64_t)threadIdx.x * kPrepPerThread;
+    int cnt[kPrepPerThread];
+    bool bad = false;
+    int tsum = 0;
+#pragma unroll
+    for (int r = 0; r < kPrepPerThread; ++r) {
+        const int64_t c = base + r;
+        cnt[r] = 0;
+        if (c < a.n_cells) {
+            const int64_t a0 = a.off_e[c], a1 = a.off_e[c + 1], b0 = a.off_g[c], b1 = a.off_g[c + 1];
+            bool b = a1 < a0 || b1 < b0;
+            if (c == 0) b = b || a0 != 0 || b0 != 0;
+            if (c == a.n_cells - 1) b = b || a1 != a.ne || b1 != a.ng;
+            if (b) {
+                bad = true;
+            } else {
+                const int64_t nmin = (a1 - a0) < (b1 - b0) ? (a1 - a0) : (b1 - b0);
+                cnt[r] = (int)nmin;
+                if (nmin > 0) {
+                    const u32x4 k = draw(a.seed, (uint64_t)c, step, kPair);
+                    a.keys[4 * c + 0] = k.a;
+                    a.keys[4 * c + 1] = k.b;
+                    a.keys[4 * c + 2] = k.c;
+                    a.keys[4 * c + 3] = k.d;
+                }
+            }
+        }
+        tsum += cnt[r];
+    }
+    if (bad) atomicMax(&a.ctrl->layout_epoch, E);
+    if (blockIdx.x == 0 && threadIdx.x == 0 && !a.use_device_step) a.ctrl->step = a.step;
+    int block_total;
+    const int tex = block_exclusive_scan(tsum, s_scan, &block_total);
+    if (threadIdx.x < 64) {
+        const uint32_t ex =
+            lookback_exclusive_wave(a.status, blockIdx.x, E, (uint32_t)block_total, &a.ctrl->scan_fault_epoch);
+        if (threadIdx.x == 0) s_prefix = (int)ex;
+    }
+    __syncthreads();
+    int run = s_prefix + tex;
+#pragma unroll
+    for (int r = 0; r < kPrepPerThread; ++r) {
+        const int64_t c = base + r;
+        if (c < a.n_cells) {
+            a.pair_off[c] = run;
+            // chunks whose first pair lies in this cell start here
+            if (cnt[r] > 0) {
+                const int64_t j0 = ((int64_t)run + kChunk - 1) / kChunk;
+                const int64_t j1 = ((int64_t)run + cnt[r] + kChunk - 1) / kChunk;
+                for (int64_t j = j0; j < j1; ++j) a.chunk_cell[j] = (int32_t)c;
+            }
+        }
+        run += cnt[r];
+    }
+    if (blockIdx.x == gridDim.x - 1) {
+        // this block's inclusive prefix is the total pair count T
+        const int T = s_prefix + block_total;
+        if (threadIdx.x == 0) a.pair_off[a.n_cells] = T;
+        const int64_t jt = ((int64_t)T + kChunk - 1) / kChunk;
+        for (int64_t j = jt + threadIdx.x; j <= a.n_chunks; j += kPrepThreads)
+            a.chunk_cell[j] = (int32_t)(a.n_cells - 1);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_step
+// ---------------------------------------------------------------------------
+constexpr int kQueueCap = 2 * kChunk;  // holds < kChunk before a chunk adds <= kChunk
+
+template <typename T>
+struct FusedArgs {
+    Particles<T> pt;
+    const int64_t *off_e, *off_g;
+    int64_t n_cells, n_chunks;
+    int chunks_per_block;
+    const int32_t* pair_off;
+    const uint32_t* keys;
+    const int32_t* chunk_cell;
+    double dt, density_norm;
+    uint64_t seed;
+    StepControl* ctrl;
+    BlockPartials part;
+    cs_stats* stats;
+};
+
+template <typename T>
+__device__ void drain_plain(const FusedArgs<T>& a, const StagedPair<T>* queue, int n, uint64_t step,
+                            CollideSums& sums) {
+    for (int base = 0; base < n; base += kChunk) {
+        const int q = base + (int)threadIdx.x;
+        // waves with no item skip the pass entirely
+        if (__any(q < n)) {
+            const bool active = q < n;
+            collide_staged<T>(a.pt, active, queue + (active ? q : 0), a.seed, step, sums);
+        }
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kChunk) void k_step(const FusedArgs<T> a) {
+    __shared__ StagedPair<T> s_queue[kQueueCap];
+    __shared__ int s_wcnt[kChunk / 64];
+    __shared__ int s_qn;
+    __shared__ double s_red_d[3 * (kChunk / 64)];
+    __shared__ long long s_red_i[4 * (kChunk / 64)];
+    const int tid = threadIdx.x;
+    const int lane = lane_id();
+    const int wave = tid >> 6;
+    StepControl* ctrl = a.ctrl;
+    const uint32_t E = ctrl->epoch;
+    const uint64_t step = ctrl->step;
+    const bool layout_ok = ctrl->layout_epoch != E && ctrl->scan_fault_epoch != E;
+    double sum_p = 0.0;
+    long long n_clip = 0, n_inv = 0, n_coll = 0;
+    CollideSums sums;
+    if (tid == 0) s_qn = 0;
+    __syncthreads();
+    if (layout_ok) {
+        const int32_t T_total = a.pair_off[a.n_cells];
+        const int64_t j_begin = (int64_t)blockIdx.x * a.chunks_per_block;
+        int64_t j_end = j_begin + a.chunks_per_block;
+        if (j_end > a.n_chunks) j_end = a.n_chunks;
+        for (int64_t j = j_begin; j < j_end; ++j) {
+            if (j * kChunk >= T_total) break;  // uniform over the block
+            const int32_t t = (int32_t)(j * kChunk) + tid;
+            const bool active = t < T_total;
+            int c = 0;
+            if (active) {
+                int lo = a.chunk_cell[j], hi = a.chunk_cell[j + 1];
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (a.pair_off[mid] <= t)
+                        lo = mid;
+                    else
+                        hi = mid - 1;
+                }
+                c = lo;
+            }
+            const PairOutcome o = pair_eval<T>(a.pt, active, a.off_e[c], a.off_e[c + 1], a.off_g[c], a.off_g[c + 1],
+                                               a.keys + 4 * c, (uint32_t)(t - (active ? a.pair_off[c] : 0)), a.dt,
+                                               a.density_norm, a.seed, step);
+            sum_p += o.P;
+            n_clip += o.clipped ? 1 : 0;
+            n_inv += o.invalid ? 1 : 0;
+            const uint64_t mask = __ballot(o.accept);
+            const int before = __popcll(mask & ((1ull << lane) - 1ull));
+            if (lane == 0) s_wcnt[wave] = __popcll(mask);
+            __syncthreads();
+            int wbase = 0, total = 0;
+#pragma unroll
+            for (int w = 0; w < kChunk / 64; ++w) {
+                wbase += w < wave ? s_wcnt[w] : 0;
+                total += s_wcnt[w];
+            }
+            const int qn = s_qn;
+            if (o.accept) {
+                StagedPair<T>& e = s_queue[qn + wbase + before];
+                e.ie = o.ie;
+                e.ig = o.ig;
+                e.p[0] = a.pt.ex[o.ie];
+                e.p[1] = a.pt.ey[o.ie];
+                e.p[2] = a.pt.ez[o.ie];
+                e.k[0] = a.pt.gx[o.ig];
+                e.k[1] = a.pt.gy[o.ig];
+                e.k[2] = a.pt.gz[o.ig];
+                e.we = a.pt.ew[o.ie];
+                e.wg = a.pt.gw[o.ig];
+            }
+            n_coll += o.accept ? 1 : 0;
+            __syncthreads();
+            if (qn + total >= kChunk) {
+                drain_plain<T>(a, s_queue, qn + total, step, sums);
+                __syncthreads();
+                if (tid == 0) s_qn = 0;
+            } else if (tid == 0) {
+                s_qn = qn + total;
+            }
+            __syncthreads();
+        }
+        const int qn = s_qn;
+        if (qn > 0) drain_plain<T>(a, s_queue, qn, step, sums);
+    }
+    // per-workgroup partials, fixed order: lanes (butterfly), then waves
+    const double w_p = wave_sum(sum_p), w_eb = wave_sum(sums.e_before), w_ea = wave_sum(sums.e_after);
+    const long long w_cl = wave_sum_i(n_clip), w_in = wave_sum_i(n_inv), w_co = wave_sum_i(n_coll);
+    if (lane == 0) {
+        s_red_d[3 * wave + 0] = w_p;
+        s_red_d[3 * wave + 1] = w_eb;
+        s_red_d[3 * wave + 2] = w_ea;
+        s_red_i[4 * wave + 0] = w_cl;
+        s_red_i[4 * wave + 1] = w_in;
+        s_red_i[4 * wave + 2] = w_co;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double p = 0.0, eb = 0.0, ea = 0.0;
+        long long cl = 0, in = 0, co = 0;
+        for (int w = 0; w < kChunk / 64; ++w) {
+            p += s_red_d[3 * w + 0];
+            eb += s_red_d[3 * w + 1];
+            ea += s_red_d[3 * w + 2];
+            cl += s_red_i[4 * w + 0];
+            in += s_red_i[4 * w + 1];
+            co += s_red_i[4 * w + 2];
+        }
+        const int b = blockIdx.x;
+        a.part.prob[b] = p;
+        a.part.e_before[b] = eb;
+        a.part.e_after[b] = ea;
+        a.part.clipped[b] = cl;
+        a.part.invalid[b] = in;
+        a.part.collided[b] = co;
+        a.part.fallback[b] = 0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_finalize_step: one workgroup reduces the per-unit partial sums in a fixed
+// order (thread stride, then 4 interleaved accumulators, then lanes, then
+// waves), writes cs_stats and advances the epoch and the device step counter.
+// ---------------------------------------------------------------------------
+constexpr int kFinalThreads = 1024;
+
+__global__ __launch_bounds__(kFinalThreads) void k_finalize_step(const FinalArgs a) {
+    __shared__ double s_d[4][kFinalThreads / 64];
+    __shared__ long long s_i[4][kFinalThreads / 64];
+    const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
+    StepControl* ctrl = a.ctrl;
+    const uint32_t E = ctrl->epoch;
+    const uint64_t step = ctrl->step;
+    // every load below is independent of the control block, so the
+    // workgroup issues them together and pays one memory round trip
+    const int32_t n_pairs_raw = a.n_cells > 0 ? a.pair_off[a.n_cells] : 0;
+    const uint32_t n_acc_raw = ctrl->n_accepted;
+    double d[3][4] = {};
+    long long q[4][4] = {};
+    for (int64_t base = tid; base < a.n_a; base += 4 * kFinalThreads) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int64_t i = base + (int64_t)r * kFinalThreads;
+            if (i < a.n_a) {
+                d[0][r] += a.a_prob[i];
+                q[0][r] += a.a_clip[i];
+                q[1][r] += a.a_inv[i];
+                if (a.a_coll) q[2][r] += a.a_coll[i];
+            }
+        }
+    }
+    for (int64_t base = tid; base < a.n_b; base += 4 * kFinalThreads) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int64_t i = base + (int64_t)r * kFinalThreads;
+            if (i < a.n_b) {
+                d[1][r] += a.b_eb[i];
+                d[2][r] += a.b_ea[i];
+                if (a.b_fb) q[3][r] += a.b_fb[i];
+            }
+        }
+    }
+    const bool layout_ok = ctrl->layout_epoch != E && ctrl->scan_fault_epoch != E;
+    double vd[3];
+    long long vi[4];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) vd[k] = wave_sum((d[k][0] + d[k][1]) + (d[k][2] + d[k][3]));
+#pragma unroll
+    for (int k = 0; k < 4; ++k) vi[k] = wave_sum_i((q[k][0] + q[k][1]) + (q[k][2] + q[k][3]));
+    if (lane == 0) {
+        for (int k = 0; k < 3; ++k) s_d[k][wave] = vd[k];
+        for (int k = 0; k < 4; ++k) s_i[k][wave] = vi[k];
+    }
+    __syncthreads();
+    if (tid == 0) {
+        cs_stats s = {};
+        for (int w = 0; w < kFinalThreads / 64; ++w) {
+            s.sum_prob += s_d[0][w];
+            s.energy_before += s_d[1][w];
+            s.energy_after += s_d[2][w];
+            s.n_clipped += s_i[0][w];
+            s.n_invalid += s_i[1][w];
+            s.n_collided += s_i[2][w];
+            s.n_fallback += s_i[3][w];
+        }
+        if (!a.a_coll) s.n_collided = (int64_t)n_acc_raw;
+        s.n_pairs = n_pairs_raw;
+        if (!layout_ok) {
+            // no particle was touched: report the layout error only
+            s = cs_stats{};
+            s.layout_error = 1;
+        }
+        if (a.stats) *a.stats = s;
+        ctrl->n_accepted = 0;
+        ctrl->step = step + 1;
+        ctrl->epoch = E + 1;
+    }
+}
+
+hipError_t launch_finalize(const FinalArgs& f, hipStream_t st) {
+    k_finalize_step<<<1, kFinalThreads, 0, st>>>(f);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// workspace and launcher
+// ---------------------------------------------------------------------------
+int64_t fused_prep_blocks(int64_t n_cells) { return (n_cells + kPrepCells - 1) / kPrepCells; }
+
+static size_t al(size_t v) { return (v + 255) & ~(size_t)255; }
+
+size_t fused_workspace_bytes(const StepShape& s) {
+    size_t b = 0;
+    b += al(sizeof(int32_t) * (s.n_cells + 1));
+    b += al(sizeof(uint32_t) * 4 * (s.n_cells > 0 ? s.n_cells : 1));
+    b += al(sizeof(int32_t) * (s.n_chunks + 1));
+    b += 7 * al(8 * s.n_step_blocks);
+    return b;
+}
+
+void carve_fused_buffers(const Workspace& w, const StepShape& s, FusedBuffers* b) {
+    b->ctrl = ws_control(w);
+    b->status = ws_status(w);
+    char* p = (char*)ws_step_area(w);
+    auto take = [&](size_t n) {
+        char* r = p;
+        p += al(n);
+        return (void*)r;
+    };
+    b->pair_off = (int32_t*)take(sizeof(int32_t) * (s.n_cells + 1));
+    b->cell_keys = (uint32_t*)take(sizeof(uint32_t) * 4 * (s.n_cells > 0 ? s.n_cells : 1));
+    b->chunk_cell = (int32_t*)take(sizeof(int32_t) * (s.n_chunks + 1));
+    b->part.prob = (double*)take(8 * s.n_step_blocks);
+    b->part.e_before = (double*)take(8 * s.n_step_blocks);
+    b->part.e_after = (double*)take(8 * s.n_step_blocks);
+    b->part.clipped = (int64_t*)take(8 * s.n_step_blocks);
+    b->part.invalid = (int64_t*)take(8 * s.n_step_blocks);
+    b->part.collided = (int64_t*)take(8 * s.n_step_blocks);
+    b->part.fallback = (int64_t*)take(8 * s.n_step_blocks);
+}
+
+hipError_t launch_prep(const StepShape& sh, StepControl* ctrl, uint64_t* status, int32_t* pair_off, uint32_t* keys,
+                       int32_t* chunk_cell, const StepParams& p, hipStream_t st) {
+    if (sh.n_cells <= 0) return hipSuccess;
+    PrepArgs pa;
+    pa.off_e = p.off_e;
+    pa.off_g = p.off_g;
+    pa.n_cells = sh.n_cells;
+    pa.ne = sh.ne;
+    pa.ng = sh.ng;
+    pa.n_chunks = sh.n_chunks;
+    pa.seed = p.seed;
+    pa.step = p.step;
+    pa.use_device_step = p.use_device_step;
+    pa.pair_off = pair_off;
+    pa.keys = keys;
+    pa.chunk_cell = chunk_cell;
+    pa.status = status;
+    pa.ctrl = ctrl;
+    k_prep_scan<<<(unsigned)fused_prep_blocks(sh.n_cells), kPrepThreads, 0, st>>>(pa);
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t launch_fused_t(const StepShape& sh, const FusedBuffers& b, const StepParams& p, hipStream_t st) {
+    auto mark = [&](int i) {
+        if (p.events) (void)hipEventRecord(p.events[i], st);
+    };
+    mark(0);
+    hipError_t e = launch_prep(sh, b.ctrl, b.status, b.pair_off, b.cell_keys, b.chunk_cell, p, st);
+    if (e != hipSuccess) return e;
+    mark(1);
+    FusedArgs<T> fa;
+    fa.pt = {(T*)p.e.x, (T*)p.e.y, (T*)p.e.z, (T*)p.e.w, (T*)p.g.x, (T*)p.g.y, (T*)p.g.z, (T*)p.g.w};
+    fa.off_e = p.off_e;
+    fa.off_g = p.off_g;
+    fa.n_cells = sh.n_cells;
+    fa.n_chunks = sh.n_chunks;
+    fa.chunks_per_block = sh.chunks_per_block;
+    fa.pair_off = b.pair_off;
+    fa.keys = b.cell_keys;
+    fa.chunk_cell = b.chunk_cell;
+    fa.dt = p.dt;
+    fa.density_norm = p.density_norm;
+    fa.seed = p.seed;
+    fa.ctrl = b.ctrl;
+    fa.part = b.part;
+    fa.stats = p.stats;
+    k_step<T><<<(unsigned)sh.n_step_blocks, kChunk, 0, st>>>(fa);
+    mark(2);
+    mark(3);
+    mark(4);
+    FinalArgs f = {};
+    f.ctrl = b.ctrl;
+    f.pair_off = b.pair_off;
+    f.n_cells = sh.n_cells;
+    f.a_prob = b.part.prob;
+    f.a_clip = b.part.clipped;
+    f.a_inv = b.part.invalid;
+    f.a_coll = b.part.collided;
+    f.n_a = sh.n_step_blocks;
+    f.b_eb = b.part.e_before;
+    f.b_ea = b.part.e_after;
+    f.b_fb = b.part.fallback;
+    f.n_b = sh.n_step_blocks;
+    f.stats = p.stats;
+    e = launch_finalize(f, st);
+    mark(5);
+    return e == hipSuccess ? hipGetLastError() : e;
+}
+
+hipError_t launch_fused(const StepShape& sh, const FusedBuffers& b, const StepParams& p, hipStream_t st) {
+    if (p.dtype == CS_F64) return launch_fused_t<double>(sh, b, p, st);
+    return launch_fused_t<float>(sh, b, p, st);
+}
+
+}  // namespace cs

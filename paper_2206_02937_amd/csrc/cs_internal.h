@@ -14,12 +14,40 @@ namespace cs {
 constexpr int kChunk = 256;       // pairs per workgroup of the pair kernel
 constexpr int kScanItems = 1024;  // items per workgroup of the scan kernels
 
-// Device workspace of one context.  Grown (never shrunk) on demand; growth
-// synchronises the caller's stream before releasing the old buffer.
+// Step-to-step control block at the start of the workspace (device memory,
+// zeroed with epoch = 1 when the workspace is allocated).
+struct StepControl {
+    uint32_t epoch;             // epoch of the current step (starts at 1)
+    uint32_t done;              // workgroups of the step's last kernel finished
+    uint32_t layout_epoch;      // epoch of the last step with an invalid layout
+    uint32_t scan_fault_epoch;  // epoch of the last step whose scan timed out
+    uint64_t step;              // device step counter (graph replay)
+    uint32_t n_accepted;        // compact strategy: accepted pairs this step
+    uint32_t done_pair;         // compact strategy: pair workgroups finished
+    double pair_prob;           // compact strategy: reduced pair partials
+    int64_t pair_clipped, pair_invalid;
+    uint64_t pad[1];
+};
+static_assert(sizeof(StepControl) == 64, "control block size");
+
+// Device workspace of one context: [control | look-back status words |
+// per-step area].  Grown (never shrunk) on demand; growth synchronises the
+// caller's stream before releasing the old buffer and re-initialises the
+// control block and the status words.
 struct Workspace {
     void* base = nullptr;
     size_t bytes = 0;
+    int64_t status_cap = 0;  // look-back status words available
 };
+
+constexpr size_t kControlBytes = 256;
+
+inline StepControl* ws_control(const Workspace& w) { return (StepControl*)w.base; }
+inline uint64_t* ws_status(const Workspace& w) { return (uint64_t*)((char*)w.base + kControlBytes); }
+inline size_t ws_fixed_bytes(int64_t status_cap) {
+    return kControlBytes + (((size_t)status_cap * sizeof(uint64_t) + 255) & ~(size_t)255);
+}
+inline void* ws_step_area(const Workspace& w) { return (char*)w.base + ws_fixed_bytes(w.status_cap); }
 
 // Sub-buffers of one step, carved from the workspace.
 struct StepBuffers {
@@ -42,10 +70,50 @@ struct StepBuffers {
 struct StepShape {
     int64_t n_cells;
     int64_t ne, ng;
-    int64_t n_chunks;         // ceil(min(ne, ng) / kChunk): upper bound of used chunks
-    int64_t n_collide_blocks; // fixed grid of the collide kernel
-    int64_t scan_tmp_len;
+    int64_t n_chunks;          // ceil(min(ne, ng) / kChunk): upper bound of used chunks
+    int64_t n_collide_blocks;  // multi-kernel: fixed grid of the collide kernel
+    int64_t scan_tmp_len;      // multi-kernel: scan scratch
+    int64_t chunks_per_block;  // fused: consecutive chunks per workgroup
+    int64_t n_step_blocks;     // fused: grid of k_step (>= 1)
+    int64_t n_prep_blocks;     // fused / compact: grid of k_prep_scan
+    int64_t n_dense_blocks;    // compact: grid of the one-wave collide kernel
 };
+
+// Per-workgroup partial sums of the fused step.
+struct BlockPartials {
+    double *prob, *e_before, *e_after;
+    int64_t *clipped, *invalid, *collided, *fallback;
+};
+
+// Sub-buffers of the fused step, carved from the per-step area.
+struct FusedBuffers {
+    StepControl* ctrl;
+    uint64_t* status;
+    int32_t* pair_off;    // [n_cells + 1]
+    uint32_t* cell_keys;  // [4 n_cells]
+    int32_t* chunk_cell;  // [n_chunks + 1]
+    BlockPartials part;   // [n_step_blocks] each
+};
+
+// Sub-buffers of the compact strategy (scan kernel, pair kernel with
+// look-back compaction, dense collide kernel).
+struct CompactBuffers {
+    StepControl* ctrl;
+    uint64_t* status;     // prep blocks, then one word per chunk
+    int32_t* pair_off;    // [n_cells + 1]
+    uint32_t* cell_keys;  // [4 n_cells]
+    int32_t* chunk_cell;  // [n_chunks + 1]
+    int2* list;           // [n_chunks * kChunk] accepted pairs, dense, pair order
+    double* chunk_prob;   // [n_chunks]
+    int64_t* chunk_clip;  // [n_chunks]
+    int64_t* chunk_inv;   // [n_chunks]
+    double* coll_eb;      // [n_collide_blocks]
+    double* coll_ea;      // [n_collide_blocks]
+};
+
+size_t fused_workspace_bytes(const StepShape& s);
+void carve_fused_buffers(const Workspace& w, const StepShape& s, FusedBuffers* b);
+int64_t fused_prep_blocks(int64_t n_cells);
 
 size_t step_workspace_bytes(const StepShape& s);
 void carve_step_buffers(void* base, const StepShape& s, StepBuffers* b);
@@ -60,12 +128,37 @@ struct StepParams {
     cs_sampler sampler;
     const cs_mlp* mlp;
     cs_stats* stats;
-    hipEvent_t* events;  // CS_STAGE_COUNT + 1 events to record between stages, or nullptr
+    hipEvent_t* events;   // CS_STAGE_COUNT + 1 events to record between stages, or nullptr
+    int use_device_step;  // 1: kernels take the step from the device counter (graph replay)
 };
 
 // Launch every kernel of one step on `stream`; returns the HIP error of the
 // launches (asynchronous faults surface later).
 hipError_t launch_step(const StepShape& shape, const StepBuffers& buf, const StepParams& p, hipStream_t stream);
+// Partial sums reduced by the finalize kernel: "a" per pair unit (chunk or
+// workgroup), "b" per collide workgroup.  a_coll / b_fb may be null (then the
+// accepted count comes from the control block, fallbacks are 0).
+struct FinalArgs {
+    StepControl* ctrl;
+    const int32_t* pair_off;
+    int64_t n_cells;
+    const double* a_prob;
+    const int64_t *a_clip, *a_inv, *a_coll;
+    int64_t n_a;
+    const double *b_eb, *b_ea;
+    const int64_t* b_fb;
+    int64_t n_b;
+    cs_stats* stats;
+};
+hipError_t launch_finalize(const FinalArgs& f, hipStream_t st);
+
+size_t compact_workspace_bytes(const StepShape& s);
+void carve_compact_buffers(const Workspace& w, const StepShape& s, CompactBuffers* b);
+hipError_t launch_compact(const StepShape& shape, const CompactBuffers& buf, const StepParams& p, hipStream_t stream);
+hipError_t launch_prep(const StepShape& sh, StepControl* ctrl, uint64_t* status, int32_t* pair_off, uint32_t* keys,
+                       int32_t* chunk_cell, const StepParams& p, hipStream_t st);
+
+hipError_t launch_fused(const StepShape& shape, const FusedBuffers& buf, const StepParams& p, hipStream_t stream);
 hipError_t launch_check_layout(const int64_t* off, int64_t n_cells, int64_t n, int32_t* flag, hipStream_t stream);
 hipError_t launch_sample_plain(cs_dtype dtype, const void* x, const void* u, int64_t n, void* mu, void* ratio,
                                hipStream_t stream);
@@ -75,6 +168,8 @@ hipError_t launch_sample_plain(cs_dtype dtype, const void* x, const void* u, int
 struct cs_ctx {
     int device = 0;
     cs::Workspace ws;
+    int64_t strategy = CS_STRATEGY_FUSED;
+    int64_t chunks_per_block = 0;  // 0: automatic
     std::string last_error;
     bool timing = false;
     bool timed_step_pending = false;

@@ -1,0 +1,187 @@
+// cs_pair.h -- the per-pair work of a Compton step, shared by every kernel
+// strategy (multi-kernel baseline and fused persistent kernel) so that all of
+// them compute bitwise-identical results.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "cs_device.h"
+
+namespace cs {
+
+template <typename T>
+struct Particles {
+    T *ex, *ey, *ez, *ew;
+    T *gx, *gy, *gz, *gw;
+};
+
+struct PairOutcome {
+    int32_t ie, ig;  // electron / photon index of the pair
+    double P;        // collision probability (0 when invalid)
+    bool accept;
+    bool clipped;
+    bool invalid;
+};
+
+__device__ __forceinline__ bool finite_pair(d3 p, double we, d3 k, double wg) {
+    return isfinite(p.x) && isfinite(p.y) && isfinite(p.z) && isfinite(k.x) && isfinite(k.y) && isfinite(k.z) &&
+           isfinite(we) && isfinite(wg) && we >= 0.0 && wg >= 0.0;
+}
+
+// Pair number i of cell c: pairing, rest-frame photon energy, Klein-Nishina
+// cross-section, probability, accept/reject.  Must be called with the whole
+// wave converged (the cross-section picks its series length per wave).
+template <typename T>
+__device__ __forceinline__ PairOutcome pair_eval(const Particles<T>& a, bool active, int64_t e0, int64_t e1,
+                                                 int64_t g0, int64_t g1, const uint32_t* key4, uint32_t i,
+                                                 double dt, double density_norm, uint64_t seed, uint64_t step) {
+    PairOutcome o;
+    o.ie = 0;
+    o.ig = 0;
+    o.P = 0.0;
+    o.accept = false;
+    o.clipped = false;
+    o.invalid = false;
+    double x = 0.0, flux = 0.0, wmax = 0.0, tau = 0.0;
+    bool compute = false;
+    if (active) {
+        const uint32_t ne = (uint32_t)(e1 - e0), ng = (uint32_t)(g1 - g0);
+        const uint32_t M = ne > ng ? ne : ng;
+        FeistelKey key;
+        key.k[0] = key4[0];
+        key.k[1] = key4[1];
+        key.k[2] = key4[2];
+        key.k[3] = key4[3];
+        key.half_bits = (ceil_log2(M) + 1u) >> 1;
+        if (ne <= ng) {
+            o.ie = (int32_t)(e0 + i);
+            o.ig = (int32_t)(g0 + shuffle_index(i, ng, key));
+        } else {
+            o.ig = (int32_t)(g0 + i);
+            o.ie = (int32_t)(e0 + shuffle_index(i, ne, key));
+        }
+        const d3 p = {(double)a.ex[o.ie], (double)a.ey[o.ie], (double)a.ez[o.ie]};
+        const d3 k = {(double)a.gx[o.ig], (double)a.gy[o.ig], (double)a.gz[o.ig]};
+        const double we = (double)a.ew[o.ie], wg = (double)a.gw[o.ig];
+        if (!finite_pair(p, we, k, wg)) {
+            o.invalid = true;
+        } else {
+            const PairInv inv = pair_invariants(p, k);
+            x = inv.x;
+            flux = inv.flux;
+            tau = dt * density_norm * (double)M;
+            wmax = we > wg ? we : wg;
+            compute = x > 0.0;
+        }
+    }
+    // cross-section on the converged wave (lanes without a valid pair see x = 0)
+    const double s = sigma_ratio(x);
+    if (compute) {
+        double P = tau * wmax * s * flux;
+        if (P > 1.0) {
+            o.clipped = true;
+            P = 1.0;
+        }
+        o.P = P;
+    }
+    if (active && !o.invalid) {
+        const u32x4 r = draw(seed, (uint64_t)o.ie, step, kCollide);
+        o.accept = uniform53(r.a, r.b) < o.P;
+    }
+    return o;
+}
+
+struct CollideSums {
+    double e_before = 0.0, e_after = 0.0;
+};
+
+template <typename T>
+__device__ __forceinline__ d3 load_p(const Particles<T>& a, int32_t i) {
+    return {(double)a.ex[i], (double)a.ey[i], (double)a.ez[i]};
+}
+template <typename T>
+__device__ __forceinline__ d3 load_k(const Particles<T>& a, int32_t i) {
+    return {(double)a.gx[i], (double)a.gy[i], (double)a.gz[i]};
+}
+
+// Write back a resolved collision under the weight rule.
+template <typename T>
+__device__ __forceinline__ void write_back(const Particles<T>& a, int32_t ie, int32_t ig, double we, double wg,
+                                           const Scattered& s, uint64_t seed, uint64_t step) {
+    bool upd_e = true, upd_g = true;
+    if (we != wg) {
+        const u32x4 rc = draw(seed, (uint64_t)ie, step, kCollide);
+        const double wmin = we < wg ? we : wg, wmx = we < wg ? wg : we;
+        const bool heavier_moves = uniform53(rc.c, rc.d) < wmin / wmx;
+        if (we > wg)
+            upd_e = heavier_moves;
+        else
+            upd_g = heavier_moves;
+    }
+    if (upd_e) {
+        a.ex[ie] = (T)s.p1.x;
+        a.ey[ie] = (T)s.p1.y;
+        a.ez[ie] = (T)s.p1.z;
+    }
+    if (upd_g) {
+        a.gx[ig] = (T)s.k1.x;
+        a.gy[ig] = (T)s.k1.y;
+        a.gz[ig] = (T)s.k1.z;
+    }
+}
+
+// Resolve the accepted pair (ie, ig) with the plain sampler and write it back.
+// Lanes with active == false run the sampler on a dummy x = 0 (the quickest
+// case) and write nothing.  The momenta are read again after the sampler so
+// that they are not held in registers across its Newton iteration.
+template <typename T>
+__device__ __forceinline__ void collide_plain(const Particles<T>& a, bool active, int32_t ie, int32_t ig,
+                                              uint64_t seed, uint64_t step, CollideSums& sums) {
+    double x = 0.0;
+    if (active) x = pair_invariants(load_p(a, ie), load_k(a, ig)).x;
+    const u32x4 r = draw(seed, (uint64_t)ie, step, kScatter);
+    const double v = angle_icdf_v(active ? uniform53(r.a, r.b) : 0.5, x);
+    if (!active) return;
+    const double u_phi = uniform53(r.c, r.d);
+    const d3 p = load_p(a, ie), k = load_k(a, ig);
+    const PairInv inv = pair_invariants(p, k);
+    const Scattered s = scatter(p, k, inv, v, u_phi);
+    write_back<T>(a, ie, ig, (double)a.ew[ie], (double)a.gw[ig], s, seed, step);
+    sums.e_before += s.e_before;
+    sums.e_after += s.e_after;
+}
+
+// An accepted pair staged in LDS with its particle values.
+template <typename T>
+struct StagedPair {
+    int32_t ie, ig;
+    T p[3], k[3], we, wg;
+};
+
+// The same as collide_plain with the particle values taken from LDS.
+template <typename T>
+__device__ __forceinline__ void collide_staged(const Particles<T>& a, bool active, const StagedPair<T>* e,
+                                               uint64_t seed, uint64_t step, CollideSums& sums) {
+    double x = 0.0;
+    int32_t ie = 0;
+    if (active) {
+        ie = e->ie;
+        const d3 p = {(double)e->p[0], (double)e->p[1], (double)e->p[2]};
+        const d3 k = {(double)e->k[0], (double)e->k[1], (double)e->k[2]};
+        x = pair_invariants(p, k).x;
+    }
+    const u32x4 r = draw(seed, (uint64_t)ie, step, kScatter);
+    const double v = angle_icdf_v(active ? uniform53(r.a, r.b) : 0.5, x);
+    if (!active) return;
+    const double u_phi = uniform53(r.c, r.d);
+    const d3 p = {(double)e->p[0], (double)e->p[1], (double)e->p[2]};
+    const d3 k = {(double)e->k[0], (double)e->k[1], (double)e->k[2]};
+    const PairInv inv = pair_invariants(p, k);
+    const Scattered s = scatter(p, k, inv, v, u_phi);
+    write_back<T>(a, ie, e->ig, (double)e->we, (double)e->wg, s, seed, step);
+    sums.e_before += s.e_before;
+    sums.e_after += s.e_after;
+}
+
+}  // namespace cs

@@ -14,8 +14,10 @@
 // Every reduction has a fixed order, so a step is bitwise reproducible.
 #include <hip/hip_runtime.h>
 
+#include "cs_block.h"
 #include "cs_device.h"
 #include "cs_internal.h"
+#include "cs_pair.h"
 
 namespace cs {
 
@@ -64,69 +66,6 @@ void carve_step_buffers(void* base, const StepShape& s, StepBuffers* b) {
     b->part_energy = (double*)take(sizeof(double) * 2 * s.n_collide_blocks);
     b->part_fallback = (int32_t*)take(sizeof(int32_t) * s.n_collide_blocks);
     b->scan_tmp = (int32_t*)take(sizeof(int32_t) * s.scan_tmp_len);
-}
-
-// ---------------------------------------------------------------------------
-// block-level primitives (wave64)
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ int lane_id() { return __lane_id(); }
-
-__device__ __forceinline__ int wave_inclusive_scan(int v) {
-    const int lane = lane_id();
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const int t = __shfl_up(v, off, 64);
-        if (lane >= off) v += t;
-    }
-    return v;
-}
-
-// Exclusive scan across the block; `lds` holds >= blockDim/64 ints.
-__device__ __forceinline__ int block_exclusive_scan(int v, int* lds, int* total) {
-    const int lane = lane_id();
-    const int wave = threadIdx.x >> 6;
-    const int nw = blockDim.x >> 6;
-    const int inc = wave_inclusive_scan(v);
-    if (lane == 63) lds[wave] = inc;
-    __syncthreads();
-    if (wave == 0) {
-        int w = lane < nw ? lds[lane] : 0;
-        const int ws = wave_inclusive_scan(w);
-        if (lane < nw) lds[lane] = ws - w;  // exclusive wave offsets
-        if (lane == nw - 1) lds[nw] = ws;
-    }
-    __syncthreads();
-    const int res = lds[wave] + inc - v;
-    if (total) *total = lds[nw];
-    __syncthreads();
-    return res;
-}
-
-// Fixed-order tree sum of one double per thread (blockDim a power of two).
-__device__ __forceinline__ double block_sum(double v, double* lds) {
-    const int tid = threadIdx.x;
-    lds[tid] = v;
-    __syncthreads();
-    for (int s = blockDim.x >> 1; s > 0; s >>= 1) {
-        if (tid < s) lds[tid] += lds[tid + s];
-        __syncthreads();
-    }
-    const double r = lds[0];
-    __syncthreads();
-    return r;
-}
-
-__device__ __forceinline__ long long block_sum_i(long long v, long long* lds) {
-    const int tid = threadIdx.x;
-    lds[tid] = v;
-    __syncthreads();
-    for (int s = blockDim.x >> 1; s > 0; s >>= 1) {
-        if (tid < s) lds[tid] += lds[tid + s];
-        __syncthreads();
-    }
-    const long long r = lds[0];
-    __syncthreads();
-    return r;
 }
 
 // ---------------------------------------------------------------------------
@@ -250,8 +189,7 @@ __global__ __launch_bounds__(256) void k_chunk_cells(const int32_t* __restrict__
 
 template <typename T>
 struct PairArgs {
-    const T *ex, *ey, *ez, *ew;
-    const T *gx, *gy, *gz, *gw;
+    Particles<T> pt;
     const int64_t *off_e, *off_g;
     int64_t n_cells;
     const int32_t* pair_off;
@@ -267,12 +205,8 @@ struct PairArgs {
     int32_t* part_inv;
 };
 
-template <typename T>
-__device__ __forceinline__ bool finite_pair(d3 p, double we, d3 k, double wg) {
-    return isfinite(p.x) && isfinite(p.y) && isfinite(p.z) && isfinite(k.x) && isfinite(k.y) && isfinite(k.z) &&
-           isfinite(we) && isfinite(wg) && we >= 0.0 && wg >= 0.0;
-}
-
+// Multi-kernel baseline, stage 1: one lane per pair, accepted pairs compacted
+// per 256-pair chunk into its own list segment (pair order, no atomics).
 template <typename T>
 __global__ __launch_bounds__(kChunk) void k_pair(const PairArgs<T> a) {
     __shared__ double s_red[kChunk];
@@ -291,11 +225,9 @@ __global__ __launch_bounds__(kChunk) void k_pair(const PairArgs<T> a) {
     }
     const int32_t T_total = a.pair_off[a.n_cells];
     const int32_t t = j * kChunk + tid;
-    bool accept = false;
-    double P = 0.0;
-    int clip = 0, invalid = 0;
-    int32_t ie = 0, ig = 0;
-    if (t < T_total) {
+    const bool active = t < T_total;
+    int c = 0;
+    if (active) {
         int lo = a.chunk_cell[j], hi = a.chunk_cell[j + 1];
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
@@ -304,44 +236,12 @@ __global__ __launch_bounds__(kChunk) void k_pair(const PairArgs<T> a) {
             else
                 hi = mid - 1;
         }
-        const int c = lo;
-        const uint32_t i = (uint32_t)(t - a.pair_off[c]);
-        const int64_t e0 = a.off_e[c], g0 = a.off_g[c];
-        const uint32_t ne = (uint32_t)(a.off_e[c + 1] - e0), ng = (uint32_t)(a.off_g[c + 1] - g0);
-        const uint32_t M = ne > ng ? ne : ng;
-        FeistelKey key;
-        key.k[0] = a.keys[4 * c + 0];
-        key.k[1] = a.keys[4 * c + 1];
-        key.k[2] = a.keys[4 * c + 2];
-        key.k[3] = a.keys[4 * c + 3];
-        key.half_bits = (ceil_log2(M) + 1u) >> 1;
-        if (ne <= ng) {
-            ie = (int32_t)(e0 + i);
-            ig = (int32_t)(g0 + shuffle_index(i, ng, key));
-        } else {
-            ig = (int32_t)(g0 + i);
-            ie = (int32_t)(e0 + shuffle_index(i, ne, key));
-        }
-        const d3 p = {(double)a.ex[ie], (double)a.ey[ie], (double)a.ez[ie]};
-        const d3 k = {(double)a.gx[ig], (double)a.gy[ig], (double)a.gz[ig]};
-        const double we = (double)a.ew[ie], wg = (double)a.gw[ig];
-        if (!finite_pair<T>(p, we, k, wg)) {
-            invalid = 1;
-        } else {
-            const PairInv inv = pair_invariants(p, k);
-            const double tau = a.dt * a.density_norm * (double)M;
-            const double wmax = we > wg ? we : wg;
-            P = inv.x > 0.0 ? tau * wmax * sigma_ratio(inv.x) * inv.flux : 0.0;
-            if (P > 1.0) {
-                clip = 1;
-                P = 1.0;
-            }
-            const u32x4 r = draw(a.seed, (uint64_t)ie, a.step, kCollide);
-            accept = uniform53(r.a, r.b) < P;
-        }
+        c = lo;
     }
-    // compaction of the accepted pairs of this chunk, in pair order
-    const uint64_t mask = __ballot(accept);
+    const PairOutcome o =
+        pair_eval<T>(a.pt, active, a.off_e[c], a.off_e[c + 1], a.off_g[c], a.off_g[c + 1], a.keys + 4 * c,
+                     (uint32_t)(t - (active ? a.pair_off[c] : 0)), a.dt, a.density_norm, a.seed, a.step);
+    const uint64_t mask = __ballot(o.accept);
     const int lane = lane_id();
     const int wave = tid >> 6;
     const int before = __popcll(mask & ((1ull << lane) - 1ull));
@@ -352,10 +252,10 @@ __global__ __launch_bounds__(kChunk) void k_pair(const PairArgs<T> a) {
         if (w < wave) wbase += s_wcnt[w];
         total += s_wcnt[w];
     }
-    if (accept) a.acc_list[(int64_t)j * kChunk + wbase + before] = make_int2(ie, ig);
-    const double sp = block_sum(P, s_red);
-    const long long sc = block_sum_i(clip, s_redi);
-    const long long si = block_sum_i(invalid, s_redi);
+    if (o.accept) a.acc_list[(int64_t)j * kChunk + wbase + before] = make_int2(o.ie, o.ig);
+    const double sp = block_sum(o.P, s_red);
+    const long long sc = block_sum_i(o.clipped ? 1 : 0, s_redi);
+    const long long si = block_sum_i(o.invalid ? 1 : 0, s_redi);
     if (tid == 0) {
         a.acc_cnt[j] = total;
         a.part_prob[j] = sp;
@@ -366,10 +266,7 @@ __global__ __launch_bounds__(kChunk) void k_pair(const PairArgs<T> a) {
 
 template <typename T>
 struct CollideArgs {
-    T *ex, *ey, *ez;
-    const T* ew;
-    T *gx, *gy, *gz;
-    const T* gw;
+    Particles<T> pt;
     const int2* acc_list;
     const int32_t* acc_off;
     int64_t n_chunks;
@@ -379,58 +276,36 @@ struct CollideArgs {
     int32_t* part_fallback;
 };
 
+// Multi-kernel baseline, stage 3: one lane per accepted pair, grid-stride.
 template <typename T>
 __global__ __launch_bounds__(256) void k_collide(const CollideArgs<T> a) {
     __shared__ double s_red[256];
     const int tid = threadIdx.x;
-    double eb = 0.0, ea = 0.0;
+    CollideSums sums;
     if (!*a.flag) {
         const int64_t A = a.acc_off[a.n_chunks];
-        for (int64_t q = (int64_t)blockIdx.x * 256 + tid; q < A; q += (int64_t)gridDim.x * 256) {
-            int64_t lo = 0, hi = a.n_chunks - 1;  // largest j with acc_off[j] <= q
-            while (lo < hi) {
-                const int64_t mid = (lo + hi + 1) >> 1;
-                if (a.acc_off[mid] <= q)
-                    lo = mid;
-                else
-                    hi = mid - 1;
+        const int64_t stride = (int64_t)gridDim.x * 256;
+        const int64_t n_iter = (A + stride - 1) / stride;  // uniform over the grid
+        for (int64_t it = 0; it < n_iter; ++it) {
+            const int64_t q = it * stride + (int64_t)blockIdx.x * 256 + tid;
+            const bool active = q < A;
+            int2 pr = make_int2(0, 0);
+            if (active) {
+                int64_t lo = 0, hi = a.n_chunks - 1;  // largest j with acc_off[j] <= q
+                while (lo < hi) {
+                    const int64_t mid = (lo + hi + 1) >> 1;
+                    if (a.acc_off[mid] <= q)
+                        lo = mid;
+                    else
+                        hi = mid - 1;
+                }
+                pr = a.acc_list[lo * kChunk + (q - a.acc_off[lo])];
             }
-            const int2 pr = a.acc_list[lo * kChunk + (q - a.acc_off[lo])];
-            const int32_t ie = pr.x, ig = pr.y;
-            const d3 p = {(double)a.ex[ie], (double)a.ey[ie], (double)a.ez[ie]};
-            const d3 k = {(double)a.gx[ig], (double)a.gy[ig], (double)a.gz[ig]};
-            const double we = (double)a.ew[ie], wg = (double)a.gw[ig];
-            const PairInv inv = pair_invariants(p, k);
-            const u32x4 r = draw(a.seed, (uint64_t)ie, a.step, kScatter);
-            const double u_mu = uniform53(r.a, r.b), u_phi = uniform53(r.c, r.d);
-            const double v = angle_icdf_v(u_mu, inv.x);
-            const Scattered s = scatter(p, k, inv, v, u_phi);
-            bool upd_e = true, upd_g = true;
-            if (we != wg) {
-                const u32x4 rc = draw(a.seed, (uint64_t)ie, a.step, kCollide);
-                const double wmin = we < wg ? we : wg, wmax = we < wg ? wg : we;
-                const bool heavier_moves = uniform53(rc.c, rc.d) < wmin / wmax;
-                if (we > wg)
-                    upd_e = heavier_moves;
-                else
-                    upd_g = heavier_moves;
-            }
-            if (upd_e) {
-                a.ex[ie] = (T)s.p1.x;
-                a.ey[ie] = (T)s.p1.y;
-                a.ez[ie] = (T)s.p1.z;
-            }
-            if (upd_g) {
-                a.gx[ig] = (T)s.k1.x;
-                a.gy[ig] = (T)s.k1.y;
-                a.gz[ig] = (T)s.k1.z;
-            }
-            eb += s.e_before;
-            ea += s.e_after;
+            collide_plain<T>(a.pt, active, pr.x, pr.y, a.seed, a.step, sums);
         }
     }
-    eb = block_sum(eb, s_red);
-    ea = block_sum(ea, s_red);
+    const double eb = block_sum(sums.e_before, s_red);
+    const double ea = block_sum(sums.e_after, s_red);
     if (tid == 0) {
         a.part_energy[2 * blockIdx.x] = eb;
         a.part_energy[2 * blockIdx.x + 1] = ea;
@@ -531,14 +406,7 @@ static hipError_t launch_step_t(const StepShape& sh, const StepBuffers& b, const
     mark(1);
     if (sh.n_chunks > 0) {
         PairArgs<T> pa;
-        pa.ex = (const T*)p.e.x;
-        pa.ey = (const T*)p.e.y;
-        pa.ez = (const T*)p.e.z;
-        pa.ew = (const T*)p.e.w;
-        pa.gx = (const T*)p.g.x;
-        pa.gy = (const T*)p.g.y;
-        pa.gz = (const T*)p.g.z;
-        pa.gw = (const T*)p.g.w;
+        pa.pt = {(T*)p.e.x, (T*)p.e.y, (T*)p.e.z, (T*)p.e.w, (T*)p.g.x, (T*)p.g.y, (T*)p.g.z, (T*)p.g.w};
         pa.off_e = p.off_e;
         pa.off_g = p.off_g;
         pa.n_cells = sh.n_cells;
@@ -561,14 +429,7 @@ static hipError_t launch_step_t(const StepShape& sh, const StepBuffers& b, const
         if (e != hipSuccess) return e;
         mark(3);
         CollideArgs<T> ca;
-        ca.ex = (T*)p.e.x;
-        ca.ey = (T*)p.e.y;
-        ca.ez = (T*)p.e.z;
-        ca.ew = (const T*)p.e.w;
-        ca.gx = (T*)p.g.x;
-        ca.gy = (T*)p.g.y;
-        ca.gz = (T*)p.g.z;
-        ca.gw = (const T*)p.g.w;
+        ca.pt = pa.pt;
         ca.acc_list = b.acc_list;
         ca.acc_off = b.acc_off;
         ca.n_chunks = sh.n_chunks;
