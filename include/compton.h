@@ -162,6 +162,78 @@ cs_status cs_check_layout(cs_ctx* ctx, const int64_t* off, int64_t n_cells, int6
 cs_status cs_sample_plain(cs_ctx* ctx, cs_dtype dtype, const void* x, const void* u, int64_t n,
                           void* mu_out, void* ratio_out, void* stream);
 
+/* ------------------------------------------------- the learned sampler --- */
+
+/*
+ * A small fully connected network standing in for the inverse-CDF sampler
+ * (Sec. 2: the network object is loaded once and run on any batch; Sec. 3.2:
+ * dense layers trained with Adam on data the conventional method produced;
+ * Sec. 4: training can run inside the simulation).  Inputs (x, u): the
+ * rest-frame photon energy x in [1e-4, 1e2] and a uniform u in [0, 1);
+ * features f1 = (log10 x + 1)/3, f2 = 2u - 1.  Hidden layers use SiLU, the
+ * output layer is linear and gives (mu_hat, r_hat) ~ (cos theta, eps'/eps).
+ * The sampler reading is mu = clamp(mu_hat, -1, 1) and r = 1/(1 + x(1 - mu)),
+ * so the Compton relation holds exactly; inputs with x outside the trained
+ * range fall back to the plain sampler.
+ *
+ * Widths: this build's kernels take exactly {2, 64, 64, 64, 64, 2}
+ * (12,802 parameters); other widths give CS_ERR_UNSUPPORTED.
+ * Parameter layout (host and device, FP32): per layer the weight matrix
+ * W[n_out][n_in] row-major, then the bias[n_out].
+ * The network owns its device memory: FP32 master weights, Adam moments and
+ * step count, and the BF16 / FP8 copies prepared by cs_mlp_quantize.
+ */
+#define CS_MLP_X_MIN 1e-4
+#define CS_MLP_X_MAX 1e2
+
+cs_status cs_mlp_create(cs_ctx* ctx, const int32_t* widths, int32_t n_widths, const float* init_params_host,
+                        cs_mlp** out); /* init_params_host: n_params floats, or NULL for zeros */
+cs_status cs_mlp_destroy(cs_mlp* mlp);
+int64_t cs_mlp_num_params(const cs_mlp* mlp); /* -1 for NULL */
+/* Synchronous host copies of the FP32 master parameters.  Setting them
+ * invalidates the BF16 / FP8 copies and keeps the Adam state. */
+cs_status cs_mlp_set_params(cs_mlp* mlp, const float* host, int64_t n);
+cs_status cs_mlp_get_params(const cs_mlp* mlp, float* host, int64_t n);
+/* Save / load (synchronous): a versioned binary file with the widths, the
+ * FP32 parameters, the Adam moments and step count, and a checksum.
+ * CS_ERR_IO on a missing, truncated or corrupt file. */
+cs_status cs_mlp_save(const cs_mlp* mlp, const char* path);
+cs_status cs_mlp_load(cs_ctx* ctx, const char* path, cs_mlp** out);
+
+/* Prepare the reduced-precision copy used by `precision` (MLP_BF16: weights
+ * rounded to BF16; MLP_FP8: weights and layer inputs scaled per layer by
+ * amax/448 and rounded to OCP FP8 E4M3, the input scales calibrated on the n
+ * device samples (calib_x, calib_u), which must lie in the trained range).
+ * MLP_F32 needs no preparation.  Queues work on `stream`. */
+cs_status cs_mlp_quantize(cs_ctx* ctx, cs_mlp* mlp, cs_sampler precision, const float* calib_x,
+                          const float* calib_u, int64_t n, void* stream);
+
+/* Raw network outputs y[2 i], y[2 i + 1] = (mu_hat, r_hat) for n device
+ * inputs, in `precision` (F32 on the VALU; BF16 / FP8 on MFMA with FP32
+ * accumulation; first and last layers FP32).  No range check. */
+cs_status cs_mlp_forward(cs_ctx* ctx, const cs_mlp* mlp, cs_sampler precision, const float* x, const float* u,
+                         int64_t n, float* y_out, void* stream);
+
+/* Sampler: mu_out[i] = clamp(mu_hat, -1, 1), ratio_out[i] = 1/(1 + x(1 - mu));
+ * where x is outside [CS_MLP_X_MIN, CS_MLP_X_MAX] the plain sampler answers
+ * and fallback_mask[i] = 1 (nullable mask, else 0). */
+cs_status cs_mlp_sample(cs_ctx* ctx, const cs_mlp* mlp, cs_sampler precision, const float* x, const float* u,
+                        int64_t n, float* mu_out, float* ratio_out, uint8_t* fallback_mask, void* stream);
+
+/* Gradient of the loss (MSE: 1/(2n) sum (y - t)^2; MAE: 1/(2n) sum |y - t|)
+ * over the n device samples with targets (mu_t, r_t), FP32, reduced over the
+ * batch in a fixed order (bitwise reproducible).  grad_out: device,
+ * n_params floats; loss_out: nullable device float. */
+cs_status cs_mlp_grad(cs_ctx* ctx, const cs_mlp* mlp, const float* x, const float* u, const float* mu_t,
+                      const float* r_t, int64_t n, cs_loss loss, float* grad_out, float* loss_out, void* stream);
+/* One Adam update (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) with
+ * the given device gradient. */
+cs_status cs_mlp_adam_step(cs_ctx* ctx, cs_mlp* mlp, const float* grad, float lr, void* stream);
+/* cs_mlp_grad followed by cs_mlp_adam_step (the paper's learning rate is
+ * 1e-3).  Invalidates the BF16 / FP8 copies. */
+cs_status cs_mlp_train_step(cs_ctx* ctx, cs_mlp* mlp, const float* x, const float* u, const float* mu_t,
+                            const float* r_t, int64_t n, float lr, cs_loss loss, float* loss_out, void* stream);
+
 /* --------------------------------------------------------- options ------ */
 
 /* Kernel strategies of cs_compton_step; all give bitwise-identical results. */

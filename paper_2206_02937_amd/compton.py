@@ -73,14 +73,14 @@ def lib():
     L.cs_set_stage_timing.restype = st
     L.cs_stage_times.argtypes = [vp, C.POINTER(C.c_float), i32, C.POINTER(i32)]
     L.cs_stage_times.restype = st
-    _optional(L)
+    _bind_mlp(L)
     _lib = L
     return L
 
 
-def _optional(L):
-    """Bind the network entry points when the library exports them."""
-    vp, i64, u64, i32, f = C.c_void_p, C.c_int64, C.c_uint64, C.c_int32, C.c_float
+def _bind_mlp(L):
+    """Signatures of the network entry points."""
+    vp, i64, i32, f = C.c_void_p, C.c_int64, C.c_int32, C.c_float
     st = C.c_int
     sigs = {
         "cs_mlp_create": ([vp, C.POINTER(i32), i32, vp, C.POINTER(vp)], st),
@@ -98,10 +98,9 @@ def _optional(L):
         "cs_mlp_train_step": ([vp, vp, vp, vp, vp, vp, i64, f, C.c_int, vp, vp], st),
     }
     for name, (args, res) in sigs.items():
-        if hasattr(L, name):
-            fn = getattr(L, name)
-            fn.argtypes = args
-            fn.restype = res
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
 
 
 def _ptr(t):
@@ -227,6 +226,116 @@ class Context:
                                    _ptr(ratio_out), _stream(stream))
         self._check(rc)
         return mu_out, ratio_out
+
+
+WIDTHS = (2, 64, 64, 64, 64, 2)
+X_MIN, X_MAX = 1e-4, 1e2
+
+
+class MLP:
+    """The sampler network on one device: FP32 parameters, Adam state and the
+    BF16 / FP8 copies the MFMA kernels read.  Parameters cross the boundary as
+    a flat float32 vector (per layer W[n_out, n_in] row-major, then b)."""
+
+    def __init__(self, ctx, params=None, _handle=None):
+        self.ctx = ctx
+        if _handle is not None:
+            self._h = _handle
+            return
+        self._h = C.c_void_p()
+        w = (C.c_int32 * len(WIDTHS))(*WIDTHS)
+        host = None
+        if params is not None:
+            host = np.ascontiguousarray(params, dtype=np.float32)
+        rc = lib().cs_mlp_create(ctx.handle, w, len(WIDTHS),
+                                 None if host is None else host.ctypes.data_as(C.c_void_p), C.byref(self._h))
+        ctx._check(rc)
+
+    @classmethod
+    def load(cls, ctx, path):
+        h = C.c_void_p()
+        ctx._check(lib().cs_mlp_load(ctx.handle, os.fsencode(path), C.byref(h)))
+        return cls(ctx, _handle=h)
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def n_params(self):
+        return int(lib().cs_mlp_num_params(self._h))
+
+    def close(self):
+        if self._h:
+            lib().cs_mlp_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _rc(self, rc, what):
+        if rc != CS_OK:
+            raise CSError(rc, what)
+
+    def get_params(self):
+        out = np.empty(self.n_params, dtype=np.float32)
+        self._rc(lib().cs_mlp_get_params(self._h, out.ctypes.data_as(C.c_void_p), out.size), "cs_mlp_get_params")
+        return out
+
+    def set_params(self, params):
+        host = np.ascontiguousarray(params, dtype=np.float32)
+        self._rc(lib().cs_mlp_set_params(self._h, host.ctypes.data_as(C.c_void_p), host.size), "cs_mlp_set_params")
+
+    def save(self, path):
+        self._rc(lib().cs_mlp_save(self._h, os.fsencode(path)), f"cs_mlp_save({path})")
+
+    def quantize(self, precision, calib_x=None, calib_u=None, stream=None):
+        n = 0 if calib_x is None else calib_x.numel()
+        self.ctx._check(lib().cs_mlp_quantize(self.ctx.handle, self._h, SAMPLERS[precision], _ptr(calib_x),
+                                              _ptr(calib_u), n, _stream(stream)))
+
+    def forward(self, x, u, precision="mlp_f32", y_out=None, stream=None):
+        """Raw outputs y[n, 2] (float32 device tensor)."""
+        import torch
+
+        y_out = torch.empty((x.numel(), 2), dtype=torch.float32, device=x.device) if y_out is None else y_out
+        self.ctx._check(lib().cs_mlp_forward(self.ctx.handle, self._h, SAMPLERS[precision], _ptr(x), _ptr(u),
+                                             x.numel(), _ptr(y_out), _stream(stream)))
+        return y_out
+
+    def sample(self, x, u, precision="mlp_f32", stream=None):
+        """(mu, ratio, fallback mask) for x, u (float32 device tensors)."""
+        import torch
+
+        mu = torch.empty_like(x)
+        r = torch.empty_like(x)
+        mask = torch.empty(x.numel(), dtype=torch.uint8, device=x.device)
+        self.ctx._check(lib().cs_mlp_sample(self.ctx.handle, self._h, SAMPLERS[precision], _ptr(x), _ptr(u),
+                                            x.numel(), _ptr(mu), _ptr(r), _ptr(mask), _stream(stream)))
+        return mu, r, mask
+
+    def grad(self, x, u, mu_t, r_t, loss="mse", stream=None):
+        """(loss, gradient) as device tensors (shape [], [n_params])."""
+        import torch
+
+        g = torch.empty(self.n_params, dtype=torch.float32, device=x.device)
+        l = torch.empty((), dtype=torch.float32, device=x.device)
+        self.ctx._check(lib().cs_mlp_grad(self.ctx.handle, self._h, _ptr(x), _ptr(u), _ptr(mu_t), _ptr(r_t),
+                                          x.numel(), LOSSES[loss], _ptr(g), _ptr(l), _stream(stream)))
+        return l, g
+
+    def adam_step(self, grad, lr=1e-3, stream=None):
+        self.ctx._check(lib().cs_mlp_adam_step(self.ctx.handle, self._h, _ptr(grad), float(lr), _stream(stream)))
+
+    def train_step(self, x, u, mu_t, r_t, lr=1e-3, loss="mse", loss_out=None, stream=None):
+        """One optimiser step on the batch; the loss (before the update) is
+        written to loss_out (a float32 device scalar) when given."""
+        self.ctx._check(lib().cs_mlp_train_step(self.ctx.handle, self._h, _ptr(x), _ptr(u), _ptr(mu_t), _ptr(r_t),
+                                                x.numel(), float(lr), LOSSES[loss], _ptr(loss_out),
+                                                _stream(stream)))
 
 
 def to_device(p, device="cuda:0"):

@@ -8,11 +8,13 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "cs_internal.h"
 
 namespace cs {
 int64_t step_scan_tmp_len(int64_t n_cells, int64_t n_chunks);
+hipError_t launch_mlp_adam(float* params, float* m, float* v, const float* grad, float lr, int64_t t, hipStream_t st);
 }
 
 namespace {
@@ -340,6 +342,319 @@ cs_status cs_stage_times(cs_ctx* ctx, float* ms_out, int32_t n, int32_t* n_writt
     if (n_written) *n_written = m;
     ctx->last_error.clear();
     return CS_OK;
+}
+
+// ---------------------------------------------------------------- network
+
+namespace {
+
+const int32_t kWidths[6] = {2, 64, 64, 64, 64, 2};
+const char kMagic[8] = {'C', 'S', 'M', 'L', 'P', '0', '0', '1'};
+
+uint64_t fnv1a(const void* data, size_t n, uint64_t h) {
+    const unsigned char* p = (const unsigned char*)data;
+    for (size_t i = 0; i < n; ++i) {
+        h ^= p[i];
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+void mlp_free(cs_mlp* m) {
+    if (!m) return;
+    (void)hipFree(m->params);
+    (void)hipFree(m->adam_m);
+    (void)hipFree(m->adam_v);
+    (void)hipFree(m->frag_bf16);
+    (void)hipFree(m->frag_fp8);
+    (void)hipFree(m->fp8_scales);
+    (void)hipFree(m->work);
+    delete m;
+}
+
+cs_status mlp_alloc(cs_ctx* ctx, cs_mlp** out) {
+    cs_mlp* m = new (std::nothrow) cs_mlp();
+    if (!m) return fail(ctx, CS_ERR_INVALID_ARG, "cs_mlp_create: out of host memory");
+    m->device = ctx->device;
+    const size_t pb = sizeof(float) * cs::kMlpParams;
+    hipError_t e = hipMalloc(&m->params, pb);
+    if (e == hipSuccess) e = hipMalloc(&m->adam_m, pb);
+    if (e == hipSuccess) e = hipMalloc(&m->adam_v, pb);
+    if (e == hipSuccess) e = hipMalloc(&m->frag_bf16, (size_t)cs::kFragCount * 16);
+    if (e == hipSuccess) e = hipMalloc(&m->frag_fp8, (size_t)cs::kFragCount * 8);
+    if (e == hipSuccess) e = hipMalloc(&m->fp8_scales, 16 * sizeof(float));
+    if (e == hipSuccess) e = hipMemset(m->params, 0, pb);
+    if (e == hipSuccess) e = hipMemset(m->adam_m, 0, pb);
+    if (e == hipSuccess) e = hipMemset(m->adam_v, 0, pb);
+    if (e == hipSuccess) e = hipMemset(m->fp8_scales, 0, 16 * sizeof(float));
+    if (e != hipSuccess) {
+        mlp_free(m);
+        return hip_fail(ctx, e, "cs_mlp_create: device allocation");
+    }
+    *out = m;
+    return CS_OK;
+}
+
+bool widths_ok(const int32_t* w, int32_t n) {
+    if (!w || n != 6) return false;
+    for (int i = 0; i < 6; ++i)
+        if (w[i] != kWidths[i]) return false;
+    return true;
+}
+
+cs_status mlp_work(cs_ctx* ctx, cs_mlp* m, size_t bytes, hipStream_t st) {
+    if (m->work_bytes >= bytes) return CS_OK;
+    hipError_t e = hipStreamSynchronize(st);
+    if (e == hipSuccess && m->work) e = hipFree(m->work);
+    m->work = nullptr;
+    m->work_bytes = 0;
+    if (e == hipSuccess) e = hipMalloc(&m->work, bytes);
+    if (e != hipSuccess) return hip_fail(ctx, e, "network workspace");
+    m->work_bytes = bytes;
+    return CS_OK;
+}
+
+cs_status check_precision(cs_ctx* ctx, const cs_mlp* m, cs_sampler p, const char* who) {
+    if (p == CS_SAMPLER_MLP_F32) return CS_OK;
+    if (p == CS_SAMPLER_MLP_BF16) {
+        if (!m->bf16_ready) return fail(ctx, CS_ERR_NOT_READY, std::string(who) + ": BF16 weights not prepared");
+        return CS_OK;
+    }
+    if (p == CS_SAMPLER_MLP_FP8) {
+        if (!m->fp8_ready) return fail(ctx, CS_ERR_NOT_READY, std::string(who) + ": FP8 weights not prepared");
+        return CS_OK;
+    }
+    return fail(ctx, CS_ERR_INVALID_ARG, std::string(who) + ": bad precision");
+}
+
+}  // namespace
+
+cs_status cs_mlp_create(cs_ctx* ctx, const int32_t* widths, int32_t n_widths, const float* init_params_host,
+                        cs_mlp** out) {
+    if (!ctx) return CS_ERR_INVALID_ARG;
+    if (!out) return fail(ctx, CS_ERR_INVALID_ARG, "cs_mlp_create: out is NULL");
+    *out = nullptr;
+    if (!widths || n_widths < 2) return fail(ctx, CS_ERR_INVALID_ARG, "cs_mlp_create: widths");
+    if (!widths_ok(widths, n_widths))
+        return fail(ctx, CS_ERR_UNSUPPORTED, "cs_mlp_create: kernels take widths {2, 64, 64, 64, 64, 2} only");
+    DeviceGuard g(ctx->device);
+    cs_mlp* m = nullptr;
+    cs_status s = mlp_alloc(ctx, &m);
+    if (s != CS_OK) return s;
+    if (init_params_host) {
+        hipError_t e = hipMemcpy(m->params, init_params_host, sizeof(float) * cs::kMlpParams, hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            mlp_free(m);
+            return hip_fail(ctx, e, "cs_mlp_create: parameter upload");
+        }
+    }
+    *out = m;
+    ctx->last_error.clear();
+    return CS_OK;
+}
+
+cs_status cs_mlp_destroy(cs_mlp* mlp) {
+    if (!mlp) return CS_ERR_INVALID_ARG;
+    DeviceGuard g(mlp->device);
+    (void)hipDeviceSynchronize();
+    mlp_free(mlp);
+    return CS_OK;
+}
+
+int64_t cs_mlp_num_params(const cs_mlp* mlp) { return mlp ? (int64_t)cs::kMlpParams : -1; }
+
+cs_status cs_mlp_set_params(cs_mlp* mlp, const float* host, int64_t n) {
+    if (!mlp || !host || n != cs::kMlpParams) return CS_ERR_INVALID_ARG;
+    DeviceGuard g(mlp->device);
+    if (hipDeviceSynchronize() != hipSuccess) return CS_ERR_HIP;
+    if (hipMemcpy(mlp->params, host, sizeof(float) * n, hipMemcpyHostToDevice) != hipSuccess) return CS_ERR_HIP;
+    mlp->bf16_ready = mlp->fp8_ready = false;
+    return CS_OK;
+}
+
+cs_status cs_mlp_get_params(const cs_mlp* mlp, float* host, int64_t n) {
+    if (!mlp || !host || n != cs::kMlpParams) return CS_ERR_INVALID_ARG;
+    DeviceGuard g(mlp->device);
+    if (hipDeviceSynchronize() != hipSuccess) return CS_ERR_HIP;
+    if (hipMemcpy(host, mlp->params, sizeof(float) * n, hipMemcpyDeviceToHost) != hipSuccess) return CS_ERR_HIP;
+    return CS_OK;
+}
+
+cs_status cs_mlp_save(const cs_mlp* mlp, const char* path) {
+    if (!mlp || !path) return CS_ERR_INVALID_ARG;
+    DeviceGuard g(mlp->device);
+    const size_t n = cs::kMlpParams;
+    std::string buf;
+    std::vector<float> p(n), m(n), v(n);
+    if (hipDeviceSynchronize() != hipSuccess) return CS_ERR_HIP;
+    if (hipMemcpy(p.data(), mlp->params, 4 * n, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(m.data(), mlp->adam_m, 4 * n, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(v.data(), mlp->adam_v, 4 * n, hipMemcpyDeviceToHost) != hipSuccess)
+        return CS_ERR_HIP;
+    const int32_t nw = 6;
+    const int64_t np = (int64_t)n, t = mlp->adam_t;
+    buf.append(kMagic, 8);
+    buf.append((const char*)&nw, 4);
+    buf.append((const char*)kWidths, 24);
+    buf.append((const char*)&np, 8);
+    buf.append((const char*)&t, 8);
+    buf.append((const char*)p.data(), 4 * n);
+    buf.append((const char*)m.data(), 4 * n);
+    buf.append((const char*)v.data(), 4 * n);
+    const uint64_t h = fnv1a(buf.data(), buf.size(), 1469598103934665603ull);
+    buf.append((const char*)&h, 8);
+    FILE* f = fopen(path, "wb");
+    if (!f) return CS_ERR_IO;
+    const size_t wr = fwrite(buf.data(), 1, buf.size(), f);
+    const int cl = fclose(f);
+    return (wr == buf.size() && cl == 0) ? CS_OK : CS_ERR_IO;
+}
+
+cs_status cs_mlp_load(cs_ctx* ctx, const char* path, cs_mlp** out) {
+    if (!ctx) return CS_ERR_INVALID_ARG;
+    if (!path || !out) return fail(ctx, CS_ERR_INVALID_ARG, "cs_mlp_load: NULL argument");
+    *out = nullptr;
+    FILE* f = fopen(path, "rb");
+    if (!f) return fail(ctx, CS_ERR_IO, std::string("cs_mlp_load: cannot open ") + path);
+    std::string buf;
+    char tmp[65536];
+    size_t r;
+    while ((r = fread(tmp, 1, sizeof(tmp), f)) > 0) buf.append(tmp, r);
+    fclose(f);
+    const size_t n = cs::kMlpParams;
+    const size_t need = 8 + 4 + 24 + 8 + 8 + 3 * 4 * n + 8;
+    if (buf.size() != need) return fail(ctx, CS_ERR_IO, "cs_mlp_load: wrong file size");
+    if (memcmp(buf.data(), kMagic, 8) != 0) return fail(ctx, CS_ERR_IO, "cs_mlp_load: bad magic");
+    uint64_t h;
+    memcpy(&h, buf.data() + need - 8, 8);
+    if (fnv1a(buf.data(), need - 8, 1469598103934665603ull) != h) return fail(ctx, CS_ERR_IO, "cs_mlp_load: checksum");
+    int32_t nw;
+    int32_t w[6];
+    int64_t np, t;
+    memcpy(&nw, buf.data() + 8, 4);
+    memcpy(w, buf.data() + 12, 24);
+    memcpy(&np, buf.data() + 36, 8);
+    memcpy(&t, buf.data() + 44, 8);
+    if (!widths_ok(w, nw) || np != (int64_t)n) return fail(ctx, CS_ERR_IO, "cs_mlp_load: unsupported widths");
+    DeviceGuard g(ctx->device);
+    cs_mlp* m = nullptr;
+    cs_status s = mlp_alloc(ctx, &m);
+    if (s != CS_OK) return s;
+    const char* base = buf.data() + 52;
+    hipError_t e = hipMemcpy(m->params, base, 4 * n, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(m->adam_m, base + 4 * n, 4 * n, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(m->adam_v, base + 8 * n, 4 * n, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        mlp_free(m);
+        return hip_fail(ctx, e, "cs_mlp_load: upload");
+    }
+    m->adam_t = t;
+    *out = m;
+    ctx->last_error.clear();
+    return CS_OK;
+}
+
+cs_status cs_mlp_quantize(cs_ctx* ctx, cs_mlp* mlp, cs_sampler precision, const float* calib_x,
+                          const float* calib_u, int64_t n, void* stream) {
+    if (!ctx) return CS_ERR_INVALID_ARG;
+    if (!mlp) return fail(ctx, CS_ERR_INVALID_ARG, "cs_mlp_quantize: NULL network");
+    if (precision == CS_SAMPLER_MLP_F32) return CS_OK;
+    if (precision != CS_SAMPLER_MLP_BF16 && precision != CS_SAMPLER_MLP_FP8)
+        return fail(ctx, CS_ERR_INVALID_ARG, "cs_mlp_quantize: bad precision");
+    if (precision == CS_SAMPLER_MLP_FP8 && (!calib_x || !calib_u || n <= 0))
+        return fail(ctx, CS_ERR_INVALID_ARG, "cs_mlp_quantize: FP8 needs calibration samples");
+    DeviceGuard g(mlp->device);
+    hipError_t e = cs::launch_mlp_quantize(mlp->params, mlp->frag_bf16, mlp->frag_fp8, mlp->fp8_scales, precision,
+                                           calib_x, calib_u, n, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "cs_mlp_quantize: launch");
+    if (precision == CS_SAMPLER_MLP_BF16)
+        mlp->bf16_ready = true;
+    else
+        mlp->fp8_ready = true;
+    ctx->last_error.clear();
+    return CS_OK;
+}
+
+cs_status cs_mlp_forward(cs_ctx* ctx, const cs_mlp* mlp, cs_sampler precision, const float* x, const float* u,
+                         int64_t n, float* y_out, void* stream) {
+    if (!ctx) return CS_ERR_INVALID_ARG;
+    if (!mlp || n < 0 || (n > 0 && (!x || !u || !y_out)))
+        return fail(ctx, CS_ERR_INVALID_ARG, "cs_mlp_forward: bad argument");
+    cs_status s = check_precision(ctx, mlp, precision, "cs_mlp_forward");
+    if (s != CS_OK) return s;
+    DeviceGuard g(mlp->device);
+    hipError_t e = cs::launch_mlp_forward(mlp->dev(), precision, x, u, n, y_out, nullptr, nullptr, nullptr,
+                                          (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "cs_mlp_forward: launch");
+    ctx->last_error.clear();
+    return CS_OK;
+}
+
+cs_status cs_mlp_sample(cs_ctx* ctx, const cs_mlp* mlp, cs_sampler precision, const float* x, const float* u,
+                        int64_t n, float* mu_out, float* ratio_out, uint8_t* fallback_mask, void* stream) {
+    if (!ctx) return CS_ERR_INVALID_ARG;
+    if (!mlp || n < 0 || (n > 0 && (!x || !u || !mu_out || !ratio_out)))
+        return fail(ctx, CS_ERR_INVALID_ARG, "cs_mlp_sample: bad argument");
+    cs_status s = check_precision(ctx, mlp, precision, "cs_mlp_sample");
+    if (s != CS_OK) return s;
+    DeviceGuard g(mlp->device);
+    hipError_t e = cs::launch_mlp_forward(mlp->dev(), precision, x, u, n, nullptr, mu_out, ratio_out, fallback_mask,
+                                          (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "cs_mlp_sample: launch");
+    ctx->last_error.clear();
+    return CS_OK;
+}
+
+static cs_status mlp_grad_impl(cs_ctx* ctx, cs_mlp* mlp, const float* x, const float* u, const float* mu_t,
+                               const float* r_t, int64_t n, cs_loss loss, float* grad_out, float* loss_out,
+                               bool adam, float lr, void* stream, const char* who) {
+    if (!ctx) return CS_ERR_INVALID_ARG;
+    if (!mlp || n <= 0 || !x || !u || !mu_t || !r_t)
+        return fail(ctx, CS_ERR_INVALID_ARG, std::string(who) + ": bad argument");
+    if (loss != CS_LOSS_MSE && loss != CS_LOSS_MAE) return fail(ctx, CS_ERR_INVALID_ARG, std::string(who) + ": loss");
+    if (adam && !(lr > 0.0f)) return fail(ctx, CS_ERR_INVALID_ARG, std::string(who) + ": lr must be > 0");
+    DeviceGuard g(mlp->device);
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t blocks = cs::mlp_grad_blocks(n);
+    const size_t bytes = (size_t)blocks * cs::kMlpParams * 4 + (size_t)blocks * 4 + 256;
+    cs_status s = mlp_work(ctx, mlp, bytes, st);
+    if (s != CS_OK) return s;
+    float* partials = mlp->work;
+    float* loss_partials = partials + (size_t)blocks * cs::kMlpParams;
+    if (adam) mlp->adam_t += 1;
+    hipError_t e = cs::launch_mlp_grad(mlp->dev(), x, u, mu_t, r_t, n, (int)loss, partials, loss_partials, grad_out,
+                                       loss_out, mlp->adam_m, mlp->adam_v, adam ? mlp->params : nullptr, lr,
+                                       mlp->adam_t, st);
+    if (e != hipSuccess) return hip_fail(ctx, e, (std::string(who) + ": launch").c_str());
+    if (adam) mlp->bf16_ready = mlp->fp8_ready = false;
+    ctx->last_error.clear();
+    return CS_OK;
+}
+
+cs_status cs_mlp_grad(cs_ctx* ctx, const cs_mlp* mlp, const float* x, const float* u, const float* mu_t,
+                      const float* r_t, int64_t n, cs_loss loss, float* grad_out, float* loss_out, void* stream) {
+    if (ctx && mlp && !grad_out) return fail(ctx, CS_ERR_INVALID_ARG, "cs_mlp_grad: grad_out is NULL");
+    return mlp_grad_impl(ctx, const_cast<cs_mlp*>(mlp), x, u, mu_t, r_t, n, loss, grad_out, loss_out, false, 0.0f,
+                         stream, "cs_mlp_grad");
+}
+
+cs_status cs_mlp_adam_step(cs_ctx* ctx, cs_mlp* mlp, const float* grad, float lr, void* stream) {
+    if (!ctx) return CS_ERR_INVALID_ARG;
+    if (!mlp || !grad || !(lr > 0.0f)) return fail(ctx, CS_ERR_INVALID_ARG, "cs_mlp_adam_step: bad argument");
+    DeviceGuard g(mlp->device);
+    mlp->adam_t += 1;
+    hipError_t e = cs::launch_mlp_adam(mlp->params, mlp->adam_m, mlp->adam_v, grad, lr, mlp->adam_t,
+                                       (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "cs_mlp_adam_step: launch");
+    mlp->bf16_ready = mlp->fp8_ready = false;
+    ctx->last_error.clear();
+    return CS_OK;
+}
+
+cs_status cs_mlp_train_step(cs_ctx* ctx, cs_mlp* mlp, const float* x, const float* u, const float* mu_t,
+                            const float* r_t, int64_t n, float lr, cs_loss loss, float* loss_out, void* stream) {
+    return mlp_grad_impl(ctx, mlp, x, u, mu_t, r_t, n, loss, nullptr, loss_out, true, lr, stream,
+                         "cs_mlp_train_step");
 }
 
 }  // extern "C"

@@ -163,7 +163,51 @@ hipError_t launch_check_layout(const int64_t* off, int64_t n_cells, int64_t n, i
 hipError_t launch_sample_plain(cs_dtype dtype, const void* x, const void* u, int64_t n, void* mu, void* ratio,
                                hipStream_t stream);
 
+// ---------------------------------------------------------------------------
+// The sampler network (fixed widths 2 -> 64 x 4 -> 2).
+// ---------------------------------------------------------------------------
+constexpr int kMlpHidden = 64;
+constexpr int kMlpParams = 12802;
+// parameter offsets: W1[64][2], b1, W2[64][64], b2, W3, b3, W4, b4, W5[2][64], b5
+constexpr int kOffW1 = 0, kOffB1 = 128, kOffW2 = 192, kOffB2 = 4288, kOffW3 = 4352, kOffB3 = 8448,
+              kOffW4 = 8512, kOffB4 = 12608, kOffW5 = 12672, kOffB5 = 12800;
+// MFMA fragments of the three hidden 64x64 layers: [layer][tile_out][kstep][lane]
+constexpr int kFragCount = 3 * 4 * 2 * 64;
+
+struct MlpDev {
+    const float* params;        // FP32 master
+    const void* frag_bf16;      // kFragCount x 8 bf16
+    const void* frag_fp8;       // kFragCount x 8 fp8 (E4M3)
+    const float* fp8_scales;    // [0..2] weight scales, [3..5] input scales, [6..8] input amax
+};
+
+hipError_t launch_mlp_forward(const MlpDev& m, cs_sampler prec, const float* x, const float* u, int64_t n,
+                              float* y, float* mu, float* ratio, uint8_t* mask, hipStream_t st);
+hipError_t launch_mlp_grad(const MlpDev& m, const float* x, const float* u, const float* mu_t, const float* r_t,
+                           int64_t n, int loss, float* partials, float* loss_partials, float* grad_out,
+                           float* loss_out, float* adam_m, float* adam_v, float* params_rw, float lr, int64_t t,
+                           hipStream_t st);
+hipError_t launch_mlp_quantize(float* params, void* frag_bf16, void* frag_fp8, float* scales, cs_sampler prec,
+                               const float* cx, const float* cu, int64_t n, hipStream_t st);
+int64_t mlp_grad_blocks(int64_t n);
+
 }  // namespace cs
+
+struct cs_mlp {
+    int device = 0;
+    int32_t widths[6] = {2, 64, 64, 64, 64, 2};
+    float* params = nullptr;  // device FP32 master
+    float* adam_m = nullptr;
+    float* adam_v = nullptr;
+    int64_t adam_t = 0;
+    void* frag_bf16 = nullptr;
+    void* frag_fp8 = nullptr;
+    float* fp8_scales = nullptr;
+    bool bf16_ready = false, fp8_ready = false;
+    float* work = nullptr;  // gradient partials, loss partials, gradient
+    size_t work_bytes = 0;
+    cs::MlpDev dev() const { return {params, frag_bf16, frag_fp8, fp8_scales}; }
+};
 
 struct cs_ctx {
     int device = 0;

@@ -1,0 +1,698 @@
+// cs_mlp.hip -- kernels of the sampler network (2 -> 64 x4 (SiLU) -> 2).
+//
+// FP32 engine (training, FP32 inference, calibration): one workgroup of 256
+// lanes holds 64 samples; its four waves split every layer's 64 output
+// neurons (wave w computes neurons 16w..16w+15 for all 64 samples), reading
+// the sample's input row from LDS (128-bit loads) and the weights as
+// wave-uniform scalar loads.  Backward keeps SiLU'(z) in registers (the lane
+// that produced z consumes it), the layer outputs in LDS for the weight
+// gradients, and writes one partial gradient per workgroup; a second kernel
+// sums the partials in a fixed order (bitwise reproducible) and applies Adam.
+//
+// MFMA engine (BF16 / FP8 inference): a wave evaluates a tile of 16 samples
+// with v_mfma_f32_16x16x32_{bf16,fp8}.  Lane l owns sample l%16 and, in group
+// g = l/16, the neurons 16t + 4g + r (t, r = 0..3): exactly the rows of the
+// accumulator fragment it holds, so a layer's output stays in registers and
+// becomes the next layer's B operand once the weight fragments list the input
+// neurons in the same order (k-slot 8g + e of k-step s <-> neuron
+// 16(2s + e/4) + 4g + e%4).  Layers 1 and 5 (K = 2, N = 2) are FP32 VALU.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "cs_block.h"
+#include "cs_device.h"
+#include "cs_internal.h"
+
+namespace cs {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr int kMlpThreads = 256;
+constexpr int kMlpSamples = 64;  // samples per FP32 workgroup
+constexpr int kRow = 68;         // LDS row stride (floats), 16-byte aligned rows
+constexpr float kE4M3Max = 448.0f;
+
+__device__ __forceinline__ float silu_f32(float z) { return z / (1.0f + expf(-z)); }
+__device__ __forceinline__ float silu_grad_f32(float z) {
+    const float s = 1.0f / (1.0f + expf(-z));
+    return s * (1.0f + z * (1.0f - s));
+}
+// SiLU for the reduced-precision paths (its result is rounded to BF16/FP8)
+__device__ __forceinline__ float silu_fast(float z) { return z * __frcp_rn(1.0f + __expf(-z)); }
+
+__device__ __forceinline__ void features(float x, float u, float& f1, float& f2) {
+    f1 = (log10f(x) + 1.0f) / 3.0f;
+    f2 = 2.0f * u - 1.0f;
+}
+
+__device__ __forceinline__ int wave_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// ---------------------------------------------------------------------------
+// FP32 engine pieces
+// ---------------------------------------------------------------------------
+// Layer 1 (2 -> 64) for this lane's 16 neurons [16w, 16w+16) of sample s.
+__device__ __forceinline__ void fwd_first(const float* P, int w, float f1, float f2, float z[16]) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int j = 16 * w + i;
+        z[i] = fmaf(P[kOffW1 + 2 * j + 1], f2, fmaf(P[kOffW1 + 2 * j], f1, P[kOffB1 + j]));
+    }
+}
+
+// Hidden layer (64 -> 64): z_j = b_j + sum_k W[j][k] h[k], k ascending.
+__device__ __forceinline__ void fwd_hidden(const float* W, const float* b, int w, const float* hrow, float z[16]) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) z[i] = b[16 * w + i];
+#pragma unroll 4
+    for (int k = 0; k < kMlpHidden; k += 4) {
+        const float4 hv = *(const float4*)(hrow + k);
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const float* wr = W + (16 * w + i) * kMlpHidden + k;
+            float a = z[i];
+            a = fmaf(wr[0], hv.x, a);
+            a = fmaf(wr[1], hv.y, a);
+            a = fmaf(wr[2], hv.z, a);
+            a = fmaf(wr[3], hv.w, a);
+            z[i] = a;
+        }
+    }
+}
+
+// Output layer (64 -> 2) for one sample, k ascending.
+__device__ __forceinline__ void fwd_out(const float* P, const float* hrow, float& y0, float& y1) {
+    float a0 = P[kOffB5], a1 = P[kOffB5 + 1];
+#pragma unroll 8
+    for (int k = 0; k < kMlpHidden; ++k) {
+        a0 = fmaf(P[kOffW5 + k], hrow[k], a0);
+        a1 = fmaf(P[kOffW5 + kMlpHidden + k], hrow[k], a1);
+    }
+    y0 = a0;
+    y1 = a1;
+}
+
+__device__ __forceinline__ uint32_t float_bits(float f) { return __float_as_uint(f); }
+
+// Forward pass of one FP32 workgroup; the last hidden output ends in H[1]
+// (ping-pong buffers H[0], H[1]).  amax (nullable): running max |h| of the
+// inputs of hidden layers 2..4, as float bits.
+__device__ __forceinline__ void fwd_block_f32(const float* P, float f1, float f2, bool active, float (*H)[kMlpSamples][kRow],
+                                              uint32_t* amax) {
+    const int tid = threadIdx.x;
+    const int w = wave_uniform(tid >> 6);
+    const int s = tid & 63;
+    float z[16];
+    fwd_first(P, w, f1, f2, z);
+    float m = 0.0f;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const float h = silu_f32(z[i]);
+        H[0][s][16 * w + i] = h;
+        m = fmaxf(m, fabsf(h));
+    }
+    if (amax && active) atomicMax(&amax[0], float_bits(m));
+    __syncthreads();
+    const float* Ws[3] = {P + kOffW2, P + kOffW3, P + kOffW4};
+    const float* Bs[3] = {P + kOffB2, P + kOffB3, P + kOffB4};
+#pragma unroll 1
+    for (int L = 0; L < 3; ++L) {
+        const int src = L & 1, dst = src ^ 1;
+        fwd_hidden(Ws[L], Bs[L], w, H[src][s], z);
+        __syncthreads();  // all reads of H[src] done before it is overwritten next layer
+        m = 0.0f;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const float h = silu_f32(z[i]);
+            H[dst][s][16 * w + i] = h;
+            m = fmaxf(m, fabsf(h));
+        }
+        if (amax && active && L < 2) atomicMax(&amax[L + 1], float_bits(m));
+        __syncthreads();
+    }
+}
+
+struct FwdArgs {
+    const float* P;
+    const float *x, *u;
+    int64_t n;
+    float* y;      // nullable, 2n
+    float* mu;     // nullable
+    float* ratio;  // nullable
+    uint8_t* mask; // nullable
+    uint32_t* amax;  // nullable: calibration
+};
+
+__device__ __forceinline__ bool in_range(float x) { return x >= (float)CS_MLP_X_MIN && x <= (float)CS_MLP_X_MAX; }
+
+// Sampler reading of the outputs (shared by every precision).
+__device__ __forceinline__ void sampler_out(const FwdArgs& a, int64_t i, float x, float u, float y0) {
+    float mu, r;
+    uint8_t fb = 0;
+    if (in_range(x)) {
+        mu = fminf(fmaxf(y0, -1.0f), 1.0f);
+        r = 1.0f / (1.0f + x * (1.0f - mu));
+    } else {
+        const double v = angle_icdf_v((double)u, (double)x);
+        mu = (float)(1.0 - v);
+        r = (float)(1.0 / (1.0 + (double)x * v));
+        fb = 1;
+    }
+    if (a.mu) a.mu[i] = mu;
+    if (a.ratio) a.ratio[i] = r;
+    if (a.mask) a.mask[i] = fb;
+}
+
+__global__ __launch_bounds__(kMlpThreads) void k_mlp_fwd_f32(const FwdArgs a) {
+    __shared__ float H[2][kMlpSamples][kRow];
+    const int s = threadIdx.x & 63;
+    const int64_t i = (int64_t)blockIdx.x * kMlpSamples + s;
+    const bool active = i < a.n;
+    const float x = active ? a.x[i] : 1.0f, u = active ? a.u[i] : 0.5f;
+    float f1, f2;
+    features(x, u, f1, f2);
+    fwd_block_f32(a.P, f1, f2, active, H, a.amax);
+    if (threadIdx.x < 64 && active) {
+        float y0, y1;
+        fwd_out(a.P, H[1][s], y0, y1);
+        if (a.y) {
+            a.y[2 * i] = y0;
+            a.y[2 * i + 1] = y1;
+        }
+        if (a.mu || a.ratio || a.mask) sampler_out(a, i, x, u, y0);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// training: forward + backward per workgroup, partial gradients
+// ---------------------------------------------------------------------------
+struct GradArgs {
+    const float* P;
+    const float *x, *u, *mu_t, *r_t;
+    int64_t n;
+    int loss;         // 0 MSE, 1 MAE
+    float* partials;  // [blocks][kMlpParams]
+    float* loss_partials;  // [blocks]
+};
+
+// A workgroup walks the 64-sample tiles blockIdx.x, blockIdx.x + gridDim.x,
+// ...; each element of its partial gradient is always produced by the same
+// lane, which adds the tiles in that order (no atomics, reproducible).
+__global__ __launch_bounds__(kMlpThreads) void k_mlp_grad_block(const GradArgs a) {
+    __shared__ float H[4][kMlpSamples][kRow];  // h1..h4
+    __shared__ float D[2][kMlpSamples][kRow];  // delta ping-pong
+    __shared__ float F[kMlpSamples][2];        // features
+    __shared__ float DY[kMlpSamples][2];       // output delta
+    __shared__ float s_loss[kMlpSamples];
+    const int tid = threadIdx.x;
+    const int w = wave_uniform(tid >> 6);
+    const int s = tid & 63;
+    const int64_t n_tiles = (a.n + kMlpSamples - 1) / kMlpSamples;
+    float* out = a.partials + (int64_t)blockIdx.x * kMlpParams;
+    // out[idx] = first tile ? v : out[idx] + v (always the same lane for idx)
+    auto put = [&](int64_t idx, float v, bool first) { out[idx] = first ? v : out[idx] + v; };
+    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        const bool first = tile == (int64_t)blockIdx.x;
+        __syncthreads();  // the previous tile's LDS reads are done
+        const int64_t i = tile * kMlpSamples + s;
+        const bool active = i < a.n;
+        const float* P = a.P;
+        float f1 = 0.0f, f2 = 0.0f;
+        if (active) features(a.x[i], a.u[i], f1, f2);
+        if (w == 0) {
+            F[s][0] = f1;
+            F[s][1] = f2;
+        }
+        // forward; SiLU'(z) of this lane's 16 neurons of every layer in registers
+        float g[4][16];
+        float z[16];
+        fwd_first(P, w, f1, f2, z);
+    #pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            H[0][s][16 * w + k] = silu_f32(z[k]);
+            g[0][k] = silu_grad_f32(z[k]);
+        }
+        __syncthreads();
+        fwd_hidden(P + kOffW2, P + kOffB2, w, H[0][s], z);
+    #pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            H[1][s][16 * w + k] = silu_f32(z[k]);
+            g[1][k] = silu_grad_f32(z[k]);
+        }
+        __syncthreads();
+        fwd_hidden(P + kOffW3, P + kOffB3, w, H[1][s], z);
+    #pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            H[2][s][16 * w + k] = silu_f32(z[k]);
+            g[2][k] = silu_grad_f32(z[k]);
+        }
+        __syncthreads();
+        fwd_hidden(P + kOffW4, P + kOffB4, w, H[2][s], z);
+    #pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            H[3][s][16 * w + k] = silu_f32(z[k]);
+            g[3][k] = silu_grad_f32(z[k]);
+        }
+        __syncthreads();
+        // output layer and loss gradient
+        if (w == 0) {
+            float y0, y1;
+            fwd_out(P, H[3][s], y0, y1);
+            float d0 = 0.0f, d1 = 0.0f, l = 0.0f;
+            if (active) {
+                const float e0 = y0 - a.mu_t[i], e1 = y1 - a.r_t[i];
+                const float inv_n = 1.0f / (float)a.n;
+                if (a.loss == 0) {
+                    d0 = e0 * inv_n;
+                    d1 = e1 * inv_n;
+                    l = 0.5f * (e0 * e0 + e1 * e1) * inv_n;
+                } else {
+                    d0 = (e0 > 0.0f ? 0.5f : (e0 < 0.0f ? -0.5f : 0.0f)) * inv_n;
+                    d1 = (e1 > 0.0f ? 0.5f : (e1 < 0.0f ? -0.5f : 0.0f)) * inv_n;
+                    l = 0.5f * (fabsf(e0) + fabsf(e1)) * inv_n;
+                }
+            }
+            DY[s][0] = d0;
+            DY[s][1] = d1;
+            s_loss[s] = l;
+        }
+        __syncthreads();
+        // layer 5 gradients: dW5[o][k] = sum_s DY[s][o] h4[s][k], db5[o] = sum_s DY[s][o]
+        if (tid < 128) {
+            const int o = tid >> 6, k = tid & 63;
+            float acc = 0.0f;
+            for (int q = 0; q < kMlpSamples; ++q) acc = fmaf(DY[q][o], H[3][q][k], acc);
+            put(kOffW5 + o * kMlpHidden + k, acc, first);
+        } else if (tid < 130) {
+            const int o = tid - 128;
+            float acc = 0.0f;
+            for (int q = 0; q < kMlpSamples; ++q) acc += DY[q][o];
+            put(kOffB5 + o, acc, first);
+        } else if (tid == 130) {
+            float acc = 0.0f;
+            for (int q = 0; q < kMlpSamples; ++q) acc += s_loss[q];
+            a.loss_partials[blockIdx.x] = first ? acc : a.loss_partials[blockIdx.x] + acc;
+        }
+        // delta4 = (W5^T DY) * g4
+    #pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const int j = 16 * w + k;
+            D[0][s][j] = (P[kOffW5 + j] * DY[s][0] + P[kOffW5 + kMlpHidden + j] * DY[s][1]) * g[3][k];
+        }
+        __syncthreads();
+        // hidden layers 4, 3, 2: weight gradient from D[cur] and H[L-1], delta of
+        // the layer below into D[cur ^ 1]
+        const int offW[3] = {kOffW4, kOffW3, kOffW2};
+        const int offB[3] = {kOffB4, kOffB3, kOffB2};
+        int cur = 0;
+    #pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            const int hin = 2 - m;  // H index of the layer input (h3, h2, h1)
+            {
+                // dW[j][k] = sum_s D[s][j] H[s][k] for j = tid%64, k in [16 w, 16 w + 16)
+                const int j = s;
+                float acc[16];
+    #pragma unroll
+                for (int k = 0; k < 16; ++k) acc[k] = 0.0f;
+                float db = 0.0f;
+                for (int q = 0; q < kMlpSamples; ++q) {
+                    const float d = D[cur][q][j];
+                    db += d;
+                    const float* hr = &H[hin][q][16 * w];
+    #pragma unroll
+                    for (int k = 0; k < 16; k += 4) {
+                        const float4 hv = *(const float4*)(hr + k);
+                        acc[k] = fmaf(d, hv.x, acc[k]);
+                        acc[k + 1] = fmaf(d, hv.y, acc[k + 1]);
+                        acc[k + 2] = fmaf(d, hv.z, acc[k + 2]);
+                        acc[k + 3] = fmaf(d, hv.w, acc[k + 3]);
+                    }
+                }
+    #pragma unroll
+                for (int k = 0; k < 16; ++k) put(offW[m] + j * kMlpHidden + 16 * w + k, acc[k], first);
+                if (w == 0) put(offB[m] + j, db, first);
+            }
+            {
+                // delta of the layer below: (W^T D[cur])[s][j] * g, j in this lane's range
+                const float* W = P + offW[m];
+                float acc[16];
+    #pragma unroll
+                for (int k = 0; k < 16; ++k) acc[k] = 0.0f;
+    #pragma unroll 4
+                for (int o = 0; o < kMlpHidden; o += 4) {
+                    const float4 dv = *(const float4*)(&D[cur][s][o]);
+    #pragma unroll
+                    for (int k = 0; k < 16; ++k) {
+                        const int j = 16 * w + k;
+                        float t = acc[k];
+                        t = fmaf(W[(o + 0) * kMlpHidden + j], dv.x, t);
+                        t = fmaf(W[(o + 1) * kMlpHidden + j], dv.y, t);
+                        t = fmaf(W[(o + 2) * kMlpHidden + j], dv.z, t);
+                        t = fmaf(W[(o + 3) * kMlpHidden + j], dv.w, t);
+                        acc[k] = t;
+                    }
+                }
+    #pragma unroll
+                for (int k = 0; k < 16; ++k) D[cur ^ 1][s][16 * w + k] = acc[k] * g[hin][k];
+            }
+            __syncthreads();
+            cur ^= 1;
+        }
+        // layer 1: dW1[j][i] = sum_s D[s][j] F[s][i], db1[j] = sum_s D[s][j]
+        if (tid < 64) {
+            const int j = tid;
+            float a0 = 0.0f, a1 = 0.0f, db = 0.0f;
+            for (int q = 0; q < kMlpSamples; ++q) {
+                const float d = D[cur][q][j];
+                a0 = fmaf(d, F[q][0], a0);
+                a1 = fmaf(d, F[q][1], a1);
+                db += d;
+            }
+            put(kOffW1 + 2 * j, a0, first);
+            put(kOffW1 + 2 * j + 1, a1, first);
+            put(kOffB1 + j, db, first);
+        }
+    }
+}
+
+// Fixed-order sum of the per-workgroup partials; then either write the
+// gradient or apply Adam (FP32 state, bias corrections from the host).
+struct ReduceArgs {
+    const float* partials;
+    const float* loss_partials;
+    int64_t blocks;
+    float* grad_out;  // nullable
+    float* loss_out;  // nullable
+    float* params;    // nullable: apply Adam
+    float *m, *v;
+    float lr, bc1, bc2;
+};
+
+__global__ __launch_bounds__(256) void k_mlp_reduce(const ReduceArgs a) {
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p < kMlpParams) {
+        float g = 0.0f;
+        for (int64_t b = 0; b < a.blocks; ++b) g += a.partials[b * kMlpParams + p];
+        if (a.grad_out) a.grad_out[p] = g;
+        if (a.params) {
+            const float m = 0.9f * a.m[p] + 0.1f * g;
+            const float v = 0.999f * a.v[p] + 0.001f * g * g;
+            a.m[p] = m;
+            a.v[p] = v;
+            const float mh = m / a.bc1, vh = v / a.bc2;
+            a.params[p] -= a.lr * mh / (sqrtf(vh) + 1e-8f);
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0 && a.loss_out) {
+        float l = 0.0f;
+        for (int64_t b = 0; b < a.blocks; ++b) l += a.loss_partials[b];
+        *a.loss_out = l;
+    }
+}
+
+__global__ void k_mlp_adam_only(float* params, float* m_, float* v_, const float* grad, float lr, float bc1,
+                                float bc2) {
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p >= kMlpParams) return;
+    const float g = grad[p];
+    const float m = 0.9f * m_[p] + 0.1f * g;
+    const float v = 0.999f * v_[p] + 0.001f * g * g;
+    m_[p] = m;
+    v_[p] = v;
+    params[p] -= lr * (m / bc1) / (sqrtf(v / bc2) + 1e-8f);
+}
+
+// ---------------------------------------------------------------------------
+// MFMA engine
+// ---------------------------------------------------------------------------
+// Input neuron of k-slot e (0..7) of k-step s in lane group g.
+__host__ __device__ __forceinline__ int frag_in_neuron(int s, int g, int e) { return 16 * (2 * s + e / 4) + 4 * g + (e & 3); }
+
+__device__ __forceinline__ uint8_t to_e4m3(float v) {
+    v = fminf(fmaxf(v, -kE4M3Max), kE4M3Max);  // saturating conversion
+    const uint32_t packed = __builtin_amdgcn_cvt_pk_fp8_f32(v, 0.0f, 0u, false);
+    return (uint8_t)(packed & 0xFFu);
+}
+
+// Build fragments: thread per (layer, tile_out, kstep, lane, e).
+__global__ void k_mlp_build_frag(const float* P, const float* scales, int prec, __bf16* fb, uint8_t* f8) {
+    const int idx = blockIdx.x * 256 + threadIdx.x;
+    if (idx >= kFragCount * 8) return;
+    const int e = idx & 7, lane = (idx >> 3) & 63, s = (idx >> 9) & 1, t = (idx >> 10) & 3, L = idx >> 12;
+    const int offW[3] = {kOffW2, kOffW3, kOffW4};
+    const int row = 16 * t + (lane & 15);
+    const int col = frag_in_neuron(s, lane >> 4, e);
+    const float wv = P[offW[L] + row * kMlpHidden + col];
+    if (prec == CS_SAMPLER_MLP_BF16)
+        fb[idx] = (__bf16)wv;
+    else
+        f8[idx] = to_e4m3(wv / scales[L]);
+}
+
+// Per-layer weight amax -> scale (one workgroup per hidden layer).
+__global__ __launch_bounds__(256) void k_mlp_weight_scale(const float* P, float* scales) {
+    __shared__ float s_m[256];
+    const int offW[3] = {kOffW2, kOffW3, kOffW4};
+    float m = 0.0f;
+    for (int i = threadIdx.x; i < kMlpHidden * kMlpHidden; i += 256) m = fmaxf(m, fabsf(P[offW[blockIdx.x] + i]));
+    s_m[threadIdx.x] = m;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) s_m[threadIdx.x] = fmaxf(s_m[threadIdx.x], s_m[threadIdx.x + st]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) scales[blockIdx.x] = fmaxf(s_m[0], 1e-30f) / kE4M3Max;
+}
+
+__global__ void k_mlp_zero_amax(uint32_t* amax) {
+    if (threadIdx.x < 3) amax[threadIdx.x] = 0u;
+}
+
+__global__ void k_mlp_act_scale(float* scales) {
+    if (threadIdx.x < 3) {
+        const float m = __uint_as_float(((const uint32_t*)scales)[6 + threadIdx.x]);
+        scales[3 + threadIdx.x] = fmaxf(m, 1e-30f) / kE4M3Max;
+    }
+}
+
+constexpr int kMfmaThreads = 256;
+
+// Compact copy of the FP32 parameters the MFMA engine reads from LDS.
+constexpr int cW1 = 0, cB1 = 128, cB2 = 192, cB3 = 256, cB4 = 320, cW5 = 384, cB5 = 512, kSmall = 514;
+
+__device__ __forceinline__ void load_small_params(const float* P, float* s) {
+    for (int i = threadIdx.x; i < kSmall; i += blockDim.x) {
+        int src;
+        if (i < cB1)
+            src = kOffW1 + i;
+        else if (i < cB2)
+            src = kOffB1 + (i - cB1);
+        else if (i < cB3)
+            src = kOffB2 + (i - cB2);
+        else if (i < cB4)
+            src = kOffB3 + (i - cB3);
+        else if (i < cW5)
+            src = kOffB4 + (i - cB4);
+        else if (i < cB5)
+            src = kOffW5 + (i - cW5);
+        else
+            src = kOffB5 + (i - cB5);
+        s[i] = P[src];
+    }
+}
+
+template <int PREC>
+struct FragT;
+template <>
+struct FragT<CS_SAMPLER_MLP_BF16> {
+    typedef bf16x8 type;
+};
+template <>
+struct FragT<CS_SAMPLER_MLP_FP8> {
+    typedef long type;
+};
+
+// One tile of 16 samples on one wave.  Every lane passes the features of
+// sample (lane % 16); every lane receives that sample's outputs.  frag, W1,
+// biases, W5 come from LDS.
+template <int PREC>
+__device__ __forceinline__ void mlp_tile(const typename FragT<PREC>::type* frag, const float* P_lds,
+                                         const float* scales, float f1, float f2, float& y0, float& y1) {
+    const int lane = lane_id();
+    const int g = lane >> 4;
+    float h[16];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int n = 16 * t + 4 * g + r;
+            h[4 * t + r] = silu_fast(fmaf(P_lds[cW1 + 2 * n + 1], f2, fmaf(P_lds[cW1 + 2 * n], f1, P_lds[cB1 + n])));
+        }
+    const int offB[3] = {cB2, cB3, cB4};
+#pragma unroll
+    for (int L = 0; L < 3; ++L) {
+        typename FragT<PREC>::type B0, B1;
+        float sc = 1.0f;
+        if constexpr (PREC == CS_SAMPLER_MLP_BF16) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                B0[e] = (__bf16)h[e];
+                B1[e] = (__bf16)h[8 + e];
+            }
+        } else {
+            const float inv = 1.0f / scales[3 + L];
+            sc = scales[L] * scales[3 + L];
+            uint64_t b0 = 0, b1 = 0;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                b0 |= (uint64_t)to_e4m3(h[e] * inv) << (8 * e);
+                b1 |= (uint64_t)to_e4m3(h[8 + e] * inv) << (8 * e);
+            }
+            B0 = (long)b0;
+            B1 = (long)b1;
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            floatx4 acc;
+            if constexpr (PREC == CS_SAMPLER_MLP_BF16) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) acc[r] = P_lds[offB[L] + 16 * t + 4 * g + r];
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(frag[((L * 4 + t) * 2 + 0) * 64 + lane], B0, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(frag[((L * 4 + t) * 2 + 1) * 64 + lane], B1, acc, 0, 0, 0);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) h[4 * t + r] = silu_fast(acc[r]);
+            } else {
+                acc = {0.0f, 0.0f, 0.0f, 0.0f};
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(frag[((L * 4 + t) * 2 + 0) * 64 + lane], B0, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(frag[((L * 4 + t) * 2 + 1) * 64 + lane], B1, acc, 0, 0, 0);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) h[4 * t + r] = silu_fast(fmaf(acc[r], sc, P_lds[offB[L] + 16 * t + 4 * g + r]));
+            }
+        }
+    }
+    float p0 = 0.0f, p1 = 0.0f;
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int n = 16 * t + 4 * g + r;
+            p0 = fmaf(P_lds[cW5 + n], h[4 * t + r], p0);
+            p1 = fmaf(P_lds[cW5 + kMlpHidden + n], h[4 * t + r], p1);
+        }
+    // sum the four lane groups (fixed butterfly order)
+    p0 += __shfl_xor(p0, 16, 64);
+    p1 += __shfl_xor(p1, 16, 64);
+    p0 += __shfl_xor(p0, 32, 64);
+    p1 += __shfl_xor(p1, 32, 64);
+    y0 = p0 + P_lds[cB5];
+    y1 = p1 + P_lds[cB5 + 1];
+}
+
+template <int PREC>
+__global__ __launch_bounds__(kMfmaThreads) void k_mlp_mfma(const FwdArgs a, const void* frag_g, const float* scales) {
+    typedef typename FragT<PREC>::type FT;
+    __shared__ FT s_frag[kFragCount];
+    __shared__ float s_P[kSmall];
+    __shared__ float s_sc[6];
+    for (int i = threadIdx.x; i < kFragCount; i += kMfmaThreads) s_frag[i] = ((const FT*)frag_g)[i];
+    load_small_params(a.P, s_P);
+    if (threadIdx.x < 6) s_sc[threadIdx.x] = PREC == CS_SAMPLER_MLP_FP8 ? scales[threadIdx.x] : 1.0f;
+    __syncthreads();
+    const int lane = lane_id();
+    const int wave = threadIdx.x >> 6;
+    const int64_t n_tiles = (a.n + 15) / 16;
+    for (int64_t tile = (int64_t)blockIdx.x * 4 + wave; tile < n_tiles; tile += (int64_t)gridDim.x * 4) {
+        const int64_t i = tile * 16 + (lane & 15);
+        const bool active = i < a.n;
+        const float x = active ? a.x[i] : 1.0f, u = active ? a.u[i] : 0.5f;
+        float f1, f2, y0, y1;
+        features(x, u, f1, f2);
+        mlp_tile<PREC>(s_frag, s_P, s_sc, f1, f2, y0, y1);
+        if (lane < 16 && active) {
+            if (a.y) {
+                a.y[2 * i] = y0;
+                a.y[2 * i + 1] = y1;
+            }
+            if (a.mu || a.ratio || a.mask) sampler_out(a, i, x, u, y0);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+constexpr int64_t kMaxGradBlocks = 1024;
+
+int64_t mlp_grad_blocks(int64_t n) {
+    const int64_t t = (n + kMlpSamples - 1) / kMlpSamples;
+    return t < kMaxGradBlocks ? t : kMaxGradBlocks;
+}
+
+hipError_t launch_mlp_forward(const MlpDev& m, cs_sampler prec, const float* x, const float* u, int64_t n, float* y,
+                              float* mu, float* ratio, uint8_t* mask, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    FwdArgs a = {m.params, x, u, n, y, mu, ratio, mask, nullptr};
+    if (prec == CS_SAMPLER_MLP_F32) {
+        k_mlp_fwd_f32<<<(unsigned)((n + kMlpSamples - 1) / kMlpSamples), kMlpThreads, 0, st>>>(a);
+    } else {
+        const int64_t tiles = (n + 15) / 16;
+        int64_t blocks = (tiles + 3) / 4;
+        if (blocks > 2048) blocks = 2048;
+        if (prec == CS_SAMPLER_MLP_BF16)
+            k_mlp_mfma<CS_SAMPLER_MLP_BF16><<<(unsigned)blocks, kMfmaThreads, 0, st>>>(a, m.frag_bf16, m.fp8_scales);
+        else
+            k_mlp_mfma<CS_SAMPLER_MLP_FP8><<<(unsigned)blocks, kMfmaThreads, 0, st>>>(a, m.frag_fp8, m.fp8_scales);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_grad(const MlpDev& m, const float* x, const float* u, const float* mu_t, const float* r_t,
+                           int64_t n, int loss, float* partials, float* loss_partials, float* grad_out,
+                           float* loss_out, float* adam_m, float* adam_v, float* params_rw, float lr, int64_t t,
+                           hipStream_t st) {
+    const int64_t blocks = mlp_grad_blocks(n);
+    GradArgs g = {m.params, x, u, mu_t, r_t, n, loss, partials, loss_partials};
+    k_mlp_grad_block<<<(unsigned)blocks, kMlpThreads, 0, st>>>(g);
+    ReduceArgs r = {};
+    r.partials = partials;
+    r.loss_partials = loss_partials;
+    r.blocks = blocks;
+    r.grad_out = grad_out;
+    r.loss_out = loss_out;
+    if (params_rw) {
+        r.params = params_rw;
+        r.m = adam_m;
+        r.v = adam_v;
+        r.lr = lr;
+        r.bc1 = (float)(1.0 - std::pow(0.9, (double)t));
+        r.bc2 = (float)(1.0 - std::pow(0.999, (double)t));
+    }
+    k_mlp_reduce<<<(kMlpParams + 255) / 256, 256, 0, st>>>(r);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_adam(float* params, float* m, float* v, const float* grad, float lr, int64_t t, hipStream_t st) {
+    const float bc1 = (float)(1.0 - std::pow(0.9, (double)t));
+    const float bc2 = (float)(1.0 - std::pow(0.999, (double)t));
+    k_mlp_adam_only<<<(kMlpParams + 255) / 256, 256, 0, st>>>(params, m, v, grad, lr, bc1, bc2);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_quantize(float* params, void* frag_bf16, void* frag_fp8, float* scales, cs_sampler prec,
+                               const float* cx, const float* cu, int64_t n, hipStream_t st) {
+    const unsigned nb = (kFragCount * 8 + 255) / 256;
+    if (prec == CS_SAMPLER_MLP_BF16) {
+        k_mlp_build_frag<<<nb, 256, 0, st>>>(params, scales, CS_SAMPLER_MLP_BF16, (__bf16*)frag_bf16, nullptr);
+    } else {
+        k_mlp_zero_amax<<<1, 64, 0, st>>>((uint32_t*)scales + 6);
+        FwdArgs a = {params, cx, cu, n, nullptr, nullptr, nullptr, nullptr, (uint32_t*)scales + 6};
+        k_mlp_fwd_f32<<<(unsigned)((n + kMlpSamples - 1) / kMlpSamples), kMlpThreads, 0, st>>>(a);
+        k_mlp_act_scale<<<1, 64, 0, st>>>(scales);
+        k_mlp_weight_scale<<<3, 256, 0, st>>>(params, scales);
+        k_mlp_build_frag<<<nb, 256, 0, st>>>(params, scales, CS_SAMPLER_MLP_FP8, nullptr, (uint8_t*)frag_fp8);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace cs
