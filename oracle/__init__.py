@@ -73,9 +73,11 @@ def lib():
     L.oracle_scatter_event.restype = None
     L.oracle_compton_step.argtypes = [
         C.c_int, vp, vp, vp, vp, i64, vp, vp, vp, vp, i64, vp, vp, i64, vp, i64,
-        d, d, u64, u64, C.POINTER(OracleStats), vp, vp, vp, vp,
+        d, d, u64, u64, C.POINTER(OracleStats), vp, vp, vp, vp, vp,
     ]
     L.oracle_compton_step.restype = C.c_int
+    L.oracle_scatter_uniforms.argtypes = [vp, i64, u64, u64, dp, dp]
+    L.oracle_scatter_uniforms.restype = None
     L.oracle_num_threads.argtypes = []
     L.oracle_num_threads.restype = C.c_int
     L.oracle_set_num_threads.argtypes = [C.c_int]
@@ -199,12 +201,23 @@ class OracleError(RuntimeError):
     pass
 
 
-def compton_step(e, g, off_e, off_g, dt, density_norm, seed, step, cells=None, diagnostics=False):
+def scatter_uniforms(idx, seed, step):
+    """(u_mu, u_phi) of the collisions of the pairs whose electrons are idx."""
+    idx = np.ascontiguousarray(idx, dtype=np.int64)
+    u_mu = np.empty(idx.size)
+    u_phi = np.empty(idx.size)
+    lib().oracle_scatter_uniforms(idx.ctypes.data, idx.size, int(seed), int(step), _dptr(u_mu), _dptr(u_phi))
+    return u_mu, u_phi
+
+
+def compton_step(e, g, off_e, off_g, dt, density_norm, seed, step, cells=None, diagnostics=False, mu_given=None):
     """One Compton step, in place, on host numpy arrays.
 
     ``e`` / ``g``: dicts with keys x, y, z, w (same dtype, float32 or float64,
     C-contiguous); ``off_e`` / ``off_g``: int64 cell offsets (n_cells + 1).
     ``cells``: optional int64 array of cell ids to process (others untouched).
+    ``mu_given``: optional float64 array over electrons: cos(theta) to use
+    when that electron's pair collides (NaN: the plain sampler draws it).
     Returns the stats dict, plus per-electron diagnostics (P, u, x, partner)
     when ``diagnostics`` is true.
     """
@@ -240,11 +253,17 @@ def compton_step(e, g, off_e, off_g, dt, density_norm, seed, step, cells=None, d
             "partner": np.full(ne, -1, dtype=np.int64),
         }
         ptrs = [diag[k].ctypes.data for k in ("P", "u", "x", "partner")]
+    mg = None
+    if mu_given is not None:
+        mg = np.ascontiguousarray(mu_given, dtype=np.float64)
+        if mg.size != ne:
+            raise OracleError("mu_given must have one entry per electron")
     rc = lib().oracle_compton_step(
         code, *[a.ctypes.data for a in arrs[:4]], ne, *[a.ctypes.data for a in arrs[4:]], ng,
         off_e.ctypes.data, off_g.ctypes.data, n_cells,
         sel.ctypes.data if sel is not None else None, sel.size if sel is not None else 0,
-        float(dt), float(density_norm), int(seed), int(step), C.byref(st), *ptrs)
+        float(dt), float(density_norm), int(seed), int(step), C.byref(st), *ptrs,
+        mg.ctypes.data if mg is not None else None)
     if rc == 2:
         raise OracleError("cell offsets are not a valid layout")
     if rc != 0:

@@ -83,6 +83,19 @@ double oracle_uniform53(uint32_t a, uint32_t b)
     return (hi * 67108864.0 + lo) / 9007199254740992.0;
 }
 
+/* The two uniforms that resolve the collision of the pair whose electron has
+ * index idx[i]: cos(theta) sampling (u_mu) and azimuth (u_phi). */
+void oracle_scatter_uniforms(const int64_t* idx, int64_t n, uint64_t seed, uint64_t step, double* u_mu,
+                             double* u_phi)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        uint32_t r[4];
+        draw(seed, (uint64_t)idx[i], step, PURPOSE_SCATTER, r);
+        u_mu[i] = oracle_uniform53(r[0], r[1]);
+        u_phi[i] = oracle_uniform53(r[2], r[3]);
+    }
+}
+
 /* ------------------------------------------------------------------------- */
 /* Pairing: a keyed pseudo-random bijection of [0, M) (the in-cell shuffle).  */
 /* A 4-round balanced Feistel network over 2h bits, 2h >= ceil(log2 M), made  */
@@ -446,7 +459,8 @@ static int finite_nonneg_pair(const double p[3], double we, const double k[3], d
 /* Process one collision cell (cells are independent). */
 static void process_cell(int dtype, void* const E[4], void* const G[4], int64_t c, int64_t e0, int64_t ne,
                          int64_t g0, int64_t ng, double dt, double density_norm, uint64_t seed, uint64_t step,
-                         cell_tally* t, double* diag_P, double* diag_u, double* diag_x, int64_t* diag_partner)
+                         cell_tally* t, double* diag_P, double* diag_u, double* diag_x, int64_t* diag_partner,
+                         const double* mu_given)
 {
     memset(t, 0, sizeof(*t));
     int64_t n_min = ne < ng ? ne : ng, n_max = ne < ng ? ng : ne;
@@ -497,7 +511,10 @@ static void process_cell(int dtype, void* const E[4], void* const G[4], int64_t 
         draw(seed, (uint64_t)ie, step, PURPOSE_SCATTER, s);
         double u_mu = oracle_uniform53(s[0], s[1]);
         double u_phi = oracle_uniform53(s[2], s[3]);
-        double v = oracle_angle_icdf_v(u_mu, x);
+        /* The learned sampler stands in for the inverse-CDF step (Sec. 3.2):
+         * when the caller supplies cos(theta) for this electron's pair, that
+         * angle is used; otherwise the plain sampler draws it. */
+        double v = (mu_given && !isnan(mu_given[ie])) ? 1.0 - mu_given[ie] : oracle_angle_icdf_v(u_mu, x);
         double p1[3], k1[3], eb, ea;
         scatter_event_v(p, k, (quad)v, u_phi, p1, k1, &eb, &ea);
         t->energy_before += eb;
@@ -533,6 +550,8 @@ static int check_offsets(const int64_t* off, int64_t n_cells, int64_t n)
  * dtype: 0 = float32 storage, 1 = float64 storage.  Arrays are updated in
  * place.  Optional per-electron diagnostics (length ne, indexed by electron):
  * P, the uniform u_c, x and the partner photon index of the electron's pair.
+ * mu_given (optional, length ne, indexed by electron): cos(theta) to use for
+ * the pair of that electron when it collides, NaN for the plain sampler.
  * Returns 0, or 2 when the offsets are not a valid cell layout (nothing is
  * modified then), or 1 for other invalid arguments.
  */
@@ -540,7 +559,7 @@ int oracle_compton_step(int dtype, void* ex, void* ey, void* ez, void* ew, int64
                         void* gz, void* gw, int64_t ng, const int64_t* cell_off_e, const int64_t* cell_off_g,
                         int64_t n_cells, const int64_t* cells, int64_t n_sel, double dt, double density_norm,
                         uint64_t seed, uint64_t step, oracle_stats* stats, double* diag_P, double* diag_u,
-                        double* diag_x, int64_t* diag_partner)
+                        double* diag_x, int64_t* diag_partner, const double* mu_given)
 {
     if (dtype != 0 && dtype != 1) return 1;
     if (n_cells < 0 || ne < 0 || ng < 0) return 1;
@@ -558,7 +577,7 @@ int oracle_compton_step(int dtype, void* ex, void* ey, void* ez, void* ew, int64
         int64_t c = cells ? cells[j] : j;
         process_cell(dtype, E, G, c, cell_off_e[c], cell_off_e[c + 1] - cell_off_e[c], cell_off_g[c],
                      cell_off_g[c + 1] - cell_off_g[c], dt, density_norm, seed, step, &tallies[j], diag_P,
-                     diag_u, diag_x, diag_partner);
+                     diag_u, diag_x, diag_partner, mu_given);
     }
     oracle_stats s;
     memset(&s, 0, sizeof(s));

@@ -226,3 +226,58 @@ def test_empty_inputs(orc):
     assert st["n_pairs"] == 0 and st["n_collided"] == 0
     st = orc.compton_step(e, g, np.zeros(4, np.int64), np.zeros(4, np.int64), 0.1, 1.0, 0, 0)
     assert st["n_pairs"] == 0
+
+
+def test_given_angle_forward_scattering_is_identity(orc):
+    """cos(theta) = 1 is no scattering: every collided pair keeps its momenta
+    (the rest-frame photon is not deflected and loses no energy)."""
+    p = small_plasma(dt=2.0)
+    before = p.copy()
+    st = orc.compton_step(p.e, p.g, p.off_e, p.off_g, p.dt, p.density_norm, p.seed, 0,
+                          mu_given=np.ones(p.e["x"].size))
+    assert st["n_collided"] > 50
+    for c in "xyz":
+        for sp, sp0 in ((p.e, before.e), (p.g, before.g)):
+            scale = np.abs(sp0[c]) + np.sqrt(sp0["x"] ** 2 + sp0["y"] ** 2 + sp0["z"] ** 2)
+            assert np.all(np.abs(sp[c] - sp0[c]) <= 1e-14 * scale + 1e-300)
+
+
+def test_given_angle_backscatter_compton_shift(orc):
+    """cos(theta) = -1 for every pair: in the rest frame the photon energy
+    becomes x / (1 + 2x) (the Compton formula at theta = pi), checked through
+    the invariant P.K1 = x' of the scattered photon and the conservation of
+    the total four-momentum of each pair."""
+    p = small_plasma(dt=2.0)
+    before = p.copy()
+    st, d = orc.compton_step(p.e, p.g, p.off_e, p.off_g, p.dt, p.density_norm, p.seed, 0, diagnostics=True,
+                             mu_given=np.full(p.e["x"].size, -1.0))
+    hit = np.nonzero(d["u"] < d["P"])[0]
+    assert hit.size > 50
+    for ie in hit[:200]:
+        ig = d["partner"][ie]
+        pe = np.array([before.e[c][ie] for c in "xyz"])
+        k = np.array([before.g[c][ig] for c in "xyz"])
+        k1 = np.array([p.g[c][ig] for c in "xyz"])
+        ge = math.sqrt(1.0 + pe @ pe)
+        x = d["x"][ie]
+        x1 = ge * math.sqrt(k1 @ k1) - pe @ k1  # rest-frame energy of the scattered photon
+        assert abs(x1 - x / (1.0 + 2.0 * x)) <= 1e-9 * x
+    assert abs(st["energy_after"] - st["energy_before"]) <= 1e-14 * st["energy_before"]
+
+
+def test_given_angle_nan_is_plain(orc):
+    p1 = small_plasma()
+    p2 = p1.copy()
+    orc.compton_step(p1.e, p1.g, p1.off_e, p1.off_g, p1.dt, p1.density_norm, p1.seed, 2)
+    orc.compton_step(p2.e, p2.g, p2.off_e, p2.off_g, p2.dt, p2.density_norm, p2.seed, 2,
+                     mu_given=np.full(p2.e["x"].size, np.nan))
+    for c in "xyz":
+        assert np.array_equal(p1.e[c], p2.e[c]) and np.array_equal(p1.g[c], p2.g[c])
+
+
+def test_scatter_uniforms_match_philox(orc):
+    idx = np.array([0, 1, 12345, 2 ** 33 + 7])
+    u_mu, u_phi = orc.scatter_uniforms(idx, seed=5, step=3)
+    for i, ie in enumerate(idx):
+        w = orc.philox4x32_10([ie & 0xFFFFFFFF, ie >> 32, 3, 3], [5, 0])
+        assert u_mu[i] == orc.uniform53(w[0], w[1]) and u_phi[i] == orc.uniform53(w[2], w[3])
