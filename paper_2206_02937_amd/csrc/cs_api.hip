@@ -167,8 +167,14 @@ cs_status cs_compton_step(cs_ctx* ctx, cs_dtype dtype, cs_species electrons, cs_
     if (sampler == CS_SAMPLER_PLAIN) {
         if (mlp) return fail(ctx, CS_ERR_INVALID_ARG, "cs_compton_step: PLAIN sampler takes mlp == NULL");
     } else if (sampler == CS_SAMPLER_MLP_F32 || sampler == CS_SAMPLER_MLP_BF16 || sampler == CS_SAMPLER_MLP_FP8) {
-        if (!mlp) return fail(ctx, CS_ERR_NOT_READY, "cs_compton_step: MLP sampler without a network");
-        return fail(ctx, CS_ERR_NOT_READY, "cs_compton_step: MLP sampler not prepared");
+        if (!mlp) return fail(ctx, CS_ERR_NOT_READY, "cs_compton_step: network sampler without a network");
+        if (mlp->device != ctx->device)
+            return fail(ctx, CS_ERR_INVALID_ARG, "cs_compton_step: network lives on another device");
+        if ((sampler == CS_SAMPLER_MLP_BF16 && !mlp->bf16_ready) || (sampler == CS_SAMPLER_MLP_FP8 && !mlp->fp8_ready))
+            return fail(ctx, CS_ERR_NOT_READY, "cs_compton_step: network not prepared for this precision");
+        if (ctx->strategy == CS_STRATEGY_MULTI_KERNEL)
+            return fail(ctx, CS_ERR_UNSUPPORTED,
+                        "cs_compton_step: the multi-kernel strategy runs the plain sampler only");
     } else {
         return fail(ctx, CS_ERR_INVALID_ARG, "cs_compton_step: bad sampler");
     }
@@ -194,8 +200,13 @@ cs_status cs_compton_step(cs_ctx* ctx, cs_dtype dtype, cs_species electrons, cs_
     sh.chunks_per_block = G;
     sh.n_step_blocks = sh.n_chunks > 0 ? (sh.n_chunks + G - 1) / G : 1;
     sh.n_prep_blocks = cs::fused_prep_blocks(n_cells);
-    int64_t nd = (nmin + 63) / 64;
-    sh.n_dense_blocks = nd < 1 ? 1 : (nd > 2048 ? 2048 : nd);
+    // dense collide grid: one lane per accepted pair at most, capped (2048
+    // one-wave workgroups, or 512 four-wave workgroups that each load the
+    // network's LDS copy)
+    const int64_t dense_threads = cs::compact_collide_threads(sampler);
+    const int64_t dense_cap = sampler == CS_SAMPLER_PLAIN ? 2048 : 512;
+    int64_t nd = (nmin + dense_threads - 1) / dense_threads;
+    sh.n_dense_blocks = nd < 1 ? 1 : (nd > dense_cap ? dense_cap : nd);
     const int64_t strategy = ctx->strategy;
     size_t bytes;
     int64_t status_words = sh.n_prep_blocks;
@@ -221,7 +232,7 @@ cs_status cs_compton_step(cs_ctx* ctx, cs_dtype dtype, cs_species electrons, cs_
     p.seed = seed;
     p.step = step;
     p.sampler = sampler;
-    p.mlp = mlp;
+    p.net = mlp ? mlp->dev() : cs::MlpDev{nullptr, nullptr, nullptr, nullptr};
     p.stats = stats;
     p.events = ctx->timing ? ctx->events : nullptr;
     p.use_device_step = 0;

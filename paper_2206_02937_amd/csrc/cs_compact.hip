@@ -7,8 +7,10 @@
 //                     over the chunks, so the list of accepted pairs is dense
 //                     and in pair order with no atomics.  Lean (no sampler),
 //                     so it runs at full occupancy.
-//   k_collide_dense   one-wave workgroups stride over the dense list: sample
-//                     the angle, scatter, write back.
+//   k_collide_dense   workgroups stride over the dense list: sample the
+//                     angle, scatter, write back (one wave per workgroup with
+//                     the plain sampler; four waves sharing the network's LDS
+//                     copy with a network sampler).
 //   k_finalize_step   (cs_fused.hip) fixed-order reduction of the partial sums.
 #include <hip/hip_runtime.h>
 
@@ -20,7 +22,8 @@
 
 namespace cs {
 
-constexpr int kDenseThreads = 64;
+constexpr int kDenseThreads = 64;      // plain sampler
+constexpr int kDenseNetThreads = 256;  // network samplers
 
 template <typename T>
 struct CompactArgs {
@@ -40,7 +43,9 @@ struct CompactArgs {
     int64_t* chunk_inv;
     double* coll_eb;
     double* coll_ea;
+    int64_t* coll_fb;
     cs_stats* stats;
+    MlpDev mlp;
 };
 
 template <typename T>
@@ -119,27 +124,52 @@ __global__ __launch_bounds__(kChunk) void k_pair_compact(const CompactArgs<T> a)
     if (tid == 0 && j == (int64_t)gridDim.x - 1) ctrl->n_accepted = (uint32_t)(s_prefix + total);
 }
 
-template <typename T>
-__global__ __launch_bounds__(kDenseThreads) void k_collide_dense(const CompactArgs<T> a) {
+template <typename T, int SAMP>
+__global__ __launch_bounds__(SAMP == CS_SAMPLER_PLAIN ? kDenseThreads : kDenseNetThreads) void k_collide_dense(const CompactArgs<T> a) {
+    constexpr int NT = SAMP == CS_SAMPLER_PLAIN ? kDenseThreads : kDenseNetThreads;
+    __shared__ NetLds<SAMP> s_net;
+    __shared__ double s_d[2 * (NT / 64)];
+    __shared__ long long s_fb[NT / 64];
+    net_load<SAMP>(s_net, a.mlp);
+    if constexpr (SAMP != CS_SAMPLER_PLAIN) __syncthreads();
     StepControl* ctrl = a.ctrl;
     const uint32_t E = ctrl->epoch;
     const uint64_t step = ctrl->step;
     const bool layout_ok = ctrl->layout_epoch != E && ctrl->scan_fault_epoch != E;
     const int64_t A = layout_ok ? (int64_t)ctrl->n_accepted : 0;
-    const int64_t stride = (int64_t)gridDim.x * kDenseThreads;
+    const int64_t stride = (int64_t)gridDim.x * NT;
     const int64_t n_iter = (A + stride - 1) / stride;  // uniform over the grid
     CollideSums sums;
     for (int64_t it = 0; it < n_iter; ++it) {
-        const int64_t q = it * stride + (int64_t)blockIdx.x * kDenseThreads + threadIdx.x;
+        const int64_t q = it * stride + (int64_t)blockIdx.x * NT + threadIdx.x;
         if (!__any(q < A)) break;
         const bool active = q < A;
         const int2 pr = active ? a.list[q] : make_int2(0, 0);
-        collide_plain<T>(a.pt, active, pr.x, pr.y, a.seed, step, sums);
+        if constexpr (SAMP == CS_SAMPLER_PLAIN)
+            collide_plain<T>(a.pt, active, pr.x, pr.y, a.seed, step, sums);
+        else
+            collide_net<T, SAMP>(a.pt, active, FromArrays<T>{pr.x, pr.y}, s_net, a.mlp, a.seed, step, sums);
     }
     const double eb = wave_sum(sums.e_before), ea = wave_sum(sums.e_after);
+    const long long fb = wave_sum_i(sums.n_fallback);
+    const int wave = threadIdx.x >> 6;
+    if (lane_id() == 0) {
+        s_d[2 * wave] = eb;
+        s_d[2 * wave + 1] = ea;
+        s_fb[wave] = fb;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
-        a.coll_eb[blockIdx.x] = eb;
-        a.coll_ea[blockIdx.x] = ea;
+        double teb = 0.0, tea = 0.0;
+        long long tfb = 0;
+        for (int w = 0; w < NT / 64; ++w) {
+            teb += s_d[2 * w];
+            tea += s_d[2 * w + 1];
+            tfb += s_fb[w];
+        }
+        a.coll_eb[blockIdx.x] = teb;
+        a.coll_ea[blockIdx.x] = tea;
+        a.coll_fb[blockIdx.x] = tfb;
     }
 }
 
@@ -152,7 +182,7 @@ size_t compact_workspace_bytes(const StepShape& s) {
     b += al(sizeof(int32_t) * (s.n_chunks + 1));
     b += al(sizeof(int2) * s.n_chunks * kChunk + 8);
     b += 3 * al(8 * (s.n_chunks > 0 ? s.n_chunks : 1));
-    b += 2 * al(8 * s.n_collide_blocks);
+    b += 3 * al(8 * s.n_collide_blocks);
     return b;
 }
 
@@ -174,9 +204,10 @@ void carve_compact_buffers(const Workspace& w, const StepShape& s, CompactBuffer
     b->chunk_inv = (int64_t*)take(8 * (s.n_chunks > 0 ? s.n_chunks : 1));
     b->coll_eb = (double*)take(8 * s.n_collide_blocks);
     b->coll_ea = (double*)take(8 * s.n_collide_blocks);
+    b->coll_fb = (int64_t*)take(8 * s.n_collide_blocks);
 }
 
-template <typename T>
+template <typename T, int SAMP>
 static hipError_t launch_compact_t(const StepShape& sh, const CompactBuffers& b, const StepParams& p, hipStream_t st) {
     auto mark = [&](int i) {
         if (p.events) (void)hipEventRecord(p.events[i], st);
@@ -206,11 +237,14 @@ static hipError_t launch_compact_t(const StepShape& sh, const CompactBuffers& b,
     a.chunk_inv = b.chunk_inv;
     a.coll_eb = b.coll_eb;
     a.coll_ea = b.coll_ea;
+    a.coll_fb = b.coll_fb;
     a.stats = p.stats;
+    a.mlp = p.net;
     if (sh.n_chunks > 0) k_pair_compact<T><<<(unsigned)sh.n_chunks, kChunk, 0, st>>>(a);
     mark(2);
     mark(3);
-    k_collide_dense<T><<<(unsigned)sh.n_collide_blocks, kDenseThreads, 0, st>>>(a);
+    k_collide_dense<T, SAMP><<<(unsigned)sh.n_collide_blocks,
+                               SAMP == CS_SAMPLER_PLAIN ? kDenseThreads : kDenseNetThreads, 0, st>>>(a);
     mark(4);
     FinalArgs f = {};
     f.ctrl = b.ctrl;
@@ -223,7 +257,7 @@ static hipError_t launch_compact_t(const StepShape& sh, const CompactBuffers& b,
     f.n_a = sh.n_chunks;
     f.b_eb = b.coll_eb;
     f.b_ea = b.coll_ea;
-    f.b_fb = nullptr;
+    f.b_fb = b.coll_fb;
     f.n_b = sh.n_collide_blocks;
     f.stats = p.stats;
     e = launch_finalize(f, st);
@@ -231,9 +265,26 @@ static hipError_t launch_compact_t(const StepShape& sh, const CompactBuffers& b,
     return e == hipSuccess ? hipGetLastError() : e;
 }
 
+template <typename T>
+static hipError_t launch_compact_s(const StepShape& sh, const CompactBuffers& b, const StepParams& p,
+                                   hipStream_t st) {
+    switch (p.sampler) {
+        case CS_SAMPLER_MLP_F32:
+            return launch_compact_t<T, CS_SAMPLER_MLP_F32>(sh, b, p, st);
+        case CS_SAMPLER_MLP_BF16:
+            return launch_compact_t<T, CS_SAMPLER_MLP_BF16>(sh, b, p, st);
+        case CS_SAMPLER_MLP_FP8:
+            return launch_compact_t<T, CS_SAMPLER_MLP_FP8>(sh, b, p, st);
+        default:
+            return launch_compact_t<T, CS_SAMPLER_PLAIN>(sh, b, p, st);
+    }
+}
+
+int64_t compact_collide_threads(cs_sampler s) { return s == CS_SAMPLER_PLAIN ? kDenseThreads : kDenseNetThreads; }
+
 hipError_t launch_compact(const StepShape& sh, const CompactBuffers& b, const StepParams& p, hipStream_t st) {
-    if (p.dtype == CS_F64) return launch_compact_t<double>(sh, b, p, st);
-    return launch_compact_t<float>(sh, b, p, st);
+    if (p.dtype == CS_F64) return launch_compact_s<double>(sh, b, p, st);
+    return launch_compact_s<float>(sh, b, p, st);
 }
 
 }  // namespace cs

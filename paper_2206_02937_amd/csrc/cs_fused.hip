@@ -135,24 +135,30 @@ struct FusedArgs {
     StepControl* ctrl;
     BlockPartials part;
     cs_stats* stats;
+    MlpDev mlp;  // network samplers only
 };
 
-template <typename T>
-__device__ void drain_plain(const FusedArgs<T>& a, const StagedPair<T>* queue, int n, uint64_t step,
-                            CollideSums& sums) {
+template <typename T, int SAMP>
+__device__ void drain(const FusedArgs<T>& a, const StagedPair<T>* queue, int n, uint64_t step, NetLds<SAMP>& s_net,
+                      CollideSums& sums) {
     for (int base = 0; base < n; base += kChunk) {
         const int q = base + (int)threadIdx.x;
         // waves with no item skip the pass entirely
         if (__any(q < n)) {
             const bool active = q < n;
-            collide_staged<T>(a.pt, active, queue + (active ? q : 0), a.seed, step, sums);
+            const StagedPair<T>* e = queue + (active ? q : 0);
+            if constexpr (SAMP == CS_SAMPLER_PLAIN)
+                collide_staged<T>(a.pt, active, e, a.seed, step, sums);
+            else
+                collide_net<T, SAMP>(a.pt, active, FromStaged<T>{e}, s_net, a.mlp, a.seed, step, sums);
         }
     }
 }
 
-template <typename T>
+template <typename T, int SAMP>
 __global__ __launch_bounds__(kChunk) void k_step(const FusedArgs<T> a) {
     __shared__ StagedPair<T> s_queue[kQueueCap];
+    __shared__ NetLds<SAMP> s_net;
     __shared__ int s_wcnt[kChunk / 64];
     __shared__ int s_qn;
     __shared__ double s_red_d[3 * (kChunk / 64)];
@@ -168,6 +174,7 @@ __global__ __launch_bounds__(kChunk) void k_step(const FusedArgs<T> a) {
     long long n_clip = 0, n_inv = 0, n_coll = 0;
     CollideSums sums;
     if (tid == 0) s_qn = 0;
+    net_load<SAMP>(s_net, a.mlp);
     __syncthreads();
     if (layout_ok) {
         const int32_t T_total = a.pair_off[a.n_cells];
@@ -223,7 +230,7 @@ __global__ __launch_bounds__(kChunk) void k_step(const FusedArgs<T> a) {
             n_coll += o.accept ? 1 : 0;
             __syncthreads();
             if (qn + total >= kChunk) {
-                drain_plain<T>(a, s_queue, qn + total, step, sums);
+                drain<T, SAMP>(a, s_queue, qn + total, step, s_net, sums);
                 __syncthreads();
                 if (tid == 0) s_qn = 0;
             } else if (tid == 0) {
@@ -232,11 +239,12 @@ __global__ __launch_bounds__(kChunk) void k_step(const FusedArgs<T> a) {
             __syncthreads();
         }
         const int qn = s_qn;
-        if (qn > 0) drain_plain<T>(a, s_queue, qn, step, sums);
+        if (qn > 0) drain<T, SAMP>(a, s_queue, qn, step, s_net, sums);
     }
     // per-workgroup partials, fixed order: lanes (butterfly), then waves
     const double w_p = wave_sum(sum_p), w_eb = wave_sum(sums.e_before), w_ea = wave_sum(sums.e_after);
     const long long w_cl = wave_sum_i(n_clip), w_in = wave_sum_i(n_inv), w_co = wave_sum_i(n_coll);
+    const long long w_fb = wave_sum_i(sums.n_fallback);
     if (lane == 0) {
         s_red_d[3 * wave + 0] = w_p;
         s_red_d[3 * wave + 1] = w_eb;
@@ -244,11 +252,12 @@ __global__ __launch_bounds__(kChunk) void k_step(const FusedArgs<T> a) {
         s_red_i[4 * wave + 0] = w_cl;
         s_red_i[4 * wave + 1] = w_in;
         s_red_i[4 * wave + 2] = w_co;
+        s_red_i[4 * wave + 3] = w_fb;
     }
     __syncthreads();
     if (tid == 0) {
         double p = 0.0, eb = 0.0, ea = 0.0;
-        long long cl = 0, in = 0, co = 0;
+        long long cl = 0, in = 0, co = 0, fb = 0;
         for (int w = 0; w < kChunk / 64; ++w) {
             p += s_red_d[3 * w + 0];
             eb += s_red_d[3 * w + 1];
@@ -256,6 +265,7 @@ __global__ __launch_bounds__(kChunk) void k_step(const FusedArgs<T> a) {
             cl += s_red_i[4 * w + 0];
             in += s_red_i[4 * w + 1];
             co += s_red_i[4 * w + 2];
+            fb += s_red_i[4 * w + 3];
         }
         const int b = blockIdx.x;
         a.part.prob[b] = p;
@@ -264,7 +274,7 @@ __global__ __launch_bounds__(kChunk) void k_step(const FusedArgs<T> a) {
         a.part.clipped[b] = cl;
         a.part.invalid[b] = in;
         a.part.collided[b] = co;
-        a.part.fallback[b] = 0;
+        a.part.fallback[b] = fb;
     }
 }
 
@@ -412,7 +422,7 @@ hipError_t launch_prep(const StepShape& sh, StepControl* ctrl, uint64_t* status,
     return hipGetLastError();
 }
 
-template <typename T>
+template <typename T, int SAMP>
 static hipError_t launch_fused_t(const StepShape& sh, const FusedBuffers& b, const StepParams& p, hipStream_t st) {
     auto mark = [&](int i) {
         if (p.events) (void)hipEventRecord(p.events[i], st);
@@ -437,7 +447,8 @@ static hipError_t launch_fused_t(const StepShape& sh, const FusedBuffers& b, con
     fa.ctrl = b.ctrl;
     fa.part = b.part;
     fa.stats = p.stats;
-    k_step<T><<<(unsigned)sh.n_step_blocks, kChunk, 0, st>>>(fa);
+    fa.mlp = p.net;
+    k_step<T, SAMP><<<(unsigned)sh.n_step_blocks, kChunk, 0, st>>>(fa);
     mark(2);
     mark(3);
     mark(4);
@@ -460,9 +471,23 @@ static hipError_t launch_fused_t(const StepShape& sh, const FusedBuffers& b, con
     return e == hipSuccess ? hipGetLastError() : e;
 }
 
+template <typename T>
+static hipError_t launch_fused_s(const StepShape& sh, const FusedBuffers& b, const StepParams& p, hipStream_t st) {
+    switch (p.sampler) {
+        case CS_SAMPLER_MLP_F32:
+            return launch_fused_t<T, CS_SAMPLER_MLP_F32>(sh, b, p, st);
+        case CS_SAMPLER_MLP_BF16:
+            return launch_fused_t<T, CS_SAMPLER_MLP_BF16>(sh, b, p, st);
+        case CS_SAMPLER_MLP_FP8:
+            return launch_fused_t<T, CS_SAMPLER_MLP_FP8>(sh, b, p, st);
+        default:
+            return launch_fused_t<T, CS_SAMPLER_PLAIN>(sh, b, p, st);
+    }
+}
+
 hipError_t launch_fused(const StepShape& sh, const FusedBuffers& b, const StepParams& p, hipStream_t st) {
-    if (p.dtype == CS_F64) return launch_fused_t<double>(sh, b, p, st);
-    return launch_fused_t<float>(sh, b, p, st);
+    if (p.dtype == CS_F64) return launch_fused_s<double>(sh, b, p, st);
+    return launch_fused_s<float>(sh, b, p, st);
 }
 
 }  // namespace cs

@@ -109,14 +109,23 @@ struct CompactBuffers {
     int64_t* chunk_inv;   // [n_chunks]
     double* coll_eb;      // [n_collide_blocks]
     double* coll_ea;      // [n_collide_blocks]
+    int64_t* coll_fb;     // [n_collide_blocks]
 };
 
+int64_t compact_collide_threads(cs_sampler s);
 size_t fused_workspace_bytes(const StepShape& s);
 void carve_fused_buffers(const Workspace& w, const StepShape& s, FusedBuffers* b);
 int64_t fused_prep_blocks(int64_t n_cells);
 
 size_t step_workspace_bytes(const StepShape& s);
 void carve_step_buffers(void* base, const StepShape& s, StepBuffers* b);
+
+struct MlpDev {
+    const float* params;        // FP32 master
+    const void* frag_bf16;      // kFragCount x 8 bf16
+    const void* frag_fp8;       // kFragCount x 8 fp8 (E4M3)
+    const float* fp8_scales;    // [0..2] weight scales, [3..5] input scales, [6..8] input amax
+};
 
 struct StepParams {
     cs_dtype dtype;
@@ -126,7 +135,7 @@ struct StepParams {
     double dt, density_norm;
     uint64_t seed, step;
     cs_sampler sampler;
-    const cs_mlp* mlp;
+    MlpDev net;  // device view of the network (network samplers)
     cs_stats* stats;
     hipEvent_t* events;   // CS_STAGE_COUNT + 1 events to record between stages, or nullptr
     int use_device_step;  // 1: kernels take the step from the device counter (graph replay)
@@ -174,12 +183,6 @@ constexpr int kOffW1 = 0, kOffB1 = 128, kOffW2 = 192, kOffB2 = 4288, kOffW3 = 43
 // MFMA fragments of the three hidden 64x64 layers: [layer][tile_out][kstep][lane]
 constexpr int kFragCount = 3 * 4 * 2 * 64;
 
-struct MlpDev {
-    const float* params;        // FP32 master
-    const void* frag_bf16;      // kFragCount x 8 bf16
-    const void* frag_fp8;       // kFragCount x 8 fp8 (E4M3)
-    const float* fp8_scales;    // [0..2] weight scales, [3..5] input scales, [6..8] input amax
-};
 
 hipError_t launch_mlp_forward(const MlpDev& m, cs_sampler prec, const float* x, const float* u, int64_t n,
                               float* y, float* mu, float* ratio, uint8_t* mask, hipStream_t st);

@@ -9,13 +9,10 @@
 // gradients, and writes one partial gradient per workgroup; a second kernel
 // sums the partials in a fixed order (bitwise reproducible) and applies Adam.
 //
-// MFMA engine (BF16 / FP8 inference): a wave evaluates a tile of 16 samples
-// with v_mfma_f32_16x16x32_{bf16,fp8}.  Lane l owns sample l%16 and, in group
-// g = l/16, the neurons 16t + 4g + r (t, r = 0..3): exactly the rows of the
-// accumulator fragment it holds, so a layer's output stays in registers and
-// becomes the next layer's B operand once the weight fragments list the input
-// neurons in the same order (k-slot 8g + e of k-step s <-> neuron
-// 16(2s + e/4) + 4g + e%4).  Layers 1 and 5 (K = 2, N = 2) are FP32 VALU.
+// MFMA engine (BF16 / FP8 inference): the tile evaluator of cs_net.h on
+// grid-strided 16-sample tiles, the fragments and small parameters in LDS.
+// Preparation kernels build the fragments (BF16 rounding, or per-layer FP8
+// scales from the weight amax and a calibration pass of the FP32 engine).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -23,31 +20,18 @@
 #include "cs_block.h"
 #include "cs_device.h"
 #include "cs_internal.h"
+#include "cs_net.h"
 
 namespace cs {
-
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 constexpr int kMlpThreads = 256;
 constexpr int kMlpSamples = 64;  // samples per FP32 workgroup
 constexpr int kRow = 68;         // LDS row stride (floats), 16-byte aligned rows
-constexpr float kE4M3Max = 448.0f;
 
-__device__ __forceinline__ float silu_f32(float z) { return z / (1.0f + expf(-z)); }
 __device__ __forceinline__ float silu_grad_f32(float z) {
     const float s = 1.0f / (1.0f + expf(-z));
     return s * (1.0f + z * (1.0f - s));
 }
-// SiLU for the reduced-precision paths (its result is rounded to BF16/FP8)
-__device__ __forceinline__ float silu_fast(float z) { return z * __frcp_rn(1.0f + __expf(-z)); }
-
-__device__ __forceinline__ void features(float x, float u, float& f1, float& f2) {
-    f1 = (log10f(x) + 1.0f) / 3.0f;
-    f2 = 2.0f * u - 1.0f;
-}
-
-__device__ __forceinline__ int wave_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 // ---------------------------------------------------------------------------
 // FP32 engine pieces
@@ -144,7 +128,6 @@ struct FwdArgs {
     uint32_t* amax;  // nullable: calibration
 };
 
-__device__ __forceinline__ bool in_range(float x) { return x >= (float)CS_MLP_X_MIN && x <= (float)CS_MLP_X_MAX; }
 
 // Sampler reading of the outputs (shared by every precision).
 __device__ __forceinline__ void sampler_out(const FwdArgs& a, int64_t i, float x, float u, float y0) {
@@ -426,14 +409,6 @@ __global__ void k_mlp_adam_only(float* params, float* m_, float* v_, const float
 // ---------------------------------------------------------------------------
 // MFMA engine
 // ---------------------------------------------------------------------------
-// Input neuron of k-slot e (0..7) of k-step s in lane group g.
-__host__ __device__ __forceinline__ int frag_in_neuron(int s, int g, int e) { return 16 * (2 * s + e / 4) + 4 * g + (e & 3); }
-
-__device__ __forceinline__ uint8_t to_e4m3(float v) {
-    v = fminf(fmaxf(v, -kE4M3Max), kE4M3Max);  // saturating conversion
-    const uint32_t packed = __builtin_amdgcn_cvt_pk_fp8_f32(v, 0.0f, 0u, false);
-    return (uint8_t)(packed & 0xFFu);
-}
 
 // Build fragments: thread per (layer, tile_out, kstep, lane, e).
 __global__ void k_mlp_build_frag(const float* P, const float* scales, int prec, __bf16* fb, uint8_t* f8) {
@@ -478,126 +453,10 @@ __global__ void k_mlp_act_scale(float* scales) {
 
 constexpr int kMfmaThreads = 256;
 
-// Compact copy of the FP32 parameters the MFMA engine reads from LDS.
-constexpr int cW1 = 0, cB1 = 128, cB2 = 192, cB3 = 256, cB4 = 320, cW5 = 384, cB5 = 512, kSmall = 514;
-
-__device__ __forceinline__ void load_small_params(const float* P, float* s) {
-    for (int i = threadIdx.x; i < kSmall; i += blockDim.x) {
-        int src;
-        if (i < cB1)
-            src = kOffW1 + i;
-        else if (i < cB2)
-            src = kOffB1 + (i - cB1);
-        else if (i < cB3)
-            src = kOffB2 + (i - cB2);
-        else if (i < cB4)
-            src = kOffB3 + (i - cB3);
-        else if (i < cW5)
-            src = kOffB4 + (i - cB4);
-        else if (i < cB5)
-            src = kOffW5 + (i - cW5);
-        else
-            src = kOffB5 + (i - cB5);
-        s[i] = P[src];
-    }
-}
-
 template <int PREC>
-struct FragT;
-template <>
-struct FragT<CS_SAMPLER_MLP_BF16> {
-    typedef bf16x8 type;
-};
-template <>
-struct FragT<CS_SAMPLER_MLP_FP8> {
-    typedef long type;
-};
-
-// One tile of 16 samples on one wave.  Every lane passes the features of
-// sample (lane % 16); every lane receives that sample's outputs.  frag, W1,
-// biases, W5 come from LDS.
-template <int PREC>
-__device__ __forceinline__ void mlp_tile(const typename FragT<PREC>::type* frag, const float* P_lds,
-                                         const float* scales, float f1, float f2, float& y0, float& y1) {
-    const int lane = lane_id();
-    const int g = lane >> 4;
-    float h[16];
-#pragma unroll
-    for (int t = 0; t < 4; ++t)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int n = 16 * t + 4 * g + r;
-            h[4 * t + r] = silu_fast(fmaf(P_lds[cW1 + 2 * n + 1], f2, fmaf(P_lds[cW1 + 2 * n], f1, P_lds[cB1 + n])));
-        }
-    const int offB[3] = {cB2, cB3, cB4};
-#pragma unroll
-    for (int L = 0; L < 3; ++L) {
-        typename FragT<PREC>::type B0, B1;
-        float sc = 1.0f;
-        if constexpr (PREC == CS_SAMPLER_MLP_BF16) {
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                B0[e] = (__bf16)h[e];
-                B1[e] = (__bf16)h[8 + e];
-            }
-        } else {
-            const float inv = 1.0f / scales[3 + L];
-            sc = scales[L] * scales[3 + L];
-            uint64_t b0 = 0, b1 = 0;
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                b0 |= (uint64_t)to_e4m3(h[e] * inv) << (8 * e);
-                b1 |= (uint64_t)to_e4m3(h[8 + e] * inv) << (8 * e);
-            }
-            B0 = (long)b0;
-            B1 = (long)b1;
-        }
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            floatx4 acc;
-            if constexpr (PREC == CS_SAMPLER_MLP_BF16) {
-#pragma unroll
-                for (int r = 0; r < 4; ++r) acc[r] = P_lds[offB[L] + 16 * t + 4 * g + r];
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(frag[((L * 4 + t) * 2 + 0) * 64 + lane], B0, acc, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(frag[((L * 4 + t) * 2 + 1) * 64 + lane], B1, acc, 0, 0, 0);
-#pragma unroll
-                for (int r = 0; r < 4; ++r) h[4 * t + r] = silu_fast(acc[r]);
-            } else {
-                acc = {0.0f, 0.0f, 0.0f, 0.0f};
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(frag[((L * 4 + t) * 2 + 0) * 64 + lane], B0, acc, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(frag[((L * 4 + t) * 2 + 1) * 64 + lane], B1, acc, 0, 0, 0);
-#pragma unroll
-                for (int r = 0; r < 4; ++r) h[4 * t + r] = silu_fast(fmaf(acc[r], sc, P_lds[offB[L] + 16 * t + 4 * g + r]));
-            }
-        }
-    }
-    float p0 = 0.0f, p1 = 0.0f;
-#pragma unroll
-    for (int t = 0; t < 4; ++t)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int n = 16 * t + 4 * g + r;
-            p0 = fmaf(P_lds[cW5 + n], h[4 * t + r], p0);
-            p1 = fmaf(P_lds[cW5 + kMlpHidden + n], h[4 * t + r], p1);
-        }
-    // sum the four lane groups (fixed butterfly order)
-    p0 += __shfl_xor(p0, 16, 64);
-    p1 += __shfl_xor(p1, 16, 64);
-    p0 += __shfl_xor(p0, 32, 64);
-    p1 += __shfl_xor(p1, 32, 64);
-    y0 = p0 + P_lds[cB5];
-    y1 = p1 + P_lds[cB5 + 1];
-}
-
-template <int PREC>
-__global__ __launch_bounds__(kMfmaThreads) void k_mlp_mfma(const FwdArgs a, const void* frag_g, const float* scales) {
-    typedef typename FragT<PREC>::type FT;
-    __shared__ FT s_frag[kFragCount];
-    __shared__ float s_P[kSmall];
-    __shared__ float s_sc[6];
-    for (int i = threadIdx.x; i < kFragCount; i += kMfmaThreads) s_frag[i] = ((const FT*)frag_g)[i];
-    load_small_params(a.P, s_P);
-    if (threadIdx.x < 6) s_sc[threadIdx.x] = PREC == CS_SAMPLER_MLP_FP8 ? scales[threadIdx.x] : 1.0f;
+__global__ __launch_bounds__(kMfmaThreads) void k_mlp_mfma(const FwdArgs a, const MlpDev m) {
+    __shared__ NetLds<PREC> s_net;
+    net_load<PREC>(s_net, m);
     __syncthreads();
     const int lane = lane_id();
     const int wave = threadIdx.x >> 6;
@@ -608,7 +467,7 @@ __global__ __launch_bounds__(kMfmaThreads) void k_mlp_mfma(const FwdArgs a, cons
         const float x = active ? a.x[i] : 1.0f, u = active ? a.u[i] : 0.5f;
         float f1, f2, y0, y1;
         features(x, u, f1, f2);
-        mlp_tile<PREC>(s_frag, s_P, s_sc, f1, f2, y0, y1);
+        mlp_tile<PREC>(s_net.frag, s_net.P, s_net.sc, f1, f2, y0, y1);
         if (lane < 16 && active) {
             if (a.y) {
                 a.y[2 * i] = y0;
@@ -640,9 +499,9 @@ hipError_t launch_mlp_forward(const MlpDev& m, cs_sampler prec, const float* x, 
         int64_t blocks = (tiles + 3) / 4;
         if (blocks > 2048) blocks = 2048;
         if (prec == CS_SAMPLER_MLP_BF16)
-            k_mlp_mfma<CS_SAMPLER_MLP_BF16><<<(unsigned)blocks, kMfmaThreads, 0, st>>>(a, m.frag_bf16, m.fp8_scales);
+            k_mlp_mfma<CS_SAMPLER_MLP_BF16><<<(unsigned)blocks, kMfmaThreads, 0, st>>>(a, m);
         else
-            k_mlp_mfma<CS_SAMPLER_MLP_FP8><<<(unsigned)blocks, kMfmaThreads, 0, st>>>(a, m.frag_fp8, m.fp8_scales);
+            k_mlp_mfma<CS_SAMPLER_MLP_FP8><<<(unsigned)blocks, kMfmaThreads, 0, st>>>(a, m);
     }
     return hipGetLastError();
 }

@@ -1,0 +1,270 @@
+// cs_net.h -- device-side evaluation of the sampler network (2 -> 64 x4
+// (SiLU) -> 2), shared by the network kernels and by the collision phase of
+// the step kernels so that both give the same bits for the same inputs.
+//
+// Inputs are FP32: f1 = (log10 x + 1) / 3 maps x in [1e-4, 1e2] onto [-1, 1],
+// f2 = 2u - 1.  Output 0 is cos(theta), output 1 the energy ratio.
+//
+// Two evaluators:
+//   * FP32: either a workgroup-wide engine (cs_mlp.hip) or, inside the step,
+//     one lane per sample (mlp_lane_f32) with the layer outputs in LDS.  Both
+//     accumulate b + sum_k W[j][k] h[k] with k ascending and fmaf, so they
+//     agree bitwise.
+//   * MFMA (BF16 / FP8 E4M3): a wave evaluates 16 samples per tile with
+//     v_mfma_f32_16x16x32_{bf16,fp8}.  Lane l owns sample l%16 and, in group
+//     g = l/16, the neurons 16t + 4g + r (t, r = 0..3): exactly the rows of
+//     the accumulator fragment it holds, so a layer's output stays in
+//     registers and becomes the next layer's B operand once the weight
+//     fragments list the input neurons in the same order (k-slot 8g + e of
+//     k-step s <-> neuron 16(2s + e/4) + 4g + e%4).  Layers 1 and 5 (K = 2,
+//     N = 2) stay in FP32 on the vector ALUs.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "cs_device.h"
+#include "cs_internal.h"
+
+namespace cs {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr float kE4M3Max = 448.0f;
+
+__device__ __forceinline__ float silu_f32(float z) { return z / (1.0f + expf(-z)); }
+
+// SiLU for the reduced-precision paths (its result is rounded to BF16/FP8)
+__device__ __forceinline__ float silu_fast(float z) { return z * __frcp_rn(1.0f + __expf(-z)); }
+
+__device__ __forceinline__ void features(float x, float u, float& f1, float& f2) {
+    f1 = (log10f(x) + 1.0f) / 3.0f;
+    f2 = 2.0f * u - 1.0f;
+}
+
+__device__ __forceinline__ int wave_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// The network answers for x in [CS_MLP_X_MIN, CS_MLP_X_MAX] (as FP32); the
+// plain sampler answers elsewhere.
+__device__ __forceinline__ bool in_range(float x) { return x >= (float)CS_MLP_X_MIN && x <= (float)CS_MLP_X_MAX; }
+
+// Input neuron of k-slot e (0..7) of k-step s in lane group g.
+__host__ __device__ __forceinline__ int frag_in_neuron(int s, int g, int e) {
+    return 16 * (2 * s + e / 4) + 4 * g + (e & 3);
+}
+
+__device__ __forceinline__ uint8_t to_e4m3(float v) {
+    v = fminf(fmaxf(v, -kE4M3Max), kE4M3Max);  // saturating conversion
+    const uint32_t packed = __builtin_amdgcn_cvt_pk_fp8_f32(v, 0.0f, 0u, false);
+    return (uint8_t)(packed & 0xFFu);
+}
+
+// Compact copy of the FP32 parameters the MFMA engine reads from LDS.
+constexpr int cW1 = 0, cB1 = 128, cB2 = 192, cB3 = 256, cB4 = 320, cW5 = 384, cB5 = 512, kSmall = 514;
+
+__device__ __forceinline__ void load_small_params(const float* P, float* s) {
+    for (int i = threadIdx.x; i < kSmall; i += blockDim.x) {
+        int src;
+        if (i < cB1)
+            src = kOffW1 + i;
+        else if (i < cB2)
+            src = kOffB1 + (i - cB1);
+        else if (i < cB3)
+            src = kOffB2 + (i - cB2);
+        else if (i < cB4)
+            src = kOffB3 + (i - cB3);
+        else if (i < cW5)
+            src = kOffB4 + (i - cB4);
+        else if (i < cB5)
+            src = kOffW5 + (i - cW5);
+        else
+            src = kOffB5 + (i - cB5);
+        s[i] = P[src];
+    }
+}
+
+template <int PREC>
+struct FragT;
+template <>
+struct FragT<CS_SAMPLER_MLP_BF16> {
+    typedef bf16x8 type;
+};
+template <>
+struct FragT<CS_SAMPLER_MLP_FP8> {
+    typedef long type;
+};
+
+// One tile of 16 samples on one wave.  Every lane passes the features of
+// sample (lane % 16); every lane receives that sample's outputs.  frag, W1,
+// biases, W5 come from LDS.
+template <int PREC>
+__device__ __forceinline__ void mlp_tile(const typename FragT<PREC>::type* frag, const float* P_lds,
+                                         const float* scales, float f1, float f2, float& y0, float& y1) {
+    const int lane = lane_id();
+    const int g = lane >> 4;
+    float h[16];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int n = 16 * t + 4 * g + r;
+            h[4 * t + r] = silu_fast(fmaf(P_lds[cW1 + 2 * n + 1], f2, fmaf(P_lds[cW1 + 2 * n], f1, P_lds[cB1 + n])));
+        }
+    const int offB[3] = {cB2, cB3, cB4};
+#pragma unroll
+    for (int L = 0; L < 3; ++L) {
+        typename FragT<PREC>::type B0, B1;
+        float sc = 1.0f;
+        if constexpr (PREC == CS_SAMPLER_MLP_BF16) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                B0[e] = (__bf16)h[e];
+                B1[e] = (__bf16)h[8 + e];
+            }
+        } else {
+            const float inv = 1.0f / scales[3 + L];
+            sc = scales[L] * scales[3 + L];
+            uint64_t b0 = 0, b1 = 0;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                b0 |= (uint64_t)to_e4m3(h[e] * inv) << (8 * e);
+                b1 |= (uint64_t)to_e4m3(h[8 + e] * inv) << (8 * e);
+            }
+            B0 = (long)b0;
+            B1 = (long)b1;
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            floatx4 acc;
+            if constexpr (PREC == CS_SAMPLER_MLP_BF16) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) acc[r] = P_lds[offB[L] + 16 * t + 4 * g + r];
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(frag[((L * 4 + t) * 2 + 0) * 64 + lane], B0, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(frag[((L * 4 + t) * 2 + 1) * 64 + lane], B1, acc, 0, 0, 0);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) h[4 * t + r] = silu_fast(acc[r]);
+            } else {
+                acc = {0.0f, 0.0f, 0.0f, 0.0f};
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(frag[((L * 4 + t) * 2 + 0) * 64 + lane], B0, acc, 0, 0,
+                                                                 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(frag[((L * 4 + t) * 2 + 1) * 64 + lane], B1, acc, 0, 0,
+                                                                 0);
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    h[4 * t + r] = silu_fast(fmaf(acc[r], sc, P_lds[offB[L] + 16 * t + 4 * g + r]));
+            }
+        }
+    }
+    float p0 = 0.0f, p1 = 0.0f;
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int n = 16 * t + 4 * g + r;
+            p0 = fmaf(P_lds[cW5 + n], h[4 * t + r], p0);
+            p1 = fmaf(P_lds[cW5 + kMlpHidden + n], h[4 * t + r], p1);
+        }
+    // sum the four lane groups (fixed butterfly order)
+    p0 += __shfl_xor(p0, 16, 64);
+    p1 += __shfl_xor(p1, 16, 64);
+    p0 += __shfl_xor(p0, 32, 64);
+    p1 += __shfl_xor(p1, 32, 64);
+    y0 = p0 + P_lds[cB5];
+    y1 = p1 + P_lds[cB5 + 1];
+}
+
+// One sample per lane in FP32 (cos theta output only).  hb: this wave's
+// [64 neurons][64 lanes] LDS buffer.  The weights are read with wave-uniform
+// addresses (scalar loads).  Must be called by the whole wave.
+__device__ __forceinline__ float mlp_lane_f32(const float* __restrict__ P, float* hb, float f1, float f2) {
+    const int lane = lane_id();
+#pragma unroll 4
+    for (int j = 0; j < kMlpHidden; ++j) {
+        const float z = fmaf(P[kOffW1 + 2 * j + 1], f2, fmaf(P[kOffW1 + 2 * j], f1, P[kOffB1 + j]));
+        hb[j * 64 + lane] = silu_f32(z);
+    }
+    const int offW[3] = {kOffW2, kOffW3, kOffW4};
+    const int offB[3] = {kOffB2, kOffB3, kOffB4};
+    float h[kMlpHidden];
+#pragma unroll 1
+    for (int L = 0; L < 3; ++L) {
+#pragma unroll
+        for (int k = 0; k < kMlpHidden; ++k) h[k] = hb[k * 64 + lane];
+        const float* W = P + offW[L];
+        const float* B = P + offB[L];
+#pragma unroll 1
+        for (int j = 0; j < kMlpHidden; ++j) {
+            float z = B[j];
+#pragma unroll
+            for (int k = 0; k < kMlpHidden; ++k) z = fmaf(W[j * kMlpHidden + k], h[k], z);
+            hb[j * 64 + lane] = silu_f32(z);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kMlpHidden; ++k) h[k] = hb[k * 64 + lane];
+    float a0 = P[kOffB5];
+#pragma unroll
+    for (int k = 0; k < kMlpHidden; ++k) a0 = fmaf(P[kOffW5 + k], h[k], a0);
+    return a0;
+}
+
+// LDS of the network inside a step kernel (nothing for the plain sampler).
+template <int SAMP>
+struct NetLds {
+    char unused;
+};
+template <>
+struct NetLds<CS_SAMPLER_MLP_F32> {
+    float h[4][kMlpHidden * 64];  // one [64][64] buffer per wave (4 waves)
+};
+template <>
+struct NetLds<CS_SAMPLER_MLP_BF16> {
+    bf16x8 frag[kFragCount];
+    float P[kSmall];
+    float sc[6];
+};
+template <>
+struct NetLds<CS_SAMPLER_MLP_FP8> {
+    long frag[kFragCount];
+    float P[kSmall];
+    float sc[6];
+};
+
+// Fill the network LDS (MFMA precisions); every thread of the block calls it,
+// followed by a barrier.
+template <int SAMP>
+__device__ __forceinline__ void net_load(NetLds<SAMP>& s, const MlpDev& m) {
+    if constexpr (SAMP == CS_SAMPLER_MLP_BF16 || SAMP == CS_SAMPLER_MLP_FP8) {
+        typedef typename FragT<SAMP>::type FT;
+        const FT* src = (const FT*)(SAMP == CS_SAMPLER_MLP_BF16 ? m.frag_bf16 : m.frag_fp8);
+        for (int i = threadIdx.x; i < kFragCount; i += blockDim.x) s.frag[i] = src[i];
+        load_small_params(m.params, s.P);
+        if (threadIdx.x < 6) s.sc[threadIdx.x] = SAMP == CS_SAMPLER_MLP_FP8 ? m.fp8_scales[threadIdx.x] : 1.0f;
+    }
+}
+
+// cos(theta) from the network for every lane of the wave with need == true
+// (features f1, f2 of the lane's own sample); other lanes get 0.  Must be
+// called by the whole wave (converged).
+template <int SAMP>
+__device__ __forceinline__ float net_mu_hat(NetLds<SAMP>& s, const MlpDev& m, bool need, float f1, float f2) {
+    float out = 0.0f;
+    if constexpr (SAMP == CS_SAMPLER_MLP_F32) {
+        if (__any(need)) out = mlp_lane_f32(m.params, s.h[wave_uniform((int)threadIdx.x >> 6)], f1, f2);
+    } else if constexpr (SAMP == CS_SAMPLER_MLP_BF16 || SAMP == CS_SAMPLER_MLP_FP8) {
+        const int lane = lane_id();
+#pragma unroll 1
+        for (int tile = 0; tile < 4; ++tile) {
+            if (!__any(need && (lane >> 4) == tile)) continue;
+            const int src = 16 * tile + (lane & 15);
+            const float g1 = __shfl(f1, src, 64), g2 = __shfl(f2, src, 64);
+            float y0, y1;
+            mlp_tile<SAMP>(s.frag, s.P, s.sc, g1, g2, y0, y1);
+            if ((lane >> 4) == tile) out = y0;
+        }
+    }
+    return need ? out : 0.0f;
+}
+
+}  // namespace cs

@@ -7,6 +7,7 @@
 #include <stdint.h>
 
 #include "cs_device.h"
+#include "cs_net.h"
 
 namespace cs {
 
@@ -94,6 +95,7 @@ __device__ __forceinline__ PairOutcome pair_eval(const Particles<T>& a, bool act
 
 struct CollideSums {
     double e_before = 0.0, e_after = 0.0;
+    long long n_fallback = 0;  // network samplers: samples the plain sampler answered
 };
 
 template <typename T>
@@ -182,6 +184,79 @@ __device__ __forceinline__ void collide_staged(const Particles<T>& a, bool activ
     write_back<T>(a, ie, e->ig, (double)e->we, (double)e->wg, s, seed, step);
     sums.e_before += s.e_before;
     sums.e_after += s.e_after;
+}
+
+// Where a collision's particle values come from: an LDS queue entry or the
+// particle arrays.
+template <typename T>
+struct FromStaged {
+    const StagedPair<T>* e;
+    __device__ __forceinline__ void get(const Particles<T>&, int32_t& ie, int32_t& ig, d3& p, d3& k, double& we,
+                                        double& wg) const {
+        ie = e->ie;
+        ig = e->ig;
+        p = {(double)e->p[0], (double)e->p[1], (double)e->p[2]};
+        k = {(double)e->k[0], (double)e->k[1], (double)e->k[2]};
+        we = (double)e->we;
+        wg = (double)e->wg;
+    }
+};
+template <typename T>
+struct FromArrays {
+    int32_t ie, ig;
+    __device__ __forceinline__ void get(const Particles<T>& a, int32_t& ie_, int32_t& ig_, d3& p, d3& k,
+                                        double& we, double& wg) const {
+        ie_ = ie;
+        ig_ = ig;
+        p = load_p(a, ie);
+        k = load_k(a, ig);
+        we = (double)a.ew[ie];
+        wg = (double)a.gw[ig];
+    }
+};
+
+// Resolve an accepted pair with the sampler network: the network maps the
+// FP32-rounded (x, u) to cos(theta), clamped to [-1, 1]; outside the
+// network's x domain the plain sampler answers (counted in n_fallback).  The
+// same Philox draw as the plain sampler supplies u and the azimuth.  Must be
+// called by the whole wave; lanes with active == false write nothing.
+template <typename T, int SAMP, typename Src>
+__device__ __forceinline__ void collide_net(const Particles<T>& a, bool active, const Src& src, NetLds<SAMP>& s_net,
+                                            const MlpDev& m, uint64_t seed, uint64_t step, CollideSums& sums) {
+    double x = 0.0;
+    int32_t ie = 0;
+    if (active) {
+        int32_t ig;
+        d3 p, k;
+        double we, wg;
+        src.get(a, ie, ig, p, k, we, wg);
+        x = pair_invariants(p, k).x;
+    }
+    const u32x4 r = draw(seed, (uint64_t)ie, step, kScatter);
+    const double u = uniform53(r.a, r.b);
+    const float xf = (float)x, uf = (float)u;
+    const bool inside = active && in_range(xf);
+    const bool fallback = active && !inside;
+    float f1 = 0.0f, f2 = 0.0f;
+    if (inside) features(xf, uf, f1, f2);
+    const float mu_hat = net_mu_hat<SAMP>(s_net, m, inside, f1, f2);
+    double v = 0.0;
+    if (__any(fallback)) {
+        const double vf = angle_icdf_v(fallback ? u : 0.5, fallback ? x : 0.0);
+        if (fallback) v = vf;
+    }
+    if (!active) return;
+    if (inside) v = 1.0 - (double)fminf(fmaxf(mu_hat, -1.0f), 1.0f);
+    int32_t ig;
+    d3 p, k;
+    double we, wg;
+    src.get(a, ie, ig, p, k, we, wg);
+    const PairInv inv = pair_invariants(p, k);
+    const Scattered s = scatter(p, k, inv, v, uniform53(r.c, r.d));
+    write_back<T>(a, ie, ig, we, wg, s, seed, step);
+    sums.e_before += s.e_before;
+    sums.e_after += s.e_after;
+    sums.n_fallback += fallback ? 1 : 0;
 }
 
 }  // namespace cs
