@@ -1,17 +1,20 @@
-"""Benchmark: scattering pairs/s of the Compton step on one MI355X.
+"""Benchmark: scattering pairs/s of the Compton step on one MI355X, the
+network sampler (BF16 on MFMA by default) against the plain inverse-CDF
+sampler, with the KS distance of their outputs.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload grid]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload grid_large]
+                    [--sampler mlp_bf16] [--strategy fused]
 
 A step is one cs_compton_step call over the whole plasma (pairing, boost,
 cross-section, probability, accept/compaction, sampling, scattering,
-write-back, stats).  The default workload is the 64x64-cell FP32 grid with
-256 electrons and 256 photons per cell (Maxwell-Juttner kT = 0.5 electrons,
-photons log-uniform in [1e-4, 1e-1]); inputs are resident in device memory
-before the timed region starts.  Prints one JSON line.
+write-back, stats).  The default workload is the 128x128-cell FP32 grid with
+256 electrons and 256 photons per cell (2^22 pairs per step; Maxwell-Juttner
+kT = 0.5 electrons, photons log-uniform in [1e-4, 1e-1]); the particles are
+resident in device memory before the timed region starts.  The sampler
+network is the trained one shipped in the package.  Prints one JSON line.
 """
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -19,8 +22,13 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+WEIGHTS = os.path.join(ROOT, "paper_2206_02937_amd", "weights", "sampler_2x64x4.csnet")
 PEAK_HBM_GBS = 8000.0
-PEAK_FP64_TFLOPS = 78.6
+PEAK_MFMA_TFLOPS = {"mlp_bf16": 2500.0, "mlp_fp8": 5000.0}
+PEAK_FP32_TFLOPS = 157.3
+MLP_MFMA_FLOPS = 3 * 64 * 64 * 2  # hidden 64x64 layers per sample
+WORKLOADS = ["grid_large", "grid", "single_cell", "uneven", "power_law"]
+METRIC = "scattering pairs/s, MLP vs plain sampler, 1 MI355X at KS≤2e-3 vs FP64 oracle"
 
 
 def parse():
@@ -28,13 +36,16 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="grid", choices=["grid", "single_cell", "uneven", "power_law", "grid_large"])
-    ap.add_argument("--sampler", default="plain")
+    ap.add_argument("--workload", default="grid_large", choices=WORKLOADS)
+    ap.add_argument("--sampler", default="mlp_bf16", choices=["plain", "mlp_f32", "mlp_bf16", "mlp_fp8"])
     ap.add_argument("--strategy", default="fused", choices=["fused", "compact", "multi_kernel"])
     ap.add_argument("--chunks-per-block", type=int, default=0, help="fused strategy; 0 = automatic")
     ap.add_argument("--sweep", action="store_true", help="time every strategy / chunks-per-block candidate")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain-sampler comparison run")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--traffic-calibration", action="store_true",
+                    help="end with one plain 256 MiB device-to-device copy (scale for the HBM byte counters)")
     return ap.parse_args()
 
 
@@ -72,35 +83,112 @@ def cpu_baseline(p, seconds):
             n_steps = int(n_steps * grow) + 1
     return {"value": pairs / elapsed, "unit": "pairs/s", "cores": threads, "kind": "oracle",
             "sample": f"{n_steps} step(s) over {n_sel} of {p.n_cells} cells ({pairs} pair-steps) of the same "
-                      f"plasma, {elapsed:.1f} s"}
+                      f"plasma, plain sampler, {elapsed:.1f} s"}
 
 
-def sweep(ctx, p, args):
-    """Time each kernel strategy on the same initial state (printed as JSON
-    lines tagged "sweep"); the measured line that follows uses the options
-    given on the command line."""
+def load_network(ctx, sampler):
+    import numpy as np
+    import torch
+
+    from paper_2206_02937_amd import compton, plasma
+
+    if sampler == "plain":
+        return None
+    net = compton.MLP.load(ctx, WEIGHTS)
+    if sampler == "mlp_bf16":
+        net.quantize("mlp_bf16")
+    elif sampler == "mlp_fp8":
+        cx, cu = plasma.sampler_inputs(65536, seed=7)
+        net.quantize("mlp_fp8", torch.from_numpy(cx.astype(np.float32)).cuda(),
+                     torch.from_numpy(cu.astype(np.float32)).cuda())
+    torch.cuda.synchronize()
+    return net
+
+
+def run_steps(ctx, p, sampler, net, steps, warmup, step0=0):
+    """Warm up, then time `steps` steps (wall clock between two device
+    synchronisations, plus the library's per-stage HIP events recorded on the
+    launch stream during the same steps)."""
     import torch
 
     from paper_2206_02937_amd import compton
 
-    cands = [("compact", 0), ("multi_kernel", 0)] + [("fused", g) for g in (2, 4, 8, 16)]
-    for strategy, gpb in cands:
-        ctx.set_strategy(strategy)
-        ctx.set_chunks_per_block(gpb)
-        e, g, oe, og = compton.to_device(p)
-        for s in range(3):
-            ctx.step(e, g, oe, og, p.dt, p.density_norm, p.seed, s, sampler=args.sampler)
+    e, g, oe, og = compton.to_device(p)
+    stats = ctx.stats_buffer()
+    step = step0
+    for _ in range(warmup):
+        ctx.step(e, g, oe, og, p.dt, p.density_norm, p.seed, step, sampler=sampler, mlp=net, stats=stats)
+        step += 1
+    torch.cuda.synchronize()
+    ctx.set_stage_timing(True)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record()
+    collided = 0
+    for _ in range(steps):
+        ctx.step(e, g, oe, og, p.dt, p.density_norm, p.seed, step, sampler=sampler, mlp=net, stats=stats)
+        step += 1
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    stage_ms = ctx.stage_times()
+    ctx.set_stage_timing(False)
+    st = compton.decode_stats(stats)
+    return {"pairs_per_s": p.n_pairs * steps / wall, "ms_per_step": wall * 1e3 / steps,
+            "gpu_ms_per_step": ev0.elapsed_time(ev1) / steps, "stage_ms": stage_ms, "last_stats": st}
+
+
+def sampler_stage(ctx, p, net, sampler, n=1 << 22):
+    """Sampler-stage throughput on the same n (x, u) inputs drawn from the
+    plasma's pairs: the plain FP64 inverse-CDF sampler and the network, plus
+    the KS distance of the network's outputs from the plain sampler's."""
+    import numpy as np
+    import torch
+
+    from paper_2206_02937_amd import sampler_quality as sq
+
+    x, u = sq.plasma_inputs(p, n, seed=0)
+    xd = torch.from_numpy(x.astype(np.float32)).cuda()
+    ud = torch.from_numpy(u.astype(np.float32)).cuda()
+    mu = torch.empty_like(xd)
+    r = torch.empty_like(xd)
+
+    def timed(fn, reps=20):
+        fn()
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        n = 50
-        for s in range(3, 3 + n):
-            ctx.step(e, g, oe, og, p.dt, p.density_norm, p.seed, s, sampler=args.sampler)
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
         torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / n
-        print(json.dumps({"sweep": True, "strategy": strategy, "chunks_per_block": gpb, "ms_per_step": dt * 1e3,
-                          "pairs_per_s": p.n_pairs / dt}), flush=True)
-    ctx.set_strategy(args.strategy)
-    ctx.set_chunks_per_block(args.chunks_per_block)
+        return a.elapsed_time(b) / reps * 1e-3
+
+    out = {"n": n, "inputs": "x of the plasma's electron-photon pairs, u uniform"}
+    out["plain"] = n / timed(lambda: ctx.sample_plain(xd, ud, mu, r))
+    mu_p, r_p = mu.cpu().numpy(), r.cpu().numpy()
+    res = {}
+    if net is not None:
+        mask = torch.empty(n, dtype=torch.uint8, device=xd.device)
+        from paper_2206_02937_amd import compton
+
+        lib = compton.lib()
+
+        def net_sample(prec):
+            ctx._check(lib.cs_mlp_sample(ctx.handle, net.handle, compton.SAMPLERS[prec], compton._ptr(xd),
+                                         compton._ptr(ud), n, compton._ptr(mu), compton._ptr(r),
+                                         compton._ptr(mask), compton._stream(None)))
+
+        precs = ["mlp_f32", sampler] if sampler != "mlp_f32" else ["mlp_f32"]
+        for prec in precs:
+            t = timed(lambda: net_sample(prec))
+            out[prec] = n / t
+            ks_mu = sq.ks_distance(mu.cpu().numpy(), mu_p)
+            ks_r = sq.ks_distance(r.cpu().numpy(), r_p)
+            res[prec] = {"mu": ks_mu, "r": ks_r, "fallback_frac": float(mask.float().mean().item()), "t": t}
+    return out, res
 
 
 def main():
@@ -109,7 +197,6 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a design note, "
                                    "not an implemented path", "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
-    import numpy as np
     import torch
 
     from paper_2206_02937_amd import compton, plasma
@@ -119,103 +206,115 @@ def main():
     ctx = compton.Context(0)
     ctx.set_strategy(args.strategy)
     ctx.set_chunks_per_block(args.chunks_per_block)
+    net = load_network(ctx, args.sampler)
     if args.sweep:
-        sweep(ctx, p, args)
-    e, g, oe, og = compton.to_device(p)
-    stats = ctx.stats_buffer()
-    step = 0
-    for _ in range(args.warmup):
-        ctx.step(e, g, oe, og, p.dt, p.density_norm, p.seed, step, sampler=args.sampler, stats=stats)
-        step += 1
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    ev0.record()
-    for _ in range(args.steps):
-        ctx.step(e, g, oe, og, p.dt, p.density_norm, p.seed, step, sampler=args.sampler, stats=stats)
-        step += 1
-    ev1.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    gpu_ms = ev0.elapsed_time(ev1)
-    st = compton.decode_stats(stats)
-    elapsed = wall
-    value = n_pairs * args.steps / elapsed
+        sweep(ctx, p, args, net)
+    print(json.dumps({"progress": "timing", "sampler": args.sampler}), flush=True)
+    main_run = run_steps(ctx, p, args.sampler, net, args.steps, args.warmup)
+    plain_run = None
+    if args.sampler != "plain" and not args.no_plain:
+        print(json.dumps({"progress": "timing", "sampler": "plain"}), flush=True)
+        plain_run = run_steps(ctx, p, "plain", None, args.steps, args.warmup)
+    print(json.dumps({"progress": "sampler stage"}), flush=True)
+    stage, ks = sampler_stage(ctx, p, net, args.sampler)
 
-    # per-stage durations with HIP events recorded on the launch stream
-    n_prof = max(10, min(args.steps, 100))
-    ctx.set_stage_timing(True)
-    acc = {k: 0.0 for k in compton.STAGES}
-    collided = 0
-    for _ in range(n_prof):
-        ctx.step(e, g, oe, og, p.dt, p.density_norm, p.seed, step, sampler=args.sampler, stats=stats)
-        step += 1
-        for k, v in ctx.stage_times().items():
-            acc[k] += v
-        collided += compton.decode_stats(stats)["n_collided"]
-    ctx.set_stage_timing(False)
-    stage_ms = {k: v / n_prof for k, v in acc.items()}
-    acc_per_step = collided / n_prof
     sb = storage_bytes(p.e["x"].dtype)
-    # algorithmic bytes per launch: pair kernel reads both species (8 values a
-    # pair) and writes 8 B per accepted pair; collide kernel reads the list
-    # entry and both particles and writes 6 values per accepted pair
-    pair_bytes = n_pairs * 8 * sb + acc_per_step * 8
-    collide_bytes = acc_per_step * (8 + 8 * sb + 6 * sb)
-    if args.strategy == "multi_kernel":
-        dominant = max(["pair", "collide"], key=lambda k: stage_ms[k])
-    elif args.strategy == "compact":
-        dominant = max(["pair", "collide"], key=lambda k: stage_ms[k])
+    st = main_run["last_stats"]
+    acc_per_step = st["n_collided"]
+    stage_ms = main_run["stage_ms"]
+    # algorithmic bytes of the dominant kernel (k_step, fused strategy: every
+    # pair reads both particles, 8 values; every collision writes 6 values
+    # back); for the other strategies the pair and collide kernels separately
+    if args.strategy == "fused":
+        kern, ms = "k_step", stage_ms["pair"]
+        bytes_launch = n_pairs * 8 * sb + acc_per_step * 6 * sb
     else:
-        dominant = "fused"
-    if dominant == "fused":
-        # fused strategy: k_step does the whole per-pair work; bytes as both
-        # stages together (reads of every pair + write-back of accepted pairs)
-        step_bytes = n_pairs * 8 * sb + acc_per_step * 6 * sb
-        achieved = step_bytes / (stage_ms["pair"] * 1e-3) / 1e9
-        roof = {"kernel": "k_step", "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": achieved / PEAK_HBM_GBS, "traffic": None,
-                "bytes_per_launch": step_bytes, "avg_ms": stage_ms["pair"]}
-    elif dominant == "pair":
-        achieved = pair_bytes / (stage_ms["pair"] * 1e-3) / 1e9
-        roof = {"kernel": "k_pair", "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": achieved / PEAK_HBM_GBS, "traffic": None,
-                "bytes_per_launch": pair_bytes, "avg_ms": stage_ms["pair"]}
-    else:
-        achieved = collide_bytes / (stage_ms["collide"] * 1e-3) / 1e9
-        roof = {"kernel": "k_collide", "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": achieved / PEAK_HBM_GBS, "traffic": None,
-                "bytes_per_launch": collide_bytes, "avg_ms": stage_ms["collide"]}
-
+        kern = "k_pair_compact" if args.strategy == "compact" else "k_pair"
+        ms = stage_ms["pair"]
+        bytes_launch = n_pairs * 8 * sb + acc_per_step * 8
+        if stage_ms["collide"] > ms:
+            kern = "k_collide_dense" if args.strategy == "compact" else "k_collide"
+            ms = stage_ms["collide"]
+            bytes_launch = acc_per_step * (8 + 8 * sb + 6 * sb)
+    achieved = bytes_launch / (ms * 1e-3) / 1e9
+    roof = {"kernel": kern, "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": achieved / PEAK_HBM_GBS, "traffic": None, "bytes_per_launch": bytes_launch, "avg_ms": ms,
+            "units_per_launch": f"{n_pairs} pairs, {acc_per_step} collisions"}
+    roof_mlp = None
+    if args.sampler in PEAK_MFMA_TFLOPS and args.sampler in ks:
+        t = ks[args.sampler]["t"]
+        tf = stage["n"] * MLP_MFMA_FLOPS / t / 1e12
+        roof_mlp = {"kernel": f"k_mlp_mfma<{args.sampler[4:]}>", "bound": "mfma", "achieved": tf,
+                    "peak": PEAK_MFMA_TFLOPS[args.sampler], "unit": "TFLOP/s",
+                    "frac": tf / PEAK_MFMA_TFLOPS[args.sampler], "traffic": None,
+                    "flops_per_launch": stage["n"] * MLP_MFMA_FLOPS, "avg_ms": t * 1e3}
     cpu = None
     if not args.no_cpu:
+        print(json.dumps({"progress": "cpu baseline"}), flush=True)
         cpu = cpu_baseline(p, args.cpu_seconds)
 
+    dtype = {"plain": "f64", "mlp_f32": "f64/f32", "mlp_bf16": "f64/bf16", "mlp_fp8": "f64/fp8"}[args.sampler]
     line = {
-        "metric": "scattering pairs/s, MLP vs plain sampler, 1 MI355X at KS<=2e-3 vs FP64 oracle",
-        "value": value,
+        "metric": METRIC,
+        "value": main_run["pairs_per_s"],
         "unit": "pairs/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": elapsed * 1e3 / args.steps,
+        "ms_per_step": main_run["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if sb == 8 else "f32 storage, f64 arithmetic",
+        "dtype": dtype,
         "data": "synthetic",
-        "config": {"workload": p.name, "cells": p.n_cells, "pairs_per_step": n_pairs, "sampler": args.sampler,
-                   "collisions_per_step": acc_per_step, "strategy": args.strategy,
-                   "chunks_per_block": args.chunks_per_block},
-        "gpu_ms_per_step": gpu_ms / args.steps,
+        "config": {"workload": f"{p.name}: {p.n_cells} cells, {n_pairs} pairs per step, "
+                               f"{'fp32' if sb == 4 else 'fp64'} particles",
+                   "cells": p.n_cells, "pairs_per_step": n_pairs, "sampler": args.sampler,
+                   "strategy": args.strategy, "chunks_per_block": args.chunks_per_block,
+                   "collisions_per_step": acc_per_step},
+        "gpu_ms_per_step": main_run["gpu_ms_per_step"],
         "stage_ms": stage_ms,
+        "plain": None if plain_run is None else {k: plain_run[k] for k in
+                                                 ("pairs_per_s", "ms_per_step", "gpu_ms_per_step", "stage_ms")},
+        "mlp_vs_plain": None if plain_run is None else main_run["pairs_per_s"] / plain_run["pairs_per_s"],
+        "ks": {k: {"mu": v["mu"], "r": v["r"], "fallback_frac": v["fallback_frac"]} for k, v in ks.items()},
+        "sampler_stage_samples_per_s": {k: v for k, v in stage.items() if k not in ("n", "inputs")},
         "roofline": roof,
+        "roofline_mlp": roof_mlp,
         "cpu_baseline": cpu,
         "last_stats": st,
     }
     print(json.dumps(line), flush=True)
+    if args.traffic_calibration:
+        # a plain copy kernel of known size: its FETCH_SIZE / WRITE_SIZE
+        # readings give the counters' scale against bytes actually moved
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"traffic_calibration_bytes": src.numel() * 4}), flush=True)
+    if net is not None:
+        net.close()
     ctx.close()
+
+
+def sweep(ctx, p, args, net):
+    """Time each kernel strategy on the same initial state (printed as JSON
+    lines tagged "sweep"); the measured run that follows uses the options
+    given on the command line."""
+    cands = [("compact", 0)] + [("fused", g) for g in (2, 4, 8, 16, 32)]
+    if args.sampler == "plain":
+        cands.append(("multi_kernel", 0))
+    for strategy, gpb in cands:
+        ctx.set_strategy(strategy)
+        ctx.set_chunks_per_block(gpb)
+        r = run_steps(ctx, p, args.sampler, net, 50, 3)
+        print(json.dumps({"sweep": True, "strategy": strategy, "chunks_per_block": gpb,
+                          "ms_per_step": r["ms_per_step"], "pairs_per_s": r["pairs_per_s"],
+                          "stage_ms": r["stage_ms"]}), flush=True)
+    ctx.set_strategy(args.strategy)
+    ctx.set_chunks_per_block(args.chunks_per_block)
 
 
 if __name__ == "__main__":

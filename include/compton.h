@@ -269,10 +269,15 @@ typedef enum {
 
 /* Enable (1) or disable (0) per-stage timing: while enabled, every
  * cs_compton_step records HIP events between its stages on its stream
- * (the Sec. 3.3 stage breakdown of the paper, measured on the device). */
+ * (the Sec. 3.3 stage breakdown of the paper, measured on the device) into a
+ * ring of 512 steps; no host synchronisation happens during the steps.
+ * Either call restarts the count of timed steps. */
 cs_status cs_set_stage_timing(cs_ctx* ctx, int enable);
 /* Synchronous: wait for the last timed step and write up to n stage
- * durations in milliseconds (index = cs_stage); *n_written gets the count. */
+ * durations in milliseconds (index = cs_stage), each the mean over the steps
+ * timed since timing was enabled or since the previous read (the last 512 of
+ * them at most); *n_written gets the count.  CS_ERR_NOT_READY when no step
+ * was timed. */
 cs_status cs_stage_times(cs_ctx* ctx, float* ms_out, int32_t n, int32_t* n_written);
 
 #ifdef __cplusplus

@@ -48,6 +48,10 @@ def lib():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2206_02937_amd.build`")
+    # torch first: the library then binds to the HIP runtime torch has loaded,
+    # so that both share one runtime (devices, streams, memory)
+    import torch  # noqa: F401
+
     L = C.CDLL(LIB_PATH)
     vp, i64, u64, d, i32 = C.c_void_p, C.c_int64, C.c_uint64, C.c_double, C.c_int32
     st = C.c_int

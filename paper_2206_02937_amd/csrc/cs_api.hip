@@ -125,6 +125,7 @@ cs_status cs_destroy(cs_ctx* ctx) {
         }
         for (auto& ev : ctx->events)
             if (ev) (void)hipEventDestroy(ev);
+        ctx->events.clear();
     }
     delete ctx;
     return CS_OK;
@@ -234,7 +235,11 @@ cs_status cs_compton_step(cs_ctx* ctx, cs_dtype dtype, cs_species electrons, cs_
     p.sampler = sampler;
     p.net = mlp ? mlp->dev() : cs::MlpDev{nullptr, nullptr, nullptr, nullptr};
     p.stats = stats;
-    p.events = ctx->timing ? ctx->events : nullptr;
+    p.events = nullptr;
+    if (ctx->timing) {
+        const int64_t slot = ctx->timed_steps % cs::kTimingRing;
+        p.events = ctx->events.data() + slot * (CS_STAGE_COUNT + 1);
+    }
     p.use_device_step = 0;
     hipError_t e;
     if (strategy == CS_STRATEGY_FUSED) {
@@ -251,7 +256,7 @@ cs_status cs_compton_step(cs_ctx* ctx, cs_dtype dtype, cs_species electrons, cs_
         e = cs::launch_step(sh, b, p, st);
     }
     if (e != hipSuccess) return hip_fail(ctx, e, "cs_compton_step: launch");
-    if (ctx->timing) ctx->timed_step_pending = true;
+    if (ctx->timing) ctx->timed_steps += 1;
     ctx->last_error.clear();
     return CS_OK;
 }
@@ -325,32 +330,41 @@ cs_status cs_sample_plain(cs_ctx* ctx, cs_dtype dtype, const void* x, const void
 cs_status cs_set_stage_timing(cs_ctx* ctx, int enable) {
     if (!ctx) return CS_ERR_INVALID_ARG;
     DeviceGuard g(ctx->device);
-    if (enable) {
+    if (enable && ctx->events.empty()) {
+        ctx->events.assign((size_t)cs::kTimingRing * (CS_STAGE_COUNT + 1), nullptr);
         for (auto& ev : ctx->events) {
-            if (ev) continue;
             hipError_t e = hipEventCreate(&ev);
             if (e != hipSuccess) return hip_fail(ctx, e, "cs_set_stage_timing: hipEventCreate");
         }
     }
     ctx->timing = enable != 0;
+    ctx->timed_steps = 0;
     ctx->last_error.clear();
     return CS_OK;
 }
 
 cs_status cs_stage_times(cs_ctx* ctx, float* ms_out, int32_t n, int32_t* n_written) {
     if (!ctx || !ms_out || n < 0) return CS_ERR_INVALID_ARG;
-    if (!ctx->timed_step_pending) return fail(ctx, CS_ERR_NOT_READY, "cs_stage_times: no timed step");
+    if (ctx->timed_steps == 0) return fail(ctx, CS_ERR_NOT_READY, "cs_stage_times: no timed step");
     DeviceGuard g(ctx->device);
-    hipError_t e = hipEventSynchronize(ctx->events[CS_STAGE_COUNT]);
+    const int64_t n_rec = ctx->timed_steps < cs::kTimingRing ? ctx->timed_steps : cs::kTimingRing;
+    const int64_t last = (ctx->timed_steps - 1) % cs::kTimingRing;
+    constexpr int kEv = CS_STAGE_COUNT + 1;
+    hipError_t e = hipEventSynchronize(ctx->events[last * kEv + CS_STAGE_COUNT]);
     if (e != hipSuccess) return hip_fail(ctx, e, "cs_stage_times: hipEventSynchronize");
-    int32_t m = n < CS_STAGE_COUNT ? n : CS_STAGE_COUNT;
-    for (int32_t i = 0; i < m; ++i) {
-        float ms = 0.f;
-        e = hipEventElapsedTime(&ms, ctx->events[i], ctx->events[i + 1]);
-        if (e != hipSuccess) return hip_fail(ctx, e, "cs_stage_times: hipEventElapsedTime");
-        ms_out[i] = ms;
+    const int32_t m = n < CS_STAGE_COUNT ? n : CS_STAGE_COUNT;
+    double acc[CS_STAGE_COUNT] = {};
+    for (int64_t slot = 0; slot < n_rec; ++slot) {
+        for (int32_t i = 0; i < m; ++i) {
+            float ms = 0.f;
+            e = hipEventElapsedTime(&ms, ctx->events[slot * kEv + i], ctx->events[slot * kEv + i + 1]);
+            if (e != hipSuccess) return hip_fail(ctx, e, "cs_stage_times: hipEventElapsedTime");
+            acc[i] += ms;
+        }
     }
+    for (int32_t i = 0; i < m; ++i) ms_out[i] = (float)(acc[i] / (double)n_rec);
     if (n_written) *n_written = m;
+    ctx->timed_steps = 0;
     ctx->last_error.clear();
     return CS_OK;
 }

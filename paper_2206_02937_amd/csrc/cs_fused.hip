@@ -138,6 +138,8 @@ struct FusedArgs {
     MlpDev mlp;  // network samplers only
 };
 
+// Resolve the n staged pairs at queue[0..n): the plain sampler, or the
+// network (every entry of this stack lies in the network's domain).
 template <typename T, int SAMP>
 __device__ void drain(const FusedArgs<T>& a, const StagedPair<T>* queue, int n, uint64_t step, NetLds<SAMP>& s_net,
                       CollideSums& sums) {
@@ -155,12 +157,28 @@ __device__ void drain(const FusedArgs<T>& a, const StagedPair<T>* queue, int n, 
     }
 }
 
+// Network samplers: the n pairs outside the network's domain, staged from
+// the top of the queue down (queue[cap - 1 - q]), go to the plain sampler in
+// dense passes.
+template <typename T>
+__device__ void drain_fallback(const FusedArgs<T>& a, const StagedPair<T>* queue, int n, uint64_t step,
+                               CollideSums& sums) {
+    for (int base = 0; base < n; base += kChunk) {
+        const int q = base + (int)threadIdx.x;
+        if (__any(q < n)) {
+            const bool active = q < n;
+            collide_staged<T>(a.pt, active, queue + (kQueueCap - 1 - (active ? q : 0)), a.seed, step, sums);
+            sums.n_fallback += active ? 1 : 0;
+        }
+    }
+}
+
 template <typename T, int SAMP>
 __global__ __launch_bounds__(kChunk) void k_step(const FusedArgs<T> a) {
     __shared__ StagedPair<T> s_queue[kQueueCap];
     __shared__ NetLds<SAMP> s_net;
-    __shared__ int s_wcnt[kChunk / 64];
-    __shared__ int s_qn;
+    __shared__ int s_wcnt[2][kChunk / 64];
+    __shared__ int s_qn, s_qf;
     __shared__ double s_red_d[3 * (kChunk / 64)];
     __shared__ long long s_red_i[4 * (kChunk / 64)];
     const int tid = threadIdx.x;
@@ -173,7 +191,7 @@ __global__ __launch_bounds__(kChunk) void k_step(const FusedArgs<T> a) {
     double sum_p = 0.0;
     long long n_clip = 0, n_inv = 0, n_coll = 0;
     CollideSums sums;
-    if (tid == 0) s_qn = 0;
+    if (tid == 0) s_qn = s_qf = 0;
     net_load<SAMP>(s_net, a.mlp);
     __syncthreads();
     if (layout_ok) {
@@ -203,19 +221,31 @@ __global__ __launch_bounds__(kChunk) void k_step(const FusedArgs<T> a) {
             sum_p += o.P;
             n_clip += o.clipped ? 1 : 0;
             n_inv += o.invalid ? 1 : 0;
-            const uint64_t mask = __ballot(o.accept);
-            const int before = __popcll(mask & ((1ull << lane) - 1ull));
-            if (lane == 0) s_wcnt[wave] = __popcll(mask);
+            // accepted pairs are staged in LDS: from the bottom of the queue,
+            // or (network samplers, x outside the network's domain) from the top
+            bool to_fb = false;
+            if constexpr (SAMP != CS_SAMPLER_PLAIN) to_fb = o.accept && !in_range((float)o.x);
+            const bool to_main = o.accept && !to_fb;
+            const uint64_t lt = (1ull << lane) - 1ull;
+            const uint64_t mask = __ballot(to_main), mask_fb = __ballot(to_fb);
+            const int before = __popcll(mask & lt), before_fb = __popcll(mask_fb & lt);
+            if (lane == 0) {
+                s_wcnt[0][wave] = __popcll(mask);
+                s_wcnt[1][wave] = __popcll(mask_fb);
+            }
             __syncthreads();
-            int wbase = 0, total = 0;
+            int wbase = 0, total = 0, wbase_fb = 0, total_fb = 0;
 #pragma unroll
             for (int w = 0; w < kChunk / 64; ++w) {
-                wbase += w < wave ? s_wcnt[w] : 0;
-                total += s_wcnt[w];
+                wbase += w < wave ? s_wcnt[0][w] : 0;
+                total += s_wcnt[0][w];
+                wbase_fb += w < wave ? s_wcnt[1][w] : 0;
+                total_fb += s_wcnt[1][w];
             }
-            const int qn = s_qn;
+            const int qn = s_qn, qf = s_qf;
             if (o.accept) {
-                StagedPair<T>& e = s_queue[qn + wbase + before];
+                StagedPair<T>& e = to_fb ? s_queue[kQueueCap - 1 - (qf + wbase_fb + before_fb)]
+                                         : s_queue[qn + wbase + before];
                 e.ie = o.ie;
                 e.ig = o.ig;
                 e.p[0] = a.pt.ex[o.ie];
@@ -229,17 +259,23 @@ __global__ __launch_bounds__(kChunk) void k_step(const FusedArgs<T> a) {
             }
             n_coll += o.accept ? 1 : 0;
             __syncthreads();
-            if (qn + total >= kChunk) {
+            // both stacks hold < kChunk entries together before a chunk adds
+            // at most kChunk, so they never meet (kQueueCap = 2 kChunk)
+            if (qn + total + qf + total_fb >= kChunk) {
                 drain<T, SAMP>(a, s_queue, qn + total, step, s_net, sums);
+                if constexpr (SAMP != CS_SAMPLER_PLAIN) drain_fallback<T>(a, s_queue, qf + total_fb, step, sums);
                 __syncthreads();
-                if (tid == 0) s_qn = 0;
+                if (tid == 0) s_qn = s_qf = 0;
             } else if (tid == 0) {
                 s_qn = qn + total;
+                s_qf = qf + total_fb;
             }
             __syncthreads();
         }
-        const int qn = s_qn;
+        const int qn = s_qn, qf = s_qf;
         if (qn > 0) drain<T, SAMP>(a, s_queue, qn, step, s_net, sums);
+        if constexpr (SAMP != CS_SAMPLER_PLAIN)
+            if (qf > 0) drain_fallback<T>(a, s_queue, qf, step, sums);
     }
     // per-workgroup partials, fixed order: lanes (butterfly), then waves
     const double w_p = wave_sum(sum_p), w_eb = wave_sum(sums.e_before), w_ea = wave_sum(sums.e_after);

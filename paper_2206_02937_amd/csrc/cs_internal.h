@@ -6,12 +6,14 @@
 #include <stdint.h>
 
 #include <string>
+#include <vector>
 
 #include "../../include/compton.h"
 
 namespace cs {
 
 constexpr int kChunk = 256;       // pairs per workgroup of the pair kernel
+constexpr int64_t kTimingRing = 512;  // steps whose stage events are kept
 constexpr int kScanItems = 1024;  // items per workgroup of the scan kernels
 
 // Step-to-step control block at the start of the workspace (device memory,
@@ -219,6 +221,6 @@ struct cs_ctx {
     int64_t chunks_per_block = 0;  // 0: automatic
     std::string last_error;
     bool timing = false;
-    bool timed_step_pending = false;
-    hipEvent_t events[CS_STAGE_COUNT + 1] = {};
+    int64_t timed_steps = 0;          // steps timed since enabling or the last read
+    std::vector<hipEvent_t> events;   // kTimingRing slots of CS_STAGE_COUNT + 1 events
 };

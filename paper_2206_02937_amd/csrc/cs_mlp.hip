@@ -129,22 +129,26 @@ struct FwdArgs {
 };
 
 
-// Sampler reading of the outputs (shared by every precision).
-__device__ __forceinline__ void sampler_out(const FwdArgs& a, int64_t i, float x, float u, float y0) {
-    float mu, r;
-    uint8_t fb = 0;
-    if (in_range(x)) {
-        mu = fminf(fmaxf(y0, -1.0f), 1.0f);
-        r = 1.0f / (1.0f + x * (1.0f - mu));
-    } else {
-        const double v = angle_icdf_v((double)u, (double)x);
-        mu = (float)(1.0 - v);
-        r = (float)(1.0 / (1.0 + (double)x * v));
-        fb = 1;
-    }
+// Sampler reading of the outputs (shared by every precision): inside the
+// network's domain cos(theta) = clamp(y0, -1, 1) and the energy ratio follows
+// from it by the Compton relation; outside it the plain sampler answers.
+__device__ __forceinline__ void net_out(const FwdArgs& a, int64_t i, float x, float y0) {
+    const float mu = fminf(fmaxf(y0, -1.0f), 1.0f);
     if (a.mu) a.mu[i] = mu;
-    if (a.ratio) a.ratio[i] = r;
-    if (a.mask) a.mask[i] = fb;
+    if (a.ratio) a.ratio[i] = 1.0f / (1.0f + x * (1.0f - mu));
+    if (a.mask) a.mask[i] = 0;
+}
+__device__ __forceinline__ void fallback_out(const FwdArgs& a, int64_t i, float x, float u) {
+    const double v = angle_icdf_v((double)u, (double)x);
+    if (a.mu) a.mu[i] = (float)(1.0 - v);
+    if (a.ratio) a.ratio[i] = (float)(1.0 / (1.0 + (double)x * v));
+    if (a.mask) a.mask[i] = 1;
+}
+__device__ __forceinline__ void sampler_out(const FwdArgs& a, int64_t i, float x, float u, float y0) {
+    if (in_range(x))
+        net_out(a, i, x, y0);
+    else
+        fallback_out(a, i, x, u);
 }
 
 __global__ __launch_bounds__(kMlpThreads) void k_mlp_fwd_f32(const FwdArgs a) {
@@ -453,29 +457,77 @@ __global__ void k_mlp_act_scale(float* scales) {
 
 constexpr int kMfmaThreads = 256;
 
+// Block-uniform loop over 64-sample groups (one 16-sample tile per wave).
+// Samples outside the network's domain are deferred: their indices are
+// compacted in order into s_fb and answered by the plain sampler in dense
+// passes, so that its Newton iteration never runs on a mostly idle wave.
 template <int PREC>
 __global__ __launch_bounds__(kMfmaThreads) void k_mlp_mfma(const FwdArgs a, const MlpDev m) {
     __shared__ NetLds<PREC> s_net;
+    __shared__ int s_fb[kMfmaThreads + 64];
+    __shared__ int s_wcnt[kMfmaThreads / 64];
+    __shared__ int s_fbn;
     net_load<PREC>(s_net, m);
+    if (threadIdx.x == 0) s_fbn = 0;
     __syncthreads();
+    const int tid = threadIdx.x;
     const int lane = lane_id();
-    const int wave = threadIdx.x >> 6;
-    const int64_t n_tiles = (a.n + 15) / 16;
-    for (int64_t tile = (int64_t)blockIdx.x * 4 + wave; tile < n_tiles; tile += (int64_t)gridDim.x * 4) {
-        const int64_t i = tile * 16 + (lane & 15);
+    const int wave = tid >> 6;
+    const bool sampling = a.mu || a.ratio || a.mask;
+    auto flush = [&](int n) {
+        for (int base = 0; base < n; base += kMfmaThreads) {
+            const int q = base + tid;
+            if (__any(q < n)) {
+                const bool act = q < n;
+                const int64_t i = act ? s_fb[q] : 0;
+                const float x = act ? a.x[i] : 0.0f, u = act ? a.u[i] : 0.5f;
+                const double v = angle_icdf_v((double)u, (double)x);
+                if (act) {
+                    if (a.mu) a.mu[i] = (float)(1.0 - v);
+                    if (a.ratio) a.ratio[i] = (float)(1.0 / (1.0 + (double)x * v));
+                    if (a.mask) a.mask[i] = 1;
+                }
+            }
+        }
+    };
+    const int64_t n_groups = (a.n + 63) / 64;
+    for (int64_t grp = blockIdx.x; grp < n_groups; grp += gridDim.x) {
+        const int64_t i = grp * 64 + wave * 16 + (lane & 15);
         const bool active = i < a.n;
         const float x = active ? a.x[i] : 1.0f, u = active ? a.u[i] : 0.5f;
         float f1, f2, y0, y1;
         features(x, u, f1, f2);
         mlp_tile<PREC>(s_net.frag, s_net.P, s_net.sc, f1, f2, y0, y1);
-        if (lane < 16 && active) {
-            if (a.y) {
-                a.y[2 * i] = y0;
-                a.y[2 * i + 1] = y1;
-            }
-            if (a.mu || a.ratio || a.mask) sampler_out(a, i, x, u, y0);
+        const bool mine = lane < 16 && active;
+        if (mine && a.y) {
+            a.y[2 * i] = y0;
+            a.y[2 * i + 1] = y1;
         }
+        if (!sampling) continue;  // uniform over the grid
+        const bool defer = mine && !in_range(x);
+        if (mine && !defer) net_out(a, i, x, y0);
+        const uint64_t msk = __ballot(defer);
+        if (lane == 0) s_wcnt[wave] = __popcll(msk);
+        __syncthreads();
+        int wbase = 0, total = 0;
+#pragma unroll
+        for (int w = 0; w < kMfmaThreads / 64; ++w) {
+            wbase += w < wave ? s_wcnt[w] : 0;
+            total += s_wcnt[w];
+        }
+        const int nf = s_fbn;  // < kMfmaThreads here; a group adds at most 64
+        if (defer) s_fb[nf + wbase + __popcll(msk & ((1ull << lane) - 1ull))] = (int)i;
+        __syncthreads();
+        if (nf + total >= kMfmaThreads) {
+            flush(nf + total);
+            __syncthreads();
+            if (tid == 0) s_fbn = 0;
+        } else if (tid == 0) {
+            s_fbn = nf + total;
+        }
+        __syncthreads();
     }
+    if (sampling) flush(s_fbn);
 }
 
 // ---------------------------------------------------------------------------

@@ -35,8 +35,12 @@ constexpr float kE4M3Max = 448.0f;
 
 __device__ __forceinline__ float silu_f32(float z) { return z / (1.0f + expf(-z)); }
 
-// SiLU for the reduced-precision paths (its result is rounded to BF16/FP8)
-__device__ __forceinline__ float silu_fast(float z) { return z * __frcp_rn(1.0f + __expf(-z)); }
+// SiLU for the reduced-precision paths: its result is rounded to BF16/FP8,
+// so the hardware exp2 and reciprocal approximations (about 1 ulp of FP32)
+// replace the correctly rounded division.
+__device__ __forceinline__ float silu_fast(float z) {
+    return z * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(z * -1.4426950408889634f));
+}
 
 __device__ __forceinline__ void features(float x, float u, float& f1, float& f2) {
     f1 = (log10f(x) + 1.0f) / 3.0f;
