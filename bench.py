@@ -44,6 +44,10 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-sampler comparison run")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--autotune", action="store_true", help="pick strategy / chunks per block with cs_autotune")
+    ap.add_argument("--graph", action="store_true", help="replay one captured step (HIP graph) in the timed loop")
+    ap.add_argument("--baseline", default=None, choices=["per_cell", "multi_kernel", "fused", "compact"],
+                    help="also time this strategy with the plain sampler (eager)")
     ap.add_argument("--traffic-calibration", action="store_true",
                     help="end with one plain 256 MiB device-to-device copy (scale for the HBM byte counters)")
     return ap.parse_args()
@@ -105,35 +109,54 @@ def load_network(ctx, sampler):
     return net
 
 
-def run_steps(ctx, p, sampler, net, steps, warmup, step0=0):
+def run_steps(ctx, p, sampler, net, steps, warmup, step0=0, graph=False):
     """Warm up, then time `steps` steps (wall clock between two device
     synchronisations, plus the library's per-stage HIP events recorded on the
-    launch stream during the same steps)."""
+    launch stream during the same steps).  graph=True replays one captured
+    step instead (no per-stage events then)."""
     import torch
 
     from paper_2206_02937_amd import compton
 
     e, g, oe, og = compton.to_device(p)
     stats = ctx.stats_buffer()
-    step = step0
-    for _ in range(warmup):
-        ctx.step(e, g, oe, og, p.dt, p.density_norm, p.seed, step, sampler=sampler, mlp=net, stats=stats)
-        step += 1
     torch.cuda.synchronize()
-    ctx.set_stage_timing(True)
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    ev0.record()
-    collided = 0
-    for _ in range(steps):
-        ctx.step(e, g, oe, og, p.dt, p.density_norm, p.seed, step, sampler=sampler, mlp=net, stats=stats)
-        step += 1
-    ev1.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    stage_ms = ctx.stage_times()
-    ctx.set_stage_timing(False)
+    stream = torch.cuda.Stream() if graph else torch.cuda.current_stream()
+    with torch.cuda.stream(stream):
+        gr = None
+        if graph:
+            gr = ctx.graph(e, g, oe, og, p.dt, p.density_norm, p.seed, sampler=sampler, mlp=net, stats=stats)
+            gr.set_step(step0)
+        step = step0
+
+        def one():
+            nonlocal step
+            if gr is not None:
+                gr.launch()
+            else:
+                ctx.step(e, g, oe, og, p.dt, p.density_norm, p.seed, step, sampler=sampler, mlp=net, stats=stats)
+            step += 1
+
+        for _ in range(warmup):
+            one()
+        torch.cuda.synchronize()
+        if gr is None:
+            ctx.set_stage_timing(True)
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        ev0.record(stream)
+        for _ in range(steps):
+            one()
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        stage_ms = None
+        if gr is None:
+            stage_ms = ctx.stage_times()
+            ctx.set_stage_timing(False)
+        else:
+            gr.close()
     st = compton.decode_stats(stats)
     return {"pairs_per_s": p.n_pairs * steps / wall, "ms_per_step": wall * 1e3 / steps,
             "gpu_ms_per_step": ev0.elapsed_time(ev1) / steps, "stage_ms": stage_ms, "last_stats": st}
@@ -209,31 +232,49 @@ def main():
     net = load_network(ctx, args.sampler)
     if args.sweep:
         sweep(ctx, p, args, net)
+    tuned = None
+    if args.autotune:
+        e, g, oe, og = compton.to_device(p)
+        tuned = ctx.autotune(e, g, oe, og, p.dt, p.density_norm, p.seed, 0, sampler=args.sampler, mlp=net, reps=5)
+        print(json.dumps({"progress": "autotune", **tuned}), flush=True)
+        del e, g, oe, og
     print(json.dumps({"progress": "timing", "sampler": args.sampler}), flush=True)
-    main_run = run_steps(ctx, p, args.sampler, net, args.steps, args.warmup)
+    # per-stage timing (eager) for the roofline, then the measured run
+    eager = run_steps(ctx, p, args.sampler, net, args.steps, args.warmup)
+    main_run = run_steps(ctx, p, args.sampler, net, args.steps, args.warmup, graph=True) if args.graph else eager
     plain_run = None
     if args.sampler != "plain" and not args.no_plain:
         print(json.dumps({"progress": "timing", "sampler": "plain"}), flush=True)
-        plain_run = run_steps(ctx, p, "plain", None, args.steps, args.warmup)
+        plain_run = run_steps(ctx, p, "plain", None, args.steps, args.warmup, graph=args.graph)
+    base_run = None
+    if args.baseline:
+        print(json.dumps({"progress": "timing", "baseline": args.baseline}), flush=True)
+        saved = (ctx.get_option(compton.OPT_STRATEGY), ctx.get_option(compton.OPT_CHUNKS_PER_BLOCK))
+        ctx.set_strategy(args.baseline)
+        ctx.set_chunks_per_block(0)
+        base_run = run_steps(ctx, p, "plain", None, args.steps, args.warmup)
+        ctx.set_option(compton.OPT_STRATEGY, saved[0])
+        ctx.set_option(compton.OPT_CHUNKS_PER_BLOCK, saved[1])
     print(json.dumps({"progress": "sampler stage"}), flush=True)
     stage, ks = sampler_stage(ctx, p, net, args.sampler)
 
     sb = storage_bytes(p.e["x"].dtype)
     st = main_run["last_stats"]
     acc_per_step = st["n_collided"]
-    stage_ms = main_run["stage_ms"]
+    stage_ms = eager["stage_ms"]
     # algorithmic bytes of the dominant kernel (k_step, fused strategy: every
     # pair reads both particles, 8 values; every collision writes 6 values
     # back); for the other strategies the pair and collide kernels separately
-    if args.strategy == "fused":
+    strategy_used = compton.STRATEGY_NAMES[ctx.get_option(compton.OPT_STRATEGY)]
+    if strategy_used == "fused":
         kern, ms = "k_step", stage_ms["pair"]
         bytes_launch = n_pairs * 8 * sb + acc_per_step * 6 * sb
     else:
-        kern = "k_pair_compact" if args.strategy == "compact" else "k_pair"
+        kern = "k_pair_compact" if strategy_used == "compact" else "k_pair"
         ms = stage_ms["pair"]
         bytes_launch = n_pairs * 8 * sb + acc_per_step * 8
         if stage_ms["collide"] > ms:
-            kern = "k_collide_dense" if args.strategy == "compact" else "k_collide"
+            kern = "k_collide_dense" if strategy_used == "compact" else "k_collide"
             ms = stage_ms["collide"]
             bytes_launch = acc_per_step * (8 + 8 * sb + 6 * sb)
     achieved = bytes_launch / (ms * 1e-3) / 1e9
@@ -270,12 +311,19 @@ def main():
         "config": {"workload": f"{p.name}: {p.n_cells} cells, {n_pairs} pairs per step, "
                                f"{'fp32' if sb == 4 else 'fp64'} particles",
                    "cells": p.n_cells, "pairs_per_step": n_pairs, "sampler": args.sampler,
-                   "strategy": args.strategy, "chunks_per_block": args.chunks_per_block,
+                   "strategy": strategy_used,
+                   "chunks_per_block": ctx.get_option(compton.OPT_CHUNKS_PER_BLOCK),
+                   "autotuned": tuned is not None, "graph": args.graph,
                    "collisions_per_step": acc_per_step},
         "gpu_ms_per_step": main_run["gpu_ms_per_step"],
         "stage_ms": stage_ms,
+        "eager_pairs_per_s": eager["pairs_per_s"],
         "plain": None if plain_run is None else {k: plain_run[k] for k in
                                                  ("pairs_per_s", "ms_per_step", "gpu_ms_per_step", "stage_ms")},
+        "baseline": None if base_run is None else {"strategy": args.baseline, "sampler": "plain",
+                                                   "pairs_per_s": base_run["pairs_per_s"],
+                                                   "ms_per_step": base_run["ms_per_step"]},
+        "autotune": tuned,
         "mlp_vs_plain": None if plain_run is None else main_run["pairs_per_s"] / plain_run["pairs_per_s"],
         "ks": {k: {"mu": v["mu"], "r": v["r"], "fallback_frac": v["fallback_frac"]} for k, v in ks.items()},
         "sampler_stage_samples_per_s": {k: v for k, v in stage.items() if k not in ("n", "inputs")},

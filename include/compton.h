@@ -37,6 +37,13 @@
 
 #include <stdint.h>
 
+/* Exported entry points (the library is built with hidden visibility). */
+#if defined(__GNUC__)
+#define CS_API __attribute__((visibility("default")))
+#else
+#define CS_API
+#endif
+
 #ifdef __cplusplus
 extern "C" {
 #endif
@@ -98,13 +105,13 @@ typedef struct {
 /* ---------------------------------------------------------------- lifecycle */
 
 /* Create a context on HIP device `device` (its workspace grows on demand). */
-cs_status cs_create(cs_ctx** out, int device);
-cs_status cs_destroy(cs_ctx* ctx);
+CS_API cs_status cs_create(cs_ctx** out, int device);
+CS_API cs_status cs_destroy(cs_ctx* ctx);
 /* Text of the last failure on this context (never NULL; "" after success).
  * With ctx == NULL: the last failure of cs_create. */
-const char* cs_last_error(const cs_ctx* ctx);
+CS_API const char* cs_last_error(const cs_ctx* ctx);
 /* Synchronous: wait for `stream` and report any asynchronous HIP error. */
-cs_status cs_sync(cs_ctx* ctx, void* stream);
+CS_API cs_status cs_sync(cs_ctx* ctx, void* stream);
 
 /* ------------------------------------------------------------ the step ---- */
 
@@ -143,13 +150,13 @@ cs_status cs_sync(cs_ctx* ctx, void* stream);
  *          CS_ERR_UNSUPPORTED (a species count >= 2^31),
  *          CS_ERR_NOT_READY (MLP sampler without prepared weights).
  */
-cs_status cs_compton_step(cs_ctx* ctx, cs_dtype dtype, cs_species electrons, cs_species photons,
+CS_API cs_status cs_compton_step(cs_ctx* ctx, cs_dtype dtype, cs_species electrons, cs_species photons,
                           const int64_t* off_e, const int64_t* off_g, int64_t n_cells, double dt,
                           double density_norm, uint64_t seed, uint64_t step, cs_sampler sampler,
                           const cs_mlp* mlp, cs_stats* stats, void* stream);
 
 /* Synchronous layout check of device offsets: CS_OK or CS_ERR_LAYOUT. */
-cs_status cs_check_layout(cs_ctx* ctx, const int64_t* off, int64_t n_cells, int64_t n_particles,
+CS_API cs_status cs_check_layout(cs_ctx* ctx, const int64_t* off, int64_t n_cells, int64_t n_particles,
                           void* stream);
 
 /*
@@ -159,7 +166,7 @@ cs_status cs_check_layout(cs_ctx* ctx, const int64_t* off, int64_t n_cells, int6
  * Arrays of n elements of `dtype` (FP64 arithmetic either way); x >= 0,
  * u in [0, 1).  Used for training targets and the sampler-stage benchmark.
  */
-cs_status cs_sample_plain(cs_ctx* ctx, cs_dtype dtype, const void* x, const void* u, int64_t n,
+CS_API cs_status cs_sample_plain(cs_ctx* ctx, cs_dtype dtype, const void* x, const void* u, int64_t n,
                           void* mu_out, void* ratio_out, void* stream);
 
 /* ------------------------------------------------- the learned sampler --- */
@@ -186,52 +193,52 @@ cs_status cs_sample_plain(cs_ctx* ctx, cs_dtype dtype, const void* x, const void
 #define CS_MLP_X_MIN 1e-4
 #define CS_MLP_X_MAX 1e2
 
-cs_status cs_mlp_create(cs_ctx* ctx, const int32_t* widths, int32_t n_widths, const float* init_params_host,
+CS_API cs_status cs_mlp_create(cs_ctx* ctx, const int32_t* widths, int32_t n_widths, const float* init_params_host,
                         cs_mlp** out); /* init_params_host: n_params floats, or NULL for zeros */
-cs_status cs_mlp_destroy(cs_mlp* mlp);
-int64_t cs_mlp_num_params(const cs_mlp* mlp); /* -1 for NULL */
+CS_API cs_status cs_mlp_destroy(cs_mlp* mlp);
+CS_API int64_t cs_mlp_num_params(const cs_mlp* mlp); /* -1 for NULL */
 /* Synchronous host copies of the FP32 master parameters.  Setting them
  * invalidates the BF16 / FP8 copies and keeps the Adam state. */
-cs_status cs_mlp_set_params(cs_mlp* mlp, const float* host, int64_t n);
-cs_status cs_mlp_get_params(const cs_mlp* mlp, float* host, int64_t n);
+CS_API cs_status cs_mlp_set_params(cs_mlp* mlp, const float* host, int64_t n);
+CS_API cs_status cs_mlp_get_params(const cs_mlp* mlp, float* host, int64_t n);
 /* Save / load (synchronous): a versioned binary file with the widths, the
  * FP32 parameters, the Adam moments and step count, and a checksum.
  * CS_ERR_IO on a missing, truncated or corrupt file. */
-cs_status cs_mlp_save(const cs_mlp* mlp, const char* path);
-cs_status cs_mlp_load(cs_ctx* ctx, const char* path, cs_mlp** out);
+CS_API cs_status cs_mlp_save(const cs_mlp* mlp, const char* path);
+CS_API cs_status cs_mlp_load(cs_ctx* ctx, const char* path, cs_mlp** out);
 
 /* Prepare the reduced-precision copy used by `precision` (MLP_BF16: weights
  * rounded to BF16; MLP_FP8: weights and layer inputs scaled per layer by
  * amax/448 and rounded to OCP FP8 E4M3, the input scales calibrated on the n
  * device samples (calib_x, calib_u), which must lie in the trained range).
  * MLP_F32 needs no preparation.  Queues work on `stream`. */
-cs_status cs_mlp_quantize(cs_ctx* ctx, cs_mlp* mlp, cs_sampler precision, const float* calib_x,
+CS_API cs_status cs_mlp_quantize(cs_ctx* ctx, cs_mlp* mlp, cs_sampler precision, const float* calib_x,
                           const float* calib_u, int64_t n, void* stream);
 
 /* Raw network outputs y[2 i], y[2 i + 1] = (mu_hat, r_hat) for n device
  * inputs, in `precision` (F32 on the VALU; BF16 / FP8 on MFMA with FP32
  * accumulation; first and last layers FP32).  No range check. */
-cs_status cs_mlp_forward(cs_ctx* ctx, const cs_mlp* mlp, cs_sampler precision, const float* x, const float* u,
+CS_API cs_status cs_mlp_forward(cs_ctx* ctx, const cs_mlp* mlp, cs_sampler precision, const float* x, const float* u,
                          int64_t n, float* y_out, void* stream);
 
 /* Sampler: mu_out[i] = clamp(mu_hat, -1, 1), ratio_out[i] = 1/(1 + x(1 - mu));
  * where x is outside [CS_MLP_X_MIN, CS_MLP_X_MAX] the plain sampler answers
  * and fallback_mask[i] = 1 (nullable mask, else 0). */
-cs_status cs_mlp_sample(cs_ctx* ctx, const cs_mlp* mlp, cs_sampler precision, const float* x, const float* u,
+CS_API cs_status cs_mlp_sample(cs_ctx* ctx, const cs_mlp* mlp, cs_sampler precision, const float* x, const float* u,
                         int64_t n, float* mu_out, float* ratio_out, uint8_t* fallback_mask, void* stream);
 
 /* Gradient of the loss (MSE: 1/(2n) sum (y - t)^2; MAE: 1/(2n) sum |y - t|)
  * over the n device samples with targets (mu_t, r_t), FP32, reduced over the
  * batch in a fixed order (bitwise reproducible).  grad_out: device,
  * n_params floats; loss_out: nullable device float. */
-cs_status cs_mlp_grad(cs_ctx* ctx, const cs_mlp* mlp, const float* x, const float* u, const float* mu_t,
+CS_API cs_status cs_mlp_grad(cs_ctx* ctx, const cs_mlp* mlp, const float* x, const float* u, const float* mu_t,
                       const float* r_t, int64_t n, cs_loss loss, float* grad_out, float* loss_out, void* stream);
 /* One Adam update (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) with
  * the given device gradient. */
-cs_status cs_mlp_adam_step(cs_ctx* ctx, cs_mlp* mlp, const float* grad, float lr, void* stream);
+CS_API cs_status cs_mlp_adam_step(cs_ctx* ctx, cs_mlp* mlp, const float* grad, float lr, void* stream);
 /* cs_mlp_grad followed by cs_mlp_adam_step (the paper's learning rate is
  * 1e-3).  Invalidates the BF16 / FP8 copies. */
-cs_status cs_mlp_train_step(cs_ctx* ctx, cs_mlp* mlp, const float* x, const float* u, const float* mu_t,
+CS_API cs_status cs_mlp_train_step(cs_ctx* ctx, cs_mlp* mlp, const float* x, const float* u, const float* mu_t,
                             const float* r_t, int64_t n, float lr, cs_loss loss, float* loss_out, void* stream);
 
 /* --------------------------------------------------------- options ------ */
@@ -241,8 +248,10 @@ typedef enum {
     CS_STRATEGY_FUSED = 0,        /* scan + persistent step kernel with an LDS queue of    */
                                   /* accepted pairs drained in place (default)             */
     CS_STRATEGY_MULTI_KERNEL = 1, /* one kernel per stage (baseline)                       */
-    CS_STRATEGY_COMPACT = 2       /* scan + pair kernel compacting accepted pairs by       */
+    CS_STRATEGY_COMPACT = 2,      /* scan + pair kernel compacting accepted pairs by       */
                                   /* decoupled look-back + dense collide kernel            */
+    CS_STRATEGY_PER_CELL = 3      /* one workgroup per cell, collisions resolved in place  */
+                                  /* without compaction (baseline; plain sampler only)     */
 } cs_strategy;
 
 typedef enum {
@@ -252,8 +261,58 @@ typedef enum {
 
 /* Set / read a context option.  CS_ERR_INVALID_ARG for unknown options or
  * out-of-range values (chunks per block in [0, 4096]). */
-cs_status cs_set_option(cs_ctx* ctx, cs_option opt, int64_t value);
-cs_status cs_get_option(const cs_ctx* ctx, cs_option opt, int64_t* value);
+CS_API cs_status cs_set_option(cs_ctx* ctx, cs_option opt, int64_t value);
+CS_API cs_status cs_get_option(const cs_ctx* ctx, cs_option opt, int64_t* value);
+
+/* ---------------------------------------------------------- autotune ---- */
+
+#define CS_TUNE_MAX 16
+
+typedef struct {
+    int32_t n;                               /* candidates timed                   */
+    int32_t best;                            /* index of the fastest               */
+    int32_t strategy[CS_TUNE_MAX];           /* cs_strategy of candidate i         */
+    int32_t chunks_per_block[CS_TUNE_MAX];   /* fused: chunks per workgroup        */
+    float ms[CS_TUNE_MAX];                   /* median step time, milliseconds     */
+} cs_tune_result;
+
+/* Pick the kernel strategy and the fused kernel's chunks per workgroup for
+ * this problem (the batching of the Sec. 3.1 step over uneven cells): every
+ * candidate (fused with 1..32 chunks per workgroup, compact) runs `reps` timed
+ * steps on a private device copy of the particles, its result after one step
+ * from the same state is checked to be bitwise identical to the first
+ * candidate's (CS_ERR_HIP if not, which would be a library defect), and the
+ * fastest is stored in the context (CS_OPT_STRATEGY, CS_OPT_CHUNKS_PER_BLOCK).
+ * The caller's particles are not modified.  Arguments as cs_compton_step
+ * (stats are not written); reps in [1, 100].  Synchronous; allocates and
+ * frees the private copy.  `out` may be NULL. */
+CS_API cs_status cs_autotune(cs_ctx* ctx, cs_dtype dtype, cs_species electrons, cs_species photons,
+                      const int64_t* cell_off_e, const int64_t* cell_off_g, int64_t n_cells, double dt,
+                      double density_norm, uint64_t seed, uint64_t step, cs_sampler sampler, const cs_mlp* mlp,
+                      int32_t reps, cs_tune_result* out, void* stream);
+
+/* ------------------------------------------------------------- graphs ---- */
+
+typedef struct cs_graph cs_graph;
+
+/* Capture one cs_compton_step with these arguments (and the context's current
+ * strategy, which must be FUSED or COMPACT) into a HIP graph.  Replays take the
+ * step index from a device counter owned by the graph: cs_graph_set_step sets
+ * it, and every replay uses it and advances it by one, so that N replays
+ * equal N cs_compton_step calls with steps s, s+1, ... .  The graph owns its
+ * workspace; the particle, offset, stats and network data must stay at the
+ * same addresses for as long as the graph is replayed.  `stream` must not be
+ * NULL (the legacy stream cannot be captured).  The counter starts at 0. */
+CS_API cs_status cs_graph_create(cs_ctx* ctx, cs_dtype dtype, cs_species electrons, cs_species photons,
+                          const int64_t* cell_off_e, const int64_t* cell_off_g, int64_t n_cells, double dt,
+                          double density_norm, uint64_t seed, cs_sampler sampler, const cs_mlp* mlp,
+                          cs_stats* stats, void* stream, cs_graph** out);
+/* Queue the step index of the next replay on `stream`. */
+CS_API cs_status cs_graph_set_step(cs_graph* graph, uint64_t step, void* stream);
+/* Queue one replay (one step) on `stream`. */
+CS_API cs_status cs_graph_launch(cs_graph* graph, void* stream);
+/* Synchronises the device, then frees the graph and its workspace. */
+CS_API cs_status cs_graph_destroy(cs_graph* graph);
 
 /* ------------------------------------------------------- measurement ---- */
 
@@ -272,13 +331,13 @@ typedef enum {
  * (the Sec. 3.3 stage breakdown of the paper, measured on the device) into a
  * ring of 512 steps; no host synchronisation happens during the steps.
  * Either call restarts the count of timed steps. */
-cs_status cs_set_stage_timing(cs_ctx* ctx, int enable);
+CS_API cs_status cs_set_stage_timing(cs_ctx* ctx, int enable);
 /* Synchronous: wait for the last timed step and write up to n stage
  * durations in milliseconds (index = cs_stage), each the mean over the steps
  * timed since timing was enabled or since the previous read (the last 512 of
  * them at most); *n_written gets the count.  CS_ERR_NOT_READY when no step
  * was timed. */
-cs_status cs_stage_times(cs_ctx* ctx, float* ms_out, int32_t n, int32_t* n_written);
+CS_API cs_status cs_stage_times(cs_ctx* ctx, float* ms_out, int32_t n, int32_t* n_written);
 
 #ifdef __cplusplus
 }

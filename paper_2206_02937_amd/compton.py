@@ -18,7 +18,9 @@ STATUS_NAMES = {0: "CS_OK", 1: "CS_ERR_INVALID_ARG", 2: "CS_ERR_LAYOUT", 3: "CS_
                 4: "CS_ERR_HIP", 5: "CS_ERR_IO", 6: "CS_ERR_NOT_READY"}
 CS_F32, CS_F64 = 0, 1
 SAMPLERS = {"plain": 0, "mlp_f32": 1, "mlp_bf16": 2, "mlp_fp8": 3}
-STRATEGIES = {"fused": 0, "multi_kernel": 1, "compact": 2}
+STRATEGIES = {"fused": 0, "multi_kernel": 1, "compact": 2, "per_cell": 3}
+STRATEGY_NAMES = {v: k for k, v in STRATEGIES.items()}
+TUNE_MAX = 16
 OPT_STRATEGY, OPT_CHUNKS_PER_BLOCK = 0, 1
 LOSSES = {"mse": 0, "mae": 1}
 
@@ -31,6 +33,11 @@ class CSError(RuntimeError):
 
 class Species(C.Structure):
     _fields_ = [("x", C.c_void_p), ("y", C.c_void_p), ("z", C.c_void_p), ("w", C.c_void_p), ("n", C.c_int64)]
+
+
+class TuneResult(C.Structure):
+    _fields_ = [("n", C.c_int32), ("best", C.c_int32), ("strategy", C.c_int32 * 16),
+                ("chunks_per_block", C.c_int32 * 16), ("ms", C.c_float * 16)]
 
 
 STAGES = ["prep", "pair", "compact", "collide", "finalize"]
@@ -77,6 +84,18 @@ def lib():
     L.cs_set_stage_timing.restype = st
     L.cs_stage_times.argtypes = [vp, C.POINTER(C.c_float), i32, C.POINTER(i32)]
     L.cs_stage_times.restype = st
+    L.cs_autotune.argtypes = [vp, C.c_int, Species, Species, vp, vp, i64, d, d, u64, u64, C.c_int, vp, i32,
+                              C.POINTER(TuneResult), vp]
+    L.cs_autotune.restype = st
+    L.cs_graph_create.argtypes = [vp, C.c_int, Species, Species, vp, vp, i64, d, d, u64, C.c_int, vp, vp, vp,
+                                  C.POINTER(vp)]
+    L.cs_graph_create.restype = st
+    L.cs_graph_set_step.argtypes = [vp, u64, vp]
+    L.cs_graph_set_step.restype = st
+    L.cs_graph_launch.argtypes = [vp, vp]
+    L.cs_graph_launch.restype = st
+    L.cs_graph_destroy.argtypes = [vp]
+    L.cs_graph_destroy.restype = st
     _bind_mlp(L)
     _lib = L
     return L
@@ -221,6 +240,26 @@ class Context:
         self._check(lib().cs_stage_times(self._h, buf, 8, C.byref(n)))
         return dict(zip(STAGES, [float(buf[i]) for i in range(n.value)]))
 
+    def autotune(self, e, g, off_e, off_g, dt, density_norm, seed, step, sampler="plain", mlp=None, reps=5,
+                 stream=None):
+        """Time the candidate strategies on a private copy of the particles and
+        keep the fastest; returns {"best": (strategy, chunks), "candidates":
+        [(strategy, chunks, ms), ...]}."""
+        res = TuneResult()
+        rc = lib().cs_autotune(self._h, _dtype_code(e["x"]), _species(e), _species(g), _ptr(off_e), _ptr(off_g),
+                               off_e.numel() - 1, float(dt), float(density_norm), int(seed), int(step),
+                               SAMPLERS[sampler], None if mlp is None else mlp.handle, int(reps), C.byref(res),
+                               _stream(stream))
+        self._check(rc)
+        cands = [(STRATEGY_NAMES[res.strategy[i]], int(res.chunks_per_block[i]), float(res.ms[i]))
+                 for i in range(res.n)]
+        return {"best": cands[res.best][:2], "candidates": cands}
+
+    def graph(self, e, g, off_e, off_g, dt, density_norm, seed, sampler="plain", mlp=None, stats=None,
+              stream=None):
+        """Capture one step into a replayable graph (see Graph)."""
+        return Graph(self, e, g, off_e, off_g, dt, density_norm, seed, sampler, mlp, stats, stream)
+
     def sample_plain(self, x, u, mu_out=None, ratio_out=None, stream=None):
         import torch
 
@@ -230,6 +269,43 @@ class Context:
                                    _ptr(ratio_out), _stream(stream))
         self._check(rc)
         return mu_out, ratio_out
+
+
+class Graph:
+    """One captured step: replays take the step index from a device counter
+    (set_step) that each replay advances.  The tensors given at capture must
+    stay alive (and in place) while the graph is used; the stream must not be
+    the legacy default stream."""
+
+    def __init__(self, ctx, e, g, off_e, off_g, dt, density_norm, seed, sampler, mlp, stats, stream):
+        import torch
+
+        self.ctx = ctx
+        self.stream = torch.cuda.current_stream() if stream is None else stream
+        self._keep = (e, g, off_e, off_g, stats, mlp)
+        self._h = C.c_void_p()
+        rc = lib().cs_graph_create(ctx.handle, _dtype_code(e["x"]), _species(e), _species(g), _ptr(off_e),
+                                   _ptr(off_g), off_e.numel() - 1, float(dt), float(density_norm), int(seed),
+                                   SAMPLERS[sampler], None if mlp is None else mlp.handle, _ptr(stats),
+                                   C.c_void_p(self.stream.cuda_stream), C.byref(self._h))
+        ctx._check(rc)
+
+    def set_step(self, step):
+        self.ctx._check(lib().cs_graph_set_step(self._h, int(step), C.c_void_p(self.stream.cuda_stream)))
+
+    def launch(self):
+        self.ctx._check(lib().cs_graph_launch(self._h, C.c_void_p(self.stream.cuda_stream)))
+
+    def close(self):
+        if self._h:
+            lib().cs_graph_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 WIDTHS = (2, 64, 64, 64, 64, 2)

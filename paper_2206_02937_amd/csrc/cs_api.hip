@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <new>
 #include <string>
 #include <vector>
@@ -36,8 +37,8 @@ cs_status hip_fail(cs_ctx* ctx, hipError_t e, const char* where) {
 // that no queued kernel still uses the old buffer, then re-initialises the
 // control block (epoch 1) and zeroes the status words (synchronous; never
 // inside a captured graph, since a captured step never grows).
-cs_status ensure_workspace(cs_ctx* ctx, size_t step_bytes, int64_t status_words, hipStream_t stream) {
-    cs::Workspace& w = ctx->ws;
+cs_status ensure_workspace(cs_ctx* ctx, cs::Workspace& w, size_t step_bytes, int64_t status_words,
+                           hipStream_t stream) {
     if (w.base && w.status_cap >= status_words && w.bytes >= cs::ws_fixed_bytes(w.status_cap) + step_bytes)
         return CS_OK;
     hipError_t e = hipStreamSynchronize(stream);
@@ -147,50 +148,63 @@ cs_status cs_sync(cs_ctx* ctx, void* stream) {
     return CS_OK;
 }
 
-cs_status cs_compton_step(cs_ctx* ctx, cs_dtype dtype, cs_species electrons, cs_species photons,
-                          const int64_t* off_e, const int64_t* off_g, int64_t n_cells, double dt,
-                          double density_norm, uint64_t seed, uint64_t step, cs_sampler sampler,
-                          const cs_mlp* mlp, cs_stats* stats, void* stream) {
-    if (!ctx) return CS_ERR_INVALID_ARG;
-    if (dtype != CS_F32 && dtype != CS_F64) return fail(ctx, CS_ERR_INVALID_ARG, "cs_compton_step: bad dtype");
+extern "C++" {
+namespace {
+
+std::string who_msg(const char* who, const char* what) { return std::string(who) + ": " + what; }
+
+cs_status validate_step(cs_ctx* ctx, cs_dtype dtype, cs_species electrons, cs_species photons, const int64_t* off_e,
+                        const int64_t* off_g, int64_t n_cells, double dt, double density_norm, cs_sampler sampler,
+                        const cs_mlp* mlp, int64_t strategy, const char* who) {
+    if (dtype != CS_F32 && dtype != CS_F64) return fail(ctx, CS_ERR_INVALID_ARG, who_msg(who, "bad dtype"));
     if (!species_ok(electrons) || !species_ok(photons))
-        return fail(ctx, CS_ERR_INVALID_ARG, "cs_compton_step: species arrays NULL or count negative");
-    if (n_cells < 0) return fail(ctx, CS_ERR_INVALID_ARG, "cs_compton_step: n_cells < 0");
-    if (!off_e || !off_g) return fail(ctx, CS_ERR_INVALID_ARG, "cs_compton_step: offsets NULL");
-    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(ctx, CS_ERR_INVALID_ARG, "cs_compton_step: dt must be > 0");
+        return fail(ctx, CS_ERR_INVALID_ARG, who_msg(who, "species arrays NULL or count negative"));
+    if (n_cells < 0) return fail(ctx, CS_ERR_INVALID_ARG, who_msg(who, "n_cells < 0"));
+    if (!off_e || !off_g) return fail(ctx, CS_ERR_INVALID_ARG, who_msg(who, "offsets NULL"));
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(ctx, CS_ERR_INVALID_ARG, who_msg(who, "dt must be > 0"));
     if (!(density_norm >= 0.0) || !std::isfinite(density_norm))
-        return fail(ctx, CS_ERR_INVALID_ARG, "cs_compton_step: density_norm must be >= 0");
+        return fail(ctx, CS_ERR_INVALID_ARG, who_msg(who, "density_norm must be >= 0"));
     if (n_cells == 0 && (electrons.n != 0 || photons.n != 0))
-        return fail(ctx, CS_ERR_INVALID_ARG, "cs_compton_step: particles given but n_cells == 0");
+        return fail(ctx, CS_ERR_INVALID_ARG, who_msg(who, "particles given but n_cells == 0"));
     if (electrons.n >= (int64_t)1 << 31 || photons.n >= (int64_t)1 << 31)
-        return fail(ctx, CS_ERR_UNSUPPORTED, "cs_compton_step: a species count >= 2^31");
-    if (n_cells >= (int64_t)1 << 31) return fail(ctx, CS_ERR_UNSUPPORTED, "cs_compton_step: n_cells >= 2^31");
+        return fail(ctx, CS_ERR_UNSUPPORTED, who_msg(who, "a species count >= 2^31"));
+    if (n_cells >= (int64_t)1 << 31) return fail(ctx, CS_ERR_UNSUPPORTED, who_msg(who, "n_cells >= 2^31"));
     if (sampler == CS_SAMPLER_PLAIN) {
-        if (mlp) return fail(ctx, CS_ERR_INVALID_ARG, "cs_compton_step: PLAIN sampler takes mlp == NULL");
+        if (mlp) return fail(ctx, CS_ERR_INVALID_ARG, who_msg(who, "PLAIN sampler takes mlp == NULL"));
     } else if (sampler == CS_SAMPLER_MLP_F32 || sampler == CS_SAMPLER_MLP_BF16 || sampler == CS_SAMPLER_MLP_FP8) {
-        if (!mlp) return fail(ctx, CS_ERR_NOT_READY, "cs_compton_step: network sampler without a network");
+        if (!mlp) return fail(ctx, CS_ERR_NOT_READY, who_msg(who, "network sampler without a network"));
         if (mlp->device != ctx->device)
-            return fail(ctx, CS_ERR_INVALID_ARG, "cs_compton_step: network lives on another device");
+            return fail(ctx, CS_ERR_INVALID_ARG, who_msg(who, "network lives on another device"));
         if ((sampler == CS_SAMPLER_MLP_BF16 && !mlp->bf16_ready) || (sampler == CS_SAMPLER_MLP_FP8 && !mlp->fp8_ready))
-            return fail(ctx, CS_ERR_NOT_READY, "cs_compton_step: network not prepared for this precision");
-        if (ctx->strategy == CS_STRATEGY_MULTI_KERNEL)
-            return fail(ctx, CS_ERR_UNSUPPORTED,
-                        "cs_compton_step: the multi-kernel strategy runs the plain sampler only");
+            return fail(ctx, CS_ERR_NOT_READY, who_msg(who, "network not prepared for this precision"));
+        if (strategy == CS_STRATEGY_MULTI_KERNEL || strategy == CS_STRATEGY_PER_CELL)
+            return fail(ctx, CS_ERR_UNSUPPORTED, who_msg(who, "the baseline strategies run the plain sampler only"));
     } else {
-        return fail(ctx, CS_ERR_INVALID_ARG, "cs_compton_step: bad sampler");
+        return fail(ctx, CS_ERR_INVALID_ARG, who_msg(who, "bad sampler"));
     }
-    DeviceGuard g(ctx->device);
-    if (!g.ok) return fail(ctx, CS_ERR_HIP, "cs_compton_step: cannot select device");
-    hipStream_t st = (hipStream_t)stream;
-    cs::StepShape sh;
+    return CS_OK;
+}
+
+struct Plan {
+    int64_t strategy = CS_STRATEGY_FUSED;
+    cs::StepShape sh = {};
+    size_t bytes = 0;
+    int64_t status_words = 0;
+};
+
+Plan plan_step(int64_t strategy, int64_t chunks_per_block, int64_t n_cells, int64_t ne, int64_t ng,
+               cs_sampler sampler) {
+    Plan pl;
+    pl.strategy = strategy;
+    cs::StepShape& sh = pl.sh;
     sh.n_cells = n_cells;
-    sh.ne = electrons.n;
-    sh.ng = photons.n;
-    const int64_t nmin = electrons.n < photons.n ? electrons.n : photons.n;
+    sh.ne = ne;
+    sh.ng = ng;
+    const int64_t nmin = ne < ng ? ne : ng;
     sh.n_chunks = (nmin + cs::kChunk - 1) / cs::kChunk;
     sh.n_collide_blocks = sh.n_chunks < 1024 ? (sh.n_chunks > 0 ? sh.n_chunks : 1) : 1024;
     sh.scan_tmp_len = cs::step_scan_tmp_len(n_cells, sh.n_chunks);
-    int64_t G = ctx->chunks_per_block;
+    int64_t G = chunks_per_block;
     if (G <= 0) {
         // automatic: about 512 workgroups (2 per compute unit at the fused
         // kernel's occupancy), at most 16 chunks each
@@ -208,20 +222,41 @@ cs_status cs_compton_step(cs_ctx* ctx, cs_dtype dtype, cs_species electrons, cs_
     const int64_t dense_cap = sampler == CS_SAMPLER_PLAIN ? 2048 : 512;
     int64_t nd = (nmin + dense_threads - 1) / dense_threads;
     sh.n_dense_blocks = nd < 1 ? 1 : (nd > dense_cap ? dense_cap : nd);
-    const int64_t strategy = ctx->strategy;
-    size_t bytes;
-    int64_t status_words = sh.n_prep_blocks;
+    pl.status_words = sh.n_prep_blocks;
     if (strategy == CS_STRATEGY_FUSED) {
-        bytes = cs::fused_workspace_bytes(sh);
+        pl.bytes = cs::fused_workspace_bytes(sh);
+    } else if (strategy == CS_STRATEGY_PER_CELL) {
+        sh.n_step_blocks = n_cells > 0 ? n_cells : 1;
+        pl.bytes = cs::fused_workspace_bytes(sh);
     } else if (strategy == CS_STRATEGY_COMPACT) {
         sh.n_collide_blocks = sh.n_dense_blocks;
-        bytes = cs::compact_workspace_bytes(sh);
-        status_words += sh.n_chunks;
+        pl.bytes = cs::compact_workspace_bytes(sh);
+        pl.status_words += sh.n_chunks;
     } else {
-        bytes = cs::step_workspace_bytes(sh);
+        pl.bytes = cs::step_workspace_bytes(sh);
     }
-    cs_status s = ensure_workspace(ctx, bytes, status_words, st);
-    if (s != CS_OK) return s;
+    return pl;
+}
+
+hipError_t launch_plan(const Plan& pl, const cs::Workspace& ws, const cs::StepParams& p, hipStream_t st) {
+    if (pl.strategy == CS_STRATEGY_FUSED || pl.strategy == CS_STRATEGY_PER_CELL) {
+        cs::FusedBuffers fb;
+        cs::carve_fused_buffers(ws, pl.sh, &fb);
+        return pl.strategy == CS_STRATEGY_FUSED ? cs::launch_fused(pl.sh, fb, p, st) : cs::launch_cell(pl.sh, fb, p, st);
+    }
+    if (pl.strategy == CS_STRATEGY_COMPACT) {
+        cs::CompactBuffers cb;
+        cs::carve_compact_buffers(ws, pl.sh, &cb);
+        return cs::launch_compact(pl.sh, cb, p, st);
+    }
+    cs::StepBuffers b;
+    cs::carve_step_buffers(cs::ws_step_area(ws), pl.sh, &b);
+    return cs::launch_step(pl.sh, b, p, st);
+}
+
+cs::StepParams make_params(cs_dtype dtype, cs_species electrons, cs_species photons, const int64_t* off_e,
+                           const int64_t* off_g, double dt, double density_norm, uint64_t seed, uint64_t step,
+                           cs_sampler sampler, const cs_mlp* mlp, cs_stats* stats) {
     cs::StepParams p;
     p.dtype = dtype;
     p.e = electrons;
@@ -236,27 +271,281 @@ cs_status cs_compton_step(cs_ctx* ctx, cs_dtype dtype, cs_species electrons, cs_
     p.net = mlp ? mlp->dev() : cs::MlpDev{nullptr, nullptr, nullptr, nullptr};
     p.stats = stats;
     p.events = nullptr;
+    p.use_device_step = 0;
+    return p;
+}
+
+}  // namespace
+}  // extern "C++"
+
+cs_status cs_compton_step(cs_ctx* ctx, cs_dtype dtype, cs_species electrons, cs_species photons,
+                          const int64_t* off_e, const int64_t* off_g, int64_t n_cells, double dt,
+                          double density_norm, uint64_t seed, uint64_t step, cs_sampler sampler,
+                          const cs_mlp* mlp, cs_stats* stats, void* stream) {
+    if (!ctx) return CS_ERR_INVALID_ARG;
+    cs_status s = validate_step(ctx, dtype, electrons, photons, off_e, off_g, n_cells, dt, density_norm, sampler, mlp,
+                                ctx->strategy, "cs_compton_step");
+    if (s != CS_OK) return s;
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(ctx, CS_ERR_HIP, "cs_compton_step: cannot select device");
+    hipStream_t st = (hipStream_t)stream;
+    const Plan pl = plan_step(ctx->strategy, ctx->chunks_per_block, n_cells, electrons.n, photons.n, sampler);
+    s = ensure_workspace(ctx, ctx->ws, pl.bytes, pl.status_words, st);
+    if (s != CS_OK) return s;
+    cs::StepParams p = make_params(dtype, electrons, photons, off_e, off_g, dt, density_norm, seed, step, sampler, mlp,
+                                   stats);
     if (ctx->timing) {
         const int64_t slot = ctx->timed_steps % cs::kTimingRing;
         p.events = ctx->events.data() + slot * (CS_STAGE_COUNT + 1);
     }
-    p.use_device_step = 0;
-    hipError_t e;
-    if (strategy == CS_STRATEGY_FUSED) {
-        cs::FusedBuffers fb;
-        cs::carve_fused_buffers(ctx->ws, sh, &fb);
-        e = cs::launch_fused(sh, fb, p, st);
-    } else if (strategy == CS_STRATEGY_COMPACT) {
-        cs::CompactBuffers cb;
-        cs::carve_compact_buffers(ctx->ws, sh, &cb);
-        e = cs::launch_compact(sh, cb, p, st);
-    } else {
-        cs::StepBuffers b;
-        cs::carve_step_buffers(cs::ws_step_area(ctx->ws), sh, &b);
-        e = cs::launch_step(sh, b, p, st);
-    }
+    const hipError_t e = launch_plan(pl, ctx->ws, p, st);
     if (e != hipSuccess) return hip_fail(ctx, e, "cs_compton_step: launch");
     if (ctx->timing) ctx->timed_steps += 1;
+    ctx->last_error.clear();
+    return CS_OK;
+}
+
+// ------------------------------------------------------------ graphs
+
+struct cs_graph {
+    cs_ctx* ctx = nullptr;
+    int device = 0;
+    cs::Workspace ws;  // the graph's own workspace (control block, step counter)
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+extern "C++" {
+namespace {
+
+__global__ void k_set_step(cs::StepControl* ctrl, uint64_t step) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) ctrl->step = step;
+}
+
+// Bitwise comparison of two buffers (32-bit words): number of differing words.
+__global__ void k_count_diff(const uint32_t* a, const uint32_t* b, int64_t n, unsigned long long* count) {
+    unsigned long long d = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        d += a[i] != b[i] ? 1ull : 0ull;
+    if (d) atomicAdd(count, d);
+}
+
+void free_graph(cs_graph* g) {
+    if (!g) return;
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    if (g->ws.base) (void)hipFree(g->ws.base);
+    delete g;
+}
+
+}  // namespace
+}  // extern "C++"
+
+cs_status cs_graph_create(cs_ctx* ctx, cs_dtype dtype, cs_species electrons, cs_species photons,
+                          const int64_t* off_e, const int64_t* off_g, int64_t n_cells, double dt,
+                          double density_norm, uint64_t seed, cs_sampler sampler, const cs_mlp* mlp,
+                          cs_stats* stats, void* stream, cs_graph** out) {
+    if (!ctx) return CS_ERR_INVALID_ARG;
+    if (!out) return fail(ctx, CS_ERR_INVALID_ARG, "cs_graph_create: out is NULL");
+    *out = nullptr;
+    if (!stream) return fail(ctx, CS_ERR_INVALID_ARG, "cs_graph_create: the legacy (NULL) stream cannot be captured");
+    if (ctx->strategy != CS_STRATEGY_FUSED && ctx->strategy != CS_STRATEGY_COMPACT)
+        return fail(ctx, CS_ERR_UNSUPPORTED, "cs_graph_create: graphs capture the fused or compact strategy");
+    cs_status s = validate_step(ctx, dtype, electrons, photons, off_e, off_g, n_cells, dt, density_norm, sampler, mlp,
+                                ctx->strategy, "cs_graph_create");
+    if (s != CS_OK) return s;
+    DeviceGuard dg(ctx->device);
+    hipStream_t st = (hipStream_t)stream;
+    cs_graph* g = new (std::nothrow) cs_graph();
+    if (!g) return fail(ctx, CS_ERR_INVALID_ARG, "cs_graph_create: out of host memory");
+    g->ctx = ctx;
+    g->device = ctx->device;
+    const Plan pl = plan_step(ctx->strategy, ctx->chunks_per_block, n_cells, electrons.n, photons.n, sampler);
+    s = ensure_workspace(ctx, g->ws, pl.bytes, pl.status_words, st);
+    if (s != CS_OK) {
+        free_graph(g);
+        return s;
+    }
+    cs::StepParams p = make_params(dtype, electrons, photons, off_e, off_g, dt, density_norm, seed, 0, sampler, mlp,
+                                   stats);
+    p.use_device_step = 1;
+    hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        free_graph(g);
+        return hip_fail(ctx, e, "cs_graph_create: hipStreamBeginCapture");
+    }
+    const hipError_t le = launch_plan(pl, g->ws, p, st);
+    e = hipStreamEndCapture(st, &g->graph);
+    if (le != hipSuccess || e != hipSuccess) {
+        free_graph(g);
+        return hip_fail(ctx, le != hipSuccess ? le : e, "cs_graph_create: capture");
+    }
+    e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        free_graph(g);
+        return hip_fail(ctx, e, "cs_graph_create: hipGraphInstantiate");
+    }
+    *out = g;
+    ctx->last_error.clear();
+    return CS_OK;
+}
+
+cs_status cs_graph_set_step(cs_graph* g, uint64_t step, void* stream) {
+    if (!g) return CS_ERR_INVALID_ARG;
+    DeviceGuard dg(g->device);
+    k_set_step<<<1, 64, 0, (hipStream_t)stream>>>(cs::ws_control(g->ws), step);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? CS_OK : hip_fail(g->ctx, e, "cs_graph_set_step");
+}
+
+cs_status cs_graph_launch(cs_graph* g, void* stream) {
+    if (!g) return CS_ERR_INVALID_ARG;
+    DeviceGuard dg(g->device);
+    const hipError_t e = hipGraphLaunch(g->exec, (hipStream_t)stream);
+    return e == hipSuccess ? CS_OK : hip_fail(g->ctx, e, "cs_graph_launch");
+}
+
+cs_status cs_graph_destroy(cs_graph* g) {
+    if (!g) return CS_ERR_INVALID_ARG;
+    DeviceGuard dg(g->device);
+    (void)hipDeviceSynchronize();
+    free_graph(g);
+    return CS_OK;
+}
+
+// ---------------------------------------------------------- autotune
+
+cs_status cs_autotune(cs_ctx* ctx, cs_dtype dtype, cs_species electrons, cs_species photons, const int64_t* off_e,
+                      const int64_t* off_g, int64_t n_cells, double dt, double density_norm, uint64_t seed,
+                      uint64_t step, cs_sampler sampler, const cs_mlp* mlp, int32_t reps, cs_tune_result* out,
+                      void* stream) {
+    if (!ctx) return CS_ERR_INVALID_ARG;
+    if (reps < 1 || reps > 100) return fail(ctx, CS_ERR_INVALID_ARG, "cs_autotune: reps must be in [1, 100]");
+    cs_status s = validate_step(ctx, dtype, electrons, photons, off_e, off_g, n_cells, dt, density_norm, sampler, mlp,
+                                CS_STRATEGY_FUSED, "cs_autotune");
+    if (s != CS_OK) return s;
+    DeviceGuard dg(ctx->device);
+    hipStream_t st = (hipStream_t)stream;
+    const size_t sb = dtype == CS_F64 ? 8 : 4;
+    const size_t be = sb * (size_t)electrons.n, bg = sb * (size_t)photons.n;
+    const size_t bytes_state = 4 * (be + bg);
+    // private state, a reference result, a stats block and a diff counter
+    char* buf = nullptr;
+    const size_t al = 256;
+    const size_t state_al = (bytes_state + al - 1) / al * al;
+    hipError_t e = hipMalloc(&buf, 2 * state_al + 2 * al);
+    if (e != hipSuccess) return hip_fail(ctx, e, "cs_autotune: hipMalloc");
+    char* state = buf;
+    char* ref = buf + state_al;
+    cs_stats* st_dev = (cs_stats*)(buf + 2 * state_al);
+    unsigned long long* diff = (unsigned long long*)(buf + 2 * state_al + al);
+    const void* src[8] = {electrons.x, electrons.y, electrons.z, electrons.w, photons.x, photons.y, photons.z, photons.w};
+    const size_t len[8] = {be, be, be, be, bg, bg, bg, bg};
+    cs_species pe = {}, pg = {};
+    {
+        size_t o = 0;
+        void** dst[8] = {&pe.x, &pe.y, &pe.z, &pe.w, &pg.x, &pg.y, &pg.z, &pg.w};
+        for (int i = 0; i < 8; ++i) {
+            *dst[i] = state + o;
+            o += len[i];
+        }
+        pe.n = electrons.n;
+        pg.n = photons.n;
+    }
+    auto restore = [&]() -> hipError_t {
+        size_t o = 0;
+        for (int i = 0; i < 8; ++i) {
+            if (len[i]) {
+                const hipError_t r = hipMemcpyAsync(state + o, src[i], len[i], hipMemcpyDeviceToDevice, st);
+                if (r != hipSuccess) return r;
+            }
+            o += len[i];
+        }
+        return hipSuccess;
+    };
+    int32_t cand_s[CS_TUNE_MAX], cand_g[CS_TUNE_MAX];
+    int n_cand = 0;
+    for (int gpb : {1, 2, 4, 8, 16, 32}) {
+        cand_s[n_cand] = CS_STRATEGY_FUSED;
+        cand_g[n_cand++] = gpb;
+    }
+    cand_s[n_cand] = CS_STRATEGY_COMPACT;
+    cand_g[n_cand++] = 0;
+    float ms_best = 0.f;
+    int best = -1;
+    float ms_all[CS_TUNE_MAX] = {};
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    e = hipEventCreate(&ev0);
+    if (e == hipSuccess) e = hipEventCreate(&ev1);
+    const int64_t saved_s = ctx->strategy, saved_g = ctx->chunks_per_block;
+    cs_status rs = CS_OK;
+    for (int c = 0; c < n_cand && e == hipSuccess && rs == CS_OK; ++c) {
+        const Plan pl = plan_step(cand_s[c], cand_g[c], n_cells, electrons.n, photons.n, sampler);
+        rs = ensure_workspace(ctx, ctx->ws, pl.bytes, pl.status_words, st);
+        if (rs != CS_OK) break;
+        const cs::StepParams p = make_params(dtype, pe, pg, off_e, off_g, dt, density_norm, seed, step, sampler, mlp,
+                                             st_dev);
+        // correctness: one step from the caller's state, compared bitwise
+        e = restore();
+        if (e == hipSuccess) e = launch_plan(pl, ctx->ws, p, st);
+        if (e != hipSuccess) break;
+        if (c == 0) {
+            e = hipMemcpyAsync(ref, state, bytes_state, hipMemcpyDeviceToDevice, st);
+        } else {
+            e = hipMemsetAsync(diff, 0, sizeof(unsigned long long), st);
+            if (e == hipSuccess && bytes_state >= 4) {
+                k_count_diff<<<1024, 256, 0, st>>>((const uint32_t*)state, (const uint32_t*)ref,
+                                                   (int64_t)(bytes_state / 4), diff);
+                e = hipGetLastError();
+            }
+            unsigned long long nd = 0;
+            if (e == hipSuccess) e = hipMemcpyAsync(&nd, diff, sizeof(nd), hipMemcpyDeviceToHost, st);
+            if (e == hipSuccess) e = hipStreamSynchronize(st);
+            if (e == hipSuccess && nd != 0) {
+                rs = fail(ctx, CS_ERR_HIP, "cs_autotune: strategies disagree (library defect)");
+                break;
+            }
+        }
+        if (e != hipSuccess) break;
+        // timing: each rep from the caller's state
+        float t[100];
+        for (int r = 0; r < reps && e == hipSuccess; ++r) {
+            e = restore();
+            if (e == hipSuccess) e = hipEventRecord(ev0, st);
+            if (e == hipSuccess) e = launch_plan(pl, ctx->ws, p, st);
+            if (e == hipSuccess) e = hipEventRecord(ev1, st);
+            if (e == hipSuccess) e = hipEventSynchronize(ev1);
+            if (e == hipSuccess) e = hipEventElapsedTime(&t[r], ev0, ev1);
+        }
+        if (e != hipSuccess) break;
+        std::sort(t, t + reps);
+        ms_all[c] = t[reps / 2];
+        if (best < 0 || ms_all[c] < ms_best) {
+            best = c;
+            ms_best = ms_all[c];
+        }
+    }
+    if (ev0) (void)hipEventDestroy(ev0);
+    if (ev1) (void)hipEventDestroy(ev1);
+    (void)hipStreamSynchronize(st);
+    (void)hipFree(buf);
+    if (rs != CS_OK || e != hipSuccess) {
+        ctx->strategy = saved_s;
+        ctx->chunks_per_block = saved_g;
+        return rs != CS_OK ? rs : hip_fail(ctx, e, "cs_autotune");
+    }
+    ctx->strategy = cand_s[best];
+    ctx->chunks_per_block = cand_g[best];
+    if (out) {
+        *out = cs_tune_result{};
+        out->n = n_cand;
+        out->best = best;
+        for (int c = 0; c < n_cand; ++c) {
+            out->strategy[c] = cand_s[c];
+            out->chunks_per_block[c] = cand_g[c];
+            out->ms[c] = ms_all[c];
+        }
+    }
     ctx->last_error.clear();
     return CS_OK;
 }
@@ -265,7 +554,8 @@ cs_status cs_set_option(cs_ctx* ctx, cs_option opt, int64_t value) {
     if (!ctx) return CS_ERR_INVALID_ARG;
     switch (opt) {
         case CS_OPT_STRATEGY:
-            if (value != CS_STRATEGY_FUSED && value != CS_STRATEGY_MULTI_KERNEL && value != CS_STRATEGY_COMPACT)
+            if (value != CS_STRATEGY_FUSED && value != CS_STRATEGY_MULTI_KERNEL && value != CS_STRATEGY_COMPACT &&
+                value != CS_STRATEGY_PER_CELL)
                 return fail(ctx, CS_ERR_INVALID_ARG, "cs_set_option: unknown strategy");
             ctx->strategy = value;
             break;
@@ -299,7 +589,7 @@ cs_status cs_check_layout(cs_ctx* ctx, const int64_t* off, int64_t n_cells, int6
     if (!off || n_cells < 0 || n_particles < 0) return fail(ctx, CS_ERR_INVALID_ARG, "cs_check_layout: bad argument");
     DeviceGuard g(ctx->device);
     hipStream_t st = (hipStream_t)stream;
-    cs_status s = ensure_workspace(ctx, 256, 0, st);
+    cs_status s = ensure_workspace(ctx, ctx->ws, 256, 0, st);
     if (s != CS_OK) return s;
     int32_t* flag = (int32_t*)cs::ws_step_area(ctx->ws);
     hipError_t e = cs::launch_check_layout(off, n_cells, n_particles, flag, st);
@@ -371,6 +661,7 @@ cs_status cs_stage_times(cs_ctx* ctx, float* ms_out, int32_t n, int32_t* n_writt
 
 // ---------------------------------------------------------------- network
 
+extern "C++" {
 namespace {
 
 const int32_t kWidths[6] = {2, 64, 64, 64, 64, 2};
@@ -453,6 +744,7 @@ cs_status check_precision(cs_ctx* ctx, const cs_mlp* m, cs_sampler p, const char
 }
 
 }  // namespace
+}  // extern "C++"
 
 cs_status cs_mlp_create(cs_ctx* ctx, const int32_t* widths, int32_t n_widths, const float* init_params_host,
                         cs_mlp** out) {

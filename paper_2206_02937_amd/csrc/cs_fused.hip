@@ -526,4 +526,127 @@ hipError_t launch_fused(const StepShape& sh, const FusedBuffers& b, const StepPa
     return launch_fused_s<float>(sh, b, p, st);
 }
 
+// ---------------------------------------------------------------------------
+// k_cell_baseline: the straightforward mapping, one workgroup per cell
+// walking its pairs 256 at a time and resolving each accepted pair in the
+// lane that found it (no compaction, so the sampler runs on mostly idle
+// waves).  A baseline for the batched strategies; same per-pair code, so the
+// same results.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kChunk) void k_cell_baseline(const FusedArgs<T> a) {
+    __shared__ double s_red_d[3 * (kChunk / 64)];
+    __shared__ long long s_red_i[3 * (kChunk / 64)];
+    const int tid = threadIdx.x;
+    const int lane = lane_id();
+    const int wave = tid >> 6;
+    const int64_t c = blockIdx.x;
+    StepControl* ctrl = a.ctrl;
+    const uint32_t E = ctrl->epoch;
+    const uint64_t step = ctrl->step;
+    const bool layout_ok = ctrl->layout_epoch != E && ctrl->scan_fault_epoch != E;
+    double sum_p = 0.0;
+    long long n_clip = 0, n_inv = 0, n_coll = 0;
+    CollideSums sums;
+    if (layout_ok && c < a.n_cells) {
+        const int32_t np = a.pair_off[c + 1] - a.pair_off[c];
+        const int64_t e0 = a.off_e[c], e1 = a.off_e[c + 1], g0 = a.off_g[c], g1 = a.off_g[c + 1];
+        for (int32_t base = 0; base < np; base += kChunk) {
+            const int32_t i = base + tid;
+            const bool active = i < np;
+            const PairOutcome o = pair_eval<T>(a.pt, active, e0, e1, g0, g1, a.keys + 4 * c, (uint32_t)(active ? i : 0),
+                                               a.dt, a.density_norm, a.seed, step);
+            sum_p += o.P;
+            n_clip += o.clipped ? 1 : 0;
+            n_inv += o.invalid ? 1 : 0;
+            n_coll += o.accept ? 1 : 0;
+            collide_plain<T>(a.pt, o.accept, o.ie, o.ig, a.seed, step, sums);
+        }
+    }
+    const double w_p = wave_sum(sum_p), w_eb = wave_sum(sums.e_before), w_ea = wave_sum(sums.e_after);
+    const long long w_cl = wave_sum_i(n_clip), w_in = wave_sum_i(n_inv), w_co = wave_sum_i(n_coll);
+    if (lane == 0) {
+        s_red_d[3 * wave + 0] = w_p;
+        s_red_d[3 * wave + 1] = w_eb;
+        s_red_d[3 * wave + 2] = w_ea;
+        s_red_i[3 * wave + 0] = w_cl;
+        s_red_i[3 * wave + 1] = w_in;
+        s_red_i[3 * wave + 2] = w_co;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double p = 0.0, eb = 0.0, ea = 0.0;
+        long long cl = 0, in = 0, co = 0;
+        for (int w = 0; w < kChunk / 64; ++w) {
+            p += s_red_d[3 * w + 0];
+            eb += s_red_d[3 * w + 1];
+            ea += s_red_d[3 * w + 2];
+            cl += s_red_i[3 * w + 0];
+            in += s_red_i[3 * w + 1];
+            co += s_red_i[3 * w + 2];
+        }
+        const int64_t b = blockIdx.x;
+        a.part.prob[b] = p;
+        a.part.e_before[b] = eb;
+        a.part.e_after[b] = ea;
+        a.part.clipped[b] = cl;
+        a.part.invalid[b] = in;
+        a.part.collided[b] = co;
+        a.part.fallback[b] = 0;
+    }
+}
+
+template <typename T>
+static hipError_t launch_cell_t(const StepShape& sh, const FusedBuffers& b, const StepParams& p, hipStream_t st) {
+    auto mark = [&](int i) {
+        if (p.events) (void)hipEventRecord(p.events[i], st);
+    };
+    mark(0);
+    hipError_t e = launch_prep(sh, b.ctrl, b.status, b.pair_off, b.cell_keys, b.chunk_cell, p, st);
+    if (e != hipSuccess) return e;
+    mark(1);
+    FusedArgs<T> fa = {};
+    fa.pt = {(T*)p.e.x, (T*)p.e.y, (T*)p.e.z, (T*)p.e.w, (T*)p.g.x, (T*)p.g.y, (T*)p.g.z, (T*)p.g.w};
+    fa.off_e = p.off_e;
+    fa.off_g = p.off_g;
+    fa.n_cells = sh.n_cells;
+    fa.n_chunks = sh.n_chunks;
+    fa.chunks_per_block = 1;
+    fa.pair_off = b.pair_off;
+    fa.keys = b.cell_keys;
+    fa.chunk_cell = b.chunk_cell;
+    fa.dt = p.dt;
+    fa.density_norm = p.density_norm;
+    fa.seed = p.seed;
+    fa.ctrl = b.ctrl;
+    fa.part = b.part;
+    fa.stats = p.stats;
+    if (sh.n_cells > 0) k_cell_baseline<T><<<(unsigned)sh.n_cells, kChunk, 0, st>>>(fa);
+    mark(2);
+    mark(3);
+    mark(4);
+    FinalArgs f = {};
+    f.ctrl = b.ctrl;
+    f.pair_off = b.pair_off;
+    f.n_cells = sh.n_cells;
+    f.a_prob = b.part.prob;
+    f.a_clip = b.part.clipped;
+    f.a_inv = b.part.invalid;
+    f.a_coll = b.part.collided;
+    f.n_a = sh.n_cells > 0 ? sh.n_cells : 0;
+    f.b_eb = b.part.e_before;
+    f.b_ea = b.part.e_after;
+    f.b_fb = b.part.fallback;
+    f.n_b = f.n_a;
+    f.stats = p.stats;
+    e = launch_finalize(f, st);
+    mark(5);
+    return e == hipSuccess ? hipGetLastError() : e;
+}
+
+hipError_t launch_cell(const StepShape& sh, const FusedBuffers& b, const StepParams& p, hipStream_t st) {
+    if (p.dtype == CS_F64) return launch_cell_t<double>(sh, b, p, st);
+    return launch_cell_t<float>(sh, b, p, st);
+}
+
 }  // namespace cs

@@ -170,6 +170,8 @@ hipError_t launch_prep(const StepShape& sh, StepControl* ctrl, uint64_t* status,
                        int32_t* chunk_cell, const StepParams& p, hipStream_t st);
 
 hipError_t launch_fused(const StepShape& shape, const FusedBuffers& buf, const StepParams& p, hipStream_t stream);
+// one workgroup per cell (baseline); shape.n_step_blocks = n_cells partials
+hipError_t launch_cell(const StepShape& shape, const FusedBuffers& buf, const StepParams& p, hipStream_t stream);
 hipError_t launch_check_layout(const int64_t* off, int64_t n_cells, int64_t n, int32_t* flag, hipStream_t stream);
 hipError_t launch_sample_plain(cs_dtype dtype, const void* x, const void* u, int64_t n, void* mu, void* ratio,
                                hipStream_t stream);

@@ -57,3 +57,15 @@ def test_null_context_and_create_errors():
         rc = L.cs_create(C.byref(h), 0)
         assert rc == compton.CS_ERR_HIP and not h.value
         assert len(L.cs_last_error(None)) > 0
+
+
+def test_library_exports_nothing_else():
+    """Built with hidden visibility: the dynamic symbol table holds exactly the
+    declared entry points (no internal C++ symbols leak)."""
+    import subprocess
+
+    if not os.path.exists(LIB):
+        pytest.fail("libcompton.so is not built (python -m paper_2206_02937_amd.build)")
+    out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True, text=True, check=True).stdout
+    exported = sorted({ln.split()[-1] for ln in out.splitlines() if " T " in ln})
+    assert exported == declared_functions()
