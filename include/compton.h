@@ -256,11 +256,14 @@ typedef enum {
 
 typedef enum {
     CS_OPT_STRATEGY = 0,         /* a cs_strategy                                        */
-    CS_OPT_CHUNKS_PER_BLOCK = 1  /* fused: 256-pair chunks per workgroup, 0 = automatic  */
+    CS_OPT_CHUNKS_PER_BLOCK = 1, /* fused: 256-pair chunks per workgroup, 0 = automatic  */
+    CS_OPT_PAIRS_PER_LANE = 2    /* compact: pairs each lane of the pair kernel takes    */
+                                 /* (1, 2 or 4), 0 = automatic                            */
 } cs_option;
 
 /* Set / read a context option.  CS_ERR_INVALID_ARG for unknown options or
- * out-of-range values (chunks per block in [0, 4096]). */
+ * out-of-range values (chunks per block in [0, 4096]; pairs per lane 0, 1, 2
+ * or 4). */
 CS_API cs_status cs_set_option(cs_ctx* ctx, cs_option opt, int64_t value);
 CS_API cs_status cs_get_option(const cs_ctx* ctx, cs_option opt, int64_t* value);
 
@@ -273,16 +276,18 @@ typedef struct {
     int32_t best;                            /* index of the fastest               */
     int32_t strategy[CS_TUNE_MAX];           /* cs_strategy of candidate i         */
     int32_t chunks_per_block[CS_TUNE_MAX];   /* fused: chunks per workgroup        */
+    int32_t pairs_per_lane[CS_TUNE_MAX];     /* compact: pairs per lane            */
     float ms[CS_TUNE_MAX];                   /* median step time, milliseconds     */
 } cs_tune_result;
 
-/* Pick the kernel strategy and the fused kernel's chunks per workgroup for
- * this problem (the batching of the Sec. 3.1 step over uneven cells): every
- * candidate (fused with 1..32 chunks per workgroup, compact) runs `reps` timed
+/* Pick the kernel strategy and its tile shape for this problem (the batching
+ * of the Sec. 3.1 step over uneven cells): every candidate (fused with 1..32
+ * chunks per workgroup, compact with 1, 2 or 4 pairs per lane) runs `reps` timed
  * steps on a private device copy of the particles, its result after one step
  * from the same state is checked to be bitwise identical to the first
  * candidate's (CS_ERR_HIP if not, which would be a library defect), and the
- * fastest is stored in the context (CS_OPT_STRATEGY, CS_OPT_CHUNKS_PER_BLOCK).
+ * fastest is stored in the context (CS_OPT_STRATEGY, CS_OPT_CHUNKS_PER_BLOCK,
+ * CS_OPT_PAIRS_PER_LANE).
  * The caller's particles are not modified.  Arguments as cs_compton_step
  * (stats are not written); reps in [1, 100].  Synchronous; allocates and
  * frees the private copy.  `out` may be NULL. */

@@ -21,7 +21,7 @@ SAMPLERS = {"plain": 0, "mlp_f32": 1, "mlp_bf16": 2, "mlp_fp8": 3}
 STRATEGIES = {"fused": 0, "multi_kernel": 1, "compact": 2, "per_cell": 3}
 STRATEGY_NAMES = {v: k for k, v in STRATEGIES.items()}
 TUNE_MAX = 16
-OPT_STRATEGY, OPT_CHUNKS_PER_BLOCK = 0, 1
+OPT_STRATEGY, OPT_CHUNKS_PER_BLOCK, OPT_PAIRS_PER_LANE = 0, 1, 2
 LOSSES = {"mse": 0, "mae": 1}
 
 
@@ -37,7 +37,7 @@ class Species(C.Structure):
 
 class TuneResult(C.Structure):
     _fields_ = [("n", C.c_int32), ("best", C.c_int32), ("strategy", C.c_int32 * 16),
-                ("chunks_per_block", C.c_int32 * 16), ("ms", C.c_float * 16)]
+                ("chunks_per_block", C.c_int32 * 16), ("pairs_per_lane", C.c_int32 * 16), ("ms", C.c_float * 16)]
 
 
 STAGES = ["prep", "pair", "compact", "collide", "finalize"]
@@ -230,6 +230,9 @@ class Context:
     def set_chunks_per_block(self, g):
         self.set_option(OPT_CHUNKS_PER_BLOCK, g)
 
+    def set_pairs_per_lane(self, n):
+        self.set_option(OPT_PAIRS_PER_LANE, n)
+
     def set_stage_timing(self, enable):
         self._check(lib().cs_set_stage_timing(self._h, 1 if enable else 0))
 
@@ -243,17 +246,17 @@ class Context:
     def autotune(self, e, g, off_e, off_g, dt, density_norm, seed, step, sampler="plain", mlp=None, reps=5,
                  stream=None):
         """Time the candidate strategies on a private copy of the particles and
-        keep the fastest; returns {"best": (strategy, chunks), "candidates":
-        [(strategy, chunks, ms), ...]}."""
+        keep the fastest; returns {"best": (strategy, chunks, pairs_per_lane),
+        "candidates": [(strategy, chunks, pairs_per_lane, ms), ...]}."""
         res = TuneResult()
         rc = lib().cs_autotune(self._h, _dtype_code(e["x"]), _species(e), _species(g), _ptr(off_e), _ptr(off_g),
                                off_e.numel() - 1, float(dt), float(density_norm), int(seed), int(step),
                                SAMPLERS[sampler], None if mlp is None else mlp.handle, int(reps), C.byref(res),
                                _stream(stream))
         self._check(rc)
-        cands = [(STRATEGY_NAMES[res.strategy[i]], int(res.chunks_per_block[i]), float(res.ms[i]))
-                 for i in range(res.n)]
-        return {"best": cands[res.best][:2], "candidates": cands}
+        cands = [(STRATEGY_NAMES[res.strategy[i]], int(res.chunks_per_block[i]), int(res.pairs_per_lane[i]),
+                  float(res.ms[i])) for i in range(res.n)]
+        return {"best": cands[res.best][:3], "candidates": cands}
 
     def graph(self, e, g, off_e, off_g, dt, density_norm, seed, sampler="plain", mlp=None, stats=None,
               stream=None):

@@ -192,8 +192,8 @@ struct Plan {
     int64_t status_words = 0;
 };
 
-Plan plan_step(int64_t strategy, int64_t chunks_per_block, int64_t n_cells, int64_t ne, int64_t ng,
-               cs_sampler sampler) {
+Plan plan_step(int64_t strategy, int64_t chunks_per_block, int64_t pairs_per_lane, int64_t n_cells, int64_t ne,
+               int64_t ng, cs_sampler sampler) {
     Plan pl;
     pl.strategy = strategy;
     cs::StepShape& sh = pl.sh;
@@ -215,6 +215,7 @@ Plan plan_step(int64_t strategy, int64_t chunks_per_block, int64_t n_cells, int6
     sh.chunks_per_block = G;
     sh.n_step_blocks = sh.n_chunks > 0 ? (sh.n_chunks + G - 1) / G : 1;
     sh.n_prep_blocks = cs::fused_prep_blocks(n_cells);
+    sh.pairs_per_lane = pairs_per_lane == 1 || pairs_per_lane == 2 || pairs_per_lane == 4 ? pairs_per_lane : 4;
     // dense collide grid: one lane per accepted pair at most, capped (2048
     // one-wave workgroups, or 512 four-wave workgroups that each load the
     // network's LDS copy)
@@ -231,7 +232,7 @@ Plan plan_step(int64_t strategy, int64_t chunks_per_block, int64_t n_cells, int6
     } else if (strategy == CS_STRATEGY_COMPACT) {
         sh.n_collide_blocks = sh.n_dense_blocks;
         pl.bytes = cs::compact_workspace_bytes(sh);
-        pl.status_words += sh.n_chunks;
+        pl.status_words += cs::compact_pair_blocks(sh);
     } else {
         pl.bytes = cs::step_workspace_bytes(sh);
     }
@@ -289,7 +290,7 @@ cs_status cs_compton_step(cs_ctx* ctx, cs_dtype dtype, cs_species electrons, cs_
     DeviceGuard g(ctx->device);
     if (!g.ok) return fail(ctx, CS_ERR_HIP, "cs_compton_step: cannot select device");
     hipStream_t st = (hipStream_t)stream;
-    const Plan pl = plan_step(ctx->strategy, ctx->chunks_per_block, n_cells, electrons.n, photons.n, sampler);
+    const Plan pl = plan_step(ctx->strategy, ctx->chunks_per_block, ctx->pairs_per_lane, n_cells, electrons.n, photons.n, sampler);
     s = ensure_workspace(ctx, ctx->ws, pl.bytes, pl.status_words, st);
     if (s != CS_OK) return s;
     cs::StepParams p = make_params(dtype, electrons, photons, off_e, off_g, dt, density_norm, seed, step, sampler, mlp,
@@ -360,7 +361,7 @@ cs_status cs_graph_create(cs_ctx* ctx, cs_dtype dtype, cs_species electrons, cs_
     if (!g) return fail(ctx, CS_ERR_INVALID_ARG, "cs_graph_create: out of host memory");
     g->ctx = ctx;
     g->device = ctx->device;
-    const Plan pl = plan_step(ctx->strategy, ctx->chunks_per_block, n_cells, electrons.n, photons.n, sampler);
+    const Plan pl = plan_step(ctx->strategy, ctx->chunks_per_block, ctx->pairs_per_lane, n_cells, electrons.n, photons.n, sampler);
     s = ensure_workspace(ctx, g->ws, pl.bytes, pl.status_words, st);
     if (s != CS_OK) {
         free_graph(g);
@@ -463,24 +464,28 @@ cs_status cs_autotune(cs_ctx* ctx, cs_dtype dtype, cs_species electrons, cs_spec
         }
         return hipSuccess;
     };
-    int32_t cand_s[CS_TUNE_MAX], cand_g[CS_TUNE_MAX];
+    int32_t cand_s[CS_TUNE_MAX], cand_g[CS_TUNE_MAX], cand_p[CS_TUNE_MAX];
     int n_cand = 0;
     for (int gpb : {1, 2, 4, 8, 16, 32}) {
         cand_s[n_cand] = CS_STRATEGY_FUSED;
+        cand_p[n_cand] = 0;
         cand_g[n_cand++] = gpb;
     }
-    cand_s[n_cand] = CS_STRATEGY_COMPACT;
-    cand_g[n_cand++] = 0;
+    for (int ppl : {1, 2, 4}) {
+        cand_s[n_cand] = CS_STRATEGY_COMPACT;
+        cand_p[n_cand] = ppl;
+        cand_g[n_cand++] = 0;
+    }
     float ms_best = 0.f;
     int best = -1;
     float ms_all[CS_TUNE_MAX] = {};
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     e = hipEventCreate(&ev0);
     if (e == hipSuccess) e = hipEventCreate(&ev1);
-    const int64_t saved_s = ctx->strategy, saved_g = ctx->chunks_per_block;
+    const int64_t saved_s = ctx->strategy, saved_g = ctx->chunks_per_block, saved_p = ctx->pairs_per_lane;
     cs_status rs = CS_OK;
     for (int c = 0; c < n_cand && e == hipSuccess && rs == CS_OK; ++c) {
-        const Plan pl = plan_step(cand_s[c], cand_g[c], n_cells, electrons.n, photons.n, sampler);
+        const Plan pl = plan_step(cand_s[c], cand_g[c], cand_p[c], n_cells, electrons.n, photons.n, sampler);
         rs = ensure_workspace(ctx, ctx->ws, pl.bytes, pl.status_words, st);
         if (rs != CS_OK) break;
         const cs::StepParams p = make_params(dtype, pe, pg, off_e, off_g, dt, density_norm, seed, step, sampler, mlp,
@@ -532,10 +537,12 @@ cs_status cs_autotune(cs_ctx* ctx, cs_dtype dtype, cs_species electrons, cs_spec
     if (rs != CS_OK || e != hipSuccess) {
         ctx->strategy = saved_s;
         ctx->chunks_per_block = saved_g;
+        ctx->pairs_per_lane = saved_p;
         return rs != CS_OK ? rs : hip_fail(ctx, e, "cs_autotune");
     }
     ctx->strategy = cand_s[best];
     ctx->chunks_per_block = cand_g[best];
+    ctx->pairs_per_lane = cand_p[best];
     if (out) {
         *out = cs_tune_result{};
         out->n = n_cand;
@@ -543,6 +550,7 @@ cs_status cs_autotune(cs_ctx* ctx, cs_dtype dtype, cs_species electrons, cs_spec
         for (int c = 0; c < n_cand; ++c) {
             out->strategy[c] = cand_s[c];
             out->chunks_per_block[c] = cand_g[c];
+            out->pairs_per_lane[c] = cand_p[c];
             out->ms[c] = ms_all[c];
         }
     }
@@ -563,6 +571,11 @@ cs_status cs_set_option(cs_ctx* ctx, cs_option opt, int64_t value) {
             if (value < 0 || value > 4096) return fail(ctx, CS_ERR_INVALID_ARG, "cs_set_option: chunks per block");
             ctx->chunks_per_block = value;
             break;
+        case CS_OPT_PAIRS_PER_LANE:
+            if (value != 0 && value != 1 && value != 2 && value != 4)
+                return fail(ctx, CS_ERR_INVALID_ARG, "cs_set_option: pairs per lane must be 0, 1, 2 or 4");
+            ctx->pairs_per_lane = value;
+            break;
         default:
             return fail(ctx, CS_ERR_INVALID_ARG, "cs_set_option: unknown option");
     }
@@ -578,6 +591,9 @@ cs_status cs_get_option(const cs_ctx* ctx, cs_option opt, int64_t* value) {
             return CS_OK;
         case CS_OPT_CHUNKS_PER_BLOCK:
             *value = ctx->chunks_per_block;
+            return CS_OK;
+        case CS_OPT_PAIRS_PER_LANE:
+            *value = ctx->pairs_per_lane;
             return CS_OK;
         default:
             return CS_ERR_INVALID_ARG;

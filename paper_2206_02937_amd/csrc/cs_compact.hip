@@ -48,63 +48,117 @@ struct CompactArgs {
     MlpDev mlp;
 };
 
-template <typename T>
+// One workgroup takes PPL consecutive 256-pair chunks, one pair of each per
+// lane.  The phases run for all PPL pairs before the next phase starts --
+// find the cell, read its offsets and key; pair; read the particles; the
+// physics -- so that each lane has PPL independent memory accesses in flight
+// instead of one.  The accepted pairs of the PPL chunks (in pair order) take
+// their place in the global list with one look-back per workgroup.
+template <typename T, int PPL>
 __global__ __launch_bounds__(kChunk) void k_pair_compact(const CompactArgs<T> a) {
-    __shared__ int s_wcnt[kChunk / 64];
+    __shared__ int s_wcnt[PPL][kChunk / 64];
     __shared__ int s_prefix;
     __shared__ double s_rd[kChunk / 64];
     __shared__ long long s_ri[2 * (kChunk / 64)];
     const int tid = threadIdx.x;
     const int lane = lane_id();
     const int wave = tid >> 6;
-    const int64_t j = blockIdx.x;
+    const int64_t blk = blockIdx.x;
     StepControl* ctrl = a.ctrl;
     const uint32_t E = ctrl->epoch;
     const uint64_t step = ctrl->step;
     const bool layout_ok = ctrl->layout_epoch != E && ctrl->scan_fault_epoch != E;
     const int32_t T_total = layout_ok ? a.pair_off[a.n_cells] : 0;
-    const int32_t t = (int32_t)(j * kChunk) + tid;
-    const bool active = t < T_total;
-    int c = 0;
-    if (active) {
-        int lo = a.chunk_cell[j], hi = a.chunk_cell[j + 1];
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (a.pair_off[mid] <= t)
-                lo = mid;
-            else
-                hi = mid - 1;
+    // phase 1: cell of each pair (binary search over the chunk's cells),
+    // then the cell's particle ranges and pairing key
+    int32_t t[PPL];
+    int c[PPL];
+    bool act[PPL];
+#pragma unroll
+    for (int q = 0; q < PPL; ++q) {
+        const int64_t j = blk * PPL + q;
+        t[q] = (int32_t)(j * kChunk) + tid;
+        act[q] = j < a.n_chunks && t[q] < T_total;
+        c[q] = 0;
+        if (act[q]) {
+            int lo = a.chunk_cell[j], hi = a.chunk_cell[j + 1];
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (a.pair_off[mid] <= t[q])
+                    lo = mid;
+                else
+                    hi = mid - 1;
+            }
+            c[q] = lo;
         }
-        c = lo;
     }
-    PairOutcome o;
-    o.accept = false;
-    o.P = 0.0;
-    o.clipped = false;
-    o.invalid = false;
-    o.ie = o.ig = 0;
-    if (__any(active))
-        o = pair_eval<T>(a.pt, active, a.off_e[c], a.off_e[c + 1], a.off_g[c], a.off_g[c + 1], a.keys + 4 * c,
-                         (uint32_t)(t - (active ? a.pair_off[c] : 0)), a.dt, a.density_norm, a.seed, step);
-    const uint64_t mask = __ballot(o.accept);
-    const int before = __popcll(mask & ((1ull << lane) - 1ull));
-    if (lane == 0) s_wcnt[wave] = __popcll(mask);
-    const double wp = wave_sum(o.P);
-    const long long wc = wave_sum_i(o.clipped ? 1 : 0), wi = wave_sum_i(o.invalid ? 1 : 0);
+    int64_t e0[PPL], e1[PPL], g0[PPL], g1[PPL];
+    uint4 key[PPL];
+    int32_t po[PPL];
+#pragma unroll
+    for (int q = 0; q < PPL; ++q) {
+        e0[q] = e1[q] = g0[q] = g1[q] = 0;
+        key[q] = make_uint4(0, 0, 0, 0);
+        po[q] = 0;
+        if (act[q]) {
+            e0[q] = a.off_e[c[q]];
+            e1[q] = a.off_e[c[q] + 1];
+            g0[q] = a.off_g[c[q]];
+            g1[q] = a.off_g[c[q] + 1];
+            key[q] = *(const uint4*)(a.keys + 4 * c[q]);
+            po[q] = a.pair_off[c[q]];
+        }
+    }
+    // phase 2: pairing and the particle reads
+    PairSlot sl[PPL];
+    PairRaw<T> raw[PPL];
+#pragma unroll
+    for (int q = 0; q < PPL; ++q)
+        sl[q] = pair_index(act[q], e0[q], e1[q], g0[q], g1[q], key[q].x, key[q].y, key[q].z, key[q].w,
+                           (uint32_t)(t[q] - po[q]));
+#pragma unroll
+    for (int q = 0; q < PPL; ++q) raw[q] = pair_load<T>(a.pt, sl[q]);
+    // phase 3: physics, per-chunk ballots
+    double sum_p = 0.0;
+    long long n_clip = 0, n_inv = 0;
+    bool acc[PPL];
+    int before[PPL];
+#pragma unroll
+    for (int q = 0; q < PPL; ++q) {
+        const PairOutcome o = pair_physics<T>(sl[q], raw[q], a.dt, a.density_norm, a.seed, step);
+        sum_p += o.P;
+        n_clip += o.clipped ? 1 : 0;
+        n_inv += o.invalid ? 1 : 0;
+        acc[q] = o.accept;
+        const uint64_t mask = __ballot(o.accept);
+        before[q] = __popcll(mask & ((1ull << lane) - 1ull));
+        if (lane == 0) s_wcnt[q][wave] = __popcll(mask);
+    }
+    const double wp = wave_sum(sum_p);
+    const long long wc = wave_sum_i(n_clip), wi = wave_sum_i(n_inv);
     if (lane == 0) {
         s_rd[wave] = wp;
         s_ri[2 * wave] = wc;
         s_ri[2 * wave + 1] = wi;
     }
     __syncthreads();
-    int wbase = 0, total = 0;
+    // position of this lane's accepted pairs within the workgroup's list:
+    // chunk-major, then wave, then lane (pair order)
+    int base[PPL];
+    int total = 0;
 #pragma unroll
-    for (int w = 0; w < kChunk / 64; ++w) {
-        wbase += w < wave ? s_wcnt[w] : 0;
-        total += s_wcnt[w];
+    for (int q = 0; q < PPL; ++q) {
+        int wb = 0, tq = 0;
+#pragma unroll
+        for (int w = 0; w < kChunk / 64; ++w) {
+            wb += w < wave ? s_wcnt[q][w] : 0;
+            tq += s_wcnt[q][w];
+        }
+        base[q] = total + wb + before[q];
+        total += tq;
     }
     if (tid < 64) {
-        const uint32_t ex = lookback_exclusive_wave(a.status, j, E, (uint32_t)total, &ctrl->scan_fault_epoch);
+        const uint32_t ex = lookback_exclusive_wave(a.status, blk, E, (uint32_t)total, &ctrl->scan_fault_epoch);
         if (tid == 0) s_prefix = (int)ex;
     }
     if (tid == 0) {
@@ -115,13 +169,16 @@ __global__ __launch_bounds__(kChunk) void k_pair_compact(const CompactArgs<T> a)
             cl += s_ri[2 * w];
             in += s_ri[2 * w + 1];
         }
-        a.chunk_prob[j] = p;
-        a.chunk_clip[j] = cl;
-        a.chunk_inv[j] = in;
+        a.chunk_prob[blk] = p;
+        a.chunk_clip[blk] = cl;
+        a.chunk_inv[blk] = in;
     }
     __syncthreads();
-    if (o.accept) a.list[s_prefix + wbase + before] = make_int2(o.ie, o.ig);
-    if (tid == 0 && j == (int64_t)gridDim.x - 1) ctrl->n_accepted = (uint32_t)(s_prefix + total);
+    const int prefix = s_prefix;
+#pragma unroll
+    for (int q = 0; q < PPL; ++q)
+        if (acc[q]) a.list[prefix + base[q]] = make_int2(sl[q].ie, sl[q].ig);
+    if (tid == 0 && blk == (int64_t)gridDim.x - 1) ctrl->n_accepted = (uint32_t)(prefix + total);
 }
 
 // Network samplers defer the pairs outside the network's domain: their list
@@ -226,6 +283,11 @@ __global__ __launch_bounds__(SAMP == CS_SAMPLER_PLAIN ? kDenseThreads : kDenseNe
 
 static size_t al(size_t v) { return (v + 255) & ~(size_t)255; }
 
+int64_t compact_pair_blocks(const StepShape& s) {
+    const int64_t ppl = s.pairs_per_lane;
+    return s.n_chunks > 0 ? (s.n_chunks + ppl - 1) / ppl : 0;
+}
+
 size_t compact_workspace_bytes(const StepShape& s) {
     size_t b = 0;
     b += al(sizeof(int32_t) * (s.n_cells + 1));
@@ -291,7 +353,15 @@ static hipError_t launch_compact_t(const StepShape& sh, const CompactBuffers& b,
     a.coll_fb = b.coll_fb;
     a.stats = p.stats;
     a.mlp = p.net;
-    if (sh.n_chunks > 0) k_pair_compact<T><<<(unsigned)sh.n_chunks, kChunk, 0, st>>>(a);
+    const int64_t n_pair_blocks = compact_pair_blocks(sh);
+    if (sh.n_chunks > 0) {
+        if (sh.pairs_per_lane == 1)
+            k_pair_compact<T, 1><<<(unsigned)n_pair_blocks, kChunk, 0, st>>>(a);
+        else if (sh.pairs_per_lane == 2)
+            k_pair_compact<T, 2><<<(unsigned)n_pair_blocks, kChunk, 0, st>>>(a);
+        else
+            k_pair_compact<T, 4><<<(unsigned)n_pair_blocks, kChunk, 0, st>>>(a);
+    }
     mark(2);
     mark(3);
     k_collide_dense<T, SAMP><<<(unsigned)sh.n_collide_blocks,
@@ -305,7 +375,7 @@ static hipError_t launch_compact_t(const StepShape& sh, const CompactBuffers& b,
     f.a_clip = b.chunk_clip;
     f.a_inv = b.chunk_inv;
     f.a_coll = nullptr;
-    f.n_a = sh.n_chunks;
+    f.n_a = n_pair_blocks;
     f.b_eb = b.coll_eb;
     f.b_ea = b.coll_ea;
     f.b_fb = b.coll_fb;

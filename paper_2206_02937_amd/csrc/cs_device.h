@@ -13,6 +13,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "cs_sigma_table.h"
+
 namespace cs {
 
 // ---------------------------------------------------------------------------
@@ -208,10 +210,21 @@ __device__ __forceinline__ double tail_series(const TailCoeffs* T, double t, dou
     return fma(t14, H, L);
 }
 
-// s(x) = sigma_KN(x) / sigma_T: series below 0.2 (14 terms below 0.02),
-// closed form with log1p above.
+// s(x) = sigma_KN(x) / sigma_T.  Below 2: the per-segment Taylor polynomial
+// of cs_sigma_table.h, evaluated per lane (each lane loads its own segment's
+// 12 coefficients; no lane waits for another's branch).  From 2 up: the
+// closed form with log1p, where its terms no longer cancel.
 __device__ __forceinline__ double sigma_ratio(double x) {
-    if (x < kSeriesSwitch) return series_split(kSigma.c, x, 0.02);
+    if (x < kSigTabMax) {
+        int j = (int)(x * kSigTabInvWidth);
+        j = j < 0 ? 0 : (j > kSigTabSegments - 1 ? kSigTabSegments - 1 : j);
+        const double t = x - ((double)j + 0.5) / kSigTabInvWidth;
+        const double* a = kSigTab + j * kSigTabTerms;
+        double acc = a[kSigTabTerms - 1];
+#pragma unroll
+        for (int n = kSigTabTerms - 2; n >= 0; --n) acc = fma(acc, t, a[n]);
+        return acc;
+    }
     const double l = log1p(2.0 * x);
     const double opx = 1.0 + x, o2x = 1.0 + 2.0 * x;
     return 0.75 * (opx / (x * x * x) * (2.0 * x * opx / o2x - l) + l / (2.0 * x) - (1.0 + 3.0 * x) / (o2x * o2x));

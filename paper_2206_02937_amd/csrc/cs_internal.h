@@ -79,6 +79,7 @@ struct StepShape {
     int64_t n_step_blocks;     // fused: grid of k_step (>= 1)
     int64_t n_prep_blocks;     // fused / compact: grid of k_prep_scan
     int64_t n_dense_blocks;    // compact: grid of the one-wave collide kernel
+    int64_t pairs_per_lane;    // compact: 256-pair chunks per pair workgroup (1, 2, 4)
 };
 
 // Per-workgroup partial sums of the fused step.
@@ -115,6 +116,7 @@ struct CompactBuffers {
 };
 
 int64_t compact_collide_threads(cs_sampler s);
+int64_t compact_pair_blocks(const StepShape& s);
 size_t fused_workspace_bytes(const StepShape& s);
 void carve_fused_buffers(const Workspace& w, const StepShape& s, FusedBuffers* b);
 int64_t fused_prep_blocks(int64_t n_cells);
@@ -221,6 +223,7 @@ struct cs_ctx {
     cs::Workspace ws;
     int64_t strategy = CS_STRATEGY_FUSED;
     int64_t chunks_per_block = 0;  // 0: automatic
+    int64_t pairs_per_lane = 0;    // compact pair kernel, 0: automatic
     std::string last_error;
     bool timing = false;
     int64_t timed_steps = 0;          // steps timed since enabling or the last read

@@ -31,16 +31,77 @@ __device__ __forceinline__ bool finite_pair(d3 p, double we, d3 k, double wg) {
            isfinite(we) && isfinite(wg) && we >= 0.0 && wg >= 0.0;
 }
 
-// Pair number i of cell c: pairing, rest-frame photon energy, Klein-Nishina
-// cross-section, probability, accept/reject.  Must be called with the whole
-// wave converged (the cross-section picks its series length per wave).
+// The three phases of a pair's evaluation, split so that a kernel can issue
+// the memory accesses of several pairs before it needs any of them:
+//   pair_index   pairing (keyed in-cell bijection) -> electron/photon index
+//   pair_load    the two particles' momenta and weights (storage type)
+//   pair_physics rest-frame photon energy, Klein-Nishina cross-section,
+//                probability, accept/reject
+// pair_eval runs the three in a row.
+struct PairSlot {
+    int32_t ie, ig;  // particle indices (0 when inactive)
+    uint32_t M;      // larger species count of the cell
+    bool active;
+};
+
 template <typename T>
-__device__ __forceinline__ PairOutcome pair_eval(const Particles<T>& a, bool active, int64_t e0, int64_t e1,
-                                                 int64_t g0, int64_t g1, const uint32_t* key4, uint32_t i,
-                                                 double dt, double density_norm, uint64_t seed, uint64_t step) {
+struct PairRaw {
+    T p[3], k[3], we, wg;
+};
+
+// Pair number i of the cell with particle ranges [e0, e1), [g0, g1) and
+// pairing key key4.
+__device__ __forceinline__ PairSlot pair_index(bool active, int64_t e0, int64_t e1, int64_t g0, int64_t g1,
+                                               uint32_t k0, uint32_t k1, uint32_t k2, uint32_t k3, uint32_t i) {
+    PairSlot s;
+    s.ie = 0;
+    s.ig = 0;
+    s.M = 0;
+    s.active = active;
+    if (active) {
+        const uint32_t ne = (uint32_t)(e1 - e0), ng = (uint32_t)(g1 - g0);
+        s.M = ne > ng ? ne : ng;
+        FeistelKey key;
+        key.k[0] = k0;
+        key.k[1] = k1;
+        key.k[2] = k2;
+        key.k[3] = k3;
+        key.half_bits = (ceil_log2(s.M) + 1u) >> 1;
+        if (ne <= ng) {
+            s.ie = (int32_t)(e0 + i);
+            s.ig = (int32_t)(g0 + shuffle_index(i, ng, key));
+        } else {
+            s.ig = (int32_t)(g0 + i);
+            s.ie = (int32_t)(e0 + shuffle_index(i, ne, key));
+        }
+    }
+    return s;
+}
+
+template <typename T>
+__device__ __forceinline__ PairRaw<T> pair_load(const Particles<T>& a, const PairSlot& s) {
+    PairRaw<T> r;
+    if (s.active) {
+        r.p[0] = a.ex[s.ie];
+        r.p[1] = a.ey[s.ie];
+        r.p[2] = a.ez[s.ie];
+        r.k[0] = a.gx[s.ig];
+        r.k[1] = a.gy[s.ig];
+        r.k[2] = a.gz[s.ig];
+        r.we = a.ew[s.ie];
+        r.wg = a.gw[s.ig];
+    } else {
+        r.p[0] = r.p[1] = r.p[2] = r.k[0] = r.k[1] = r.k[2] = r.we = r.wg = (T)0;
+    }
+    return r;
+}
+
+template <typename T>
+__device__ __forceinline__ PairOutcome pair_physics(const PairSlot& s, const PairRaw<T>& r, double dt,
+                                                    double density_norm, uint64_t seed, uint64_t step) {
     PairOutcome o;
-    o.ie = 0;
-    o.ig = 0;
+    o.ie = s.ie;
+    o.ig = s.ig;
     o.x = 0.0;
     o.P = 0.0;
     o.accept = false;
@@ -48,52 +109,50 @@ __device__ __forceinline__ PairOutcome pair_eval(const Particles<T>& a, bool act
     o.invalid = false;
     double x = 0.0, flux = 0.0, wmax = 0.0, tau = 0.0;
     bool compute = false;
-    if (active) {
-        const uint32_t ne = (uint32_t)(e1 - e0), ng = (uint32_t)(g1 - g0);
-        const uint32_t M = ne > ng ? ne : ng;
-        FeistelKey key;
-        key.k[0] = key4[0];
-        key.k[1] = key4[1];
-        key.k[2] = key4[2];
-        key.k[3] = key4[3];
-        key.half_bits = (ceil_log2(M) + 1u) >> 1;
-        if (ne <= ng) {
-            o.ie = (int32_t)(e0 + i);
-            o.ig = (int32_t)(g0 + shuffle_index(i, ng, key));
-        } else {
-            o.ig = (int32_t)(g0 + i);
-            o.ie = (int32_t)(e0 + shuffle_index(i, ne, key));
-        }
-        const d3 p = {(double)a.ex[o.ie], (double)a.ey[o.ie], (double)a.ez[o.ie]};
-        const d3 k = {(double)a.gx[o.ig], (double)a.gy[o.ig], (double)a.gz[o.ig]};
-        const double we = (double)a.ew[o.ie], wg = (double)a.gw[o.ig];
+    if (s.active) {
+        const d3 p = {(double)r.p[0], (double)r.p[1], (double)r.p[2]};
+        const d3 k = {(double)r.k[0], (double)r.k[1], (double)r.k[2]};
+        const double we = (double)r.we, wg = (double)r.wg;
         if (!finite_pair(p, we, k, wg)) {
             o.invalid = true;
         } else {
             const PairInv inv = pair_invariants(p, k);
             x = inv.x;
             flux = inv.flux;
-            tau = dt * density_norm * (double)M;
+            tau = dt * density_norm * (double)s.M;
             wmax = we > wg ? we : wg;
             compute = x > 0.0;
         }
     }
-    // cross-section on the converged wave (lanes without a valid pair see x = 0)
-    const double s = sigma_ratio(x);
     if (compute) {
-        double P = tau * wmax * s * flux;
+        double P = tau * wmax * sigma_ratio(x) * flux;
         if (P > 1.0) {
             o.clipped = true;
             P = 1.0;
         }
         o.P = P;
     }
-    if (active && !o.invalid) {
-        const u32x4 r = draw(seed, (uint64_t)o.ie, step, kCollide);
-        o.accept = uniform53(r.a, r.b) < o.P;
+    if (s.active && !o.invalid) {
+        const u32x4 u = draw(seed, (uint64_t)o.ie, step, kCollide);
+        o.accept = uniform53(u.a, u.b) < o.P;
     }
     o.x = x;
     return o;
+}
+
+template <typename T>
+__device__ __forceinline__ PairOutcome pair_eval(const Particles<T>& a, bool active, int64_t e0, int64_t e1,
+                                                 int64_t g0, int64_t g1, const uint32_t* key4, uint32_t i,
+                                                 double dt, double density_norm, uint64_t seed, uint64_t step) {
+    uint32_t k0 = 0, k1 = 0, k2 = 0, k3 = 0;
+    if (active) {
+        k0 = key4[0];
+        k1 = key4[1];
+        k2 = key4[2];
+        k3 = key4[3];
+    }
+    const PairSlot s = pair_index(active, e0, e1, g0, g1, k0, k1, k2, k3, i);
+    return pair_physics<T>(s, pair_load<T>(a, s), dt, density_norm, seed, step);
 }
 
 struct CollideSums {

@@ -149,14 +149,16 @@ def test_autotune_keeps_particles_and_bits(ctx, net, sampler):
     _log(f"  autotune {sampler}: {res}")
     torch.cuda.synchronize()
     assert _same(compton.to_host(e), before_e) and _same(compton.to_host(g), before_g)
-    assert len(res["candidates"]) == 7 and all(c[2] > 0 for c in res["candidates"])
+    assert len(res["candidates"]) == 9 and all(c[3] > 0 for c in res["candidates"])
     best = res["best"]
     assert ctx.get_option(compton.OPT_STRATEGY) == compton.STRATEGIES[best[0]]
     assert ctx.get_option(compton.OPT_CHUNKS_PER_BLOCK) == best[1]
+    assert ctx.get_option(compton.OPT_PAIRS_PER_LANE) == best[2]
     # the tuned configuration and the default one give the same bits
     ctx.step(e, g, oe, og, p.dt, p.density_norm, p.seed, 3, sampler=sampler, mlp=mlp)
     ctx.set_strategy("fused")
     ctx.set_chunks_per_block(0)
+    ctx.set_pairs_per_lane(0)
     e2, g2, oe2, og2 = compton.to_device(p)
     ctx.step(e2, g2, oe2, og2, p.dt, p.density_norm, p.seed, 3, sampler=sampler, mlp=mlp)
     torch.cuda.synchronize()

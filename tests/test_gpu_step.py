@@ -283,8 +283,9 @@ def test_sample_plain_parity(ctx, orc, dtype):
 
 @pytest.mark.parametrize("workload", ["grid_small", "uneven_small", "unequal"])
 def test_strategies_bitwise_identical(ctx, workload):
-    """Every kernel strategy (fused with several chunks per workgroup, and the
-    multi-kernel baseline) gives bitwise-identical particles and counters; the
+    """Every kernel strategy (compact with 1, 2, 4 pairs per lane, fused with
+    several chunks per workgroup, the multi-kernel and per-cell baselines)
+    gives bitwise-identical particles and counters; the
     FP64 sums of the stats differ only by summation order."""
     import torch
 
@@ -296,11 +297,14 @@ def test_strategies_bitwise_identical(ctx, workload):
         p = plasma.uneven(seed=8, side=40, mean=20, peak=20.0, area_frac=0.05)
     else:
         p = _unequal_plasma(np.float32)
-    configs = [("compact", 0), ("fused", 0), ("fused", 1), ("fused", 3), ("fused", 64), ("multi_kernel", 0)]
+    # (strategy, chunks per workgroup or pairs per lane)
+    configs = [("compact", 4), ("compact", 1), ("compact", 2), ("fused", 0), ("fused", 1), ("fused", 3),
+               ("fused", 64), ("multi_kernel", 0), ("per_cell", 0)]
     results = []
     for strategy, g in configs:
         ctx.set_strategy(strategy)
-        ctx.set_chunks_per_block(g)
+        ctx.set_chunks_per_block(g if strategy == "fused" else 0)
+        ctx.set_pairs_per_lane(g if strategy == "compact" else 0)
         e_dev, g_dev, oe, og = compton.to_device(p)
         stats = ctx.stats_buffer()
         for s in range(3):
@@ -309,6 +313,7 @@ def test_strategies_bitwise_identical(ctx, workload):
         results.append((compton.to_host(e_dev), compton.to_host(g_dev), stats.cpu().numpy().copy()))
     ctx.set_strategy("fused")
     ctx.set_chunks_per_block(0)
+    ctx.set_pairs_per_lane(0)
     e0, g0, s0 = results[0]
     for (strategy, g), (e1, g1, s1) in zip(configs[1:], results[1:]):
         for k in "xyzw":
