@@ -105,37 +105,18 @@ __device__ __forceinline__ uint32_t shuffle_index(uint32_t i, uint32_t M, const 
 // s(x) = (3/8) int_{-1}^{1} f dmu.
 // ---------------------------------------------------------------------------
 
-// Taylor coefficients of s(x) about 0, from integrating the binomial series
-// of a^-n term by term:
-//   c_k = (3/8) (-1)^k 2^{k+1} [ (k+2)/2 + 1/(k+1) - 4(k+1)/((k+2)(k+3)) ].
-// Radius of convergence 1/2; |c_k| x^k ~ (3/8) k (2x)^k, so 48 terms reach
-// round-off for x < 0.2.
+// Length of the upper-tail series below (t = x v <= 2x < 0.4 in the series
+// branch); the closed form takes over from x = 0.2.
 constexpr int kSeriesTerms = 48;
 constexpr double kSeriesSwitch = 0.2;
-
-struct Coeffs {
-    double c[kSeriesTerms];
-};
-
-constexpr Coeffs sigma_series_coeffs() {
-    Coeffs r{};
-    double two = 2.0;  // 2^{k+1}
-    for (int k = 0; k < kSeriesTerms; ++k) {
-        const double kk = (double)k;
-        const double br = (kk + 2.0) / 2.0 + 1.0 / (kk + 1.0) - 4.0 * (kk + 1.0) / ((kk + 2.0) * (kk + 3.0));
-        r.c[k] = 0.375 * ((k & 1) ? -two : two) * br;
-        two *= 2.0;
-    }
-    return r;
-}
 
 // Series of the upper tail of the angular integral (v = 1 - mu, t = x v):
 //   int_{mu}^{1} f = v sum_k (-t)^k [ A_k/(k+1) - 2 v (k+1)/(k+2) + v^2 (k+1)/(k+3) ],
 //   A_k = (k+1)(k+2)/2 + 1,
 // from integrating the binomial series of a^-n term by term.  Stored per k as
-// the signed coefficients of 1, v and v^2, so that one Horner pass in t with
-// coefficient e_k(v) = a_k + v (b_k + v c_k) evaluates it.
-// t <= 2x < 0.4 in the series branch; 48 terms reach round-off.
+// the signed coefficients of 1, v and v^2: the series is A(t) + v B(t) +
+// v^2 C(t) with three polynomials in t.  t <= 2x < 0.4 in the series branch;
+// 48 terms reach round-off.
 struct TailCoeffs {
     double a[kSeriesTerms], b[kSeriesTerms], c[kSeriesTerms];
 };
@@ -152,54 +133,43 @@ constexpr TailCoeffs tail_series_coeffs() {
     return r;
 }
 
-__constant__ constexpr Coeffs kSigma = sigma_series_coeffs();
 __constant__ constexpr TailCoeffs kTail = tail_series_coeffs();
 
-// Horner over coefficients [N0, N1) of a table.  The table pointer is passed
-// through an empty asm so that the compiler re-reads the coefficients (scalar
-// loads) on every call instead of hoisting a whole table into vector
-// registers across the sampler's Newton loop.
 typedef const __attribute__((address_space(4))) double* cdptr;  // constant (scalar-load) space
 
-template <int N0, int N1>
-__device__ __forceinline__ double horner_range(const double* c_generic, double x) {
-    cdptr c = (cdptr)c_generic;
-    asm volatile("" : "+s"(c));
-    double acc = c[N1 - 1];
-#pragma unroll
-    for (int k = N1 - 2; k >= N0; --k) acc = fma(acc, x, c[k]);
-    return acc;
+// a * b + c with c held in a scalar register pair: one v_fma_f64 that reads
+// the coefficient directly (the compiler's own selection copies each scalar
+// coefficient into vector registers first, two extra instructions per term).
+__device__ __forceinline__ double fma_sgpr(double a, double b, double c) {
+    double r;
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(c));
+    return r;
 }
 
-// A 48-term series split at 14 terms: below `low_switch` the value is defined
-// as the 14-term sum (the dropped tail is below 2e-19 relative for the tables
-// here), above it as L + x^14 H.  The value depends on x alone; the wave
-// skips H when none of its active lanes needs it.
-constexpr int kLowTerms = 14;
-
-__device__ __forceinline__ double series_split(const double* c, double x, double low_switch) {
-    const double L = horner_range<0, kLowTerms>(c, x);
-    if (__all(x < low_switch)) return L;
-    const double H = horner_range<kLowTerms, kSeriesTerms>(c, x);
-    if (x < low_switch) return L;
-    const double x2 = x * x, x4 = x2 * x2, x8 = x4 * x4;
-    const double x14 = x8 * x4 * x2;
-    return fma(x14, H, L);
-}
-
-// Horner in t over terms [N0, N1) of the tail series, coefficient
-// e_k(v) = a_k + v (b_k + v c_k).
+// Horner in t over terms [N0, N1) of the three tail polynomials, returning
+// A + v (B + v C).  The coefficient pointers pass through an empty asm so
+// that the compiler reads the coefficients with scalar loads at each use
+// instead of hoisting whole tables into vector registers across the
+// sampler's Newton loop.
 template <int N0, int N1>
 __device__ __forceinline__ double tail_horner(const TailCoeffs* T_generic, double t, double v) {
     cdptr A = (cdptr)T_generic->a, B = (cdptr)T_generic->b, C = (cdptr)T_generic->c;
     asm volatile("" : "+s"(A), "+s"(B), "+s"(C));
-    double acc = fma(v, fma(v, C[N1 - 1], B[N1 - 1]), A[N1 - 1]);
+    double pa = A[N1 - 1], pb = B[N1 - 1], pc = C[N1 - 1];
 #pragma unroll
-    for (int k = N1 - 2; k >= N0; --k) acc = fma(acc, t, fma(v, fma(v, C[k], B[k]), A[k]));
-    return acc;
+    for (int k = N1 - 2; k >= N0; --k) {
+        pa = fma_sgpr(pa, t, A[k]);
+        pb = fma_sgpr(pb, t, B[k]);
+        pc = fma_sgpr(pc, t, C[k]);
+    }
+    return fma(v, fma(v, pc, pb), pa);
 }
 
-// The same 14-term split as series_split, with the switch at t = 0.04.
+// A 48-term series split at 14 terms: below t = 0.04 the value is defined as
+// the 14-term sum (the dropped tail is below 2e-19 relative), above it as
+// L + t^14 H.  The wave skips H when none of its lanes needs it.
+constexpr int kLowTerms = 14;
+
 __device__ __forceinline__ double tail_series(const TailCoeffs* T, double t, double v) {
     const double L = tail_horner<0, kLowTerms>(T, t, v);
     if (__all(t < 0.04)) return L;
