@@ -3,7 +3,7 @@ network sampler (BF16 on MFMA by default) against the plain inverse-CDF
 sampler, with the KS distance of their outputs.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload grid_large]
-                    [--sampler mlp_bf16] [--strategy fused]
+                    [--sampler mlp_bf16] [--no-autotune --strategy fused] [--no-graph]
 
 A step is one cs_compton_step call over the whole plasma (pairing, boost,
 cross-section, probability, accept/compaction, sampling, scattering,
@@ -11,7 +11,10 @@ write-back, stats).  The default workload is the 128x128-cell FP32 grid with
 256 electrons and 256 photons per cell (2^22 pairs per step; Maxwell-Juttner
 kT = 0.5 electrons, photons log-uniform in [1e-4, 1e-1]); the particles are
 resident in device memory before the timed region starts.  The sampler
-network is the trained one shipped in the package.  Prints one JSON line.
+network is the trained one shipped in the package.  By default the library's
+autotuner picks the kernel strategy and tile shape first (on a private copy of
+the particles), and the timed steps replay one captured step as a HIP graph
+(the step index advances in device memory).  Prints one JSON line.
 """
 import argparse
 import json
@@ -38,14 +41,16 @@ def parse():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="grid_large", choices=WORKLOADS)
     ap.add_argument("--sampler", default="mlp_bf16", choices=["plain", "mlp_f32", "mlp_bf16", "mlp_fp8"])
-    ap.add_argument("--strategy", default="fused", choices=["fused", "compact", "multi_kernel"])
+    ap.add_argument("--strategy", default="fused", choices=["fused", "compact", "multi_kernel", "per_cell"])
     ap.add_argument("--chunks-per-block", type=int, default=0, help="fused strategy; 0 = automatic")
     ap.add_argument("--sweep", action="store_true", help="time every strategy / chunks-per-block candidate")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-sampler comparison run")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
-    ap.add_argument("--autotune", action="store_true", help="pick strategy / chunks per block with cs_autotune")
-    ap.add_argument("--graph", action="store_true", help="replay one captured step (HIP graph) in the timed loop")
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
+                    help="keep --strategy / --chunks-per-block instead of choosing with cs_autotune")
+    ap.add_argument("--no-graph", dest="graph", action="store_false",
+                    help="time eager cs_compton_step calls instead of replaying one captured step (HIP graph)")
     ap.add_argument("--baseline", default=None, choices=["per_cell", "multi_kernel", "fused", "compact"],
                     help="also time this strategy with the plain sampler (eager)")
     ap.add_argument("--traffic-calibration", action="store_true",
@@ -238,6 +243,8 @@ def main():
         tuned = ctx.autotune(e, g, oe, og, p.dt, p.density_norm, p.seed, 0, sampler=args.sampler, mlp=net, reps=5)
         print(json.dumps({"progress": "autotune", **tuned}), flush=True)
         del e, g, oe, og
+    if compton.STRATEGY_NAMES[ctx.get_option(compton.OPT_STRATEGY)] not in ("fused", "compact"):
+        args.graph = False  # graphs capture the fused or compact strategy only
     print(json.dumps({"progress": "timing", "sampler": args.sampler}), flush=True)
     # per-stage timing (eager) for the roofline, then the measured run
     eager = run_steps(ctx, p, args.sampler, net, args.steps, args.warmup)

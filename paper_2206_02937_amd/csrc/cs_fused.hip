@@ -32,7 +32,7 @@ namespace cs {
 // k_prep_scan
 // ---------------------------------------------------------------------------
 constexpr int kPrepThreads = 256;
-constexpr int kPrepPerThread = 4;
+constexpr int kPrepPerThread = 1;
 constexpr int kPrepCells = kPrepThreads * kPrepPerThread;
 
 struct PrepArgs {
@@ -316,57 +316,52 @@ __global__ __launch_bounds__(kChunk) void k_step(const FusedArgs<T> a) {
 
 // ---------------------------------------------------------------------------
 // k_finalize_step: one workgroup reduces the per-unit partial sums in a fixed
-// order (thread stride, then 4 interleaved accumulators, then lanes, then
-// waves), writes cs_stats and advances the epoch and the device step counter.
+// order (thread stride, then lanes, then waves), writes cs_stats and advances
+// the epoch and the device step counter.  Small on purpose: one accumulator
+// per quantity keeps everything in registers.
 // ---------------------------------------------------------------------------
-constexpr int kFinalThreads = 1024;
+constexpr int kFinalThreads = 256;
 
 __global__ __launch_bounds__(kFinalThreads) void k_finalize_step(const FinalArgs a) {
-    __shared__ double s_d[4][kFinalThreads / 64];
+    __shared__ double s_d[3][kFinalThreads / 64];
     __shared__ long long s_i[4][kFinalThreads / 64];
     const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
     StepControl* ctrl = a.ctrl;
     const uint32_t E = ctrl->epoch;
     const uint64_t step = ctrl->step;
-    // every load below is independent of the control block, so the
-    // workgroup issues them together and pays one memory round trip
     const int32_t n_pairs_raw = a.n_cells > 0 ? a.pair_off[a.n_cells] : 0;
     const uint32_t n_acc_raw = ctrl->n_accepted;
-    double d[3][4] = {};
-    long long q[4][4] = {};
-    for (int64_t base = tid; base < a.n_a; base += 4 * kFinalThreads) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int64_t i = base + (int64_t)r * kFinalThreads;
-            if (i < a.n_a) {
-                d[0][r] += a.a_prob[i];
-                q[0][r] += a.a_clip[i];
-                q[1][r] += a.a_inv[i];
-                if (a.a_coll) q[2][r] += a.a_coll[i];
-            }
-        }
+    double sp = 0.0, eb = 0.0, ea = 0.0;
+    long long cl = 0, in = 0, co = 0, fb = 0;
+#pragma unroll 4
+    for (int64_t i = tid; i < a.n_a; i += kFinalThreads) {
+        sp += a.a_prob[i];
+        cl += a.a_clip[i];
+        in += a.a_inv[i];
+        if (a.a_coll) co += a.a_coll[i];
     }
-    for (int64_t base = tid; base < a.n_b; base += 4 * kFinalThreads) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int64_t i = base + (int64_t)r * kFinalThreads;
-            if (i < a.n_b) {
-                d[1][r] += a.b_eb[i];
-                d[2][r] += a.b_ea[i];
-                if (a.b_fb) q[3][r] += a.b_fb[i];
-            }
-        }
+#pragma unroll 4
+    for (int64_t i = tid; i < a.n_b; i += kFinalThreads) {
+        eb += a.b_eb[i];
+        ea += a.b_ea[i];
+        if (a.b_fb) fb += a.b_fb[i];
     }
     const bool layout_ok = ctrl->layout_epoch != E && ctrl->scan_fault_epoch != E;
-    double vd[3];
-    long long vi[4];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) vd[k] = wave_sum((d[k][0] + d[k][1]) + (d[k][2] + d[k][3]));
-#pragma unroll
-    for (int k = 0; k < 4; ++k) vi[k] = wave_sum_i((q[k][0] + q[k][1]) + (q[k][2] + q[k][3]));
+    sp = wave_sum(sp);
+    eb = wave_sum(eb);
+    ea = wave_sum(ea);
+    cl = wave_sum_i(cl);
+    in = wave_sum_i(in);
+    co = wave_sum_i(co);
+    fb = wave_sum_i(fb);
     if (lane == 0) {
-        for (int k = 0; k < 3; ++k) s_d[k][wave] = vd[k];
-        for (int k = 0; k < 4; ++k) s_i[k][wave] = vi[k];
+        s_d[0][wave] = sp;
+        s_d[1][wave] = eb;
+        s_d[2][wave] = ea;
+        s_i[0][wave] = cl;
+        s_i[1][wave] = in;
+        s_i[2][wave] = co;
+        s_i[3][wave] = fb;
     }
     __syncthreads();
     if (tid == 0) {
