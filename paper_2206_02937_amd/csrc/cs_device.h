@@ -146,22 +146,54 @@ __device__ __forceinline__ double fma_sgpr(double a, double b, double c) {
     return r;
 }
 
-// Horner in t over terms [N0, N1) of the three tail polynomials, returning
+// t^N by repeated squaring (N known at compile time).
+template <int N>
+__device__ __forceinline__ double ipow(double t) {
+    if constexpr (N == 1) {
+        return t;
+    } else if constexpr (N % 2 == 0) {
+        const double h = ipow<N / 2>(t);
+        return h * h;
+    } else {
+        return ipow<N - 1>(t) * t;
+    }
+}
+
+// sum_{k = N0}^{N1 - 1} c_k t^(k - N0): chunks of CH terms by Horner (the
+// chunks are independent, so their dependency chains overlap), combined in
+// powers of t^CH.  Coefficients are read from scalar registers.
+template <int N0, int N1, int CH>
+__device__ __forceinline__ double poly_chunked(cdptr c, double t) {
+    constexpr int NC = (N1 - N0 + CH - 1) / CH;
+    double part[NC];
+#pragma unroll
+    for (int i = 0; i < NC; ++i) {
+        const int lo = N0 + i * CH;
+        const int hi = lo + CH < N1 ? lo + CH : N1;
+        double acc = c[hi - 1];
+#pragma unroll
+        for (int k = hi - 2; k >= lo; --k) acc = fma_sgpr(acc, t, c[k]);
+        part[i] = acc;
+    }
+    const double tc = ipow<CH>(t);
+    double r = part[NC - 1];
+#pragma unroll
+    for (int i = NC - 2; i >= 0; --i) r = fma(r, tc, part[i]);
+    return r;
+}
+
+// The three tail polynomials over terms [N0, N1) in chunks of CH, returning
 // A + v (B + v C).  The coefficient pointers pass through an empty asm so
 // that the compiler reads the coefficients with scalar loads at each use
 // instead of hoisting whole tables into vector registers across the
-// sampler's Newton loop.
-template <int N0, int N1>
-__device__ __forceinline__ double tail_horner(const TailCoeffs* T_generic, double t, double v) {
+// sampler's iteration.
+template <int N0, int N1, int CH>
+__device__ __forceinline__ double tail_poly(const TailCoeffs* T_generic, double t, double v) {
     cdptr A = (cdptr)T_generic->a, B = (cdptr)T_generic->b, C = (cdptr)T_generic->c;
     asm volatile("" : "+s"(A), "+s"(B), "+s"(C));
-    double pa = A[N1 - 1], pb = B[N1 - 1], pc = C[N1 - 1];
-#pragma unroll
-    for (int k = N1 - 2; k >= N0; --k) {
-        pa = fma_sgpr(pa, t, A[k]);
-        pb = fma_sgpr(pb, t, B[k]);
-        pc = fma_sgpr(pc, t, C[k]);
-    }
+    const double pa = poly_chunked<N0, N1, CH>(A, t);
+    const double pb = poly_chunked<N0, N1, CH>(B, t);
+    const double pc = poly_chunked<N0, N1, CH>(C, t);
     return fma(v, fma(v, pc, pb), pa);
 }
 
@@ -171,13 +203,11 @@ __device__ __forceinline__ double tail_horner(const TailCoeffs* T_generic, doubl
 constexpr int kLowTerms = 14;
 
 __device__ __forceinline__ double tail_series(const TailCoeffs* T, double t, double v) {
-    const double L = tail_horner<0, kLowTerms>(T, t, v);
+    const double L = tail_poly<0, kLowTerms, 7>(T, t, v);
     if (__all(t < 0.04)) return L;
-    const double H = tail_horner<kLowTerms, kSeriesTerms>(T, t, v);
+    const double H = tail_poly<kLowTerms, kSeriesTerms, 9>(T, t, v);
     if (t < 0.04) return L;
-    const double t2 = t * t, t4 = t2 * t2, t8 = t4 * t4;
-    const double t14 = t8 * t4 * t2;
-    return fma(t14, H, L);
+    return fma(ipow<kLowTerms>(t), H, L);
 }
 
 // s(x) = sigma_KN(x) / sigma_T.  Below 2: the per-segment Taylor polynomial
@@ -205,6 +235,14 @@ __device__ __forceinline__ double angle_density_v(double v, double x) {
     const double a = 1.0 + x * v;
     const double ia = 1.0 / a;
     return ia * ia * ia + ia - v * (2.0 - v) * ia * ia;
+}
+
+// 1/a to about an ulp (hardware estimate and two Newton steps): for the
+// iteration's step sizes, whose rounding does not reach the converged root.
+__device__ __forceinline__ double recip_approx(double a) {
+    double r = __builtin_amdgcn_rcp(a);
+    r = fma(fma(-a, r, 1.0), r, r);
+    return fma(fma(-a, r, 1.0), r, r);
 }
 
 // int_{1 - v}^{1} f dmu (upper tail), for 0 <= v <= 2.
@@ -241,11 +279,15 @@ __device__ __forceinline__ double thomson_root(double u) {
 // in x: with tail = v(2 - v + v^2/3) - x v^2 (2 - 4v/3 + v^2/2) + O(x^2) and
 // Z = 8/3 - 16x/3 + O(x^2), v1 = [v0^2 (2 - 4 v0/3 + v0^2/2) - 16(1 - u)/3]
 // / (2 - 2 v0 + v0^2); for x >= 1/2 the inverse of the large-x law
-// F ~ ln((1+2x)/a) / ln(1+2x), a = 1 + x v.  Then Newton in v, safeguarded
-// by a bisection bracket.  A step below 1e-8 v is accepted and ends the
-// iteration: the error after it is C v (1e-8)^2 with C = |f'/2f| v <= O(1)
-// for the Klein-Nishina density, i.e. at round-off.  An exact zero residual
-// ends it too.
+// F ~ ln((1+2x)/a) / ln(1+2x), a = 1 + x v.  Then Halley's iteration in v
+// (slope: the density f; curvature: f' in closed form), safeguarded by a
+// bisection bracket, falling back to a Newton step if Halley's denominator
+// is not positive.  A step below 1e-8 v is accepted and ends the iteration:
+// the error after it is far below round-off (cubic convergence; even the
+// Newton fallback leaves C v (1e-8)^2 with C = |f'/2f| v <= O(1)).  An exact
+// zero residual ends it too.  Only the residual (the tail series or closed
+// form) decides where the iteration lands, so the step sizes use reciprocal
+// estimates refined to about an ulp.
 __device__ __forceinline__ double angle_icdf_v(double u, double x) {
     const double Z = (8.0 / 3.0) * sigma_ratio(x);
     const double target = (1.0 - u) * Z;  // 1 - u is exact for u = k 2^-53
@@ -267,7 +309,14 @@ __device__ __forceinline__ double angle_icdf_v(double u, double x) {
             hi = v;
         else
             lo = v;
-        double next = v - R / angle_density_v(v, x);
+        // Halley step on the tail: slope f (the density) and curvature f'
+        const double ia = recip_approx(1.0 + x * v);
+        const double ia2 = ia * ia, ia3 = ia2 * ia;
+        const double w = v * (2.0 - v);
+        const double f = ia3 + ia - w * ia2;
+        const double fp = -3.0 * x * ia3 * ia - x * ia2 - (2.0 - 2.0 * v) * ia2 + 2.0 * x * w * ia3;
+        const double den = 2.0 * f * f - R * fp;
+        double next = den > 0.0 ? v - 2.0 * R * f * recip_approx(den) : v - R * recip_approx(f);
         if (fabs(next - v) <= 1e-8 * next) {
             v = next;
             break;
