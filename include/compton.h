@@ -256,9 +256,12 @@ typedef enum {
 
 typedef enum {
     CS_OPT_STRATEGY = 0,         /* a cs_strategy                                        */
-    CS_OPT_CHUNKS_PER_BLOCK = 1, /* fused: 256-pair chunks per workgroup, 0 = automatic  */
-    CS_OPT_PAIRS_PER_LANE = 2    /* compact: pairs each lane of the pair kernel takes    */
-                                 /* (1, 2 or 4), 0 = automatic                            */
+    CS_OPT_CHUNKS_PER_BLOCK = 1, /* fused: 256-pair chunks per workgroup; compact: the  */
+                                 /* pair kernel's chunks per workgroup (rounded up to a  */
+                                 /* multiple of the pairs per lane, at most 16);         */
+                                 /* 0 = automatic                                        */
+    CS_OPT_PAIRS_PER_LANE = 2    /* compact: chunks each lane of the pair kernel takes   */
+                                 /* at a time (1, 2 or 4), 0 = automatic (1)             */
 } cs_option;
 
 /* Set / read a context option.  CS_ERR_INVALID_ARG for unknown options or

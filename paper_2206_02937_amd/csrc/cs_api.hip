@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <algorithm>
+#include <utility>
 #include <new>
 #include <string>
 #include <vector>
@@ -215,7 +216,7 @@ Plan plan_step(int64_t strategy, int64_t chunks_per_block, int64_t pairs_per_lan
     sh.chunks_per_block = G;
     sh.n_step_blocks = sh.n_chunks > 0 ? (sh.n_chunks + G - 1) / G : 1;
     sh.n_prep_blocks = cs::fused_prep_blocks(n_cells);
-    sh.pairs_per_lane = pairs_per_lane == 1 || pairs_per_lane == 2 || pairs_per_lane == 4 ? pairs_per_lane : 4;
+    sh.pairs_per_lane = pairs_per_lane == 1 || pairs_per_lane == 2 || pairs_per_lane == 4 ? pairs_per_lane : 1;
     // dense collide grid: one lane per accepted pair at most, capped (2048
     // one-wave workgroups, or 512 four-wave workgroups that each load the
     // network's LDS copy)
@@ -230,6 +231,17 @@ Plan plan_step(int64_t strategy, int64_t chunks_per_block, int64_t pairs_per_lan
         sh.n_step_blocks = n_cells > 0 ? n_cells : 1;
         pl.bytes = cs::fused_workspace_bytes(sh);
     } else if (strategy == CS_STRATEGY_COMPACT) {
+        // pair workgroups take G consecutive chunks, a multiple of the pairs
+        // per lane and at most kCompactMaxChunks (LDS staging of the
+        // accepted pairs); automatic: about 2048 workgroups (two rounds at
+        // the pair kernel's occupancy on a 256-CU device, so that the second
+        // round fills the SIMDs the first one leaves)
+        const int64_t ppl = sh.pairs_per_lane;
+        int64_t Gc = chunks_per_block > 0 ? chunks_per_block : sh.n_chunks / 2048;
+        Gc = (Gc + ppl - 1) / ppl * ppl;
+        if (Gc < ppl) Gc = ppl;
+        if (Gc > cs::kCompactMaxChunks) Gc = cs::kCompactMaxChunks;
+        sh.chunks_per_block = Gc;
         sh.n_collide_blocks = sh.n_dense_blocks;
         pl.bytes = cs::compact_workspace_bytes(sh);
         pl.status_words += cs::compact_pair_blocks(sh);
@@ -466,15 +478,16 @@ cs_status cs_autotune(cs_ctx* ctx, cs_dtype dtype, cs_species electrons, cs_spec
     };
     int32_t cand_s[CS_TUNE_MAX], cand_g[CS_TUNE_MAX], cand_p[CS_TUNE_MAX];
     int n_cand = 0;
-    for (int gpb : {1, 2, 4, 8, 16, 32}) {
+    for (int gpb : {4, 8, 16, 32}) {
         cand_s[n_cand] = CS_STRATEGY_FUSED;
         cand_p[n_cand] = 0;
         cand_g[n_cand++] = gpb;
     }
-    for (int ppl : {1, 2, 4}) {
+    // compact: (pairs per lane, chunks per pair workgroup)
+    for (const auto& pg : {std::pair<int, int>{1, 4}, {1, 8}, {1, 16}, {2, 8}, {2, 16}}) {
         cand_s[n_cand] = CS_STRATEGY_COMPACT;
-        cand_p[n_cand] = ppl;
-        cand_g[n_cand++] = 0;
+        cand_p[n_cand] = pg.first;
+        cand_g[n_cand++] = pg.second;
     }
     float ms_best = 0.f;
     int best = -1;

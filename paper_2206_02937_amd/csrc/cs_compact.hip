@@ -1,12 +1,13 @@
 // cs_compact.hip -- the step as four kernels (default strategy):
 //
 //   k_prep_scan       (cs_fused.hip) cells -> pair offsets, keys, chunk map
-//   k_pair_compact    one lane per pair, one workgroup per 256-pair chunk:
-//                     pairing, x, s(x), P, accept; the accepted pairs of the
-//                     chunk get their global position by decoupled look-back
-//                     over the chunks, so the list of accepted pairs is dense
-//                     and in pair order with no atomics.  Lean (no sampler),
-//                     so it runs at full occupancy.
+//   k_pair_compact    one lane per pair, each workgroup loops over G
+//                     consecutive 256-pair chunks: pairing, x, s(x), P,
+//                     accept; the workgroup's accepted pairs, staged in LDS,
+//                     get their global position by decoupled look-back over
+//                     the workgroups, so the list of accepted pairs is dense
+//                     and in a fixed order with no atomics.  Lean (no
+//                     sampler), so it runs at high occupancy.
 //   k_collide_dense   workgroups stride over the dense list: sample the
 //                     angle, scatter, write back (one wave per workgroup with
 //                     the plain sampler; four waves sharing the network's LDS
@@ -30,6 +31,7 @@ struct CompactArgs {
     Particles<T> pt;
     const int64_t *off_e, *off_g;
     int64_t n_cells, n_chunks;
+    int32_t chunks_per_block;  // pair kernel: consecutive chunks per workgroup
     const int32_t* pair_off;
     const uint32_t* keys;
     const int32_t* chunk_cell;
@@ -48,15 +50,88 @@ struct CompactArgs {
     MlpDev mlp;
 };
 
-// One workgroup takes PPL consecutive 256-pair chunks, one pair of each per
-// lane.  The phases run for all PPL pairs before the next phase starts --
-// find the cell, read its offsets and key; pair; read the particles; the
-// physics -- so that each lane has PPL independent memory accesses in flight
-// instead of one.  The accepted pairs of the PPL chunks (in pair order) take
-// their place in the global list with one look-back per workgroup.
+// Phases 1 and 2 of one step of the pair kernel for one lane: the pairs of
+// chunks j0 .. j0 + PPL - 1 (one pair of each), their cells, particle ranges
+// and pairing keys, the pairing, and the particle reads -- issued, to be
+// consumed a step later.  The chunk's first cell is the same for the whole
+// wave: its metadata come by scalar loads; lanes whose pair lies in a later
+// cell of the chunk find it by binary search and read its metadata.  `cc`
+// holds chunk_cell[blk G + lane]; c0 is the step's first chunk relative to
+// blk G.  valid == false (uniform) yields inactive slots.
+// s_waitcnt immediate that waits for vmcnt 0 only (gfx9 encoding: vmcnt in
+// bits 3:0 and 15:14, expcnt 6:4 and lgkmcnt 11:8 at their maxima).
+constexpr int kWaitVmcnt0 = 0x0F70;
+
+// Read-only data at a wave-uniform index through the constant address space,
+// so that the read is one scalar load (the data do not change while the
+// kernel runs).
+template <typename X>
+__device__ __forceinline__ X ld_uniform(const X* p, int64_t i) {
+    return ((const __attribute__((address_space(4))) X*)p)[i];
+}
+
+template <typename T, int PPL>
+__device__ __forceinline__ void pair_fetch(const CompactArgs<T>& a, bool valid, int64_t j0, int c0, int cc,
+                                           int32_t T_total, int tid, PairSlot (&sl)[PPL],
+                                           PairRaw<T> (&raw)[PPL]) {
+#pragma unroll
+    for (int q = 0; q < PPL; ++q) {
+        const int64_t j = j0 + q;
+        const int32_t t = (int32_t)(j * kChunk) + tid;
+        const bool jv = valid && j < a.n_chunks && j * kChunk < (int64_t)T_total;  // uniform
+        const bool act = jv && t < T_total;
+        int64_t e0 = 0, e1 = 0, g0 = 0, g1 = 0;
+        uint4 key = make_uint4(0, 0, 0, 0);
+        int32_t po = 0, po_next = 0;
+        if (jv) {
+            const int cs0 = __builtin_amdgcn_readlane(cc, c0 + q);
+            e0 = ld_uniform(a.off_e, cs0);
+            e1 = ld_uniform(a.off_e, cs0 + 1);
+            g0 = ld_uniform(a.off_g, cs0);
+            g1 = ld_uniform(a.off_g, cs0 + 1);
+            key = make_uint4(ld_uniform(a.keys, 4 * cs0), ld_uniform(a.keys, 4 * cs0 + 1),
+                             ld_uniform(a.keys, 4 * cs0 + 2), ld_uniform(a.keys, 4 * cs0 + 3));
+            po = ld_uniform(a.pair_off, cs0);
+            po_next = ld_uniform(a.pair_off, cs0 + 1);
+            if (act && t >= po_next) {
+                int lo = cs0 + 1, hi = __builtin_amdgcn_readlane(cc, c0 + q + 1);
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (a.pair_off[mid] <= t)
+                        lo = mid;
+                    else
+                        hi = mid - 1;
+                }
+                e0 = a.off_e[lo];
+                e1 = a.off_e[lo + 1];
+                g0 = a.off_g[lo];
+                g1 = a.off_g[lo + 1];
+                key = *(const uint4*)(a.keys + 4 * lo);
+                po = a.pair_off[lo];
+                // complete these reads inside the branch, so that no read of
+                // it is still counted as possibly in flight after it (which
+                // would make later waits include the particle reads)
+                __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+            }
+        }
+        sl[q] = pair_index(act, e0, e1, g0, g1, key.x, key.y, key.z, key.w, (uint32_t)(t - po));
+        raw[q] = pair_load_all<T>(a.pt, sl[q]);
+    }
+}
+
+// One workgroup takes G consecutive 256-pair chunks, PPL of them per step
+// (one pair of each per lane).  Software pipeline: the pairing and particle
+// reads of step s + 1 are issued before the physics of step s, so their
+// latency hides behind it (the physics reads nothing from global memory:
+// the s(x) table is copied to LDS first).  Accepted pairs are staged in LDS,
+// per wave in the order the wave meets them; after the last step the
+// workgroup's list (wave 0's pairs, then wave 1's, ...) takes its place in
+// the global list with one look-back.
 template <typename T, int PPL>
 __global__ __launch_bounds__(kChunk) void k_pair_compact(const CompactArgs<T> a) {
-    __shared__ int s_wcnt[PPL][kChunk / 64];
+    extern __shared__ int2 s_stage[];  // [kChunk / 64][64 G]
+    __shared__ double s_sig[kSigTabSegments * kSigTabTerms];
+    __shared__ int s_wcnt[kChunk / 64];
     __shared__ int s_prefix;
     __shared__ double s_rd[kChunk / 64];
     __shared__ long long s_ri[2 * (kChunk / 64)];
@@ -64,75 +139,54 @@ __global__ __launch_bounds__(kChunk) void k_pair_compact(const CompactArgs<T> a)
     const int lane = lane_id();
     const int wave = tid >> 6;
     const int64_t blk = blockIdx.x;
+    const int G = a.chunks_per_block;
+    for (int i = tid; i < kSigTabSegments * kSigTabTerms; i += kChunk) s_sig[i] = kSigTab[i];
     StepControl* ctrl = a.ctrl;
     const uint32_t E = ctrl->epoch;
     const uint64_t step = ctrl->step;
     const bool layout_ok = ctrl->layout_epoch != E && ctrl->scan_fault_epoch != E;
     const int32_t T_total = layout_ok ? a.pair_off[a.n_cells] : 0;
-    // phase 1: cell of each pair (binary search over the chunk's cells),
-    // then the cell's particle ranges and pairing key
-    int32_t t[PPL];
-    int c[PPL];
-    bool act[PPL];
-#pragma unroll
-    for (int q = 0; q < PPL; ++q) {
-        const int64_t j = blk * PPL + q;
-        t[q] = (int32_t)(j * kChunk) + tid;
-        act[q] = j < a.n_chunks && t[q] < T_total;
-        c[q] = 0;
-        if (act[q]) {
-            int lo = a.chunk_cell[j], hi = a.chunk_cell[j + 1];
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (a.pair_off[mid] <= t[q])
-                    lo = mid;
-                else
-                    hi = mid - 1;
-            }
-            c[q] = lo;
-        }
-    }
-    int64_t e0[PPL], e1[PPL], g0[PPL], g1[PPL];
-    uint4 key[PPL];
-    int32_t po[PPL];
-#pragma unroll
-    for (int q = 0; q < PPL; ++q) {
-        e0[q] = e1[q] = g0[q] = g1[q] = 0;
-        key[q] = make_uint4(0, 0, 0, 0);
-        po[q] = 0;
-        if (act[q]) {
-            e0[q] = a.off_e[c[q]];
-            e1[q] = a.off_e[c[q] + 1];
-            g0[q] = a.off_g[c[q]];
-            g1[q] = a.off_g[c[q] + 1];
-            key[q] = *(const uint4*)(a.keys + 4 * c[q]);
-            po[q] = a.pair_off[c[q]];
-        }
-    }
-    // phase 2: pairing and the particle reads
-    PairSlot sl[PPL];
-    PairRaw<T> raw[PPL];
-#pragma unroll
-    for (int q = 0; q < PPL; ++q)
-        sl[q] = pair_index(act[q], e0[q], e1[q], g0[q], g1[q], key[q].x, key[q].y, key[q].z, key[q].w,
-                           (uint32_t)(t[q] - po[q]));
-#pragma unroll
-    for (int q = 0; q < PPL; ++q) raw[q] = pair_load<T>(a.pt, sl[q]);
-    // phase 3: physics, per-chunk ballots
+    // chunk_cell of the workgroup's chunks and of the one after them, lane i
+    // holding entry blk G + i (G < 64)
+    const int64_t jc = blk * G + lane;
+    const int cc = lane <= G && jc <= a.n_chunks ? a.chunk_cell[jc] : 0;
+    // steps of this workgroup: its chunks below min(n_chunks, ceil(T / kChunk))
+    int64_t n_used = ((int64_t)T_total + kChunk - 1) / kChunk;
+    if (n_used > a.n_chunks) n_used = a.n_chunks;
+    int64_t n_mine = n_used - blk * G;
+    n_mine = n_mine < 0 ? 0 : (n_mine > G ? G : n_mine);
+    const int n_steps = (int)((n_mine + PPL - 1) / PPL);
+    int2* stage = s_stage + (int64_t)wave * 64 * G;
+    int n_stage = 0;  // wave-uniform
+    const uint64_t lanes_below = (1ull << lane) - 1ull;
     double sum_p = 0.0;
     long long n_clip = 0, n_inv = 0;
-    bool acc[PPL];
-    int before[PPL];
+    // physics of one step; accepted pairs go to the wave's staging list
+    auto physics = [&](const PairSlot(&sl)[PPL], const PairRaw<T>(&raw)[PPL]) {
 #pragma unroll
-    for (int q = 0; q < PPL; ++q) {
-        const PairOutcome o = pair_physics<T>(sl[q], raw[q], a.dt, a.density_norm, a.seed, step);
-        sum_p += o.P;
-        n_clip += o.clipped ? 1 : 0;
-        n_inv += o.invalid ? 1 : 0;
-        acc[q] = o.accept;
-        const uint64_t mask = __ballot(o.accept);
-        before[q] = __popcll(mask & ((1ull << lane) - 1ull));
-        if (lane == 0) s_wcnt[q][wave] = __popcll(mask);
+        for (int q = 0; q < PPL; ++q) {
+            const PairOutcome o = pair_physics<T>(sl[q], raw[q], a.dt, a.density_norm, a.seed, step, s_sig);
+            sum_p += o.P;
+            n_clip += o.clipped ? 1 : 0;
+            n_inv += o.invalid ? 1 : 0;
+            const uint64_t mask = __ballot(o.accept);
+            if (o.accept) stage[n_stage + __popcll(mask & lanes_below)] = make_int2(sl[q].ie, sl[q].ig);
+            n_stage += __popcll(mask);
+        }
+    };
+    // two register sets in turn (no copies, which would wait for the reads)
+    PairSlot sl_a[PPL], sl_b[PPL];
+    PairRaw<T> raw_a[PPL], raw_b[PPL];
+    pair_fetch<T, PPL>(a, n_steps > 0, blk * G, 0, cc, T_total, tid, sl_a, raw_a);
+    __syncthreads();  // s_sig
+    for (int st = 0; st < n_steps; st += 2) {
+        pair_fetch<T, PPL>(a, st + 1 < n_steps, blk * G + (st + 1) * PPL, (st + 1) * PPL, cc, T_total, tid, sl_b,
+                           raw_b);
+        physics(sl_a, raw_a);
+        if (st + 1 >= n_steps) break;
+        pair_fetch<T, PPL>(a, st + 2 < n_steps, blk * G + (st + 2) * PPL, (st + 2) * PPL, cc, T_total, tid, sl_a,
+                           raw_a);
+        physics(sl_b, raw_b);
     }
     const double wp = wave_sum(sum_p);
     const long long wc = wave_sum_i(n_clip), wi = wave_sum_i(n_inv);
@@ -140,22 +194,14 @@ __global__ __launch_bounds__(kChunk) void k_pair_compact(const CompactArgs<T> a)
         s_rd[wave] = wp;
         s_ri[2 * wave] = wc;
         s_ri[2 * wave + 1] = wi;
+        s_wcnt[wave] = n_stage;
     }
     __syncthreads();
-    // position of this lane's accepted pairs within the workgroup's list:
-    // chunk-major, then wave, then lane (pair order)
-    int base[PPL];
-    int total = 0;
+    int wbase = 0, total = 0;
 #pragma unroll
-    for (int q = 0; q < PPL; ++q) {
-        int wb = 0, tq = 0;
-#pragma unroll
-        for (int w = 0; w < kChunk / 64; ++w) {
-            wb += w < wave ? s_wcnt[q][w] : 0;
-            tq += s_wcnt[q][w];
-        }
-        base[q] = total + wb + before[q];
-        total += tq;
+    for (int w = 0; w < kChunk / 64; ++w) {
+        wbase += w < wave ? s_wcnt[w] : 0;
+        total += s_wcnt[w];
     }
     if (tid < 64) {
         const uint32_t ex = lookback_exclusive_wave(a.status, blk, E, (uint32_t)total, &ctrl->scan_fault_epoch);
@@ -174,11 +220,9 @@ __global__ __launch_bounds__(kChunk) void k_pair_compact(const CompactArgs<T> a)
         a.chunk_inv[blk] = in;
     }
     __syncthreads();
-    const int prefix = s_prefix;
-#pragma unroll
-    for (int q = 0; q < PPL; ++q)
-        if (acc[q]) a.list[prefix + base[q]] = make_int2(sl[q].ie, sl[q].ig);
-    if (tid == 0 && blk == (int64_t)gridDim.x - 1) ctrl->n_accepted = (uint32_t)(prefix + total);
+    int2* dst = a.list + s_prefix + wbase;
+    for (int i = lane; i < n_stage; i += 64) dst[i] = stage[i];
+    if (tid == 0 && blk == (int64_t)gridDim.x - 1) ctrl->n_accepted = (uint32_t)(s_prefix + total);
 }
 
 // Network samplers defer the pairs outside the network's domain: their list
@@ -284,9 +328,11 @@ __global__ __launch_bounds__(SAMP == CS_SAMPLER_PLAIN ? kDenseThreads : kDenseNe
 static size_t al(size_t v) { return (v + 255) & ~(size_t)255; }
 
 int64_t compact_pair_blocks(const StepShape& s) {
-    const int64_t ppl = s.pairs_per_lane;
-    return s.n_chunks > 0 ? (s.n_chunks + ppl - 1) / ppl : 0;
+    const int64_t G = s.chunks_per_block;
+    return s.n_chunks > 0 ? (s.n_chunks + G - 1) / G : 0;
 }
+
+size_t compact_stage_bytes(int64_t chunks_per_block) { return sizeof(int2) * kChunk * (size_t)chunks_per_block; }
 
 size_t compact_workspace_bytes(const StepShape& s) {
     size_t b = 0;
@@ -336,6 +382,7 @@ static hipError_t launch_compact_t(const StepShape& sh, const CompactBuffers& b,
     a.off_g = p.off_g;
     a.n_cells = sh.n_cells;
     a.n_chunks = sh.n_chunks;
+    a.chunks_per_block = (int32_t)sh.chunks_per_block;
     a.pair_off = b.pair_off;
     a.keys = b.cell_keys;
     a.chunk_cell = b.chunk_cell;
@@ -355,12 +402,13 @@ static hipError_t launch_compact_t(const StepShape& sh, const CompactBuffers& b,
     a.mlp = p.net;
     const int64_t n_pair_blocks = compact_pair_blocks(sh);
     if (sh.n_chunks > 0) {
+        const size_t lds = compact_stage_bytes(sh.chunks_per_block);
         if (sh.pairs_per_lane == 1)
-            k_pair_compact<T, 1><<<(unsigned)n_pair_blocks, kChunk, 0, st>>>(a);
+            k_pair_compact<T, 1><<<(unsigned)n_pair_blocks, kChunk, lds, st>>>(a);
         else if (sh.pairs_per_lane == 2)
-            k_pair_compact<T, 2><<<(unsigned)n_pair_blocks, kChunk, 0, st>>>(a);
+            k_pair_compact<T, 2><<<(unsigned)n_pair_blocks, kChunk, lds, st>>>(a);
         else
-            k_pair_compact<T, 4><<<(unsigned)n_pair_blocks, kChunk, 0, st>>>(a);
+            k_pair_compact<T, 4><<<(unsigned)n_pair_blocks, kChunk, lds, st>>>(a);
     }
     mark(2);
     mark(3);

@@ -213,13 +213,15 @@ __device__ __forceinline__ double tail_series(const TailCoeffs* T, double t, dou
 // s(x) = sigma_KN(x) / sigma_T.  Below 2: the per-segment Taylor polynomial
 // of cs_sigma_table.h, evaluated per lane (each lane loads its own segment's
 // 12 coefficients; no lane waits for another's branch).  From 2 up: the
-// closed form with log1p, where its terms no longer cancel.
-__device__ __forceinline__ double sigma_ratio(double x) {
+// closed form with log1p, where its terms no longer cancel.  `tab` is
+// kSigTab or a copy of it (e.g. in LDS): the same coefficients, the same
+// result.
+__device__ __forceinline__ double sigma_ratio_tab(double x, const double* tab) {
     if (x < kSigTabMax) {
         int j = (int)(x * kSigTabInvWidth);
         j = j < 0 ? 0 : (j > kSigTabSegments - 1 ? kSigTabSegments - 1 : j);
         const double t = x - ((double)j + 0.5) / kSigTabInvWidth;
-        const double* a = kSigTab + j * kSigTabTerms;
+        const double* a = tab + j * kSigTabTerms;
         double acc = a[kSigTabTerms - 1];
 #pragma unroll
         for (int n = kSigTabTerms - 2; n >= 0; --n) acc = fma(acc, t, a[n]);
@@ -229,6 +231,8 @@ __device__ __forceinline__ double sigma_ratio(double x) {
     const double opx = 1.0 + x, o2x = 1.0 + 2.0 * x;
     return 0.75 * (opx / (x * x * x) * (2.0 * x * opx / o2x - l) + l / (2.0 * x) - (1.0 + 3.0 * x) / (o2x * o2x));
 }
+
+__device__ __forceinline__ double sigma_ratio(double x) { return sigma_ratio_tab(x, kSigTab); }
 
 // Unnormalised angular density f at mu = 1 - v, for x >= 0.
 __device__ __forceinline__ double angle_density_v(double v, double x) {
@@ -335,38 +339,49 @@ struct d3 {
     double x, y, z;
 };
 
-__device__ __forceinline__ double dot(d3 a, d3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ double dot(d3 a, d3 b) { return fma(a.x, b.x, fma(a.y, b.y, a.z * b.z)); }
 __device__ __forceinline__ d3 cross(d3 a, d3 b) {
-    return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+    return {fma(a.y, b.z, -(a.z * b.y)), fma(a.z, b.x, -(a.x * b.z)), fma(a.x, b.y, -(a.y * b.x))};
 }
 __device__ __forceinline__ d3 axpy(double a, d3 x, d3 y) { return {fma(a, x.x, y.x), fma(a, x.y, y.y), fma(a, x.z, y.z)}; }
 __device__ __forceinline__ d3 scale(double a, d3 x) { return {a * x.x, a * x.y, a * x.z}; }
 
-struct PairInv {
-    double gamma, eps, x, flux;  // x = gamma eps - p.k (rest-frame photon energy)
+struct XFlux {
+    double x, flux;  // rest-frame photon energy x = gamma eps - p.k, flux = x / (gamma eps)
 };
 
-// x = gamma eps - p.k; for p.k > 0 use x = (eps^2 + |p x k|^2)/(gamma eps + p.k)
-// (gamma^2 eps^2 - (p.k)^2 = eps^2 + |p x k|^2), which has no cancellation.
-// flux = 1 - beta . k_hat = x / (gamma eps).
-__device__ __forceinline__ PairInv pair_invariants(d3 p, d3 k) {
-    PairInv r;
-    r.gamma = sqrt(1.0 + dot(p, p));
-    r.eps = sqrt(dot(k, k));
-    if (r.eps == 0.0) {
-        r.x = 0.0;
-        r.flux = 0.0;
-        return r;
-    }
+// gamma eps = sqrt((1 + p.p) k.k) (one square root); x = gamma eps - p.k, and
+// for p.k > 0 the cancellation-free x = (k.k + |p x k|^2) / (gamma eps + p.k)
+// (gamma^2 eps^2 - (p.k)^2 = eps^2 + |p x k|^2).  Both cases share one
+// division: flux = num / den with (num, den) = (gamma eps - p.k, gamma eps),
+// resp. (k.k + |p x k|^2, gamma eps (gamma eps + p.k)), and then x = flux
+// gamma eps in the second case.  pp = p.p, kk = k.k.
+__device__ __forceinline__ XFlux x_flux(d3 p, d3 k, double pp, double kk) {
+    if (kk == 0.0) return {0.0, 0.0};
+    const double ge = sqrt((1.0 + pp) * kk);
     const double pk = dot(p, k);
-    const double ge = r.gamma * r.eps;
-    if (pk <= 0.0) {
-        r.x = ge - pk;
-    } else {
-        const d3 c = cross(p, k);
-        r.x = (r.eps * r.eps + dot(c, c)) / (ge + pk);
-    }
-    r.flux = r.x / ge;
+    const bool fwd = pk > 0.0;
+    const d3 c = cross(p, k);
+    const double num = fwd ? kk + dot(c, c) : ge - pk;
+    const double den = fwd ? ge * (ge + pk) : ge;
+    XFlux r;
+    r.flux = num / den;
+    r.x = fwd ? r.flux * ge : num;
+    return r;
+}
+
+struct PairInv {
+    double gamma, eps, x, flux;
+};
+
+__device__ __forceinline__ PairInv pair_invariants(d3 p, d3 k) {
+    const double pp = dot(p, p), kk = dot(k, k);
+    const XFlux xf = x_flux(p, k, pp, kk);
+    PairInv r;
+    r.gamma = sqrt(1.0 + pp);
+    r.eps = sqrt(kk);
+    r.x = xf.x;
+    r.flux = xf.flux;
     return r;
 }
 

@@ -13,6 +13,7 @@
 namespace cs {
 
 constexpr int kChunk = 256;       // pairs per workgroup of the pair kernel
+constexpr int64_t kCompactMaxChunks = 16;  // compact pair kernel: chunks per workgroup (LDS staging)
 constexpr int64_t kTimingRing = 512;  // steps whose stage events are kept
 constexpr int kScanItems = 1024;  // items per workgroup of the scan kernels
 
@@ -75,11 +76,11 @@ struct StepShape {
     int64_t n_chunks;          // ceil(min(ne, ng) / kChunk): upper bound of used chunks
     int64_t n_collide_blocks;  // multi-kernel: fixed grid of the collide kernel
     int64_t scan_tmp_len;      // multi-kernel: scan scratch
-    int64_t chunks_per_block;  // fused: consecutive chunks per workgroup
+    int64_t chunks_per_block;  // fused / compact pair kernel: consecutive chunks per workgroup
     int64_t n_step_blocks;     // fused: grid of k_step (>= 1)
     int64_t n_prep_blocks;     // fused / compact: grid of k_prep_scan
     int64_t n_dense_blocks;    // compact: grid of the one-wave collide kernel
-    int64_t pairs_per_lane;    // compact: 256-pair chunks per pair workgroup (1, 2, 4)
+    int64_t pairs_per_lane;    // compact: chunks each pair-kernel lane takes at a time (1, 2, 4)
 };
 
 // Per-workgroup partial sums of the fused step.
@@ -106,7 +107,7 @@ struct CompactBuffers {
     int32_t* pair_off;    // [n_cells + 1]
     uint32_t* cell_keys;  // [4 n_cells]
     int32_t* chunk_cell;  // [n_chunks + 1]
-    int2* list;           // [n_chunks * kChunk] accepted pairs, dense, pair order
+    int2* list;           // [n_chunks * kChunk] accepted pairs, dense (workgroup, wave, pair order)
     double* chunk_prob;   // [n_chunks]
     int64_t* chunk_clip;  // [n_chunks]
     int64_t* chunk_inv;   // [n_chunks]

@@ -59,7 +59,9 @@ __device__ __forceinline__ uint32_t lookback_exclusive(uint64_t* status, int64_t
 // Wave-wide variant: called by all 64 lanes of one wave of workgroup `idx`.
 // Lane l reads the status word of predecessor idx-1-l, so each round trip to
 // memory covers 64 predecessors (cross-die atomic latency dominates a walk
-// that reads one word at a time).  Returns the exclusive prefix in every lane.
+// that reads one word at a time).  A window is complete once every
+// predecessor up to the nearest inclusive prefix in it has published; the
+// older ones are not needed.  Returns the exclusive prefix in every lane.
 __device__ __forceinline__ uint32_t lookback_exclusive_wave(uint64_t* status, int64_t idx, uint32_t E,
                                                             uint32_t aggregate, uint32_t* fault) {
     const uint32_t Et = E & 0x3FFFFFFFu;
@@ -77,7 +79,11 @@ __device__ __forceinline__ uint32_t lookback_exclusive_wave(uint64_t* status, in
                                   : pack_status(E, kFlagPrefix, 0);
         const uint64_t fl = (w >> 32) & 3u;
         const bool ready = (uint32_t)(w >> 34) == Et && fl != 0;
-        if (!__all(ready)) {
+        const uint64_t rm = __ballot(ready);
+        const uint64_t pm = __ballot(ready && fl == kFlagPrefix);
+        const int first = pm ? (int)__ffsll((unsigned long long)pm) - 1 : 63;
+        const uint64_t need = first == 63 ? ~0ull : ((2ull << first) - 1ull);  // lanes 0 .. first
+        if ((rm & need) != need) {
             if (++spins > kSpinLimit) {
                 if (lane == 0) atomicMax(fault, E);
                 break;
@@ -85,8 +91,6 @@ __device__ __forceinline__ uint32_t lookback_exclusive_wave(uint64_t* status, in
             __builtin_amdgcn_s_sleep(1);
             continue;
         }
-        const uint64_t pm = __ballot(fl == kFlagPrefix);
-        const int first = pm ? (int)__ffsll((unsigned long long)pm) - 1 : 63;
         uint32_t val = lane <= first ? (uint32_t)w : 0u;
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) val += __shfl_xor(val, off, 64);

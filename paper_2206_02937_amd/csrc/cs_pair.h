@@ -96,9 +96,31 @@ __device__ __forceinline__ PairRaw<T> pair_load(const Particles<T>& a, const Pai
     return r;
 }
 
+// The reads of pair_load issued by every lane: inactive lanes read element 0
+// (which exists whenever a pair does) and leave the values unused (the
+// physics reads them only for active slots), so that the number of reads in
+// flight does not depend on which lanes are active and no lane waits for
+// them before they are used.
+template <typename T>
+__device__ __forceinline__ PairRaw<T> pair_load_all(const Particles<T>& a, const PairSlot& s) {
+    const int32_t ie = s.active ? s.ie : 0, ig = s.active ? s.ig : 0;
+    PairRaw<T> r;
+    r.p[0] = a.ex[ie];
+    r.p[1] = a.ey[ie];
+    r.p[2] = a.ez[ie];
+    r.k[0] = a.gx[ig];
+    r.k[1] = a.gy[ig];
+    r.k[2] = a.gz[ig];
+    r.we = a.ew[ie];
+    r.wg = a.gw[ig];
+    return r;
+}
+
+// `sig_tab`: kSigTab or a copy of it (see sigma_ratio_tab).
 template <typename T>
 __device__ __forceinline__ PairOutcome pair_physics(const PairSlot& s, const PairRaw<T>& r, double dt,
-                                                    double density_norm, uint64_t seed, uint64_t step) {
+                                                    double density_norm, uint64_t seed, uint64_t step,
+                                                    const double* sig_tab = kSigTab) {
     PairOutcome o;
     o.ie = s.ie;
     o.ig = s.ig;
@@ -116,16 +138,16 @@ __device__ __forceinline__ PairOutcome pair_physics(const PairSlot& s, const Pai
         if (!finite_pair(p, we, k, wg)) {
             o.invalid = true;
         } else {
-            const PairInv inv = pair_invariants(p, k);
-            x = inv.x;
-            flux = inv.flux;
+            const XFlux xf = x_flux(p, k, dot(p, p), dot(k, k));
+            x = xf.x;
+            flux = xf.flux;
             tau = dt * density_norm * (double)s.M;
             wmax = we > wg ? we : wg;
             compute = x > 0.0;
         }
     }
     if (compute) {
-        double P = tau * wmax * sigma_ratio(x) * flux;
+        double P = tau * wmax * sigma_ratio_tab(x, sig_tab) * flux;
         if (P > 1.0) {
             o.clipped = true;
             P = 1.0;

@@ -283,8 +283,9 @@ def test_sample_plain_parity(ctx, orc, dtype):
 
 @pytest.mark.parametrize("workload", ["grid_small", "uneven_small", "unequal"])
 def test_strategies_bitwise_identical(ctx, workload):
-    """Every kernel strategy (compact with 1, 2, 4 pairs per lane, fused with
-    several chunks per workgroup, the multi-kernel and per-cell baselines)
+    """Every kernel strategy (compact with 1, 2, 4 pairs per lane and several
+    chunks per pair workgroup, fused with several chunks per workgroup, the
+    multi-kernel and per-cell baselines)
     gives bitwise-identical particles and counters; the
     FP64 sums of the stats differ only by summation order."""
     import torch
@@ -297,14 +298,15 @@ def test_strategies_bitwise_identical(ctx, workload):
         p = plasma.uneven(seed=8, side=40, mean=20, peak=20.0, area_frac=0.05)
     else:
         p = _unequal_plasma(np.float32)
-    # (strategy, chunks per workgroup or pairs per lane)
-    configs = [("compact", 4), ("compact", 1), ("compact", 2), ("fused", 0), ("fused", 1), ("fused", 3),
-               ("fused", 64), ("multi_kernel", 0), ("per_cell", 0)]
+    # (strategy, pairs per lane, chunks per workgroup)
+    configs = [("compact", 4, 0), ("compact", 1, 0), ("compact", 2, 0), ("compact", 1, 16), ("compact", 2, 5),
+               ("compact", 4, 8), ("fused", 0, 0), ("fused", 0, 1), ("fused", 0, 3), ("fused", 0, 64),
+               ("multi_kernel", 0, 0), ("per_cell", 0, 0)]
     results = []
-    for strategy, g in configs:
+    for strategy, ppl, g in configs:
         ctx.set_strategy(strategy)
-        ctx.set_chunks_per_block(g if strategy == "fused" else 0)
-        ctx.set_pairs_per_lane(g if strategy == "compact" else 0)
+        ctx.set_chunks_per_block(g)
+        ctx.set_pairs_per_lane(ppl)
         e_dev, g_dev, oe, og = compton.to_device(p)
         stats = ctx.stats_buffer()
         for s in range(3):
@@ -315,7 +317,7 @@ def test_strategies_bitwise_identical(ctx, workload):
     ctx.set_chunks_per_block(0)
     ctx.set_pairs_per_lane(0)
     e0, g0, s0 = results[0]
-    for (strategy, g), (e1, g1, s1) in zip(configs[1:], results[1:]):
+    for (strategy, _, g), (e1, g1, s1) in zip(configs[1:], results[1:]):
         for k in "xyzw":
             assert np.array_equal(e0[k], e1[k]), (strategy, g, k)
             assert np.array_equal(g0[k], g1[k]), (strategy, g, k)
