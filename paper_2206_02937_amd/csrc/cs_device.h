@@ -25,14 +25,23 @@ struct u32x4 {
     uint32_t a, b, c, d;
 };
 
+// a ^ b ^ c in one v_bitop3_b32 (truth table 0x96); c must be wave-uniform
+// (it is read from a scalar register).
+__device__ __forceinline__ uint32_t xor3_uniform(uint32_t a, uint32_t b, uint32_t c) {
+    uint32_t r;
+    asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(r) : "v"(a), "v"(b), "s"(c));
+    return r;
+}
+
+// The key (k0, k1) must be wave-uniform (it is the seed everywhere here).
 __device__ __forceinline__ u32x4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
                                           uint32_t k1) {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
         const uint64_t m0 = (uint64_t)0xD2511F53u * c0;
         const uint64_t m1 = (uint64_t)0xCD9E8D57u * c2;
-        const uint32_t n0 = (uint32_t)(m1 >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = (uint32_t)(m0 >> 32) ^ c3 ^ k1;
+        const uint32_t n0 = xor3_uniform((uint32_t)(m1 >> 32), c1, k0);
+        const uint32_t n2 = xor3_uniform((uint32_t)(m0 >> 32), c3, k1);
         c1 = (uint32_t)m1;
         c3 = (uint32_t)m0;
         c0 = n0;
@@ -105,30 +114,37 @@ __device__ __forceinline__ uint32_t shuffle_index(uint32_t i, uint32_t M, const 
 // s(x) = (3/8) int_{-1}^{1} f dmu.
 // ---------------------------------------------------------------------------
 
-// Length of the upper-tail series below (t = x v <= 2x < 0.4 in the series
-// branch); the closed form takes over from x = 0.2.
-constexpr int kSeriesTerms = 48;
-constexpr double kSeriesSwitch = 0.2;
+// Upper tail of the angular integral, T(v) = int_{1-v}^{1} f dmu, by the
+// three integrals in w = 1 - mu (a = 1 + x w; z = x v, A = 1 + z):
+//   int a^-3 dw = v (2 + z) / (2 A^2),
+//   int a^-1 dw = log1p(z) / x,
+//   int w (2 - w) a^-2 dw = 2 phi2(z) / x^2 - phi3(z) / x^3,
+//     phi2 = log1p(z) - z / (1 + z),  phi3 = z - 2 log1p(z) + z / (1 + z),
+// and T = first + second - third.  With s = z / (2 + z) (so log1p(z) =
+// 2 atanh(s)) and q = s / x = v / (2 + z), sigma = s^2:
+//   log1p(z) / x = 2 q S1,            S1 = sum_{k>=0} sigma^k / (2k+1),
+//   phi2 / x^2 = q^2 (2 / (1 + s) + s S2),  S2 = sum_{k>=0} 2 sigma^k / (2k+3),
+//   phi3 / x^3 = q^3 S3,              S3 = sum_{k>=0} 8 (k+1) sigma^k / (2k+3).
+// Every term of the three series is positive, so they lose nothing to
+// cancellation at small x (where the closed form loses about 1/x^2 of its
+// precision); they converge like sigma^k with sigma < 1/4 for z < 2.  The
+// series branch serves x < 1; kTailTerms terms reach round-off at sigma
+// just below 1/4, and a wave whose lanes all have a smaller sigma takes
+// fewer (see tail_series).
+constexpr int kTailTerms = 28;
+constexpr double kSeriesSwitch = 1.0;
 
-// Series of the upper tail of the angular integral (v = 1 - mu, t = x v):
-//   int_{mu}^{1} f = v sum_k (-t)^k [ A_k/(k+1) - 2 v (k+1)/(k+2) + v^2 (k+1)/(k+3) ],
-//   A_k = (k+1)(k+2)/2 + 1,
-// from integrating the binomial series of a^-n term by term.  Stored per k as
-// the signed coefficients of 1, v and v^2: the series is A(t) + v B(t) +
-// v^2 C(t) with three polynomials in t.  t <= 2x < 0.4 in the series branch;
-// 48 terms reach round-off.
 struct TailCoeffs {
-    double a[kSeriesTerms], b[kSeriesTerms], c[kSeriesTerms];
+    double s1[kTailTerms], s2[kTailTerms], s3[kTailTerms];
 };
 
 constexpr TailCoeffs tail_series_coeffs() {
     TailCoeffs r{};
-    for (int k = 0; k < kSeriesTerms; ++k) {
+    for (int k = 0; k < kTailTerms; ++k) {
         const double kk = (double)k;
-        const double sgn = (k & 1) ? -1.0 : 1.0;
-        r.a[k] = sgn * (((kk + 1.0) * (kk + 2.0) / 2.0 + 1.0) / (kk + 1.0));
-        r.b[k] = sgn * (-2.0 * (kk + 1.0) / (kk + 2.0));
-        r.c[k] = sgn * ((kk + 1.0) / (kk + 3.0));
+        r.s1[k] = 1.0 / (2.0 * kk + 1.0);
+        r.s2[k] = 2.0 / (2.0 * kk + 3.0);
+        r.s3[k] = 8.0 * (kk + 1.0) / (2.0 * kk + 3.0);
     }
     return r;
 }
@@ -175,39 +191,54 @@ __device__ __forceinline__ double poly_chunked(cdptr c, double t) {
         for (int k = hi - 2; k >= lo; --k) acc = fma_sgpr(acc, t, c[k]);
         part[i] = acc;
     }
-    const double tc = ipow<CH>(t);
-    double r = part[NC - 1];
+    if constexpr (NC == 1) {
+        return part[0];
+    } else {
+        const double tc = ipow<CH>(t);
+        double r = part[NC - 1];
 #pragma unroll
-    for (int i = NC - 2; i >= 0; --i) r = fma(r, tc, part[i]);
-    return r;
+        for (int i = NC - 2; i >= 0; --i) r = fma(r, tc, part[i]);
+        return r;
+    }
 }
 
-// The three tail polynomials over terms [N0, N1) in chunks of CH, returning
-// A + v (B + v C).  The coefficient pointers pass through an empty asm so
-// that the compiler reads the coefficients with scalar loads at each use
-// instead of hoisting whole tables into vector registers across the
-// sampler's iteration.
-template <int N0, int N1, int CH>
-__device__ __forceinline__ double tail_poly(const TailCoeffs* T_generic, double t, double v) {
-    cdptr A = (cdptr)T_generic->a, B = (cdptr)T_generic->b, C = (cdptr)T_generic->c;
-    asm volatile("" : "+s"(A), "+s"(B), "+s"(C));
-    const double pa = poly_chunked<N0, N1, CH>(A, t);
-    const double pb = poly_chunked<N0, N1, CH>(B, t);
-    const double pc = poly_chunked<N0, N1, CH>(C, t);
-    return fma(v, fma(v, pc, pb), pa);
+// 1/a to about an ulp (hardware estimate and two Newton steps).
+__device__ __forceinline__ double recip_approx(double a) {
+    double r = __builtin_amdgcn_rcp(a);
+    r = fma(fma(-a, r, 1.0), r, r);
+    return fma(fma(-a, r, 1.0), r, r);
 }
 
-// A 48-term series split at 14 terms: below t = 0.04 the value is defined as
-// the 14-term sum (the dropped tail is below 2e-19 relative), above it as
-// L + t^14 H.  The wave skips H when none of its lanes needs it.
-constexpr int kLowTerms = 14;
+// T(v) from the three series with N terms each.  The coefficient pointers
+// pass through an empty asm so that the compiler reads the coefficients with
+// scalar loads at each use instead of hoisting whole tables into vector
+// registers across the sampler's iteration.
+template <int N, int CH>
+__device__ __forceinline__ double tail_terms(double v, double z, double A, double s, double q, double sig) {
+    cdptr S1 = (cdptr)kTail.s1, S2 = (cdptr)kTail.s2, S3 = (cdptr)kTail.s3;
+    asm volatile("" : "+s"(S1), "+s"(S2), "+s"(S3));
+    const double p1 = poly_chunked<0, N, CH>(S1, sig);
+    const double p2 = poly_chunked<0, N, CH>(S2, sig);
+    const double p3 = poly_chunked<0, N, CH>(S3, sig);
+    const double iA = recip_approx(A);
+    const double first = 0.5 * v * (2.0 + z) * iA * iA;
+    const double inner = fma(s, p2, 2.0 * recip_approx(1.0 + s));
+    return first + 2.0 * q * p1 - 2.0 * q * q * inner + q * q * q * p3;
+}
 
-__device__ __forceinline__ double tail_series(const TailCoeffs* T, double t, double v) {
-    const double L = tail_poly<0, kLowTerms, 7>(T, t, v);
-    if (__all(t < 0.04)) return L;
-    const double H = tail_poly<kLowTerms, kSeriesTerms, 9>(T, t, v);
-    if (t < 0.04) return L;
-    return fma(ipow<kLowTerms>(t), H, L);
+// Series branch of T(v) for x < kSeriesSwitch.  The wave takes as many terms
+// as its largest sigma needs for the truncated remainder to stay below
+// 1e-17 of the sum: 6 terms up to sigma = 1.5e-3, 12 up to 0.035, 18 up to
+// 0.112, else kTailTerms (sigma < 1/4).
+__device__ __forceinline__ double tail_series(double x, double v) {
+    const double z = x * v;
+    const double r = recip_approx(2.0 + z);
+    const double s = z * r, q = v * r, sig = s * s;
+    const double A = 1.0 + z;
+    if (__all(sig <= 1.5e-3)) return tail_terms<6, 6>(v, z, A, s, q, sig);
+    if (__all(sig <= 0.035)) return tail_terms<12, 6>(v, z, A, s, q, sig);
+    if (__all(sig <= 0.112)) return tail_terms<18, 9>(v, z, A, s, q, sig);
+    return tail_terms<kTailTerms, 14>(v, z, A, s, q, sig);
 }
 
 // s(x) = sigma_KN(x) / sigma_T.  Below 2: the per-segment Taylor polynomial
@@ -241,24 +272,14 @@ __device__ __forceinline__ double angle_density_v(double v, double x) {
     return ia * ia * ia + ia - v * (2.0 - v) * ia * ia;
 }
 
-// 1/a to about an ulp (hardware estimate and two Newton steps): for the
-// iteration's step sizes, whose rounding does not reach the converged root.
-__device__ __forceinline__ double recip_approx(double a) {
-    double r = __builtin_amdgcn_rcp(a);
-    r = fma(fma(-a, r, 1.0), r, r);
-    return fma(fma(-a, r, 1.0), r, r);
-}
 
 // int_{1 - v}^{1} f dmu (upper tail), for 0 <= v <= 2.
-//   series branch (x < 0.2): as above;
+//   series branch (x < kSeriesSwitch): as above;
 //   closed branch: with a = 1 + x v and G' = f in a,
 //   (1/x)[G(a) - G(1)] = (1/x)[ x v (2 + x v) / (2 a^2) + log1p(x v)
 //                        - (-(x v) + (2x+2) log1p(x v) - (2x+1) x v / a) / x^2 ].
 __device__ __forceinline__ double angle_tail(double v, double x) {
-    if (x < kSeriesSwitch) {
-        const double t = x * v;  // <= 2x < 0.4; 14 terms suffice below 0.04
-        return v * tail_series(&kTail, t, v);
-    }
+    if (x < kSeriesSwitch) return tail_series(x, v);
     const double xv = x * v;
     const double a = 1.0 + xv;
     const double L = log1p(xv);
@@ -346,6 +367,31 @@ __device__ __forceinline__ d3 cross(d3 a, d3 b) {
 __device__ __forceinline__ d3 axpy(double a, d3 x, d3 y) { return {fma(a, x.x, y.x), fma(a, x.y, y.y), fma(a, x.z, y.z)}; }
 __device__ __forceinline__ d3 scale(double a, d3 x) { return {a * x.x, a * x.y, a * x.z}; }
 
+// sqrt(a) for a normal, positive a: the hardware reciprocal square root
+// refined by Goldschmidt's iteration with two residual corrections (within
+// about an ulp; no scaling or special-case handling).
+__device__ __forceinline__ double sqrt_normal(double a) {
+    const double y = __builtin_amdgcn_rsq(a);
+    double g = a * y, h = 0.5 * y;
+    const double r = fma(-h, g, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    double d = fma(-g, g, a);
+    g = fma(d, h, g);
+    d = fma(-g, g, a);
+    return fma(d, h, g);
+}
+
+// n / d for normal d: the hardware reciprocal refined by two Newton steps,
+// the quotient, and one residual correction (within about an ulp).
+__device__ __forceinline__ double div_normal(double n, double d) {
+    double r = __builtin_amdgcn_rcp(d);
+    r = fma(fma(-d, r, 1.0), r, r);
+    r = fma(fma(-d, r, 1.0), r, r);
+    const double q = n * r;
+    return fma(fma(-d, q, n), r, q);
+}
+
 struct XFlux {
     double x, flux;  // rest-frame photon energy x = gamma eps - p.k, flux = x / (gamma eps)
 };
@@ -355,19 +401,31 @@ struct XFlux {
 // (gamma^2 eps^2 - (p.k)^2 = eps^2 + |p x k|^2).  Both cases share one
 // division: flux = num / den with (num, den) = (gamma eps - p.k, gamma eps),
 // resp. (k.k + |p x k|^2, gamma eps (gamma eps + p.k)), and then x = flux
-// gamma eps in the second case.  pp = p.p, kk = k.k.
-__device__ __forceinline__ XFlux x_flux(d3 p, d3 k, double pp, double kk) {
-    if (kk == 0.0) return {0.0, 0.0};
-    const double ge = sqrt((1.0 + pp) * kk);
+// gamma eps in the second case.  pp = p.p, kk = k.k.  FAST: the square root
+// and the division are the refined hardware estimates above, valid while
+// their operands are normal numbers.
+template <bool FAST>
+__device__ __forceinline__ XFlux x_flux_impl(d3 p, d3 k, double pp, double kk) {
+    const double a = (1.0 + pp) * kk;
+    const double ge = FAST ? sqrt_normal(a) : sqrt(a);
     const double pk = dot(p, k);
     const bool fwd = pk > 0.0;
     const d3 c = cross(p, k);
     const double num = fwd ? kk + dot(c, c) : ge - pk;
     const double den = fwd ? ge * (ge + pk) : ge;
     XFlux r;
-    r.flux = num / den;
+    r.flux = FAST ? div_normal(num, den) : num / den;
     r.x = fwd ? r.flux * ge : num;
     return r;
+}
+
+// The fast form wherever (1 + p.p) k.k lies in [1e-300, 1e300] (then every
+// operand above is normal); the IEEE square root and division outside.
+__device__ __forceinline__ XFlux x_flux(d3 p, d3 k, double pp, double kk) {
+    if (kk == 0.0) return {0.0, 0.0};
+    const double a = (1.0 + pp) * kk;
+    if (a >= 1e-300 && a <= 1e300) return x_flux_impl<true>(p, k, pp, kk);
+    return x_flux_impl<false>(p, k, pp, kk);
 }
 
 struct PairInv {
