@@ -58,6 +58,41 @@ def parse():
     return ap.parse_args()
 
 
+def source_digest():
+    """16 hex digits of SHA-1 over the kernel sources (csrc/*.hip and *.h in
+    name order, each file's name then its bytes): identifies the kernels a
+    counter record was taken with."""
+    import glob
+    import hashlib
+
+    h = hashlib.sha1()
+    csrc = os.path.join(ROOT, "paper_2206_02937_amd", "csrc")
+    for f in sorted(glob.glob(os.path.join(csrc, "*.hip")) + glob.glob(os.path.join(csrc, "*.h"))):
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_record(kernel, workload):
+    """HBM bytes per launch of `kernel` on `workload` from the FETCH_SIZE /
+    WRITE_SIZE counter summaries under profiles/ ("traffic-record:" lines),
+    scaled by the copy-kernel calibration recorded there; None when no record
+    matches or the kernel sources changed since the counters were taken."""
+    import glob
+
+    digest = source_digest()
+    for f in sorted(glob.glob(os.path.join(ROOT, "profiles", "counters_*.md"))):
+        with open(f) as fh:
+            for line in fh:
+                if not line.startswith("traffic-record:"):
+                    continue
+                kv = dict(t.split("=", 1) for t in line.split()[1:] if "=" in t)
+                if kv.get("kernel") == kernel and kv.get("workload") == workload and kv.get("source_sha") == digest:
+                    return int(kv["bytes_per_launch"])
+    return None
+
+
 def storage_bytes(dtype):
     return 8 if str(dtype).endswith("64") else 4
 
@@ -286,7 +321,8 @@ def main():
             bytes_launch = acc_per_step * (8 + 8 * sb + 6 * sb)
     achieved = bytes_launch / (ms * 1e-3) / 1e9
     roof = {"kernel": kern, "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": achieved / PEAK_HBM_GBS, "traffic": None, "bytes_per_launch": bytes_launch, "avg_ms": ms,
+            "frac": achieved / PEAK_HBM_GBS, "traffic": traffic_record(kern, p.name),
+            "bytes_per_launch": bytes_launch, "avg_ms": ms,
             "units_per_launch": f"{n_pairs} pairs, {acc_per_step} collisions"}
     roof_mlp = None
     if args.sampler in PEAK_MFMA_TFLOPS and args.sampler in ks:
