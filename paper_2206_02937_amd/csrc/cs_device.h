@@ -243,16 +243,27 @@ __device__ __forceinline__ double tail_series(double x, double v) {
 
 // s(x) = sigma_KN(x) / sigma_T.  Below 2: the per-segment Taylor polynomial
 // of cs_sigma_table.h, evaluated per lane (each lane loads its own segment's
-// 12 coefficients; no lane waits for another's branch).  From 2 up: the
-// closed form with log1p, where its terms no longer cancel.  `tab` is
-// kSigTab or a copy of it (e.g. in LDS): the same coefficients, the same
-// result.
+// 12 coefficients; no lane waits for another's branch).  `tab` is kSigTab or
+// a copy of it (e.g. in LDS): the same coefficients, the same result.  From
+// 2 to 2^17 the second table (segment index and centre from the exponent and
+// the top four mantissa bits); above, the closed form with log1p.
 __device__ __forceinline__ double sigma_ratio_tab(double x, const double* tab) {
     if (x < kSigTabMax) {
         int j = (int)(x * kSigTabInvWidth);
         j = j < 0 ? 0 : (j > kSigTabSegments - 1 ? kSigTabSegments - 1 : j);
         const double t = x - ((double)j + 0.5) / kSigTabInvWidth;
         const double* a = tab + j * kSigTabTerms;
+        double acc = a[kSigTabTerms - 1];
+#pragma unroll
+        for (int n = kSigTabTerms - 2; n >= 0; --n) acc = fma(acc, t, a[n]);
+        return acc;
+    }
+    if (x < kSigTabHiMax) {
+        // (hi >> 16) = (1023 + e) << 4 | m for x = 2^e (1 + m/16 + ...)
+        const int hi = __double2hiint(x);
+        const int j = (hi >> 16) - ((1023 + 1) << 4);
+        const double t = x - __hiloint2double((hi & (int)0xFFFF0000) | 0x8000, 0);
+        const double* a = kSigTabHi + j * kSigTabTerms;
         double acc = a[kSigTabTerms - 1];
 #pragma unroll
         for (int n = kSigTabTerms - 2; n >= 0; --n) acc = fma(acc, t, a[n]);

@@ -1,11 +1,13 @@
-"""The device cross-section table (csrc/cs_sigma_table.h, piecewise Taylor
-polynomials of s(x) on [0, 2)) against the oracle's s(x), evaluated on the
-CPU the way the device evaluates it (segment index, local variable, Horner),
-and the header against its generator."""
+"""The device cross-section tables (csrc/cs_sigma_table.h, piecewise Taylor
+polynomials of s(x) on [0, 2) and on [2, 2^17)) against the oracle's s(x),
+evaluated on the CPU the way the device evaluates them (segment index, local
+variable, Horner), and the header against its generator."""
 import os
 import re
 import subprocess
 import sys
+
+import struct
 
 import numpy as np
 
@@ -20,6 +22,28 @@ def load_table():
     body = re.sub(r"//[^\n]*", "", body)
     vals = np.array([float(v) for v in body.replace("\n", " ").split(",") if v.strip()])
     return vals.reshape(64, 12)
+
+
+def load_table_hi():
+    src = open(HDR).read()
+    body = src[src.index("kSigTabHi[3072]"):]
+    body = body[body.index("{") + 1:body.index("};")]
+    body = re.sub(r"//[^\n]*", "", body)
+    vals = np.array([float(v) for v in body.replace("\n", " ").split(",") if v.strip()])
+    return vals.reshape(256, 12)
+
+
+def table_hi_eval(tab, x):
+    """The device's evaluation for 2 <= x < 2^17: segment index and centre
+    from the high word of the double (exponent, top four mantissa bits)."""
+    hi = struct.unpack("<q", struct.pack("<d", x))[0] >> 32
+    j = (hi >> 16) - ((1023 + 1) << 4)
+    c = struct.unpack("<d", struct.pack("<q", ((hi & 0xFFFF0000) | 0x8000) << 32))[0]
+    t = x - c
+    acc = tab[j, 11]
+    for n in range(10, -1, -1):
+        acc = acc * t + tab[j, n]
+    return acc
 
 
 def table_eval(tab, x):
@@ -43,6 +67,21 @@ def test_table_matches_oracle(orc):
     # the table is within ~1e-16 of the closed form (its generator's check);
     # the oracle's series is pinned to 1e-14 and reaches ~1.3e-15 near x = 0.15
     assert rel.max() <= 3e-15, (rel.max(), x[np.argmax(rel)])
+
+
+def test_table_above_two_matches_oracle(orc):
+    tab = load_table_hi()
+    rng = np.random.default_rng(4)
+    x = np.concatenate([2.0 ** rng.uniform(1, 17, 4000), 2.0 ** np.arange(1, 17),
+                        2.0 ** np.arange(2, 18) * (1 - 2 ** -52), [2.0 + 2 ** -51, 3.0, 100.0]])
+    got = np.array([table_hi_eval(tab, float(v)) for v in x])
+    ref = np.array([orc.sigma_ratio(float(v)) for v in x])
+    rel = np.abs(got - ref) / ref
+    assert rel.max() <= 3e-15, (rel.max(), x[np.argmax(rel)])
+    # the segment index covers exactly [2, 2^17)
+    hi_lo = struct.unpack("<q", struct.pack("<d", 2.0))[0] >> 48
+    hi_top = struct.unpack("<q", struct.pack("<d", 2.0 ** 17 * (1 - 2 ** -52)))[0] >> 48
+    assert hi_lo - ((1023 + 1) << 4) == 0 and hi_top - ((1023 + 1) << 4) == 255
 
 
 def test_table_endpoints():
