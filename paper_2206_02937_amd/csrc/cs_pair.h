@@ -219,21 +219,37 @@ __device__ __forceinline__ void write_back(const Particles<T>& a, int32_t ie, in
 
 // Resolve the accepted pair (ie, ig) with the plain sampler and write it back.
 // Lanes with active == false run the sampler on a dummy x = 0 (the quickest
-// case) and write nothing.  The momenta are read again after the sampler so
-// that they are not held in registers across its Newton iteration.
+// case) and write nothing.  The particle values are read once, before the
+// sampler, and kept in their storage type across it (8 registers for FP32).
 template <typename T>
 __device__ __forceinline__ void collide_plain(const Particles<T>& a, bool active, int32_t ie, int32_t ig,
                                               uint64_t seed, uint64_t step, CollideSums& sums) {
+    T raw[8] = {};
+    if (active) {
+        raw[0] = a.ex[ie];
+        raw[1] = a.ey[ie];
+        raw[2] = a.ez[ie];
+        raw[3] = a.gx[ig];
+        raw[4] = a.gy[ig];
+        raw[5] = a.gz[ig];
+        raw[6] = a.ew[ie];
+        raw[7] = a.gw[ig];
+    }
     double x = 0.0;
-    if (active) x = pair_invariants(load_p(a, ie), load_k(a, ig)).x;
+    if (active) {
+        const d3 p = {(double)raw[0], (double)raw[1], (double)raw[2]};
+        const d3 k = {(double)raw[3], (double)raw[4], (double)raw[5]};
+        x = x_flux(p, k, dot(p, p), dot(k, k)).x;
+    }
     const u32x4 r = draw(seed, (uint64_t)ie, step, kScatter);
     const double v = angle_icdf_v(active ? uniform53(r.a, r.b) : 0.5, x);
     if (!active) return;
     const double u_phi = uniform53(r.c, r.d);
-    const d3 p = load_p(a, ie), k = load_k(a, ig);
+    const d3 p = {(double)raw[0], (double)raw[1], (double)raw[2]};
+    const d3 k = {(double)raw[3], (double)raw[4], (double)raw[5]};
     const PairInv inv = pair_invariants(p, k);
     const Scattered s = scatter(p, k, inv, v, u_phi);
-    write_back<T>(a, ie, ig, (double)a.ew[ie], (double)a.gw[ig], s, seed, step);
+    write_back<T>(a, ie, ig, (double)raw[6], (double)raw[7], s, seed, step);
     sums.e_before += s.e_before;
     sums.e_after += s.e_after;
 }
@@ -311,11 +327,10 @@ template <typename T, int SAMP, bool DEFER = false, typename Src>
 __device__ __forceinline__ bool collide_net(const Particles<T>& a, bool active, const Src& src, NetLds<SAMP>& s_net,
                                             const MlpDev& m, uint64_t seed, uint64_t step, CollideSums& sums) {
     double x = 0.0;
-    int32_t ie = 0;
+    int32_t ie = 0, ig = 0;
+    d3 p = {0.0, 0.0, 0.0}, k = {0.0, 0.0, 0.0};
+    double we = 0.0, wg = 0.0;
     if (active) {
-        int32_t ig;
-        d3 p, k;
-        double we, wg;
         src.get(a, ie, ig, p, k, we, wg);
         x = pair_invariants(p, k).x;
     }
@@ -338,10 +353,6 @@ __device__ __forceinline__ bool collide_net(const Particles<T>& a, bool active, 
         if (!active) return false;
     }
     if (inside) v = 1.0 - (double)fminf(fmaxf(mu_hat, -1.0f), 1.0f);
-    int32_t ig;
-    d3 p, k;
-    double we, wg;
-    src.get(a, ie, ig, p, k, we, wg);
     const PairInv inv = pair_invariants(p, k);
     const Scattered s = scatter(p, k, inv, v, uniform53(r.c, r.d));
     write_back<T>(a, ie, ig, we, wg, s, seed, step);
