@@ -98,10 +98,13 @@ void oracle_scatter_uniforms(const int64_t* idx, int64_t n, uint64_t seed, uint6
 
 /* ------------------------------------------------------------------------- */
 /* Pairing: a keyed pseudo-random bijection of [0, M) (the in-cell shuffle).  */
-/* A 4-round balanced Feistel network over 2h bits, 2h >= ceil(log2 M), made  */
-/* a bijection of [0, M) by cycle-walking (Black & Rogaway 2002).  Round r    */
-/* mixes the right half with key word r through the MurmurHash3 32-bit        */
-/* finaliser.  The four key words are the Philox output for                   */
+/* A 4-round Feistel network over b = ceil(log2 M) bits, made a bijection of  */
+/* [0, M) by cycle-walking (Black & Rogaway 2002).  The b bits split into a   */
+/* left part of a = floor(b/2) bits and a right part of c = b - a bits; each  */
+/* round replaces (L, R) by (R, L xor F_r(R)), so the two widths trade places */
+/* every round and are back after four (for even b both halves are b/2 wide).*/
+/* F_r mixes R with key word r through the MurmurHash3 32-bit finaliser and   */
+/* keeps as many bits as L has.  The four key words are the Philox output for */
 /* (index = cell id, step, purpose PAIR).                                      */
 /* ------------------------------------------------------------------------- */
 static uint32_t murmur_fmix32(uint32_t h)
@@ -119,21 +122,24 @@ uint64_t oracle_shuffle_index(uint64_t i, uint64_t M, uint64_t seed, uint64_t ce
     if (M <= 1) return 0;
     int bits = 0;
     while (((uint64_t)1 << bits) < M) ++bits;        /* bits = ceil(log2 M) */
-    int h = (bits + 1) / 2;
-    uint64_t mask = ((uint64_t)1 << h) - 1;
+    const int a = bits / 2, c = bits - a;             /* widths of L and R    */
     uint32_t keys[4];
     draw(seed, cell, step, PURPOSE_PAIR, keys);
     uint64_t v = i;
     do {
-        uint64_t L = v >> h, R = v & mask;
+        uint64_t L = v >> c, R = v & (((uint64_t)1 << c) - 1);
+        int wl = a, wr = c;                           /* current widths       */
         for (int r = 0; r < 4; ++r) {
-            uint64_t f = murmur_fmix32((uint32_t)R ^ keys[r]) & mask;
+            uint64_t f = murmur_fmix32((uint32_t)R ^ keys[r]) & (((uint64_t)1 << wl) - 1);
             uint64_t newL = R;
             uint64_t newR = L ^ f;
             L = newL;
             R = newR;
+            int t = wl;
+            wl = wr;
+            wr = t;
         }
-        v = (L << h) | R;
+        v = (L << c) | R;                              /* wl = a, wr = c again */
     } while (v >= M);
     return v;
 }

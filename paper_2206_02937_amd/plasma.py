@@ -22,7 +22,7 @@ import numpy as np
 # the FP64 reference cross-section (script: tests/golden/derive_dt.py).
 DT_SINGLE_CELL = 0.051594173859536484
 DT_GRID = 0.05284409308615999
-DT_UNEVEN = 0.019673593012240267
+DT_UNEVEN = 0.019678706187464638
 DT_POWERLAW = 0.050011220840244015
 
 
