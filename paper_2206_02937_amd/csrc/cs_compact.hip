@@ -50,14 +50,6 @@ struct CompactArgs {
     MlpDev mlp;
 };
 
-// Phases 1 and 2 of one step of the pair kernel for one lane: the pairs of
-// chunks j0 .. j0 + PPL - 1 (one pair of each), their cells, particle ranges
-// and pairing keys, the pairing, and the particle reads -- issued, to be
-// consumed a step later.  The chunk's first cell is the same for the whole
-// wave: its metadata come by scalar loads; lanes whose pair lies in a later
-// cell of the chunk find it by binary search and read its metadata.  `cc`
-// holds chunk_cell[blk G + lane]; c0 is the step's first chunk relative to
-// blk G.  valid == false (uniform) yields inactive slots.
 // s_waitcnt immediate that waits for vmcnt 0 only (gfx9 encoding: vmcnt in
 // bits 3:0 and 15:14, expcnt 6:4 and lgkmcnt 11:8 at their maxima).
 constexpr int kWaitVmcnt0 = 0x0F70;
@@ -70,6 +62,17 @@ __device__ __forceinline__ X ld_uniform(const X* p, int64_t i) {
     return ((const __attribute__((address_space(4))) X*)p)[i];
 }
 
+// Phases 1 and 2 of one step of the pair kernel for one lane: the pairs of
+// chunks j0 .. j0 + PPL - 1 (one pair of each), their cells, particle ranges
+// and pairing keys, the pairing, and the particle reads -- issued, to be
+// consumed a step later.  The chunk's first cell is the same for the whole
+// wave: its metadata come by scalar loads.  If some lane's pair lies in a
+// later cell, the wave reads the metadata of the chunk's cells (up to 64, one
+// per lane) in one coalesced round trip and each lane finds its own cell
+// among them by a binary search over lane shuffles (chunks of more than 64
+// cells: a binary search per lane in global memory).  `cc`
+// holds chunk_cell[blk G + lane]; c0 is the step's first chunk relative to
+// blk G.  valid == false (uniform) yields inactive slots.
 template <typename T, int PPL>
 __device__ __forceinline__ void pair_fetch(const CompactArgs<T>& a, bool valid, int64_t j0, int c0, int cc,
                                            int32_t T_total, int tid, PairSlot (&sl)[PPL],
@@ -93,21 +96,60 @@ __device__ __forceinline__ void pair_fetch(const CompactArgs<T>& a, bool valid, 
                              ld_uniform(a.keys, 4 * cs0 + 2), ld_uniform(a.keys, 4 * cs0 + 3));
             po = ld_uniform(a.pair_off, cs0);
             po_next = ld_uniform(a.pair_off, cs0 + 1);
-            if (act && t >= po_next) {
-                int lo = cs0 + 1, hi = __builtin_amdgcn_readlane(cc, c0 + q + 1);
-                while (lo < hi) {
-                    const int mid = (lo + hi + 1) >> 1;
-                    if (a.pair_off[mid] <= t)
-                        lo = mid;
-                    else
-                        hi = mid - 1;
+            const int ch = __builtin_amdgcn_readlane(cc, c0 + q + 1);
+            const int nc = ch - cs0 + 1;  // cells cs0 .. ch hold the chunk's pairs
+            if (__any(act && t >= po_next)) {
+                if (nc <= 64) {
+                    // lane l reads cell cs0 + l's metadata (one coalesced
+                    // round trip); each lane finds its cell among them by
+                    // a binary search over the wave's pair offsets and takes
+                    // that cell's values by lane shuffles
+                    const int cl = cs0 + (lane_id() < nc ? lane_id() : nc - 1);
+                    const int32_t po_l = a.pair_off[cl];
+                    const int64_t e0_l = a.off_e[cl], g0_l = a.off_g[cl];
+                    const int32_t ne_l = (int32_t)(a.off_e[cl + 1] - e0_l), ng_l = (int32_t)(a.off_g[cl + 1] - g0_l);
+                    const uint4 key_l = *(const uint4*)(a.keys + 4 * cl);
+                    int lo = 0, hi = nc - 1;
+#pragma unroll
+                    for (int it = 0; it < 6; ++it) {  // nc <= 64 = 2^6
+                        const int mid = (lo + hi + 1) >> 1;
+                        if (__shfl(po_l, mid, 64) <= t)
+                            lo = mid;
+                        else
+                            hi = mid - 1;
+                    }
+                    // (shuffles by the whole wave, then the selection)
+                    const int64_t e0c = (int64_t)__shfl((unsigned long long)e0_l, lo, 64);
+                    const int64_t g0c = (int64_t)__shfl((unsigned long long)g0_l, lo, 64);
+                    const int32_t nec = __shfl(ne_l, lo, 64), ngc = __shfl(ng_l, lo, 64);
+                    const uint4 keyc = make_uint4(__shfl(key_l.x, lo, 64), __shfl(key_l.y, lo, 64),
+                                                  __shfl(key_l.z, lo, 64), __shfl(key_l.w, lo, 64));
+                    const int32_t poc = __shfl(po_l, lo, 64);
+                    if (act && t >= po_next) {
+                        e0 = e0c;
+                        g0 = g0c;
+                        e1 = e0c + nec;
+                        g1 = g0c + ngc;
+                        key = keyc;
+                        po = poc;
+                    }
+                } else if (act && t >= po_next) {
+                    // more than 64 cells in the chunk: per-lane binary search
+                    int lo = cs0 + 1, hi = ch;
+                    while (lo < hi) {
+                        const int mid = (lo + hi + 1) >> 1;
+                        if (a.pair_off[mid] <= t)
+                            lo = mid;
+                        else
+                            hi = mid - 1;
+                    }
+                    e0 = a.off_e[lo];
+                    e1 = a.off_e[lo + 1];
+                    g0 = a.off_g[lo];
+                    g1 = a.off_g[lo + 1];
+                    key = *(const uint4*)(a.keys + 4 * lo);
+                    po = a.pair_off[lo];
                 }
-                e0 = a.off_e[lo];
-                e1 = a.off_e[lo + 1];
-                g0 = a.off_g[lo];
-                g1 = a.off_g[lo + 1];
-                key = *(const uint4*)(a.keys + 4 * lo);
-                po = a.pair_off[lo];
                 // complete these reads inside the branch, so that no read of
                 // it is still counted as possibly in flight after it (which
                 // would make later waits include the particle reads)

@@ -67,9 +67,12 @@ __device__ __forceinline__ double uniform53(uint32_t a, uint32_t b) {
 }
 
 // ---------------------------------------------------------------------------
-// In-cell pairing: 4-round balanced Feistel network over 2h bits
-// (2h >= ceil(log2 M)) with cycle-walking into [0, M) (Black & Rogaway 2002).
-// Round function: MurmurHash3's 32-bit finaliser of (right half ^ key word).
+// In-cell pairing: 4-round Feistel network over b = ceil(log2 M) bits with
+// cycle-walking into [0, M) (Black & Rogaway 2002).  The left part has
+// floor(b/2) bits and the right part the rest; a round maps (L, R) to
+// (R, L ^ F(R)), so the widths trade places each round and are back after
+// four.  Round function: MurmurHash3's 32-bit finaliser of (right part ^ key
+// word), cut to the width of the left part.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ uint32_t fmix32(uint32_t h) {
     h ^= h >> 16;
@@ -82,28 +85,28 @@ __device__ __forceinline__ uint32_t fmix32(uint32_t h) {
 
 struct FeistelKey {
     uint32_t k[4];
-    uint32_t half_bits;  // h
+    uint32_t bits;  // b = ceil(log2 M)
 };
 
 __device__ __forceinline__ uint32_t ceil_log2(uint32_t M) { return M <= 1 ? 0u : 32u - __clz(M - 1u); }
 
 // The cycle-walk always ends: i lies on a cycle of the permutation of
-// [0, 2^{2h}), and that cycle returns to i, which is < M.
+// [0, 2^b), and that cycle returns to i, which is < M.
 __device__ __forceinline__ uint32_t shuffle_index(uint32_t i, uint32_t M, const FeistelKey& key) {
     if (M <= 1u) return 0u;
-    const uint32_t h = key.half_bits;
-    const uint32_t mask = (1u << h) - 1u;
+    const uint32_t a = key.bits >> 1, c = key.bits - a;
+    const uint32_t mask_a = (1u << a) - 1u, mask_c = (1u << c) - 1u;
     uint32_t v = i;
     do {
-        uint32_t L = v >> h, R = v & mask;
+        uint32_t L = v >> c, R = v & mask_c;  // widths a, c
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const uint32_t f = fmix32(R ^ key.k[r]) & mask;
-            const uint32_t nR = L ^ f;
-            L = R;
-            R = nR;
+        for (int r = 0; r < 4; r += 2) {
+            const uint32_t R1 = L ^ (fmix32(R ^ key.k[r]) & mask_a);  // (L, R) -> (R, R1): widths c, a
+            const uint32_t R2 = R ^ (fmix32(R1 ^ key.k[r + 1]) & mask_c);  // -> (R1, R2): widths a, c
+            L = R1;
+            R = R2;
         }
-        v = (L << h) | R;
+        v = (L << c) | R;
     } while (v >= M);
     return v;
 }

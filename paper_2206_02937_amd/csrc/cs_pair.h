@@ -66,7 +66,7 @@ __device__ __forceinline__ PairSlot pair_index(bool active, int64_t e0, int64_t 
         key.k[1] = k1;
         key.k[2] = k2;
         key.k[3] = k3;
-        key.half_bits = (ceil_log2(s.M) + 1u) >> 1;
+        key.bits = ceil_log2(s.M);
         if (ne <= ng) {
             s.ie = (int32_t)(e0 + i);
             s.ig = (int32_t)(g0 + shuffle_index(i, ng, key));
