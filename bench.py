@@ -363,6 +363,7 @@ def main():
                    "cells": p.n_cells, "pairs_per_step": n_pairs, "sampler": args.sampler,
                    "strategy": strategy_used,
                    "chunks_per_block": ctx.get_option(compton.OPT_CHUNKS_PER_BLOCK),
+                   "pairs_per_lane": ctx.get_option(compton.OPT_PAIRS_PER_LANE),
                    "autotuned": tuned is not None, "graph": args.graph,
                    "collisions_per_step": acc_per_step},
         "gpu_ms_per_step": main_run["gpu_ms_per_step"],

@@ -37,6 +37,10 @@ def test_struct_sizes_match_header():
 
     assert C.sizeof(compton.Species) == 40
     assert compton.STATS_BYTES == 128
+    # cs_tune_result: n, best, then four arrays of CS_TUNE_MAX (16) 4-byte values
+    assert C.sizeof(compton.TuneResult) == 8 + 4 * 16 * 4
+    assert [f[0] for f in compton.TuneResult._fields_] == ["n", "best", "strategy", "chunks_per_block",
+                                                          "pairs_per_lane", "ms"]
 
 
 def test_null_context_and_create_errors():
