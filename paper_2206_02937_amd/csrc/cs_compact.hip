@@ -39,7 +39,8 @@ struct CompactArgs {
     uint64_t seed;
     StepControl* ctrl;
     uint64_t* status;  // one word per chunk
-    int2* list;
+    int32_t* list;          // dense list of accepted pairs: their stash slots
+    StashPair<T>* stash;    // accepted pairs with their values, per-wave regions
     double* chunk_prob;
     int64_t* chunk_clip;
     int64_t* chunk_inv;
@@ -165,13 +166,13 @@ __device__ __forceinline__ void pair_fetch(const CompactArgs<T>& a, bool valid, 
 // (one pair of each per lane).  Software pipeline: the pairing and particle
 // reads of step s + 1 are issued before the physics of step s, so their
 // latency hides behind it (the physics reads nothing from global memory:
-// the s(x) table is copied to LDS first).  Accepted pairs are staged in LDS,
-// per wave in the order the wave meets them; after the last step the
-// workgroup's list (wave 0's pairs, then wave 1's, ...) takes its place in
-// the global list with one look-back.
+// the s(x) table is copied to LDS first).  Each wave writes its accepted
+// pairs, with the particle values it read, to its own region of the stash
+// (64 G slots) in the order it meets them; after the last step one look-back
+// places the workgroup's slots (wave 0's, then wave 1's, ...) in the dense
+// list, whose entry q names the stash slot of accepted pair q.
 template <typename T, int PPL>
 __global__ __launch_bounds__(kChunk) void k_pair_compact(const CompactArgs<T> a) {
-    extern __shared__ int2 s_stage[];  // [kChunk / 64][64 G]
     __shared__ double s_sig[kSigTabSegments * kSigTabTerms];
     __shared__ int s_wcnt[kChunk / 64];
     __shared__ int s_prefix;
@@ -198,12 +199,13 @@ __global__ __launch_bounds__(kChunk) void k_pair_compact(const CompactArgs<T> a)
     int64_t n_mine = n_used - blk * G;
     n_mine = n_mine < 0 ? 0 : (n_mine > G ? G : n_mine);
     const int n_steps = (int)((n_mine + PPL - 1) / PPL);
-    int2* stage = s_stage + (int64_t)wave * 64 * G;
+    const int32_t slot0 = (int32_t)((blk * (kChunk / 64) + wave) * 64 * G);  // the wave's stash region
+    StashPair<T>* stage = a.stash + slot0;
     int n_stage = 0;  // wave-uniform
     const uint64_t lanes_below = (1ull << lane) - 1ull;
     double sum_p = 0.0;
     long long n_clip = 0, n_inv = 0;
-    // physics of one step; accepted pairs go to the wave's staging list
+    // physics of one step; accepted pairs go to the wave's stash region
     auto physics = [&](const PairSlot(&sl)[PPL], const PairRaw<T>(&raw)[PPL]) {
 #pragma unroll
         for (int q = 0; q < PPL; ++q) {
@@ -212,7 +214,7 @@ __global__ __launch_bounds__(kChunk) void k_pair_compact(const CompactArgs<T> a)
             n_clip += o.clipped ? 1 : 0;
             n_inv += o.invalid ? 1 : 0;
             const uint64_t mask = __ballot(o.accept);
-            if (o.accept) stage[n_stage + __popcll(mask & lanes_below)] = make_int2(sl[q].ie, sl[q].ig);
+            if (o.accept) stage[n_stage + __popcll(mask & lanes_below)] = make_stash<T>(sl[q], raw[q]);
             n_stage += __popcll(mask);
         }
     };
@@ -262,8 +264,8 @@ __global__ __launch_bounds__(kChunk) void k_pair_compact(const CompactArgs<T> a)
         a.chunk_inv[blk] = in;
     }
     __syncthreads();
-    int2* dst = a.list + s_prefix + wbase;
-    for (int i = lane; i < n_stage; i += 64) dst[i] = stage[i];
+    int32_t* dst = a.list + s_prefix + wbase;
+    for (int i = lane; i < n_stage; i += 64) dst[i] = slot0 + i;
     if (tid == 0 && blk == (int64_t)gridDim.x - 1) ctrl->n_accepted = (uint32_t)(s_prefix + total);
 }
 
@@ -304,8 +306,8 @@ __global__ __launch_bounds__(SAMP == CS_SAMPLER_PLAIN ? kDenseThreads : kDenseNe
             const int q2 = base + tid;
             if (__any(q2 < n)) {
                 const bool act = q2 < n;
-                const int2 pr = act ? a.list[s_fb[q2]] : make_int2(0, 0);
-                collide_plain<T>(a.pt, act, pr.x, pr.y, a.seed, step, sums);
+                const int32_t slot = act ? a.list[s_fb[q2]] : 0;
+                collide_stash<T>(a.pt, act, a.stash + slot, a.seed, step, sums);
                 sums.n_fallback += act ? 1 : 0;
             }
         }
@@ -315,13 +317,13 @@ __global__ __launch_bounds__(SAMP == CS_SAMPLER_PLAIN ? kDenseThreads : kDenseNe
         const bool active = q < A;
         if constexpr (!NET) {
             if (!__any(active)) break;
-            const int2 pr = active ? a.list[q] : make_int2(0, 0);
-            collide_plain<T>(a.pt, active, pr.x, pr.y, a.seed, step, sums);
+            const int32_t slot = active ? a.list[q] : 0;
+            collide_stash<T>(a.pt, active, a.stash + slot, a.seed, step, sums);
         } else {
             // every wave takes part in every iteration (barriers below)
-            const int2 pr = active ? a.list[q] : make_int2(0, 0);
+            const int32_t slot = active ? a.list[q] : 0;
             const bool defer =
-                collide_net<T, SAMP, true>(a.pt, active, FromArrays<T>{pr.x, pr.y}, s_net, a.mlp, a.seed, step, sums);
+                collide_net<T, SAMP, true>(a.pt, active, FromStash<T>{a.stash + slot}, s_net, a.mlp, a.seed, step, sums);
             const uint64_t m = __ballot(defer);
             if (lane == 0) s_wcnt[wave] = __popcll(m);
             __syncthreads();
@@ -374,14 +376,19 @@ int64_t compact_pair_blocks(const StepShape& s) {
     return s.n_chunks > 0 ? (s.n_chunks + G - 1) / G : 0;
 }
 
-size_t compact_stage_bytes(int64_t chunks_per_block) { return sizeof(int2) * kChunk * (size_t)chunks_per_block; }
+// stash slots: 64 G per wave of every pair workgroup (the largest entry
+// type, so that one workspace serves either storage type)
+static size_t compact_stash_bytes(const StepShape& s) {
+    return sizeof(StashPair<double>) * (size_t)compact_pair_blocks(s) * kChunk * (size_t)s.chunks_per_block;
+}
 
 size_t compact_workspace_bytes(const StepShape& s) {
     size_t b = 0;
     b += al(sizeof(int32_t) * (s.n_cells + 1));
     b += al(sizeof(uint32_t) * 4 * (s.n_cells > 0 ? s.n_cells : 1));
     b += al(sizeof(int32_t) * (s.n_chunks + 1));
-    b += al(sizeof(int2) * s.n_chunks * kChunk + 8);
+    b += al(sizeof(int32_t) * s.n_chunks * kChunk + 8);
+    b += al(compact_stash_bytes(s) + 16);
     b += 3 * al(8 * (s.n_chunks > 0 ? s.n_chunks : 1));
     b += 3 * al(8 * s.n_collide_blocks);
     return b;
@@ -399,7 +406,8 @@ void carve_compact_buffers(const Workspace& w, const StepShape& s, CompactBuffer
     b->pair_off = (int32_t*)take(sizeof(int32_t) * (s.n_cells + 1));
     b->cell_keys = (uint32_t*)take(sizeof(uint32_t) * 4 * (s.n_cells > 0 ? s.n_cells : 1));
     b->chunk_cell = (int32_t*)take(sizeof(int32_t) * (s.n_chunks + 1));
-    b->list = (int2*)take(sizeof(int2) * s.n_chunks * kChunk + 8);
+    b->list = (int32_t*)take(sizeof(int32_t) * s.n_chunks * kChunk + 8);
+    b->stash = take(compact_stash_bytes(s) + 16);
     b->chunk_prob = (double*)take(8 * (s.n_chunks > 0 ? s.n_chunks : 1));
     b->chunk_clip = (int64_t*)take(8 * (s.n_chunks > 0 ? s.n_chunks : 1));
     b->chunk_inv = (int64_t*)take(8 * (s.n_chunks > 0 ? s.n_chunks : 1));
@@ -434,6 +442,7 @@ static hipError_t launch_compact_t(const StepShape& sh, const CompactBuffers& b,
     a.ctrl = b.ctrl;
     a.status = b.status + sh.n_prep_blocks;
     a.list = b.list;
+    a.stash = (StashPair<T>*)b.stash;
     a.chunk_prob = b.chunk_prob;
     a.chunk_clip = b.chunk_clip;
     a.chunk_inv = b.chunk_inv;
@@ -444,13 +453,12 @@ static hipError_t launch_compact_t(const StepShape& sh, const CompactBuffers& b,
     a.mlp = p.net;
     const int64_t n_pair_blocks = compact_pair_blocks(sh);
     if (sh.n_chunks > 0) {
-        const size_t lds = compact_stage_bytes(sh.chunks_per_block);
         if (sh.pairs_per_lane == 1)
-            k_pair_compact<T, 1><<<(unsigned)n_pair_blocks, kChunk, lds, st>>>(a);
+            k_pair_compact<T, 1><<<(unsigned)n_pair_blocks, kChunk, 0, st>>>(a);
         else if (sh.pairs_per_lane == 2)
-            k_pair_compact<T, 2><<<(unsigned)n_pair_blocks, kChunk, lds, st>>>(a);
+            k_pair_compact<T, 2><<<(unsigned)n_pair_blocks, kChunk, 0, st>>>(a);
         else
-            k_pair_compact<T, 4><<<(unsigned)n_pair_blocks, kChunk, lds, st>>>(a);
+            k_pair_compact<T, 4><<<(unsigned)n_pair_blocks, kChunk, 0, st>>>(a);
     }
     mark(2);
     mark(3);

@@ -13,7 +13,7 @@
 namespace cs {
 
 constexpr int kChunk = 256;       // pairs per workgroup of the pair kernel
-constexpr int64_t kCompactMaxChunks = 16;  // compact pair kernel: chunks per workgroup (LDS staging)
+constexpr int64_t kCompactMaxChunks = 16;  // compact pair kernel: chunks per workgroup
 constexpr int64_t kTimingRing = 512;  // steps whose stage events are kept
 constexpr int kScanItems = 1024;  // items per workgroup of the scan kernels
 
@@ -107,7 +107,8 @@ struct CompactBuffers {
     int32_t* pair_off;    // [n_cells + 1]
     uint32_t* cell_keys;  // [4 n_cells]
     int32_t* chunk_cell;  // [n_chunks + 1]
-    int2* list;           // [n_chunks * kChunk] accepted pairs, dense (workgroup, wave, pair order)
+    int32_t* list;        // [n_chunks * kChunk] stash slots of the accepted pairs, dense (workgroup, wave, pair order)
+    void* stash;          // accepted pairs with their particle values: 64 G slots per pair-kernel wave
     double* chunk_prob;   // [n_chunks]
     int64_t* chunk_clip;  // [n_chunks]
     int64_t* chunk_inv;   // [n_chunks]

@@ -217,24 +217,13 @@ __device__ __forceinline__ void write_back(const Particles<T>& a, int32_t ie, in
     }
 }
 
-// Resolve the accepted pair (ie, ig) with the plain sampler and write it back.
-// Lanes with active == false run the sampler on a dummy x = 0 (the quickest
-// case) and write nothing.  The particle values are read once, before the
-// sampler, and kept in their storage type across it (8 registers for FP32).
+// Resolve the accepted pair (ie, ig) with particle values raw = (p, k, we, wg)
+// in their storage type with the plain sampler and write it back.  Lanes
+// with active == false run the sampler on a dummy x = 0 (the quickest case)
+// and write nothing.
 template <typename T>
-__device__ __forceinline__ void collide_plain(const Particles<T>& a, bool active, int32_t ie, int32_t ig,
-                                              uint64_t seed, uint64_t step, CollideSums& sums) {
-    T raw[8] = {};
-    if (active) {
-        raw[0] = a.ex[ie];
-        raw[1] = a.ey[ie];
-        raw[2] = a.ez[ie];
-        raw[3] = a.gx[ig];
-        raw[4] = a.gy[ig];
-        raw[5] = a.gz[ig];
-        raw[6] = a.ew[ie];
-        raw[7] = a.gw[ig];
-    }
+__device__ __forceinline__ void collide_raw(const Particles<T>& a, bool active, int32_t ie, int32_t ig,
+                                            const T (&raw)[8], uint64_t seed, uint64_t step, CollideSums& sums) {
     double x = 0.0;
     if (active) {
         const d3 p = {(double)raw[0], (double)raw[1], (double)raw[2]};
@@ -252,6 +241,76 @@ __device__ __forceinline__ void collide_plain(const Particles<T>& a, bool active
     write_back<T>(a, ie, ig, (double)raw[6], (double)raw[7], s, seed, step);
     sums.e_before += s.e_before;
     sums.e_after += s.e_after;
+}
+
+// The same with the particle values read from the arrays (once, before the
+// sampler, kept in their storage type across it: 8 registers for FP32).
+template <typename T>
+__device__ __forceinline__ void collide_plain(const Particles<T>& a, bool active, int32_t ie, int32_t ig,
+                                              uint64_t seed, uint64_t step, CollideSums& sums) {
+    T raw[8] = {};
+    if (active) {
+        raw[0] = a.ex[ie];
+        raw[1] = a.ey[ie];
+        raw[2] = a.ez[ie];
+        raw[3] = a.gx[ig];
+        raw[4] = a.gy[ig];
+        raw[5] = a.gz[ig];
+        raw[6] = a.ew[ie];
+        raw[7] = a.gw[ig];
+    }
+    collide_raw<T>(a, active, ie, ig, raw, seed, step, sums);
+}
+
+// An accepted pair kept in global memory between the pair and the collide
+// kernels: its indices and the particle values the pair kernel read, in 16-
+// byte units (3 for FP32, 5 for FP64), so that the collide kernel reads them
+// in a few wide loads instead of gathering eight scattered elements.
+template <typename T>
+struct alignas(16) StashPair {
+    T p[3], we;
+    T k[3], wg;
+    int32_t ie, ig, pad0, pad1;
+};
+
+template <typename T>
+__device__ __forceinline__ StashPair<T> make_stash(const PairSlot& s, const PairRaw<T>& r) {
+    StashPair<T> e;
+    e.p[0] = r.p[0];
+    e.p[1] = r.p[1];
+    e.p[2] = r.p[2];
+    e.we = r.we;
+    e.k[0] = r.k[0];
+    e.k[1] = r.k[1];
+    e.k[2] = r.k[2];
+    e.wg = r.wg;
+    e.ie = s.ie;
+    e.ig = s.ig;
+    e.pad0 = 0;
+    e.pad1 = 0;
+    return e;
+}
+
+// collide_raw with the pair taken from a stash entry.
+template <typename T>
+__device__ __forceinline__ void collide_stash(const Particles<T>& a, bool active, const StashPair<T>* e,
+                                              uint64_t seed, uint64_t step, CollideSums& sums) {
+    T raw[8] = {};
+    int32_t ie = 0, ig = 0;
+    if (active) {
+        const StashPair<T> v = *e;
+        raw[0] = v.p[0];
+        raw[1] = v.p[1];
+        raw[2] = v.p[2];
+        raw[3] = v.k[0];
+        raw[4] = v.k[1];
+        raw[5] = v.k[2];
+        raw[6] = v.we;
+        raw[7] = v.wg;
+        ie = v.ie;
+        ig = v.ig;
+    }
+    collide_raw<T>(a, active, ie, ig, raw, seed, step, sums);
 }
 
 // An accepted pair staged in LDS with its particle values.
@@ -286,8 +345,8 @@ __device__ __forceinline__ void collide_staged(const Particles<T>& a, bool activ
     sums.e_after += s.e_after;
 }
 
-// Where a collision's particle values come from: an LDS queue entry or the
-// particle arrays.
+// Where a collision's particle values come from: an LDS queue entry, a stash
+// entry or the particle arrays.
 template <typename T>
 struct FromStaged {
     const StagedPair<T>* e;
@@ -299,6 +358,20 @@ struct FromStaged {
         k = {(double)e->k[0], (double)e->k[1], (double)e->k[2]};
         we = (double)e->we;
         wg = (double)e->wg;
+    }
+};
+template <typename T>
+struct FromStash {
+    const StashPair<T>* e;
+    __device__ __forceinline__ void get(const Particles<T>&, int32_t& ie, int32_t& ig, d3& p, d3& k, double& we,
+                                        double& wg) const {
+        const StashPair<T> v = *e;
+        ie = v.ie;
+        ig = v.ig;
+        p = {(double)v.p[0], (double)v.p[1], (double)v.p[2]};
+        k = {(double)v.k[0], (double)v.k[1], (double)v.k[2]};
+        we = (double)v.we;
+        wg = (double)v.wg;
     }
 };
 template <typename T>
