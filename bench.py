@@ -307,6 +307,10 @@ def main():
     # algorithmic bytes of the dominant kernel (k_step, fused strategy: every
     # pair reads both particles, 8 values; every collision writes 6 values
     # back); for the other strategies the pair and collide kernels separately
+    # (compact: the pair kernel stashes each accepted pair's 8 values and two
+    # indices and writes its 4-byte list slot, which the collide kernel reads
+    # back; multi-kernel: an 8-byte index pair per accepted pair, and the
+    # collide kernel gathers the 8 values)
     strategy_used = compton.STRATEGY_NAMES[ctx.get_option(compton.OPT_STRATEGY)]
     if strategy_used == "fused":
         kern, ms = "k_step", stage_ms["pair"]
@@ -314,11 +318,13 @@ def main():
     else:
         kern = "k_pair_compact" if strategy_used == "compact" else "k_pair"
         ms = stage_ms["pair"]
-        bytes_launch = n_pairs * 8 * sb + acc_per_step * 8
+        per_acc = 8 * sb + 8 + 4 if strategy_used == "compact" else 8
+        bytes_launch = n_pairs * 8 * sb + acc_per_step * per_acc
         if stage_ms["collide"] > ms:
             kern = "k_collide_dense" if strategy_used == "compact" else "k_collide"
             ms = stage_ms["collide"]
-            bytes_launch = acc_per_step * (8 + 8 * sb + 6 * sb)
+            bytes_launch = acc_per_step * (per_acc + 8 * sb + 6 * sb if strategy_used != "compact"
+                                           else per_acc + 6 * sb)
     # the library's stage events bracket each kernel; with the compact
     # strategy the "compact" stage is an empty bracket (two events back to
     # back), i.e. the events' own cost, which is taken off the kernel's time

@@ -162,6 +162,22 @@ __device__ __forceinline__ void pair_fetch(const CompactArgs<T>& a, bool valid, 
     }
 }
 
+// A SIMD's arbiter issues from the oldest of its waves first, so waves of
+// equal work (one per workgroup on the SIMD) drift apart and finish one after
+// another, the last ones alone with their latency exposed.  Before each step
+// a wave takes the priority (rem - 1) mod 4 from the steps it has left, rem:
+// among waves within a few steps of each other the one behind is issued first
+// (except across a wrap of the four levels), and in the last four steps the
+// order is exact, so that the waves finish close together.
+__device__ __forceinline__ void balance_priority(int rem) {
+    switch ((rem - 1) & 3) {
+        case 3: __builtin_amdgcn_s_setprio(3); break;
+        case 2: __builtin_amdgcn_s_setprio(2); break;
+        case 1: __builtin_amdgcn_s_setprio(1); break;
+        default: __builtin_amdgcn_s_setprio(0); break;
+    }
+}
+
 // One workgroup takes G consecutive 256-pair chunks, PPL of them per step
 // (one pair of each per lane).  Software pipeline: the pairing and particle
 // reads of step s + 1 are issued before the physics of step s, so their
@@ -226,12 +242,15 @@ __global__ __launch_bounds__(kChunk) void k_pair_compact(const CompactArgs<T> a)
     for (int st = 0; st < n_steps; st += 2) {
         pair_fetch<T, PPL>(a, st + 1 < n_steps, blk * G + (st + 1) * PPL, (st + 1) * PPL, cc, T_total, tid, sl_b,
                            raw_b);
+        balance_priority(n_steps - st);
         physics(sl_a, raw_a);
         if (st + 1 >= n_steps) break;
         pair_fetch<T, PPL>(a, st + 2 < n_steps, blk * G + (st + 2) * PPL, (st + 2) * PPL, cc, T_total, tid, sl_a,
                            raw_a);
+        balance_priority(n_steps - st - 1);
         physics(sl_b, raw_b);
     }
+    __builtin_amdgcn_s_setprio(0);
     const double wp = wave_sum(sum_p);
     const long long wc = wave_sum_i(n_clip), wi = wave_sum_i(n_inv);
     if (lane == 0) {
