@@ -32,6 +32,7 @@ struct CompactArgs {
     const int64_t *off_e, *off_g;
     int64_t n_cells, n_chunks;
     int32_t chunks_per_block;  // pair kernel: consecutive chunks per workgroup
+    int32_t balance;           // pair kernel: pace the waves (the grid is one round of resident workgroups)
     const int32_t* pair_off;
     const uint32_t* keys;
     const int32_t* chunk_cell;
@@ -168,7 +169,10 @@ __device__ __forceinline__ void pair_fetch(const CompactArgs<T>& a, bool valid, 
 // a wave takes the priority (rem - 1) mod 4 from the steps it has left, rem:
 // among waves within a few steps of each other the one behind is issued first
 // (except across a wrap of the four levels), and in the last four steps the
-// order is exact, so that the waves finish close together.
+// order is exact, so that the waves finish close together.  Used only when
+// every workgroup of the grid is resident at once: with more workgroups than
+// that, a workgroup that finishes early makes room for a waiting one, which
+// pacing would delay.
 __device__ __forceinline__ void balance_priority(int rem) {
     switch ((rem - 1) & 3) {
         case 3: __builtin_amdgcn_s_setprio(3); break;
@@ -242,12 +246,12 @@ __global__ __launch_bounds__(kChunk) void k_pair_compact(const CompactArgs<T> a)
     for (int st = 0; st < n_steps; st += 2) {
         pair_fetch<T, PPL>(a, st + 1 < n_steps, blk * G + (st + 1) * PPL, (st + 1) * PPL, cc, T_total, tid, sl_b,
                            raw_b);
-        balance_priority(n_steps - st);
+        if (a.balance) balance_priority(n_steps - st);
         physics(sl_a, raw_a);
         if (st + 1 >= n_steps) break;
         pair_fetch<T, PPL>(a, st + 2 < n_steps, blk * G + (st + 2) * PPL, (st + 2) * PPL, cc, T_total, tid, sl_a,
                            raw_a);
-        balance_priority(n_steps - st - 1);
+        if (a.balance) balance_priority(n_steps - st - 1);
         physics(sl_b, raw_b);
     }
     __builtin_amdgcn_s_setprio(0);
@@ -435,6 +439,30 @@ void carve_compact_buffers(const Workspace& w, const StepShape& s, CompactBuffer
     b->coll_fb = (int64_t*)take(8 * s.n_collide_blocks);
 }
 
+// Workgroups of k_pair_compact<T, PPL> resident at once on the current
+// device (its compute units times the kernel's occupancy), computed once.
+template <typename T, int PPL>
+static int64_t pair_resident_blocks() {
+    static int64_t cached = -1;
+    if (cached < 0) {
+        int dev = 0, n_cu = 0, per_cu = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&k_pair_compact<T, PPL>),
+                                                         kChunk, 0) != hipSuccess)
+            return 0;  // unknown: no pacing
+        cached = (int64_t)n_cu * per_cu;
+    }
+    return cached;
+}
+
+template <typename T, int PPL>
+static hipError_t launch_pair_compact(CompactArgs<T> a, int64_t n_blocks, hipStream_t st) {
+    a.balance = n_blocks <= pair_resident_blocks<T, PPL>() ? 1 : 0;
+    k_pair_compact<T, PPL><<<(unsigned)n_blocks, kChunk, 0, st>>>(a);
+    return hipGetLastError();
+}
+
 template <typename T, int SAMP>
 static hipError_t launch_compact_t(const StepShape& sh, const CompactBuffers& b, const StepParams& p, hipStream_t st) {
     auto mark = [&](int i) {
@@ -473,11 +501,12 @@ static hipError_t launch_compact_t(const StepShape& sh, const CompactBuffers& b,
     const int64_t n_pair_blocks = compact_pair_blocks(sh);
     if (sh.n_chunks > 0) {
         if (sh.pairs_per_lane == 1)
-            k_pair_compact<T, 1><<<(unsigned)n_pair_blocks, kChunk, 0, st>>>(a);
+            e = launch_pair_compact<T, 1>(a, n_pair_blocks, st);
         else if (sh.pairs_per_lane == 2)
-            k_pair_compact<T, 2><<<(unsigned)n_pair_blocks, kChunk, 0, st>>>(a);
+            e = launch_pair_compact<T, 2>(a, n_pair_blocks, st);
         else
-            k_pair_compact<T, 4><<<(unsigned)n_pair_blocks, kChunk, 0, st>>>(a);
+            e = launch_pair_compact<T, 4>(a, n_pair_blocks, st);
+        if (e != hipSuccess) return e;
     }
     mark(2);
     mark(3);
