@@ -292,10 +292,10 @@ __global__ __launch_bounds__(kChunk) void k_pair_compact(const CompactArgs<T> a)
     if (tid == 0 && blk == (int64_t)gridDim.x - 1) ctrl->n_accepted = (uint32_t)(s_prefix + total);
 }
 
-// Network samplers defer the pairs outside the network's domain: their list
-// positions are compacted in order into s_fb and resolved with the plain
-// sampler in dense passes once a full workgroup's worth has gathered (and at
-// the end), so that the Newton iteration never runs on a mostly idle wave.
+// Network samplers resolve the pairs outside the network's domain in place
+// with the plain sampler: the lanes of a wave that need it run it together.
+// (Collecting them for separate dense passes was measured slower: the kernel
+// is bound by the latency of one pass, not by issue.)
 template <typename T, int SAMP>
 __global__ __launch_bounds__(SAMP == CS_SAMPLER_PLAIN ? kDenseThreads : kDenseNetThreads) void k_collide_dense(
     const CompactArgs<T> a) {
@@ -304,17 +304,11 @@ __global__ __launch_bounds__(SAMP == CS_SAMPLER_PLAIN ? kDenseThreads : kDenseNe
     __shared__ NetLds<SAMP> s_net;
     __shared__ double s_d[2 * (NT / 64)];
     __shared__ long long s_fbc[NT / 64];
-    __shared__ int s_fb[NET ? 2 * NT : 1];
-    __shared__ int s_wcnt[NT / 64];
-    __shared__ int s_fbn;
     const int tid = threadIdx.x;
     const int lane = lane_id();
     const int wave = tid >> 6;
     net_load<SAMP>(s_net, a.mlp);
-    if constexpr (NET) {
-        if (tid == 0) s_fbn = 0;
-        __syncthreads();
-    }
+    if constexpr (NET) __syncthreads();
     StepControl* ctrl = a.ctrl;
     const uint32_t E = ctrl->epoch;
     const uint64_t step = ctrl->step;
@@ -323,53 +317,16 @@ __global__ __launch_bounds__(SAMP == CS_SAMPLER_PLAIN ? kDenseThreads : kDenseNe
     const int64_t stride = (int64_t)gridDim.x * NT;
     const int64_t n_iter = (A + stride - 1) / stride;  // uniform over the grid
     CollideSums sums;
-    // dense plain-sampler passes over the deferred list positions
-    auto flush = [&](int n) {
-        for (int base = 0; base < n; base += NT) {
-            const int q2 = base + tid;
-            if (__any(q2 < n)) {
-                const bool act = q2 < n;
-                const int32_t slot = act ? a.list[s_fb[q2]] : 0;
-                collide_stash<T>(a.pt, act, a.stash + slot, a.seed, step, sums);
-                sums.n_fallback += act ? 1 : 0;
-            }
-        }
-    };
     for (int64_t it = 0; it < n_iter; ++it) {
         const int64_t q = it * stride + (int64_t)blockIdx.x * NT + tid;
         const bool active = q < A;
-        if constexpr (!NET) {
-            if (!__any(active)) break;
-            const int32_t slot = active ? a.list[q] : 0;
+        if (!__any(active)) break;
+        const int32_t slot = active ? a.list[q] : 0;
+        if constexpr (!NET)
             collide_stash<T>(a.pt, active, a.stash + slot, a.seed, step, sums);
-        } else {
-            // every wave takes part in every iteration (barriers below)
-            const int32_t slot = active ? a.list[q] : 0;
-            const bool defer =
-                collide_net<T, SAMP, true>(a.pt, active, FromStash<T>{a.stash + slot}, s_net, a.mlp, a.seed, step, sums);
-            const uint64_t m = __ballot(defer);
-            if (lane == 0) s_wcnt[wave] = __popcll(m);
-            __syncthreads();
-            int wbase = 0, total = 0;
-#pragma unroll
-            for (int w = 0; w < NT / 64; ++w) {
-                wbase += w < wave ? s_wcnt[w] : 0;
-                total += s_wcnt[w];
-            }
-            const int nf = s_fbn;  // < NT here, so nf + total < 2 NT
-            if (defer) s_fb[nf + wbase + __popcll(m & ((1ull << lane) - 1ull))] = (int)q;
-            __syncthreads();
-            if (nf + total >= NT) {
-                flush(nf + total);
-                __syncthreads();
-                if (tid == 0) s_fbn = 0;
-            } else if (tid == 0) {
-                s_fbn = nf + total;
-            }
-            __syncthreads();
-        }
+        else
+            collide_net<T, SAMP>(a.pt, active, FromStash<T>{a.stash + slot}, s_net, a.mlp, a.seed, step, sums);
     }
-    if constexpr (NET) flush(s_fbn);
     const double eb = wave_sum(sums.e_before), ea = wave_sum(sums.e_after);
     const long long fb = wave_sum_i(sums.n_fallback);
     if (lane == 0) {

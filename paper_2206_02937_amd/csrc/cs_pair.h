@@ -393,11 +393,8 @@ struct FromArrays {
 // network's x domain the plain sampler answers (counted in n_fallback).  The
 // same Philox draw as the plain sampler supplies u and the azimuth.  Must be
 // called by the whole wave; lanes with active == false write nothing.
-// DEFER: lanes outside the domain do nothing and return true, so that the
-// caller resolves them later in a dense batch with the plain sampler (the
-// result is the same: both take x from the same particle values).
-template <typename T, int SAMP, bool DEFER = false, typename Src>
-__device__ __forceinline__ bool collide_net(const Particles<T>& a, bool active, const Src& src, NetLds<SAMP>& s_net,
+template <typename T, int SAMP, typename Src>
+__device__ __forceinline__ void collide_net(const Particles<T>& a, bool active, const Src& src, NetLds<SAMP>& s_net,
                                             const MlpDev& m, uint64_t seed, uint64_t step, CollideSums& sums) {
     double x = 0.0;
     int32_t ie = 0, ig = 0;
@@ -416,15 +413,11 @@ __device__ __forceinline__ bool collide_net(const Particles<T>& a, bool active, 
     if (inside) features(xf, uf, f1, f2);
     const float mu_hat = net_mu_hat<SAMP>(s_net, m, inside, f1, f2);
     double v = 0.0;
-    if constexpr (DEFER) {
-        if (fallback || !active) return fallback;
-    } else {
-        if (__any(fallback)) {
-            const double vf = angle_icdf_v(fallback ? u : 0.5, fallback ? x : 0.0);
-            if (fallback) v = vf;
-        }
-        if (!active) return false;
+    if (__any(fallback)) {
+        const double vf = angle_icdf_v(fallback ? u : 0.5, fallback ? x : 0.0);
+        if (fallback) v = vf;
     }
+    if (!active) return;
     if (inside) v = 1.0 - (double)fminf(fmaxf(mu_hat, -1.0f), 1.0f);
     const PairInv inv = pair_invariants(p, k);
     const Scattered s = scatter(p, k, inv, v, uniform53(r.c, r.d));
@@ -432,7 +425,6 @@ __device__ __forceinline__ bool collide_net(const Particles<T>& a, bool active, 
     sums.e_before += s.e_before;
     sums.e_after += s.e_after;
     sums.n_fallback += fallback ? 1 : 0;
-    return false;
 }
 
 }  // namespace cs
