@@ -244,7 +244,7 @@ Plan plan_step(int64_t strategy, int64_t chunks_per_block, int64_t pairs_per_lan
         sh.chunks_per_block = Gc;
         sh.n_collide_blocks = sh.n_dense_blocks;
         pl.bytes = cs::compact_workspace_bytes(sh);
-        pl.status_words += cs::compact_pair_blocks(sh);
+        pl.status_words += cs::kPairStatusStride * cs::compact_pair_blocks(sh);
     } else {
         pl.bytes = cs::step_workspace_bytes(sh);
     }

@@ -39,7 +39,7 @@ struct CompactArgs {
     double dt, density_norm;
     uint64_t seed;
     StepControl* ctrl;
-    uint64_t* status;  // one word per chunk
+    uint64_t* status;  // pair kernel: one word per workgroup, kPairStatusStride apart
     int32_t* list;          // dense list of accepted pairs: their stash slots
     StashPair<T>* stash;    // accepted pairs with their values, per-wave regions
     double* chunk_prob;
@@ -271,7 +271,8 @@ __global__ __launch_bounds__(kChunk) void k_pair_compact(const CompactArgs<T> a)
         total += s_wcnt[w];
     }
     if (tid < 64) {
-        const uint32_t ex = lookback_exclusive_wave(a.status, blk, E, (uint32_t)total, &ctrl->scan_fault_epoch);
+        const uint32_t ex =
+            lookback_exclusive_wave<kPairStatusStride>(a.status, blk, E, (uint32_t)total, &ctrl->scan_fault_epoch);
         if (tid == 0) s_prefix = (int)ex;
     }
     if (tid == 0) {
@@ -426,7 +427,7 @@ static hipError_t launch_compact_t(const StepShape& sh, const CompactBuffers& b,
         if (p.events) (void)hipEventRecord(p.events[i], st);
     };
     mark(0);
-    // prep status words first, then one per chunk
+    // prep status words first, then the pair workgroups' (kPairStatusStride apart)
     hipError_t e = launch_prep(sh, b.ctrl, b.status, b.pair_off, b.cell_keys, b.chunk_cell, p, st);
     if (e != hipSuccess) return e;
     mark(1);

@@ -14,6 +14,7 @@ namespace cs {
 
 constexpr int kChunk = 256;       // pairs per workgroup of the pair kernel
 constexpr int64_t kCompactMaxChunks = 16;  // compact pair kernel: chunks per workgroup
+constexpr int kPairStatusStride = 16;      // compact pair kernel: look-back status words apart (one 128-byte line each)
 constexpr int64_t kTimingRing = 512;  // steps whose stage events are kept
 constexpr int kScanItems = 1024;  // items per workgroup of the scan kernels
 

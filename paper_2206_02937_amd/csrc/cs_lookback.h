@@ -20,54 +20,23 @@ __device__ __forceinline__ uint64_t pack_status(uint32_t epoch, uint64_t flag, u
     return ((uint64_t)(epoch & 0x3FFFFFFFu) << 34) | (flag << 32) | (uint64_t)value;
 }
 
-// Called by one thread of workgroup `idx`.  Returns the exclusive prefix of
-// `aggregate`; on a spin-limit overrun records the epoch in *fault and
-// continues with the prefix gathered so far.
-__device__ __forceinline__ uint32_t lookback_exclusive(uint64_t* status, int64_t idx, uint32_t E, uint32_t aggregate,
-                                                       uint32_t* fault) {
-    const uint32_t Et = E & 0x3FFFFFFFu;
-    if (idx == 0) {
-        __hip_atomic_store(&status[0], pack_status(E, kFlagPrefix, aggregate), __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-        return 0;
-    }
-    __hip_atomic_store(&status[idx], pack_status(E, kFlagAggregate, aggregate), __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_AGENT);
-    uint32_t excl = 0;
-    int64_t k = idx - 1;
-    uint32_t spins = 0;
-    while (k >= 0) {
-        const uint64_t w = __hip_atomic_load(&status[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const uint64_t fl = (w >> 32) & 3u;
-        if ((uint32_t)(w >> 34) == Et && fl != 0) {
-            excl += (uint32_t)w;
-            if (fl == kFlagPrefix) break;
-            --k;
-            spins = 0;
-        } else if (++spins > kSpinLimit) {
-            atomicMax(fault, E);
-            break;
-        } else {
-            __builtin_amdgcn_s_sleep(1);
-        }
-    }
-    __hip_atomic_store(&status[idx], pack_status(E, kFlagPrefix, excl + aggregate), __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_AGENT);
-    return excl;
-}
-
-// Wave-wide variant: called by all 64 lanes of one wave of workgroup `idx`.
-// Lane l reads the status word of predecessor idx-1-l, so each round trip to
-// memory covers 64 predecessors (cross-die atomic latency dominates a walk
-// that reads one word at a time).  A window is complete once every
+// Called by all 64 lanes of one wave of workgroup `idx`; on a spin-limit
+// overrun records the epoch in *fault and continues with the prefix gathered
+// so far.  Lane l reads the status word of predecessor idx-1-l, so each round
+// trip to memory covers 64 predecessors (cross-die atomic latency dominates a
+// walk that reads one word at a time).  A window is complete once every
 // predecessor up to the nearest inclusive prefix in it has published; the
-// older ones are not needed.  Returns the exclusive prefix in every lane.
+// older ones are not needed.  Workgroup i's word is status[i S]: with S = 16
+// each word has a 128-byte line of its own, which spreads the polling of many
+// workgroups over the memory channels.  Returns the exclusive prefix in every
+// lane.
+template <int S = 1>
 __device__ __forceinline__ uint32_t lookback_exclusive_wave(uint64_t* status, int64_t idx, uint32_t E,
                                                             uint32_t aggregate, uint32_t* fault) {
     const uint32_t Et = E & 0x3FFFFFFFu;
     const int lane = __lane_id();
     if (lane == 0)
-        __hip_atomic_store(&status[idx], pack_status(E, idx == 0 ? kFlagPrefix : kFlagAggregate, aggregate),
+        __hip_atomic_store(&status[idx * S], pack_status(E, idx == 0 ? kFlagPrefix : kFlagAggregate, aggregate),
                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (idx == 0) return 0;
     uint32_t excl = 0;
@@ -75,7 +44,7 @@ __device__ __forceinline__ uint32_t lookback_exclusive_wave(uint64_t* status, in
     uint32_t spins = 0;
     while (true) {
         const int64_t k = base - lane;
-        const uint64_t w = k >= 0 ? __hip_atomic_load(&status[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+        const uint64_t w = k >= 0 ? __hip_atomic_load(&status[k * S], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
                                   : pack_status(E, kFlagPrefix, 0);
         const uint64_t fl = (w >> 32) & 3u;
         const bool ready = (uint32_t)(w >> 34) == Et && fl != 0;
@@ -99,7 +68,7 @@ __device__ __forceinline__ uint32_t lookback_exclusive_wave(uint64_t* status, in
         base -= 64;
     }
     if (lane == 0)
-        __hip_atomic_store(&status[idx], pack_status(E, kFlagPrefix, excl + aggregate), __ATOMIC_RELAXED,
+        __hip_atomic_store(&status[idx * S], pack_status(E, kFlagPrefix, excl + aggregate), __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
     return excl;
 }
