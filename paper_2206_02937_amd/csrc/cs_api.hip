@@ -217,11 +217,12 @@ Plan plan_step(int64_t strategy, int64_t chunks_per_block, int64_t pairs_per_lan
     sh.n_step_blocks = sh.n_chunks > 0 ? (sh.n_chunks + G - 1) / G : 1;
     sh.n_prep_blocks = cs::fused_prep_blocks(n_cells);
     sh.pairs_per_lane = pairs_per_lane == 1 || pairs_per_lane == 2 || pairs_per_lane == 4 ? pairs_per_lane : 1;
-    // dense collide grid: one lane per accepted pair at most, capped (2048
-    // one-wave workgroups, or 512 four-wave workgroups that each load the
-    // network's LDS copy)
+    // dense collide grid: one lane per accepted pair at most, capped (768
+    // four-wave workgroups with the plain sampler, three per compute unit at
+    // its occupancy; 512 with a network sampler, whose workgroups each load
+    // the network's LDS copy)
     const int64_t dense_threads = cs::compact_collide_threads(sampler);
-    const int64_t dense_cap = sampler == CS_SAMPLER_PLAIN ? 2048 : 512;
+    const int64_t dense_cap = sampler == CS_SAMPLER_PLAIN ? 768 : 512;
     int64_t nd = (nmin + dense_threads - 1) / dense_threads;
     sh.n_dense_blocks = nd < 1 ? 1 : (nd > dense_cap ? dense_cap : nd);
     pl.status_words = sh.n_prep_blocks;

@@ -3,15 +3,18 @@
 //   k_prep_scan       (cs_fused.hip) cells -> pair offsets, keys, chunk map
 //   k_pair_compact    one lane per pair, each workgroup loops over G
 //                     consecutive 256-pair chunks: pairing, x, s(x), P,
-//                     accept; the workgroup's accepted pairs, staged in LDS,
-//                     get their global position by decoupled look-back over
-//                     the workgroups, so the list of accepted pairs is dense
-//                     and in a fixed order with no atomics.  Lean (no
-//                     sampler), so it runs at high occupancy.
-//   k_collide_dense   workgroups stride over the dense list: sample the
-//                     angle, scatter, write back (one wave per workgroup with
-//                     the plain sampler; four waves sharing the network's LDS
-//                     copy with a network sampler).
+//                     accept; each wave writes its accepted pairs with their
+//                     values to its stash region and the workgroup lists
+//                     their slots in order: in a segment of its own (up to
+//                     kSegMax workgroups), or, for more workgroups, at its
+//                     place in a dense list found by decoupled look-back.
+//                     Either way the order is fixed and no atomics are used.
+//                     Lean (no sampler), so it runs at high occupancy.
+//   k_collide_dense   workgroups stride over the accepted pairs in that
+//                     order (segments: each collide workgroup first forms the
+//                     prefix sums of the segment lengths): sample the angle,
+//                     scatter, write back (four waves per workgroup; with a
+//                     network sampler they share the network's LDS copy).
 //   k_finalize_step   (cs_fused.hip) fixed-order reduction of the partial sums.
 #include <hip/hip_runtime.h>
 
@@ -23,7 +26,7 @@
 
 namespace cs {
 
-constexpr int kDenseThreads = 64;      // plain sampler
+constexpr int kDenseThreads = 256;     // plain sampler
 constexpr int kDenseNetThreads = 256;  // network samplers
 
 template <typename T>
@@ -40,7 +43,9 @@ struct CompactArgs {
     uint64_t seed;
     StepControl* ctrl;
     uint64_t* status;  // pair kernel: one word per workgroup, kPairStatusStride apart
-    int32_t* list;          // dense list of accepted pairs: their stash slots
+    int32_t* list;          // accepted pairs' stash slots: dense, or one segment per pair workgroup
+    int32_t* seg_count;     // segmented: accepted pairs of each pair workgroup
+    int32_t n_seg;          // pair workgroups when segmented, else 0 (look-back)
     StashPair<T>* stash;    // accepted pairs with their values, per-wave regions
     double* chunk_prob;
     int64_t* chunk_clip;
@@ -270,12 +275,14 @@ __global__ __launch_bounds__(kChunk) void k_pair_compact(const CompactArgs<T> a)
         wbase += w < wave ? s_wcnt[w] : 0;
         total += s_wcnt[w];
     }
-    if (tid < 64) {
+    const bool seg = a.n_seg > 0;  // uniform
+    if (!seg && tid < 64) {
         const uint32_t ex =
             lookback_exclusive_wave<kPairStatusStride>(a.status, blk, E, (uint32_t)total, &ctrl->scan_fault_epoch);
         if (tid == 0) s_prefix = (int)ex;
     }
     if (tid == 0) {
+        if (seg) a.seg_count[blk] = total;
         double p = 0.0;
         long long cl = 0, in = 0;
         for (int w = 0; w < kChunk / 64; ++w) {
@@ -288,9 +295,90 @@ __global__ __launch_bounds__(kChunk) void k_pair_compact(const CompactArgs<T> a)
         a.chunk_inv[blk] = in;
     }
     __syncthreads();
-    int32_t* dst = a.list + s_prefix + wbase;
+    int32_t* dst = a.list + (seg ? blk * kChunk * G : (int64_t)s_prefix) + wbase;
     for (int i = lane; i < n_stage; i += 64) dst[i] = slot0 + i;
-    if (tid == 0 && blk == (int64_t)gridDim.x - 1) ctrl->n_accepted = (uint32_t)(s_prefix + total);
+    if (!seg && tid == 0 && blk == (int64_t)gridDim.x - 1) ctrl->n_accepted = (uint32_t)(s_prefix + total);
+}
+
+// Segmented list: prefix sums over the pair workgroups' counts, computed by
+// every collide workgroup instead of a look-back chain in the pair kernel
+// (whose workgroups, finishing together, would wait for one another).
+// Thread t of NT takes counts [P t, P (t + 1)), P = kSegMax / NT; s receives
+// the n <= kSegMax exclusive prefixes.  Called by every thread; returns the
+// total.
+constexpr int kSegMax = 4096;
+
+template <int NT>
+__device__ __forceinline__ int32_t seg_prefix(const int32_t* cnt, int n, int32_t* s, int32_t* s_wtot) {
+    constexpr int kSegPerThread = kSegMax / NT;
+    const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
+    const int k0 = tid * kSegPerThread;
+    int32_t v[kSegPerThread];
+#pragma unroll
+    for (int i = 0; i < kSegPerThread; ++i) v[i] = k0 + i < n ? cnt[k0 + i] : 0;
+    int32_t run = 0;
+#pragma unroll
+    for (int i = 0; i < kSegPerThread; ++i) {
+        const int32_t c = v[i];
+        v[i] = run;
+        run += c;
+    }
+    int32_t incl = run;  // inclusive scan of the thread totals over the wave
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int32_t y = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += y;
+    }
+    int32_t excl = incl - run, total;
+    if constexpr (NT > 64) {
+        if (lane == 63) s_wtot[wave] = incl;
+        __syncthreads();
+        int32_t wb = 0;
+        total = 0;
+#pragma unroll
+        for (int w = 0; w < NT / 64; ++w) {
+            wb += w < wave ? s_wtot[w] : 0;
+            total += s_wtot[w];
+        }
+        excl += wb;
+    } else {
+        total = __shfl(incl, 63, 64);
+    }
+#pragma unroll
+    for (int i = 0; i < kSegPerThread; ++i)
+        if (k0 + i < n) s[k0 + i] = excl + v[i];
+    __syncthreads();
+    return total;
+}
+
+// The segment holding dense position q is the last b with s[b] <= q (empty
+// segments share their prefix with the next one).  seg_bsearch: binary
+// search in [lo, hi] given s[lo] <= q.  seg_gallop: from b0 with s[b0] <= q,
+// probes b0 + 1, + 2, + 4, ... first: within a wave the positions are
+// consecutive, so that from the wave's first segment the answer is near.
+__device__ __forceinline__ int seg_bsearch(const int32_t* s, int lo, int hi, int32_t q) {
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s[mid] <= q)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ int seg_gallop(const int32_t* s, int n, int b0, int32_t q) {
+    int lo = b0, hi = n - 1;
+    for (int step = 1;; step <<= 1) {
+        const int probe = b0 + step;
+        if (probe >= n) break;
+        if (s[probe] > q) {
+            hi = probe - 1;
+            break;
+        }
+        lo = probe;
+    }
+    return seg_bsearch(s, lo, hi, q);
 }
 
 // Network samplers resolve the pairs outside the network's domain in place
@@ -305,6 +393,8 @@ __global__ __launch_bounds__(SAMP == CS_SAMPLER_PLAIN ? kDenseThreads : kDenseNe
     __shared__ NetLds<SAMP> s_net;
     __shared__ double s_d[2 * (NT / 64)];
     __shared__ long long s_fbc[NT / 64];
+    __shared__ int32_t s_wtot[NT / 64];
+    extern __shared__ int32_t s_seg[];  // segmented: the n_seg prefixes
     const int tid = threadIdx.x;
     const int lane = lane_id();
     const int wave = tid >> 6;
@@ -314,7 +404,18 @@ __global__ __launch_bounds__(SAMP == CS_SAMPLER_PLAIN ? kDenseThreads : kDenseNe
     const uint32_t E = ctrl->epoch;
     const uint64_t step = ctrl->step;
     const bool layout_ok = ctrl->layout_epoch != E && ctrl->scan_fault_epoch != E;
-    const int64_t A = layout_ok ? (int64_t)ctrl->n_accepted : 0;
+    const bool seg = a.n_seg > 0;  // uniform
+    int64_t A;
+    if (seg) {
+        // (the counts are read whatever the layout, so that their reads need
+        // not wait for the control block's)
+        const int32_t total = seg_prefix<NT>(a.seg_count, a.n_seg, s_seg, s_wtot);
+        A = layout_ok ? (int64_t)total : 0;
+        if (blockIdx.x == 0 && tid == 0) ctrl->n_accepted = (uint32_t)A;
+    } else {
+        A = layout_ok ? (int64_t)ctrl->n_accepted : 0;
+    }
+    const int64_t seg_len = (int64_t)kChunk * a.chunks_per_block;
     const int64_t stride = (int64_t)gridDim.x * NT;
     const int64_t n_iter = (A + stride - 1) / stride;  // uniform over the grid
     CollideSums sums;
@@ -322,7 +423,19 @@ __global__ __launch_bounds__(SAMP == CS_SAMPLER_PLAIN ? kDenseThreads : kDenseNe
         const int64_t q = it * stride + (int64_t)blockIdx.x * NT + tid;
         const bool active = q < A;
         if (!__any(active)) break;
-        const int32_t slot = active ? a.list[q] : 0;
+        // lane 0 holds the wave's smallest position, and is active if any
+        // lane is: its segment, searched once per wave, starts every lane's
+        // search
+        const int b_wave = seg ? seg_bsearch(s_seg, 0, a.n_seg - 1, __builtin_amdgcn_readfirstlane((int32_t)q)) : 0;
+        int32_t slot = 0;
+        if (active) {
+            int64_t li = q;
+            if (seg) {
+                const int b = seg_gallop(s_seg, a.n_seg, b_wave, (int32_t)q);
+                li = b * seg_len + (q - s_seg[b]);
+            }
+            slot = a.list[li];
+        }
         if constexpr (!NET)
             collide_stash<T>(a.pt, active, a.stash + slot, a.seed, step, sums);
         else
@@ -357,6 +470,13 @@ int64_t compact_pair_blocks(const StepShape& s) {
     return s.n_chunks > 0 ? (s.n_chunks + G - 1) / G : 0;
 }
 
+// list entries: one segment of kChunk G per pair workgroup covers both the
+// dense and the segmented layout
+static int64_t compact_list_len(const StepShape& s) {
+    const int64_t seg = compact_pair_blocks(s) * kChunk * s.chunks_per_block;
+    return seg > s.n_chunks * kChunk ? seg : s.n_chunks * kChunk;
+}
+
 // stash slots: 64 G per wave of every pair workgroup (the largest entry
 // type, so that one workspace serves either storage type)
 static size_t compact_stash_bytes(const StepShape& s) {
@@ -368,7 +488,8 @@ size_t compact_workspace_bytes(const StepShape& s) {
     b += al(sizeof(int32_t) * (s.n_cells + 1));
     b += al(sizeof(uint32_t) * 4 * (s.n_cells > 0 ? s.n_cells : 1));
     b += al(sizeof(int32_t) * (s.n_chunks + 1));
-    b += al(sizeof(int32_t) * s.n_chunks * kChunk + 8);
+    b += al(sizeof(int32_t) * compact_list_len(s) + 8);
+    b += al(sizeof(int32_t) * (compact_pair_blocks(s) + 1));
     b += al(compact_stash_bytes(s) + 16);
     b += 3 * al(8 * (s.n_chunks > 0 ? s.n_chunks : 1));
     b += 3 * al(8 * s.n_collide_blocks);
@@ -387,7 +508,8 @@ void carve_compact_buffers(const Workspace& w, const StepShape& s, CompactBuffer
     b->pair_off = (int32_t*)take(sizeof(int32_t) * (s.n_cells + 1));
     b->cell_keys = (uint32_t*)take(sizeof(uint32_t) * 4 * (s.n_cells > 0 ? s.n_cells : 1));
     b->chunk_cell = (int32_t*)take(sizeof(int32_t) * (s.n_chunks + 1));
-    b->list = (int32_t*)take(sizeof(int32_t) * s.n_chunks * kChunk + 8);
+    b->list = (int32_t*)take(sizeof(int32_t) * compact_list_len(s) + 8);
+    b->seg_count = (int32_t*)take(sizeof(int32_t) * (compact_pair_blocks(s) + 1));
     b->stash = take(compact_stash_bytes(s) + 16);
     b->chunk_prob = (double*)take(8 * (s.n_chunks > 0 ? s.n_chunks : 1));
     b->chunk_clip = (int64_t*)take(8 * (s.n_chunks > 0 ? s.n_chunks : 1));
@@ -447,6 +569,7 @@ static hipError_t launch_compact_t(const StepShape& sh, const CompactBuffers& b,
     a.ctrl = b.ctrl;
     a.status = b.status + sh.n_prep_blocks;
     a.list = b.list;
+    a.seg_count = b.seg_count;
     a.stash = (StashPair<T>*)b.stash;
     a.chunk_prob = b.chunk_prob;
     a.chunk_clip = b.chunk_clip;
@@ -456,7 +579,12 @@ static hipError_t launch_compact_t(const StepShape& sh, const CompactBuffers& b,
     a.coll_fb = b.coll_fb;
     a.stats = p.stats;
     a.mlp = p.net;
+    constexpr int kCollideThreads = SAMP == CS_SAMPLER_PLAIN ? kDenseThreads : kDenseNetThreads;
     const int64_t n_pair_blocks = compact_pair_blocks(sh);
+    // segmented list whenever a collide workgroup can scan the pair
+    // workgroups' counts in one pass (at most kSegMax); else the pair
+    // kernel's look-back
+    a.n_seg = n_pair_blocks > 0 && n_pair_blocks <= kSegMax ? (int32_t)n_pair_blocks : 0;
     if (sh.n_chunks > 0) {
         if (sh.pairs_per_lane == 1)
             e = launch_pair_compact<T, 1>(a, n_pair_blocks, st);
@@ -468,8 +596,7 @@ static hipError_t launch_compact_t(const StepShape& sh, const CompactBuffers& b,
     }
     mark(2);
     mark(3);
-    k_collide_dense<T, SAMP><<<(unsigned)sh.n_collide_blocks,
-                               SAMP == CS_SAMPLER_PLAIN ? kDenseThreads : kDenseNetThreads, 0, st>>>(a);
+    k_collide_dense<T, SAMP><<<(unsigned)sh.n_collide_blocks, kCollideThreads, sizeof(int32_t) * (size_t)a.n_seg, st>>>(a);
     mark(4);
     FinalArgs f = {};
     f.ctrl = b.ctrl;

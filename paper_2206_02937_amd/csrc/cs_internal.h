@@ -110,6 +110,7 @@ struct CompactBuffers {
     int32_t* chunk_cell;  // [n_chunks + 1]
     int32_t* list;        // [n_chunks * kChunk] stash slots of the accepted pairs, dense (workgroup, wave, pair order)
     void* stash;          // accepted pairs with their particle values: 64 G slots per pair-kernel wave
+    int32_t* seg_count;   // [pair workgroups + 1] accepted pairs per pair workgroup (segmented list)
     double* chunk_prob;   // [n_chunks]
     int64_t* chunk_clip;  // [n_chunks]
     int64_t* chunk_inv;   // [n_chunks]

@@ -281,6 +281,44 @@ def test_sample_plain_parity(ctx, orc, dtype):
     assert np.max(np.abs(r - r_ref) / r_ref) <= tol
 
 
+def test_compact_list_modes_identical(ctx):
+    """The compact strategy lists its accepted pairs in one of two ways: one
+    segment per pair workgroup whose prefix sums the collide kernel forms
+    (up to 4096 pair workgroups), or a dense list ordered by the pair
+    kernel's look-back (more workgroups).  A 68x68-cell grid (4624 chunks)
+    with one chunk per pair workgroup takes the look-back, with 16 the
+    segments; both match the fused strategy bitwise."""
+    import torch
+
+    from paper_2206_02937_amd import compton
+
+    p = plasma.grid(seed=21, nx=68, ny=68, per_cell=256)
+    n_chunks = int(np.minimum(np.diff(p.off_e), np.diff(p.off_g)).sum()) // 256
+    assert n_chunks > 4096
+    results = []
+    for strategy, g in (("fused", 0), ("compact", 1), ("compact", 16)):
+        ctx.set_strategy(strategy)
+        ctx.set_chunks_per_block(g)
+        ctx.set_pairs_per_lane(1 if strategy == "compact" else 0)
+        e_dev, g_dev, oe, og = compton.to_device(p)
+        stats = ctx.stats_buffer()
+        for s in range(2):
+            ctx.step(e_dev, g_dev, oe, og, p.dt, p.density_norm, p.seed, s, stats=stats)
+        torch.cuda.synchronize()
+        results.append((compton.to_host(e_dev), compton.to_host(g_dev), stats.cpu().numpy().copy()))
+    ctx.set_strategy("fused")
+    ctx.set_chunks_per_block(0)
+    ctx.set_pairs_per_lane(0)
+    e0, g0, s0 = results[0]
+    assert s0[1] > 0  # collisions happened
+    for e1, g1, s1 in results[1:]:
+        for k in "xyzw":
+            assert np.array_equal(e0[k], e1[k]), k
+            assert np.array_equal(g0[k], g1[k]), k
+        assert np.array_equal(s0[:8], s1[:8])
+        assert np.allclose(s0.view(np.float64)[8:11], s1.view(np.float64)[8:11], rtol=1e-13, atol=0)
+
+
 @pytest.mark.parametrize("workload", ["grid_small", "uneven_small", "unequal"])
 def test_strategies_bitwise_identical(ctx, workload):
     """Every kernel strategy (compact with 1, 2, 4 pairs per lane and several
