@@ -99,83 +99,112 @@ struct FragT<CS_SAMPLER_MLP_FP8> {
     typedef long type;
 };
 
-// One tile of 16 samples on one wave.  Every lane passes the features of
-// sample (lane % 16); every lane receives that sample's outputs.  frag, W1,
-// biases, W5 come from LDS.
-template <int PREC>
-__device__ __forceinline__ void mlp_tile(const typename FragT<PREC>::type* frag, const float* P_lds,
-                                         const float* scales, float f1, float f2, float& y0, float& y1) {
+// NTL tiles of 16 samples each on one wave, evaluated side by side (their
+// MFMA and SiLU chains are independent, so each hides the others' latency).
+// For tile k every lane passes the features of sample (lane % 16) in f1[k],
+// f2[k] and receives that sample's outputs in y0[k], y1[k].  frag, W1,
+// biases, W5 come from LDS.  Each tile's arithmetic is that of a lone tile.
+template <int PREC, int NTL>
+__device__ __forceinline__ void mlp_tiles(const typename FragT<PREC>::type* frag, const float* P_lds,
+                                          const float* scales, const float (&f1)[NTL], const float (&f2)[NTL],
+                                          float (&y0)[NTL], float (&y1)[NTL]) {
     const int lane = lane_id();
     const int g = lane >> 4;
-    float h[16];
+    float h[NTL][16];
 #pragma unroll
     for (int t = 0; t < 4; ++t)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int n = 16 * t + 4 * g + r;
-            h[4 * t + r] = silu_fast(fmaf(P_lds[cW1 + 2 * n + 1], f2, fmaf(P_lds[cW1 + 2 * n], f1, P_lds[cB1 + n])));
+            const float w1a = P_lds[cW1 + 2 * n], w1b = P_lds[cW1 + 2 * n + 1], b1 = P_lds[cB1 + n];
+#pragma unroll
+            for (int k = 0; k < NTL; ++k) h[k][4 * t + r] = silu_fast(fmaf(w1b, f2[k], fmaf(w1a, f1[k], b1)));
         }
     const int offB[3] = {cB2, cB3, cB4};
 #pragma unroll
     for (int L = 0; L < 3; ++L) {
-        typename FragT<PREC>::type B0, B1;
+        typename FragT<PREC>::type B0[NTL], B1[NTL];
         float sc = 1.0f;
         if constexpr (PREC == CS_SAMPLER_MLP_BF16) {
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                B0[e] = (__bf16)h[e];
-                B1[e] = (__bf16)h[8 + e];
-            }
+            for (int k = 0; k < NTL; ++k)
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    B0[k][e] = (__bf16)h[k][e];
+                    B1[k][e] = (__bf16)h[k][8 + e];
+                }
         } else {
             const float inv = 1.0f / scales[3 + L];
             sc = scales[L] * scales[3 + L];
-            uint64_t b0 = 0, b1 = 0;
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                b0 |= (uint64_t)to_e4m3(h[e] * inv) << (8 * e);
-                b1 |= (uint64_t)to_e4m3(h[8 + e] * inv) << (8 * e);
+            for (int k = 0; k < NTL; ++k) {
+                uint64_t b0 = 0, b1 = 0;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    b0 |= (uint64_t)to_e4m3(h[k][e] * inv) << (8 * e);
+                    b1 |= (uint64_t)to_e4m3(h[k][8 + e] * inv) << (8 * e);
+                }
+                B0[k] = (long)b0;
+                B1[k] = (long)b1;
             }
-            B0 = (long)b0;
-            B1 = (long)b1;
         }
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-            floatx4 acc;
-            if constexpr (PREC == CS_SAMPLER_MLP_BF16) {
+            const auto A0 = frag[((L * 4 + t) * 2 + 0) * 64 + lane];
+            const auto A1 = frag[((L * 4 + t) * 2 + 1) * 64 + lane];
+            float bias[4];
 #pragma unroll
-                for (int r = 0; r < 4; ++r) acc[r] = P_lds[offB[L] + 16 * t + 4 * g + r];
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(frag[((L * 4 + t) * 2 + 0) * 64 + lane], B0, acc, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(frag[((L * 4 + t) * 2 + 1) * 64 + lane], B1, acc, 0, 0, 0);
+            for (int r = 0; r < 4; ++r) bias[r] = P_lds[offB[L] + 16 * t + 4 * g + r];
 #pragma unroll
-                for (int r = 0; r < 4; ++r) h[4 * t + r] = silu_fast(acc[r]);
-            } else {
-                acc = {0.0f, 0.0f, 0.0f, 0.0f};
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(frag[((L * 4 + t) * 2 + 0) * 64 + lane], B0, acc, 0, 0,
-                                                                 0);
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(frag[((L * 4 + t) * 2 + 1) * 64 + lane], B1, acc, 0, 0,
-                                                                 0);
+            for (int k = 0; k < NTL; ++k) {
+                floatx4 acc;
+                if constexpr (PREC == CS_SAMPLER_MLP_BF16) {
 #pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    h[4 * t + r] = silu_fast(fmaf(acc[r], sc, P_lds[offB[L] + 16 * t + 4 * g + r]));
+                    for (int r = 0; r < 4; ++r) acc[r] = bias[r];
+                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A0, B0[k], acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A1, B1[k], acc, 0, 0, 0);
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) h[k][4 * t + r] = silu_fast(acc[r]);
+                } else {
+                    acc = {0.0f, 0.0f, 0.0f, 0.0f};
+                    acc = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(A0, B0[k], acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(A1, B1[k], acc, 0, 0, 0);
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) h[k][4 * t + r] = silu_fast(fmaf(acc[r], sc, bias[r]));
+                }
             }
         }
     }
-    float p0 = 0.0f, p1 = 0.0f;
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
+    for (int k = 0; k < NTL; ++k) {
+        float p0 = 0.0f, p1 = 0.0f;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int n = 16 * t + 4 * g + r;
-            p0 = fmaf(P_lds[cW5 + n], h[4 * t + r], p0);
-            p1 = fmaf(P_lds[cW5 + kMlpHidden + n], h[4 * t + r], p1);
-        }
-    // sum the four lane groups (fixed butterfly order)
-    p0 += __shfl_xor(p0, 16, 64);
-    p1 += __shfl_xor(p1, 16, 64);
-    p0 += __shfl_xor(p0, 32, 64);
-    p1 += __shfl_xor(p1, 32, 64);
-    y0 = p0 + P_lds[cB5];
-    y1 = p1 + P_lds[cB5 + 1];
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int n = 16 * t + 4 * g + r;
+                p0 = fmaf(P_lds[cW5 + n], h[k][4 * t + r], p0);
+                p1 = fmaf(P_lds[cW5 + kMlpHidden + n], h[k][4 * t + r], p1);
+            }
+        // sum the four lane groups (fixed butterfly order)
+        p0 += __shfl_xor(p0, 16, 64);
+        p1 += __shfl_xor(p1, 16, 64);
+        p0 += __shfl_xor(p0, 32, 64);
+        p1 += __shfl_xor(p1, 32, 64);
+        y0[k] = p0 + P_lds[cB5];
+        y1[k] = p1 + P_lds[cB5 + 1];
+    }
+}
+
+// One tile of 16 samples on one wave (mlp_tiles with one tile).
+template <int PREC>
+__device__ __forceinline__ void mlp_tile(const typename FragT<PREC>::type* frag, const float* P_lds,
+                                         const float* scales, float f1, float f2, float& y0, float& y1) {
+    const float a1[1] = {f1}, a2[1] = {f2};
+    float b0[1], b1[1];
+    mlp_tiles<PREC, 1>(frag, P_lds, scales, a1, a2, b0, b1);
+    y0 = b0[0];
+    y1 = b1[0];
 }
 
 // One sample per lane in FP32 (cos theta output only).  hb: this wave's
@@ -257,15 +286,23 @@ __device__ __forceinline__ float net_mu_hat(NetLds<SAMP>& s, const MlpDev& m, bo
     if constexpr (SAMP == CS_SAMPLER_MLP_F32) {
         if (__any(need)) out = mlp_lane_f32(m.params, s.h[wave_uniform((int)threadIdx.x >> 6)], f1, f2);
     } else if constexpr (SAMP == CS_SAMPLER_MLP_BF16 || SAMP == CS_SAMPLER_MLP_FP8) {
+        // the wave's four tiles two at a time, side by side; a pair of tiles
+        // none of whose samples is needed is skipped
         const int lane = lane_id();
 #pragma unroll 1
-        for (int tile = 0; tile < 4; ++tile) {
-            if (!__any(need && (lane >> 4) == tile)) continue;
-            const int src = 16 * tile + (lane & 15);
-            const float g1 = __shfl(f1, src, 64), g2 = __shfl(f2, src, 64);
-            float y0, y1;
-            mlp_tile<SAMP>(s.frag, s.P, s.sc, g1, g2, y0, y1);
-            if ((lane >> 4) == tile) out = y0;
+        for (int tile = 0; tile < 4; tile += 2) {
+            if (!__any(need && (lane >> 5) == (tile >> 1))) continue;
+            float g1[2], g2[2], y0[2], y1[2];
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                const int src = 16 * (tile + k) + (lane & 15);
+                g1[k] = __shfl(f1, src, 64);
+                g2[k] = __shfl(f2, src, 64);
+            }
+            mlp_tiles<SAMP, 2>(s.frag, s.P, s.sc, g1, g2, y0, y1);
+#pragma unroll
+            for (int k = 0; k < 2; ++k)
+                if ((lane >> 4) == tile + k) out = y0[k];
         }
     }
     return need ? out : 0.0f;
