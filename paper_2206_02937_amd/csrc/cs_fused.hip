@@ -333,18 +333,36 @@ __global__ __launch_bounds__(kFinalThreads) void k_finalize_step(const FinalArgs
     const uint32_t n_acc_raw = ctrl->n_accepted;
     double sp = 0.0, eb = 0.0, ea = 0.0;
     long long cl = 0, in = 0, co = 0, fb = 0;
-#pragma unroll 4
-    for (int64_t i = tid; i < a.n_a; i += kFinalThreads) {
-        sp += a.a_prob[i];
-        cl += a.a_clip[i];
-        in += a.a_inv[i];
-        if (a.a_coll) co += a.a_coll[i];
-    }
-#pragma unroll 4
-    for (int64_t i = tid; i < a.n_b; i += kFinalThreads) {
-        eb += a.b_eb[i];
-        ea += a.b_ea[i];
-        if (a.b_fb) fb += a.b_fb[i];
+    // both partial sets in one pass, four entries of each per thread at a
+    // time, every read of a batch issued before its sums (entries past an
+    // array's end read as zeros, which leaves the sums unchanged: each thread
+    // still adds its entries of an array in increasing order)
+    const int64_t n_ab = a.n_a > a.n_b ? a.n_a : a.n_b;
+    for (int64_t base = tid; base < n_ab; base += 4 * kFinalThreads) {
+        double vp[4], ve[4], va[4];
+        long long vc[4], vi[4], vo[4], vf[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int64_t i = base + (int64_t)k * kFinalThreads;
+            const bool ia = i < a.n_a, ib = i < a.n_b;
+            vp[k] = ia ? a.a_prob[i] : 0.0;
+            vc[k] = ia ? a.a_clip[i] : 0;
+            vi[k] = ia ? a.a_inv[i] : 0;
+            vo[k] = ia && a.a_coll ? a.a_coll[i] : 0;
+            ve[k] = ib ? a.b_eb[i] : 0.0;
+            va[k] = ib ? a.b_ea[i] : 0.0;
+            vf[k] = ib && a.b_fb ? a.b_fb[i] : 0;
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            sp += vp[k];
+            cl += vc[k];
+            in += vi[k];
+            co += vo[k];
+            eb += ve[k];
+            ea += va[k];
+            fb += vf[k];
+        }
     }
     const bool layout_ok = ctrl->layout_epoch != E && ctrl->scan_fault_epoch != E;
     sp = wave_sum(sp);
