@@ -257,7 +257,7 @@ def sampler_stage(ctx, p, net, sampler, n=1 << 22):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a design note, "
+        print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU sharding is a design note, "
                                    "not an implemented path", "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
     import torch

@@ -52,7 +52,7 @@ typedef enum {
     CS_OK = 0,
     CS_ERR_INVALID_ARG = 1, /* null pointer, bad size, dt <= 0, bad enum ...      */
     CS_ERR_LAYOUT = 2,      /* cell offsets not a valid layout (cs_check_layout) */
-    CS_ERR_UNSUPPORTED = 3, /* valid request this build does not handle         */
+    CS_ERR_UNSUPPORTED = 3, /* valid request this library does not handle       */
     CS_ERR_HIP = 4,         /* the HIP runtime reported an error                */
     CS_ERR_IO = 5,          /* file missing, unreadable or corrupt              */
     CS_ERR_NOT_READY = 6    /* MLP sampler requested without a usable network   */
@@ -183,7 +183,7 @@ CS_API cs_status cs_sample_plain(cs_ctx* ctx, cs_dtype dtype, const void* x, con
  * so the Compton relation holds exactly; inputs with x outside the trained
  * range fall back to the plain sampler.
  *
- * Widths: this build's kernels take exactly {2, 64, 64, 64, 64, 2}
+ * Widths: the library's kernels take exactly {2, 64, 64, 64, 64, 2}
  * (12,802 parameters); other widths give CS_ERR_UNSUPPORTED.
  * Parameter layout (host and device, FP32): per layer the weight matrix
  * W[n_out][n_in] row-major, then the bias[n_out].

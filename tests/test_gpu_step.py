@@ -337,11 +337,11 @@ def test_strategies_bitwise_identical(ctx, workload):
     else:
         p = _unequal_plasma(np.float32)
     # (strategy, pairs per lane, chunks per workgroup)
-    configs = [("compact", 4, 0), ("compact", 1, 0), ("compact", 2, 0), ("compact", 1, 16), ("compact", 2, 5),
+    variants = [("compact", 4, 0), ("compact", 1, 0), ("compact", 2, 0), ("compact", 1, 16), ("compact", 2, 5),
                ("compact", 4, 8), ("fused", 0, 0), ("fused", 0, 1), ("fused", 0, 3), ("fused", 0, 64),
                ("multi_kernel", 0, 0), ("per_cell", 0, 0)]
     results = []
-    for strategy, ppl, g in configs:
+    for strategy, ppl, g in variants:
         ctx.set_strategy(strategy)
         ctx.set_chunks_per_block(g)
         ctx.set_pairs_per_lane(ppl)
@@ -355,7 +355,7 @@ def test_strategies_bitwise_identical(ctx, workload):
     ctx.set_chunks_per_block(0)
     ctx.set_pairs_per_lane(0)
     e0, g0, s0 = results[0]
-    for (strategy, _, g), (e1, g1, s1) in zip(configs[1:], results[1:]):
+    for (strategy, _, g), (e1, g1, s1) in zip(variants[1:], results[1:]):
         for k in "xyzw":
             assert np.array_equal(e0[k], e1[k]), (strategy, g, k)
             assert np.array_equal(g0[k], g1[k]), (strategy, g, k)
