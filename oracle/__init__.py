@@ -6,7 +6,8 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
 (``paper_2206_02937_amd``) and never imports it.
 
 This module is a thin ctypes wrapper over ``liboracle.so`` (plain C, see
-``compton_oracle.c``); the MLP oracle lives in ``mlp_oracle.py`` (numpy FP64).
+``compton_oracle.c``); the MLP oracle lives in ``mlp_oracle.py`` (numpy FP64)
+and the cell-binning oracle in ``binning.py``.
 """
 import ctypes as C
 import os
