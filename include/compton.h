@@ -160,6 +160,30 @@ CS_API cs_status cs_check_layout(cs_ctx* ctx, const int64_t* off, int64_t n_cell
                           void* stream);
 
 /*
+ * cs_bin_particles -- group one species by collision cell, the staging that
+ * precedes pairing (Sec. 3.1: the particles of each cell are collected
+ * before pairs are formed), so that a caller need not sort on the host.
+ *
+ * cell[i] (int32, device) is particle i's cell.  The particles with a cell
+ * in [0, n_cells) are written to `out` in cell order, stable (inside a cell
+ * they keep their input order): out position off[c] + k holds the k-th
+ * particle of cell c.  off (int64 device array of n_cells + 1) receives the
+ * CSR offsets, off[n_cells] = number of such particles; `out` is then a
+ * valid species for cs_compton_step with these offsets.  Particles whose id
+ * lies outside [0, n_cells) belong to no cell: they are counted into
+ * *n_invalid (int64 device scalar, may be NULL) and placed after the cells,
+ * at out positions off[n_cells] .. n - 1, in input order.
+ *
+ * in and out: distinct device SoA arrays (x, y, z, w) of `dtype`, in.n =
+ * out.n = n with 0 <= n < 2^31; 0 <= n_cells < 2^31 - 1.  Caller-owned; the
+ * library keeps a scratch buffer in the context (about 40 n bytes, grown on
+ * demand: a growth synchronises `stream` first).  Asynchronous on `stream`.
+ * CS_ERR_INVALID_ARG for bad sizes, NULL or overlapping arrays.
+ */
+CS_API cs_status cs_bin_particles(cs_ctx* ctx, cs_dtype dtype, const int32_t* cell, cs_species in, cs_species out,
+                          int64_t* off, int64_t n_cells, int64_t* n_invalid, void* stream);
+
+/*
  * cs_sample_plain -- the conventional sampler on its own: for each i,
  * mu[i] = F^-1(u[i]; x[i]) with F the CDF of the rest-frame scattering cosine
  * under the Klein-Nishina law, and ratio[i] = eps'/eps = 1/(1 + x(1 - mu)).

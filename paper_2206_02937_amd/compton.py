@@ -76,6 +76,8 @@ def lib():
     L.cs_check_layout.restype = st
     L.cs_sample_plain.argtypes = [vp, C.c_int, vp, vp, i64, vp, vp, vp]
     L.cs_sample_plain.restype = st
+    L.cs_bin_particles.argtypes = [vp, C.c_int, vp, Species, Species, vp, i64, vp, vp]
+    L.cs_bin_particles.restype = st
     L.cs_set_option.argtypes = [vp, C.c_int, i64]
     L.cs_set_option.restype = st
     L.cs_get_option.argtypes = [vp, C.c_int, C.POINTER(i64)]
@@ -262,6 +264,24 @@ class Context:
               stream=None):
         """Capture one step into a replayable graph (see Graph)."""
         return Graph(self, e, g, off_e, off_g, dt, density_norm, seed, sampler, mlp, stats, stream)
+
+    def bin_particles(self, cell, species, n_cells, out=None, off=None, n_invalid=None, stream=None):
+        """Group one species by cell (cs_bin_particles).  cell: int32 device
+        tensor; species: dict of x, y, z, w device tensors.  Returns (out
+        species dict, int64 offsets of n_cells + 1, int64 n_invalid tensor of
+        one element); out from off[n_cells] on holds the particles with no
+        valid cell, in input order."""
+        import torch
+
+        if out is None:
+            out = {k: torch.empty_like(species[k]) for k in "xyzw"}
+        dev = species["x"].device
+        off = torch.empty(n_cells + 1, dtype=torch.int64, device=dev) if off is None else off
+        n_invalid = torch.zeros(1, dtype=torch.int64, device=dev) if n_invalid is None else n_invalid
+        rc = lib().cs_bin_particles(self._h, _dtype_code(species["x"]), _ptr(cell), _species(species),
+                                    _species(out), _ptr(off), n_cells, _ptr(n_invalid), _stream(stream))
+        self._check(rc)
+        return out, off, n_invalid
 
     def sample_plain(self, x, u, mu_out=None, ratio_out=None, stream=None):
         import torch

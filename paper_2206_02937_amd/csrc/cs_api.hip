@@ -121,10 +121,9 @@ cs_status cs_destroy(cs_ctx* ctx) {
     if (!ctx) return CS_ERR_INVALID_ARG;
     {
         DeviceGuard g(ctx->device);
-        if (ctx->ws.base) {
-            (void)hipDeviceSynchronize();
-            (void)hipFree(ctx->ws.base);
-        }
+        if (ctx->ws.base || ctx->bin_ws) (void)hipDeviceSynchronize();
+        if (ctx->ws.base) (void)hipFree(ctx->ws.base);
+        if (ctx->bin_ws) (void)hipFree(ctx->bin_ws);
         for (auto& ev : ctx->events)
             if (ev) (void)hipEventDestroy(ev);
         ctx->events.clear();
@@ -643,6 +642,54 @@ cs_status cs_sample_plain(cs_ctx* ctx, cs_dtype dtype, const void* x, const void
     DeviceGuard g(ctx->device);
     hipError_t e = cs::launch_sample_plain(dtype, x, u, n, mu_out, ratio_out, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "cs_sample_plain: launch");
+    ctx->last_error.clear();
+    return CS_OK;
+}
+
+cs_status cs_bin_particles(cs_ctx* ctx, cs_dtype dtype, const int32_t* cell, cs_species in, cs_species out,
+                           int64_t* off, int64_t n_cells, int64_t* n_invalid, void* stream) {
+    if (!ctx) return CS_ERR_INVALID_ARG;
+    if (dtype != CS_F32 && dtype != CS_F64) return fail(ctx, CS_ERR_INVALID_ARG, "cs_bin_particles: bad dtype");
+    const int64_t n = in.n;
+    if (n < 0 || n >= ((int64_t)1 << 31) || out.n != n)
+        return fail(ctx, CS_ERR_INVALID_ARG, "cs_bin_particles: need 0 <= in.n = out.n < 2^31");
+    if (n_cells < 0 || n_cells >= ((int64_t)1 << 31) - 1)
+        return fail(ctx, CS_ERR_INVALID_ARG, "cs_bin_particles: need 0 <= n_cells < 2^31 - 1");
+    if (!off) return fail(ctx, CS_ERR_INVALID_ARG, "cs_bin_particles: NULL offsets");
+    if (n > 0 && (!cell || !in.x || !in.y || !in.z || !in.w || !out.x || !out.y || !out.z || !out.w))
+        return fail(ctx, CS_ERR_INVALID_ARG, "cs_bin_particles: NULL array");
+    if (n > 0) {
+        const void* ins[4] = {in.x, in.y, in.z, in.w};
+        const void* outs[4] = {out.x, out.y, out.z, out.w};
+        for (int a = 0; a < 4; ++a)
+            for (int b = 0; b < 4; ++b)
+                if (ins[a] == outs[b]) return fail(ctx, CS_ERR_INVALID_ARG, "cs_bin_particles: in and out overlap");
+    }
+    DeviceGuard g(ctx->device);
+    hipStream_t st = (hipStream_t)stream;
+    const size_t want = cs::bin_workspace_bytes(n);
+    if (ctx->bin_bytes < want) {
+        // no queued binning may still use the old scratch
+        hipError_t e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return hip_fail(ctx, e, "cs_bin_particles: stream synchronize");
+        if (ctx->bin_ws) {
+            e = hipFree(ctx->bin_ws);
+            ctx->bin_ws = nullptr;
+            ctx->bin_bytes = 0;
+            if (e != hipSuccess) return hip_fail(ctx, e, "cs_bin_particles: hipFree");
+        }
+        const size_t grow = want + want / 4;
+        e = hipMalloc(&ctx->bin_ws, grow);
+        if (e != hipSuccess) {
+            ctx->bin_ws = nullptr;
+            return hip_fail(ctx, e, "cs_bin_particles: hipMalloc");
+        }
+        ctx->bin_bytes = grow;
+    }
+    void* const outp[4] = {out.x, out.y, out.z, out.w};
+    const void* const inp[4] = {in.x, in.y, in.z, in.w};
+    hipError_t e = cs::launch_bin(dtype, cell, n, n_cells, inp, outp, off, n_invalid, ctx->bin_ws, st);
+    if (e != hipSuccess) return hip_fail(ctx, e, "cs_bin_particles: launch");
     ctx->last_error.clear();
     return CS_OK;
 }

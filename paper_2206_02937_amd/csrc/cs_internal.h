@@ -181,6 +181,11 @@ hipError_t launch_cell(const StepShape& shape, const FusedBuffers& buf, const St
 hipError_t launch_check_layout(const int64_t* off, int64_t n_cells, int64_t n, int32_t* flag, hipStream_t stream);
 hipError_t launch_sample_plain(cs_dtype dtype, const void* x, const void* u, int64_t n, void* mu, void* ratio,
                                hipStream_t stream);
+// cell binning of one species (cs_bin.hip): workspace bytes for n particles,
+// and the launch (in/out: x, y, z, w arrays of the dtype)
+size_t bin_workspace_bytes(int64_t n);
+hipError_t launch_bin(cs_dtype dtype, const int32_t* cell, int64_t n, int64_t n_cells, const void* const in[4],
+                      void* const out[4], int64_t* off, int64_t* n_invalid, void* ws, hipStream_t stream);
 
 // ---------------------------------------------------------------------------
 // The sampler network (fixed widths 2 -> 64 x 4 -> 2).
@@ -232,4 +237,6 @@ struct cs_ctx {
     bool timing = false;
     int64_t timed_steps = 0;          // steps timed since enabling or the last read
     std::vector<hipEvent_t> events;   // kTimingRing slots of CS_STAGE_COUNT + 1 events
+    void* bin_ws = nullptr;           // cell-binning scratch, grown on demand
+    size_t bin_bytes = 0;
 };
