@@ -130,6 +130,43 @@ def cpu_baseline(p, seconds):
                       f"plasma, plain sampler, {elapsed:.1f} s"}
 
 
+def binning_stage(ctx, p, reps=20):
+    """Cell binning (cs_bin_particles) of the workload's electrons after a
+    seeded shuffle: particles/s and the HBM roofline of the whole call, whose
+    algorithmic bytes per particle are its cell id and four values read and
+    the four values written (plus 8 B per cell offset)."""
+    import numpy as np
+    import torch
+
+    rng = np.random.default_rng(1)
+    n = p.e["x"].size
+    cell = np.repeat(np.arange(p.n_cells, dtype=np.int32), np.diff(p.off_e))
+    perm = rng.permutation(n)
+    sp = {k: torch.from_numpy(np.ascontiguousarray(p.e[k][perm])).cuda() for k in "xyzw"}
+    cell_d = torch.from_numpy(cell[perm]).cuda()
+    out = {k: torch.empty_like(sp[k]) for k in "xyzw"}
+    off = torch.empty(p.n_cells + 1, dtype=torch.int64, device="cuda")
+    n_inv = torch.zeros(1, dtype=torch.int64, device="cuda")
+    for _ in range(3):
+        ctx.bin_particles(cell_d, sp, p.n_cells, out, off, n_inv)
+    torch.cuda.synchronize()
+    assert np.array_equal(off.cpu().numpy(), p.off_e), "binning offsets differ from the workload's"
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(reps):
+        ctx.bin_particles(cell_d, sp, p.n_cells, out, off, n_inv)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / reps
+    sb = sp["x"].element_size()
+    bytes_call = n * (4 + 8 * sb) + 8 * (p.n_cells + 1)
+    gbs = bytes_call / (ms * 1e-3) / 1e9
+    return {"particles_per_s": n / (ms * 1e-3), "ms_per_call": ms, "particles": n, "cells": p.n_cells,
+            "roofline": {"kernel": "cs_bin_particles (all passes)", "bound": "hbm", "achieved": gbs,
+                         "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS, "traffic": None,
+                         "bytes_per_launch": bytes_call, "avg_ms": ms}}
+
+
 def load_network(ctx, sampler):
     import numpy as np
     import torch
@@ -345,6 +382,8 @@ def main():
                     "peak": PEAK_MFMA_TFLOPS[args.sampler], "unit": "TFLOP/s",
                     "frac": tf / PEAK_MFMA_TFLOPS[args.sampler], "traffic": None,
                     "flops_per_launch": stage["n"] * MLP_MFMA_FLOPS, "avg_ms": t * 1e3}
+    print(json.dumps({"progress": "binning"}), flush=True)
+    binned = binning_stage(ctx, p)
     cpu = None
     if not args.no_cpu:
         print(json.dumps({"progress": "cpu baseline"}), flush=True)
@@ -386,6 +425,7 @@ def main():
         "sampler_stage_samples_per_s": {k: v for k, v in stage.items() if k not in ("n", "inputs")},
         "roofline": roof,
         "roofline_mlp": roof_mlp,
+        "binning": binned,
         "cpu_baseline": cpu,
         "last_stats": st,
     }
