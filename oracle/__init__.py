@@ -7,7 +7,8 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
 
 This module is a thin ctypes wrapper over ``liboracle.so`` (plain C, see
 ``compton_oracle.c``); the MLP oracle lives in ``mlp_oracle.py`` (numpy FP64)
-and the cell-binning oracle in ``binning.py``.
+the cell-binning oracle in ``binning.py`` and the probability-network
+oracle in ``pnet_oracle.py``.
 """
 import ctypes as C
 import os
