@@ -193,6 +193,49 @@ CS_API cs_status cs_bin_particles(cs_ctx* ctx, cs_dtype dtype, const int32_t* ce
 CS_API cs_status cs_sample_plain(cs_ctx* ctx, cs_dtype dtype, const void* x, const void* u, int64_t n,
                           void* mu_out, void* ratio_out, void* stream);
 
+/* ------------------------------------------- the probability network --- */
+
+/*
+ * The paper's own learned component (Sec. 3.2): a dense network that maps a
+ * candidate pair to its probability of interaction against the cell's
+ * majorant, y' = P / P_max, in place of the analytic evaluation.
+ *
+ * Inputs: CS_PNET_INPUTS FP32 values per pair, row-major [n][9]: photon
+ * momentum k (3), lepton momentum p (3), the majorant P_max, the weights
+ * w_e, w_g (code units).  Network 9 -> 9 -> 12 -> 9 -> 1, ReLU hidden layers,
+ * sigmoid output.  Parameters: CS_PNET_PARAMS FP32 values, per layer the
+ * weight matrix W[n_out][n_in] row-major, then the bias b[n_out].  All arrays
+ * are caller-owned device memory; every call is asynchronous on `stream`;
+ * CS_ERR_INVALID_ARG for NULL arrays or bad sizes.
+ */
+#define CS_PNET_INPUTS 9
+#define CS_PNET_PARAMS 337
+
+/* The analytic target of each pair: y = P / P_max = s(x) (1 - beta . k_hat)
+ * / 2 with x the rest-frame photon energy and s = sigma_KN / sigma_T (FP64
+ * arithmetic, Sec. 3.2), independent of P_max and the weights given that
+ * P_max bounds the pair's P = tau w_max s(x) (1 - beta . k_hat). */
+CS_API cs_status cs_pnet_target(cs_ctx* ctx, const float* in, int64_t n, float* y_out, void* stream);
+
+/* y_out[i] = the network's y' for pair i. */
+CS_API cs_status cs_pnet_forward(cs_ctx* ctx, const float* params, const float* in, int64_t n, float* y_out,
+                          void* stream);
+
+/* Gradient of the mean loss over the n pairs (MAE, the paper's, or MSE:
+ * mean |y' - t|, mean (y' - t)^2 / 2) with respect to the parameters into
+ * grad_out (CS_PNET_PARAMS), and the loss into *loss_out (device scalar, may
+ * be NULL).  Per-pair contributions are summed in a fixed order (the result
+ * does not depend on timing).  The context keeps a scratch of about 1.3 n
+ * bytes, grown on demand (a growth synchronises `stream`). */
+CS_API cs_status cs_pnet_grad(cs_ctx* ctx, const float* params, const float* in, const float* target, int64_t n,
+                       cs_loss loss, float* grad_out, float* loss_out, void* stream);
+
+/* One Adam step (Kingma & Ba: beta1 0.9, beta2 0.999, eps 1e-8, bias
+ * corrected) on the CS_PNET_PARAMS parameters with moments m, v (zero before
+ * step 1); t >= 1 the step number, lr > 0 (the paper's: 1e-3). */
+CS_API cs_status cs_pnet_adam(cs_ctx* ctx, float* params, const float* grad, float* m, float* v, int64_t t, float lr,
+                       void* stream);
+
 /* ------------------------------------------------- the learned sampler --- */
 
 /*

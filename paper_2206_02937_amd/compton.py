@@ -23,6 +23,7 @@ STRATEGY_NAMES = {v: k for k, v in STRATEGIES.items()}
 TUNE_MAX = 16
 OPT_STRATEGY, OPT_CHUNKS_PER_BLOCK, OPT_PAIRS_PER_LANE = 0, 1, 2
 LOSSES = {"mse": 0, "mae": 1}
+PNET_INPUTS, PNET_PARAMS = 9, 337  # the probability network (include/compton.h)
 
 
 class CSError(RuntimeError):
@@ -78,6 +79,14 @@ def lib():
     L.cs_sample_plain.restype = st
     L.cs_bin_particles.argtypes = [vp, C.c_int, vp, Species, Species, vp, i64, vp, vp]
     L.cs_bin_particles.restype = st
+    L.cs_pnet_target.argtypes = [vp, vp, i64, vp, vp]
+    L.cs_pnet_target.restype = st
+    L.cs_pnet_forward.argtypes = [vp, vp, vp, i64, vp, vp]
+    L.cs_pnet_forward.restype = st
+    L.cs_pnet_grad.argtypes = [vp, vp, vp, vp, i64, C.c_int, vp, vp, vp]
+    L.cs_pnet_grad.restype = st
+    L.cs_pnet_adam.argtypes = [vp, vp, vp, vp, vp, i64, C.c_float, vp]
+    L.cs_pnet_adam.restype = st
     L.cs_set_option.argtypes = [vp, C.c_int, i64]
     L.cs_set_option.restype = st
     L.cs_get_option.argtypes = [vp, C.c_int, C.POINTER(i64)]
@@ -282,6 +291,37 @@ class Context:
                                     _species(out), _ptr(off), n_cells, _ptr(n_invalid), _stream(stream))
         self._check(rc)
         return out, off, n_invalid
+
+    # -- the probability network (inputs: float32 device tensor [n, 9]) --
+    def pnet_target(self, inputs, y_out=None, stream=None):
+        import torch
+
+        n = inputs.shape[0]
+        y_out = torch.empty(n, dtype=torch.float32, device=inputs.device) if y_out is None else y_out
+        self._check(lib().cs_pnet_target(self._h, _ptr(inputs), n, _ptr(y_out), _stream(stream)))
+        return y_out
+
+    def pnet_forward(self, params, inputs, y_out=None, stream=None):
+        import torch
+
+        n = inputs.shape[0]
+        y_out = torch.empty(n, dtype=torch.float32, device=inputs.device) if y_out is None else y_out
+        self._check(lib().cs_pnet_forward(self._h, _ptr(params), _ptr(inputs), n, _ptr(y_out), _stream(stream)))
+        return y_out
+
+    def pnet_grad(self, params, inputs, target, loss="mae", grad_out=None, loss_out=None, stream=None):
+        import torch
+
+        grad_out = torch.empty(PNET_PARAMS, dtype=torch.float32, device=params.device) if grad_out is None \
+            else grad_out
+        loss_out = torch.empty(1, dtype=torch.float32, device=params.device) if loss_out is None else loss_out
+        self._check(lib().cs_pnet_grad(self._h, _ptr(params), _ptr(inputs), _ptr(target), inputs.shape[0],
+                                       LOSSES[loss], _ptr(grad_out), _ptr(loss_out), _stream(stream)))
+        return grad_out, loss_out
+
+    def pnet_adam(self, params, grad, m, v, t, lr=1e-3, stream=None):
+        self._check(lib().cs_pnet_adam(self._h, _ptr(params), _ptr(grad), _ptr(m), _ptr(v), t, lr,
+                                       _stream(stream)))
 
     def sample_plain(self, x, u, mu_out=None, ratio_out=None, stream=None):
         import torch

@@ -121,9 +121,10 @@ cs_status cs_destroy(cs_ctx* ctx) {
     if (!ctx) return CS_ERR_INVALID_ARG;
     {
         DeviceGuard g(ctx->device);
-        if (ctx->ws.base || ctx->bin_ws) (void)hipDeviceSynchronize();
+        if (ctx->ws.base || ctx->bin_ws || ctx->pnet_ws) (void)hipDeviceSynchronize();
         if (ctx->ws.base) (void)hipFree(ctx->ws.base);
         if (ctx->bin_ws) (void)hipFree(ctx->bin_ws);
+        if (ctx->pnet_ws) (void)hipFree(ctx->pnet_ws);
         for (auto& ev : ctx->events)
             if (ev) (void)hipEventDestroy(ev);
         ctx->events.clear();
@@ -690,6 +691,81 @@ cs_status cs_bin_particles(cs_ctx* ctx, cs_dtype dtype, const int32_t* cell, cs_
     const void* const inp[4] = {in.x, in.y, in.z, in.w};
     hipError_t e = cs::launch_bin(dtype, cell, n, n_cells, inp, outp, off, n_invalid, ctx->bin_ws, st);
     if (e != hipSuccess) return hip_fail(ctx, e, "cs_bin_particles: launch");
+    ctx->last_error.clear();
+    return CS_OK;
+}
+
+// Grow a context scratch buffer to `want` bytes (synchronises `stream` first
+// so that no queued kernel still uses the old one).
+static cs_status grow_scratch(cs_ctx* ctx, void** buf, size_t* bytes, size_t want, hipStream_t st,
+                              const char* what) {
+    if (*bytes >= want) return CS_OK;
+    hipError_t e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(ctx, e, what);
+    if (*buf) {
+        e = hipFree(*buf);
+        *buf = nullptr;
+        *bytes = 0;
+        if (e != hipSuccess) return hip_fail(ctx, e, what);
+    }
+    const size_t grow = want + want / 4;
+    e = hipMalloc(buf, grow);
+    if (e != hipSuccess) {
+        *buf = nullptr;
+        return hip_fail(ctx, e, what);
+    }
+    *bytes = grow;
+    return CS_OK;
+}
+
+cs_status cs_pnet_target(cs_ctx* ctx, const float* in, int64_t n, float* y, void* stream) {
+    if (!ctx) return CS_ERR_INVALID_ARG;
+    if (n < 0 || (n > 0 && (!in || !y))) return fail(ctx, CS_ERR_INVALID_ARG, "cs_pnet_target: bad arguments");
+    DeviceGuard g(ctx->device);
+    hipError_t e = cs::launch_pnet_target(in, n, y, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "cs_pnet_target: launch");
+    ctx->last_error.clear();
+    return CS_OK;
+}
+
+cs_status cs_pnet_forward(cs_ctx* ctx, const float* params, const float* in, int64_t n, float* y, void* stream) {
+    if (!ctx) return CS_ERR_INVALID_ARG;
+    if (n < 0 || !params || (n > 0 && (!in || !y)))
+        return fail(ctx, CS_ERR_INVALID_ARG, "cs_pnet_forward: bad arguments");
+    DeviceGuard g(ctx->device);
+    hipError_t e = cs::launch_pnet_forward(params, in, n, y, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "cs_pnet_forward: launch");
+    ctx->last_error.clear();
+    return CS_OK;
+}
+
+cs_status cs_pnet_grad(cs_ctx* ctx, const float* params, const float* in, const float* target, int64_t n,
+                       cs_loss loss, float* grad_out, float* loss_out, void* stream) {
+    if (!ctx) return CS_ERR_INVALID_ARG;
+    if (n < 0 || !params || !grad_out || (n > 0 && (!in || !target)) || (loss != CS_LOSS_MSE && loss != CS_LOSS_MAE))
+        return fail(ctx, CS_ERR_INVALID_ARG, "cs_pnet_grad: bad arguments");
+    DeviceGuard g(ctx->device);
+    hipStream_t st = (hipStream_t)stream;
+    cs_status rs = grow_scratch(ctx, &ctx->pnet_ws, &ctx->pnet_bytes, cs::pnet_workspace_bytes(n), st,
+                                "cs_pnet_grad: scratch");
+    if (rs != CS_OK) return rs;
+    hipError_t e =
+        cs::launch_pnet_grad(params, in, target, n, loss == CS_LOSS_MAE ? 1 : 0, grad_out, loss_out, ctx->pnet_ws, st);
+    if (e != hipSuccess) return hip_fail(ctx, e, "cs_pnet_grad: launch");
+    ctx->last_error.clear();
+    return CS_OK;
+}
+
+cs_status cs_pnet_adam(cs_ctx* ctx, float* params, const float* grad, float* m, float* v, int64_t t, float lr,
+                       void* stream) {
+    if (!ctx) return CS_ERR_INVALID_ARG;
+    if (!params || !grad || !m || !v || t < 1 || !(lr > 0.0f))
+        return fail(ctx, CS_ERR_INVALID_ARG, "cs_pnet_adam: bad arguments");
+    DeviceGuard g(ctx->device);
+    const float bc1 = (float)(1.0 - std::pow(0.9, (double)t));
+    const float bc2 = (float)(1.0 - std::pow(0.999, (double)t));
+    hipError_t e = cs::launch_pnet_adam(params, grad, m, v, lr, bc1, bc2, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "cs_pnet_adam: launch");
     ctx->last_error.clear();
     return CS_OK;
 }

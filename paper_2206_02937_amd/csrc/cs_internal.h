@@ -184,6 +184,14 @@ hipError_t launch_sample_plain(cs_dtype dtype, const void* x, const void* u, int
 // cell binning of one species (cs_bin.hip): workspace bytes for n particles,
 // and the launch (in/out: x, y, z, w arrays of the dtype)
 size_t bin_workspace_bytes(int64_t n);
+// probability network (cs_pnet.hip)
+size_t pnet_workspace_bytes(int64_t n);
+hipError_t launch_pnet_target(const float* in, int64_t n, float* y, hipStream_t st);
+hipError_t launch_pnet_forward(const float* params, const float* in, int64_t n, float* y, hipStream_t st);
+hipError_t launch_pnet_grad(const float* params, const float* in, const float* target, int64_t n, int mae,
+                            float* grad, float* loss, void* ws, hipStream_t st);
+hipError_t launch_pnet_adam(float* params, const float* grad, float* m, float* v, float lr, float bc1, float bc2,
+                            hipStream_t st);
 hipError_t launch_bin(cs_dtype dtype, const int32_t* cell, int64_t n, int64_t n_cells, const void* const in[4],
                       void* const out[4], int64_t* off, int64_t* n_invalid, void* ws, hipStream_t stream);
 
@@ -239,4 +247,6 @@ struct cs_ctx {
     std::vector<hipEvent_t> events;   // kTimingRing slots of CS_STAGE_COUNT + 1 events
     void* bin_ws = nullptr;           // cell-binning scratch, grown on demand
     size_t bin_bytes = 0;
+    void* pnet_ws = nullptr;          // probability-network gradient partials, grown on demand
+    size_t pnet_bytes = 0;
 };

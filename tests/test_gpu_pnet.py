@@ -1,0 +1,120 @@
+"""The probability network on the GPU (cs_pnet_*) against its FP64 oracle:
+the analytic target y = P / P_max, the forward pass, the gradient of the mean
+MSE and MAE losses over a ragged batch, one Adam step, the empty batch, and
+a short training run that lowers the loss."""
+import numpy as np
+import pytest
+
+from oracle import pnet_oracle as N
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2206_02937_amd import compton
+
+    c = compton.Context(0)
+    yield c
+    c.close()
+
+
+def _pairs(rng, n):
+    """Isotropic photons of energy 1e-3 .. 10 and leptons of |p| 0 .. 50 (m_e c)."""
+    def iso(m):
+        v = rng.standard_normal((m, 3))
+        return v / np.linalg.norm(v, axis=1, keepdims=True)
+    k = iso(n) * 10 ** rng.uniform(-3, 1, (n, 1))
+    p = iso(n) * rng.uniform(0, 50, (n, 1))
+    return N.inputs(k, p, rng.uniform(0.01, 1.0, n), rng.uniform(0.5, 2, n), rng.uniform(0.5, 2, n))
+
+
+def _dev(a):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def test_target_matches_oracle(ctx):
+    rng = np.random.default_rng(1)
+    X = _pairs(rng, 3000).astype(np.float32)
+    y = ctx.pnet_target(_dev(X)).cpu().numpy().astype(np.float64)
+    X64 = X.astype(np.float64)
+    ref = N.target_ratio(X64[:, 0:3], X64[:, 3:6])
+    assert np.all((ref >= 0) & (ref <= 1))
+    assert np.max(np.abs(y - ref) / np.maximum(ref, 1e-30)) <= 2e-7
+
+
+def test_forward_matches_oracle(ctx):
+    rng = np.random.default_rng(2)
+    params = N.glorot_uniform(rng) + rng.normal(0, 0.05, N.n_params())
+    params32 = params.astype(np.float32)
+    X = _pairs(rng, 1000).astype(np.float32)
+    y = ctx.pnet_forward(_dev(params32), _dev(X)).cpu().numpy()
+    ref = N.forward(params32.astype(np.float64), X.astype(np.float64))
+    assert np.max(np.abs(y - ref)) <= 1e-5
+
+
+@pytest.mark.parametrize("kind", ["mse", "mae"])
+def test_grad_matches_oracle(ctx, kind):
+    rng = np.random.default_rng(3)
+    params = (N.glorot_uniform(rng) + rng.normal(0, 0.05, N.n_params())).astype(np.float32)
+    n = 1000  # ragged: four workgroups, the last one partly filled
+    X = (_pairs(rng, n) * np.array([1, 1, 1, 0.1, 0.1, 0.1, 1, 1, 1])).astype(np.float32)
+    p64, X64 = params.astype(np.float64), X.astype(np.float64)
+    y = N.forward(p64, X64)
+    # MAE: targets well away from the outputs (no sign flips from rounding)
+    t = np.where(y > 0.5, y - 0.3, y + 0.3) if kind == "mae" else rng.uniform(0, 1, n)
+    g, l = ctx.pnet_grad(_dev(params), _dev(X), _dev(t), kind)
+    g = g.cpu().numpy().astype(np.float64)
+    g_ref, l_ref = N.grad(p64, X64, t.astype(np.float32).astype(np.float64), kind)
+    assert np.max(np.abs(g - g_ref)) <= 2e-5 * np.max(np.abs(g_ref))
+    assert float(l.cpu().numpy()[0]) == pytest.approx(l_ref, rel=1e-5)
+
+
+def test_adam_matches_oracle(ctx):
+    import torch
+
+    rng = np.random.default_rng(4)
+    p0 = rng.standard_normal(N.n_params()).astype(np.float32)
+    g = rng.standard_normal(N.n_params()).astype(np.float32) * 1e-2
+    m0 = (rng.standard_normal(N.n_params()) * 1e-3).astype(np.float32)
+    v0 = (rng.uniform(0, 1e-4, N.n_params())).astype(np.float32)
+    params, m, v = _dev(p0), _dev(m0), _dev(v0)
+    ctx.pnet_adam(params, _dev(g), m, v, 7, lr=1e-3)
+    torch.cuda.synchronize()
+    ref, m_ref, v_ref = N.adam_step(p0.astype(np.float64), g.astype(np.float64), m0, v0, 7, lr=1e-3)
+    assert np.allclose(params.cpu().numpy(), ref, rtol=0, atol=1e-6)
+    # FP32 arithmetic on terms of size ~1e-3 (m) and ~1e-4 (v), which may cancel
+    assert np.allclose(m.cpu().numpy(), m_ref, rtol=1e-6, atol=1e-9)
+    assert np.allclose(v.cpu().numpy(), v_ref, rtol=1e-6, atol=1e-11)
+
+
+def test_empty_batch(ctx):
+    import torch
+
+    params = _dev(np.ones(N.n_params()))
+    X = torch.empty((0, 9), dtype=torch.float32, device="cuda")
+    g, l = ctx.pnet_grad(params, X, torch.empty(0, dtype=torch.float32, device="cuda"), "mae")
+    assert np.all(g.cpu().numpy() == 0) and float(l.cpu().numpy()[0]) == 0.0
+
+
+def test_training_lowers_the_loss(ctx):
+    import torch
+
+    rng = np.random.default_rng(5)
+    X = _dev(_pairs(rng, 4096))
+    t = ctx.pnet_target(X)
+    params = _dev(N.glorot_uniform(rng))
+    m = torch.zeros_like(params)
+    v = torch.zeros_like(params)
+    losses = []
+    for step in range(1, 301):
+        g, l = ctx.pnet_grad(params, X, t, "mae")
+        ctx.pnet_adam(params, g, m, v, step, lr=1e-3)
+        if step in (1, 300):
+            losses.append(float(l.cpu().numpy()[0]))
+    assert losses[1] < 0.7 * losses[0], losses
