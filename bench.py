@@ -167,6 +167,49 @@ def binning_stage(ctx, p, reps=20):
                          "bytes_per_launch": bytes_call, "avg_ms": ms}}
 
 
+def pnet_stage(ctx, p, reps=20):
+    """The paper's probability network against the analytic ratio it
+    replaces, on the workload's 2^22 candidate pairs (photon, lepton, P_max and
+    weights per pair: nine FP32 inputs, 36 B in and 4 B out per pair).  The
+    network's parameters are Glorot-uniform: the timing does not depend on
+    them.  Roofline: HBM (40 B per pair) and FP32 vector arithmetic (612
+    multiply-adds counted as 2 flops: 2 (81 + 108 + 108 + 9))."""
+    import numpy as np
+    import torch
+
+    from paper_2206_02937_amd import train_pnet
+
+    n = min(p.e["x"].size, p.g["x"].size)
+    rows = np.stack([p.g["x"][:n], p.g["y"][:n], p.g["z"][:n], p.e["x"][:n], p.e["y"][:n], p.e["z"][:n],
+                     np.full(n, 0.5), p.e["w"][:n], p.g["w"][:n]], axis=1).astype(np.float32)
+    X = torch.from_numpy(rows).cuda()
+    params = torch.from_numpy(train_pnet.glorot_uniform(np.random.default_rng(0))).cuda()
+    y = torch.empty(n, dtype=torch.float32, device="cuda")
+
+    def timed(fn):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(reps):
+            fn()
+        ev1.record()
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1) / reps
+
+    ms_net = timed(lambda: ctx.pnet_forward(params, X, y))
+    ms_ana = timed(lambda: ctx.pnet_target(X, y))
+    gbs = n * 40 / (ms_net * 1e-3) / 1e9
+    tfs = n * 612 / (ms_net * 1e-3) / 1e12
+    return {"pairs": n, "network_pairs_per_s": n / (ms_net * 1e-3), "analytic_pairs_per_s": n / (ms_ana * 1e-3),
+            "network_ms": ms_net, "analytic_ms": ms_ana,
+            "roofline": {"kernel": "k_pnet_fwd", "bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS,
+                         "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS, "traffic": None,
+                         "bytes_per_launch": n * 40, "avg_ms": ms_net,
+                         "fp32_tflops": tfs, "fp32_frac": tfs / 157.3}}
+
+
 def load_network(ctx, sampler):
     import numpy as np
     import torch
@@ -384,6 +427,8 @@ def main():
                     "flops_per_launch": stage["n"] * MLP_MFMA_FLOPS, "avg_ms": t * 1e3}
     print(json.dumps({"progress": "binning"}), flush=True)
     binned = binning_stage(ctx, p)
+    print(json.dumps({"progress": "probability network"}), flush=True)
+    pnet = pnet_stage(ctx, p)
     cpu = None
     if not args.no_cpu:
         print(json.dumps({"progress": "cpu baseline"}), flush=True)
@@ -426,6 +471,7 @@ def main():
         "roofline": roof,
         "roofline_mlp": roof_mlp,
         "binning": binned,
+        "pnet": pnet,
         "cpu_baseline": cpu,
         "last_stats": st,
     }

@@ -118,3 +118,26 @@ def test_training_lowers_the_loss(ctx):
         if step in (1, 300):
             losses.append(float(l.cpu().numpy()[0]))
     assert losses[1] < 0.7 * losses[0], losses
+
+
+def test_training_driver_stages_and_export(ctx):
+    """A short run of the staged training driver: the loss falls, and the
+    exported parameters (scales folded into the first layer) give on inputs
+    in code units the outputs the trained network gives on scaled inputs."""
+    import torch
+
+    from paper_2206_02937_amd import train_pnet as T
+
+    X_eval = torch.from_numpy(T.head_on_inputs()).cuda()
+    y_eval = ctx.pnet_target(X_eval).cpu().numpy().astype(np.float64)
+    init = T.glorot_uniform(np.random.default_rng(11))
+    entries = []
+    params, report = T.train(ctx, init, T.STAGES, 150, 12, X_eval, y_eval, entries.append)
+    assert [e["stage"] for e in report] == [1, 2, 3]
+    assert report[-1]["train_mae"] < 0.35
+    X = np.random.default_rng(13).uniform(-1, 1, (500, 9)).astype(np.float32) * T.SCALE
+    scaled = params.copy()
+    scaled[:81] = (scaled[:81].reshape(9, 9) * T.SCALE[None, :]).ravel()
+    y_raw = ctx.pnet_forward(_dev(params), _dev(X)).cpu().numpy()
+    y_scaled = ctx.pnet_forward(_dev(scaled), _dev(X / T.SCALE)).cpu().numpy()
+    assert np.max(np.abs(y_raw - y_scaled)) <= 1e-5
