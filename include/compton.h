@@ -325,8 +325,9 @@ typedef enum {
     CS_OPT_STRATEGY = 0,         /* a cs_strategy                                        */
     CS_OPT_CHUNKS_PER_BLOCK = 1, /* fused: 256-pair chunks per workgroup; compact: the  */
                                  /* pair kernel's chunks per workgroup (rounded up to a  */
-                                 /* multiple of the pairs per lane, at most 16);         */
-                                 /* 0 = automatic                                        */
+                                 /* multiple of the pairs per lane, at most 32);         */
+                                 /* 0 = automatic (compact: the fewest with which every  */
+                                 /* pair workgroup is resident on the device at once)    */
     CS_OPT_PAIRS_PER_LANE = 2    /* compact: chunks each lane of the pair kernel takes   */
                                  /* at a time (1, 2 or 4), 0 = automatic (1)             */
 } cs_option;
@@ -351,8 +352,10 @@ typedef struct {
 } cs_tune_result;
 
 /* Pick the kernel strategy and its tile shape for this problem (the batching
- * of the Sec. 3.1 step over uneven cells): every candidate (fused with 1..32
- * chunks per workgroup, compact with 1, 2 or 4 pairs per lane) runs `reps` timed
+ * of the Sec. 3.1 step over uneven cells): every candidate (fused with 4..32
+ * chunks per workgroup, compact with 1 or 2 pairs per lane and several chunks
+ * per workgroup, among them the fewest that keep the pair grid resident at
+ * once) runs `reps` timed
  * steps on a private device copy of the particles, its result after one step
  * from the same state is checked to be bitwise identical to the first
  * candidate's (CS_ERR_HIP if not, which would be a library defect), and the

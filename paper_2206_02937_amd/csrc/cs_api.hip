@@ -194,7 +194,7 @@ struct Plan {
 };
 
 Plan plan_step(int64_t strategy, int64_t chunks_per_block, int64_t pairs_per_lane, int64_t n_cells, int64_t ne,
-               int64_t ng, cs_sampler sampler) {
+               int64_t ng, cs_sampler sampler, cs_dtype dtype) {
     Plan pl;
     pl.strategy = strategy;
     cs::StepShape& sh = pl.sh;
@@ -233,12 +233,11 @@ Plan plan_step(int64_t strategy, int64_t chunks_per_block, int64_t pairs_per_lan
         pl.bytes = cs::fused_workspace_bytes(sh);
     } else if (strategy == CS_STRATEGY_COMPACT) {
         // pair workgroups take G consecutive chunks, a multiple of the pairs
-        // per lane and at most kCompactMaxChunks (LDS staging of the
-        // accepted pairs); automatic: about 2048 workgroups (two rounds at
-        // the pair kernel's occupancy on a 256-CU device, so that the second
-        // round fills the SIMDs the first one leaves)
+        // per lane and at most kCompactMaxChunks (chunk_cell held one entry
+        // per lane); automatic: the fewest with which every pair workgroup
+        // is resident at once (one round, the waves paced)
         const int64_t ppl = sh.pairs_per_lane;
-        int64_t Gc = chunks_per_block > 0 ? chunks_per_block : sh.n_chunks / 2048;
+        int64_t Gc = chunks_per_block > 0 ? chunks_per_block : cs::compact_fit_chunks(dtype, ppl, sh.n_chunks);
         Gc = (Gc + ppl - 1) / ppl * ppl;
         if (Gc < ppl) Gc = ppl;
         if (Gc > cs::kCompactMaxChunks) Gc = cs::kCompactMaxChunks;
@@ -303,7 +302,8 @@ cs_status cs_compton_step(cs_ctx* ctx, cs_dtype dtype, cs_species electrons, cs_
     DeviceGuard g(ctx->device);
     if (!g.ok) return fail(ctx, CS_ERR_HIP, "cs_compton_step: cannot select device");
     hipStream_t st = (hipStream_t)stream;
-    const Plan pl = plan_step(ctx->strategy, ctx->chunks_per_block, ctx->pairs_per_lane, n_cells, electrons.n, photons.n, sampler);
+    const Plan pl = plan_step(ctx->strategy, ctx->chunks_per_block, ctx->pairs_per_lane, n_cells, electrons.n,
+                              photons.n, sampler, dtype);
     s = ensure_workspace(ctx, ctx->ws, pl.bytes, pl.status_words, st);
     if (s != CS_OK) return s;
     cs::StepParams p = make_params(dtype, electrons, photons, off_e, off_g, dt, density_norm, seed, step, sampler, mlp,
@@ -374,7 +374,8 @@ cs_status cs_graph_create(cs_ctx* ctx, cs_dtype dtype, cs_species electrons, cs_
     if (!g) return fail(ctx, CS_ERR_INVALID_ARG, "cs_graph_create: out of host memory");
     g->ctx = ctx;
     g->device = ctx->device;
-    const Plan pl = plan_step(ctx->strategy, ctx->chunks_per_block, ctx->pairs_per_lane, n_cells, electrons.n, photons.n, sampler);
+    const Plan pl = plan_step(ctx->strategy, ctx->chunks_per_block, ctx->pairs_per_lane, n_cells, electrons.n,
+                              photons.n, sampler, dtype);
     s = ensure_workspace(ctx, g->ws, pl.bytes, pl.status_words, st);
     if (s != CS_OK) {
         free_graph(g);
@@ -484,11 +485,23 @@ cs_status cs_autotune(cs_ctx* ctx, cs_dtype dtype, cs_species electrons, cs_spec
         cand_p[n_cand] = 0;
         cand_g[n_cand++] = gpb;
     }
-    // compact: (pairs per lane, chunks per pair workgroup)
+    // compact: (pairs per lane, chunks per pair workgroup), plus for one and
+    // two pairs per lane the fewest chunks with which the pair grid is
+    // resident at once
+    const int64_t n_chunks_tune = ((electrons.n < photons.n ? electrons.n : photons.n) + 255) / 256;
     for (const auto& pg : {std::pair<int, int>{1, 4}, {1, 8}, {1, 16}, {2, 8}, {2, 16}}) {
         cand_s[n_cand] = CS_STRATEGY_COMPACT;
         cand_p[n_cand] = pg.first;
         cand_g[n_cand++] = pg.second;
+    }
+    for (int ppl : {1, 2}) {
+        const int g = (int)cs::compact_fit_chunks(dtype, ppl, n_chunks_tune);
+        bool dup = false;
+        for (int c = 0; c < n_cand; ++c) dup = dup || (cand_s[c] == CS_STRATEGY_COMPACT && cand_p[c] == ppl && cand_g[c] == g);
+        if (dup) continue;
+        cand_s[n_cand] = CS_STRATEGY_COMPACT;
+        cand_p[n_cand] = ppl;
+        cand_g[n_cand++] = g;
     }
     float ms_best = 0.f;
     int best = -1;
@@ -499,7 +512,7 @@ cs_status cs_autotune(cs_ctx* ctx, cs_dtype dtype, cs_species electrons, cs_spec
     const int64_t saved_s = ctx->strategy, saved_g = ctx->chunks_per_block, saved_p = ctx->pairs_per_lane;
     cs_status rs = CS_OK;
     for (int c = 0; c < n_cand && e == hipSuccess && rs == CS_OK; ++c) {
-        const Plan pl = plan_step(cand_s[c], cand_g[c], cand_p[c], n_cells, electrons.n, photons.n, sampler);
+        const Plan pl = plan_step(cand_s[c], cand_g[c], cand_p[c], n_cells, electrons.n, photons.n, sampler, dtype);
         rs = ensure_workspace(ctx, ctx->ws, pl.bytes, pl.status_words, st);
         if (rs != CS_OK) break;
         const cs::StepParams p = make_params(dtype, pe, pg, off_e, off_g, dt, density_norm, seed, step, sampler, mlp,

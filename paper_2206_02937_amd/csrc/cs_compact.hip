@@ -536,6 +536,22 @@ static int64_t pair_resident_blocks() {
     return cached;
 }
 
+int64_t compact_fit_chunks(cs_dtype dtype, int64_t ppl, int64_t n_chunks) {
+    int64_t r;
+    if (dtype == CS_F64)
+        r = ppl == 1 ? pair_resident_blocks<double, 1>()
+                     : ppl == 2 ? pair_resident_blocks<double, 2>() : pair_resident_blocks<double, 4>();
+    else
+        r = ppl == 1 ? pair_resident_blocks<float, 1>()
+                     : ppl == 2 ? pair_resident_blocks<float, 2>() : pair_resident_blocks<float, 4>();
+    if (r <= 0) r = 1024;
+    int64_t g = (n_chunks + r - 1) / r;
+    g = (g + ppl - 1) / ppl * ppl;
+    if (g < ppl) g = ppl;
+    if (g > kCompactMaxChunks) g = kCompactMaxChunks / ppl * ppl;
+    return g;
+}
+
 template <typename T, int PPL>
 static hipError_t launch_pair_compact(CompactArgs<T> a, int64_t n_blocks, hipStream_t st) {
     a.balance = n_blocks <= pair_resident_blocks<T, PPL>() ? 1 : 0;

@@ -13,7 +13,7 @@
 namespace cs {
 
 constexpr int kChunk = 256;       // pairs per workgroup of the pair kernel
-constexpr int64_t kCompactMaxChunks = 16;  // compact pair kernel: chunks per workgroup
+constexpr int64_t kCompactMaxChunks = 32;  // compact pair kernel: chunks per workgroup
 constexpr int kPairStatusStride = 16;      // compact pair kernel: look-back status words apart (one 128-byte line each)
 constexpr int64_t kTimingRing = 512;  // steps whose stage events are kept
 constexpr int kScanItems = 1024;  // items per workgroup of the scan kernels
@@ -120,6 +120,10 @@ struct CompactBuffers {
 };
 
 int64_t compact_collide_threads(cs_sampler s);
+// compact: the fewest chunks per pair workgroup (a multiple of the pairs per
+// lane, at most kCompactMaxChunks) with which every pair workgroup of
+// n_chunks chunks is resident at once on the current device
+int64_t compact_fit_chunks(cs_dtype dtype, int64_t ppl, int64_t n_chunks);
 int64_t compact_pair_blocks(const StepShape& s);
 size_t fused_workspace_bytes(const StepShape& s);
 void carve_fused_buffers(const Workspace& w, const StepShape& s, FusedBuffers* b);
