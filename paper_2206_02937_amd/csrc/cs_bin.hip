@@ -4,7 +4,8 @@
 // the CSR offsets of the cells.
 //
 // The sort is a least-significant-digit radix sort of the cell ids with
-// 8-bit digits (one pass per byte of the largest id) that moves the
+// 8-bit digits, the lowest digit widened to up to 9 bits when that saves a
+// pass (17 bits of key: 9 + 8), that moves the
 // particles' values along with their keys, so that every access to the
 // values is a run of consecutive elements (never a gather from random
 // positions).  Every pass is stable, so the result is the stable sort;
@@ -13,13 +14,14 @@
 // after every valid particle.
 //
 //   per pass:
-//   k_bin_hist    per 4096-key tile, the 256 digit counts (LDS atomics)
+//   k_bin_hist    per 4096-key tile, the digit counts (LDS atomics)
 //   k_bin_scan    one workgroup per digit: exclusive prefix over the tiles of
 //                 that digit's counts, and the digit's total
 //   k_bin_scatter per tile: digit bases from the totals and the tile
 //                 prefixes; each wave takes 1024 consecutive keys in 16
 //                 chunks of 64, in order, and ranks each key among the
-//                 chunk's keys of the same digit by eight ballots; the tile,
+//                 chunk's keys of the same digit by one ballot per digit
+//                 bit; the tile,
 //                 ordered by digit in LDS, is then written out run by run
 //                 with the particles' four values
 //   k_bin_offsets off[c] = first sorted position with key >= c (binary
@@ -38,7 +40,7 @@ constexpr int kBinThreads = 256;
 constexpr int kBinChunks = 16;                             // 64-key chunks per wave
 constexpr int kBinWaveKeys = 64 * kBinChunks;             // 1024
 constexpr int kBinTile = kBinWaveKeys * (kBinThreads / 64);  // 4096
-constexpr int kBinDigits = 256;
+constexpr int kBinDigits = 512;  // at most: a 9-bit digit
 
 template <typename T>
 struct BinArrays {
@@ -59,20 +61,23 @@ __device__ __forceinline__ uint32_t bin_key(const uint32_t* keys, const int32_t*
 
 // hist[d * n_tiles + t] = keys of tile t whose digit is d
 __global__ __launch_bounds__(kBinThreads) void k_bin_hist(const uint32_t* keys, const int32_t* cell, int64_t n,
-                                                          int64_t n_cells, int shift, int64_t n_tiles,
+                                                          int64_t n_cells, int shift, int dbits, int64_t n_tiles,
                                                           uint32_t* hist) {
     __shared__ uint32_t s_cnt[kBinDigits];
     const int tid = threadIdx.x;
+    const uint32_t mask = (1u << dbits) - 1u;
+    const int nd = 1 << dbits;
     s_cnt[tid] = 0;
+    s_cnt[tid + kBinThreads] = 0;
     __syncthreads();
     const int64_t t0 = (int64_t)blockIdx.x * kBinTile;
 #pragma unroll 4
     for (int j = 0; j < kBinTile / kBinThreads; ++j) {
         const int64_t i = t0 + (int64_t)j * kBinThreads + tid;
-        if (i < n) atomicAdd(&s_cnt[(bin_key(keys, cell, n_cells, i) >> shift) & 0xFFu], 1u);
+        if (i < n) atomicAdd(&s_cnt[(bin_key(keys, cell, n_cells, i) >> shift) & mask], 1u);
     }
     __syncthreads();
-    hist[(int64_t)tid * n_tiles + blockIdx.x] = s_cnt[tid];
+    for (int d = tid; d < nd; d += kBinThreads) hist[(int64_t)d * n_tiles + blockIdx.x] = s_cnt[d];
 }
 
 // Workgroup d: exclusive prefix of hist[d][0 .. n_tiles) in place, the sum to
@@ -115,9 +120,10 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_scan(uint32_t* hist, int64_
 // access is coalesced.
 template <typename T>
 __global__ __launch_bounds__(kBinThreads) void k_bin_scatter(const uint32_t* keys_in, const int32_t* cell,
-                                                             int64_t n, int64_t n_cells, int shift, int64_t n_tiles,
-                                                             const uint32_t* hist, const uint32_t* totals,
-                                                             BinArrays<T> src, uint32_t* keys_out, BinOut<T> dst) {
+                                                             int64_t n, int64_t n_cells, int shift, int dbits,
+                                                             int64_t n_tiles, const uint32_t* hist,
+                                                             const uint32_t* totals, BinArrays<T> src,
+                                                             uint32_t* keys_out, BinOut<T> dst) {
     constexpr int kPer = kBinTile / kBinThreads;               // 16 outputs per thread
     __shared__ uint32_t s_cnt[kBinThreads / 64][kBinDigits];  // per wave counts, then running local bases
     __shared__ uint32_t s_toff[kBinDigits];                    // tile-local start of each digit's run
@@ -133,34 +139,52 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_scatter(const uint32_t* key
     const int64_t rem = n - t0;
     const int len = rem < kBinTile ? (int)rem : kBinTile;
     const int wl0 = wave * kBinWaveKeys;  // this wave's first key in the tile
+    const uint32_t mask = (1u << dbits) - 1u;
+    const int nd = 1 << dbits;
+    // thread t looks after digits 2t and 2t + 1 in the scans below
+    const int d0 = 2 * tid, d1 = 2 * tid + 1;
 #pragma unroll
-    for (int w = 0; w < kBinThreads / 64; ++w) s_cnt[w][tid] = 0;
-    // digit base over all tiles: exclusive prefix of the totals (thread = digit)
-    int unused;
-    const uint32_t dbase = (uint32_t)block_exclusive_scan((int)totals[tid], s_scan, &unused);
-    s_gbase[tid] = dbase + hist[(int64_t)tid * n_tiles + t];
+    for (int w = 0; w < kBinThreads / 64; ++w) {
+        s_cnt[w][d0] = 0;
+        s_cnt[w][d1] = 0;
+    }
+    // digit base over all tiles: exclusive prefix of the totals
+    {
+        const uint32_t t0v = d0 < nd ? totals[d0] : 0u, t1v = d1 < nd ? totals[d1] : 0u;
+        int unused;
+        const uint32_t ex = (uint32_t)block_exclusive_scan((int)(t0v + t1v), s_scan, &unused);
+        if (d0 < nd) s_gbase[d0] = ex + hist[(int64_t)d0 * n_tiles + t];
+        if (d1 < nd) s_gbase[d1] = ex + t0v + hist[(int64_t)d1 * n_tiles + t];
+    }
     uint32_t key[kBinChunks];
 #pragma unroll
     for (int c = 0; c < kBinChunks; ++c) {
         const int li = wl0 + c * 64 + lane;
         key[c] = li < len ? bin_key(keys_in, cell, n_cells, t0 + li) : 0u;
-        if (li < len) atomicAdd(&s_cnt[wave][(key[c] >> shift) & 0xFFu], 1u);
+        if (li < len) atomicAdd(&s_cnt[wave][(key[c] >> shift) & mask], 1u);
     }
     __syncthreads();
-    // thread = digit: the tile-local start of its run, then each wave's
-    // running base inside it (waves in key order)
+    // the tile-local start of each digit's run, then each wave's running
+    // base inside it (waves in key order)
     {
-        uint32_t tc = 0;
-#pragma unroll
-        for (int w = 0; w < kBinThreads / 64; ++w) tc += s_cnt[w][tid];
-        int unused2;
-        uint32_t run = (uint32_t)block_exclusive_scan((int)tc, s_scan, &unused2);
-        s_toff[tid] = run;
+        uint32_t tc0 = 0, tc1 = 0;
 #pragma unroll
         for (int w = 0; w < kBinThreads / 64; ++w) {
-            const uint32_t c = s_cnt[w][tid];
-            s_cnt[w][tid] = run;
-            run += c;
+            tc0 += s_cnt[w][d0];
+            tc1 += s_cnt[w][d1];
+        }
+        int unused2;
+        uint32_t run0 = (uint32_t)block_exclusive_scan((int)(tc0 + tc1), s_scan, &unused2);
+        uint32_t run1 = run0 + tc0;
+        s_toff[d0] = run0;
+        s_toff[d1] = run1;
+#pragma unroll
+        for (int w = 0; w < kBinThreads / 64; ++w) {
+            const uint32_t c0 = s_cnt[w][d0], c1 = s_cnt[w][d1];
+            s_cnt[w][d0] = run0;
+            s_cnt[w][d1] = run1;
+            run0 += c0;
+            run1 += c1;
         }
     }
     __syncthreads();
@@ -168,12 +192,14 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_scatter(const uint32_t* key
     for (int c = 0; c < kBinChunks; ++c) {
         const int li = wl0 + c * 64 + lane;  // tile-local index
         const bool act = li < len;
-        const uint32_t d = (key[c] >> shift) & 0xFFu;
+        const uint32_t d = (key[c] >> shift) & mask;
         uint64_t eq = __ballot(act);
 #pragma unroll
-        for (int b = 0; b < 8; ++b) {
-            const uint64_t m = __ballot(act && ((d >> b) & 1u));
-            eq &= ((d >> b) & 1u) ? m : ~m;
+        for (int b = 0; b < 9; ++b) {
+            if (b < dbits) {
+                const uint64_t m = __ballot(act && ((d >> b) & 1u));
+                eq &= ((d >> b) & 1u) ? m : ~m;
+            }
         }
         if (act) {
             const uint32_t lp = s_cnt[wave][d] + (uint32_t)__popcll(eq & below);
@@ -193,7 +219,7 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_scatter(const uint32_t* key
         pos[q] = 0;
         if (j < len) {
             const uint32_t k = s_key[j];
-            const uint32_t d = (k >> shift) & 0xFFu;
+            const uint32_t d = (k >> shift) & mask;
             pos[q] = s_gbase[d] + ((uint32_t)j - s_toff[d]);
             keys_out[pos[q]] = k;
         }
@@ -250,23 +276,25 @@ size_t bin_workspace_bytes(int64_t n) {
 template <typename T>
 static void launch_passes(const int32_t* cell, int64_t n, int64_t n_cells, const void* const in[4],
                           void* const out[4], uint32_t* const keys[2], void* const tmp[4], uint32_t* hist,
-                          uint32_t* totals, int passes, hipStream_t st) {
+                          uint32_t* totals, int passes, int low_bits, hipStream_t st) {
     const int64_t n_tiles = bin_tiles(n);
     const BinArrays<T> in_a = {(const T*)in[0], (const T*)in[1], (const T*)in[2], (const T*)in[3]};
     const BinOut<T> out_a = {(T*)out[0], (T*)out[1], (T*)out[2], (T*)out[3]};
     const BinOut<T> tmp_a = {(T*)tmp[0], (T*)tmp[1], (T*)tmp[2], (T*)tmp[3]};
     for (int ps = 0; ps < passes; ++ps) {
-        const int shift = 8 * ps;
+        // the first pass takes the low_bits lowest bits, the others 8 each
+        const int shift = ps == 0 ? 0 : low_bits + 8 * (ps - 1);
+        const int dbits = ps == 0 ? low_bits : 8;
         const uint32_t* kin = ps == 0 ? nullptr : keys[(ps - 1) & 1];
         // the last pass writes the output; before it the passes alternate
         // between the scratch copy and the output
         const BinOut<T> dst = ((passes - 1 - ps) & 1) == 0 ? out_a : tmp_a;
         const BinOut<T> prev = ((passes - ps) & 1) == 0 ? out_a : tmp_a;
         const BinArrays<T> src = ps == 0 ? in_a : BinArrays<T>{prev.x, prev.y, prev.z, prev.w};
-        k_bin_hist<<<(unsigned)n_tiles, kBinThreads, 0, st>>>(kin, cell, n, n_cells, shift, n_tiles, hist);
-        k_bin_scan<<<kBinDigits, kBinThreads, 0, st>>>(hist, n_tiles, totals);
-        k_bin_scatter<T><<<(unsigned)n_tiles, kBinThreads, 0, st>>>(kin, cell, n, n_cells, shift, n_tiles, hist,
-                                                                    totals, src, keys[ps & 1], dst);
+        k_bin_hist<<<(unsigned)n_tiles, kBinThreads, 0, st>>>(kin, cell, n, n_cells, shift, dbits, n_tiles, hist);
+        k_bin_scan<<<1u << dbits, kBinThreads, 0, st>>>(hist, n_tiles, totals);
+        k_bin_scatter<T><<<(unsigned)n_tiles, kBinThreads, 0, st>>>(kin, cell, n, n_cells, shift, dbits, n_tiles,
+                                                                    hist, totals, src, keys[ps & 1], dst);
     }
 }
 
@@ -290,15 +318,17 @@ hipError_t launch_bin(cs_dtype dtype, const int32_t* cell, int64_t n, int64_t n_
     uint32_t* totals = (uint32_t*)p;
 
     // the largest key is n_cells (the mark of an invalid id); at least one
-    // pass, which also writes the keys the offsets are read from
+    // pass, which also writes the keys the offsets are read from.  Passes of
+    // 8 bits, the lowest digit up to 9 bits wide: 17 bits take 9 + 8.
     int bits = 0;
     while (bits < 32 && ((uint64_t)n_cells >> bits) != 0) ++bits;
-    const int passes = bits > 8 ? (bits + 7) / 8 : 1;
+    const int passes = bits <= 9 ? 1 : (bits - 9 + 7) / 8 + 1;
+    const int low_bits = bits <= 9 ? (bits > 0 ? bits : 1) : bits - 8 * (passes - 1);
     if (n > 0) {
         if (dtype == CS_F32)
-            launch_passes<float>(cell, n, n_cells, in, out, keys, tmp, hist, totals, passes, st);
+            launch_passes<float>(cell, n, n_cells, in, out, keys, tmp, hist, totals, passes, low_bits, st);
         else
-            launch_passes<double>(cell, n, n_cells, in, out, keys, tmp, hist, totals, passes, st);
+            launch_passes<double>(cell, n, n_cells, in, out, keys, tmp, hist, totals, passes, low_bits, st);
     }
     const unsigned off_blocks = (unsigned)((n_cells + 1 + kBinThreads - 1) / kBinThreads);
     k_bin_offsets<<<off_blocks, kBinThreads, 0, st>>>(keys[(passes - 1) & 1], n, n_cells, off, n_invalid);
