@@ -328,13 +328,18 @@ typedef enum {
                                  /* multiple of the pairs per lane, at most 32);         */
                                  /* 0 = automatic (compact: the fewest with which every  */
                                  /* pair workgroup is resident on the device at once)    */
-    CS_OPT_PAIRS_PER_LANE = 2    /* compact: chunks each lane of the pair kernel takes   */
+    CS_OPT_PAIRS_PER_LANE = 2,   /* compact: chunks each lane of the pair kernel takes   */
                                  /* at a time (1, 2 or 4), 0 = automatic (1)             */
+    CS_OPT_WIDE_INDEX = 3        /* compact: 0 (default) = the pair kernel reads the     */
+                                 /* particles with 32-bit byte offsets whenever each     */
+                                 /* species has at most 2^32 / element-size entries,     */
+                                 /* 64-bit indexing otherwise; 1 = 64-bit indexing       */
+                                 /* always (same results)                                */
 } cs_option;
 
 /* Set / read a context option.  CS_ERR_INVALID_ARG for unknown options or
  * out-of-range values (chunks per block in [0, 4096]; pairs per lane 0, 1, 2
- * or 4). */
+ * or 4; wide index 0 or 1). */
 CS_API cs_status cs_set_option(cs_ctx* ctx, cs_option opt, int64_t value);
 CS_API cs_status cs_get_option(const cs_ctx* ctx, cs_option opt, int64_t* value);
 

@@ -21,7 +21,7 @@ SAMPLERS = {"plain": 0, "mlp_f32": 1, "mlp_bf16": 2, "mlp_fp8": 3}
 STRATEGIES = {"fused": 0, "multi_kernel": 1, "compact": 2, "per_cell": 3}
 STRATEGY_NAMES = {v: k for k, v in STRATEGIES.items()}
 TUNE_MAX = 16
-OPT_STRATEGY, OPT_CHUNKS_PER_BLOCK, OPT_PAIRS_PER_LANE = 0, 1, 2
+OPT_STRATEGY, OPT_CHUNKS_PER_BLOCK, OPT_PAIRS_PER_LANE, OPT_WIDE_INDEX = 0, 1, 2, 3
 LOSSES = {"mse": 0, "mae": 1}
 PNET_INPUTS, PNET_PARAMS = 9, 337  # the probability network (include/compton.h)
 
@@ -243,6 +243,9 @@ class Context:
 
     def set_pairs_per_lane(self, n):
         self.set_option(OPT_PAIRS_PER_LANE, n)
+
+    def set_wide_index(self, on):
+        self.set_option(OPT_WIDE_INDEX, 1 if on else 0)
 
     def set_stage_timing(self, enable):
         self._check(lib().cs_set_stage_timing(self._h, 1 if enable else 0))

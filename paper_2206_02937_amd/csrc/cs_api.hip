@@ -269,7 +269,7 @@ hipError_t launch_plan(const Plan& pl, const cs::Workspace& ws, const cs::StepPa
 
 cs::StepParams make_params(cs_dtype dtype, cs_species electrons, cs_species photons, const int64_t* off_e,
                            const int64_t* off_g, double dt, double density_norm, uint64_t seed, uint64_t step,
-                           cs_sampler sampler, const cs_mlp* mlp, cs_stats* stats) {
+                           cs_sampler sampler, const cs_mlp* mlp, cs_stats* stats, int64_t wide_index) {
     cs::StepParams p;
     p.dtype = dtype;
     p.e = electrons;
@@ -285,6 +285,7 @@ cs::StepParams make_params(cs_dtype dtype, cs_species electrons, cs_species phot
     p.stats = stats;
     p.events = nullptr;
     p.use_device_step = 0;
+    p.wide_index = wide_index ? 1 : 0;
     return p;
 }
 
@@ -307,7 +308,7 @@ cs_status cs_compton_step(cs_ctx* ctx, cs_dtype dtype, cs_species electrons, cs_
     s = ensure_workspace(ctx, ctx->ws, pl.bytes, pl.status_words, st);
     if (s != CS_OK) return s;
     cs::StepParams p = make_params(dtype, electrons, photons, off_e, off_g, dt, density_norm, seed, step, sampler, mlp,
-                                   stats);
+                                   stats, ctx->wide_index);
     if (ctx->timing) {
         const int64_t slot = ctx->timed_steps % cs::kTimingRing;
         p.events = ctx->events.data() + slot * (CS_STAGE_COUNT + 1);
@@ -382,7 +383,7 @@ cs_status cs_graph_create(cs_ctx* ctx, cs_dtype dtype, cs_species electrons, cs_
         return s;
     }
     cs::StepParams p = make_params(dtype, electrons, photons, off_e, off_g, dt, density_norm, seed, 0, sampler, mlp,
-                                   stats);
+                                   stats, ctx->wide_index);
     p.use_device_step = 1;
     hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) {
@@ -516,7 +517,7 @@ cs_status cs_autotune(cs_ctx* ctx, cs_dtype dtype, cs_species electrons, cs_spec
         rs = ensure_workspace(ctx, ctx->ws, pl.bytes, pl.status_words, st);
         if (rs != CS_OK) break;
         const cs::StepParams p = make_params(dtype, pe, pg, off_e, off_g, dt, density_norm, seed, step, sampler, mlp,
-                                             st_dev);
+                                             st_dev, ctx->wide_index);
         // correctness: one step from the caller's state, compared bitwise
         e = restore();
         if (e == hipSuccess) e = launch_plan(pl, ctx->ws, p, st);
@@ -603,6 +604,10 @@ cs_status cs_set_option(cs_ctx* ctx, cs_option opt, int64_t value) {
                 return fail(ctx, CS_ERR_INVALID_ARG, "cs_set_option: pairs per lane must be 0, 1, 2 or 4");
             ctx->pairs_per_lane = value;
             break;
+        case CS_OPT_WIDE_INDEX:
+            if (value != 0 && value != 1) return fail(ctx, CS_ERR_INVALID_ARG, "cs_set_option: wide index must be 0 or 1");
+            ctx->wide_index = value;
+            break;
         default:
             return fail(ctx, CS_ERR_INVALID_ARG, "cs_set_option: unknown option");
     }
@@ -621,6 +626,9 @@ cs_status cs_get_option(const cs_ctx* ctx, cs_option opt, int64_t* value) {
             return CS_OK;
         case CS_OPT_PAIRS_PER_LANE:
             *value = ctx->pairs_per_lane;
+            return CS_OK;
+        case CS_OPT_WIDE_INDEX:
+            *value = ctx->wide_index;
             return CS_OK;
         default:
             return CS_ERR_INVALID_ARG;

@@ -80,7 +80,7 @@ __device__ __forceinline__ X ld_uniform(const X* p, int64_t i) {
 // cells: a binary search per lane in global memory).  `cc`
 // holds chunk_cell[blk G + lane]; c0 is the step's first chunk relative to
 // blk G.  valid == false (uniform) yields inactive slots.
-template <typename T, int PPL>
+template <typename T, int PPL, bool O32>
 __device__ __forceinline__ void pair_fetch(const CompactArgs<T>& a, bool valid, int64_t j0, int c0, int cc,
                                            int32_t T_total, int tid, PairSlot (&sl)[PPL],
                                            PairRaw<T> (&raw)[PPL]) {
@@ -164,7 +164,7 @@ __device__ __forceinline__ void pair_fetch(const CompactArgs<T>& a, bool valid, 
             }
         }
         sl[q] = pair_index(act, e0, e1, g0, g1, key.x, key.y, key.z, key.w, (uint32_t)(t - po));
-        raw[q] = pair_load_all<T>(a.pt, sl[q]);
+        raw[q] = pair_load_all<T, O32>(a.pt, sl[q]);
     }
 }
 
@@ -196,7 +196,7 @@ __device__ __forceinline__ void balance_priority(int rem) {
 // (64 G slots) in the order it meets them; after the last step one look-back
 // places the workgroup's slots (wave 0's, then wave 1's, ...) in the dense
 // list, whose entry q names the stash slot of accepted pair q.
-template <typename T, int PPL>
+template <typename T, int PPL, bool O32>
 __global__ __launch_bounds__(kChunk) void k_pair_compact(const CompactArgs<T> a) {
     __shared__ double s_sig[kSigTabSegments * kSigTabTerms];
     __shared__ int s_wcnt[kChunk / 64];
@@ -246,15 +246,15 @@ __global__ __launch_bounds__(kChunk) void k_pair_compact(const CompactArgs<T> a)
     // two register sets in turn (no copies, which would wait for the reads)
     PairSlot sl_a[PPL], sl_b[PPL];
     PairRaw<T> raw_a[PPL], raw_b[PPL];
-    pair_fetch<T, PPL>(a, n_steps > 0, blk * G, 0, cc, T_total, tid, sl_a, raw_a);
+    pair_fetch<T, PPL, O32>(a, n_steps > 0, blk * G, 0, cc, T_total, tid, sl_a, raw_a);
     __syncthreads();  // s_sig
     for (int st = 0; st < n_steps; st += 2) {
-        pair_fetch<T, PPL>(a, st + 1 < n_steps, blk * G + (st + 1) * PPL, (st + 1) * PPL, cc, T_total, tid, sl_b,
+        pair_fetch<T, PPL, O32>(a, st + 1 < n_steps, blk * G + (st + 1) * PPL, (st + 1) * PPL, cc, T_total, tid, sl_b,
                            raw_b);
         if (a.balance) balance_priority(n_steps - st);
         physics(sl_a, raw_a);
         if (st + 1 >= n_steps) break;
-        pair_fetch<T, PPL>(a, st + 2 < n_steps, blk * G + (st + 2) * PPL, (st + 2) * PPL, cc, T_total, tid, sl_a,
+        pair_fetch<T, PPL, O32>(a, st + 2 < n_steps, blk * G + (st + 2) * PPL, (st + 2) * PPL, cc, T_total, tid, sl_a,
                            raw_a);
         if (a.balance) balance_priority(n_steps - st - 1);
         physics(sl_b, raw_b);
@@ -519,17 +519,17 @@ void carve_compact_buffers(const Workspace& w, const StepShape& s, CompactBuffer
     b->coll_fb = (int64_t*)take(8 * s.n_collide_blocks);
 }
 
-// Workgroups of k_pair_compact<T, PPL> resident at once on the current
+// Workgroups of k_pair_compact<T, PPL, O32> resident at once on the current
 // device (its compute units times the kernel's occupancy), computed once.
-template <typename T, int PPL>
+template <typename T, int PPL, bool O32 = true>
 static int64_t pair_resident_blocks() {
     static int64_t cached = -1;
     if (cached < 0) {
         int dev = 0, n_cu = 0, per_cu = 0;
         if (hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&k_pair_compact<T, PPL>),
-                                                         kChunk, 0) != hipSuccess)
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &per_cu, reinterpret_cast<const void*>(&k_pair_compact<T, PPL, O32>), kChunk, 0) != hipSuccess)
             return 0;  // unknown: no pacing
         cached = (int64_t)n_cu * per_cu;
     }
@@ -552,10 +552,20 @@ int64_t compact_fit_chunks(cs_dtype dtype, int64_t ppl, int64_t n_chunks) {
     return g;
 }
 
+// 32-bit byte offsets into the particle arrays whenever both species fit
+// (at most 2^32 / sizeof(T) elements) and `wide` is 0; 64-bit indexing
+// otherwise.
 template <typename T, int PPL>
-static hipError_t launch_pair_compact(CompactArgs<T> a, int64_t n_blocks, hipStream_t st) {
-    a.balance = n_blocks <= pair_resident_blocks<T, PPL>() ? 1 : 0;
-    k_pair_compact<T, PPL><<<(unsigned)n_blocks, kChunk, 0, st>>>(a);
+static hipError_t launch_pair_compact(CompactArgs<T> a, int64_t n_blocks, int64_t ne, int64_t ng, int wide,
+                                      hipStream_t st) {
+    constexpr int64_t kO32Max = ((int64_t)1 << 32) / (int64_t)sizeof(T);
+    if (!wide && ne <= kO32Max && ng <= kO32Max) {
+        a.balance = n_blocks <= pair_resident_blocks<T, PPL, true>() ? 1 : 0;
+        k_pair_compact<T, PPL, true><<<(unsigned)n_blocks, kChunk, 0, st>>>(a);
+    } else {
+        a.balance = n_blocks <= pair_resident_blocks<T, PPL, false>() ? 1 : 0;
+        k_pair_compact<T, PPL, false><<<(unsigned)n_blocks, kChunk, 0, st>>>(a);
+    }
     return hipGetLastError();
 }
 
@@ -603,11 +613,11 @@ static hipError_t launch_compact_t(const StepShape& sh, const CompactBuffers& b,
     a.n_seg = n_pair_blocks > 0 && n_pair_blocks <= kSegMax ? (int32_t)n_pair_blocks : 0;
     if (sh.n_chunks > 0) {
         if (sh.pairs_per_lane == 1)
-            e = launch_pair_compact<T, 1>(a, n_pair_blocks, st);
+            e = launch_pair_compact<T, 1>(a, n_pair_blocks, sh.ne, sh.ng, p.wide_index, st);
         else if (sh.pairs_per_lane == 2)
-            e = launch_pair_compact<T, 2>(a, n_pair_blocks, st);
+            e = launch_pair_compact<T, 2>(a, n_pair_blocks, sh.ne, sh.ng, p.wide_index, st);
         else
-            e = launch_pair_compact<T, 4>(a, n_pair_blocks, st);
+            e = launch_pair_compact<T, 4>(a, n_pair_blocks, sh.ne, sh.ng, p.wide_index, st);
         if (e != hipSuccess) return e;
     }
     mark(2);

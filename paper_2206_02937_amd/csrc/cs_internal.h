@@ -151,6 +151,7 @@ struct StepParams {
     cs_stats* stats;
     hipEvent_t* events;   // CS_STAGE_COUNT + 1 events to record between stages, or nullptr
     int use_device_step;  // 1: kernels take the step from the device counter (graph replay)
+    int wide_index;       // compact pair kernel: 1 = 64-bit particle indexing even where 32-bit offsets fit
 };
 
 // Launch every kernel of one step on `stream`; returns the HIP error of the
@@ -245,6 +246,7 @@ struct cs_ctx {
     int64_t strategy = CS_STRATEGY_FUSED;
     int64_t chunks_per_block = 0;  // 0: automatic
     int64_t pairs_per_lane = 0;    // compact pair kernel, 0: automatic
+    int64_t wide_index = 0;        // compact pair kernel, 1: always 64-bit particle indexing
     std::string last_error;
     bool timing = false;
     int64_t timed_steps = 0;          // steps timed since enabling or the last read

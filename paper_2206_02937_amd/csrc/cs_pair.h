@@ -97,22 +97,38 @@ __device__ __forceinline__ PairRaw<T> pair_load(const Particles<T>& a, const Pai
 }
 
 // The reads of pair_load issued by every lane: inactive lanes read element 0
-// (which exists whenever a pair does) and leave the values unused (the
-// physics reads them only for active slots), so that the number of reads in
-// flight does not depend on which lanes are active and no lane waits for
-// them before they are used.
-template <typename T>
+// (which exists whenever a pair does; pair_index leaves index 0 in inactive
+// slots) and leave the values unused (the physics reads them only for active
+// slots), so that the number of reads in flight does not depend on which
+// lanes are active and no lane waits for them before they are used.  With
+// O32 the byte offsets are formed as unsigned 32-bit values (one multiply
+// instead of a 64-bit shift-add per array; the loads take the array base in
+// scalar registers), valid while every species has at most 2^32 / sizeof(T)
+// elements -- the caller checks that.
+template <typename T, bool O32 = false>
 __device__ __forceinline__ PairRaw<T> pair_load_all(const Particles<T>& a, const PairSlot& s) {
-    const int32_t ie = s.active ? s.ie : 0, ig = s.active ? s.ig : 0;
     PairRaw<T> r;
-    r.p[0] = a.ex[ie];
-    r.p[1] = a.ey[ie];
-    r.p[2] = a.ez[ie];
-    r.k[0] = a.gx[ig];
-    r.k[1] = a.gy[ig];
-    r.k[2] = a.gz[ig];
-    r.we = a.ew[ie];
-    r.wg = a.gw[ig];
+    if constexpr (O32) {
+        const uint32_t oe = (uint32_t)s.ie * (uint32_t)sizeof(T), og = (uint32_t)s.ig * (uint32_t)sizeof(T);
+        auto at = [](const T* b, uint32_t o) { return *(const T*)((const char*)b + (uint64_t)o); };
+        r.p[0] = at(a.ex, oe);
+        r.p[1] = at(a.ey, oe);
+        r.p[2] = at(a.ez, oe);
+        r.k[0] = at(a.gx, og);
+        r.k[1] = at(a.gy, og);
+        r.k[2] = at(a.gz, og);
+        r.we = at(a.ew, oe);
+        r.wg = at(a.gw, og);
+    } else {
+        r.p[0] = a.ex[s.ie];
+        r.p[1] = a.ey[s.ie];
+        r.p[2] = a.ez[s.ie];
+        r.k[0] = a.gx[s.ig];
+        r.k[1] = a.gy[s.ig];
+        r.k[2] = a.gz[s.ig];
+        r.we = a.ew[s.ie];
+        r.wg = a.gw[s.ig];
+    }
     return r;
 }
 

@@ -287,7 +287,9 @@ def test_compact_list_modes_identical(ctx):
     (up to 4096 pair workgroups), or a dense list ordered by the pair
     kernel's look-back (more workgroups).  A 68x68-cell grid (4624 chunks)
     with one chunk per pair workgroup takes the look-back, with 16 the
-    segments; both match the fused strategy bitwise."""
+    segments; both match the fused strategy bitwise, and so does the pair
+    kernel forced to 64-bit particle indexing (it otherwise reads with
+    32-bit byte offsets)."""
     import torch
 
     from paper_2206_02937_amd import compton
@@ -296,10 +298,12 @@ def test_compact_list_modes_identical(ctx):
     n_chunks = int(np.minimum(np.diff(p.off_e), np.diff(p.off_g)).sum()) // 256
     assert n_chunks > 4096
     results = []
-    for strategy, g in (("fused", 0), ("compact", 1), ("compact", 16)):
+    for strategy, g, wide in (("fused", 0, 0), ("compact", 1, 0), ("compact", 16, 0), ("compact", 16, 1),
+                              ("compact", 1, 1)):
         ctx.set_strategy(strategy)
         ctx.set_chunks_per_block(g)
         ctx.set_pairs_per_lane(1 if strategy == "compact" else 0)
+        ctx.set_wide_index(wide)
         e_dev, g_dev, oe, og = compton.to_device(p)
         stats = ctx.stats_buffer()
         for s in range(2):
@@ -309,6 +313,8 @@ def test_compact_list_modes_identical(ctx):
     ctx.set_strategy("fused")
     ctx.set_chunks_per_block(0)
     ctx.set_pairs_per_lane(0)
+    ctx.set_wide_index(0)
+    assert ctx.get_option(compton.OPT_WIDE_INDEX) == 0
     e0, g0, s0 = results[0]
     assert s0[1] > 0  # collisions happened
     for e1, g1, s1 in results[1:]:
@@ -354,6 +360,8 @@ def test_strategies_bitwise_identical(ctx, workload):
     ctx.set_strategy("fused")
     ctx.set_chunks_per_block(0)
     ctx.set_pairs_per_lane(0)
+    ctx.set_wide_index(0)
+    assert ctx.get_option(compton.OPT_WIDE_INDEX) == 0
     e0, g0, s0 = results[0]
     for (strategy, _, g), (e1, g1, s1) in zip(variants[1:], results[1:]):
         for k in "xyzw":
