@@ -78,6 +78,11 @@ def lib():
         d, d, u64, u64, C.POINTER(OracleStats), vp, vp, vp, vp, vp,
     ]
     L.oracle_compton_step.restype = C.c_int
+    L.oracle_ntc_counts.argtypes = [C.c_int] + [vp] * 4 + [i64] + [vp] * 4 + [i64, vp, vp, i64, d, d, u64, u64, vp]
+    L.oracle_ntc_counts.restype = C.c_int
+    L.oracle_ntc_step.argtypes = ([C.c_int] + [vp] * 4 + [i64] + [vp] * 4 + [i64, vp, vp, i64, d, d, u64, u64,
+                                  C.POINTER(OracleStats)] + [vp] * 4)
+    L.oracle_ntc_step.restype = C.c_int
     L.oracle_scatter_uniforms.argtypes = [vp, i64, u64, u64, dp, dp]
     L.oracle_scatter_uniforms.restype = None
     L.oracle_num_threads.argtypes = []
@@ -272,5 +277,71 @@ def compton_step(e, g, off_e, off_g, dt, density_norm, seed, step, cells=None, d
         raise OracleError(f"invalid argument (code {rc})")
     out = st.as_dict()
     if diagnostics:
+        return out, diag
+    return out
+
+
+# the no-time-counter step
+# ----------------------------------------------------------------------------
+def _species_args(e, g, off_e, off_g):
+    dtype = e["x"].dtype
+    if dtype not in (np.float32, np.float64):
+        raise OracleError("storage dtype must be float32 or float64")
+    arrs = [e[c] for c in "xyzw"] + [g[c] for c in "xyzw"]
+    for a in arrs:
+        if a.dtype != dtype or not a.flags.c_contiguous:
+            raise OracleError("species arrays must share one dtype and be contiguous")
+    off_e = np.ascontiguousarray(off_e, dtype=np.int64)
+    off_g = np.ascontiguousarray(off_g, dtype=np.int64)
+    if off_g.size != off_e.size:
+        raise OracleError("offset arrays differ in length")
+    code = 1 if dtype == np.float64 else 0
+    head = [code, *[a.ctypes.data for a in arrs[:4]], e["x"].size, *[a.ctypes.data for a in arrs[4:]], g["x"].size,
+            off_e.ctypes.data, off_g.ctypes.data, off_e.size - 1]
+    return head, (off_e, off_g)
+
+
+def _ntc_rc(rc):
+    if rc == 2:
+        raise OracleError("cell offsets are not a valid layout")
+    if rc == 3:
+        raise OracleError("candidate count reaches 2^31")
+    if rc != 0:
+        raise OracleError(f"invalid argument (code {rc})")
+
+
+def ntc_counts(e, g, off_e, off_g, dt, density_norm, seed, step):
+    """Candidate count of every cell under no-time-counter selection
+    (N_e N_g P_max rounded stochastically; -1 where it would reach 2^31)."""
+    head, keep = _species_args(e, g, off_e, off_g)
+    counts = np.zeros(max(head[-1], 1), dtype=np.int64)
+    _ntc_rc(lib().oracle_ntc_counts(*head, float(dt), float(density_norm), int(seed), int(step), counts.ctypes.data))
+    return counts[:head[-1]]
+
+
+def ntc_step(e, g, off_e, off_g, dt, density_norm, seed, step, diagnostics=False):
+    """One no-time-counter Compton step (Bird's candidate selection, each
+    cell's candidates taken in order), in place on host numpy arrays (the
+    layout of compton_step).  Returns the stats dict (n_pairs = candidates,
+    sum_prob = sum of P / P_max), plus with ``diagnostics`` per-candidate
+    arrays ie, ig, ratio (P / P_max, -1 for invalid pairs), u (acceptance
+    uniform) and cell, candidates ordered cell by cell."""
+    head, keep = _species_args(e, g, off_e, off_g)
+    ptrs = [None] * 4
+    diag = None
+    if diagnostics:
+        counts = ntc_counts(e, g, off_e, off_g, dt, density_norm, seed, step)
+        if np.any(counts < 0):
+            raise OracleError("candidate count reaches 2^31")
+        n = int(counts.sum())
+        diag = {"ie": np.zeros(max(n, 1), dtype=np.int64), "ig": np.zeros(max(n, 1), dtype=np.int64),
+                "ratio": np.zeros(max(n, 1)), "u": np.zeros(max(n, 1))}
+        ptrs = [diag[k].ctypes.data for k in ("ie", "ig", "ratio", "u")]
+    st = OracleStats()
+    _ntc_rc(lib().oracle_ntc_step(*head, float(dt), float(density_norm), int(seed), int(step), C.byref(st), *ptrs))
+    out = st.as_dict()
+    if diagnostics:
+        diag = {k: v[:n] for k, v in diag.items()}
+        diag["cell"] = np.repeat(np.arange(counts.size, dtype=np.int64), counts)
         return out, diag
     return out

@@ -63,7 +63,9 @@ void oracle_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t
 }
 
 /* Stream purposes carried in the fourth counter word. */
-enum { PURPOSE_PAIR = 1, PURPOSE_COLLIDE = 2, PURPOSE_SCATTER = 3 };
+enum { PURPOSE_PAIR = 1, PURPOSE_COLLIDE = 2, PURPOSE_SCATTER = 3,
+       /* no-time-counter candidate selection */
+       PURPOSE_NTC_COUNT = 4, PURPOSE_NTC_PICK = 5, PURPOSE_NTC_SCATTER = 6, PURPOSE_NTC_WEIGHT = 7 };
 
 /* counter = (index lo, index hi, step lo, (step hi << 8) | purpose), key = seed */
 static void draw(uint64_t seed, uint64_t index, uint64_t step, uint32_t purpose, uint32_t out[4])
@@ -597,6 +599,217 @@ int oracle_compton_step(int dtype, void* ex, void* ey, void* ez, void* ew, int64
         s.energy_after += tallies[j].energy_after;
     }
     free(tallies);
+    if (stats) *stats = s;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* No-time-counter candidate selection (Sec. 3.1: the NTC method of Bird      */
+/* shortens each cell's pair list; the probability of Sec. 3.2).              */
+/* ------------------------------------------------------------------------- */
+/*
+ * Readings (the paper names the method and its bound only):
+ *   - The interaction probability of one electron-photon pair over the step is
+ *     P = dt n w_max s(x) flux (n = density_norm, w_max the larger of the two
+ *     weights); summed over all N_e N_g pairs of a cell it is the expected
+ *     number of collisions.  Since s <= 1 and flux <= 2, P never exceeds the
+ *     cell's bound P_max = 2 dt n W, W the largest valid weight among the
+ *     cell's particles (the paper's P_max with sigma_T c folded into n).
+ *   - The cell draws N_cand = N_e N_g P_max candidates, rounded
+ *     stochastically (floor, plus one with the fractional part's
+ *     probability), each an electron and a photon picked uniformly with
+ *     replacement, accepted with probability P / P_max.
+ *   - Candidates are taken in order, each one seeing the momenta the earlier
+ *     collisions of its cell left: Bird's sequential scheme.
+ * Random numbers (Philox4x32-10, counter as above): the count from
+ * draw(cell, COUNT); candidate l of cell c uses the index (c << 32) | l for
+ * PICK (electron: (r0 N_e) >> 32, photon: (r1 N_g) >> 32, acceptance uniform
+ * from r2, r3), SCATTER (u_mu, u_phi) and WEIGHT (the weight rule's uniform).
+ */
+static double cell_max_weight(int dtype, void* const E[4], void* const G[4], int64_t e0, int64_t ne, int64_t g0,
+                              int64_t ng)
+{
+    double w = 0.0;
+    for (int64_t i = 0; i < ne; ++i) {
+        double v = load_val(dtype, E[3], e0 + i);
+        if (isfinite(v) && v > w) w = v;
+    }
+    for (int64_t i = 0; i < ng; ++i) {
+        double v = load_val(dtype, G[3], g0 + i);
+        if (isfinite(v) && v > w) w = v;
+    }
+    return w;
+}
+
+/* Candidate count of one cell; -1 when it would reach 2^31. */
+static int64_t ntc_cell_count(int dtype, void* const E[4], void* const G[4], int64_t c, int64_t e0, int64_t ne,
+                              int64_t g0, int64_t ng, double dt, double density_norm, uint64_t seed, uint64_t step,
+                              double* p_max_out)
+{
+    *p_max_out = 0.0;
+    if (ne == 0 || ng == 0) return 0;
+    double p_max = 2.0 * dt * density_norm * cell_max_weight(dtype, E, G, e0, ne, g0, ng);
+    *p_max_out = p_max;
+    double n_exp = (double)ne * (double)ng * p_max;
+    if (!(n_exp < 2147483647.0)) return -1;
+    double fl = floor(n_exp);
+    uint32_t r[4];
+    draw(seed, (uint64_t)c, step, PURPOSE_NTC_COUNT, r);
+    return (int64_t)fl + (oracle_uniform53(r[0], r[1]) < n_exp - fl ? 1 : 0);
+}
+
+/* Candidate counts of every cell (-1 for a cell whose count would reach
+ * 2^31).  Returns 0, or 2 for an invalid layout, 1 for other bad arguments. */
+int oracle_ntc_counts(int dtype, void* ex, void* ey, void* ez, void* ew, int64_t ne, void* gx, void* gy, void* gz,
+                      void* gw, int64_t ng, const int64_t* cell_off_e, const int64_t* cell_off_g, int64_t n_cells,
+                      double dt, double density_norm, uint64_t seed, uint64_t step, int64_t* counts)
+{
+    if (dtype != 0 && dtype != 1) return 1;
+    if (n_cells < 0 || ne < 0 || ng < 0) return 1;
+    if (!(dt > 0.0) || !isfinite(dt) || !(density_norm >= 0.0) || !isfinite(density_norm)) return 1;
+    if (!check_offsets(cell_off_e, n_cells, ne) || !check_offsets(cell_off_g, n_cells, ng)) return 2;
+    void* E[4] = {ex, ey, ez, ew};
+    void* G[4] = {gx, gy, gz, gw};
+#pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < n_cells; ++c) {
+        double pm;
+        counts[c] = ntc_cell_count(dtype, E, G, c, cell_off_e[c], cell_off_e[c + 1] - cell_off_e[c], cell_off_g[c],
+                                   cell_off_g[c + 1] - cell_off_g[c], dt, density_norm, seed, step, &pm);
+    }
+    return 0;
+}
+
+/* Process the candidates of one cell in order.  Optional per-candidate
+ * diagnostics at base (the cell's first candidate number): electron and
+ * photon index, P / P_max and the acceptance uniform. */
+static void ntc_cell(int dtype, void* const E[4], void* const G[4], int64_t c, int64_t e0, int64_t ne, int64_t g0,
+                     int64_t ng, double dt, double density_norm, uint64_t seed, uint64_t step, int64_t n_cand,
+                     double p_max, cell_tally* t, int64_t base, int64_t* d_ie, int64_t* d_ig, double* d_ratio,
+                     double* d_u)
+{
+    for (int64_t l = 0; l < n_cand; ++l) {
+        uint64_t idx = ((uint64_t)c << 32) | (uint64_t)l;
+        uint32_t r[4];
+        draw(seed, idx, step, PURPOSE_NTC_PICK, r);
+        int64_t ie = e0 + (int64_t)(((uint64_t)r[0] * (uint64_t)ne) >> 32);
+        int64_t ig = g0 + (int64_t)(((uint64_t)r[1] * (uint64_t)ng) >> 32);
+        double u_c = oracle_uniform53(r[2], r[3]);
+        t->n_pairs++;
+        if (d_ie) {
+            d_ie[base + l] = ie;
+            d_ig[base + l] = ig;
+            d_ratio[base + l] = -1.0;
+            d_u[base + l] = u_c;
+        }
+        double p[3] = {load_val(dtype, E[0], ie), load_val(dtype, E[1], ie), load_val(dtype, E[2], ie)};
+        double k[3] = {load_val(dtype, G[0], ig), load_val(dtype, G[1], ig), load_val(dtype, G[2], ig)};
+        double we = load_val(dtype, E[3], ie), wg = load_val(dtype, G[3], ig);
+        if (!finite_nonneg_pair(p, we, k, wg)) {
+            t->n_invalid++;
+            continue;
+        }
+        double x, flux;
+        oracle_pair_invariants(p, k, &x, &flux);
+        double w_max = we > wg ? we : wg, w_min = we > wg ? wg : we;
+        double P = (x > 0.0) ? dt * density_norm * w_max * oracle_sigma_ratio(x) * flux : 0.0;
+        double ratio = P / p_max;
+        if (ratio > 1.0) t->n_clipped++;
+        t->sum_prob += ratio;
+        if (d_ratio) d_ratio[base + l] = ratio;
+        if (!(u_c < ratio)) continue;
+        t->n_collided++;
+        uint32_t s[4];
+        draw(seed, idx, step, PURPOSE_NTC_SCATTER, s);
+        double v = oracle_angle_icdf_v(oracle_uniform53(s[0], s[1]), x);
+        double p1[3], k1[3], eb, ea;
+        scatter_event_v(p, k, (quad)v, oracle_uniform53(s[2], s[3]), p1, k1, &eb, &ea);
+        t->energy_before += eb;
+        t->energy_after += ea;
+        int upd_e = 1, upd_g = 1;
+        if (we != wg) {
+            uint32_t q[4];
+            draw(seed, idx, step, PURPOSE_NTC_WEIGHT, q);
+            int heavier_moves = oracle_uniform53(q[0], q[1]) < w_min / w_max;
+            if (we > wg)
+                upd_e = heavier_moves;
+            else
+                upd_g = heavier_moves;
+        }
+        if (upd_e)
+            for (int d = 0; d < 3; ++d) store_val(dtype, E[d], ie, p1[d]);
+        if (upd_g)
+            for (int d = 0; d < 3; ++d) store_val(dtype, G[d], ig, k1[d]);
+    }
+}
+
+/*
+ * One no-time-counter step over every cell, in place.  stats as for the
+ * pairing step, with n_pairs = candidates, n_clipped = candidates whose
+ * P / P_max exceeded 1 (never, by the bound) and sum_prob = the sum of
+ * P / P_max over valid candidates (the expected collision count).  Optional
+ * per-candidate diagnostics (length = total candidates, cell by cell): see
+ * ntc_cell.  Returns 0, 2 for an invalid layout, 3 when a cell's or the
+ * step's candidate count would reach 2^31, 1 for other bad arguments.
+ */
+int oracle_ntc_step(int dtype, void* ex, void* ey, void* ez, void* ew, int64_t ne, void* gx, void* gy, void* gz,
+                    void* gw, int64_t ng, const int64_t* cell_off_e, const int64_t* cell_off_g, int64_t n_cells,
+                    double dt, double density_norm, uint64_t seed, uint64_t step, oracle_stats* stats,
+                    int64_t* d_ie, int64_t* d_ig, double* d_ratio, double* d_u)
+{
+    if (dtype != 0 && dtype != 1) return 1;
+    if (n_cells < 0 || ne < 0 || ng < 0) return 1;
+    if (!(dt > 0.0) || !isfinite(dt) || !(density_norm >= 0.0) || !isfinite(density_norm)) return 1;
+    if (!check_offsets(cell_off_e, n_cells, ne) || !check_offsets(cell_off_g, n_cells, ng)) return 2;
+    void* E[4] = {ex, ey, ez, ew};
+    void* G[4] = {gx, gy, gz, gw};
+    int64_t* counts = (int64_t*)calloc((size_t)(n_cells + 1), sizeof(int64_t));
+    double* p_max = (double*)calloc((size_t)(n_cells + 1), sizeof(double));
+    cell_tally* tallies = (cell_tally*)calloc((size_t)(n_cells > 0 ? n_cells : 1), sizeof(cell_tally));
+    if (!counts || !p_max || !tallies) {
+        free(counts);
+        free(p_max);
+        free(tallies);
+        return 1;
+    }
+    /* every count first (the weights do not change during the step) */
+#pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < n_cells; ++c)
+        counts[c] = ntc_cell_count(dtype, E, G, c, cell_off_e[c], cell_off_e[c + 1] - cell_off_e[c], cell_off_g[c],
+                                   cell_off_g[c + 1] - cell_off_g[c], dt, density_norm, seed, step, &p_max[c]);
+    int64_t total = 0;
+    int bad = 0;
+    for (int64_t c = 0; c < n_cells; ++c) {
+        if (counts[c] < 0) bad = 1;
+        total += counts[c] < 0 ? 0 : counts[c];
+    }
+    if (bad || total >= 2147483647) {
+        free(counts);
+        free(p_max);
+        free(tallies);
+        return 3;
+    }
+    int64_t* base = (int64_t*)calloc((size_t)(n_cells + 1), sizeof(int64_t));
+    for (int64_t c = 0; c < n_cells; ++c) base[c + 1] = base[c] + counts[c];
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t c = 0; c < n_cells; ++c)
+        ntc_cell(dtype, E, G, c, cell_off_e[c], cell_off_e[c + 1] - cell_off_e[c], cell_off_g[c],
+                 cell_off_g[c + 1] - cell_off_g[c], dt, density_norm, seed, step, counts[c], p_max[c], &tallies[c],
+                 base[c], d_ie, d_ig, d_ratio, d_u);
+    oracle_stats s;
+    memset(&s, 0, sizeof(s));
+    for (int64_t c = 0; c < n_cells; ++c) {
+        s.n_pairs += tallies[c].n_pairs;
+        s.n_collided += tallies[c].n_collided;
+        s.n_clipped += tallies[c].n_clipped;
+        s.n_invalid += tallies[c].n_invalid;
+        s.sum_prob += tallies[c].sum_prob;
+        s.energy_before += tallies[c].energy_before;
+        s.energy_after += tallies[c].energy_after;
+    }
+    free(counts);
+    free(p_max);
+    free(tallies);
+    free(base);
     if (stats) *stats = s;
     return 0;
 }
