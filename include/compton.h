@@ -159,6 +159,43 @@ CS_API cs_status cs_compton_step(cs_ctx* ctx, cs_dtype dtype, cs_species electro
 CS_API cs_status cs_check_layout(cs_ctx* ctx, const int64_t* off, int64_t n_cells, int64_t n_particles,
                           void* stream);
 
+/* cs_ntc_step -- one Compton step with no-time-counter candidate selection
+ * (Bird's NTC method, named in Sec. 3.1 as the way the module shortens each
+ * cell's pair list; probability and its bound from Sec. 3.2), in place of
+ * the 1:1 pairing of cs_compton_step.  Same arrays, layout, units and
+ * weight rule as cs_compton_step, plain inverse-CDF sampler.
+ *
+ * Per cell, with W the largest finite non-negative weight among its
+ * electrons and photons: P_max = 2 dt density_norm W; N_e N_g P_max
+ * candidates, rounded stochastically, each an electron and a photon picked
+ * uniformly with replacement and accepted with probability P / P_max,
+ * P = dt density_norm max(w_e, w_g) s(x) flux.  A cell's candidates are
+ * taken in order, each on the momenta the earlier collisions of its cell
+ * left; the GPU resolves candidates that share no particle in parallel, with
+ * the same result.  Random numbers: Philox4x32-10 keyed by `seed`, counters
+ * from (cell, candidate number, step, purpose).
+ *
+ * stats (nullable device pointer): n_pairs = candidates, n_collided,
+ * n_invalid (candidates with a non-finite value or a negative weight),
+ * n_clipped = candidates with P > P_max (none, by the bound), sum_prob = the
+ * sum of P / P_max over valid candidates (the expected collision count),
+ * energy sums as cs_compton_step.
+ *
+ * The call synchronises `stream` once (the host needs the step's candidate
+ * count to size the launches) and keeps scratch in the context: about
+ * 40 bytes per candidate, 30 per cell, and 32 per particle (tags that
+ * persist across calls).
+ * Errors: CS_ERR_INVALID_ARG (NULL arrays with n > 0, NULL offsets,
+ *         n_cells >= 2^31 - 1, dt <= 0 or non-finite, density_norm < 0),
+ *         CS_ERR_UNSUPPORTED (a species count >= 2^31, or 2^31 - 1 or more
+ *         candidates in the step; nothing was changed),
+ *         CS_ERR_LAYOUT (offsets not a valid layout; nothing was changed,
+ *         stats->layout_error = 1).
+ */
+CS_API cs_status cs_ntc_step(cs_ctx* ctx, cs_dtype dtype, cs_species electrons, cs_species photons,
+                             const int64_t* off_e, const int64_t* off_g, int64_t n_cells, double dt,
+                             double density_norm, uint64_t seed, uint64_t step, cs_stats* stats, void* stream);
+
 /*
  * cs_bin_particles -- group one species by collision cell, the staging that
  * precedes pairing (Sec. 3.1: the particles of each cell are collected

@@ -73,6 +73,8 @@ def lib():
     L.cs_sync.restype = st
     L.cs_compton_step.argtypes = [vp, C.c_int, Species, Species, vp, vp, i64, d, d, u64, u64, C.c_int, vp, vp, vp]
     L.cs_compton_step.restype = st
+    L.cs_ntc_step.argtypes = [vp, C.c_int, Species, Species, vp, vp, i64, d, d, u64, u64, vp, vp]
+    L.cs_ntc_step.restype = st
     L.cs_check_layout.argtypes = [vp, vp, i64, i64, vp]
     L.cs_check_layout.restype = st
     L.cs_sample_plain.argtypes = [vp, C.c_int, vp, vp, i64, vp, vp, vp]
@@ -218,6 +220,15 @@ class Context:
                                    off_e.numel() - 1, float(dt), float(density_norm), int(seed), int(step),
                                    SAMPLERS[sampler], None if mlp is None else mlp.handle, _ptr(stats),
                                    _stream(stream))
+        self._check(rc)
+
+    def ntc_step(self, e, g, off_e, off_g, dt, density_norm, seed, step, stats=None, stream=None):
+        """One Compton step with no-time-counter candidate selection, in place
+        on device tensors (the layout of step); synchronises the stream once."""
+        code = _dtype_code(e["x"])
+        rc = lib().cs_ntc_step(self._h, code, _species(e), _species(g), _ptr(off_e), _ptr(off_g),
+                               off_e.numel() - 1, float(dt), float(density_norm), int(seed), int(step), _ptr(stats),
+                               _stream(stream))
         self._check(rc)
 
     def check_layout(self, off, n, stream=None):

@@ -121,8 +121,9 @@ cs_status cs_destroy(cs_ctx* ctx) {
     if (!ctx) return CS_ERR_INVALID_ARG;
     {
         DeviceGuard g(ctx->device);
-        if (ctx->ws.base || ctx->bin_ws || ctx->pnet_ws) (void)hipDeviceSynchronize();
+        if (ctx->ws.base || ctx->bin_ws || ctx->pnet_ws || ctx->ntc.cell_ws) (void)hipDeviceSynchronize();
         if (ctx->ws.base) (void)hipFree(ctx->ws.base);
+        cs::ntc_free(ctx->ntc);
         if (ctx->bin_ws) (void)hipFree(ctx->bin_ws);
         if (ctx->pnet_ws) (void)hipFree(ctx->pnet_ws);
         for (auto& ev : ctx->events)
@@ -718,6 +719,33 @@ cs_status cs_bin_particles(cs_ctx* ctx, cs_dtype dtype, const int32_t* cell, cs_
 
 // Grow a context scratch buffer to `want` bytes (synchronises `stream` first
 // so that no queued kernel still uses the old one).
+cs_status cs_ntc_step(cs_ctx* ctx, cs_dtype dtype, cs_species electrons, cs_species photons, const int64_t* off_e,
+                      const int64_t* off_g, int64_t n_cells, double dt, double density_norm, uint64_t seed,
+                      uint64_t step, cs_stats* stats, void* stream) {
+    if (!ctx) return CS_ERR_INVALID_ARG;
+    if (dtype != CS_F32 && dtype != CS_F64) return fail(ctx, CS_ERR_INVALID_ARG, "cs_ntc_step: bad dtype");
+    if (electrons.n < 0 || photons.n < 0 || n_cells < 0 || n_cells >= ((int64_t)1 << 31) - 1)
+        return fail(ctx, CS_ERR_INVALID_ARG, "cs_ntc_step: negative size or n_cells >= 2^31 - 1");
+    if (electrons.n >= ((int64_t)1 << 31) || photons.n >= ((int64_t)1 << 31))
+        return fail(ctx, CS_ERR_UNSUPPORTED, "cs_ntc_step: a species count >= 2^31");
+    if ((electrons.n > 0 && (!electrons.x || !electrons.y || !electrons.z || !electrons.w)) ||
+        (photons.n > 0 && (!photons.x || !photons.y || !photons.z || !photons.w)) || !off_e || !off_g)
+        return fail(ctx, CS_ERR_INVALID_ARG, "cs_ntc_step: NULL array");
+    if (!(dt > 0.0) || !std::isfinite(dt) || !(density_norm >= 0.0) || !std::isfinite(density_norm))
+        return fail(ctx, CS_ERR_INVALID_ARG, "cs_ntc_step: need finite dt > 0 and density_norm >= 0");
+    DeviceGuard g(ctx->device);
+    hipStream_t st = (hipStream_t)stream;
+    cs::NtcOutcome out = cs::NtcOutcome::kOk;
+    const hipError_t e = cs::ntc_step(ctx->ntc, dtype, electrons, photons, off_e, off_g, n_cells, dt, density_norm,
+                                      seed, step, stats, st, &out);
+    if (e != hipSuccess) return hip_fail(ctx, e, "cs_ntc_step");
+    if (out == cs::NtcOutcome::kLayout) return fail(ctx, CS_ERR_LAYOUT, "cs_ntc_step: offsets are not a valid layout");
+    if (out == cs::NtcOutcome::kTooMany)
+        return fail(ctx, CS_ERR_UNSUPPORTED, "cs_ntc_step: 2^31 - 1 or more candidates in one step");
+    ctx->last_error.clear();
+    return CS_OK;
+}
+
 static cs_status grow_scratch(cs_ctx* ctx, void** buf, size_t* bytes, size_t want, hipStream_t st,
                               const char* what) {
     if (*bytes >= want) return CS_OK;

@@ -53,7 +53,16 @@ __device__ __forceinline__ u32x4 philox10(uint32_t c0, uint32_t c1, uint32_t c2,
 }
 
 // Stream purposes (fourth counter word, low byte).
-enum : uint32_t { kPair = 1, kCollide = 2, kScatter = 3 };
+enum : uint32_t {
+    kPair = 1,
+    kCollide = 2,
+    kScatter = 3,
+    // no-time-counter candidate selection
+    kNtcCount = 4,
+    kNtcPick = 5,
+    kNtcScatter = 6,
+    kNtcWeight = 7
+};
 
 // counter = (index lo, index hi, step lo, step hi << 8 | purpose), key = seed.
 __device__ __forceinline__ u32x4 draw(uint64_t seed, uint64_t index, uint64_t step, uint32_t purpose) {

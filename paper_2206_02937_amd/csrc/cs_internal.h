@@ -189,6 +189,24 @@ hipError_t launch_sample_plain(cs_dtype dtype, const void* x, const void* u, int
 // cell binning of one species (cs_bin.hip): workspace bytes for n particles,
 // and the launch (in/out: x, y, z, w arrays of the dtype)
 size_t bin_workspace_bytes(int64_t n);
+// no-time-counter step (cs_ntc.hip): device scratch and the pinned read-back
+// kept by the context between calls; the touch words (two sets of one
+// 64-bit word per electron and per photon) keep their tags across steps.
+struct NtcState {
+    void* cell_ws = nullptr;
+    size_t cell_bytes = 0;
+    void* cand_ws = nullptr;
+    size_t cand_bytes = 0;
+    void* touch = nullptr;
+    int64_t cap_e = 0, cap_g = 0;
+    uint32_t epoch = 1;
+    void* host = nullptr;
+};
+enum class NtcOutcome { kOk, kLayout, kTooMany };
+hipError_t ntc_step(NtcState& s, cs_dtype dtype, const cs_species& e, const cs_species& g, const int64_t* off_e,
+                    const int64_t* off_g, int64_t n_cells, double dt, double dn, uint64_t seed, uint64_t step,
+                    cs_stats* stats, hipStream_t st, NtcOutcome* out);
+void ntc_free(NtcState& s);
 // probability network (cs_pnet.hip)
 size_t pnet_workspace_bytes(int64_t n);
 hipError_t launch_pnet_target(const float* in, int64_t n, float* y, hipStream_t st);
@@ -255,4 +273,5 @@ struct cs_ctx {
     size_t bin_bytes = 0;
     void* pnet_ws = nullptr;          // probability-network gradient partials, grown on demand
     size_t pnet_bytes = 0;
+    cs::NtcState ntc;                 // no-time-counter step scratch
 };

@@ -1,0 +1,594 @@
+// cs_ntc.hip -- no-time-counter candidate selection (the NTC method of Bird
+// that Sec. 3.1 names to shorten each cell's pair list) with the probability
+// and bound of Sec. 3.2.
+//
+// Per cell c with N_e electrons, N_g photons and W the largest valid weight
+// among them: P_max = 2 dt n W bounds the pair probability
+// P = dt n max(w_e, w_g) s(x) flux (s <= 1, flux <= 2); the cell draws
+// N_e N_g P_max candidates rounded stochastically, each an electron and a
+// photon picked uniformly with replacement and accepted with probability
+// P / P_max.  The candidates of a cell are taken in order, each on the
+// momenta the earlier collisions of its cell left (Bird's sequential scheme).
+//
+// Data-parallel form.  A candidate's outcome depends only on its own two
+// particles, so candidates that share no particle commute, and any order
+// in which each candidate follows every earlier candidate of its cell that
+// shares a particle with it gives the sequential result.  Rounds:
+//   k_ntc_count    one wave per cell: W (wave max), P_max, the count
+//   k_ntc_scan_*   candidate offsets (int64 exclusive scan over cells); the
+//                  host reads the total (one stream synchronisation)
+//   k_ntc_pick     per candidate: its cell (binary search), electron and
+//                  photon; registers in both particles' "first toucher"
+//                  words: atomicMax of (round tag << 32 | ~candidate), so
+//                  each word ends up holding the earliest candidate that
+//                  touches the particle
+//   k_ntc_round t  per unresolved candidate: ready when it is the earliest
+//                  unresolved toucher of both its particles; ready ones are
+//                  resolved (probability, accept, collision, write-back);
+//                  the others register for round t + 1 in the other word
+//                  set (two sets alternate, so a round never reads a word
+//                  that the same round writes); after the last round they
+//                  mark their cell
+//   k_ntc_serial   one thread per marked cell resolves its remaining
+//                  candidates in order (long chains: a cell with one
+//                  electron and many candidates)
+//   k_ntc_reduce / k_ntc_final  fixed-order sums into cs_stats
+// Tags grow by one per round and never repeat (a per-context epoch), so the
+// touch words are never cleared between steps.
+//
+// Random numbers: Philox4x32-10 as elsewhere; the count from
+// (cell, kNtcCount), candidate l of cell c from index (c << 32) | l with
+// kNtcPick (electron (r0 N_e) >> 32, photon (r1 N_g) >> 32, acceptance
+// uniform from r2, r3), kNtcScatter (u_mu, u_phi) and kNtcWeight.
+#include <hip/hip_runtime.h>
+
+#include "cs_block.h"
+#include "cs_device.h"
+#include "cs_internal.h"
+#include "cs_pair.h"
+
+namespace cs {
+
+constexpr int kNtcThreads = 256;
+constexpr int kNtcRounds = 4;
+constexpr int kNtcScanPer = 4;                              // cells per thread in the scan
+constexpr int kNtcScanBlock = kNtcThreads * kNtcScanPer;   // cells per scan workgroup
+constexpr int kNtcRedPer = 16;                              // candidates per thread in the reduction
+constexpr int64_t kNtcMaxCand = 2147483647;                 // candidates per step: below 2^31 - 1
+
+struct NtcCtl {
+    long long total;
+    int32_t layout_bad;
+    int32_t too_many;
+};
+
+struct NtcPart {
+    double prob, eb, ea;
+    long long coll, inv, clip;
+};
+
+template <typename T>
+struct NtcArgs {
+    Particles<T> pt;
+    const int64_t *off_e, *off_g;
+    int64_t n_cells, total;
+    double dt, dn;
+    uint64_t seed, step;
+    uint32_t epoch;
+    const int64_t* cand_off;  // [n_cells + 1]
+    const double* p_max;      // [n_cells]
+    int32_t *c_ie, *c_ig, *c_cell;
+    uint8_t* status;  // 0 unresolved; else 1 | 2 collided | 4 invalid | 8 P > P_max
+    double *r_ratio, *r_eb, *r_ea;
+    unsigned long long *touch_e, *touch_g;  // [2][cap_e], [2][cap_g]
+    int64_t cap_e, cap_g;
+    uint8_t* pending;  // [n_cells]
+};
+
+__device__ __forceinline__ unsigned long long ntc_tag(uint32_t round_tag, int64_t j) {
+    return ((unsigned long long)round_tag << 32) | (unsigned long long)(0xFFFFFFFFu - (uint32_t)j);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kNtcThreads) void k_ntc_count(const T* ew, const T* gw, const int64_t* off_e,
+                                                         const int64_t* off_g, int64_t n_cells, int64_t ne,
+                                                         int64_t ng, double dt, double dn, uint64_t seed,
+                                                         uint64_t step, int64_t* count, double* p_max,
+                                                         NtcCtl* ctl) {
+    const int lane = lane_id();
+    const int64_t c = (int64_t)blockIdx.x * (kNtcThreads / 64) + (threadIdx.x >> 6);
+    if (c >= n_cells) return;
+    const int64_t e0 = off_e[c], e1 = off_e[c + 1], g0 = off_g[c], g1 = off_g[c + 1];
+    const bool bad = e0 < 0 || e1 < e0 || e1 > ne || g0 < 0 || g1 < g0 || g1 > ng ||
+                     (c == 0 && (e0 != 0 || g0 != 0)) || (c == n_cells - 1 && (e1 != ne || g1 != ng));
+    if (bad) {
+        if (lane == 0) {
+            ctl->layout_bad = 1;
+            count[c] = 0;
+            p_max[c] = 0.0;
+        }
+        return;
+    }
+    double w = 0.0;
+    for (int64_t i = e0 + lane; i < e1; i += 64) {
+        const double v = (double)ew[i];
+        if (isfinite(v) && v > w) w = v;
+    }
+    for (int64_t i = g0 + lane; i < g1; i += 64) {
+        const double v = (double)gw[i];
+        if (isfinite(v) && v > w) w = v;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const double v = __shfl_xor(w, o, 64);
+        w = v > w ? v : w;
+    }
+    if (lane == 0) {
+        const int64_t nec = e1 - e0, ngc = g1 - g0;
+        int64_t n = 0;
+        double pm = 0.0;
+        if (nec > 0 && ngc > 0) {
+            pm = 2.0 * dt * dn * w;
+            const double n_exp = (double)nec * (double)ngc * pm;
+            if (!(n_exp < (double)kNtcMaxCand)) {
+                ctl->too_many = 1;
+            } else {
+                const double fl = floor(n_exp);
+                const u32x4 r = draw(seed, (uint64_t)c, step, kNtcCount);
+                n = (int64_t)fl + (uniform53(r.a, r.b) < n_exp - fl ? 1 : 0);
+            }
+        }
+        count[c] = n;
+        p_max[c] = pm;
+    }
+}
+
+__device__ __forceinline__ long long wave_incl_scan64(long long v) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const long long t = __shfl_up(v, o, 64);
+        if (lane >= o) v += t;
+    }
+    return v;
+}
+
+// Exclusive scan of the workgroup's thread values (fixed order), and the total.
+__device__ __forceinline__ long long block_excl_scan64(long long v, long long* lds, long long* total) {
+    const int lane = lane_id(), wave = threadIdx.x >> 6;
+    const long long inc = wave_incl_scan64(v);
+    if (lane == 63) lds[wave] = inc;
+    __syncthreads();
+    long long before = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < kNtcThreads / 64; ++w) {
+        if (w < wave) before += lds[w];
+        tot += lds[w];
+    }
+    __syncthreads();
+    *total = tot;
+    return before + inc - v;
+}
+
+// Local exclusive prefixes of the counts within each block of kNtcScanBlock
+// cells, and the block sums.
+__global__ __launch_bounds__(kNtcThreads) void k_ntc_scan_local(const int64_t* count, int64_t n_cells,
+                                                              int64_t* cand_off, long long* bsum) {
+    __shared__ long long s[kNtcThreads / 64];
+    const int64_t base = (int64_t)blockIdx.x * kNtcScanBlock + (int64_t)threadIdx.x * kNtcScanPer;
+    long long v[kNtcScanPer], t = 0;
+#pragma unroll
+    for (int q = 0; q < kNtcScanPer; ++q) {
+        v[q] = base + q < n_cells ? count[base + q] : 0;
+        t += v[q];
+    }
+    long long tot;
+    long long run = block_excl_scan64(t, s, &tot);
+#pragma unroll
+    for (int q = 0; q < kNtcScanPer; ++q) {
+        if (base + q < n_cells) cand_off[base + q] = run;
+        run += v[q];
+    }
+    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+// One workgroup: exclusive scan of the block sums (in place), the total.
+__global__ __launch_bounds__(kNtcThreads) void k_ntc_scan_top(long long* bsum, int64_t n_blocks, int64_t n_cells,
+                                                            int64_t* cand_off, NtcCtl* ctl) {
+    __shared__ long long s[kNtcThreads / 64];
+    long long carry = 0;
+    for (int64_t b0 = 0; b0 < n_blocks; b0 += kNtcThreads) {
+        const int64_t b = b0 + threadIdx.x;
+        const long long v = b < n_blocks ? bsum[b] : 0;
+        long long tot;
+        const long long ex = block_excl_scan64(v, s, &tot);
+        if (b < n_blocks) bsum[b] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) {
+        cand_off[n_cells] = carry;
+        ctl->total = carry;
+        if (carry >= kNtcMaxCand) ctl->too_many = 1;
+    }
+}
+
+__global__ __launch_bounds__(kNtcThreads) void k_ntc_scan_add(const long long* boff, int64_t n_cells,
+                                                            int64_t* cand_off) {
+    const int64_t c = (int64_t)blockIdx.x * kNtcThreads + threadIdx.x;
+    if (c < n_cells) cand_off[c] += boff[c / kNtcScanBlock];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kNtcThreads) void k_ntc_pick(const NtcArgs<T> a) {
+    const int64_t j = (int64_t)blockIdx.x * kNtcThreads + threadIdx.x;
+    if (j >= a.total) return;
+    // the cell holding candidate j: the last c with cand_off[c] <= j (a cell
+    // with no candidates shares its offset with the next cell)
+    int64_t lo = 0, hi = a.n_cells - 1;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) >> 1;
+        if (a.cand_off[mid] <= j)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const int64_t c = lo, l = j - a.cand_off[c];
+    const int64_t e0 = a.off_e[c], g0 = a.off_g[c];
+    const uint64_t nec = (uint64_t)(a.off_e[c + 1] - e0), ngc = (uint64_t)(a.off_g[c + 1] - g0);
+    const u32x4 r = draw(a.seed, ((uint64_t)c << 32) | (uint64_t)l, a.step, kNtcPick);
+    const int32_t ie = (int32_t)(e0 + (int64_t)(((uint64_t)r.a * nec) >> 32));
+    const int32_t ig = (int32_t)(g0 + (int64_t)(((uint64_t)r.b * ngc) >> 32));
+    a.c_ie[j] = ie;
+    a.c_ig[j] = ig;
+    a.c_cell[j] = (int32_t)c;
+    a.status[j] = 0;
+    const unsigned long long tag = ntc_tag(a.epoch, j);
+    atomicMax(a.touch_e + ie, tag);
+    atomicMax(a.touch_g + ig, tag);
+}
+
+// Resolve candidate j (cell c, particles ie, ig) on the current momenta.
+template <typename T>
+__device__ __forceinline__ void ntc_resolve(const NtcArgs<T>& a, int64_t j, int32_t c, int32_t ie, int32_t ig) {
+    const uint64_t idx = ((uint64_t)c << 32) | (uint64_t)(j - a.cand_off[c]);
+    const u32x4 r = draw(a.seed, idx, a.step, kNtcPick);
+    const double u_c = uniform53(r.c, r.d);
+    const d3 p = load_p(a.pt, ie), k = load_k(a.pt, ig);
+    const double we = (double)a.pt.ew[ie], wg = (double)a.pt.gw[ig];
+    uint8_t st = 1;
+    double ratio = -1.0, eb = 0.0, ea = 0.0;
+    if (!finite_pair(p, we, k, wg)) {
+        st |= 4;
+    } else {
+        const PairInv inv = pair_invariants(p, k);
+        const double wmax = we > wg ? we : wg;
+        const double P = inv.x > 0.0 ? a.dt * a.dn * wmax * sigma_ratio(inv.x) * inv.flux : 0.0;
+        ratio = P / a.p_max[c];
+        if (ratio > 1.0) st |= 8;
+        if (u_c < ratio) {
+            st |= 2;
+            const u32x4 s = draw(a.seed, idx, a.step, kNtcScatter);
+            const double v = angle_icdf_v(uniform53(s.a, s.b), inv.x);
+            const Scattered sc = scatter(p, k, inv, v, uniform53(s.c, s.d));
+            eb = sc.e_before;
+            ea = sc.e_after;
+            bool upd_e = true, upd_g = true;
+            if (we != wg) {
+                const u32x4 q = draw(a.seed, idx, a.step, kNtcWeight);
+                const double wmin = we < wg ? we : wg;
+                const bool heavier_moves = uniform53(q.a, q.b) < wmin / wmax;
+                if (we > wg)
+                    upd_e = heavier_moves;
+                else
+                    upd_g = heavier_moves;
+            }
+            if (upd_e) {
+                a.pt.ex[ie] = (T)sc.p1.x;
+                a.pt.ey[ie] = (T)sc.p1.y;
+                a.pt.ez[ie] = (T)sc.p1.z;
+            }
+            if (upd_g) {
+                a.pt.gx[ig] = (T)sc.k1.x;
+                a.pt.gy[ig] = (T)sc.k1.y;
+                a.pt.gz[ig] = (T)sc.k1.z;
+            }
+        }
+    }
+    a.r_ratio[j] = ratio;
+    a.r_eb[j] = eb;
+    a.r_ea[j] = ea;
+    a.status[j] = st;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kNtcThreads) void k_ntc_round(const NtcArgs<T> a, int t) {
+    const int64_t j = (int64_t)blockIdx.x * kNtcThreads + threadIdx.x;
+    if (j >= a.total || a.status[j] != 0) return;
+    const int32_t ie = a.c_ie[j], ig = a.c_ig[j];
+    const unsigned long long* te = a.touch_e + (t & 1) * a.cap_e;
+    const unsigned long long* tg = a.touch_g + (t & 1) * a.cap_g;
+    const unsigned long long mine = ntc_tag(a.epoch + (uint32_t)t, j);
+    if (te[ie] == mine && tg[ig] == mine) {
+        ntc_resolve<T>(a, j, a.c_cell[j], ie, ig);
+    } else if (t + 1 < kNtcRounds) {
+        const unsigned long long next = ntc_tag(a.epoch + (uint32_t)(t + 1), j);
+        atomicMax(a.touch_e + ((t + 1) & 1) * a.cap_e + ie, next);
+        atomicMax(a.touch_g + ((t + 1) & 1) * a.cap_g + ig, next);
+    } else {
+        a.pending[a.c_cell[j]] = 1;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kNtcThreads) void k_ntc_serial(const NtcArgs<T> a) {
+    const int64_t c = (int64_t)blockIdx.x * kNtcThreads + threadIdx.x;
+    if (c >= a.n_cells || !a.pending[c]) return;
+    a.pending[c] = 0;
+    for (int64_t j = a.cand_off[c]; j < a.cand_off[c + 1]; ++j)
+        if (a.status[j] == 0) ntc_resolve<T>(a, j, (int32_t)c, a.c_ie[j], a.c_ig[j]);
+}
+
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ long long wave_sum_ll(long long v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Sum a workgroup's per-thread partials in a fixed order (butterfly in each
+// wave, then the waves in order); thread 0 gets the result.
+__device__ __forceinline__ NtcPart block_sum_part(NtcPart v, NtcPart* lds) {
+    const int lane = lane_id(), wave = threadIdx.x >> 6;
+    v.prob = wave_sum_d(v.prob);
+    v.eb = wave_sum_d(v.eb);
+    v.ea = wave_sum_d(v.ea);
+    v.coll = wave_sum_ll(v.coll);
+    v.inv = wave_sum_ll(v.inv);
+    v.clip = wave_sum_ll(v.clip);
+    if (lane == 0) lds[wave] = v;
+    __syncthreads();
+    NtcPart r = {0.0, 0.0, 0.0, 0, 0, 0};
+    if (threadIdx.x == 0)
+        for (int w = 0; w < kNtcThreads / 64; ++w) {
+            r.prob += lds[w].prob;
+            r.eb += lds[w].eb;
+            r.ea += lds[w].ea;
+            r.coll += lds[w].coll;
+            r.inv += lds[w].inv;
+            r.clip += lds[w].clip;
+        }
+    return r;
+}
+
+__global__ __launch_bounds__(kNtcThreads) void k_ntc_reduce(const uint8_t* status, const double* ratio,
+                                                          const double* eb, const double* ea, int64_t total,
+                                                          NtcPart* part) {
+    __shared__ NtcPart s[kNtcThreads / 64];
+    NtcPart v = {0.0, 0.0, 0.0, 0, 0, 0};
+    const int64_t base = (int64_t)blockIdx.x * kNtcThreads * kNtcRedPer + threadIdx.x;
+    for (int q = 0; q < kNtcRedPer; ++q) {
+        const int64_t j = base + (int64_t)q * kNtcThreads;
+        if (j >= total) break;
+        const uint8_t st = status[j];
+        if (st & 4) {
+            v.inv += 1;
+            continue;
+        }
+        v.prob += ratio[j];
+        v.clip += (st & 8) ? 1 : 0;
+        if (st & 2) {
+            v.coll += 1;
+            v.eb += eb[j];
+            v.ea += ea[j];
+        }
+    }
+    const NtcPart r = block_sum_part(v, s);
+    if (threadIdx.x == 0) part[blockIdx.x] = r;
+}
+
+__global__ __launch_bounds__(kNtcThreads) void k_ntc_final(const NtcPart* part, int64_t n_part, int64_t total,
+                                                         cs_stats* stats) {
+    __shared__ NtcPart s[kNtcThreads / 64];
+    NtcPart v = {0.0, 0.0, 0.0, 0, 0, 0};
+    for (int64_t b = threadIdx.x; b < n_part; b += kNtcThreads) {
+        const NtcPart p = part[b];
+        v.prob += p.prob;
+        v.eb += p.eb;
+        v.ea += p.ea;
+        v.coll += p.coll;
+        v.inv += p.inv;
+        v.clip += p.clip;
+    }
+    const NtcPart r = block_sum_part(v, s);
+    if (threadIdx.x == 0) {
+        cs_stats o = {};
+        o.n_pairs = total;
+        o.n_collided = r.coll;
+        o.n_clipped = r.clip;
+        o.n_invalid = r.inv;
+        o.sum_prob = r.prob;
+        o.energy_before = r.eb;
+        o.energy_after = r.ea;
+        *stats = o;
+    }
+}
+
+__global__ void k_ntc_stats_layout(cs_stats* stats) {
+    cs_stats o = {};
+    o.layout_error = 1;
+    *stats = o;
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+static inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+static hipError_t grow(void** buf, size_t* bytes, size_t want, hipStream_t st) {
+    if (*bytes >= want) return hipSuccess;
+    hipError_t e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return e;
+    if (*buf) {
+        e = hipFree(*buf);
+        *buf = nullptr;
+        *bytes = 0;
+        if (e != hipSuccess) return e;
+    }
+    const size_t g = want + want / 4;
+    e = hipMalloc(buf, g);
+    if (e != hipSuccess) {
+        *buf = nullptr;
+        return e;
+    }
+    *bytes = g;
+    return hipSuccess;
+}
+
+void ntc_free(NtcState& s) {
+    if (s.cell_ws) (void)hipFree(s.cell_ws);
+    if (s.cand_ws) (void)hipFree(s.cand_ws);
+    if (s.touch) (void)hipFree(s.touch);
+    if (s.host) (void)hipHostFree(s.host);
+    s = NtcState{};
+}
+
+template <typename T>
+static hipError_t ntc_launch(NtcState& s, const cs_species& e, const cs_species& g, const int64_t* off_e,
+                             const int64_t* off_g, int64_t n_cells, double dt, double dn, uint64_t seed,
+                             uint64_t step, cs_stats* stats, hipStream_t st, NtcOutcome* out) {
+    *out = NtcOutcome::kOk;
+    // per-cell area: counts, offsets, P_max, marks, block sums, control
+    const int64_t nb = (n_cells + kNtcScanBlock - 1) / kNtcScanBlock;
+    const size_t b_count = align256(8 * (size_t)(n_cells > 0 ? n_cells : 1));
+    const size_t b_off = align256(8 * (size_t)(n_cells + 1));
+    const size_t b_pmax = b_count;
+    const size_t b_pend = align256((size_t)(n_cells > 0 ? n_cells : 1));
+    const size_t b_bsum = align256(8 * (size_t)(nb > 0 ? nb : 1));
+    const size_t b_ctl = align256(sizeof(NtcCtl));
+    hipError_t err = grow(&s.cell_ws, &s.cell_bytes, b_count + b_off + b_pmax + b_pend + b_bsum + b_ctl, st);
+    if (err != hipSuccess) return err;
+    char* cw = (char*)s.cell_ws;
+    int64_t* count = (int64_t*)cw;
+    int64_t* cand_off = (int64_t*)(cw += b_count);
+    double* p_max = (double*)(cw += b_off);
+    uint8_t* pending = (uint8_t*)(cw += b_pmax);
+    long long* bsum = (long long*)(cw += b_pend);
+    NtcCtl* ctl = (NtcCtl*)(cw += b_bsum);
+    if (!s.host) {
+        err = hipHostMalloc(&s.host, sizeof(NtcCtl), hipHostMallocDefault);
+        if (err != hipSuccess) {
+            s.host = nullptr;
+            return err;
+        }
+    }
+    // touch words: two sets per species, zero when (re)allocated
+    if (s.cap_e < e.n || s.cap_g < g.n || s.touch == nullptr) {
+        err = hipStreamSynchronize(st);
+        if (err != hipSuccess) return err;
+        if (s.touch) (void)hipFree(s.touch);
+        s.touch = nullptr;
+        s.cap_e = e.n > s.cap_e ? e.n + e.n / 4 : s.cap_e;
+        s.cap_g = g.n > s.cap_g ? g.n + g.n / 4 : s.cap_g;
+        if (s.cap_e < 1) s.cap_e = 1;
+        if (s.cap_g < 1) s.cap_g = 1;
+        const size_t tb = 2 * 8 * (size_t)(s.cap_e + s.cap_g);
+        err = hipMalloc(&s.touch, tb);
+        if (err != hipSuccess) {
+            s.touch = nullptr;
+            s.cap_e = s.cap_g = 0;
+            return err;
+        }
+        err = hipMemsetAsync(s.touch, 0, tb, st);
+        if (err != hipSuccess) return err;
+        s.epoch = 1;
+    }
+    if (s.epoch > 0xFFFFFFFFu - 2 * kNtcRounds) {  // tags would wrap: clear and restart
+        err = hipMemsetAsync(s.touch, 0, 2 * 8 * (size_t)(s.cap_e + s.cap_g), st);
+        if (err != hipSuccess) return err;
+        s.epoch = 1;
+    }
+    err = hipMemsetAsync(ctl, 0, sizeof(NtcCtl), st);
+    if (err == hipSuccess && n_cells > 0) err = hipMemsetAsync(pending, 0, (size_t)n_cells, st);
+    if (err != hipSuccess) return err;
+    if (n_cells > 0) {
+        k_ntc_count<T><<<(unsigned)((n_cells + 3) / 4), kNtcThreads, 0, st>>>(
+            (const T*)e.w, (const T*)g.w, off_e, off_g, n_cells, e.n, g.n, dt, dn, seed, step, count, p_max, ctl);
+        k_ntc_scan_local<<<(unsigned)nb, kNtcThreads, 0, st>>>(count, n_cells, cand_off, bsum);
+    }
+    k_ntc_scan_top<<<1, kNtcThreads, 0, st>>>(bsum, nb, n_cells, cand_off, ctl);
+    if (n_cells > 0)
+        k_ntc_scan_add<<<(unsigned)((n_cells + kNtcThreads - 1) / kNtcThreads), kNtcThreads, 0, st>>>(bsum, n_cells,
+                                                                                                   cand_off);
+    err = hipGetLastError();
+    if (err == hipSuccess) err = hipMemcpyAsync(s.host, ctl, sizeof(NtcCtl), hipMemcpyDeviceToHost, st);
+    if (err == hipSuccess) err = hipStreamSynchronize(st);
+    if (err != hipSuccess) return err;
+    const NtcCtl h = *(const NtcCtl*)s.host;
+    if (h.layout_bad || (n_cells == 0 && (e.n != 0 || g.n != 0))) {
+        *out = NtcOutcome::kLayout;
+        if (stats) k_ntc_stats_layout<<<1, 1, 0, st>>>(stats);
+        return hipGetLastError();
+    }
+    if (h.too_many) {
+        *out = NtcOutcome::kTooMany;
+        return hipSuccess;
+    }
+    const int64_t total = h.total;
+    // per-candidate area
+    const int64_t n_part = (total + kNtcThreads * kNtcRedPer - 1) / (kNtcThreads * kNtcRedPer);
+    const size_t tc = (size_t)(total > 0 ? total : 1);
+    const size_t b_i32 = align256(4 * tc), b_u8 = align256(tc), b_d = align256(8 * tc);
+    const size_t b_part = align256(sizeof(NtcPart) * (size_t)(n_part > 0 ? n_part : 1));
+    err = grow(&s.cand_ws, &s.cand_bytes, 3 * b_i32 + b_u8 + 3 * b_d + b_part, st);
+    if (err != hipSuccess) return err;
+    NtcArgs<T> a;
+    a.pt = {(T*)e.x, (T*)e.y, (T*)e.z, (T*)e.w, (T*)g.x, (T*)g.y, (T*)g.z, (T*)g.w};
+    a.off_e = off_e;
+    a.off_g = off_g;
+    a.n_cells = n_cells;
+    a.total = total;
+    a.dt = dt;
+    a.dn = dn;
+    a.seed = seed;
+    a.step = step;
+    a.epoch = s.epoch;
+    a.cand_off = cand_off;
+    a.p_max = p_max;
+    char* q = (char*)s.cand_ws;
+    a.c_ie = (int32_t*)q;
+    a.c_ig = (int32_t*)(q += b_i32);
+    a.c_cell = (int32_t*)(q += b_i32);
+    a.status = (uint8_t*)(q += b_i32);
+    a.r_ratio = (double*)(q += b_u8);
+    a.r_eb = (double*)(q += b_d);
+    a.r_ea = (double*)(q += b_d);
+    NtcPart* part = (NtcPart*)(q += b_d);
+    a.touch_e = (unsigned long long*)s.touch;
+    a.touch_g = a.touch_e + 2 * s.cap_e;
+    a.cap_e = s.cap_e;
+    a.cap_g = s.cap_g;
+    a.pending = pending;
+    s.epoch += kNtcRounds;
+    if (total > 0) {
+        const unsigned grid = (unsigned)((total + kNtcThreads - 1) / kNtcThreads);
+        k_ntc_pick<T><<<grid, kNtcThreads, 0, st>>>(a);
+        for (int t = 0; t < kNtcRounds; ++t) k_ntc_round<T><<<grid, kNtcThreads, 0, st>>>(a, t);
+        k_ntc_serial<T><<<(unsigned)((n_cells + kNtcThreads - 1) / kNtcThreads), kNtcThreads, 0, st>>>(a);
+        k_ntc_reduce<<<(unsigned)n_part, kNtcThreads, 0, st>>>(a.status, a.r_ratio, a.r_eb, a.r_ea, total, part);
+    }
+    if (stats) k_ntc_final<<<1, kNtcThreads, 0, st>>>(part, n_part, total, stats);
+    return hipGetLastError();
+}
+
+hipError_t ntc_step(NtcState& s, cs_dtype dtype, const cs_species& e, const cs_species& g, const int64_t* off_e,
+                    const int64_t* off_g, int64_t n_cells, double dt, double dn, uint64_t seed, uint64_t step,
+                    cs_stats* stats, hipStream_t st, NtcOutcome* out) {
+    if (dtype == CS_F64) return ntc_launch<double>(s, e, g, off_e, off_g, n_cells, dt, dn, seed, step, stats, st, out);
+    return ntc_launch<float>(s, e, g, off_e, off_g, n_cells, dt, dn, seed, step, stats, st, out);
+}
+
+}  // namespace cs
