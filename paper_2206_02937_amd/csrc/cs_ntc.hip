@@ -15,20 +15,26 @@
 // in which each candidate follows every earlier candidate of its cell that
 // shares a particle with it gives the sequential result.  Rounds:
 //   k_ntc_count    one wave per cell: W (wave max), P_max, the count
-//   k_ntc_scan_*   candidate offsets (int64 exclusive scan over cells); the
+//   k_ntc_scan_*   candidate offsets (int64 exclusive scan over cells, the
+//                  block offsets added by k_ntc_pick); the
 //                  host reads the total (one stream synchronisation)
-//   k_ntc_pick     per candidate: its cell (binary search), electron and
-//                  photon; registers in both particles' "first toucher"
-//                  words: atomicMax of (round tag << 32 | ~candidate), so
-//                  each word ends up holding the earliest candidate that
-//                  touches the particle
+//   k_ntc_pick     one wave per cell: its candidates' electrons and
+//                  photons; each registers in both particles' "first
+//                  toucher" words: atomicMax of (round tag << 32 |
+//                  ~candidate), so each word ends up holding the earliest
+//                  candidate that touches the particle
 //   k_ntc_round t  per unresolved candidate: ready when it is the earliest
 //                  unresolved toucher of both its particles; ready ones are
-//                  resolved (probability, accept, collision, write-back);
-//                  the others register for round t + 1 in the other word
-//                  set (two sets alternate, so a round never reads a word
-//                  that the same round writes); after the last round they
-//                  mark their cell
+//                  evaluated (probability, accept) and the accepted ones
+//                  listed; the others register for round t + 1 in the other
+//                  word set (two sets alternate, so a round never reads a
+//                  word that the same round writes); after the last round
+//                  they mark their cell
+//   k_ntc_round_collide  round 0's accepted candidates, one per lane:
+//                  scattering and write-back (listing them first keeps the
+//                  long collision path off the lanes that only evaluate;
+//                  in the later rounds, with few candidates left, the
+//                  accepted ones collide in the round kernel itself)
 //   k_ntc_serial   one thread per marked cell resolves its remaining
 //                  candidates in order (long chains: a cell with one
 //                  electron and many candidates)
@@ -50,12 +56,16 @@
 namespace cs {
 
 constexpr int kNtcThreads = 256;
-constexpr int kNtcRounds = 4;
+constexpr int kNtcRounds = 3;
 constexpr int kNtcScanPer = 4;                              // cells per thread in the scan
 constexpr int kNtcScanBlock = kNtcThreads * kNtcScanPer;   // cells per scan workgroup
-constexpr int kNtcRedPer = 16;                              // candidates per thread in the reduction
+constexpr int kNtcRedPer = 2;                               // candidates per thread in the reduction
 constexpr int64_t kNtcMaxCand = 2147483647;                 // candidates per step: below 2^31 - 1
 
+// Control words of a step: flags and the total for the host, the list
+// counts of the rounds.  Zero at the start of every step: zeroed when
+// allocated and by k_ntc_final at the end of the previous step (they sit at
+// the start of the per-cell scratch, whatever the cell count).
 struct NtcCtl {
     long long total;
     int32_t layout_bad;
@@ -75,14 +85,20 @@ struct NtcArgs {
     double dt, dn;
     uint64_t seed, step;
     uint32_t epoch;
-    const int64_t* cand_off;  // [n_cells + 1]
+    const int64_t* cand_off;  // [n_cells + 1] prefixes within each scan block
+    int64_t* cand_full;       // [n_cells + 1] candidate offsets (written by k_ntc_pick)
     const double* p_max;      // [n_cells]
-    int32_t *c_ie, *c_ig, *c_cell;
-    uint8_t* status;  // 0 unresolved; else 1 | 2 collided | 4 invalid | 8 P > P_max
+    int32_t *c_ie, *c_ig, *c_cell, *c_local;
+    double* c_u;              // acceptance uniform of each candidate
+    const long long* boff;    // block offsets of the candidate scan (cand_off holds block-local prefixes)
+    uint8_t* status;  // bit 0 resolved; 2 collided, 4 invalid, 8 P > P_max; 16 unresolved and ready in round 0
     double *r_ratio, *r_eb, *r_ea;
     unsigned long long *touch_e, *touch_g;  // [2][cap_e], [2][cap_g]
     int64_t cap_e, cap_g;
-    uint8_t* pending;  // [n_cells]
+    uint8_t* pending;    // [n_cells]
+    int32_t* list;       // [kNtcRounds][list_len]: accepted candidates, a 256-entry segment per round workgroup
+    int32_t* seg_cnt;    // [kNtcRounds][round workgroups]: entries of each segment
+    int64_t list_len, n_round_blocks;
 };
 
 __device__ __forceinline__ unsigned long long ntc_tag(uint32_t round_tag, int64_t j) {
@@ -94,10 +110,11 @@ __global__ __launch_bounds__(kNtcThreads) void k_ntc_count(const T* ew, const T*
                                                          const int64_t* off_g, int64_t n_cells, int64_t ne,
                                                          int64_t ng, double dt, double dn, uint64_t seed,
                                                          uint64_t step, int64_t* count, double* p_max,
-                                                         NtcCtl* ctl) {
+                                                         uint8_t* pending, NtcCtl* ctl) {
     const int lane = lane_id();
     const int64_t c = (int64_t)blockIdx.x * (kNtcThreads / 64) + (threadIdx.x >> 6);
     if (c >= n_cells) return;
+    if (lane == 0) pending[c] = 0;
     const int64_t e0 = off_e[c], e1 = off_e[c + 1], g0 = off_g[c], g1 = off_g[c + 1];
     const bool bad = e0 < 0 || e1 < e0 || e1 > ne || g0 < 0 || g1 < g0 || g1 > ng ||
                      (c == 0 && (e0 != 0 || g0 != 0)) || (c == n_cells - 1 && (e1 != ne || g1 != ng));
@@ -212,111 +229,177 @@ __global__ __launch_bounds__(kNtcThreads) void k_ntc_scan_top(long long* bsum, i
     }
 }
 
-__global__ __launch_bounds__(kNtcThreads) void k_ntc_scan_add(const long long* boff, int64_t n_cells,
-                                                            int64_t* cand_off) {
-    const int64_t c = (int64_t)blockIdx.x * kNtcThreads + threadIdx.x;
-    if (c < n_cells) cand_off[c] += boff[c / kNtcScanBlock];
-}
-
+// One wave per cell: the cell's candidates, 64 at a time.  A cell of at most
+// 64 candidates is settled in the wave: a candidate that shares no particle
+// with an earlier one of its cell is ready in round 0 (status 16) and the
+// others wait for round 1 (they register there when round 0 finds them not
+// ready); no touch word is needed.  Larger cells register every candidate.
 template <typename T>
 __global__ __launch_bounds__(kNtcThreads) void k_ntc_pick(const NtcArgs<T> a) {
-    const int64_t j = (int64_t)blockIdx.x * kNtcThreads + threadIdx.x;
-    if (j >= a.total) return;
-    // the cell holding candidate j: the last c with cand_off[c] <= j (a cell
-    // with no candidates shares its offset with the next cell)
-    int64_t lo = 0, hi = a.n_cells - 1;
-    while (lo < hi) {
-        const int64_t mid = (lo + hi + 1) >> 1;
-        if (a.cand_off[mid] <= j)
-            lo = mid;
-        else
-            hi = mid - 1;
+    const int64_t c = (int64_t)blockIdx.x * (kNtcThreads / 64) + (threadIdx.x >> 6);
+    if (c >= a.n_cells) return;
+    // cand_off holds prefixes within each scan block: add the block offsets,
+    // and keep the full offsets for the serial pass
+    const int64_t j0 = a.cand_off[c] + a.boff[c / kNtcScanBlock];
+    const int64_t j1 = c + 1 < a.n_cells ? a.cand_off[c + 1] + a.boff[(c + 1) / kNtcScanBlock] : a.total;
+    const int lane = lane_id();
+    if (lane == 0) {
+        a.cand_full[c] = j0;
+        if (c + 1 == a.n_cells) a.cand_full[c + 1] = j1;
     }
-    const int64_t c = lo, l = j - a.cand_off[c];
+    if (j0 == j1) return;
     const int64_t e0 = a.off_e[c], g0 = a.off_g[c];
     const uint64_t nec = (uint64_t)(a.off_e[c + 1] - e0), ngc = (uint64_t)(a.off_g[c + 1] - g0);
-    const u32x4 r = draw(a.seed, ((uint64_t)c << 32) | (uint64_t)l, a.step, kNtcPick);
-    const int32_t ie = (int32_t)(e0 + (int64_t)(((uint64_t)r.a * nec) >> 32));
-    const int32_t ig = (int32_t)(g0 + (int64_t)(((uint64_t)r.b * ngc) >> 32));
-    a.c_ie[j] = ie;
-    a.c_ig[j] = ig;
-    a.c_cell[j] = (int32_t)c;
-    a.status[j] = 0;
-    const unsigned long long tag = ntc_tag(a.epoch, j);
-    atomicMax(a.touch_e + ie, tag);
-    atomicMax(a.touch_g + ig, tag);
+    const bool small = j1 - j0 <= 64;
+    for (int64_t jb = j0; jb < j1; jb += 64) {
+        const int64_t j = jb + lane;
+        const bool act = j < j1;
+        int32_t ie = -1, ig = -1;
+        if (act) {
+            const u32x4 r = draw(a.seed, ((uint64_t)c << 32) | (uint64_t)(j - j0), a.step, kNtcPick);
+            ie = (int32_t)(e0 + (int64_t)(((uint64_t)r.a * nec) >> 32));
+            ig = (int32_t)(g0 + (int64_t)(((uint64_t)r.b * ngc) >> 32));
+            a.c_local[j] = (int32_t)(j - j0);
+            a.c_u[j] = uniform53(r.c, r.d);
+        }
+        if (small) {
+            const int n = (int)(j1 - j0);
+            bool conflict = false;
+            for (int m = 0; m < n; ++m) {
+                const int32_t ie_m = __shfl(ie, m, 64), ig_m = __shfl(ig, m, 64);
+                conflict = conflict || (m < lane && (ie_m == ie || ig_m == ig));
+            }
+            if (act) {
+                a.c_ie[j] = ie;
+                a.c_ig[j] = ig;
+                a.c_cell[j] = (int32_t)c;
+                a.status[j] = conflict ? 0 : 16;
+            }
+        } else if (act) {
+            a.c_ie[j] = ie;
+            a.c_ig[j] = ig;
+            a.c_cell[j] = (int32_t)c;
+            a.status[j] = 0;
+            const unsigned long long tag = ntc_tag(a.epoch, j);
+            atomicMax(a.touch_e + ie, tag);
+            atomicMax(a.touch_g + ig, tag);
+        }
+    }
 }
 
-// Resolve candidate j (cell c, particles ie, ig) on the current momenta.
+// The probability of candidate j (cell c, particles ie, ig) on the current
+// momenta and its accept/reject decision; writes its status and P / P_max
+// and returns whether it collides (the collision itself: ntc_collide).
 template <typename T>
-__device__ __forceinline__ void ntc_resolve(const NtcArgs<T>& a, int64_t j, int32_t c, int32_t ie, int32_t ig) {
-    const uint64_t idx = ((uint64_t)c << 32) | (uint64_t)(j - a.cand_off[c]);
-    const u32x4 r = draw(a.seed, idx, a.step, kNtcPick);
-    const double u_c = uniform53(r.c, r.d);
+__device__ __forceinline__ bool ntc_evaluate(const NtcArgs<T>& a, int64_t j, int32_t c, int32_t ie, int32_t ig) {
+    const double u_c = a.c_u[j];
     const d3 p = load_p(a.pt, ie), k = load_k(a.pt, ig);
     const double we = (double)a.pt.ew[ie], wg = (double)a.pt.gw[ig];
     uint8_t st = 1;
-    double ratio = -1.0, eb = 0.0, ea = 0.0;
+    double ratio = -1.0;
     if (!finite_pair(p, we, k, wg)) {
         st |= 4;
     } else {
-        const PairInv inv = pair_invariants(p, k);
+        const XFlux xf = x_flux(p, k, dot(p, p), dot(k, k));
         const double wmax = we > wg ? we : wg;
-        const double P = inv.x > 0.0 ? a.dt * a.dn * wmax * sigma_ratio(inv.x) * inv.flux : 0.0;
+        const double P = xf.x > 0.0 ? a.dt * a.dn * wmax * sigma_ratio(xf.x) * xf.flux : 0.0;
         ratio = P / a.p_max[c];
         if (ratio > 1.0) st |= 8;
-        if (u_c < ratio) {
-            st |= 2;
-            const u32x4 s = draw(a.seed, idx, a.step, kNtcScatter);
-            const double v = angle_icdf_v(uniform53(s.a, s.b), inv.x);
-            const Scattered sc = scatter(p, k, inv, v, uniform53(s.c, s.d));
-            eb = sc.e_before;
-            ea = sc.e_after;
-            bool upd_e = true, upd_g = true;
-            if (we != wg) {
-                const u32x4 q = draw(a.seed, idx, a.step, kNtcWeight);
-                const double wmin = we < wg ? we : wg;
-                const bool heavier_moves = uniform53(q.a, q.b) < wmin / wmax;
-                if (we > wg)
-                    upd_e = heavier_moves;
-                else
-                    upd_g = heavier_moves;
-            }
-            if (upd_e) {
-                a.pt.ex[ie] = (T)sc.p1.x;
-                a.pt.ey[ie] = (T)sc.p1.y;
-                a.pt.ez[ie] = (T)sc.p1.z;
-            }
-            if (upd_g) {
-                a.pt.gx[ig] = (T)sc.k1.x;
-                a.pt.gy[ig] = (T)sc.k1.y;
-                a.pt.gz[ig] = (T)sc.k1.z;
-            }
-        }
+        if (u_c < ratio) st |= 2;
     }
     a.r_ratio[j] = ratio;
-    a.r_eb[j] = eb;
-    a.r_ea[j] = ea;
     a.status[j] = st;
+    return (st & 2) != 0;
 }
 
+// Resolve the accepted candidate j: scattering angle from the plain
+// sampler, both momenta updated under the weight rule.
+template <typename T>
+__device__ __forceinline__ void ntc_collide(const NtcArgs<T>& a, int64_t j, int32_t c, int32_t ie, int32_t ig) {
+    const uint64_t idx = ((uint64_t)c << 32) | (uint64_t)a.c_local[j];
+    const d3 p = load_p(a.pt, ie), k = load_k(a.pt, ig);
+    const double we = (double)a.pt.ew[ie], wg = (double)a.pt.gw[ig];
+    const PairInv inv = pair_invariants(p, k);
+    const u32x4 s = draw(a.seed, idx, a.step, kNtcScatter);
+    const double v = angle_icdf_v(uniform53(s.a, s.b), inv.x);
+    const Scattered sc = scatter(p, k, inv, v, uniform53(s.c, s.d));
+    bool upd_e = true, upd_g = true;
+    if (we != wg) {
+        const u32x4 q = draw(a.seed, idx, a.step, kNtcWeight);
+        const double wmin = we < wg ? we : wg, wmax = we < wg ? wg : we;
+        const bool heavier_moves = uniform53(q.a, q.b) < wmin / wmax;
+        if (we > wg)
+            upd_e = heavier_moves;
+        else
+            upd_g = heavier_moves;
+    }
+    if (upd_e) {
+        a.pt.ex[ie] = (T)sc.p1.x;
+        a.pt.ey[ie] = (T)sc.p1.y;
+        a.pt.ez[ie] = (T)sc.p1.z;
+    }
+    if (upd_g) {
+        a.pt.gx[ig] = (T)sc.k1.x;
+        a.pt.gy[ig] = (T)sc.k1.y;
+        a.pt.gz[ig] = (T)sc.k1.z;
+    }
+    a.r_eb[j] = sc.e_before;
+    a.r_ea[j] = sc.e_after;
+}
+
+// Round t: ready candidates (earliest unresolved toucher of both their
+// particles) are evaluated, and the accepted ones listed in the workgroup's
+// segment for k_ntc_round_collide; the others register for round t + 1, or
+// after the last round mark their cell.
 template <typename T>
 __global__ __launch_bounds__(kNtcThreads) void k_ntc_round(const NtcArgs<T> a, int t) {
+    __shared__ int s_cnt[kNtcThreads / 64];
     const int64_t j = (int64_t)blockIdx.x * kNtcThreads + threadIdx.x;
-    if (j >= a.total || a.status[j] != 0) return;
-    const int32_t ie = a.c_ie[j], ig = a.c_ig[j];
-    const unsigned long long* te = a.touch_e + (t & 1) * a.cap_e;
-    const unsigned long long* tg = a.touch_g + (t & 1) * a.cap_g;
-    const unsigned long long mine = ntc_tag(a.epoch + (uint32_t)t, j);
-    if (te[ie] == mine && tg[ig] == mine) {
-        ntc_resolve<T>(a, j, a.c_cell[j], ie, ig);
-    } else if (t + 1 < kNtcRounds) {
-        const unsigned long long next = ntc_tag(a.epoch + (uint32_t)(t + 1), j);
-        atomicMax(a.touch_e + ((t + 1) & 1) * a.cap_e + ie, next);
-        atomicMax(a.touch_g + ((t + 1) & 1) * a.cap_g + ig, next);
-    } else {
-        a.pending[a.c_cell[j]] = 1;
+    const int lane = lane_id(), wave = threadIdx.x >> 6;
+    bool acc = false;
+    const uint8_t st = j < a.total ? a.status[j] : (uint8_t)1;
+    if (!(st & 1)) {
+        const int32_t ie = a.c_ie[j], ig = a.c_ig[j];
+        const unsigned long long* te = a.touch_e + (t & 1) * a.cap_e;
+        const unsigned long long* tg = a.touch_g + (t & 1) * a.cap_g;
+        const unsigned long long mine = ntc_tag(a.epoch + (uint32_t)t, j);
+        if ((t == 0 && st == 16) || (te[ie] == mine && tg[ig] == mine)) {
+            acc = ntc_evaluate<T>(a, j, a.c_cell[j], ie, ig);
+            // after round 0 few candidates are left: they collide here
+            if (t > 0 && acc) {
+                ntc_collide<T>(a, j, a.c_cell[j], ie, ig);
+                acc = false;
+            }
+        } else if (t + 1 < kNtcRounds) {
+            const unsigned long long next = ntc_tag(a.epoch + (uint32_t)(t + 1), j);
+            atomicMax(a.touch_e + ((t + 1) & 1) * a.cap_e + ie, next);
+            atomicMax(a.touch_g + ((t + 1) & 1) * a.cap_g + ig, next);
+        } else {
+            a.pending[a.c_cell[j]] = 1;
+        }
     }
+    const unsigned long long m = __ballot(acc);
+    if (lane == 0) s_cnt[wave] = __popcll(m);
+    __syncthreads();
+    int before = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < kNtcThreads / 64; ++w) {
+        before += w < wave ? s_cnt[w] : 0;
+        tot += s_cnt[w];
+    }
+    int32_t* seg = a.list + (int64_t)t * a.list_len + (int64_t)blockIdx.x * kNtcThreads;
+    if (acc) seg[before + __popcll(m & ((1ull << lane) - 1))] = (int32_t)j;
+    if (threadIdx.x == 0) a.seg_cnt[(int64_t)t * a.n_round_blocks + blockIdx.x] = tot;
+}
+
+// The collisions round t accepted: workgroup b takes the segment of round
+// workgroup b, one entry per lane.
+template <typename T>
+__global__ __launch_bounds__(kNtcThreads) void k_ntc_round_collide(const NtcArgs<T> a, int t) {
+    const int n = a.seg_cnt[(int64_t)t * a.n_round_blocks + blockIdx.x];
+    if ((int)threadIdx.x >= n) return;
+    const int64_t j = a.list[(int64_t)t * a.list_len + (int64_t)blockIdx.x * kNtcThreads + threadIdx.x];
+    ntc_collide<T>(a, j, a.c_cell[j], a.c_ie[j], a.c_ig[j]);
 }
 
 template <typename T>
@@ -324,8 +407,9 @@ __global__ __launch_bounds__(kNtcThreads) void k_ntc_serial(const NtcArgs<T> a) 
     const int64_t c = (int64_t)blockIdx.x * kNtcThreads + threadIdx.x;
     if (c >= a.n_cells || !a.pending[c]) return;
     a.pending[c] = 0;
-    for (int64_t j = a.cand_off[c]; j < a.cand_off[c + 1]; ++j)
-        if (a.status[j] == 0) ntc_resolve<T>(a, j, (int32_t)c, a.c_ie[j], a.c_ig[j]);
+    for (int64_t j = a.cand_full[c]; j < a.cand_full[c + 1]; ++j)
+        if (!(a.status[j] & 1) && ntc_evaluate<T>(a, j, (int32_t)c, a.c_ie[j], a.c_ig[j]))
+            ntc_collide<T>(a, j, (int32_t)c, a.c_ie[j], a.c_ig[j]);
 }
 
 __device__ __forceinline__ double wave_sum_d(double v) {
@@ -391,7 +475,7 @@ __global__ __launch_bounds__(kNtcThreads) void k_ntc_reduce(const uint8_t* statu
 }
 
 __global__ __launch_bounds__(kNtcThreads) void k_ntc_final(const NtcPart* part, int64_t n_part, int64_t total,
-                                                         cs_stats* stats) {
+                                                         cs_stats* stats, NtcCtl* ctl) {
     __shared__ NtcPart s[kNtcThreads / 64];
     NtcPart v = {0.0, 0.0, 0.0, 0, 0, 0};
     for (int64_t b = threadIdx.x; b < n_part; b += kNtcThreads) {
@@ -405,6 +489,10 @@ __global__ __launch_bounds__(kNtcThreads) void k_ntc_final(const NtcPart* part, 
     }
     const NtcPart r = block_sum_part(v, s);
     if (threadIdx.x == 0) {
+        NtcCtl z = {};
+        *ctl = z;
+    }
+    if (threadIdx.x == 0 && stats) {
         cs_stats o = {};
         o.n_pairs = total;
         o.n_collided = r.coll;
@@ -428,7 +516,8 @@ __global__ void k_ntc_stats_layout(cs_stats* stats) {
 // ---------------------------------------------------------------------------
 static inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
-static hipError_t grow(void** buf, size_t* bytes, size_t want, hipStream_t st) {
+static hipError_t grow(void** buf, size_t* bytes, size_t want, hipStream_t st, bool* fresh = nullptr) {
+    if (fresh) *fresh = false;
     if (*bytes >= want) return hipSuccess;
     hipError_t e = hipStreamSynchronize(st);
     if (e != hipSuccess) return e;
@@ -445,6 +534,7 @@ static hipError_t grow(void** buf, size_t* bytes, size_t want, hipStream_t st) {
         return e;
     }
     *bytes = g;
+    if (fresh) *fresh = true;
     return hipSuccess;
 }
 
@@ -469,15 +559,23 @@ static hipError_t ntc_launch(NtcState& s, const cs_species& e, const cs_species&
     const size_t b_pend = align256((size_t)(n_cells > 0 ? n_cells : 1));
     const size_t b_bsum = align256(8 * (size_t)(nb > 0 ? nb : 1));
     const size_t b_ctl = align256(sizeof(NtcCtl));
-    hipError_t err = grow(&s.cell_ws, &s.cell_bytes, b_count + b_off + b_pmax + b_pend + b_bsum + b_ctl, st);
+    bool fresh = false;
+    hipError_t err =
+        grow(&s.cell_ws, &s.cell_bytes, b_count + 2 * b_off + b_pmax + b_pend + b_bsum + b_ctl, st, &fresh);
     if (err != hipSuccess) return err;
+    if (fresh) {  // the control words start at zero
+        err = hipMemsetAsync(s.cell_ws, 0, s.cell_bytes, st);
+        if (err != hipSuccess) return err;
+    }
+    // the control words first: their place does not depend on the cell count
     char* cw = (char*)s.cell_ws;
-    int64_t* count = (int64_t*)cw;
+    NtcCtl* ctl = (NtcCtl*)cw;
+    int64_t* count = (int64_t*)(cw += b_ctl);
     int64_t* cand_off = (int64_t*)(cw += b_count);
     double* p_max = (double*)(cw += b_off);
     uint8_t* pending = (uint8_t*)(cw += b_pmax);
     long long* bsum = (long long*)(cw += b_pend);
-    NtcCtl* ctl = (NtcCtl*)(cw += b_bsum);
+    int64_t* cand_full = (int64_t*)(cw += b_bsum);
     if (!s.host) {
         err = hipHostMalloc(&s.host, sizeof(NtcCtl), hipHostMallocDefault);
         if (err != hipSuccess) {
@@ -511,18 +609,12 @@ static hipError_t ntc_launch(NtcState& s, const cs_species& e, const cs_species&
         if (err != hipSuccess) return err;
         s.epoch = 1;
     }
-    err = hipMemsetAsync(ctl, 0, sizeof(NtcCtl), st);
-    if (err == hipSuccess && n_cells > 0) err = hipMemsetAsync(pending, 0, (size_t)n_cells, st);
-    if (err != hipSuccess) return err;
     if (n_cells > 0) {
         k_ntc_count<T><<<(unsigned)((n_cells + 3) / 4), kNtcThreads, 0, st>>>(
-            (const T*)e.w, (const T*)g.w, off_e, off_g, n_cells, e.n, g.n, dt, dn, seed, step, count, p_max, ctl);
+            (const T*)e.w, (const T*)g.w, off_e, off_g, n_cells, e.n, g.n, dt, dn, seed, step, count, p_max, pending, ctl);
         k_ntc_scan_local<<<(unsigned)nb, kNtcThreads, 0, st>>>(count, n_cells, cand_off, bsum);
     }
     k_ntc_scan_top<<<1, kNtcThreads, 0, st>>>(bsum, nb, n_cells, cand_off, ctl);
-    if (n_cells > 0)
-        k_ntc_scan_add<<<(unsigned)((n_cells + kNtcThreads - 1) / kNtcThreads), kNtcThreads, 0, st>>>(bsum, n_cells,
-                                                                                                   cand_off);
     err = hipGetLastError();
     if (err == hipSuccess) err = hipMemcpyAsync(s.host, ctl, sizeof(NtcCtl), hipMemcpyDeviceToHost, st);
     if (err == hipSuccess) err = hipStreamSynchronize(st);
@@ -531,11 +623,12 @@ static hipError_t ntc_launch(NtcState& s, const cs_species& e, const cs_species&
     if (h.layout_bad || (n_cells == 0 && (e.n != 0 || g.n != 0))) {
         *out = NtcOutcome::kLayout;
         if (stats) k_ntc_stats_layout<<<1, 1, 0, st>>>(stats);
-        return hipGetLastError();
+        err = hipGetLastError();
+        return err == hipSuccess ? hipMemsetAsync(ctl, 0, sizeof(NtcCtl), st) : err;
     }
     if (h.too_many) {
         *out = NtcOutcome::kTooMany;
-        return hipSuccess;
+        return hipMemsetAsync(ctl, 0, sizeof(NtcCtl), st);
     }
     const int64_t total = h.total;
     // per-candidate area
@@ -543,7 +636,11 @@ static hipError_t ntc_launch(NtcState& s, const cs_species& e, const cs_species&
     const size_t tc = (size_t)(total > 0 ? total : 1);
     const size_t b_i32 = align256(4 * tc), b_u8 = align256(tc), b_d = align256(8 * tc);
     const size_t b_part = align256(sizeof(NtcPart) * (size_t)(n_part > 0 ? n_part : 1));
-    err = grow(&s.cand_ws, &s.cand_bytes, 3 * b_i32 + b_u8 + 3 * b_d + b_part, st);
+    const int64_t n_rb = (total + kNtcThreads - 1) / kNtcThreads;
+    const int64_t list_len = (n_rb > 0 ? n_rb : 1) * kNtcThreads;
+    const size_t b_list = align256(4 * (size_t)kNtcRounds * (size_t)list_len);
+    const size_t b_seg = align256(4 * (size_t)kNtcRounds * (size_t)(n_rb > 0 ? n_rb : 1));
+    err = grow(&s.cand_ws, &s.cand_bytes, 4 * b_i32 + b_u8 + 4 * b_d + b_part + b_list + b_seg, st);
     if (err != hipSuccess) return err;
     NtcArgs<T> a;
     a.pt = {(T*)e.x, (T*)e.y, (T*)e.z, (T*)e.w, (T*)g.x, (T*)g.y, (T*)g.z, (T*)g.w};
@@ -557,16 +654,24 @@ static hipError_t ntc_launch(NtcState& s, const cs_species& e, const cs_species&
     a.step = step;
     a.epoch = s.epoch;
     a.cand_off = cand_off;
+    a.boff = bsum;
+    a.cand_full = cand_full;
     a.p_max = p_max;
     char* q = (char*)s.cand_ws;
     a.c_ie = (int32_t*)q;
     a.c_ig = (int32_t*)(q += b_i32);
     a.c_cell = (int32_t*)(q += b_i32);
+    a.c_local = (int32_t*)(q += b_i32);
     a.status = (uint8_t*)(q += b_i32);
     a.r_ratio = (double*)(q += b_u8);
     a.r_eb = (double*)(q += b_d);
     a.r_ea = (double*)(q += b_d);
+    a.c_u = (double*)(q += b_d);
     NtcPart* part = (NtcPart*)(q += b_d);
+    a.list = (int32_t*)(q += b_part);
+    a.seg_cnt = (int32_t*)(q += b_list);
+    a.list_len = list_len;
+    a.n_round_blocks = n_rb;
     a.touch_e = (unsigned long long*)s.touch;
     a.touch_g = a.touch_e + 2 * s.cap_e;
     a.cap_e = s.cap_e;
@@ -575,12 +680,15 @@ static hipError_t ntc_launch(NtcState& s, const cs_species& e, const cs_species&
     s.epoch += kNtcRounds;
     if (total > 0) {
         const unsigned grid = (unsigned)((total + kNtcThreads - 1) / kNtcThreads);
-        k_ntc_pick<T><<<grid, kNtcThreads, 0, st>>>(a);
-        for (int t = 0; t < kNtcRounds; ++t) k_ntc_round<T><<<grid, kNtcThreads, 0, st>>>(a, t);
+        k_ntc_pick<T><<<(unsigned)((n_cells + 3) / 4), kNtcThreads, 0, st>>>(a);
+        for (int t = 0; t < kNtcRounds; ++t) {
+            k_ntc_round<T><<<grid, kNtcThreads, 0, st>>>(a, t);
+            if (t == 0) k_ntc_round_collide<T><<<grid, kNtcThreads, 0, st>>>(a, t);
+        }
         k_ntc_serial<T><<<(unsigned)((n_cells + kNtcThreads - 1) / kNtcThreads), kNtcThreads, 0, st>>>(a);
         k_ntc_reduce<<<(unsigned)n_part, kNtcThreads, 0, st>>>(a.status, a.r_ratio, a.r_eb, a.r_ea, total, part);
     }
-    if (stats) k_ntc_final<<<1, kNtcThreads, 0, st>>>(part, n_part, total, stats);
+    k_ntc_final<<<1, kNtcThreads, 0, st>>>(part, n_part, total, stats, ctl);
     return hipGetLastError();
 }
 
