@@ -167,6 +167,34 @@ def binning_stage(ctx, p, reps=20):
                          "bytes_per_launch": bytes_call, "avg_ms": ms}}
 
 
+def ntc_stage(ctx, p, steps=50, warmup=5):
+    """The step with no-time-counter candidate selection (cs_ntc_step) on the
+    same plasma: milliseconds per step by wall clock around the calls (each
+    call synchronises once), candidates and collisions per step, and the
+    workload's 1:1-pairing pair count per second for comparison with the
+    headline (both advance the same plasma by one step)."""
+    import time
+
+    import torch
+
+    from paper_2206_02937_amd import compton
+
+    e, g, oe, og = compton.to_device(p)
+    stats = ctx.stats_buffer()
+    for s in range(warmup):
+        ctx.ntc_step(e, g, oe, og, p.dt, p.density_norm, p.seed, s, stats=stats)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(warmup, warmup + steps):
+        ctx.ntc_step(e, g, oe, og, p.dt, p.density_norm, p.seed, s, stats=stats)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    st = stats.cpu().numpy()
+    return {"ms_per_step": ms, "candidates_per_step": int(st[0]), "collisions_per_step": int(st[1]),
+            "candidates_per_s": int(st[0]) / (ms * 1e-3), "pairs_equivalent_per_s": p.n_pairs / (ms * 1e-3),
+            "expected_collisions": float(st.view("float64")[8])}
+
+
 def pnet_stage(ctx, p, reps=20):
     """The paper's probability network against the analytic ratio it
     replaces, on the workload's 2^22 candidate pairs (photon, lepton, P_max and
@@ -429,6 +457,8 @@ def main():
     binned = binning_stage(ctx, p)
     print(json.dumps({"progress": "probability network"}), flush=True)
     pnet = pnet_stage(ctx, p)
+    print(json.dumps({"progress": "ntc"}), flush=True)
+    ntc = ntc_stage(ctx, p)
     cpu = None
     if not args.no_cpu:
         print(json.dumps({"progress": "cpu baseline"}), flush=True)
@@ -472,6 +502,7 @@ def main():
         "roofline_mlp": roof_mlp,
         "binning": binned,
         "pnet": pnet,
+        "ntc": ntc,
         "cpu_baseline": cpu,
         "last_stats": st,
     }
