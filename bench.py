@@ -195,6 +195,18 @@ def ntc_stage(ctx, p, steps=50, warmup=5):
             "expected_collisions": float(st.view("float64")[8])}
 
 
+def beam_gas_stage(ctx, net, sampler, steps=10, n_cells=4096):
+    """The paper's inverse-Compton benchmark at p_e = 100 m_e c (photon gas of
+    2.5 m_e c^2): scattered-photon spectra with the plain sampler and with
+    the network after `steps` steps (peak position, KS distance between the
+    two, the network's fallback fraction)."""
+    from paper_2206_02937_amd import beam_gas as B
+
+    if sampler not in ("mlp_f32", "mlp_bf16"):
+        return None
+    return B.compare_beam(ctx, 100.0, net, sampler, steps, n_cells)
+
+
 def pnet_stage(ctx, p, reps=20):
     """The paper's probability network against the analytic ratio it
     replaces, on the workload's 2^22 candidate pairs (photon, lepton, P_max and
@@ -459,6 +471,8 @@ def main():
     pnet = pnet_stage(ctx, p)
     print(json.dumps({"progress": "ntc"}), flush=True)
     ntc = ntc_stage(ctx, p)
+    print(json.dumps({"progress": "beam_gas"}), flush=True)
+    beam = beam_gas_stage(ctx, net, args.sampler)
     cpu = None
     if not args.no_cpu:
         print(json.dumps({"progress": "cpu baseline"}), flush=True)
@@ -503,6 +517,7 @@ def main():
         "binning": binned,
         "pnet": pnet,
         "ntc": ntc,
+        "beam_gas": beam,
         "cpu_baseline": cpu,
         "last_stats": st,
     }

@@ -207,6 +207,21 @@ def sampler_inputs(n, seed=0, x_min=1e-4, x_max=1e2):
     return log_uniform(rng, n, x_min, x_max), rng.random(n)
 
 
+def beam_gas(seed=0, p_e=100.0, eps=2.5, n_cells=1024, per_cell=256, dtype=np.float32, dt=1.0):
+    """Inverse-Compton beam in a photon gas (the paper's Sec. 3.3 benchmark):
+    in every cell per_cell electrons of momentum p_e along +z and per_cell
+    photons of energy eps with isotropic directions; unit weights.  With
+    density_norm = 1 / per_cell the pair probability of a step is
+    dt s(x)(1 - beta . k_hat): of order 1 % for p_e = 100 and dt = 1."""
+    rng = np.random.default_rng([seed, 7])
+    n = n_cells * per_cell
+    e = _species(np.zeros(n), np.zeros(n), np.full(n, float(p_e)), np.ones(n), dtype)
+    g = _photons_from_energy(rng, np.full(n, float(eps)), dtype)
+    off = _uniform_offsets(n_cells, per_cell)
+    return Plasma(f"beam_gas_pe{p_e:g}_eps{eps:g}_{n_cells}x{per_cell}", e, g, off, off.copy(), dt, 1.0 / per_cell,
+                  seed, {"cells": n_cells, "per_cell": per_cell, "p_e": p_e, "eps": eps})
+
+
 def make(name, seed=0):
     if name == "single_cell":
         return single_cell(seed)
@@ -218,4 +233,6 @@ def make(name, seed=0):
         return uneven(seed)
     if name == "power_law":
         return power_law(seed)
+    if name.startswith("beam_gas_"):
+        return beam_gas(seed, p_e=float(name[len("beam_gas_"):]))
     raise KeyError(name)

@@ -1,0 +1,71 @@
+"""The beam-gas workload (the paper's inverse-Compton benchmark, Sec. 3.3,
+Fig. 4a) on the GPU: the step matches the oracle element by element (1:1
+pairing with the fused and compact strategies, and the no-time-counter
+step), and the scattered photons' spectra with the plain sampler and with
+the BF16 sampler network agree (two-sample KS within the 99 % critical
+value of independent samples, the same peak bin just below p_e).  For
+p_e = 100 most rest-frame energies exceed the network's x range, so most of
+those samples come from the plain sampler (the fallback fraction is
+reported and checked)."""
+import numpy as np
+import pytest
+
+from paper_2206_02937_amd import plasma
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2206_02937_amd import compton
+
+    c = compton.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("strategy", ["fused", "compact"])
+def test_step_matches_oracle(ctx, orc, strategy):
+    from .test_gpu_step import step_and_compare
+
+    p = plasma.beam_gas(seed=2, p_e=100.0, n_cells=64, per_cell=256, dtype=np.float32)
+    ctx.set_strategy(strategy)
+    try:
+        res = step_and_compare(ctx, orc, p, [0, 1])
+    finally:
+        ctx.set_strategy("fused")
+    assert sum(r[0]["n_collided"] for r in res) > 100
+
+
+def test_ntc_step_matches_oracle(ctx, orc):
+    from .test_gpu_ntc import _chain_compare
+
+    p = plasma.beam_gas(seed=2, p_e=50.0, n_cells=64, per_cell=256, dtype=np.float32)
+    res = _chain_compare(ctx, orc, p, [0, 1])
+    assert res[0][0]["n_collided"] > 100
+
+
+@pytest.mark.parametrize("p_e", [25.0, 50.0, 100.0])
+def test_plain_and_network_spectra_agree(ctx, p_e):
+    from paper_2206_02937_amd import beam_gas as B
+
+    ctx.set_strategy("compact")
+    net = B.load_sampler(ctx, "mlp_bf16")
+    try:
+        r = B.compare_beam(ctx, p_e, net, "mlp_bf16", steps=10, n_cells=1024)
+    finally:
+        net.close()
+        ctx.set_strategy("fused")
+    a, b = r["plain"], r["mlp_bf16"]
+    n = min(a["scattered"], b["scattered"])
+    assert n > 2000
+    assert r["ks"] <= 1.63 * np.sqrt(2.0 / n), r
+    assert a["mode_over_pe"] == b["mode_over_pe"] and 0.85 <= a["mode_over_pe"] <= 1.1, r
+    assert abs(a["collisions"] - b["collisions"]) <= 5 * np.sqrt(a["collisions"]), r
+    if p_e == 100.0:
+        assert b["fallback_fraction"] > 0.6, r
+    if p_e == 25.0:
+        assert b["fallback_fraction"] < 0.5, r
