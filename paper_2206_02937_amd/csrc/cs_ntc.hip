@@ -19,22 +19,26 @@
 //                  block offsets added by k_ntc_pick); the
 //                  host reads the total (one stream synchronisation)
 //   k_ntc_pick     one wave per cell: its candidates' electrons and
-//                  photons; each registers in both particles' "first
-//                  toucher" words: atomicMax of (round tag << 32 |
-//                  ~candidate), so each word ends up holding the earliest
-//                  candidate that touches the particle
+//                  photons.  A cell of at most 64 candidates is settled in
+//                  the wave: candidates sharing no particle with an earlier
+//                  one are evaluated (probability, accept) and the accepted
+//                  ones listed; the others register for round 1 in the
+//                  particles' "first toucher" words (atomicMax of (round
+//                  tag << 32 | ~candidate): each word ends up holding the
+//                  earliest candidate that touches the particle).  Larger
+//                  cells register every candidate for round 0.
+//   k_ntc_collide_list  the listed accepted candidates, one per lane:
+//                  scattering and write-back (listing them first keeps the
+//                  long collision path off the lanes that only evaluate)
 //   k_ntc_round t  per unresolved candidate: ready when it is the earliest
 //                  unresolved toucher of both its particles; ready ones are
-//                  evaluated (probability, accept) and the accepted ones
-//                  listed; the others register for round t + 1 in the other
-//                  word set (two sets alternate, so a round never reads a
-//                  word that the same round writes); after the last round
-//                  they mark their cell
-//   k_ntc_round_collide  round 0's accepted candidates, one per lane:
-//                  scattering and write-back (listing them first keeps the
-//                  long collision path off the lanes that only evaluate;
-//                  in the later rounds, with few candidates left, the
-//                  accepted ones collide in the round kernel itself)
+//                  evaluated; round 0 (run only when a cell has more than
+//                  64 candidates) lists its accepted ones for the dense
+//                  collide, later rounds, with few candidates left, collide
+//                  them in place; the others register for round t + 1 in
+//                  the other word set (two sets alternate, so a round never
+//                  reads a word that the same round writes); after the last
+//                  round they mark their cell
 //   k_ntc_serial   one thread per marked cell resolves its remaining
 //                  candidates in order (long chains: a cell with one
 //                  electron and many candidates)
@@ -70,6 +74,8 @@ struct NtcCtl {
     long long total;
     int32_t layout_bad;
     int32_t too_many;
+    int32_t has_large;  // a cell with more than 64 candidates
+    int32_t pad;
 };
 
 struct NtcPart {
@@ -91,14 +97,15 @@ struct NtcArgs {
     int32_t *c_ie, *c_ig, *c_cell, *c_local;
     double* c_u;              // acceptance uniform of each candidate
     const long long* boff;    // block offsets of the candidate scan (cand_off holds block-local prefixes)
-    uint8_t* status;  // bit 0 resolved; 2 collided, 4 invalid, 8 P > P_max; 16 unresolved and ready in round 0
+    uint8_t* status;  // bit 0 resolved; 2 collided, 4 invalid, 8 P > P_max
     double *r_ratio, *r_eb, *r_ea;
     unsigned long long *touch_e, *touch_g;  // [2][cap_e], [2][cap_g]
     int64_t cap_e, cap_g;
     uint8_t* pending;    // [n_cells]
-    int32_t* list;       // [kNtcRounds][list_len]: accepted candidates, a 256-entry segment per round workgroup
-    int32_t* seg_cnt;    // [kNtcRounds][round workgroups]: entries of each segment
+    int32_t* list;       // round 0's accepted candidates, a 256-entry segment per round workgroup
+    int32_t* seg_cnt;    // [round workgroups]: entries of each segment
     int64_t list_len, n_round_blocks;
+    int32_t *pick_list, *pick_cnt;  // accepted candidates of the pick kernel: 256 per pick workgroup
 };
 
 __device__ __forceinline__ unsigned long long ntc_tag(uint32_t round_tag, int64_t j) {
@@ -153,6 +160,7 @@ __global__ __launch_bounds__(kNtcThreads) void k_ntc_count(const T* ew, const T*
                 const double fl = floor(n_exp);
                 const u32x4 r = draw(seed, (uint64_t)c, step, kNtcCount);
                 n = (int64_t)fl + (uniform53(r.a, r.b) < n_exp - fl ? 1 : 0);
+                if (n > 64) ctl->has_large = 1;
             }
         }
         count[c] = n;
@@ -231,60 +239,81 @@ __global__ __launch_bounds__(kNtcThreads) void k_ntc_scan_top(long long* bsum, i
 
 // One wave per cell: the cell's candidates, 64 at a time.  A cell of at most
 // 64 candidates is settled in the wave: a candidate that shares no particle
-// with an earlier one of its cell is ready in round 0 (status 16) and the
-// others wait for round 1 (they register there when round 0 finds them not
-// ready); no touch word is needed.  Larger cells register every candidate.
+// with an earlier one of its cell is ready, and is evaluated here (the
+// accepted ones listed in the workgroup's segment for the dense collide);
+// the others register for round 1.  Larger cells register every candidate
+// for round 0.
+template <typename T>
+__device__ __forceinline__ bool ntc_evaluate(const NtcArgs<T>& a, int64_t j, int32_t c, int32_t ie, int32_t ig);
+
 template <typename T>
 __global__ __launch_bounds__(kNtcThreads) void k_ntc_pick(const NtcArgs<T> a) {
-    const int64_t c = (int64_t)blockIdx.x * (kNtcThreads / 64) + (threadIdx.x >> 6);
-    if (c >= a.n_cells) return;
-    // cand_off holds prefixes within each scan block: add the block offsets,
-    // and keep the full offsets for the serial pass
-    const int64_t j0 = a.cand_off[c] + a.boff[c / kNtcScanBlock];
-    const int64_t j1 = c + 1 < a.n_cells ? a.cand_off[c + 1] + a.boff[(c + 1) / kNtcScanBlock] : a.total;
-    const int lane = lane_id();
-    if (lane == 0) {
-        a.cand_full[c] = j0;
-        if (c + 1 == a.n_cells) a.cand_full[c + 1] = j1;
-    }
-    if (j0 == j1) return;
-    const int64_t e0 = a.off_e[c], g0 = a.off_g[c];
-    const uint64_t nec = (uint64_t)(a.off_e[c + 1] - e0), ngc = (uint64_t)(a.off_g[c + 1] - g0);
-    const bool small = j1 - j0 <= 64;
-    for (int64_t jb = j0; jb < j1; jb += 64) {
-        const int64_t j = jb + lane;
-        const bool act = j < j1;
-        int32_t ie = -1, ig = -1;
-        if (act) {
-            const u32x4 r = draw(a.seed, ((uint64_t)c << 32) | (uint64_t)(j - j0), a.step, kNtcPick);
-            ie = (int32_t)(e0 + (int64_t)(((uint64_t)r.a * nec) >> 32));
-            ig = (int32_t)(g0 + (int64_t)(((uint64_t)r.b * ngc) >> 32));
-            a.c_local[j] = (int32_t)(j - j0);
-            a.c_u[j] = uniform53(r.c, r.d);
+    __shared__ int s_cnt[kNtcThreads / 64];
+    const int lane = lane_id(), wave = threadIdx.x >> 6;
+    const int64_t c = (int64_t)blockIdx.x * (kNtcThreads / 64) + wave;
+    bool acc = false;
+    int64_t j_acc = 0;
+    if (c < a.n_cells) {
+        // cand_off holds prefixes within each scan block: add the block offsets,
+        // and keep the full offsets for the serial pass
+        const int64_t j0 = a.cand_off[c] + a.boff[c / kNtcScanBlock];
+        const int64_t j1 = c + 1 < a.n_cells ? a.cand_off[c + 1] + a.boff[(c + 1) / kNtcScanBlock] : a.total;
+        if (lane == 0) {
+            a.cand_full[c] = j0;
+            if (c + 1 == a.n_cells) a.cand_full[c + 1] = j1;
         }
-        if (small) {
-            const int n = (int)(j1 - j0);
-            bool conflict = false;
-            for (int m = 0; m < n; ++m) {
-                const int32_t ie_m = __shfl(ie, m, 64), ig_m = __shfl(ig, m, 64);
-                conflict = conflict || (m < lane && (ie_m == ie || ig_m == ig));
-            }
+        const int64_t e0 = a.off_e[c], g0 = a.off_g[c];
+        const uint64_t nec = (uint64_t)(a.off_e[c + 1] - e0), ngc = (uint64_t)(a.off_g[c + 1] - g0);
+        const bool small = j1 - j0 <= 64;
+        for (int64_t jb = j0; jb < j1; jb += 64) {
+            const int64_t j = jb + lane;
+            const bool act = j < j1;
+            int32_t ie = -1, ig = -1;
             if (act) {
+                const u32x4 r = draw(a.seed, ((uint64_t)c << 32) | (uint64_t)(j - j0), a.step, kNtcPick);
+                ie = (int32_t)(e0 + (int64_t)(((uint64_t)r.a * nec) >> 32));
+                ig = (int32_t)(g0 + (int64_t)(((uint64_t)r.b * ngc) >> 32));
+                a.c_local[j] = (int32_t)(j - j0);
+                a.c_u[j] = uniform53(r.c, r.d);
                 a.c_ie[j] = ie;
                 a.c_ig[j] = ig;
                 a.c_cell[j] = (int32_t)c;
-                a.status[j] = conflict ? 0 : 16;
+                a.status[j] = 0;
             }
-        } else if (act) {
-            a.c_ie[j] = ie;
-            a.c_ig[j] = ig;
-            a.c_cell[j] = (int32_t)c;
-            a.status[j] = 0;
-            const unsigned long long tag = ntc_tag(a.epoch, j);
-            atomicMax(a.touch_e + ie, tag);
-            atomicMax(a.touch_g + ig, tag);
+            if (small) {
+                const int n = (int)(j1 - j0);
+                bool conflict = false;
+                for (int m = 0; m < n; ++m) {
+                    const int32_t ie_m = __shfl(ie, m, 64), ig_m = __shfl(ig, m, 64);
+                    conflict = conflict || (m < lane && (ie_m == ie || ig_m == ig));
+                }
+                if (act && !conflict) {
+                    acc = ntc_evaluate<T>(a, j, (int32_t)c, ie, ig);
+                    j_acc = j;
+                } else if (act) {
+                    const unsigned long long tag = ntc_tag(a.epoch + 1u, j);
+                    atomicMax(a.touch_e + a.cap_e + ie, tag);
+                    atomicMax(a.touch_g + a.cap_g + ig, tag);
+                }
+            } else if (act) {
+                const unsigned long long tag = ntc_tag(a.epoch, j);
+                atomicMax(a.touch_e + ie, tag);
+                atomicMax(a.touch_g + ig, tag);
+            }
         }
     }
+    // the workgroup's accepted candidates (small cells: at most one per lane)
+    const unsigned long long m = __ballot(acc);
+    if (lane == 0) s_cnt[wave] = __popcll(m);
+    __syncthreads();
+    int before = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < kNtcThreads / 64; ++w) {
+        before += w < wave ? s_cnt[w] : 0;
+        tot += s_cnt[w];
+    }
+    if (acc) a.pick_list[(int64_t)blockIdx.x * kNtcThreads + before + __popcll(m & ((1ull << lane) - 1))] = (int32_t)j_acc;
+    if (threadIdx.x == 0) a.pick_cnt[blockIdx.x] = tot;
 }
 
 // The probability of candidate j (cell c, particles ie, ig) on the current
@@ -349,7 +378,8 @@ __device__ __forceinline__ void ntc_collide(const NtcArgs<T>& a, int64_t j, int3
 
 // Round t: ready candidates (earliest unresolved toucher of both their
 // particles) are evaluated, and the accepted ones listed in the workgroup's
-// segment for k_ntc_round_collide; the others register for round t + 1, or
+// segment for k_ntc_collide_list (round 0) or collide in place (later
+// rounds); the others register for round t + 1, or
 // after the last round mark their cell.
 template <typename T>
 __global__ __launch_bounds__(kNtcThreads) void k_ntc_round(const NtcArgs<T> a, int t) {
@@ -363,7 +393,7 @@ __global__ __launch_bounds__(kNtcThreads) void k_ntc_round(const NtcArgs<T> a, i
         const unsigned long long* te = a.touch_e + (t & 1) * a.cap_e;
         const unsigned long long* tg = a.touch_g + (t & 1) * a.cap_g;
         const unsigned long long mine = ntc_tag(a.epoch + (uint32_t)t, j);
-        if ((t == 0 && st == 16) || (te[ie] == mine && tg[ig] == mine)) {
+        if (te[ie] == mine && tg[ig] == mine) {
             acc = ntc_evaluate<T>(a, j, a.c_cell[j], ie, ig);
             // after round 0 few candidates are left: they collide here
             if (t > 0 && acc) {
@@ -378,6 +408,7 @@ __global__ __launch_bounds__(kNtcThreads) void k_ntc_round(const NtcArgs<T> a, i
             a.pending[a.c_cell[j]] = 1;
         }
     }
+    if (t != 0) return;  // (uniform) only round 0 lists its accepted candidates
     const unsigned long long m = __ballot(acc);
     if (lane == 0) s_cnt[wave] = __popcll(m);
     __syncthreads();
@@ -387,18 +418,19 @@ __global__ __launch_bounds__(kNtcThreads) void k_ntc_round(const NtcArgs<T> a, i
         before += w < wave ? s_cnt[w] : 0;
         tot += s_cnt[w];
     }
-    int32_t* seg = a.list + (int64_t)t * a.list_len + (int64_t)blockIdx.x * kNtcThreads;
+    int32_t* seg = a.list + (int64_t)blockIdx.x * kNtcThreads;
     if (acc) seg[before + __popcll(m & ((1ull << lane) - 1))] = (int32_t)j;
-    if (threadIdx.x == 0) a.seg_cnt[(int64_t)t * a.n_round_blocks + blockIdx.x] = tot;
+    if (threadIdx.x == 0) a.seg_cnt[blockIdx.x] = tot;
 }
 
-// The collisions round t accepted: workgroup b takes the segment of round
-// workgroup b, one entry per lane.
+// Accepted candidates listed in segments of 256 (one per listing
+// workgroup): workgroup b collides segment b, one entry per lane.
 template <typename T>
-__global__ __launch_bounds__(kNtcThreads) void k_ntc_round_collide(const NtcArgs<T> a, int t) {
-    const int n = a.seg_cnt[(int64_t)t * a.n_round_blocks + blockIdx.x];
+__global__ __launch_bounds__(kNtcThreads) void k_ntc_collide_list(const NtcArgs<T> a, const int32_t* list,
+                                                                const int32_t* cnt) {
+    const int n = cnt[blockIdx.x];
     if ((int)threadIdx.x >= n) return;
-    const int64_t j = a.list[(int64_t)t * a.list_len + (int64_t)blockIdx.x * kNtcThreads + threadIdx.x];
+    const int64_t j = list[(int64_t)blockIdx.x * kNtcThreads + threadIdx.x];
     ntc_collide<T>(a, j, a.c_cell[j], a.c_ie[j], a.c_ig[j]);
 }
 
@@ -638,9 +670,13 @@ static hipError_t ntc_launch(NtcState& s, const cs_species& e, const cs_species&
     const size_t b_part = align256(sizeof(NtcPart) * (size_t)(n_part > 0 ? n_part : 1));
     const int64_t n_rb = (total + kNtcThreads - 1) / kNtcThreads;
     const int64_t list_len = (n_rb > 0 ? n_rb : 1) * kNtcThreads;
-    const size_t b_list = align256(4 * (size_t)kNtcRounds * (size_t)list_len);
-    const size_t b_seg = align256(4 * (size_t)kNtcRounds * (size_t)(n_rb > 0 ? n_rb : 1));
-    err = grow(&s.cand_ws, &s.cand_bytes, 4 * b_i32 + b_u8 + 4 * b_d + b_part + b_list + b_seg, st);
+    const int64_t n_pb = (n_cells + kNtcThreads / 64 - 1) / (kNtcThreads / 64);  // pick workgroups
+    const size_t b_list = align256(4 * (size_t)list_len);
+    const size_t b_seg = align256(4 * (size_t)(n_rb > 0 ? n_rb : 1));
+    const size_t b_plist = align256(4 * (size_t)(n_pb > 0 ? n_pb : 1) * kNtcThreads);
+    const size_t b_pcnt = align256(4 * (size_t)(n_pb > 0 ? n_pb : 1));
+    err = grow(&s.cand_ws, &s.cand_bytes, 4 * b_i32 + b_u8 + 4 * b_d + b_part + b_list + b_seg + b_plist + b_pcnt,
+               st);
     if (err != hipSuccess) return err;
     NtcArgs<T> a;
     a.pt = {(T*)e.x, (T*)e.y, (T*)e.z, (T*)e.w, (T*)g.x, (T*)g.y, (T*)g.z, (T*)g.w};
@@ -670,6 +706,8 @@ static hipError_t ntc_launch(NtcState& s, const cs_species& e, const cs_species&
     NtcPart* part = (NtcPart*)(q += b_d);
     a.list = (int32_t*)(q += b_part);
     a.seg_cnt = (int32_t*)(q += b_list);
+    a.pick_list = (int32_t*)(q += b_seg);
+    a.pick_cnt = (int32_t*)(q += b_plist);
     a.list_len = list_len;
     a.n_round_blocks = n_rb;
     a.touch_e = (unsigned long long*)s.touch;
@@ -680,11 +718,15 @@ static hipError_t ntc_launch(NtcState& s, const cs_species& e, const cs_species&
     s.epoch += kNtcRounds;
     if (total > 0) {
         const unsigned grid = (unsigned)((total + kNtcThreads - 1) / kNtcThreads);
-        k_ntc_pick<T><<<(unsigned)((n_cells + 3) / 4), kNtcThreads, 0, st>>>(a);
-        for (int t = 0; t < kNtcRounds; ++t) {
-            k_ntc_round<T><<<grid, kNtcThreads, 0, st>>>(a, t);
-            if (t == 0) k_ntc_round_collide<T><<<grid, kNtcThreads, 0, st>>>(a, t);
+        k_ntc_pick<T><<<(unsigned)n_pb, kNtcThreads, 0, st>>>(a);
+        k_ntc_collide_list<T><<<(unsigned)n_pb, kNtcThreads, 0, st>>>(a, a.pick_list, a.pick_cnt);
+        // round 0 only for cells of more than 64 candidates (the others were
+        // settled in the pick kernel and registered for round 1)
+        if (h.has_large) {
+            k_ntc_round<T><<<grid, kNtcThreads, 0, st>>>(a, 0);
+            k_ntc_collide_list<T><<<grid, kNtcThreads, 0, st>>>(a, a.list, a.seg_cnt);
         }
+        for (int t = 1; t < kNtcRounds; ++t) k_ntc_round<T><<<grid, kNtcThreads, 0, st>>>(a, t);
         k_ntc_serial<T><<<(unsigned)((n_cells + kNtcThreads - 1) / kNtcThreads), kNtcThreads, 0, st>>>(a);
         k_ntc_reduce<<<(unsigned)n_part, kNtcThreads, 0, st>>>(a.status, a.r_ratio, a.r_eb, a.r_ea, total, part);
     }
