@@ -195,6 +195,38 @@ def ntc_stage(ctx, p, steps=50, warmup=5):
             "expected_collisions": float(st.view("float64")[8])}
 
 
+def training_stage(ctx, batch=4096, steps=200):
+    """One optimiser step of the sampler network (cs_mlp_train_step: forward,
+    backward, fixed-order gradient sum, Adam) at the training driver's batch
+    of 4096 samples, on a separate copy of the network: samples/s and the
+    FP32 rate at 75 k flops per sample (forward 25 k, backward 50 k)."""
+    import numpy as np
+    import torch
+
+    from paper_2206_02937_amd import compton, plasma
+
+    net = compton.MLP.load(ctx, WEIGHTS)
+    x, u = plasma.sampler_inputs(batch, seed=11)
+    xd = torch.from_numpy(x.astype(np.float32)).cuda()
+    ud = torch.from_numpy(u.astype(np.float32)).cuda()
+    mu, r = ctx.sample_plain(xd, ud)
+    loss = torch.zeros((), dtype=torch.float32, device="cuda")
+    for _ in range(10):
+        net.train_step(xd, ud, mu, r, lr=1e-4, loss_out=loss)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(steps):
+        net.train_step(xd, ud, mu, r, lr=1e-4, loss_out=loss)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / steps
+    net.close()
+    tfs = 75e3 * batch / (ms * 1e-3) / 1e12
+    return {"batch": batch, "ms_per_step": ms, "samples_per_s": batch / (ms * 1e-3), "fp32_tflops": tfs,
+            "fp32_frac": tfs / PEAK_FP32_TFLOPS}
+
+
 def beam_gas_stage(ctx, net, sampler, steps=10, n_cells=4096):
     """The paper's inverse-Compton benchmark at p_e = 100 m_e c (photon gas of
     2.5 m_e c^2): scattered-photon spectra with the plain sampler and with
@@ -473,6 +505,8 @@ def main():
     ntc = ntc_stage(ctx, p)
     print(json.dumps({"progress": "beam_gas"}), flush=True)
     beam = beam_gas_stage(ctx, net, args.sampler)
+    print(json.dumps({"progress": "training"}), flush=True)
+    training = training_stage(ctx)
     cpu = None
     if not args.no_cpu:
         print(json.dumps({"progress": "cpu baseline"}), flush=True)
@@ -518,6 +552,7 @@ def main():
         "pnet": pnet,
         "ntc": ntc,
         "beam_gas": beam,
+        "training": training,
         "cpu_baseline": cpu,
         "last_stats": st,
     }
