@@ -183,7 +183,7 @@ CS_API cs_status cs_check_layout(cs_ctx* ctx, const int64_t* off, int64_t n_cell
  *
  * The call synchronises `stream` once (the host needs the step's candidate
  * count to size the launches) and keeps scratch in the context: about
- * 40 bytes per candidate, 30 per cell, and 32 per particle (tags that
+ * 60 bytes per candidate, 300 per cell, and 32 per particle (tags that
  * persist across calls).
  * Errors: CS_ERR_INVALID_ARG (NULL arrays with n > 0, NULL offsets,
  *         n_cells >= 2^31 - 1, dt <= 0 or non-finite, density_norm < 0),
