@@ -39,9 +39,9 @@
 //                  the other word set (two sets alternate, so a round never
 //                  reads a word that the same round writes); after the last
 //                  round they mark their cell
-//   k_ntc_serial   one thread per marked cell resolves its remaining
-//                  candidates in order (long chains: a cell with one
-//                  electron and many candidates)
+//   k_ntc_serial   one wave per marked cell; its lane 0 resolves the
+//                  cell's remaining candidates in order (long chains: a
+//                  cell with one electron and many candidates)
 //   k_ntc_reduce / k_ntc_final  fixed-order sums into cs_stats
 // Tags grow by one per round and never repeat (a per-context epoch), so the
 // touch words are never cleared between steps.
@@ -434,14 +434,27 @@ __global__ __launch_bounds__(kNtcThreads) void k_ntc_collide_list(const NtcArgs<
     ntc_collide<T>(a, j, a.c_cell[j], a.c_ie[j], a.c_ig[j]);
 }
 
+// One wave per marked cell: the wave reads the statuses of 64 candidates at
+// a time and lane 0 resolves the unresolved ones among them in order.
 template <typename T>
 __global__ __launch_bounds__(kNtcThreads) void k_ntc_serial(const NtcArgs<T> a) {
-    const int64_t c = (int64_t)blockIdx.x * kNtcThreads + threadIdx.x;
-    if (c >= a.n_cells || !a.pending[c]) return;
-    a.pending[c] = 0;
-    for (int64_t j = a.cand_full[c]; j < a.cand_full[c + 1]; ++j)
-        if (!(a.status[j] & 1) && ntc_evaluate<T>(a, j, (int32_t)c, a.c_ie[j], a.c_ig[j]))
-            ntc_collide<T>(a, j, (int32_t)c, a.c_ie[j], a.c_ig[j]);
+    const int64_t c = (int64_t)blockIdx.x * (kNtcThreads / 64) + (threadIdx.x >> 6);
+    if (c >= a.n_cells || !a.pending[c]) return;  // (uniform in the wave)
+    const int lane = lane_id();
+    const int64_t j0 = a.cand_full[c], j1 = a.cand_full[c + 1];
+    for (int64_t jb = j0; jb < j1; jb += 64) {
+        const int64_t j = jb + lane;
+        unsigned long long m = __ballot(j < j1 && !(a.status[j] & 1));
+        if (lane == 0) {
+            while (m) {
+                const int64_t q = jb + (__ffsll((long long)m) - 1);
+                m &= m - 1;
+                if (ntc_evaluate<T>(a, q, (int32_t)c, a.c_ie[q], a.c_ig[q]))
+                    ntc_collide<T>(a, q, (int32_t)c, a.c_ie[q], a.c_ig[q]);
+            }
+        }
+    }
+    if (lane == 0) a.pending[c] = 0;
 }
 
 __device__ __forceinline__ double wave_sum_d(double v) {
@@ -727,7 +740,7 @@ static hipError_t ntc_launch(NtcState& s, const cs_species& e, const cs_species&
             k_ntc_collide_list<T><<<grid, kNtcThreads, 0, st>>>(a, a.list, a.seg_cnt);
         }
         for (int t = 1; t < kNtcRounds; ++t) k_ntc_round<T><<<grid, kNtcThreads, 0, st>>>(a, t);
-        k_ntc_serial<T><<<(unsigned)((n_cells + kNtcThreads - 1) / kNtcThreads), kNtcThreads, 0, st>>>(a);
+        k_ntc_serial<T><<<(unsigned)n_pb, kNtcThreads, 0, st>>>(a);
         k_ntc_reduce<<<(unsigned)n_part, kNtcThreads, 0, st>>>(a.status, a.r_ratio, a.r_eb, a.r_ea, total, part);
     }
     k_ntc_final<<<1, kNtcThreads, 0, st>>>(part, n_part, total, stats, ctl);
