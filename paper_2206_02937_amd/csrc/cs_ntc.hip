@@ -133,15 +133,31 @@ __global__ __launch_bounds__(kNtcThreads) void k_ntc_count(const T* ew, const T*
         }
         return;
     }
+    // largest finite non-negative weight; four reads in flight per lane (a
+    // maximum does not depend on the order)
     double w = 0.0;
-    for (int64_t i = e0 + lane; i < e1; i += 64) {
-        const double v = (double)ew[i];
-        if (isfinite(v) && v > w) w = v;
-    }
-    for (int64_t i = g0 + lane; i < g1; i += 64) {
-        const double v = (double)gw[i];
-        if (isfinite(v) && v > w) w = v;
-    }
+    auto scan = [&](const T* arr, int64_t b, int64_t end) {
+        double m0 = 0.0, m1 = 0.0, m2 = 0.0, m3 = 0.0;
+        int64_t i = b + lane;
+        for (; i + 192 < end; i += 256) {
+            const double v0 = (double)arr[i], v1 = (double)arr[i + 64], v2 = (double)arr[i + 128],
+                         v3 = (double)arr[i + 192];
+            if (isfinite(v0) && v0 > m0) m0 = v0;
+            if (isfinite(v1) && v1 > m1) m1 = v1;
+            if (isfinite(v2) && v2 > m2) m2 = v2;
+            if (isfinite(v3) && v3 > m3) m3 = v3;
+        }
+        for (; i < end; i += 64) {
+            const double v = (double)arr[i];
+            if (isfinite(v) && v > m0) m0 = v;
+        }
+        m0 = m0 > m1 ? m0 : m1;
+        m2 = m2 > m3 ? m2 : m3;
+        m0 = m0 > m2 ? m0 : m2;
+        if (m0 > w) w = m0;
+    };
+    scan(ew, e0, e1);
+    scan(gw, g0, g1);
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
         const double v = __shfl_xor(w, o, 64);
