@@ -229,9 +229,10 @@ def test_deterministic(ctx):
         assert sa == sb
 
 
-def test_full_grid_matches_oracle(ctx, orc):
-    """The 128x128-cell grid (2^22 electrons and photons, FP32), one step."""
-    p = plasma.grid(seed=0, nx=128, ny=128, per_cell=256, dtype=np.float32)
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_full_grid_matches_oracle(ctx, orc, dtype):
+    """The 128x128-cell grid (2^22 electrons and photons), one step."""
+    p = plasma.grid(seed=0, nx=128, ny=128, per_cell=256, dtype=dtype)
     res = _chain_compare(ctx, orc, p, [0])
     st, gst, _ = res[0]
     assert st["n_pairs"] > 100000 and st["n_collided"] > 10000
