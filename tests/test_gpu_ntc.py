@@ -236,3 +236,14 @@ def test_full_grid_matches_oracle(ctx, orc, dtype):
     res = _chain_compare(ctx, orc, p, [0])
     st, gst, _ = res[0]
     assert st["n_pairs"] > 100000 and st["n_collided"] > 10000
+
+
+def test_uneven_cells_match_oracle(ctx, orc):
+    """Poisson cell counts with a dense bump (64 x 64 cells): the bump's cells
+    draw hundreds of candidates each, so they take the tagged rounds rather
+    than the in-wave path of small cells."""
+    p = plasma.uneven(seed=1, side=64)
+    res = _chain_compare(ctx, orc, p, [0, 1])
+    st, gst, diag = res[0]
+    per_cell = np.bincount(diag["cell"], minlength=p.n_cells)
+    assert per_cell.max() > 64 and st["n_collided"] > 1000, (per_cell.max(), st)
