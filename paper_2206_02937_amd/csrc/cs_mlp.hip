@@ -456,78 +456,109 @@ __global__ void k_mlp_act_scale(float* scales) {
 }
 
 constexpr int kMfmaThreads = 256;
+// Register budget and tiles in flight of the inference kernel: with all four
+// tiles of a group side by side and at most 168 registers (three waves per
+// SIMD) it needs no spills; measured on 2^22 samples this was the fastest of
+// {2, 4} tiles x {2, 3, 4} waves per SIMD (all of which give the same bits).
+constexpr int kMfmaWavesPerSimd = 3;
+constexpr int kMfmaTilesAtOnce = 4;
+constexpr int kFbCap = 128;  // deferred samples one wave can hold (it flushes at 64)
 
-// Block-uniform loop over 64-sample groups (one 16-sample tile per wave).
-// Samples outside the network's domain are deferred: their indices are
-// compacted in order into s_fb and answered by the plain sampler in dense
-// passes, so that its Newton iteration never runs on a mostly idle wave.
-template <int PREC>
-__global__ __launch_bounds__(kMfmaThreads) void k_mlp_mfma(const FwdArgs a, const MlpDev m) {
-    __shared__ NetLds<PREC> s_net;
-    __shared__ int s_fb[kMfmaThreads + 64];
-    __shared__ int s_wcnt[kMfmaThreads / 64];
-    __shared__ int s_fbn;
-    net_load<PREC>(s_net, m);
-    if (threadIdx.x == 0) s_fbn = 0;
-    __syncthreads();
-    const int tid = threadIdx.x;
+// The plain sampler for the first `cnt` (<= 64) deferred samples of a wave's
+// queue, one per lane.  Called by the whole wave.
+__device__ __forceinline__ void fallback_pass(const FwdArgs& a, const int64_t* q, int cnt) {
     const int lane = lane_id();
-    const int wave = tid >> 6;
+    const bool act = lane < cnt;
+    const int64_t i = act ? q[lane] : 0;
+    const float x = act ? a.x[i] : 0.0f, u = act ? a.u[i] : 0.5f;
+    const double v = angle_icdf_v((double)u, (double)x);
+    if (act) {
+        if (a.mu) a.mu[i] = (float)(1.0 - v);
+        if (a.ratio) a.ratio[i] = (float)(1.0 / (1.0 + (double)x * v));
+        if (a.mask) a.mask[i] = 1;
+    }
+}
+
+// Each wave walks groups of 64 consecutive samples (wave-strided over the
+// grid): lane l reads sample l and forms its features once, the four
+// 16-sample tiles are evaluated side by side, and lane
+// l takes its own sample's outputs back and writes them (whole-line stores).
+// Samples outside the network's domain are answered afterwards, in a second
+// walk over the same groups: they are queued per wave in LDS, in order, and
+// the plain sampler takes them in dense passes of 64, so that its Newton
+// iteration never runs on a mostly idle wave (and its registers are not
+// live while the network runs).  No workgroup barrier after the set-up.
+template <int PREC>
+__global__ __launch_bounds__(kMfmaThreads, kMfmaWavesPerSimd) void k_mlp_mfma(const FwdArgs a, const MlpDev m) {
+    __shared__ NetLds<PREC> s_net;
+    __shared__ int64_t s_fb[kMfmaThreads / 64][kFbCap];
+    net_load<PREC>(s_net, m);
+    __syncthreads();
+    const int lane = lane_id();
+    const int wave = wave_uniform((int)threadIdx.x >> 6);
     const bool sampling = a.mu || a.ratio || a.mask;
-    auto flush = [&](int n) {
-        for (int base = 0; base < n; base += kMfmaThreads) {
-            const int q = base + tid;
-            if (__any(q < n)) {
-                const bool act = q < n;
-                const int64_t i = act ? s_fb[q] : 0;
-                const float x = act ? a.x[i] : 0.0f, u = act ? a.u[i] : 0.5f;
-                const double v = angle_icdf_v((double)u, (double)x);
-                if (act) {
-                    if (a.mu) a.mu[i] = (float)(1.0 - v);
-                    if (a.ratio) a.ratio[i] = (float)(1.0 / (1.0 + (double)x * v));
-                    if (a.mask) a.mask[i] = 1;
-                }
-            }
-        }
-    };
     const int64_t n_groups = (a.n + 63) / 64;
-    for (int64_t grp = blockIdx.x; grp < n_groups; grp += gridDim.x) {
-        const int64_t i = grp * 64 + wave * 16 + (lane & 15);
+    const int64_t first = (int64_t)blockIdx.x * (kMfmaThreads / 64) + wave;
+    const int64_t stride = (int64_t)gridDim.x * (kMfmaThreads / 64);
+    for (int64_t grp = first; grp < n_groups; grp += stride) {
+        const int64_t i = grp * 64 + lane;
         const bool active = i < a.n;
         const float x = active ? a.x[i] : 1.0f, u = active ? a.u[i] : 0.5f;
-        float f1, f2, y0, y1;
+        float f1, f2;
         features(x, u, f1, f2);
-        mlp_tile<PREC>(s_net.frag, s_net.P, s_net.sc, f1, f2, y0, y1);
-        const bool mine = lane < 16 && active;
-        if (mine && a.y) {
-            a.y[2 * i] = y0;
-            a.y[2 * i + 1] = y1;
-        }
-        if (!sampling) continue;  // uniform over the grid
-        const bool defer = mine && !in_range(x);
-        if (mine && !defer) net_out(a, i, x, y0);
-        const uint64_t msk = __ballot(defer);
-        if (lane == 0) s_wcnt[wave] = __popcll(msk);
-        __syncthreads();
-        int wbase = 0, total = 0;
+        // the network's LDS copy is re-read for every group: an opaque
+        // (wave-uniform, zero) offset keeps the compiler from hoisting all of
+        // it into registers, which would cost occupancy
+        int opaque = 0;
+        asm volatile("" : "+s"(opaque));
+        const auto* frag = s_net.frag + opaque;
+        const float* P = s_net.P + opaque;
+        const float* sc = s_net.sc + opaque;
+        float o0 = 0.0f, o1 = 0.0f;
 #pragma unroll
-        for (int w = 0; w < kMfmaThreads / 64; ++w) {
-            wbase += w < wave ? s_wcnt[w] : 0;
-            total += s_wcnt[w];
+        for (int t0 = 0; t0 < 4; t0 += kMfmaTilesAtOnce) {
+            float g1[kMfmaTilesAtOnce], g2[kMfmaTilesAtOnce], y0[kMfmaTilesAtOnce], y1[kMfmaTilesAtOnce];
+#pragma unroll
+            for (int k = 0; k < kMfmaTilesAtOnce; ++k) {
+                const int src = 16 * (t0 + k) + (lane & 15);
+                g1[k] = __shfl(f1, src, 64);
+                g2[k] = __shfl(f2, src, 64);
+            }
+            mlp_tiles<PREC, kMfmaTilesAtOnce>(frag, P, sc, g1, g2, y0, y1);
+#pragma unroll
+            for (int k = 0; k < kMfmaTilesAtOnce; ++k)
+                if ((lane >> 4) == t0 + k) {
+                    o0 = y0[k];
+                    o1 = y1[k];
+                }
         }
-        const int nf = s_fbn;  // < kMfmaThreads here; a group adds at most 64
-        if (defer) s_fb[nf + wbase + __popcll(msk & ((1ull << lane) - 1ull))] = (int)i;
-        __syncthreads();
-        if (nf + total >= kMfmaThreads) {
-            flush(nf + total);
-            __syncthreads();
-            if (tid == 0) s_fbn = 0;
-        } else if (tid == 0) {
-            s_fbn = nf + total;
-        }
-        __syncthreads();
+        if (active && a.y) *(float2*)(a.y + 2 * i) = make_float2(o0, o1);
+        if (sampling && active && in_range(x)) net_out(a, i, x, o0);
     }
-    if (sampling) flush(s_fbn);
+    if (!sampling) return;
+    int64_t* fb = s_fb[wave];
+    int nfb = 0;  // wave-uniform
+    for (int64_t grp = first; grp < n_groups; grp += stride) {
+        const int64_t i = grp * 64 + lane;
+        const bool defer = i < a.n && !in_range(a.x[i]);
+        const uint64_t msk = __ballot(defer);
+        if (msk == 0) continue;
+        if (defer) fb[nfb + __popcll(msk & ((1ull << lane) - 1ull))] = i;
+        nfb += __popcll(msk);
+        // the queue's writes precede the pass's reads (one wave, in order)
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        if (nfb >= 64) {
+            fallback_pass(a, fb, 64);
+            const int64_t rest = lane < nfb - 64 ? fb[64 + lane] : 0;
+            __builtin_amdgcn_wave_barrier();
+            if (lane < nfb - 64) fb[lane] = rest;
+            nfb -= 64;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+    if (nfb > 0) fallback_pass(a, fb, nfb);
 }
 
 // ---------------------------------------------------------------------------
@@ -547,8 +578,10 @@ hipError_t launch_mlp_forward(const MlpDev& m, cs_sampler prec, const float* x, 
     if (prec == CS_SAMPLER_MLP_F32) {
         k_mlp_fwd_f32<<<(unsigned)((n + kMlpSamples - 1) / kMlpSamples), kMlpThreads, 0, st>>>(a);
     } else {
-        const int64_t tiles = (n + 15) / 16;
-        int64_t blocks = (tiles + 3) / 4;
+        // one 64-sample group per wave and step of the loop; 2048 workgroups
+        // (8 per compute unit) cover the chip
+        const int64_t groups = (n + 63) / 64;
+        int64_t blocks = (groups + kMfmaThreads / 64 - 1) / (kMfmaThreads / 64);
         if (blocks > 2048) blocks = 2048;
         if (prec == CS_SAMPLER_MLP_BF16)
             k_mlp_mfma<CS_SAMPLER_MLP_BF16><<<(unsigned)blocks, kMfmaThreads, 0, st>>>(a, m);

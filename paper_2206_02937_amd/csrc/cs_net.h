@@ -16,8 +16,9 @@
 //     the accumulator fragment it holds, so a layer's output stays in
 //     registers and becomes the next layer's B operand once the weight
 //     fragments list the input neurons in the same order (k-slot 8g + e of
-//     k-step s <-> neuron 16(2s + e/4) + 4g + e%4).  Layers 1 and 5 (K = 2,
-//     N = 2) stay in FP32 on the vector ALUs.
+//     k-step s <-> neuron 16(2s + e/4) + 4g + e%4, i.e. the lane's neurons
+//     0..7 form k-step 0 and 8..15 k-step 1).  Layers 1 and 5 (K = 2, N = 2)
+//     stay in FP32 on the vector ALUs.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -99,100 +100,138 @@ struct FragT<CS_SAMPLER_MLP_FP8> {
     typedef long type;
 };
 
+// Packed reduced-precision operand of 8 layer inputs.
+template <int PREC>
+__device__ __forceinline__ typename FragT<PREC>::type pack_inputs(const float (&h)[8], float inv) {
+    if constexpr (PREC == CS_SAMPLER_MLP_BF16) {
+        bf16x8 b;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) b[e] = (__bf16)h[e];
+        return b;
+    } else {
+        uint64_t b = 0;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) b |= (uint64_t)to_e4m3(h[e] * inv) << (8 * e);
+        return (long)b;
+    }
+}
+
 // NTL tiles of 16 samples each on one wave, evaluated side by side (their
 // MFMA and SiLU chains are independent, so each hides the others' latency).
 // For tile k every lane passes the features of sample (lane % 16) in f1[k],
 // f2[k] and receives that sample's outputs in y0[k], y1[k].  frag, W1,
 // biases, W5 come from LDS.  Each tile's arithmetic is that of a lone tile.
+//
+// A hidden layer's outputs are packed into the next layer's B operands as
+// they are produced (lane neurons 0..7 -> B0, 8..15 -> B1), so only the
+// packed inputs and outputs of a layer are live; the last hidden layer's
+// outputs go straight into the output layer's sums, in the order the lane's
+// neurons are produced (t ascending, then r).
 template <int PREC, int NTL>
 __device__ __forceinline__ void mlp_tiles(const typename FragT<PREC>::type* frag, const float* P_lds,
                                           const float* scales, const float (&f1)[NTL], const float (&f2)[NTL],
                                           float (&y0)[NTL], float (&y1)[NTL]) {
+    typedef typename FragT<PREC>::type FT;
     const int lane = lane_id();
     const int g = lane >> 4;
-    float h[NTL][16];
+    FT B0[NTL], B1[NTL];
+    {
+        const float inv = PREC == CS_SAMPLER_MLP_FP8 ? 1.0f / scales[3] : 1.0f;
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
+        for (int half = 0; half < 2; ++half) {
+            float h[NTL][8];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int n = 16 * t + 4 * g + r;
-            const float w1a = P_lds[cW1 + 2 * n], w1b = P_lds[cW1 + 2 * n + 1], b1 = P_lds[cB1 + n];
+            for (int e = 0; e < 8; ++e) {
+                const int n = 16 * (2 * half + e / 4) + 4 * g + (e & 3);
+                const float w1a = P_lds[cW1 + 2 * n], w1b = P_lds[cW1 + 2 * n + 1], b1 = P_lds[cB1 + n];
 #pragma unroll
-            for (int k = 0; k < NTL; ++k) h[k][4 * t + r] = silu_fast(fmaf(w1b, f2[k], fmaf(w1a, f1[k], b1)));
-        }
-    const int offB[3] = {cB2, cB3, cB4};
-#pragma unroll
-    for (int L = 0; L < 3; ++L) {
-        typename FragT<PREC>::type B0[NTL], B1[NTL];
-        float sc = 1.0f;
-        if constexpr (PREC == CS_SAMPLER_MLP_BF16) {
-#pragma unroll
-            for (int k = 0; k < NTL; ++k)
-#pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    B0[k][e] = (__bf16)h[k][e];
-                    B1[k][e] = (__bf16)h[k][8 + e];
-                }
-        } else {
-            const float inv = 1.0f / scales[3 + L];
-            sc = scales[L] * scales[3 + L];
+                for (int k = 0; k < NTL; ++k) h[k][e] = silu_fast(fmaf(w1b, f2[k], fmaf(w1a, f1[k], b1)));
+            }
 #pragma unroll
             for (int k = 0; k < NTL; ++k) {
-                uint64_t b0 = 0, b1 = 0;
-#pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    b0 |= (uint64_t)to_e4m3(h[k][e] * inv) << (8 * e);
-                    b1 |= (uint64_t)to_e4m3(h[k][8 + e] * inv) << (8 * e);
-                }
-                B0[k] = (long)b0;
-                B1[k] = (long)b1;
+                if (half == 0)
+                    B0[k] = pack_inputs<PREC>(h[k], inv);
+                else
+                    B1[k] = pack_inputs<PREC>(h[k], inv);
             }
         }
+    }
+    const int offB[3] = {cB2, cB3, cB4};
+    float p0[NTL], p1[NTL];
+#pragma unroll
+    for (int k = 0; k < NTL; ++k) p0[k] = p1[k] = 0.0f;
+#pragma unroll
+    for (int L = 0; L < 3; ++L) {
+        float sc = 1.0f, inv_next = 1.0f;
+        if constexpr (PREC == CS_SAMPLER_MLP_FP8) {
+            sc = scales[L] * scales[3 + L];
+            if (L < 2) inv_next = 1.0f / scales[4 + L];
+        }
+        FT N0[NTL], N1[NTL];
+        float half[NTL][4];  // outputs of an even tile t, packed with tile t + 1
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-            const auto A0 = frag[((L * 4 + t) * 2 + 0) * 64 + lane];
-            const auto A1 = frag[((L * 4 + t) * 2 + 1) * 64 + lane];
+            const FT A0 = frag[((L * 4 + t) * 2 + 0) * 64 + lane];
+            const FT A1 = frag[((L * 4 + t) * 2 + 1) * 64 + lane];
             float bias[4];
 #pragma unroll
             for (int r = 0; r < 4; ++r) bias[r] = P_lds[offB[L] + 16 * t + 4 * g + r];
 #pragma unroll
             for (int k = 0; k < NTL; ++k) {
                 floatx4 acc;
+                float o[4];
                 if constexpr (PREC == CS_SAMPLER_MLP_BF16) {
 #pragma unroll
                     for (int r = 0; r < 4; ++r) acc[r] = bias[r];
                     acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A0, B0[k], acc, 0, 0, 0);
                     acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A1, B1[k], acc, 0, 0, 0);
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) h[k][4 * t + r] = silu_fast(acc[r]);
+                    for (int r = 0; r < 4; ++r) o[r] = silu_fast(acc[r]);
                 } else {
                     acc = {0.0f, 0.0f, 0.0f, 0.0f};
                     acc = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(A0, B0[k], acc, 0, 0, 0);
                     acc = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(A1, B1[k], acc, 0, 0, 0);
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) h[k][4 * t + r] = silu_fast(fmaf(acc[r], sc, bias[r]));
+                    for (int r = 0; r < 4; ++r) o[r] = silu_fast(fmaf(acc[r], sc, bias[r]));
                 }
+                if (L == 2) {
+                    // output layer sums, neuron order t ascending then r
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int n = 16 * t + 4 * g + r;
+                        p0[k] = fmaf(P_lds[cW5 + n], o[r], p0[k]);
+                        p1[k] = fmaf(P_lds[cW5 + kMlpHidden + n], o[r], p1[k]);
+                    }
+                } else if ((t & 1) == 0) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) half[k][r] = o[r];
+                } else {
+                    const float h8[8] = {half[k][0], half[k][1], half[k][2], half[k][3], o[0], o[1], o[2], o[3]};
+                    if (t == 1)
+                        N0[k] = pack_inputs<PREC>(h8, inv_next);
+                    else
+                        N1[k] = pack_inputs<PREC>(h8, inv_next);
+                }
+            }
+        }
+        if (L < 2) {
+#pragma unroll
+            for (int k = 0; k < NTL; ++k) {
+                B0[k] = N0[k];
+                B1[k] = N1[k];
             }
         }
     }
 #pragma unroll
     for (int k = 0; k < NTL; ++k) {
-        float p0 = 0.0f, p1 = 0.0f;
-#pragma unroll
-        for (int t = 0; t < 4; ++t)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int n = 16 * t + 4 * g + r;
-                p0 = fmaf(P_lds[cW5 + n], h[k][4 * t + r], p0);
-                p1 = fmaf(P_lds[cW5 + kMlpHidden + n], h[k][4 * t + r], p1);
-            }
+        float q0 = p0[k], q1 = p1[k];
         // sum the four lane groups (fixed butterfly order)
-        p0 += __shfl_xor(p0, 16, 64);
-        p1 += __shfl_xor(p1, 16, 64);
-        p0 += __shfl_xor(p0, 32, 64);
-        p1 += __shfl_xor(p1, 32, 64);
-        y0[k] = p0 + P_lds[cB5];
-        y1[k] = p1 + P_lds[cB5 + 1];
+        q0 += __shfl_xor(q0, 16, 64);
+        q1 += __shfl_xor(q1, 16, 64);
+        q0 += __shfl_xor(q0, 32, 64);
+        q1 += __shfl_xor(q1, 32, 64);
+        y0[k] = q0 + P_lds[cB5];
+        y1[k] = q1 + P_lds[cB5 + 1];
     }
 }
 

@@ -8,7 +8,10 @@ Pairs whose acceptance is decided within rounding (|u - P| <= delta P, delta
 equal to the tolerance) are "ambiguous": both particles of such a pair are
 left out of the per-event comparison and counted; the count must stay small
 against its expectation 2 delta sum(P).  Every particle the oracle leaves
-untouched must be bitwise unchanged on the GPU.
+bitwise untouched (invalid inputs included, NaN payloads and all) must be
+bitwise unchanged on the GPU.  Every other particle of the compared set is
+compared: a GPU value that is not finite where the oracle's is finite counts
+as an infinite error, and the number compared must equal the size of the set.
 """
 import numpy as np
 
@@ -29,6 +32,32 @@ def run_oracle(orc, p, state_e, state_g, step, cells=None):
     return e, g, st, diag
 
 
+def _bits(d):
+    """Bit patterns of the three momentum components (n x 3 unsigned ints)."""
+    cols = []
+    for c in "xyz":
+        a = np.ascontiguousarray(d[c])
+        cols.append(a.view(np.uint64 if a.dtype.itemsize == 8 else np.uint32))
+    return np.stack(cols, axis=1)
+
+
+def _vec(d):
+    return np.stack([d["x"], d["y"], d["z"]], axis=1).astype(np.float64)
+
+
+def _event_errors(gpu, ref, scale):
+    """|gpu - ref| / scale per particle; 0 where the two are bitwise equal,
+    inf where the GPU value is not finite but the oracle's is (or the scale
+    is not a positive finite number while the two differ)."""
+    g, r = _vec(gpu), _vec(ref)
+    same = np.all(_bits(gpu) == _bits(ref), axis=1)
+    with np.errstate(invalid="ignore", divide="ignore", over="ignore"):
+        err = np.linalg.norm(g - r, axis=1) / scale
+    ok = np.isfinite(err) & np.all(np.isfinite(g), axis=1)
+    err = np.where(ok, err, np.inf)
+    return np.where(same, 0.0, err)
+
+
 def compare(before_e, before_g, gpu_e, gpu_g, ref_e, ref_g, diag, dtype, e_mask=None, g_mask=None):
     """Return a dict with max errors, ambiguous count and its expectation.
     e_mask / g_mask restrict the comparison to the processed particles."""
@@ -43,37 +72,36 @@ def compare(before_e, before_g, gpu_e, gpu_g, ref_e, ref_g, diag, dtype, e_mask=
     e_mask &= ~amb
     g_mask[partner[amb]] = False
 
-    def arr(d):
-        return np.stack([d["x"], d["y"], d["z"]], axis=1).astype(np.float64)
-
-    pr, pg = arr(ref_e), arr(gpu_e)
-    kr, kg = arr(ref_g), arr(gpu_g)
-    gam = np.sqrt(1.0 + (pr * pr).sum(1))
-    eps = np.sqrt((kr * kr).sum(1))
-    err_e = np.linalg.norm(pg - pr, axis=1) / gam
-    with np.errstate(divide="ignore", invalid="ignore"):
-        err_g = np.where(eps > 0, np.linalg.norm(kg - kr, axis=1) / np.where(eps > 0, eps, 1), 0.0)
-    # untouched by the oracle -> bitwise unchanged on the GPU
-    same_e = np.all(arr(ref_e) == arr(before_e), axis=1) & e_mask
-    same_g = np.all(arr(ref_g) == arr(before_g), axis=1) & g_mask
-    bad_e = ~np.all(arr(gpu_e)[same_e] == arr(before_e)[same_e], axis=1)
-    bad_g = ~np.all(arr(gpu_g)[same_g] == arr(before_g)[same_g], axis=1)
-    ew = e_mask & ~np.isnan(err_e)
-    gw = g_mask & ~np.isnan(err_g)
+    pr, kr = _vec(ref_e), _vec(ref_g)
+    with np.errstate(invalid="ignore", over="ignore"):
+        gam = np.sqrt(1.0 + (pr * pr).sum(1))
+        eps = np.sqrt((kr * kr).sum(1))
+    # a photon of zero energy keeps its (zero) momentum: absolute error there
+    err_e = _event_errors(gpu_e, ref_e, gam)
+    err_g = _event_errors(gpu_g, ref_g, np.where(eps > 0, eps, 1.0))
+    # untouched by the oracle (bit for bit) -> bitwise unchanged on the GPU
+    same_e = np.all(_bits(ref_e) == _bits(before_e), axis=1) & e_mask
+    same_g = np.all(_bits(ref_g) == _bits(before_g), axis=1) & g_mask
+    bad_e = ~np.all(_bits(gpu_e)[same_e] == _bits(before_e)[same_e], axis=1)
+    bad_g = ~np.all(_bits(gpu_g)[same_g] == _bits(before_g)[same_g], axis=1)
     return {
-        "max_err_e": float(err_e[ew].max()) if ew.any() else 0.0,
-        "max_err_g": float(err_g[gw].max()) if gw.any() else 0.0,
+        "max_err_e": float(err_e[e_mask].max()) if e_mask.any() else 0.0,
+        "max_err_g": float(err_g[g_mask].max()) if g_mask.any() else 0.0,
         "n_ambiguous": int(amb.sum()),
         "expected_ambiguous": float(2 * delta * P[paired].sum()),
         "untouched_changed": int(bad_e.sum() + bad_g.sum()),
-        "n_compared_e": int(ew.sum()),
-        "n_compared_g": int(gw.sum()),
+        "n_compared_e": int(np.isfinite(err_e[e_mask]).sum()),
+        "n_compared_g": int(np.isfinite(err_g[g_mask]).sum()),
+        "n_expected_e": int(e_mask.sum()),
+        "n_expected_g": int(g_mask.sum()),
     }
 
 
 def assert_parity(res, dtype, what=""):
     tol = tolerance(dtype)
     assert res["untouched_changed"] == 0, (what, res)
+    assert res["n_compared_e"] == res["n_expected_e"], (what, res)
+    assert res["n_compared_g"] == res["n_expected_g"], (what, res)
     assert res["max_err_e"] <= tol, (what, res)
     assert res["max_err_g"] <= tol, (what, res)
     assert res["n_ambiguous"] <= 10 * res["expected_ambiguous"] + 3, (what, res)

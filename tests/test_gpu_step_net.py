@@ -192,32 +192,102 @@ def test_step_f32_network_matches_oracle(ctx, orc, mo, dtype, strategy):
     assert abs(st["energy_after"] - st["energy_before"]) <= 1e-12 * st["energy_before"]
 
 
+# One rounding step of each reduced format at unit magnitude (the spacing of
+# the format's values in [1, 2)): the largest change one rounding decision of
+# a unit-sized quantity can make.
+ROUNDING_STEP = {"mlp_bf16": 2.0 ** -7, "mlp_fp8": 2.0 ** -3}
+
+
+def gpu_network_mu(net, precision, diag, u_mu, sel):
+    """cos(theta) the library's network gives (cs_mlp_sample) at the FP32
+    rounding of the oracle's (x, u) of the electrons in sel; NaN elsewhere."""
+    mu = np.full(diag["x"].size, np.nan)
+    if not sel.any():
+        return mu
+    xf = diag["x"][sel].astype(np.float32)
+    uf = u_mu[sel].astype(np.float32)
+    m, _, mask = net.sample(_dev(xf), _dev(uf), precision)
+    assert not mask.cpu().numpy().any()  # every listed x is inside the domain
+    mu[sel] = m.cpu().numpy().astype(np.float64)
+    return mu
+
+
+def network_parity(orc, p, net, precision, before_e, before_g, gpu_e, gpu_g, step, cells=None, emu=None):
+    """Per-event parity of a GPU step with the network sampler, in two parts
+    that bound every event:
+      (1) the oracle step fed, for each collided pair inside the network's
+          domain, the cos(theta) the library's network gives at that pair's
+          (x, u) must match the GPU step per event to the storage tolerance
+          (everything but the network evaluation is checked in full);
+      (2) that cos(theta) must lie within one rounding step of the format
+          (ROUNDING_STEP) of the network oracle's emulation, for every event
+          (emu: callable (x, u) -> raw outputs y[n, 2]).
+    Returns (parity result, mu deviations |mu_gpu - mu_emu|, event count)."""
+    from oracle import mlp_oracle as mo
+
+    _, _, _, diag = parity.run_oracle(orc, p, before_e, before_g, step, cells=cells)
+    ne = before_e["x"].size
+    u_mu, _ = orc.scatter_uniforms(np.arange(ne), p.seed, step)
+    x = diag["x"]
+    xf = x.astype(np.float32)
+    valid = (diag["P"] >= 0) & (x > 0)
+    inside = valid & (xf >= np.float32(mo.X_MIN)) & (xf <= np.float32(mo.X_MAX))
+    collided = valid & (diag["u"] < diag["P"])
+    # the network is asked for every pair that could collide (ambiguous
+    # decisions included), so the oracle step never falls back by accident
+    mu_gpu = gpu_network_mu(net, precision, diag, u_mu, inside)
+    e = {k: v.copy() for k, v in before_e.items()}
+    g = {k: v.copy() for k, v in before_g.items()}
+    orc.compton_step(e, g, p.off_e, p.off_g, p.dt, p.density_norm, p.seed, step, cells=cells, mu_given=mu_gpu)
+    me = mg = None
+    if cells is not None:
+        me, mg = parity.cell_masks(p, cells)
+    res = parity.compare(before_e, before_g, gpu_e, gpu_g, e, g, diag, before_e["x"].dtype, me, mg)
+    dev = np.zeros(0)
+    sel = collided & inside
+    if emu is not None and sel.any():
+        y = emu(xf[sel].astype(np.float64), u_mu[sel].astype(np.float32).astype(np.float64))
+        dev = np.abs(np.clip(y[:, 0], -1.0, 1.0) - mu_gpu[sel])
+    return res, dev, int(sel.sum())
+
+
 @pytest.mark.parametrize("precision", ["mlp_bf16", "mlp_fp8"])
 def test_step_quantized_network_matches_emulation(ctx, orc, mo, precision):
-    """Reduced-precision networks against the oracle step fed the network
-    oracle's rounding emulation.  The kernel's SiLU and its accumulation order
-    differ from the emulation by ~1e-6 relative, which moves a few layer
-    inputs across a rounding boundary: most events agree to FP32 accuracy, the
-    rest within the size of one rounding step."""
+    """Reduced-precision networks inside the step, every event bounded: the
+    step matches the FP64 oracle fed the library network's cos(theta) to
+    1e-12 per event (FP64 storage), and that cos(theta) lies within one
+    rounding step of the format of the oracle's rounding emulation.  (The
+    kernel's SiLU and accumulation order differ from the emulation by ~1e-6
+    relative, which moves a few layer inputs across a rounding boundary.)"""
+    from paper_2206_02937_amd import compton
+
     p = _plasma(np.float64)
-    (before_e, before_g, gpu_e, gpu_g, ref_e, ref_g, st, ost, diag, mu, collided,
-     inside) = run_case(ctx, orc, mo, p, precision)
-    amb = _ambiguous(diag)
-    err_e, err_g, _, _ = per_event_errors(before_e, before_g, gpu_e, gpu_g, ref_e, ref_g, diag)
-    sel = collided & inside & ~amb
-    e = np.maximum(err_e[sel], err_g[diag["partner"][sel]])
-    frac_tight = float(np.mean(e <= 1e-5))
-    _log(f"  {precision}: {sel.sum()} events, within 1e-5: {frac_tight:.4f}, "
-         f"p99 {np.percentile(e, 99):.2e}, max {e.max():.2e}")
-    big = 2e-2 if precision == "mlp_bf16" else 2e-1
-    assert frac_tight >= (0.8 if precision == "mlp_bf16" else 0.5)
-    assert np.percentile(e, 99) <= big
-    # fallback events use the plain sampler on both sides: FP64 parity
-    fb = collided & ~inside & ~amb
-    if fb.any():
-        assert np.maximum(err_e[fb], err_g[diag["partner"][fb]]).max() <= 1e-12
-    assert st["n_fallback"] == int((collided & ~inside).sum())
+    params = _net_params(mo)
+    net = compton.MLP(ctx, params)
+    calib = None
+    if precision == "mlp_bf16":
+        net.quantize("mlp_bf16")
+    else:
+        cx, cu = plasma.sampler_inputs(65536, seed=7)
+        calib = (cx.astype(np.float32), cu.astype(np.float32))
+        net.quantize("mlp_fp8", _dev(calib[0]), _dev(calib[1]))
+    e_dev, g_dev, oe, og = compton.to_device(p)
+    before_e, before_g = compton.to_host(e_dev), compton.to_host(g_dev)
+    stats = ctx.stats_buffer()
+    ctx.step(e_dev, g_dev, oe, og, p.dt, p.density_norm, p.seed, 1, sampler=precision, mlp=net, stats=stats)
+    st = compton.decode_stats(stats)
+    gpu_e, gpu_g = compton.to_host(e_dev), compton.to_host(g_dev)
+    emu = lambda x, u: _quantized_forward(mo, params.astype(np.float64), x, u, precision, calib)  # noqa: E731
+    res, dev, n_ev = network_parity(orc, p, net, precision, before_e, before_g, gpu_e, gpu_g, 1, emu=emu)
+    _log(f"  {precision}: {n_ev} network events; {res}; |mu - emu| max {dev.max():.3e}, "
+         f"p99 {np.percentile(dev, 99):.3e}, exact to 1e-6: {np.mean(dev <= 1e-6):.4f}")
+    parity.assert_parity(res, np.float64, precision)
+    assert n_ev > 1000
+    assert dev.max() <= ROUNDING_STEP[precision], dev.max()
+    # the oracle emulation reproduces most events to FP32 accuracy
+    assert np.mean(dev <= 1e-5) >= (0.8 if precision == "mlp_bf16" else 0.5)
     assert abs(st["energy_after"] - st["energy_before"]) <= 1e-12 * st["energy_before"]
+    net.close()
 
 
 def test_step_network_fallback_heavy(ctx, orc, mo):
