@@ -155,6 +155,31 @@ CS_API cs_status cs_compton_step(cs_ctx* ctx, cs_dtype dtype, cs_species electro
                           double density_norm, uint64_t seed, uint64_t step, cs_sampler sampler,
                           const cs_mlp* mlp, cs_stats* stats, void* stream);
 
+/*
+ * cs_compton_step_noalloc -- cs_compton_step for callers that cannot
+ * allocate device memory during the step (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): it calls no
+ * hipMalloc, hipFree or allocating routine.  Same arguments, semantics,
+ * results (bit for bit) and errors as cs_compton_step; it always runs the
+ * fused strategy, whatever the context's options.
+ *
+ * Its workspace is a static device buffer of 8 MiB that the library holds on
+ * every device it runs on until the process ends (looked up and initialised
+ * once per device by cs_create).  That bounds the problem: about 24 bytes per
+ * cell plus 4 per 256 pairs, i.e. roughly 340,000 cells of 256 pairs; larger
+ * problems fail with CS_ERR_UNSUPPORTED (and cs_last_error says how much the
+ * step would need) before anything is queued.
+ *
+ * Every call on one device shares that device's buffer, whatever the
+ * context: calls on one stream (or otherwise ordered) are safe; calls that
+ * overlap on one device -- concurrent streams, or threads -- race and give
+ * undefined results.
+ */
+CS_API cs_status cs_compton_step_noalloc(cs_ctx* ctx, cs_dtype dtype, cs_species electrons, cs_species photons,
+                                  const int64_t* off_e, const int64_t* off_g, int64_t n_cells, double dt,
+                                  double density_norm, uint64_t seed, uint64_t step, cs_sampler sampler,
+                                  const cs_mlp* mlp, cs_stats* stats, void* stream);
+
 /* Synchronous layout check of device offsets: CS_OK or CS_ERR_LAYOUT. */
 CS_API cs_status cs_check_layout(cs_ctx* ctx, const int64_t* off, int64_t n_cells, int64_t n_particles,
                           void* stream);

@@ -73,6 +73,8 @@ def lib():
     L.cs_sync.restype = st
     L.cs_compton_step.argtypes = [vp, C.c_int, Species, Species, vp, vp, i64, d, d, u64, u64, C.c_int, vp, vp, vp]
     L.cs_compton_step.restype = st
+    L.cs_compton_step_noalloc.argtypes = L.cs_compton_step.argtypes
+    L.cs_compton_step_noalloc.restype = st
     L.cs_ntc_step.argtypes = [vp, C.c_int, Species, Species, vp, vp, i64, d, d, u64, u64, vp, vp]
     L.cs_ntc_step.restype = st
     L.cs_check_layout.argtypes = [vp, vp, i64, i64, vp]
@@ -220,6 +222,17 @@ class Context:
                                    off_e.numel() - 1, float(dt), float(density_norm), int(seed), int(step),
                                    SAMPLERS[sampler], None if mlp is None else mlp.handle, _ptr(stats),
                                    _stream(stream))
+        self._check(rc)
+
+    def step_noalloc(self, e, g, off_e, off_g, dt, density_norm, seed, step, sampler="plain", mlp=None, stats=None,
+                     stream=None):
+        """step through cs_compton_step_noalloc (no device allocation; the
+        library's static scratch, shared by every call on the device)."""
+        code = _dtype_code(e["x"])
+        rc = lib().cs_compton_step_noalloc(self._h, code, _species(e), _species(g), _ptr(off_e), _ptr(off_g),
+                                           off_e.numel() - 1, float(dt), float(density_norm), int(seed), int(step),
+                                           SAMPLERS[sampler], None if mlp is None else mlp.handle, _ptr(stats),
+                                           _stream(stream))
         self._check(rc)
 
     def ntc_step(self, e, g, off_e, off_g, dt, density_norm, seed, step, stats=None, stream=None):

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <algorithm>
+#include <mutex>
 #include <utility>
 #include <new>
 #include <string>
@@ -86,6 +87,58 @@ bool species_ok(const cs_species& s) {
     return s.x && s.y && s.z && s.w;
 }
 
+// Scratch of cs_compton_step_noalloc: a file-scope device array holding one
+// step workspace (control block, look-back status words, per-step area).
+// Each device that runs the library holds its own copy until the process
+// ends.  Host code never passes the array's name to a kernel (in host code it
+// is a stand-in, not a device address): cs_create looks up the device address
+// of its copy on each device once, with that device current, and everything
+// after that uses the looked-up address.
+constexpr size_t kStaticScratchBytes = (size_t)8 << 20;
+constexpr int64_t kStaticStatusWords = 4096;
+__device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+constexpr int kMaxStaticDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxStaticDevices] = {};  // device address of `scratch`, per device
+
+// Look up and initialise the scratch of the current device (once per device;
+// called by cs_create with `device` current).  The control block starts at
+// epoch 1 and the status words at zero; afterwards every step leaves them
+// valid for the next one (their values carry the epoch of the step that wrote
+// them), so no call has to clear anything.
+cs_status setup_static_scratch(int device, std::string* err) {
+    if (device < 0 || device >= kMaxStaticDevices) {
+        *err = "cs_create: device index beyond the static scratch table";
+        return CS_ERR_UNSUPPORTED;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_dev[device]) return CS_OK;
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+        *err = std::string("cs_create: hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+        return CS_ERR_HIP;
+    }
+    const size_t fixed = cs::ws_fixed_bytes(kStaticStatusWords);
+    e = hipMemset(ptr, 0, fixed);
+    cs::StepControl init = {};
+    init.epoch = 1;
+    if (e == hipSuccess) e = hipMemcpy(ptr, &init, sizeof(init), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        *err = std::string("cs_create: static scratch initialisation: ") + hipGetErrorString(e);
+        return CS_ERR_HIP;
+    }
+    g_scratch_dev[device] = ptr;
+    return CS_OK;
+}
+
+void* static_scratch(int device) {
+    if (device < 0 || device >= kMaxStaticDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return g_scratch_dev[device];
+}
+
 }  // namespace
 
 extern "C" {
@@ -106,6 +159,15 @@ cs_status cs_create(cs_ctx** out, int device) {
     if (device < 0 || device >= n) {
         g_create_error = "cs_create: device index out of range";
         return CS_ERR_INVALID_ARG;
+    }
+    {
+        DeviceGuard g(device);
+        if (!g.ok) {
+            g_create_error = "cs_create: cannot select device";
+            return CS_ERR_HIP;
+        }
+        const cs_status ss = setup_static_scratch(device, &g_create_error);
+        if (ss != CS_OK) return ss;
     }
     cs_ctx* c = new (std::nothrow) cs_ctx();
     if (!c) {
@@ -317,6 +379,40 @@ cs_status cs_compton_step(cs_ctx* ctx, cs_dtype dtype, cs_species electrons, cs_
     const hipError_t e = launch_plan(pl, ctx->ws, p, st);
     if (e != hipSuccess) return hip_fail(ctx, e, "cs_compton_step: launch");
     if (ctx->timing) ctx->timed_steps += 1;
+    ctx->last_error.clear();
+    return CS_OK;
+}
+
+cs_status cs_compton_step_noalloc(cs_ctx* ctx, cs_dtype dtype, cs_species electrons, cs_species photons,
+                                  const int64_t* off_e, const int64_t* off_g, int64_t n_cells, double dt,
+                                  double density_norm, uint64_t seed, uint64_t step, cs_sampler sampler,
+                                  const cs_mlp* mlp, cs_stats* stats, void* stream) {
+    if (!ctx) return CS_ERR_INVALID_ARG;
+    cs_status s = validate_step(ctx, dtype, electrons, photons, off_e, off_g, n_cells, dt, density_norm, sampler, mlp,
+                                CS_STRATEGY_FUSED, "cs_compton_step_noalloc");
+    if (s != CS_OK) return s;
+    void* base = static_scratch(ctx->device);
+    if (!base) return fail(ctx, CS_ERR_NOT_READY, "cs_compton_step_noalloc: no static scratch on this device");
+    const Plan pl = plan_step(CS_STRATEGY_FUSED, 0, 0, n_cells, electrons.n, photons.n, sampler, dtype);
+    const size_t fixed = cs::ws_fixed_bytes(kStaticStatusWords);
+    if (pl.status_words > kStaticStatusWords || pl.bytes > kStaticScratchBytes - fixed) {
+        char msg[256];
+        std::snprintf(msg, sizeof msg,
+                      "cs_compton_step_noalloc: the step needs %zu bytes of scratch, more than the %zu the static "
+                      "buffer holds (about 24 bytes per cell and 4 per 256 pairs)",
+                      pl.bytes + fixed, kStaticScratchBytes);
+        return fail(ctx, CS_ERR_UNSUPPORTED, msg);
+    }
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(ctx, CS_ERR_HIP, "cs_compton_step_noalloc: cannot select device");
+    cs::Workspace w;
+    w.base = base;
+    w.bytes = kStaticScratchBytes;
+    w.status_cap = kStaticStatusWords;
+    const cs::StepParams p = make_params(dtype, electrons, photons, off_e, off_g, dt, density_norm, seed, step, sampler,
+                                         mlp, stats, 0);
+    const hipError_t e = launch_plan(pl, w, p, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "cs_compton_step_noalloc: launch");
     ctx->last_error.clear();
     return CS_OK;
 }
