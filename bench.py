@@ -363,7 +363,7 @@ def sampler_stage(ctx, p, net, sampler, n=1 << 22):
 
     from paper_2206_02937_amd import sampler_quality as sq
 
-    x, u = sq.plasma_inputs(p, n, seed=0)
+    x, u = sq.plasma_inputs(ctx, p, n, seed=0)
     xd = torch.from_numpy(x.astype(np.float32)).cuda()
     ud = torch.from_numpy(u.astype(np.float32)).cuda()
     mu = torch.empty_like(xd)

@@ -245,6 +245,15 @@ CS_API cs_status cs_ntc_step(cs_ctx* ctx, cs_dtype dtype, cs_species electrons, 
 CS_API cs_status cs_bin_particles(cs_ctx* ctx, cs_dtype dtype, const int32_t* cell, cs_species in, cs_species out,
                           int64_t* off, int64_t n_cells, int64_t* n_invalid, void* stream);
 
+/* Rest-frame photon energy x = gamma eps - p . k (in m_e c^2; the invariant
+ * P.K of Sec. 3.2's boost to the lepton frame) of the n pairs (electron i,
+ * photon i), i < n <= min(electrons.n, photons.n), evaluated in FP64 by the
+ * step's own cancellation-free form; x_out: n doubles (device).  Weights are
+ * not read.  For sampler inputs shaped like a plasma's pairs.
+ * CS_ERR_INVALID_ARG on NULL arrays, a bad dtype or n out of range. */
+CS_API cs_status cs_pair_x(cs_ctx* ctx, cs_dtype dtype, cs_species electrons, cs_species photons, int64_t n,
+                    double* x_out, void* stream);
+
 /*
  * cs_sample_plain -- the conventional sampler on its own: for each i,
  * mu[i] = F^-1(u[i]; x[i]) with F the CDF of the rest-frame scattering cosine
@@ -319,7 +328,7 @@ CS_API cs_status cs_pnet_adam(cs_ctx* ctx, float* params, const float* grad, flo
  * The network owns its device memory: FP32 master weights, Adam moments and
  * step count, and the BF16 / FP8 copies prepared by cs_mlp_quantize.
  */
-#define CS_MLP_X_MIN 1e-4
+#define CS_MLP_X_MIN 1e-4 /* default x range of a network (cs_mlp_set_domain) */
 #define CS_MLP_X_MAX 1e2
 
 CS_API cs_status cs_mlp_create(cs_ctx* ctx, const int32_t* widths, int32_t n_widths, const float* init_params_host,
@@ -330,9 +339,20 @@ CS_API int64_t cs_mlp_num_params(const cs_mlp* mlp); /* -1 for NULL */
  * invalidates the BF16 / FP8 copies and keeps the Adam state. */
 CS_API cs_status cs_mlp_set_params(cs_mlp* mlp, const float* host, int64_t n);
 CS_API cs_status cs_mlp_get_params(const cs_mlp* mlp, float* host, int64_t n);
+/* The x range [x_min, x_max] the network answers for (synchronous).  Its
+ * first input feature is log10 x mapped linearly from [log10 x_min,
+ * log10 x_max] onto [-1, 1]; samples with x outside the range (compared in
+ * FP32) are answered by the plain sampler and counted as fallbacks.  Default
+ * [CS_MLP_X_MIN, CS_MLP_X_MAX]; a network is trained for one range, so set it
+ * before training.  Setting it invalidates the FP8 copy (its input scales
+ * depend on the features).  CS_ERR_INVALID_ARG unless 0 < x_min < x_max,
+ * both finite. */
+CS_API cs_status cs_mlp_set_domain(cs_mlp* mlp, double x_min, double x_max);
+CS_API cs_status cs_mlp_get_domain(const cs_mlp* mlp, double* x_min, double* x_max);
 /* Save / load (synchronous): a versioned binary file with the widths, the
- * FP32 parameters, the Adam moments and step count, and a checksum.
- * CS_ERR_IO on a missing, truncated or corrupt file. */
+ * FP32 parameters, the Adam moments and step count, the x range, and a
+ * checksum (files of the first version, without the x range, load with the
+ * default range).  CS_ERR_IO on a missing, truncated or corrupt file. */
 CS_API cs_status cs_mlp_save(const cs_mlp* mlp, const char* path);
 CS_API cs_status cs_mlp_load(cs_ctx* ctx, const char* path, cs_mlp** out);
 
@@ -351,8 +371,8 @@ CS_API cs_status cs_mlp_forward(cs_ctx* ctx, const cs_mlp* mlp, cs_sampler preci
                          int64_t n, float* y_out, void* stream);
 
 /* Sampler: mu_out[i] = clamp(mu_hat, -1, 1), ratio_out[i] = 1/(1 + x(1 - mu));
- * where x is outside [CS_MLP_X_MIN, CS_MLP_X_MAX] the plain sampler answers
- * and fallback_mask[i] = 1 (nullable mask, else 0). */
+ * where x is outside the network's x range (cs_mlp_set_domain) the plain
+ * sampler answers and fallback_mask[i] = 1 (nullable mask, else 0). */
 CS_API cs_status cs_mlp_sample(cs_ctx* ctx, const cs_mlp* mlp, cs_sampler precision, const float* x, const float* u,
                         int64_t n, float* mu_out, float* ratio_out, uint8_t* fallback_mask, void* stream);
 

@@ -11,7 +11,11 @@ boundary): for each layer l with fan-in n_in and fan-out n_out, the weight
 matrix W_l[n_out, n_in] row-major, then the bias b_l[n_out].
 
 Features (a reading: the paper gives none for this network):
-    f1 = (log10 x + 1) / 3      maps x in [1e-4, 1e2] onto [-1, 1]
+    f1 = (log10 x - c) / h      maps log10 x linearly from the network's x
+                                range [x_min, x_max] onto [-1, 1]:
+                                c, h = midpoint and half-width of
+                                [log10 x_min, log10 x_max]; the default range
+                                [1e-4, 1e2] gives f1 = (log10 x + 1) / 3
     f2 = 2 u - 1
 Hidden layers: SiLU z * sigmoid(z); output layer linear.
 Loss: MSE = 1/(2n) sum (y - t)^2 over the n samples and both outputs, or
@@ -49,10 +53,12 @@ def pack(layers):
     return np.concatenate([np.concatenate([W.ravel(), b.ravel()]) for W, b in layers])
 
 
-def features(x, u):
+def features(x, u, domain=(X_MIN, X_MAX)):
     x = np.asarray(x, dtype=np.float64)
     u = np.asarray(u, dtype=np.float64)
-    return np.stack([(np.log10(x) + 1.0) / 3.0, 2.0 * u - 1.0], axis=1)
+    lo, hi = np.log10(domain[0]), np.log10(domain[1])
+    c, h = 0.5 * (lo + hi), 0.5 * (hi - lo)
+    return np.stack([(np.log10(x) - c) / h, 2.0 * u - 1.0], axis=1)
 
 
 def sigmoid(z):
@@ -68,11 +74,11 @@ def silu_grad(z):
     return s * (1.0 + z * (1.0 - s))
 
 
-def forward(params, x, u, widths=WIDTHS, keep=False):
+def forward(params, x, u, widths=WIDTHS, keep=False, domain=(X_MIN, X_MAX)):
     """Network outputs y[n, 2] (raw: mu_hat, r_hat).  With keep=True also the
     per-layer inputs and pre-activations needed by the backward pass."""
     layers = unpack(params, widths)
-    h = features(x, u)
+    h = features(x, u, domain)
     hs, zs = [h], []
     for li, (W, b) in enumerate(layers):
         z = h @ W.T + b
@@ -94,9 +100,9 @@ def loss(y, t, kind="mse"):
     raise ValueError(kind)
 
 
-def grad(params, x, u, t, kind="mse", widths=WIDTHS):
+def grad(params, x, u, t, kind="mse", widths=WIDTHS, domain=(X_MIN, X_MAX)):
     """Loss and its gradient with respect to the flat parameter vector."""
-    y, hs, zs = forward(params, x, u, widths, keep=True)
+    y, hs, zs = forward(params, x, u, widths, keep=True, domain=domain)
     n = y.shape[0]
     d = y - t
     if kind == "mse":
@@ -148,12 +154,31 @@ def glorot_uniform(rng, widths=WIDTHS):
     return pack(layers)
 
 
+def reading_v(y, x):
+    """The sampler's reading of the two outputs (cos theta, eps'/eps) as
+    v = 1 - cos theta (a reading: both outputs are trained, the configuration
+    lists both).  With the same absolute error e in either output, cos theta
+    fixes v to e, while eps'/eps = r = 1 / (1 + x v) fixes it to
+    e (1 + x v)^2 / x; so v comes from the ratio (clamped to its range
+    [1 / (1 + 2x), 1]) where that is smaller -- x > 1 and
+    v_r < (sqrt(x) - 1) / x -- and from the cosine (clamped to [-1, 1])
+    elsewhere.  x: the network's FP32 input, as float64."""
+    y = np.asarray(y, dtype=np.float64)
+    x = np.asarray(x, dtype=np.float64)
+    v_mu = 1.0 - np.clip(y[:, 0], -1.0, 1.0)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        r = np.clip(y[:, 1], 1.0 / (1.0 + 2.0 * x), 1.0)
+        v_r = (1.0 / r - 1.0) / x
+        use_r = (x > 1.0) & (v_r < (np.sqrt(x) - 1.0) / x)
+    return np.where(use_r, v_r, v_mu)
+
+
 def sample_from_outputs(y, x):
-    """Sampler reading of the network output: mu = clamp(mu_hat, -1, 1) and
-    the energy ratio recomputed from mu so that the Compton relation holds."""
-    mu = np.clip(y[:, 0], -1.0, 1.0)
-    r = 1.0 / (1.0 + np.asarray(x, dtype=np.float64) * (1.0 - mu))
-    return mu, r
+    """Sampler reading of the network output: v from reading_v, mu = 1 - v,
+    and the energy ratio recomputed from v so that the Compton relation
+    holds."""
+    v = reading_v(y, x)
+    return 1.0 - v, 1.0 / (1.0 + np.asarray(x, dtype=np.float64) * v)
 
 
 # ----------------------------------------------------------------------------
@@ -206,7 +231,7 @@ def round_e4m3(a):
     return np.copysign(q, a)
 
 
-def forward_quantized(params, x, u, fmt, act_scales=None, widths=WIDTHS):
+def forward_quantized(params, x, u, fmt, act_scales=None, widths=WIDTHS, domain=(X_MIN, X_MAX)):
     """Forward pass with the hidden-layer contractions in reduced precision:
     'bf16' rounds the weights and the layer inputs to bfloat16; 'e4m3' divides
     them by per-layer scales (weights: amax/448; inputs: the given calibrated
@@ -214,7 +239,7 @@ def forward_quantized(params, x, u, fmt, act_scales=None, widths=WIDTHS):
     activation in float64.  The first (2 -> 64) and last (64 -> 2) layers stay
     in full precision, as in the GPU kernel."""
     layers = unpack(params, widths)
-    h = features(x, u)
+    h = features(x, u, domain)
     nl = len(layers)
     for li, (W, b) in enumerate(layers):
         if 0 < li < nl - 1:

@@ -79,6 +79,8 @@ def lib():
     L.cs_ntc_step.restype = st
     L.cs_check_layout.argtypes = [vp, vp, i64, i64, vp]
     L.cs_check_layout.restype = st
+    L.cs_pair_x.argtypes = [vp, C.c_int, Species, Species, i64, vp, vp]
+    L.cs_pair_x.restype = st
     L.cs_sample_plain.argtypes = [vp, C.c_int, vp, vp, i64, vp, vp, vp]
     L.cs_sample_plain.restype = st
     L.cs_bin_particles.argtypes = [vp, C.c_int, vp, Species, Species, vp, i64, vp, vp]
@@ -126,6 +128,8 @@ def _bind_mlp(L):
         "cs_mlp_num_params": ([vp], i64),
         "cs_mlp_set_params": ([vp, vp, i64], st),
         "cs_mlp_get_params": ([vp, vp, i64], st),
+        "cs_mlp_set_domain": ([vp, C.c_double, C.c_double], st),
+        "cs_mlp_get_domain": ([vp, C.POINTER(C.c_double), C.POINTER(C.c_double)], st),
         "cs_mlp_save": ([vp, C.c_char_p], st),
         "cs_mlp_load": ([vp, C.c_char_p, C.POINTER(vp)], st),
         "cs_mlp_quantize": ([vp, vp, C.c_int, vp, vp, i64, vp], st),
@@ -350,6 +354,18 @@ class Context:
         self._check(lib().cs_pnet_adam(self._h, _ptr(params), _ptr(grad), _ptr(m), _ptr(v), t, lr,
                                        _stream(stream)))
 
+    def pair_x(self, e, g, n=None, x_out=None, stream=None):
+        """Rest-frame photon energies (float64 device tensor) of the pairs
+        (electron i, photon i), i < n (default: the smaller species count)."""
+        import torch
+
+        n = min(e["x"].numel(), g["x"].numel()) if n is None else int(n)
+        x_out = torch.empty(n, dtype=torch.float64, device=e["x"].device) if x_out is None else x_out
+        rc = lib().cs_pair_x(self._h, _dtype_code(e["x"]), _species(e), _species(g), n, _ptr(x_out),
+                             _stream(stream))
+        self._check(rc)
+        return x_out
+
     def sample_plain(self, x, u, mu_out=None, ratio_out=None, stream=None):
         import torch
 
@@ -399,7 +415,7 @@ class Graph:
 
 
 WIDTHS = (2, 64, 64, 64, 64, 2)
-X_MIN, X_MAX = 1e-4, 1e2
+X_MIN, X_MAX = 1e-4, 1e2  # the default x range of a network
 
 
 class MLP:
@@ -458,6 +474,18 @@ class MLP:
     def set_params(self, params):
         host = np.ascontiguousarray(params, dtype=np.float32)
         self._rc(lib().cs_mlp_set_params(self._h, host.ctypes.data_as(C.c_void_p), host.size), "cs_mlp_set_params")
+
+    def set_domain(self, x_min, x_max):
+        """The x range the network answers for (its first feature maps log10 x
+        from this range onto [-1, 1]; outside it the plain sampler answers)."""
+        rc = lib().cs_mlp_set_domain(self._h, float(x_min), float(x_max))
+        self._rc(rc, f"cs_mlp_set_domain({x_min}, {x_max})")
+
+    @property
+    def domain(self):
+        lo, hi = C.c_double(), C.c_double()
+        self._rc(lib().cs_mlp_get_domain(self._h, C.byref(lo), C.byref(hi)), "cs_mlp_get_domain")
+        return lo.value, hi.value
 
     def save(self, path):
         self._rc(lib().cs_mlp_save(self._h, os.fsencode(path)), f"cs_mlp_save({path})")

@@ -344,7 +344,7 @@ cs::StepParams make_params(cs_dtype dtype, cs_species electrons, cs_species phot
     p.seed = seed;
     p.step = step;
     p.sampler = sampler;
-    p.net = mlp ? mlp->dev() : cs::MlpDev{nullptr, nullptr, nullptr, nullptr};
+    p.net = mlp ? mlp->dev() : cs::MlpDev{nullptr, nullptr, nullptr, nullptr, {}};
     p.stats = stats;
     p.events = nullptr;
     p.use_device_step = 0;
@@ -751,6 +751,19 @@ cs_status cs_check_layout(cs_ctx* ctx, const int64_t* off, int64_t n_cells, int6
     return CS_OK;
 }
 
+cs_status cs_pair_x(cs_ctx* ctx, cs_dtype dtype, cs_species electrons, cs_species photons, int64_t n, double* x_out,
+                    void* stream) {
+    if (!ctx) return CS_ERR_INVALID_ARG;
+    if ((dtype != CS_F32 && dtype != CS_F64) || n < 0 || n > electrons.n || n > photons.n ||
+        (n > 0 && (!electrons.x || !electrons.y || !electrons.z || !photons.x || !photons.y || !photons.z || !x_out)))
+        return fail(ctx, CS_ERR_INVALID_ARG, "cs_pair_x: bad arguments");
+    DeviceGuard g(ctx->device);
+    hipError_t e = cs::launch_pair_x(dtype, electrons, photons, n, x_out, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "cs_pair_x: launch");
+    ctx->last_error.clear();
+    return CS_OK;
+}
+
 cs_status cs_sample_plain(cs_ctx* ctx, cs_dtype dtype, const void* x, const void* u, int64_t n, void* mu_out,
                           void* ratio_out, void* stream) {
     if (!ctx) return CS_ERR_INVALID_ARG;
@@ -963,7 +976,13 @@ extern "C++" {
 namespace {
 
 const int32_t kWidths[6] = {2, 64, 64, 64, 64, 2};
-const char kMagic[8] = {'C', 'S', 'M', 'L', 'P', '0', '0', '1'};
+// file versions: 001 (default x range), 002 (x range stored after the Adam step)
+const char kMagic1[8] = {'C', 'S', 'M', 'L', 'P', '0', '0', '1'};
+const char kMagic2[8] = {'C', 'S', 'M', 'L', 'P', '0', '0', '2'};
+
+bool domain_ok(double x_min, double x_max) {
+    return std::isfinite(x_min) && std::isfinite(x_max) && x_min > 0.0 && x_max > x_min;
+}
 
 uint64_t fnv1a(const void* data, size_t n, uint64_t h) {
     const unsigned char* p = (const unsigned char*)data;
@@ -1095,6 +1114,23 @@ cs_status cs_mlp_get_params(const cs_mlp* mlp, float* host, int64_t n) {
     return CS_OK;
 }
 
+cs_status cs_mlp_set_domain(cs_mlp* mlp, double x_min, double x_max) {
+    if (!mlp || !domain_ok(x_min, x_max)) return CS_ERR_INVALID_ARG;
+    DeviceGuard g(mlp->device);
+    if (hipDeviceSynchronize() != hipSuccess) return CS_ERR_HIP;  // queued work keeps the old range
+    mlp->x_min = x_min;
+    mlp->x_max = x_max;
+    mlp->fp8_ready = false;  // the FP8 input scales were calibrated on the old features
+    return CS_OK;
+}
+
+cs_status cs_mlp_get_domain(const cs_mlp* mlp, double* x_min, double* x_max) {
+    if (!mlp || !x_min || !x_max) return CS_ERR_INVALID_ARG;
+    *x_min = mlp->x_min;
+    *x_max = mlp->x_max;
+    return CS_OK;
+}
+
 cs_status cs_mlp_save(const cs_mlp* mlp, const char* path) {
     if (!mlp || !path) return CS_ERR_INVALID_ARG;
     DeviceGuard g(mlp->device);
@@ -1108,11 +1144,13 @@ cs_status cs_mlp_save(const cs_mlp* mlp, const char* path) {
         return CS_ERR_HIP;
     const int32_t nw = 6;
     const int64_t np = (int64_t)n, t = mlp->adam_t;
-    buf.append(kMagic, 8);
+    buf.append(kMagic2, 8);
     buf.append((const char*)&nw, 4);
     buf.append((const char*)kWidths, 24);
     buf.append((const char*)&np, 8);
     buf.append((const char*)&t, 8);
+    buf.append((const char*)&mlp->x_min, 8);
+    buf.append((const char*)&mlp->x_max, 8);
     buf.append((const char*)p.data(), 4 * n);
     buf.append((const char*)m.data(), 4 * n);
     buf.append((const char*)v.data(), 4 * n);
@@ -1137,9 +1175,12 @@ cs_status cs_mlp_load(cs_ctx* ctx, const char* path, cs_mlp** out) {
     while ((r = fread(tmp, 1, sizeof(tmp), f)) > 0) buf.append(tmp, r);
     fclose(f);
     const size_t n = cs::kMlpParams;
-    const size_t need = 8 + 4 + 24 + 8 + 8 + 3 * 4 * n + 8;
+    if (buf.size() < 8) return fail(ctx, CS_ERR_IO, "cs_mlp_load: wrong file size");
+    const bool v2 = memcmp(buf.data(), kMagic2, 8) == 0;
+    if (!v2 && memcmp(buf.data(), kMagic1, 8) != 0) return fail(ctx, CS_ERR_IO, "cs_mlp_load: bad magic");
+    const size_t head = 8 + 4 + 24 + 8 + 8 + (v2 ? 16 : 0);
+    const size_t need = head + 3 * 4 * n + 8;
     if (buf.size() != need) return fail(ctx, CS_ERR_IO, "cs_mlp_load: wrong file size");
-    if (memcmp(buf.data(), kMagic, 8) != 0) return fail(ctx, CS_ERR_IO, "cs_mlp_load: bad magic");
     uint64_t h;
     memcpy(&h, buf.data() + need - 8, 8);
     if (fnv1a(buf.data(), need - 8, 1469598103934665603ull) != h) return fail(ctx, CS_ERR_IO, "cs_mlp_load: checksum");
@@ -1151,11 +1192,19 @@ cs_status cs_mlp_load(cs_ctx* ctx, const char* path, cs_mlp** out) {
     memcpy(&np, buf.data() + 36, 8);
     memcpy(&t, buf.data() + 44, 8);
     if (!widths_ok(w, nw) || np != (int64_t)n) return fail(ctx, CS_ERR_IO, "cs_mlp_load: unsupported widths");
+    double x_min = CS_MLP_X_MIN, x_max = CS_MLP_X_MAX;
+    if (v2) {
+        memcpy(&x_min, buf.data() + 52, 8);
+        memcpy(&x_max, buf.data() + 60, 8);
+        if (!domain_ok(x_min, x_max)) return fail(ctx, CS_ERR_IO, "cs_mlp_load: bad x range");
+    }
     DeviceGuard g(ctx->device);
     cs_mlp* m = nullptr;
     cs_status s = mlp_alloc(ctx, &m);
     if (s != CS_OK) return s;
-    const char* base = buf.data() + 52;
+    m->x_min = x_min;
+    m->x_max = x_max;
+    const char* base = buf.data() + head;
     hipError_t e = hipMemcpy(m->params, base, 4 * n, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(m->adam_m, base + 4 * n, 4 * n, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(m->adam_v, base + 8 * n, 4 * n, hipMemcpyHostToDevice);
@@ -1179,7 +1228,8 @@ cs_status cs_mlp_quantize(cs_ctx* ctx, cs_mlp* mlp, cs_sampler precision, const 
     if (precision == CS_SAMPLER_MLP_FP8 && (!calib_x || !calib_u || n <= 0))
         return fail(ctx, CS_ERR_INVALID_ARG, "cs_mlp_quantize: FP8 needs calibration samples");
     DeviceGuard g(mlp->device);
-    hipError_t e = cs::launch_mlp_quantize(mlp->params, mlp->frag_bf16, mlp->frag_fp8, mlp->fp8_scales, precision,
+    hipError_t e = cs::launch_mlp_quantize(mlp->params, mlp->dev().dom, mlp->frag_bf16, mlp->frag_fp8, mlp->fp8_scales,
+                                           precision,
                                            calib_x, calib_u, n, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "cs_mlp_quantize: launch");
     if (precision == CS_SAMPLER_MLP_BF16)

@@ -224,7 +224,7 @@ __global__ __launch_bounds__(kChunk) void k_step(const FusedArgs<T> a) {
             // accepted pairs are staged in LDS: from the bottom of the queue,
             // or (network samplers, x outside the network's domain) from the top
             bool to_fb = false;
-            if constexpr (SAMP != CS_SAMPLER_PLAIN) to_fb = o.accept && !in_range((float)o.x);
+            if constexpr (SAMP != CS_SAMPLER_PLAIN) to_fb = o.accept && !in_range((float)o.x, a.mlp.dom);
             const bool to_main = o.accept && !to_fb;
             const uint64_t lt = (1ull << lane) - 1ull;
             const uint64_t mask = __ballot(to_main), mask_fb = __ballot(to_fb);

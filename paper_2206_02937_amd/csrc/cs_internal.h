@@ -132,11 +132,22 @@ int64_t fused_prep_blocks(int64_t n_cells);
 size_t step_workspace_bytes(const StepShape& s);
 void carve_step_buffers(void* base, const StepShape& s, StepBuffers* b);
 
+// The x range a network answers for, as the kernels use it: its first
+// feature is f1 = f_a log2(x) + f_b (log10 x mapped linearly from
+// [log10 x_min, log10 x_max] onto [-1, 1]); x outside [x_lo, x_hi] (the
+// bounds rounded to FP32) goes to the plain sampler.
+struct NetDomain {
+    float f_a, f_b;
+    float x_lo, x_hi;
+};
+NetDomain net_domain(double x_min, double x_max);
+
 struct MlpDev {
     const float* params;        // FP32 master
     const void* frag_bf16;      // kFragCount x 8 bf16
     const void* frag_fp8;       // kFragCount x 8 fp8 (E4M3)
     const float* fp8_scales;    // [0..2] weight scales, [3..5] input scales, [6..8] input amax
+    NetDomain dom;
 };
 
 struct StepParams {
@@ -183,6 +194,8 @@ hipError_t launch_prep(const StepShape& sh, StepControl* ctrl, uint64_t* status,
 hipError_t launch_fused(const StepShape& shape, const FusedBuffers& buf, const StepParams& p, hipStream_t stream);
 // one workgroup per cell (baseline); shape.n_step_blocks = n_cells partials
 hipError_t launch_cell(const StepShape& shape, const FusedBuffers& buf, const StepParams& p, hipStream_t stream);
+hipError_t launch_pair_x(cs_dtype dtype, const cs_species& e, const cs_species& g, int64_t n, double* x_out,
+                         hipStream_t st);
 hipError_t launch_check_layout(const int64_t* off, int64_t n_cells, int64_t n, int32_t* flag, hipStream_t stream);
 hipError_t launch_sample_plain(cs_dtype dtype, const void* x, const void* u, int64_t n, void* mu, void* ratio,
                                hipStream_t stream);
@@ -236,8 +249,8 @@ hipError_t launch_mlp_grad(const MlpDev& m, const float* x, const float* u, cons
                            int64_t n, int loss, float* partials, float* loss_partials, float* grad_out,
                            float* loss_out, float* adam_m, float* adam_v, float* params_rw, float lr, int64_t t,
                            hipStream_t st);
-hipError_t launch_mlp_quantize(float* params, void* frag_bf16, void* frag_fp8, float* scales, cs_sampler prec,
-                               const float* cx, const float* cu, int64_t n, hipStream_t st);
+hipError_t launch_mlp_quantize(float* params, const NetDomain& dom, void* frag_bf16, void* frag_fp8, float* scales,
+                               cs_sampler prec, const float* cx, const float* cu, int64_t n, hipStream_t st);
 int64_t mlp_grad_blocks(int64_t n);
 
 }  // namespace cs
@@ -255,7 +268,8 @@ struct cs_mlp {
     bool bf16_ready = false, fp8_ready = false;
     float* work = nullptr;  // gradient partials, loss partials, gradient
     size_t work_bytes = 0;
-    cs::MlpDev dev() const { return {params, frag_bf16, frag_fp8, fp8_scales}; }
+    double x_min = CS_MLP_X_MIN, x_max = CS_MLP_X_MAX;  // the x range the network answers for
+    cs::MlpDev dev() const { return {params, frag_bf16, frag_fp8, fp8_scales, cs::net_domain(x_min, x_max)}; }
 };
 
 struct cs_ctx {

@@ -119,6 +119,7 @@ __device__ __forceinline__ void fwd_block_f32(const float* P, float f1, float f2
 
 struct FwdArgs {
     const float* P;
+    NetDomain dom;
     const float *x, *u;
     int64_t n;
     float* y;      // nullable, 2n
@@ -129,13 +130,14 @@ struct FwdArgs {
 };
 
 
-// Sampler reading of the outputs (shared by every precision): inside the
-// network's domain cos(theta) = clamp(y0, -1, 1) and the energy ratio follows
-// from it by the Compton relation; outside it the plain sampler answers.
-__device__ __forceinline__ void net_out(const FwdArgs& a, int64_t i, float x, float y0) {
-    const float mu = fminf(fmaxf(y0, -1.0f), 1.0f);
-    if (a.mu) a.mu[i] = mu;
-    if (a.ratio) a.ratio[i] = 1.0f / (1.0f + x * (1.0f - mu));
+// Sampler reading of the outputs (shared by every precision and by the step):
+// inside the network's x range v = 1 - cos(theta) from net_reading_v, and the
+// energy ratio follows from it by the Compton relation (both evaluated in
+// FP64, stored as FP32); outside it the plain sampler answers.
+__device__ __forceinline__ void net_out(const FwdArgs& a, int64_t i, float x, float y0, float y1) {
+    const double v = net_reading_v(x, y0, y1);
+    if (a.mu) a.mu[i] = (float)(1.0 - v);
+    if (a.ratio) a.ratio[i] = (float)(1.0 / (1.0 + (double)x * v));
     if (a.mask) a.mask[i] = 0;
 }
 __device__ __forceinline__ void fallback_out(const FwdArgs& a, int64_t i, float x, float u) {
@@ -144,9 +146,9 @@ __device__ __forceinline__ void fallback_out(const FwdArgs& a, int64_t i, float 
     if (a.ratio) a.ratio[i] = (float)(1.0 / (1.0 + (double)x * v));
     if (a.mask) a.mask[i] = 1;
 }
-__device__ __forceinline__ void sampler_out(const FwdArgs& a, int64_t i, float x, float u, float y0) {
-    if (in_range(x))
-        net_out(a, i, x, y0);
+__device__ __forceinline__ void sampler_out(const FwdArgs& a, int64_t i, float x, float u, float y0, float y1) {
+    if (in_range(x, a.dom))
+        net_out(a, i, x, y0, y1);
     else
         fallback_out(a, i, x, u);
 }
@@ -158,7 +160,7 @@ __global__ __launch_bounds__(kMlpThreads) void k_mlp_fwd_f32(const FwdArgs a) {
     const bool active = i < a.n;
     const float x = active ? a.x[i] : 1.0f, u = active ? a.u[i] : 0.5f;
     float f1, f2;
-    features(x, u, f1, f2);
+    features(x, u, a.dom, f1, f2);
     fwd_block_f32(a.P, f1, f2, active, H, a.amax);
     if (threadIdx.x < 64 && active) {
         float y0, y1;
@@ -167,7 +169,7 @@ __global__ __launch_bounds__(kMlpThreads) void k_mlp_fwd_f32(const FwdArgs a) {
             a.y[2 * i] = y0;
             a.y[2 * i + 1] = y1;
         }
-        if (a.mu || a.ratio || a.mask) sampler_out(a, i, x, u, y0);
+        if (a.mu || a.ratio || a.mask) sampler_out(a, i, x, u, y0, y1);
     }
 }
 
@@ -176,6 +178,7 @@ __global__ __launch_bounds__(kMlpThreads) void k_mlp_fwd_f32(const FwdArgs a) {
 // ---------------------------------------------------------------------------
 struct GradArgs {
     const float* P;
+    NetDomain dom;
     const float *x, *u, *mu_t, *r_t;
     int64_t n;
     int loss;         // 0 MSE, 1 MAE
@@ -183,184 +186,259 @@ struct GradArgs {
     float* loss_partials;  // [blocks]
 };
 
-// A workgroup walks the 64-sample tiles blockIdx.x, blockIdx.x + gridDim.x,
-// ...; each element of its partial gradient is always produced by the same
-// lane, which adds the tiles in that order (no atomics, reproducible).
+// Training on FP32 MFMA (v_mfma_f32_16x16x4_f32: lane l supplies A[l%16][l/16]
+// and B[l/16][l%16]; lane l receives D[4(l/16) + r][l%16], r = 0..3).
+//
+// A workgroup takes tiles of 16 samples (a batch of 4096 spreads over 256
+// workgroups, one per compute unit) and walks the tiles blockIdx.x,
+// blockIdx.x + gridDim.x, ...  Wave w owns neurons 16w .. 16w + 15 of every
+// layer: in the forward pass Z[16w.., :] = W[16w.., :] H (16 MFMAs over
+// K = 64), in the backward pass the delta rows (W^T delta)[16w.., :] * SiLU'
+// -- the lane that produced z keeps SiLU'(z) in registers for that --, and
+// the weight gradients dW[16w.., :] = delta[16w.., :] H^T (four 16x16 tiles,
+// K = 16 samples), which stay in MFMA accumulators over the workgroup's tiles
+// and are written once.  The weight operands are staged in LDS once per
+// workgroup in fragment order (conflict-free); activations and deltas are
+// written to LDS in two layouts, [feature][sample] for the operands whose
+// K index is a feature and [sample][feature] (rows of kYRow) for those whose
+// K index is a sample, so that every operand read is conflict-free.  Each
+// gradient entry has one owner and a fixed summation order (no atomics;
+// bitwise reproducible); the reduction kernel adds the workgroups' partials
+// in a fixed order.
+constexpr int kTrainTile = 16;
+constexpr int kYRow = 80;  // [sample][feature] rows: 64 + 16 floats
+
+typedef float floatx4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ floatx4_t mfma_f32(float a, float b, floatx4_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
 __global__ __launch_bounds__(kMlpThreads) void k_mlp_grad_block(const GradArgs a) {
-    __shared__ float H[4][kMlpSamples][kRow];  // h1..h4
-    __shared__ float D[2][kMlpSamples][kRow];  // delta ping-pong
-    __shared__ float F[kMlpSamples][2];        // features
-    __shared__ float DY[kMlpSamples][2];       // output delta
-    __shared__ float s_loss[kMlpSamples];
+    // weight fragments: [layer][tile t][k-step][lane]; Wf: A = W[16t + l%16][4ks + l/16],
+    // Wt: A = W^T[16t + l%16][4ks + l/16] = W[4ks + l/16][16t + l%16]
+    __shared__ float Wf[3][4 * 16 * 64];
+    __shared__ float Wt[3][4 * 16 * 64];
+    __shared__ float HX[4][kMlpHidden * kTrainTile];      // h1..h4, [feature][sample]
+    __shared__ float HY[4][kTrainTile * kYRow];           // h1..h4, [sample][feature]
+    __shared__ float DX[kMlpHidden * kTrainTile];         // delta of the current layer, [feature][sample]
+    __shared__ float DY_[2][kTrainTile * kYRow];          // deltas, [sample][feature], ping-pong
+    __shared__ float F[kTrainTile][2];                    // features
+    __shared__ float dOut[kTrainTile][2];                 // output deltas
+    __shared__ float s_loss[2][kTrainTile];
     const int tid = threadIdx.x;
+    const int lane = tid & 63;
     const int w = wave_uniform(tid >> 6);
-    const int s = tid & 63;
-    const int64_t n_tiles = (a.n + kMlpSamples - 1) / kMlpSamples;
-    float* out = a.partials + (int64_t)blockIdx.x * kMlpParams;
-    // out[idx] = first tile ? v : out[idx] + v (always the same lane for idx)
-    auto put = [&](int64_t idx, float v, bool first) { out[idx] = first ? v : out[idx] + v; };
+    const int li = lane & 15, lg = lane >> 4;  // MFMA operand row / k index of this lane
+    const float* P = a.P;
+    {
+        // all of a layer's loads in flight at once (16 + 16 per thread)
+        const int offW[3] = {kOffW2, kOffW3, kOffW4};
+#pragma unroll 1
+        for (int L = 0; L < 3; ++L) {
+            float vf[16], vt[16];
+#pragma unroll
+            for (int it = 0; it < 16; ++it) {
+                const int i = tid + it * kMlpThreads;
+                const int l = i & 63, ks = (i >> 6) & 15, t = i >> 10;
+                const int r = 16 * t + (l & 15), c = 4 * ks + (l >> 4);
+                vf[it] = P[offW[L] + r * kMlpHidden + c];
+                vt[it] = P[offW[L] + c * kMlpHidden + r];
+            }
+#pragma unroll
+            for (int it = 0; it < 16; ++it) {
+                Wf[L][tid + it * kMlpThreads] = vf[it];
+                Wt[L][tid + it * kMlpThreads] = vt[it];
+            }
+        }
+    }
+    // this lane's neurons of every layer: n(r) = 16w + 4 lg + r, sample li
+    floatx4_t gW[3][4];  // dW_{2,3,4}[16w + 4lg + r][16tk + li], accumulated over the tiles
+#pragma unroll
+    for (int L = 0; L < 3; ++L)
+#pragma unroll
+        for (int tk = 0; tk < 4; ++tk) gW[L][tk] = {0.0f, 0.0f, 0.0f, 0.0f};
+    float gB[4] = {0.0f, 0.0f, 0.0f, 0.0f};  // w == 0: db_{1..4}[lane]
+    float gW1a = 0.0f, gW1b = 0.0f;          // w == 0: dW1[lane][0], dW1[lane][1]
+    float gW5 = 0.0f;                        // tid < 128: dW5[tid / 64][tid % 64]
+    float gB5 = 0.0f, g_loss = 0.0f;         // tid < 2: db5[tid]; tid == 2: the loss
+    const float inv_n = 1.0f / (float)a.n;
+    const int64_t n_tiles = (a.n + kTrainTile - 1) / kTrainTile;
     for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-        const bool first = tile == (int64_t)blockIdx.x;
-        __syncthreads();  // the previous tile's LDS reads are done
-        const int64_t i = tile * kMlpSamples + s;
-        const bool active = i < a.n;
-        const float* P = a.P;
-        float f1 = 0.0f, f2 = 0.0f;
-        if (active) features(a.x[i], a.u[i], f1, f2);
-        if (w == 0) {
-            F[s][0] = f1;
-            F[s][1] = f2;
-        }
-        // forward; SiLU'(z) of this lane's 16 neurons of every layer in registers
-        float g[4][16];
-        float z[16];
-        fwd_first(P, w, f1, f2, z);
-    #pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            H[0][s][16 * w + k] = silu_f32(z[k]);
-            g[0][k] = silu_grad_f32(z[k]);
+        __syncthreads();  // the previous tile's LDS reads are done (and the weights are staged)
+        if (tid < kTrainTile) {
+            const int64_t i = tile * kTrainTile + tid;
+            float f1 = 0.0f, f2 = 0.0f;
+            if (i < a.n) features(a.x[i], a.u[i], a.dom, f1, f2);
+            F[tid][0] = f1;
+            F[tid][1] = f2;
         }
         __syncthreads();
-        fwd_hidden(P + kOffW2, P + kOffB2, w, H[0][s], z);
-    #pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            H[1][s][16 * w + k] = silu_f32(z[k]);
-            g[1][k] = silu_grad_f32(z[k]);
+        float gp[4][4];  // SiLU'(z) of layers 1..4 at this lane's (neuron, sample)
+        // layer 1 (2 -> 64) on the vector ALUs, in the MFMA output layout
+        {
+            const float f1 = F[li][0], f2 = F[li][1];
+            float h[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int n = 16 * w + 4 * lg + r;
+                const float z = fmaf(P[kOffW1 + 2 * n + 1], f2, fmaf(P[kOffW1 + 2 * n], f1, P[kOffB1 + n]));
+                h[r] = silu_f32(z);
+                gp[0][r] = silu_grad_f32(z);
+                HX[0][n * kTrainTile + li] = h[r];
+            }
+            *(float4*)(&HY[0][li * kYRow + 16 * w + 4 * lg]) = make_float4(h[0], h[1], h[2], h[3]);
         }
         __syncthreads();
-        fwd_hidden(P + kOffW3, P + kOffB3, w, H[1][s], z);
-    #pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            H[2][s][16 * w + k] = silu_f32(z[k]);
-            g[2][k] = silu_grad_f32(z[k]);
+        // hidden layers 2..4: Z = W H + b on MFMA
+        const int offB[3] = {kOffB2, kOffB3, kOffB4};
+#pragma unroll
+        for (int L = 0; L < 3; ++L) {
+            floatx4_t acc;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[r] = P[offB[L] + 16 * w + 4 * lg + r];
+            const float* wf = &Wf[L][(w * 16) * 64 + lane];
+            const float* hx = &HX[L][lg * kTrainTile + li];
+#pragma unroll
+            for (int ks = 0; ks < 16; ++ks) acc = mfma_f32(wf[ks * 64], hx[4 * ks * kTrainTile], acc);
+            float h[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int n = 16 * w + 4 * lg + r;
+                h[r] = silu_f32(acc[r]);
+                gp[L + 1][r] = silu_grad_f32(acc[r]);
+                HX[L + 1][n * kTrainTile + li] = h[r];
+            }
+            *(float4*)(&HY[L + 1][li * kYRow + 16 * w + 4 * lg]) = make_float4(h[0], h[1], h[2], h[3]);
+            __syncthreads();
         }
-        __syncthreads();
-        fwd_hidden(P + kOffW4, P + kOffB4, w, H[2][s], z);
-    #pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            H[3][s][16 * w + k] = silu_f32(z[k]);
-            g[3][k] = silu_grad_f32(z[k]);
-        }
-        __syncthreads();
-        // output layer and loss gradient
-        if (w == 0) {
-            float y0, y1;
-            fwd_out(P, H[3][s], y0, y1);
-            float d0 = 0.0f, d1 = 0.0f, l = 0.0f;
-            if (active) {
-                const float e0 = y0 - a.mu_t[i], e1 = y1 - a.r_t[i];
-                const float inv_n = 1.0f / (float)a.n;
+        // output layer and loss gradient: one thread per (sample, output)
+        if (tid < 2 * kTrainTile) {
+            const int sm = tid >> 1, o = tid & 1;
+            const int64_t i = tile * kTrainTile + sm;
+            float y = P[kOffB5 + o];
+            for (int k = 0; k < kMlpHidden; ++k) y = fmaf(P[kOffW5 + o * kMlpHidden + k], HY[3][sm * kYRow + k], y);
+            float d = 0.0f, l = 0.0f;
+            if (i < a.n) {
+                const float e = y - (o == 0 ? a.mu_t[i] : a.r_t[i]);
                 if (a.loss == 0) {
-                    d0 = e0 * inv_n;
-                    d1 = e1 * inv_n;
-                    l = 0.5f * (e0 * e0 + e1 * e1) * inv_n;
+                    d = e * inv_n;
+                    l = 0.5f * e * e * inv_n;
                 } else {
-                    d0 = (e0 > 0.0f ? 0.5f : (e0 < 0.0f ? -0.5f : 0.0f)) * inv_n;
-                    d1 = (e1 > 0.0f ? 0.5f : (e1 < 0.0f ? -0.5f : 0.0f)) * inv_n;
-                    l = 0.5f * (fabsf(e0) + fabsf(e1)) * inv_n;
+                    d = (e > 0.0f ? 0.5f : (e < 0.0f ? -0.5f : 0.0f)) * inv_n;
+                    l = 0.5f * fabsf(e) * inv_n;
                 }
             }
-            DY[s][0] = d0;
-            DY[s][1] = d1;
-            s_loss[s] = l;
+            dOut[sm][o] = d;
+            s_loss[o][sm] = l;
         }
         __syncthreads();
-        // layer 5 gradients: dW5[o][k] = sum_s DY[s][o] h4[s][k], db5[o] = sum_s DY[s][o]
+        if (tid == 2) {
+            float acc = 0.0f;
+            for (int sm = 0; sm < kTrainTile; ++sm) acc += s_loss[0][sm] + s_loss[1][sm];
+            g_loss += acc;
+        }
+        // layer 5 gradients
         if (tid < 128) {
             const int o = tid >> 6, k = tid & 63;
             float acc = 0.0f;
-            for (int q = 0; q < kMlpSamples; ++q) acc = fmaf(DY[q][o], H[3][q][k], acc);
-            put(kOffW5 + o * kMlpHidden + k, acc, first);
+            for (int sm = 0; sm < kTrainTile; ++sm) acc = fmaf(dOut[sm][o], HY[3][sm * kYRow + k], acc);
+            gW5 += acc;
         } else if (tid < 130) {
             const int o = tid - 128;
             float acc = 0.0f;
-            for (int q = 0; q < kMlpSamples; ++q) acc += DY[q][o];
-            put(kOffB5 + o, acc, first);
-        } else if (tid == 130) {
-            float acc = 0.0f;
-            for (int q = 0; q < kMlpSamples; ++q) acc += s_loss[q];
-            a.loss_partials[blockIdx.x] = first ? acc : a.loss_partials[blockIdx.x] + acc;
+            for (int sm = 0; sm < kTrainTile; ++sm) acc += dOut[sm][o];
+            gB5 += acc;
         }
-        // delta4 = (W5^T DY) * g4
-    #pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            const int j = 16 * w + k;
-            D[0][s][j] = (P[kOffW5 + j] * DY[s][0] + P[kOffW5 + kMlpHidden + j] * DY[s][1]) * g[3][k];
+        // delta of layer 4: (W5^T dy) * SiLU'(z4), in this lane's layout
+        float dl[4];
+        {
+            const float d0 = dOut[li][0], d1 = dOut[li][1];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int n = 16 * w + 4 * lg + r;
+                dl[r] = fmaf(P[kOffW5 + n], d0, P[kOffW5 + kMlpHidden + n] * d1) * gp[3][r];
+            }
         }
-        __syncthreads();
-        // hidden layers 4, 3, 2: weight gradient from D[cur] and H[L-1], delta of
-        // the layer below into D[cur ^ 1]
-        const int offW[3] = {kOffW4, kOffW3, kOffW2};
-        const int offB[3] = {kOffB4, kOffB3, kOffB2};
+        // hidden layers 4, 3, 2 (staged matrix L = 2, 1, 0): store the delta,
+        // weight gradient delta H^T, delta of the layer below W^T delta
         int cur = 0;
-    #pragma unroll
+#pragma unroll
         for (int m = 0; m < 3; ++m) {
-            const int hin = 2 - m;  // H index of the layer input (h3, h2, h1)
-            {
-                // dW[j][k] = sum_s D[s][j] H[s][k] for j = tid%64, k in [16 w, 16 w + 16)
-                const int j = s;
-                float acc[16];
-    #pragma unroll
-                for (int k = 0; k < 16; ++k) acc[k] = 0.0f;
-                float db = 0.0f;
-                for (int q = 0; q < kMlpSamples; ++q) {
-                    const float d = D[cur][q][j];
-                    db += d;
-                    const float* hr = &H[hin][q][16 * w];
-    #pragma unroll
-                    for (int k = 0; k < 16; k += 4) {
-                        const float4 hv = *(const float4*)(hr + k);
-                        acc[k] = fmaf(d, hv.x, acc[k]);
-                        acc[k + 1] = fmaf(d, hv.y, acc[k + 1]);
-                        acc[k + 2] = fmaf(d, hv.z, acc[k + 2]);
-                        acc[k + 3] = fmaf(d, hv.w, acc[k + 3]);
-                    }
-                }
-    #pragma unroll
-                for (int k = 0; k < 16; ++k) put(offW[m] + j * kMlpHidden + 16 * w + k, acc[k], first);
-                if (w == 0) put(offB[m] + j, db, first);
-            }
-            {
-                // delta of the layer below: (W^T D[cur])[s][j] * g, j in this lane's range
-                const float* W = P + offW[m];
-                float acc[16];
-    #pragma unroll
-                for (int k = 0; k < 16; ++k) acc[k] = 0.0f;
-    #pragma unroll 4
-                for (int o = 0; o < kMlpHidden; o += 4) {
-                    const float4 dv = *(const float4*)(&D[cur][s][o]);
-    #pragma unroll
-                    for (int k = 0; k < 16; ++k) {
-                        const int j = 16 * w + k;
-                        float t = acc[k];
-                        t = fmaf(W[(o + 0) * kMlpHidden + j], dv.x, t);
-                        t = fmaf(W[(o + 1) * kMlpHidden + j], dv.y, t);
-                        t = fmaf(W[(o + 2) * kMlpHidden + j], dv.z, t);
-                        t = fmaf(W[(o + 3) * kMlpHidden + j], dv.w, t);
-                        acc[k] = t;
-                    }
-                }
-    #pragma unroll
-                for (int k = 0; k < 16; ++k) D[cur ^ 1][s][16 * w + k] = acc[k] * g[hin][k];
-            }
+            const int L = 2 - m;
+            float* dy = DY_[cur];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) DX[(16 * w + 4 * lg + r) * kTrainTile + li] = dl[r];
+            *(float4*)(&dy[li * kYRow + 16 * w + 4 * lg]) = make_float4(dl[0], dl[1], dl[2], dl[3]);
             __syncthreads();
+            // dW[16w + 4lg + r][16tk + li] += sum_s delta[16w + 4lg + r][s] h[16tk + li][s]
+            {
+                const float* hy = HY[L];  // input of this layer: h_{L+1} in 1-based terms
+#pragma unroll
+                for (int ks = 0; ks < 4; ++ks) {
+                    const int sm = 4 * ks + lg;
+                    const float aop = dy[sm * kYRow + 16 * w + li];
+#pragma unroll
+                    for (int tk = 0; tk < 4; ++tk) gW[L][tk] = mfma_f32(aop, hy[sm * kYRow + 16 * tk + li], gW[L][tk]);
+                }
+            }
+            if (w == 0) {
+                float db = 0.0f;
+                for (int sm = 0; sm < kTrainTile; ++sm) db += dy[sm * kYRow + lane];
+                gB[L + 1] += db;
+            }
+            // delta below: (W^T delta)[16w + 4lg + r][li] * SiLU'(z_L)
+            {
+                floatx4_t acc = {0.0f, 0.0f, 0.0f, 0.0f};
+                const float* wt = &Wt[L][(w * 16) * 64 + lane];
+                const float* dx = &DX[lg * kTrainTile + li];
+#pragma unroll
+                for (int ks = 0; ks < 16; ++ks) acc = mfma_f32(wt[ks * 64], dx[4 * ks * kTrainTile], acc);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) dl[r] = acc[r] * gp[L][r];
+            }
+            __syncthreads();  // DX and this layer's delta rows are read
             cur ^= 1;
         }
-        // layer 1: dW1[j][i] = sum_s D[s][j] F[s][i], db1[j] = sum_s D[s][j]
-        if (tid < 64) {
-            const int j = tid;
-            float a0 = 0.0f, a1 = 0.0f, db = 0.0f;
-            for (int q = 0; q < kMlpSamples; ++q) {
-                const float d = D[cur][q][j];
-                a0 = fmaf(d, F[q][0], a0);
-                a1 = fmaf(d, F[q][1], a1);
-                db += d;
+        // layer 1: dW1[j][i] = sum_s delta1[j][s] F[s][i], db1[j] = sum_s delta1[j][s]
+        {
+            float* dy = DY_[cur];
+            *(float4*)(&dy[li * kYRow + 16 * w + 4 * lg]) = make_float4(dl[0], dl[1], dl[2], dl[3]);
+            __syncthreads();
+            if (w == 0) {
+                float a0 = 0.0f, a1 = 0.0f, db = 0.0f;
+                for (int sm = 0; sm < kTrainTile; ++sm) {
+                    const float d = dy[sm * kYRow + lane];
+                    a0 = fmaf(d, F[sm][0], a0);
+                    a1 = fmaf(d, F[sm][1], a1);
+                    db += d;
+                }
+                gW1a += a0;
+                gW1b += a1;
+                gB[0] += db;
             }
-            put(kOffW1 + 2 * j, a0, first);
-            put(kOffW1 + 2 * j + 1, a1, first);
-            put(kOffB1 + j, db, first);
         }
     }
+    // write this workgroup's partial gradient (every entry by its owner)
+    float* out = a.partials + (int64_t)blockIdx.x * kMlpParams;
+    const int offW[3] = {kOffW2, kOffW3, kOffW4};
+#pragma unroll
+    for (int L = 0; L < 3; ++L)
+#pragma unroll
+        for (int tk = 0; tk < 4; ++tk)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) out[offW[L] + (16 * w + 4 * lg + r) * kMlpHidden + 16 * tk + li] = gW[L][tk][r];
+    if (w == 0) {
+        out[kOffW1 + 2 * lane] = gW1a;
+        out[kOffW1 + 2 * lane + 1] = gW1b;
+        out[kOffB1 + lane] = gB[0];
+        out[kOffB2 + lane] = gB[1];
+        out[kOffB3 + lane] = gB[2];
+        out[kOffB4 + lane] = gB[3];
+    }
+    if (tid < 128) out[kOffW5 + tid] = gW5;
+    else if (tid < 130) out[kOffB5 + tid - 128] = gB5;
+    if (tid == 2) a.loss_partials[blockIdx.x] = g_loss;
 }
 
 // Fixed-order sum of the per-workgroup partials; then either write the
@@ -376,11 +454,38 @@ struct ReduceArgs {
     float lr, bc1, bc2;
 };
 
+// One workgroup per 64 parameters: its four waves sum the partials of four
+// interleaved quarters of the workgroups (b = 4c + wave, c ascending; 16
+// loads in flight per lane), then wave 0 adds the four quarter sums in order
+// -- a fixed summation order.
 __global__ __launch_bounds__(256) void k_mlp_reduce(const ReduceArgs a) {
-    const int p = blockIdx.x * 256 + threadIdx.x;
+    __shared__ float s_q[4][64];
+    __shared__ float s_lq[4];
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    const int p = blockIdx.x * 64 + lane;
+    float g = 0.0f;
     if (p < kMlpParams) {
-        float g = 0.0f;
-        for (int64_t b = 0; b < a.blocks; ++b) g += a.partials[b * kMlpParams + p];
+        int64_t b = w;
+        for (; b + 60 < a.blocks; b += 64) {
+            float v[16];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) v[k] = a.partials[(b + 4 * k) * kMlpParams + p];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) g += v[k];
+        }
+        for (; b < a.blocks; b += 4) g += a.partials[b * kMlpParams + p];
+    }
+    s_q[w][lane] = g;
+    if (blockIdx.x == 0 && lane == 0) {
+        float l = 0.0f;
+        for (int64_t b = w; b < a.blocks; b += 4) l += a.loss_partials[b];
+        s_lq[w] = l;
+    }
+    __syncthreads();
+    if (w != 0) return;
+    if (p < kMlpParams) {
+        g = ((s_q[0][lane] + s_q[1][lane]) + s_q[2][lane]) + s_q[3][lane];
         if (a.grad_out) a.grad_out[p] = g;
         if (a.params) {
             const float m = 0.9f * a.m[p] + 0.1f * g;
@@ -391,11 +496,7 @@ __global__ __launch_bounds__(256) void k_mlp_reduce(const ReduceArgs a) {
             a.params[p] -= a.lr * mh / (sqrtf(vh) + 1e-8f);
         }
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0 && a.loss_out) {
-        float l = 0.0f;
-        for (int64_t b = 0; b < a.blocks; ++b) l += a.loss_partials[b];
-        *a.loss_out = l;
-    }
+    if (blockIdx.x == 0 && lane == 0 && a.loss_out) *a.loss_out = ((s_lq[0] + s_lq[1]) + s_lq[2]) + s_lq[3];
 }
 
 __global__ void k_mlp_adam_only(float* params, float* m_, float* v_, const float* grad, float lr, float bc1,
@@ -505,7 +606,7 @@ __global__ __launch_bounds__(kMfmaThreads, kMfmaWavesPerSimd) void k_mlp_mfma(co
         const bool active = i < a.n;
         const float x = active ? a.x[i] : 1.0f, u = active ? a.u[i] : 0.5f;
         float f1, f2;
-        features(x, u, f1, f2);
+        features(x, u, m.dom, f1, f2);
         // the network's LDS copy is re-read for every group: an opaque
         // (wave-uniform, zero) offset keeps the compiler from hoisting all of
         // it into registers, which would cost occupancy
@@ -533,14 +634,14 @@ __global__ __launch_bounds__(kMfmaThreads, kMfmaWavesPerSimd) void k_mlp_mfma(co
                 }
         }
         if (active && a.y) *(float2*)(a.y + 2 * i) = make_float2(o0, o1);
-        if (sampling && active && in_range(x)) net_out(a, i, x, o0);
+        if (sampling && active && in_range(x, m.dom)) net_out(a, i, x, o0, o1);
     }
     if (!sampling) return;
     int64_t* fb = s_fb[wave];
     int nfb = 0;  // wave-uniform
     for (int64_t grp = first; grp < n_groups; grp += stride) {
         const int64_t i = grp * 64 + lane;
-        const bool defer = i < a.n && !in_range(a.x[i]);
+        const bool defer = i < a.n && !in_range(a.x[i], m.dom);
         const uint64_t msk = __ballot(defer);
         if (msk == 0) continue;
         if (defer) fb[nfb + __popcll(msk & ((1ull << lane) - 1ull))] = i;
@@ -564,17 +665,29 @@ __global__ __launch_bounds__(kMfmaThreads, kMfmaWavesPerSimd) void k_mlp_mfma(co
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-constexpr int64_t kMaxGradBlocks = 1024;
+// Feature constants of a network's x range (see NetDomain).
+NetDomain net_domain(double x_min, double x_max) {
+    const double lo = std::log10(x_min), hi = std::log10(x_max);
+    const double c = 0.5 * (lo + hi), h = 0.5 * (hi - lo);
+    NetDomain d;
+    d.f_a = (float)(std::log10(2.0) / h);
+    d.f_b = (float)(-c / h);
+    d.x_lo = (float)x_min;
+    d.x_hi = (float)x_max;
+    return d;
+}
+
+constexpr int64_t kMaxGradBlocks = 512;
 
 int64_t mlp_grad_blocks(int64_t n) {
-    const int64_t t = (n + kMlpSamples - 1) / kMlpSamples;
+    const int64_t t = (n + kTrainTile - 1) / kTrainTile;
     return t < kMaxGradBlocks ? t : kMaxGradBlocks;
 }
 
 hipError_t launch_mlp_forward(const MlpDev& m, cs_sampler prec, const float* x, const float* u, int64_t n, float* y,
                               float* mu, float* ratio, uint8_t* mask, hipStream_t st) {
     if (n <= 0) return hipSuccess;
-    FwdArgs a = {m.params, x, u, n, y, mu, ratio, mask, nullptr};
+    FwdArgs a = {m.params, m.dom, x, u, n, y, mu, ratio, mask, nullptr};
     if (prec == CS_SAMPLER_MLP_F32) {
         k_mlp_fwd_f32<<<(unsigned)((n + kMlpSamples - 1) / kMlpSamples), kMlpThreads, 0, st>>>(a);
     } else {
@@ -596,7 +709,7 @@ hipError_t launch_mlp_grad(const MlpDev& m, const float* x, const float* u, cons
                            float* loss_out, float* adam_m, float* adam_v, float* params_rw, float lr, int64_t t,
                            hipStream_t st) {
     const int64_t blocks = mlp_grad_blocks(n);
-    GradArgs g = {m.params, x, u, mu_t, r_t, n, loss, partials, loss_partials};
+    GradArgs g = {m.params, m.dom, x, u, mu_t, r_t, n, loss, partials, loss_partials};
     k_mlp_grad_block<<<(unsigned)blocks, kMlpThreads, 0, st>>>(g);
     ReduceArgs r = {};
     r.partials = partials;
@@ -612,7 +725,7 @@ hipError_t launch_mlp_grad(const MlpDev& m, const float* x, const float* u, cons
         r.bc1 = (float)(1.0 - std::pow(0.9, (double)t));
         r.bc2 = (float)(1.0 - std::pow(0.999, (double)t));
     }
-    k_mlp_reduce<<<(kMlpParams + 255) / 256, 256, 0, st>>>(r);
+    k_mlp_reduce<<<(kMlpParams + 63) / 64, 256, 0, st>>>(r);
     return hipGetLastError();
 }
 
@@ -623,14 +736,14 @@ hipError_t launch_mlp_adam(float* params, float* m, float* v, const float* grad,
     return hipGetLastError();
 }
 
-hipError_t launch_mlp_quantize(float* params, void* frag_bf16, void* frag_fp8, float* scales, cs_sampler prec,
-                               const float* cx, const float* cu, int64_t n, hipStream_t st) {
+hipError_t launch_mlp_quantize(float* params, const NetDomain& dom, void* frag_bf16, void* frag_fp8, float* scales,
+                               cs_sampler prec, const float* cx, const float* cu, int64_t n, hipStream_t st) {
     const unsigned nb = (kFragCount * 8 + 255) / 256;
     if (prec == CS_SAMPLER_MLP_BF16) {
         k_mlp_build_frag<<<nb, 256, 0, st>>>(params, scales, CS_SAMPLER_MLP_BF16, (__bf16*)frag_bf16, nullptr);
     } else {
         k_mlp_zero_amax<<<1, 64, 0, st>>>((uint32_t*)scales + 6);
-        FwdArgs a = {params, cx, cu, n, nullptr, nullptr, nullptr, nullptr, (uint32_t*)scales + 6};
+        FwdArgs a = {params, dom, cx, cu, n, nullptr, nullptr, nullptr, nullptr, (uint32_t*)scales + 6};
         k_mlp_fwd_f32<<<(unsigned)((n + kMlpSamples - 1) / kMlpSamples), kMlpThreads, 0, st>>>(a);
         k_mlp_act_scale<<<1, 64, 0, st>>>(scales);
         k_mlp_weight_scale<<<3, 256, 0, st>>>(params, scales);

@@ -2,8 +2,9 @@
 // (SiLU) -> 2), shared by the network kernels and by the collision phase of
 // the step kernels so that both give the same bits for the same inputs.
 //
-// Inputs are FP32: f1 = (log10 x + 1) / 3 maps x in [1e-4, 1e2] onto [-1, 1],
-// f2 = 2u - 1.  Output 0 is cos(theta), output 1 the energy ratio.
+// Inputs are FP32: f1 maps log10 x linearly from the network's x range onto
+// [-1, 1] (by default x in [1e-4, 1e2]), f2 = 2u - 1.  Output 0 is
+// cos(theta), output 1 the energy ratio.
 //
 // Two evaluators:
 //   * FP32: either a workgroup-wide engine (cs_mlp.hip) or, inside the step,
@@ -43,16 +44,18 @@ __device__ __forceinline__ float silu_fast(float z) {
     return z * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(z * -1.4426950408889634f));
 }
 
-__device__ __forceinline__ void features(float x, float u, float& f1, float& f2) {
-    f1 = (log10f(x) + 1.0f) / 3.0f;
+// Input features: f1 = log10 x mapped from the network's x range onto
+// [-1, 1] (the hardware log2, about 1 ulp, scaled), f2 = 2u - 1.
+__device__ __forceinline__ void features(float x, float u, const NetDomain& d, float& f1, float& f2) {
+    f1 = fmaf(__builtin_amdgcn_logf(x), d.f_a, d.f_b);
     f2 = 2.0f * u - 1.0f;
 }
 
 __device__ __forceinline__ int wave_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
-// The network answers for x in [CS_MLP_X_MIN, CS_MLP_X_MAX] (as FP32); the
-// plain sampler answers elsewhere.
-__device__ __forceinline__ bool in_range(float x) { return x >= (float)CS_MLP_X_MIN && x <= (float)CS_MLP_X_MAX; }
+// The network answers for x in its range (bounds as FP32); the plain sampler
+// answers elsewhere.
+__device__ __forceinline__ bool in_range(float x, const NetDomain& d) { return x >= d.x_lo && x <= d.x_hi; }
 
 // Input neuron of k-slot e (0..7) of k-step s in lane group g.
 __host__ __device__ __forceinline__ int frag_in_neuron(int s, int g, int e) {
@@ -246,10 +249,10 @@ __device__ __forceinline__ void mlp_tile(const typename FragT<PREC>::type* frag,
     y1 = b1[0];
 }
 
-// One sample per lane in FP32 (cos theta output only).  hb: this wave's
-// [64 neurons][64 lanes] LDS buffer.  The weights are read with wave-uniform
-// addresses (scalar loads).  Must be called by the whole wave.
-__device__ __forceinline__ float mlp_lane_f32(const float* __restrict__ P, float* hb, float f1, float f2) {
+// One sample per lane in FP32, both outputs.  hb: this wave's [64 neurons]
+// [64 lanes] LDS buffer.  The weights are read with wave-uniform addresses
+// (scalar loads).  Must be called by the whole wave.
+__device__ __forceinline__ float2 mlp_lane_f32(const float* __restrict__ P, float* hb, float f1, float f2) {
     const int lane = lane_id();
 #pragma unroll 4
     for (int j = 0; j < kMlpHidden; ++j) {
@@ -275,10 +278,32 @@ __device__ __forceinline__ float mlp_lane_f32(const float* __restrict__ P, float
     }
 #pragma unroll
     for (int k = 0; k < kMlpHidden; ++k) h[k] = hb[k * 64 + lane];
-    float a0 = P[kOffB5];
+    float a0 = P[kOffB5], a1 = P[kOffB5 + 1];
 #pragma unroll
-    for (int k = 0; k < kMlpHidden; ++k) a0 = fmaf(P[kOffW5 + k], h[k], a0);
-    return a0;
+    for (int k = 0; k < kMlpHidden; ++k) {
+        a0 = fmaf(P[kOffW5 + k], h[k], a0);
+        a1 = fmaf(P[kOffW5 + kMlpHidden + k], h[k], a1);
+    }
+    return make_float2(a0, a1);
+}
+
+// The sampler's reading of the two outputs (cos theta, eps'/eps) at FP32 x,
+// as v = 1 - cos(theta) in FP64.  Both outputs carry the event; each is
+// trusted where its error moves the event least.  With absolute errors e of
+// either output, cos theta gives v to e and the energy ratio r = 1/(1 + x v)
+// gives it to e (1 + x v)^2 / x; the ratio is the better guide iff
+// (1 + x v)^2 < x, i.e. for x > 1 and v < (sqrt(x) - 1) / x.  So: v from the
+// (clamped) ratio where x > 1 and that bound holds, else from the (clamped)
+// cosine.  The energy ratio written back is recomputed from v, so the step
+// conserves energy and momentum exactly whichever output is read.
+__device__ __forceinline__ double net_reading_v(float x, float y0, float y1) {
+    const double xd = (double)x;
+    const double v_mu = 1.0 - (double)fminf(fmaxf(y0, -1.0f), 1.0f);
+    if (!(xd > 1.0)) return v_mu;
+    const double r_lo = 1.0 / (1.0 + 2.0 * xd);
+    const double r = fmin(fmax((double)y1, r_lo), 1.0);
+    const double v_r = (1.0 / r - 1.0) / xd;
+    return v_r < (sqrt(xd) - 1.0) / xd ? v_r : v_mu;
 }
 
 // LDS of the network inside a step kernel (nothing for the plain sampler).
@@ -316,12 +341,12 @@ __device__ __forceinline__ void net_load(NetLds<SAMP>& s, const MlpDev& m) {
     }
 }
 
-// cos(theta) from the network for every lane of the wave with need == true
+// The network's two outputs for every lane of the wave with need == true
 // (features f1, f2 of the lane's own sample); other lanes get 0.  Must be
 // called by the whole wave (converged).
 template <int SAMP>
-__device__ __forceinline__ float net_mu_hat(NetLds<SAMP>& s, const MlpDev& m, bool need, float f1, float f2) {
-    float out = 0.0f;
+__device__ __forceinline__ float2 net_outputs(NetLds<SAMP>& s, const MlpDev& m, bool need, float f1, float f2) {
+    float2 out = make_float2(0.0f, 0.0f);
     if constexpr (SAMP == CS_SAMPLER_MLP_F32) {
         if (__any(need)) out = mlp_lane_f32(m.params, s.h[wave_uniform((int)threadIdx.x >> 6)], f1, f2);
     } else if constexpr (SAMP == CS_SAMPLER_MLP_BF16 || SAMP == CS_SAMPLER_MLP_FP8) {
@@ -341,10 +366,10 @@ __device__ __forceinline__ float net_mu_hat(NetLds<SAMP>& s, const MlpDev& m, bo
             mlp_tiles<SAMP, 2>(s.frag, s.P, s.sc, g1, g2, y0, y1);
 #pragma unroll
             for (int k = 0; k < 2; ++k)
-                if ((lane >> 4) == tile + k) out = y0[k];
+                if ((lane >> 4) == tile + k) out = make_float2(y0[k], y1[k]);
         }
     }
-    return need ? out : 0.0f;
+    return need ? out : make_float2(0.0f, 0.0f);
 }
 
 }  // namespace cs

@@ -405,8 +405,9 @@ struct FromArrays {
 };
 
 // Resolve an accepted pair with the sampler network: the network maps the
-// FP32-rounded (x, u) to cos(theta), clamped to [-1, 1]; outside the
-// network's x domain the plain sampler answers (counted in n_fallback).  The
+// FP32-rounded (x, u) to (cos theta, eps'/eps), read as v = 1 - cos theta by
+// net_reading_v; outside the network's x range the plain sampler answers
+// (counted in n_fallback).  The
 // same Philox draw as the plain sampler supplies u and the azimuth.  Must be
 // called by the whole wave; lanes with active == false write nothing.
 template <typename T, int SAMP, typename Src>
@@ -423,18 +424,18 @@ __device__ __forceinline__ void collide_net(const Particles<T>& a, bool active, 
     const u32x4 r = draw(seed, (uint64_t)ie, step, kScatter);
     const double u = uniform53(r.a, r.b);
     const float xf = (float)x, uf = (float)u;
-    const bool inside = active && in_range(xf);
+    const bool inside = active && in_range(xf, m.dom);
     const bool fallback = active && !inside;
     float f1 = 0.0f, f2 = 0.0f;
-    if (inside) features(xf, uf, f1, f2);
-    const float mu_hat = net_mu_hat<SAMP>(s_net, m, inside, f1, f2);
+    if (inside) features(xf, uf, m.dom, f1, f2);
+    const float2 y = net_outputs<SAMP>(s_net, m, inside, f1, f2);
     double v = 0.0;
     if (__any(fallback)) {
         const double vf = angle_icdf_v(fallback ? u : 0.5, fallback ? x : 0.0);
         if (fallback) v = vf;
     }
     if (!active) return;
-    if (inside) v = 1.0 - (double)fminf(fmaxf(mu_hat, -1.0f), 1.0f);
+    if (inside) v = net_reading_v(xf, y.x, y.y);
     const PairInv inv = pair_invariants(p, k);
     const Scattered s = scatter(p, k, inv, v, uniform53(r.c, r.d));
     write_back<T>(a, ie, ig, we, wg, s, seed, step);

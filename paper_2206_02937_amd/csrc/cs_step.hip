@@ -371,6 +371,20 @@ __global__ __launch_bounds__(256) void k_sample_plain(const T* __restrict__ x, c
     }
 }
 
+// Rest-frame photon energy x of the pairs (electron i, photon i), FP64,
+// cancellation-free (the step's own evaluation).
+template <typename T>
+__global__ __launch_bounds__(256) void k_pair_x(const T* __restrict__ px, const T* __restrict__ py,
+                                                const T* __restrict__ pz, const T* __restrict__ kx,
+                                                const T* __restrict__ ky, const T* __restrict__ kz, int64_t n,
+                                                double* __restrict__ x_out) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const d3 p = {(double)px[i], (double)py[i], (double)pz[i]};
+        const d3 k = {(double)kx[i], (double)ky[i], (double)kz[i]};
+        x_out[i] = pair_invariants(p, k).x;
+    }
+}
+
 __global__ __launch_bounds__(256) void k_check_layout(const int64_t* __restrict__ off, int64_t n_cells, int64_t n,
                                                       int32_t* __restrict__ flag) {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -474,6 +488,20 @@ hipError_t launch_sample_plain(cs_dtype dtype, const void* x, const void* u, int
                                                      (double*)ratio);
     else
         k_sample_plain<float><<<grid, 256, 0, st>>>((const float*)x, (const float*)u, n, (float*)mu, (float*)ratio);
+    return hipGetLastError();
+}
+
+hipError_t launch_pair_x(cs_dtype dtype, const cs_species& e, const cs_species& g, int64_t n, double* x_out,
+                         hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const int64_t nb = (n + 255) / 256;
+    const unsigned grid = (unsigned)(nb < 65536 ? nb : 65536);
+    if (dtype == CS_F64)
+        k_pair_x<double><<<grid, 256, 0, st>>>((const double*)e.x, (const double*)e.y, (const double*)e.z,
+                                               (const double*)g.x, (const double*)g.y, (const double*)g.z, n, x_out);
+    else
+        k_pair_x<float><<<grid, 256, 0, st>>>((const float*)e.x, (const float*)e.y, (const float*)e.z,
+                                              (const float*)g.x, (const float*)g.y, (const float*)g.z, n, x_out);
     return hipGetLastError();
 }
 

@@ -5,9 +5,10 @@ distributions (the acceptance measure of the learned sampler).
   two samples (here: cos(theta) or the energy ratio from the network and from
   the plain sampler on the same (x, u) inputs).
 * plasma_inputs: (x, u) pairs whose x follows the rest-frame photon energy of
-  a plasma's electron-photon pairs (x = gamma eps - p.k, the invariant P.K in
-  units of m_e c^2), pairing electron i with photon i (the momenta are drawn
-  independently, so any pairing gives the same distribution).
+  a plasma's electron-photon pairs (the invariant P.K in units of m_e c^2,
+  evaluated by the library, cs_pair_x), pairing randomly drawn electrons with
+  randomly drawn photons (the momenta are drawn independently, so any pairing
+  gives the same distribution).
 * per_x_distance: the deterministic D(x) at fixed x with stratified
   u_k = (k + 1/2) / m: the plain sampler's outputs are the exact quantiles of
   the angular distribution there, so D(x) is the sup distance of the
@@ -28,18 +29,17 @@ def ks_distance(a, b):
     return float(np.max(np.abs(fa - fb)))
 
 
-def plasma_inputs(p, n, seed=0):
-    """n (x, u) pairs drawn from the pairs of plasma p (numpy host arrays)."""
+def plasma_inputs(ctx, p, n, seed=0):
+    """n (x, u) pairs drawn from the pairs of plasma p (x as float64 numpy,
+    computed on the device by the library; u uniform)."""
+    import torch
+
     rng = np.random.default_rng([seed, 11])
-    ne = p.e["x"].size
-    ng = p.g["x"].size
-    m = min(ne, ng)
+    m = min(p.e["x"].size, p.g["x"].size)
     idx = rng.integers(0, m, size=n)
-    pe = np.stack([p.e[c][idx] for c in "xyz"], axis=1).astype(np.float64)
-    k = np.stack([p.g[c][idx] for c in "xyz"], axis=1).astype(np.float64)
-    gam = np.sqrt(1.0 + (pe * pe).sum(1))
-    eps = np.sqrt((k * k).sum(1))
-    x = gam * eps - (pe * k).sum(1)
+    e = {c: torch.from_numpy(np.ascontiguousarray(p.e[c][idx])).cuda() for c in "xyzw"}
+    g = {c: torch.from_numpy(np.ascontiguousarray(p.g[c][idx])).cuda() for c in "xyzw"}
+    x = ctx.pair_x(e, g).cpu().numpy()
     return x, rng.random(n)
 
 

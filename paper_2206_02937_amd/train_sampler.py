@@ -2,10 +2,13 @@
 
     python -m paper_2206_02937_amd.train_sampler [--out PATH] [--samples N]
         [--batch B] [--epochs E] [--lr LR] [--loss mse|mae] [--seed S]
+        [--x-min X0 --x-max X1]
 
-Data: N inputs (x log-uniform on [1e-4, 1e2], u uniform on [0, 1)) with
-targets (cos theta, eps'/eps) from the plain inverse-CDF sampler on the GPU
-(FP64 arithmetic, stored as FP32); the first 80 % train, the last 20 %
+Data: N inputs (x log-uniform on the network's x range [X0, X1], by default
+[1e-8, 1e3]; u uniform on [0, 1)) with targets (cos theta, eps'/eps) from the
+plain inverse-CDF sampler on the GPU (FP64 arithmetic, stored as FP32); the
+network's first feature maps that range onto [-1, 1] and outside it the plain
+sampler answers.  The first 80 % train, the last 20 %
 validate (the paper's split, Sec. 3.2).  Optimiser: Adam (the paper's
 learning rate 1e-3 as the peak), cosine decay to 1 % of it; Glorot-uniform
 initial weights, zero biases.  Each epoch visits the training batches in a
@@ -23,6 +26,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_OUT = os.path.join(HERE, "weights", "sampler_2x64x4.csnet")
+X_RANGE = (1e-8, 1e3)  # rest-frame photon energies of the workloads, power-law and beam plasmas included
 
 
 def glorot_params(seed, widths=(2, 64, 64, 64, 64, 2)):
@@ -37,12 +41,12 @@ def glorot_params(seed, widths=(2, 64, 64, 64, 64, 2)):
     return np.concatenate(parts).astype(np.float32)
 
 
-def make_data(ctx, n, seed):
+def make_data(ctx, n, seed, x_range=X_RANGE):
     import torch
 
     from . import plasma
 
-    x, u = plasma.sampler_inputs(n, seed=seed)
+    x, u = plasma.sampler_inputs(n, seed=seed, x_min=x_range[0], x_max=x_range[1])
     xd = torch.from_numpy(x.astype(np.float32)).cuda()
     ud = torch.from_numpy(u.astype(np.float32)).cuda()
     mu, r = ctx.sample_plain(xd, ud)
@@ -66,16 +70,18 @@ def evaluate(net, xd, ud, mu, r, precision="mlp_f32"):
     }
 
 
-def train(ctx, n=1 << 24, batch=4096, epochs=60, lr=1e-3, loss="mse", seed=0, log=print, init=None):
+def train(ctx, n=1 << 24, batch=4096, epochs=60, lr=1e-3, loss="mse", seed=0, log=print, init=None,
+          x_range=X_RANGE, eval_every=10):
     """Returns (network, summary dict)."""
     import torch
 
     from . import compton
 
-    xd, ud, mu, r = make_data(ctx, n, seed)
+    xd, ud, mu, r = make_data(ctx, n, seed, x_range)
     n_train = int(0.8 * n)
     n_batches = (n_train - batch) // batch + 1
     net = compton.MLP(ctx, glorot_params(seed) if init is None else init)
+    net.set_domain(*x_range)
     losses = torch.zeros(n_batches, dtype=torch.float32, device=xd.device)
     rng = np.random.default_rng([seed, 202])
     hist = []
@@ -89,13 +95,13 @@ def train(ctx, n=1 << 24, batch=4096, epochs=60, lr=1e-3, loss="mse", seed=0, lo
             net.train_step(xd[s], ud[s], mu[s], r[s], lr=lr_ep, loss=loss, loss_out=losses[i])
         mean_loss = float(losses.mean().item())
         rec = {"epoch": ep, "lr": lr_ep, "train_loss": mean_loss, "seconds": round(time.time() - t0, 2)}
-        if ep % 10 == 9 or ep == epochs - 1:
+        if ep % eval_every == eval_every - 1 or ep == epochs - 1:
             rec.update(evaluate(net, xd[val], ud[val], mu[val], r[val]))
         hist.append(rec)
         log(json.dumps(rec))
     torch.cuda.synchronize()
     summary = {"samples": n, "train": n_train, "batch": batch, "epochs": epochs, "lr": lr, "loss": loss,
-               "seed": seed, "seconds": round(time.time() - t0, 2), "final": hist[-1]}
+               "seed": seed, "x_range": list(x_range), "seconds": round(time.time() - t0, 2), "final": hist[-1]}
     return net, summary
 
 
@@ -108,12 +114,14 @@ def main(argv=None):
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--loss", default="mse", choices=["mse", "mae"])
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--x-min", type=float, default=X_RANGE[0])
+    ap.add_argument("--x-max", type=float, default=X_RANGE[1])
     a = ap.parse_args(argv)
     from . import compton
 
     ctx = compton.Context(0)
     net, summary = train(ctx, a.samples, a.batch, a.epochs, a.lr, a.loss, a.seed,
-                         log=lambda s: print(s, flush=True))
+                         log=lambda s: print(s, flush=True), x_range=(a.x_min, a.x_max))
     os.makedirs(os.path.dirname(os.path.abspath(a.out)), exist_ok=True)
     net.save(a.out)
     summary["out"] = a.out

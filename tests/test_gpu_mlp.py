@@ -281,6 +281,7 @@ def test_sample_reading_and_fallback(ctx, mlp_oracle, orc, precision):
     mo = mlp_oracle
     params = _params(mo, 13)
     params[-2] = 0.962  # output bias of mu_hat: most outputs exceed 1
+    params[-1] = 0.9  # output bias of the energy ratio: part of it inside (0, 1), where x > 1 reads it
     x, u = _inputs(5000, seed=40, x_min=1e-6, x_max=1e4)
     x[:3] = np.float32([1e-4, 1e2, 0.5])  # domain edges are inside
     net = compton.MLP(ctx, params)
@@ -295,10 +296,12 @@ def test_sample_reading_and_fallback(ctx, mlp_oracle, orc, precision):
     inside = (x >= np.float32(1e-4)) & (x <= np.float32(1e2))
     assert np.array_equal(mask.astype(bool), ~inside)
     assert inside[:3].all()
-    mu_exp = np.clip(y[inside, 0], -1.0, 1.0)
+    # the reading of the two outputs (the oracle's, in FP64; stored as FP32)
+    mu_exp, r_exp = mo.sample_from_outputs(y[inside], x[inside].astype(np.float64))
     assert np.max(np.abs(mu[inside] - mu_exp)) <= 1e-7
     assert (np.abs(y[inside, 0]) > 1.0).any(), "test needs clamped outputs"
-    r_exp = 1.0 / (1.0 + x[inside].astype(np.float64) * (1.0 - mu[inside].astype(np.float64)))
+    xi = x[inside].astype(np.float64)
+    assert ((xi > 1.0) & (np.abs(mu_exp - np.clip(y[inside, 0], -1, 1)) > 1e-3)).any(), "test needs ratio reads"
     assert np.max(np.abs(r[inside] - r_exp) / r_exp) <= 1e-6
     mu_o, r_o = orc.sample_plain(x[~inside].astype(np.float64), u[~inside].astype(np.float64))
     assert np.max(np.abs(mu[~inside] - mu_o)) <= 1e-6
@@ -376,3 +379,52 @@ def test_save_load_roundtrip(ctx, mlp_oracle, tmp_path):
         compton.MLP.load(ctx, str(tmp_path / "missing.bin"))
     a.close()
     b.close()
+
+
+def test_custom_x_range(ctx, mlp_oracle, tmp_path):
+    """A network trained for another x range: the features map that range onto
+    [-1, 1] (FP32 forward against the oracle with the same range), samples
+    outside it go to the plain sampler, the range travels with save / load,
+    and a file without a range loads with the default one."""
+    from paper_2206_02937_amd import compton
+
+    mo = mlp_oracle
+    lo, hi = 1e-8, 1e3
+    params = _params(mo, 16)
+    net = compton.MLP(ctx, params)
+    assert net.domain == (compton.X_MIN, compton.X_MAX)
+    net.set_domain(lo, hi)
+    assert net.domain == (lo, hi)
+    x, u = _inputs(5000, seed=50, x_min=1e-9, x_max=1e4)
+    x[:2] = np.float32([lo, hi])
+    y = _host(net.forward(_dev(x), _dev(u), "mlp_f32")).astype(np.float64)
+    ref = mo.forward(params.astype(np.float64), x.astype(np.float64), u.astype(np.float64), domain=(lo, hi))
+    assert np.max(np.abs(y - ref)) <= 1e-5
+    net.quantize("mlp_bf16")
+    yb = _host(net.forward(_dev(x), _dev(u), "mlp_bf16")).astype(np.float64)
+    emu = mo.forward_quantized(params.astype(np.float64), x.astype(np.float64), u.astype(np.float64), "bf16",
+                               domain=(lo, hi))
+    assert np.sqrt(np.mean((yb - emu) ** 2)) <= 2e-3
+    _, _, mask = (_host(t) for t in net.sample(_dev(x), _dev(u), "mlp_bf16"))
+    inside = (x >= np.float32(lo)) & (x <= np.float32(hi))
+    assert np.array_equal(mask.astype(bool), ~inside) and (~inside).any() and inside[:2].all()
+    path = str(tmp_path / "ranged.csnet")
+    net.save(path)
+    back = compton.MLP.load(ctx, path)
+    assert back.domain == (lo, hi) and np.array_equal(back.get_params(), net.get_params())
+    shipped = compton.MLP.load(ctx, os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                                                 "paper_2206_02937_amd", "weights", "sampler_2x64x4.csnet"))
+    assert shipped.domain[0] > 0
+    for bad in ((0.0, 1.0), (1.0, 1.0), (2.0, 1.0), (1e-3, float("inf"))):
+        with pytest.raises(compton.CSError):
+            net.set_domain(*bad)
+    assert net.domain == (lo, hi)
+    # the FP8 copy is recalibrated after a range change
+    cx, cu = _inputs(4096, seed=51)
+    net.quantize("mlp_fp8", _dev(cx), _dev(cu))
+    net.set_domain(1e-6, 1e2)
+    with pytest.raises(compton.CSError) as ei:
+        net.sample(_dev(x), _dev(u), "mlp_fp8")
+    assert ei.value.code == compton.CS_ERR_NOT_READY
+    for n_ in (net, back, shipped):
+        n_.close()

@@ -5,11 +5,12 @@ the plain inverse-CDF sampler's on the same 2^22 (x, u) inputs drawn from the
 BF16 inference; an untrained network fails the same gate; FP8's distance is
 measured and bounded loosely (E4M3's 3-bit mantissa does not reach 2e-3).
 After one step from the same state, the lab-frame photon energies of the
-collided pairs agree to the same distance.  Also what the network gains:
-its sampler stage against the plain sampler's on the same inputs."""
+collided pairs agree to the same distance.  Also what the network changes in
+the sampler stage (its cost against the plain sampler's over x), and that
+the library's own training reproduces the shipped network from Glorot
+weights."""
 import os
 import sys
-import time
 
 import numpy as np
 import pytest
@@ -51,7 +52,8 @@ def trained(ctx):
     from paper_2206_02937_amd import compton
 
     net = compton.MLP.load(ctx, WEIGHTS)
-    cx, cu = plasma.sampler_inputs(65536, seed=7)
+    lo, hi = net.domain
+    cx, cu = plasma.sampler_inputs(65536, seed=7, x_min=lo, x_max=hi)
     net.quantize("mlp_bf16")
     net.quantize("mlp_fp8", _dev(cx), _dev(cu))
     yield net
@@ -61,15 +63,16 @@ def trained(ctx):
 @pytest.fixture(scope="module")
 def plasma_xu(ctx):
     p = plasma.make("grid_large", seed=0)
-    x, u = sq.plasma_inputs(p, 1 << 22, seed=0)
+    x, u = sq.plasma_inputs(ctx, p, 1 << 22, seed=0)
     xd, ud = _dev(x), _dev(u)
     mu, r = ctx.sample_plain(xd, ud)
     return xd, ud, mu.cpu().numpy(), r.cpu().numpy()
 
 
 @pytest.fixture(scope="module")
-def domain_xu(ctx):
-    x, u = plasma.sampler_inputs(1 << 22, seed=5)
+def domain_xu(ctx, trained):
+    lo, hi = trained.domain
+    x, u = plasma.sampler_inputs(1 << 22, seed=5, x_min=lo, x_max=hi)
     xd, ud = _dev(x), _dev(u)
     mu, r = ctx.sample_plain(xd, ud)
     return xd, ud, mu.cpu().numpy(), r.cpu().numpy()
@@ -113,7 +116,8 @@ def test_conditional_distance_per_x(ctx, trained):
     m = 1 << 14
     us = sq.stratified_u(m)
     worst = {}
-    for x in sq.log_spaced_x(21):
+    lo, hi = trained.domain
+    for x in sq.log_spaced_x(23, lo, hi):
         xd, ud = _dev(np.full(m, x)), _dev(us)
         mu_p, _ = ctx.sample_plain(xd, ud)
         for prec in ("mlp_f32", "mlp_bf16"):
@@ -158,26 +162,65 @@ def test_step_lab_energy_ks(ctx, trained):
     assert abs(s1["energy_after"] - s1["energy_before"]) <= 1e-12 * s1["energy_before"]
 
 
-def test_network_sampler_stage_gain(ctx, trained, plasma_xu):
-    """What the network buys: the sampler stage on the same 2^22 inputs, the
-    BF16 network against the plain FP64 inverse-CDF sampler."""
+def test_network_sampler_stage_cost(ctx, trained):
+    """What the network changes in the sampler stage on this GPU: its cost
+    does not depend on x (one fixed-size evaluation per sample), while the
+    plain sampler's does (series terms and root-finder steps vary with x), on
+    2^22 samples each of four x distributions (the grid plasma's pairs, the
+    power-law/blackbody plasma's, the p_e = 100 beam's, and the network's
+    whole x range).  It does not outrun the plain FP64 sampler here (see the
+    measured rates); the floor on its rate guards the MFMA kernel."""
     import torch
 
-    xd, ud, _, _ = plasma_xu
+    n = 1 << 22
+    cases = {"grid": sq.plasma_inputs(ctx, plasma.make("grid_large", seed=0), n),
+             "power_law": sq.plasma_inputs(ctx, plasma.power_law(seed=0, n_cells=16384), n),
+             "beam_pe100": sq.plasma_inputs(ctx, plasma.beam_gas(seed=0, p_e=100.0, n_cells=16384), n),
+             "range": plasma.sampler_inputs(n, seed=5, x_min=trained.domain[0], x_max=trained.domain[1])}
 
     def timed(fn, reps=20):
         fn()
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
         for _ in range(reps):
             fn()
+        b.record()
         torch.cuda.synchronize()
-        return (time.perf_counter() - t0) / reps
+        return a.elapsed_time(b) / reps * 1e-3
 
-    mu = torch.empty_like(xd)
-    r = torch.empty_like(xd)
-    t_plain = timed(lambda: ctx.sample_plain(xd, ud, mu, r))
-    t_bf16 = timed(lambda: trained.sample(xd, ud, "mlp_bf16"))
-    n = xd.numel()
-    _log(f"  sampler stage: plain {n / t_plain / 1e9:.2f} G/s, bf16 network {n / t_bf16 / 1e9:.2f} G/s")
-    assert t_bf16 > 0 and t_plain > 0
+    rates = {}
+    for k, (x, u) in cases.items():
+        xd, ud = _dev(x), _dev(u)
+        mu = torch.empty_like(xd)
+        r = torch.empty_like(xd)
+        rates[k] = (n / timed(lambda: ctx.sample_plain(xd, ud, mu, r)) / 1e9,
+                    n / timed(lambda: trained.sample(xd, ud, "mlp_bf16")) / 1e9)
+    _log("  sampler stage, G samples/s (plain, bf16 network): " +
+         ", ".join(f"{k} ({a:.1f}, {b:.1f})" for k, (a, b) in rates.items()))
+    plain = [a for a, _ in rates.values()]
+    net = [b for _, b in rates.values()]
+    assert max(net) <= 1.15 * min(net)
+    assert max(plain) >= 2.0 * min(plain)
+    assert min(net) >= 10.0
+
+
+def test_training_from_glorot_reproduces_the_shipped_network(ctx, plasma_xu):
+    """The shipped weights are what the library's own training gives: the
+    driver's default run (Glorot-uniform start, 2^24 plain-sampler targets
+    over the network's x range, batch 4096, 60 epochs of Adam with the
+    paper's learning rate 1e-3 cosine-decayed) reproduces them bit for bit on
+    the GPU within a fixed budget, and the result meets the KS gate."""
+    from paper_2206_02937_amd import compton, train_sampler
+
+    net, summary = train_sampler.train(ctx, log=lambda s: None)
+    _log(f"  trained in {summary['seconds']} s: {summary['final']}")
+    shipped = compton.MLP.load(ctx, WEIGHTS)
+    assert net.domain == shipped.domain == tuple(train_sampler.X_RANGE)
+    assert np.array_equal(net.get_params(), shipped.get_params())
+    assert summary["seconds"] < 60.0
+    net.quantize("mlp_bf16")
+    ks_mu, ks_r, fb = _ks(net, plasma_xu, "mlp_bf16")
+    assert ks_mu <= KS_GATE and ks_r <= KS_GATE and fb < 1e-3
+    net.close()
+    shipped.close()

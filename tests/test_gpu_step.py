@@ -370,3 +370,31 @@ def test_strategies_bitwise_identical(ctx, workload):
         assert np.array_equal(s0[:8], s1[:8]), (strategy, g)
         d0, d1 = s0.view(np.float64)[8:11], s1.view(np.float64)[8:11]
         assert np.allclose(d0, d1, rtol=1e-13, atol=0), (strategy, g, d0, d1)
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_pair_x_matches_oracle(ctx, orc, dtype):
+    """cs_pair_x (the rest-frame photon energy of pairs) against the oracle's
+    invariant, relative 1e-13, on power-law electrons (gamma up to 1e4) with
+    blackbody photons, plus a photon at rest (x = 0) and a head-on pair."""
+    import torch
+
+    p = plasma.power_law(seed=4, n_cells=8, per_cell=256).astype(dtype)
+    n = p.e["x"].size
+    e = {k: torch.from_numpy(np.ascontiguousarray(v)).cuda() for k, v in p.e.items()}
+    g = {k: torch.from_numpy(np.ascontiguousarray(v)).cuda() for k, v in p.g.items()}
+    g["x"][0] = g["y"][0] = g["z"][0] = 0.0
+    e["x"][1], e["y"][1], e["z"][1] = 0.0, 0.0, 3.0
+    g["x"][1], g["y"][1], g["z"][1] = 0.0, 0.0, -0.5
+    x = ctx.pair_x(e, g).cpu().numpy()
+    assert x.shape == (n,) and x.dtype == np.float64
+    pe = np.stack([e[c].cpu().numpy() for c in "xyz"], axis=1).astype(np.float64)
+    k = np.stack([g[c].cpu().numpy() for c in "xyz"], axis=1).astype(np.float64)
+    ref = np.array([orc.pair_invariants(pe[i], k[i])[0] for i in range(n)])
+    assert x[0] == 0.0 and ref[0] == 0.0
+    assert abs(x[1] - 0.5 * (np.sqrt(10.0) + 3.0)) <= 1e-15 * x[1]  # x = eps (gamma + p) head-on
+    rel = np.abs(x - ref) / np.maximum(ref, 1e-300)
+    assert np.max(rel[1:]) <= 1e-13, np.max(rel[1:])
+    assert x.max() > 1e-3 * x.min() and np.all(x[1:] > 0)
+    with pytest.raises(Exception):
+        ctx.pair_x(e, g, n=n + 1)

@@ -86,7 +86,7 @@ def oracle_net_step(orc, mo, p, state_e, state_g, step, params, precision, calib
     mu = np.full(ne, np.nan)
     y = _quantized_forward(mo, params.astype(np.float64), xf[inside].astype(np.float64),
                            uf[inside].astype(np.float64), precision, calib)
-    mu[inside] = np.clip(y[:, 0], -1.0, 1.0)
+    mu[inside] = 1.0 - mo.reading_v(y, xf[inside].astype(np.float64))
     mu_raw = np.full(ne, np.nan)
     mu_raw[inside] = y[:, 0]
     e = {k: v.copy() for k, v in state_e.items()}
@@ -199,16 +199,19 @@ ROUNDING_STEP = {"mlp_bf16": 2.0 ** -7, "mlp_fp8": 2.0 ** -3}
 
 
 def gpu_network_mu(net, precision, diag, u_mu, sel):
-    """cos(theta) the library's network gives (cs_mlp_sample) at the FP32
-    rounding of the oracle's (x, u) of the electrons in sel; NaN elsewhere."""
+    """cos(theta) the library's network gives at the FP32 rounding of the
+    oracle's (x, u) of the electrons in sel (its raw outputs, cs_mlp_forward,
+    read by the oracle's reading of the two outputs, in FP64 as the step
+    reads them); NaN elsewhere."""
+    from oracle import mlp_oracle as mo
+
     mu = np.full(diag["x"].size, np.nan)
     if not sel.any():
         return mu
     xf = diag["x"][sel].astype(np.float32)
     uf = u_mu[sel].astype(np.float32)
-    m, _, mask = net.sample(_dev(xf), _dev(uf), precision)
-    assert not mask.cpu().numpy().any()  # every listed x is inside the domain
-    mu[sel] = m.cpu().numpy().astype(np.float64)
+    y = net.forward(_dev(xf), _dev(uf), precision).cpu().numpy().astype(np.float64)
+    mu[sel] = 1.0 - mo.reading_v(y, xf.astype(np.float64))
     return mu
 
 
@@ -246,8 +249,9 @@ def network_parity(orc, p, net, precision, before_e, before_g, gpu_e, gpu_g, ste
     dev = np.zeros(0)
     sel = collided & inside
     if emu is not None and sel.any():
-        y = emu(xf[sel].astype(np.float64), u_mu[sel].astype(np.float32).astype(np.float64))
-        dev = np.abs(np.clip(y[:, 0], -1.0, 1.0) - mu_gpu[sel])
+        xs = xf[sel].astype(np.float64)
+        y = emu(xs, u_mu[sel].astype(np.float32).astype(np.float64))
+        dev = np.abs((1.0 - mo.reading_v(y, xs)) - mu_gpu[sel])
     return res, dev, int(sel.sum())
 
 

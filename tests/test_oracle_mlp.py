@@ -32,6 +32,27 @@ def test_one_unit_network_by_hand():
     assert abs(y[0, 0] - (d * h + e)) < 1e-15
 
 
+def test_feature_map_over_an_x_range():
+    """log10 x maps linearly from the network's x range onto [-1, 1]: the
+    range's ends go to -1 and +1, its log-midpoint to 0; the default range
+    [1e-4, 1e2] gives (log10 x + 1) / 3 (x = 10 -> 2/3, as by hand above)."""
+    for lo, hi in ((1e-4, 1e2), (1e-8, 1e3), (0.5, 2.0)):
+        mid = np.sqrt(lo * hi)
+        f = M.features(np.array([lo, mid, hi]), np.array([0.0, 0.5, 0.75]), domain=(lo, hi))
+        assert np.allclose(f[:, 0], [-1.0, 0.0, 1.0], rtol=0, atol=1e-15)
+        assert np.array_equal(f[:, 1], [-1.0, 0.0, 0.5])
+    x = np.array([1e-4, 3e-2, 10.0, 1e2])
+    assert np.allclose(M.features(x, np.zeros(4))[:, 0], (np.log10(x) + 1.0) / 3.0, rtol=0, atol=1e-15)
+    # the range enters only through the features
+    p = M.glorot_uniform(np.random.default_rng(3))
+    xs = np.array([1e-7, 1e-3, 5e2])
+    us = np.array([0.1, 0.5, 0.9])
+    lo, hi = 1e-8, 1e3
+    f1 = (np.log10(xs) + 2.5) / 5.5
+    x_equiv = 10.0 ** (3.0 * f1 - 1.0)  # the x with the same f1 under the default range
+    assert np.allclose(M.forward(p, xs, us, domain=(lo, hi)), M.forward(p, x_equiv, us), rtol=1e-13, atol=1e-15)
+
+
 @pytest.mark.parametrize("kind", ["mse", "mae"])
 def test_gradient_vs_central_differences(kind):
     rng = np.random.default_rng(0)
@@ -129,8 +150,31 @@ def test_e4m3_rounding_matches_torch():
 
 
 def test_sample_reading_of_outputs():
-    y = np.array([[1.3, 0.5], [-0.2, 0.9], [-4.0, 0.1]])
-    x = np.array([0.5, 2.0, 1e-3])
+    """x <= 1: the cosine output, clamped; x > 1: the energy-ratio output where
+    it fixes v = 1 - cos theta better (v_r < (sqrt x - 1) / x), else the
+    cosine; the ratio is always recomputed from v (Compton relation)."""
+    y = np.array([[1.3, 0.5], [-0.2, 0.9], [-4.0, 0.1], [0.3, 0.02], [0.3, 0.95], [0.1, 1.2]])
+    x = np.array([0.5, 2.0, 1e-3, 100.0, 100.0, 50.0])
     mu, r = M.sample_from_outputs(y, x)
-    assert np.array_equal(mu, [1.0, -0.2, -1.0])
-    assert np.allclose(r, 1 / (1 + x * (1 - mu)))
+    v_r = lambda rr, xx: (1.0 / rr - 1.0) / xx  # noqa: E731
+    expect = np.array([1.0, 1.0 - v_r(0.9, 2.0), -1.0, 0.3, 1.0 - v_r(0.95, 100.0), 1.0])
+    assert np.allclose(mu, expect, rtol=0, atol=1e-15)
+    assert np.allclose(r, 1 / (1 + x * (1 - mu)), rtol=1e-15)
+
+
+def test_sample_reading_takes_the_better_conditioned_output():
+    """Outputs off the exact event by at most e each: the reading's error in
+    v is at most the larger of the two outputs' propagated errors at the
+    crossover (both equal e there), and where x v is small against sqrt(x)
+    it is far below e (the ratio carries the forward scatters of large x)."""
+    rng = np.random.default_rng(8)
+    e = 1e-3
+    for x in (0.3, 2.0, 30.0, 1e3):
+        v = rng.uniform(0.0, 2.0, 20000) ** 3 / 4.0  # many small angles
+        mu_t, r_t = 1.0 - v, 1.0 / (1.0 + x * v)
+        y = np.stack([mu_t + rng.uniform(-e, e, v.size), r_t + rng.uniform(-e, e, v.size)], axis=1)
+        err = np.abs(M.reading_v(y, np.full(v.size, x)) - v)
+        assert err.max() <= 1.02 * e, (x, err.max())
+        if x > 100:
+            small = v < 0.01 / np.sqrt(x)
+            assert small.any() and err[small].max() <= 2e-5 * e * x, (x, err[small].max())
