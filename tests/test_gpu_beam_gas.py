@@ -3,10 +3,10 @@ Fig. 4a) on the GPU: the step matches the oracle element by element (1:1
 pairing with the fused and compact strategies, and the no-time-counter
 step), and the scattered photons' spectra with the plain sampler and with
 the BF16 sampler network agree (two-sample KS within the 99 % critical
-value of independent samples, the same peak bin just below p_e).  For
-p_e = 100 most rest-frame energies exceed the network's x range, so most of
-those samples come from the plain sampler (the fallback fraction is
-reported and checked)."""
+value of independent samples, the same peak bin just below p_e).  The
+shipped network's x range reaches 1e3, past the beams' rest-frame energies
+(up to ~1e3 for p_e = 100), so the network answers (nearly) every sample
+(the fallback fraction is checked)."""
 import numpy as np
 import pytest
 
@@ -65,7 +65,4 @@ def test_plain_and_network_spectra_agree(ctx, p_e):
     assert r["ks"] <= 1.63 * np.sqrt(2.0 / n), r
     assert a["mode_over_pe"] == b["mode_over_pe"] and 0.85 <= a["mode_over_pe"] <= 1.1, r
     assert abs(a["collisions"] - b["collisions"]) <= 5 * np.sqrt(a["collisions"]), r
-    if p_e == 100.0:
-        assert b["fallback_fraction"] > 0.6, r
-    if p_e == 25.0:
-        assert b["fallback_fraction"] < 0.5, r
+    assert b["fallback_fraction"] < 0.05, r

@@ -94,7 +94,7 @@ def test_headline_configuration_matches_oracle(ctx, orc, workload, sampler):
                     _log(f"  {res}")
                     parity.assert_parity(res, np.float32, f"step {step}")
                 else:
-                    emu = lambda x, u: mo.forward_quantized(params64, x, u, "bf16")  # noqa: E731
+                    emu = lambda x, u: mo.forward_quantized(params64, x, u, "bf16", domain=net.domain)  # noqa: E731
                     res, dev, n_ev = network_parity(orc, p, net, sampler, before_e, before_g, gpu_e, gpu_g, step,
                                                     cells=cells, emu=emu)
                     _log(f"  {n_ev} network events; {res}; |mu - emu| max {dev.max():.3e}")

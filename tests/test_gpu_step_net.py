@@ -224,7 +224,8 @@ def network_parity(orc, p, net, precision, before_e, before_g, gpu_e, gpu_g, ste
           (everything but the network evaluation is checked in full);
       (2) that cos(theta) must lie within one rounding step of the format
           (ROUNDING_STEP) of the network oracle's emulation, for every event
-          (emu: callable (x, u) -> raw outputs y[n, 2]).
+          (emu: callable (x, u) -> raw outputs y[n, 2] of the network's
+          oracle with the network's x range).
     Returns (parity result, mu deviations |mu_gpu - mu_emu|, event count)."""
     from oracle import mlp_oracle as mo
 
@@ -233,8 +234,9 @@ def network_parity(orc, p, net, precision, before_e, before_g, gpu_e, gpu_g, ste
     u_mu, _ = orc.scatter_uniforms(np.arange(ne), p.seed, step)
     x = diag["x"]
     xf = x.astype(np.float32)
+    lo, hi = net.domain
     valid = (diag["P"] >= 0) & (x > 0)
-    inside = valid & (xf >= np.float32(mo.X_MIN)) & (xf <= np.float32(mo.X_MAX))
+    inside = valid & (xf >= np.float32(lo)) & (xf <= np.float32(hi))
     collided = valid & (diag["u"] < diag["P"])
     # the network is asked for every pair that could collide (ambiguous
     # decisions included), so the oracle step never falls back by accident
