@@ -53,6 +53,8 @@ def parse():
                     help="time eager cs_compton_step calls instead of replaying one captured step (HIP graph)")
     ap.add_argument("--baseline", default=None, choices=["per_cell", "multi_kernel", "fused", "compact"],
                     help="also time this strategy with the plain sampler (eager)")
+    ap.add_argument("--no-workloads", action="store_true",
+                    help="skip the uneven-cell and power-law workloads")
     ap.add_argument("--traffic-calibration", action="store_true",
                     help="end with one plain 256 MiB device-to-device copy (scale for the HBM byte counters)")
     return ap.parse_args()
@@ -283,6 +285,8 @@ def pnet_stage(ctx, p, reps=20):
 
 
 def load_network(ctx, sampler):
+    """The shipped sampler network, prepared for BF16 and for FP8 (calibrated
+    on 2^16 inputs log-uniform over the network's x range)."""
     import numpy as np
     import torch
 
@@ -291,12 +295,11 @@ def load_network(ctx, sampler):
     if sampler == "plain":
         return None
     net = compton.MLP.load(ctx, WEIGHTS)
-    if sampler == "mlp_bf16":
-        net.quantize("mlp_bf16")
-    elif sampler == "mlp_fp8":
-        cx, cu = plasma.sampler_inputs(65536, seed=7)
-        net.quantize("mlp_fp8", torch.from_numpy(cx.astype(np.float32)).cuda(),
-                     torch.from_numpy(cu.astype(np.float32)).cuda())
+    lo, hi = net.domain
+    net.quantize("mlp_bf16")
+    cx, cu = plasma.sampler_inputs(65536, seed=7, x_min=lo, x_max=hi)
+    net.quantize("mlp_fp8", torch.from_numpy(cx.astype(np.float32)).cuda(),
+                 torch.from_numpy(cu.astype(np.float32)).cuda())
     torch.cuda.synchronize()
     return net
 
@@ -396,14 +399,159 @@ def sampler_stage(ctx, p, net, sampler, n=1 << 22):
                                          compton._ptr(ud), n, compton._ptr(mu), compton._ptr(r),
                                          compton._ptr(mask), compton._stream(None)))
 
-        precs = ["mlp_f32", sampler] if sampler != "mlp_f32" else ["mlp_f32"]
-        for prec in precs:
+        for prec in ("mlp_f32", "mlp_bf16", "mlp_fp8"):
             t = timed(lambda: net_sample(prec))
             out[prec] = n / t
             ks_mu = sq.ks_distance(mu.cpu().numpy(), mu_p)
             ks_r = sq.ks_distance(r.cpu().numpy(), r_p)
             res[prec] = {"mu": ks_mu, "r": ks_r, "fallback_frac": float(mask.float().mean().item()), "t": t}
     return out, res
+
+
+def mfma_roofline(prec, stage, ks):
+    """MFMA rate of the network kernel (k_mlp_mfma) from its sampler-stage
+    time: 3 x 64 x 64 x 2 flops per sample in the hidden layers."""
+    if prec not in ks:
+        return None
+    t = ks[prec]["t"]
+    tf = stage["n"] * MLP_MFMA_FLOPS / t / 1e12
+    return {"kernel": f"k_mlp_mfma<{prec[4:]}>", "bound": "mfma", "achieved": tf, "peak": PEAK_MFMA_TFLOPS[prec],
+            "unit": "TFLOP/s", "frac": tf / PEAK_MFMA_TFLOPS[prec], "traffic": None,
+            "flops_per_launch": stage["n"] * MLP_MFMA_FLOPS, "avg_ms": t * 1e3}
+
+
+def pair_roofline(p, run, strategy):
+    """HBM roofline of the pair kernel from a stage-timed (eager) run:
+    algorithmic bytes = every pair's 8 particle values read + per collision
+    its stash entry (8 values, 2 indices) and list slot written."""
+    sb = storage_bytes(p.e["x"].dtype)
+    st = run["last_stats"]
+    stage_ms = run["stage_ms"]
+    if strategy != "compact" or not stage_ms:
+        return None
+    ms = stage_ms["pair"] - stage_ms["compact"]
+    b = p.n_pairs * 8 * sb + st["n_collided"] * (8 * sb + 12)
+    gbs = b / (ms * 1e-3) / 1e9
+    return {"kernel": "k_pair_compact", "bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": gbs / PEAK_HBM_GBS, "traffic": traffic_record("k_pair_compact", p.name), "bytes_per_launch": b,
+            "avg_ms": ms, "units_per_launch": f"{p.n_pairs} pairs, {st['n_collided']} collisions",
+            "working_set_mib": p.nbytes() / 2**20}
+
+
+def workload_stage(ctx, p, net, samplers, steps, warmup, autotune_sampler="mlp_bf16", baseline=None,
+                   baseline_steps=5):
+    """One more workload, measured like the headline: the autotuner's pick,
+    graph-replayed steps for each sampler, a stage-timed eager run (the pair
+    kernel's HBM roofline), optionally the plain sampler under a baseline
+    strategy, and the network's KS distance on 2^20 of the plasma's pair
+    inputs.  The context's options are restored afterwards."""
+    import numpy as np
+    import torch
+
+    from paper_2206_02937_amd import compton, sampler_quality as sq
+
+    saved = [ctx.get_option(o) for o in (compton.OPT_STRATEGY, compton.OPT_CHUNKS_PER_BLOCK,
+                                         compton.OPT_PAIRS_PER_LANE)]
+    e, g, oe, og = compton.to_device(p)
+    tuned = ctx.autotune(e, g, oe, og, p.dt, p.density_norm, p.seed, 0, sampler=autotune_sampler,
+                         mlp=net if autotune_sampler != "plain" else None, reps=3)
+    del e, g, oe, og
+    strategy = compton.STRATEGY_NAMES[ctx.get_option(compton.OPT_STRATEGY)]
+    out = {"workload": f"{p.name}: {p.n_cells} cells, {p.n_pairs} pairs per step", "pairs_per_step": p.n_pairs,
+           "autotune_best": tuned["best"], "steps": steps}
+    for sampler in samplers:
+        r = run_steps(ctx, p, sampler, net if sampler != "plain" else None, steps, warmup, graph=True)
+        out[sampler] = {"pairs_per_s": r["pairs_per_s"], "ms_per_step": r["ms_per_step"],
+                        "collisions_per_step": r["last_stats"]["n_collided"],
+                        "fallback_per_step": r["last_stats"]["n_fallback"]}
+    eager = run_steps(ctx, p, "plain", None, steps, warmup)
+    out["roofline"] = pair_roofline(p, eager, strategy)
+    if baseline:
+        ctx.set_strategy(baseline)
+        ctx.set_chunks_per_block(0)
+        r = run_steps(ctx, p, "plain", None, baseline_steps, 1)
+        out["baseline"] = {"strategy": baseline, "sampler": "plain", "pairs_per_s": r["pairs_per_s"],
+                           "ms_per_step": r["ms_per_step"]}
+    for o, v in zip((compton.OPT_STRATEGY, compton.OPT_CHUNKS_PER_BLOCK, compton.OPT_PAIRS_PER_LANE), saved):
+        ctx.set_option(o, v)
+    if net is not None:
+        n = 1 << 20
+        x, u = sq.plasma_inputs(ctx, p, n, seed=0)
+        xd = torch.from_numpy(x.astype(np.float32)).cuda()
+        ud = torch.from_numpy(u.astype(np.float32)).cuda()
+        mu_p, r_p = ctx.sample_plain(xd, ud)
+        mu_p, r_p = mu_p.cpu().numpy(), r_p.cpu().numpy()
+        out["ks"] = {}
+        for prec in samplers:
+            if prec == "plain":
+                continue
+            m, rr, fb = net.sample(xd, ud, prec)
+            out["ks"][prec] = {"mu": sq.ks_distance(m.cpu().numpy(), mu_p), "r": sq.ks_distance(rr.cpu().numpy(), r_p),
+                               "fallback_frac": float(fb.float().mean().item())}
+    return out
+
+
+def gpu_step_cells(ctx, p, sampler, net, cells, step=0):
+    """One eager step of the whole plasma from its initial state with the
+    context's strategy; returns the sampled cells' particles (host)."""
+    import numpy as np
+    import torch
+
+    from paper_2206_02937_amd import compton
+
+    e, g, oe, og = compton.to_device(p)
+    ctx.step(e, g, oe, og, p.dt, p.density_norm, p.seed, step, sampler=sampler,
+             mlp=net if sampler != "plain" else None)
+    ie = np.concatenate([np.arange(p.off_e[c], p.off_e[c + 1]) for c in cells])
+    ig = np.concatenate([np.arange(p.off_g[c], p.off_g[c + 1]) for c in cells])
+    tie, tig = torch.from_numpy(ie).cuda(), torch.from_numpy(ig).cuda()
+    out = ({k: v.index_select(0, tie).cpu().numpy() for k, v in e.items()},
+           {k: v.index_select(0, tig).cpu().numpy() for k, v in g.items()}, ie, ig)
+    torch.cuda.synchronize()
+    return out
+
+
+def oracle_leg(ctx, p, net, samplers, seconds, n_cells_err=128):
+    """The oracle's leg: the FP64 oracle timed on this host's cores over a
+    bounded sample of the workload (cpu_baseline), and, from the same initial
+    state, the per-event error of the GPU step against it on n_cells_err
+    sampled cells (photon |k - k_ref| / eps_ref, electron |p - p_ref| /
+    gamma_ref over the particles the step moved): the plain sampler must
+    match to the storage tolerance; for the network samplers this is their
+    error against the exact method."""
+    import numpy as np
+
+    import oracle
+
+    cpu = cpu_baseline(p, seconds) if seconds > 0 else None
+    rng = np.random.default_rng(5)
+    cells = np.sort(rng.choice(p.n_cells, min(n_cells_err, p.n_cells), replace=False))
+    ref = p.copy()
+    oracle.compton_step(ref.e, ref.g, ref.off_e, ref.off_g, ref.dt, ref.density_norm, ref.seed, 0, cells=cells)
+    errs = {}
+    for sampler in samplers:
+        ge, gg, ie, ig = gpu_step_cells(ctx, p, sampler, net, cells)
+
+        def vec(d, idx=None):
+            return np.stack([d[c] if idx is None else d[c][idx] for c in "xyz"], axis=1).astype(np.float64)
+
+        pr, kr = vec(ref.e, ie), vec(ref.g, ig)
+        p0, k0 = vec(p.e, ie), vec(p.g, ig)
+        moved_e = np.any(pr != p0, axis=1) | np.any(vec(ge) != p0, axis=1)
+        moved_g = np.any(kr != k0, axis=1) | np.any(vec(gg) != k0, axis=1)
+        ee = np.linalg.norm(vec(ge) - pr, axis=1)[moved_e] / np.sqrt(1.0 + (pr * pr).sum(1))[moved_e]
+        eg = np.linalg.norm(vec(gg) - kr, axis=1)[moved_g] / np.linalg.norm(kr, axis=1)[moved_g]
+        unmoved_same = bool(np.array_equal(vec(ge)[~moved_e], p0[~moved_e]) and
+                            np.array_equal(vec(gg)[~moved_g], k0[~moved_g]))
+        q = lambda a, f: float(f(a)) if a.size else 0.0  # noqa: E731
+        errs[sampler] = {"events": int(moved_g.sum()),
+                         "photon_rel_err": {"median": q(eg, np.median), "p99": q(eg, lambda a: np.percentile(a, 99)),
+                                            "max": q(eg, np.max)},
+                         "electron_rel_err": {"median": q(ee, np.median),
+                                              "p99": q(ee, lambda a: np.percentile(a, 99)), "max": q(ee, np.max)},
+                         "untouched_bitwise": unmoved_same}
+    return cpu, {"cells": int(cells.size), "step": 0, "metric": "|k - k_ref| / eps_ref, |p - p_ref| / gamma_ref "
+                 "per moved particle against the FP64 oracle's plain-sampler step", **errs}
 
 
 def main():
@@ -449,6 +597,10 @@ def main():
         base_run = run_steps(ctx, p, "plain", None, args.steps, args.warmup)
         ctx.set_option(compton.OPT_STRATEGY, saved[0])
         ctx.set_option(compton.OPT_CHUNKS_PER_BLOCK, saved[1])
+    fp8_run = None
+    if net is not None and args.sampler != "mlp_fp8":
+        print(json.dumps({"progress": "timing", "sampler": "mlp_fp8"}), flush=True)
+        fp8_run = run_steps(ctx, p, "mlp_fp8", net, args.steps, args.warmup, graph=args.graph)
     print(json.dumps({"progress": "sampler stage"}), flush=True)
     stage, ks = sampler_stage(ctx, p, net, args.sampler)
 
@@ -489,14 +641,19 @@ def main():
             "bytes_per_launch": bytes_launch, "avg_ms": ms, "avg_ms_events": ms_events,
             "event_overhead_ms": overhead,
             "units_per_launch": f"{n_pairs} pairs, {acc_per_step} collisions"}
-    roof_mlp = None
-    if args.sampler in PEAK_MFMA_TFLOPS and args.sampler in ks:
-        t = ks[args.sampler]["t"]
-        tf = stage["n"] * MLP_MFMA_FLOPS / t / 1e12
-        roof_mlp = {"kernel": f"k_mlp_mfma<{args.sampler[4:]}>", "bound": "mfma", "achieved": tf,
-                    "peak": PEAK_MFMA_TFLOPS[args.sampler], "unit": "TFLOP/s",
-                    "frac": tf / PEAK_MFMA_TFLOPS[args.sampler], "traffic": None,
-                    "flops_per_launch": stage["n"] * MLP_MFMA_FLOPS, "avg_ms": t * 1e3}
+    roof_mlp = mfma_roofline("mlp_bf16", stage, ks)
+    roof_mlp_fp8 = mfma_roofline("mlp_fp8", stage, ks)
+    uneven = power = None
+    if not args.no_workloads:
+        from paper_2206_02937_amd import plasma as plasma_mod
+
+        print(json.dumps({"progress": "uneven workload"}), flush=True)
+        pu = plasma_mod.make("uneven", seed=0)
+        uneven = workload_stage(ctx, pu, net, ["plain", "mlp_bf16"], args.steps, args.warmup, baseline="per_cell")
+        del pu
+        print(json.dumps({"progress": "power-law workload"}), flush=True)
+        pw = plasma_mod.make("power_law", seed=0)
+        power = workload_stage(ctx, pw, net, ["plain", "mlp_bf16", "mlp_fp8"], args.steps, args.warmup)
     print(json.dumps({"progress": "binning"}), flush=True)
     binned = binning_stage(ctx, p)
     print(json.dumps({"progress": "probability network"}), flush=True)
@@ -507,10 +664,13 @@ def main():
     beam = beam_gas_stage(ctx, net, args.sampler)
     print(json.dumps({"progress": "training"}), flush=True)
     training = training_stage(ctx)
-    cpu = None
+    cpu = parity = None
     if not args.no_cpu:
         print(json.dumps({"progress": "cpu baseline"}), flush=True)
-        cpu = cpu_baseline(p, args.cpu_seconds)
+        samplers = ["plain"] + ([] if net is None else ["mlp_bf16", "mlp_fp8"])
+        cpu, parity = oracle_leg(ctx, p, net, samplers, args.cpu_seconds)
+        if power is not None:
+            _, power["error_vs_oracle"] = oracle_leg(ctx, pw, net, samplers, 0.0, n_cells_err=64)
 
     dtype = {"plain": "f64", "mlp_f32": "f64/f32", "mlp_bf16": "f64/bf16", "mlp_fp8": "f64/fp8"}[args.sampler]
     line = {
@@ -546,8 +706,16 @@ def main():
         "mlp_vs_plain": None if plain_run is None else main_run["pairs_per_s"] / plain_run["pairs_per_s"],
         "ks": {k: {"mu": v["mu"], "r": v["r"], "fallback_frac": v["fallback_frac"]} for k, v in ks.items()},
         "sampler_stage_samples_per_s": {k: v for k, v in stage.items() if k not in ("n", "inputs")},
+        "fp8": None if fp8_run is None else {"pairs_per_s": fp8_run["pairs_per_s"],
+                                             "ms_per_step": fp8_run["ms_per_step"],
+                                             "vs_plain": None if plain_run is None else
+                                             fp8_run["pairs_per_s"] / plain_run["pairs_per_s"]},
         "roofline": roof,
         "roofline_mlp": roof_mlp,
+        "roofline_mlp_fp8": roof_mlp_fp8,
+        "error_vs_oracle": parity,
+        "uneven": uneven,
+        "power_law": power,
         "binning": binned,
         "pnet": pnet,
         "ntc": ntc,
