@@ -161,15 +161,17 @@ def reading_v(y, x):
     fixes v to e, while eps'/eps = r = 1 / (1 + x v) fixes it to
     e (1 + x v)^2 / x; so v comes from the ratio (clamped to its range
     [1 / (1 + 2x), 1]) where that is smaller -- x > 1 and
-    v_r < (sqrt(x) - 1) / x -- and from the cosine (clamped to [-1, 1])
-    elsewhere.  x: the network's FP32 input, as float64."""
+    v_r < (sqrt(x) - 1) / x, i.e. r > 1 / sqrt(x) -- and from the cosine
+    (clamped to [-1, 1]) elsewhere.  x: the network's FP32 input, as
+    float64."""
     y = np.asarray(y, dtype=np.float64)
     x = np.asarray(x, dtype=np.float64)
     v_mu = 1.0 - np.clip(y[:, 0], -1.0, 1.0)
     with np.errstate(divide="ignore", invalid="ignore"):
         r = np.clip(y[:, 1], 1.0 / (1.0 + 2.0 * x), 1.0)
-        v_r = (1.0 / r - 1.0) / x
-        use_r = (x > 1.0) & (v_r < (np.sqrt(x) - 1.0) / x)
+        v_r = (1.0 - r) / (r * x)
+        # v_r < (sqrt(x) - 1) / x  <=>  1 + x v_r < sqrt(x)  <=>  r > 1 / sqrt(x)
+        use_r = (x > 1.0) & (r * r * x > 1.0)
     return np.where(use_r, v_r, v_mu)
 
 
@@ -231,20 +233,28 @@ def round_e4m3(a):
     return np.copysign(q, a)
 
 
+# The BF16 network rounds its hidden-layer inputs scaled by -log2(e) (a
+# reading of the reduced-precision scheme: the kernel carries SiLU's
+# exponential argument t = -log2(e) z, so the value it rounds is -log2(e)
+# SiLU(z)); the factor is undone exactly in the next layer.
+SILU_SCALE = -np.log2(np.e)
+
+
 def forward_quantized(params, x, u, fmt, act_scales=None, widths=WIDTHS, domain=(X_MIN, X_MAX)):
     """Forward pass with the hidden-layer contractions in reduced precision:
-    'bf16' rounds the weights and the layer inputs to bfloat16; 'e4m3' divides
-    them by per-layer scales (weights: amax/448; inputs: the given calibrated
-    amax/448) and rounds to FP8 E4M3.  Products and sums in float64, bias and
-    activation in float64.  The first (2 -> 64) and last (64 -> 2) layers stay
-    in full precision, as in the GPU kernel."""
+    'bf16' rounds the weights and the layer inputs (scaled by SILU_SCALE,
+    then unscaled) to bfloat16; 'e4m3' divides them by per-layer scales
+    (weights: amax/448; inputs: the given calibrated amax/448) and rounds to
+    FP8 E4M3.  Products and sums in float64, bias and activation in float64.
+    The first (2 -> 64) and last (64 -> 2) layers stay in full precision, as
+    in the GPU kernel."""
     layers = unpack(params, widths)
     h = features(x, u, domain)
     nl = len(layers)
     for li, (W, b) in enumerate(layers):
         if 0 < li < nl - 1:
             if fmt == "bf16":
-                z = round_bf16(h) @ round_bf16(W).T + b
+                z = (round_bf16(SILU_SCALE * h) / SILU_SCALE) @ round_bf16(W).T + b
             elif fmt == "e4m3":
                 sw = np.max(np.abs(W)) / E4M3_MAX
                 sh = act_scales[li] / E4M3_MAX

@@ -137,7 +137,7 @@ struct FwdArgs {
 __device__ __forceinline__ void net_out(const FwdArgs& a, int64_t i, float x, float y0, float y1) {
     const double v = net_reading_v(x, y0, y1);
     if (a.mu) a.mu[i] = (float)(1.0 - v);
-    if (a.ratio) a.ratio[i] = (float)(1.0 / (1.0 + (double)x * v));
+    if (a.ratio) a.ratio[i] = (float)recip_approx(fma((double)x, v, 1.0));
     if (a.mask) a.mask[i] = 0;
 }
 __device__ __forceinline__ void fallback_out(const FwdArgs& a, int64_t i, float x, float u) {

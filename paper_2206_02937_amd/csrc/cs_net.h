@@ -37,11 +37,19 @@ constexpr float kE4M3Max = 448.0f;
 
 __device__ __forceinline__ float silu_f32(float z) { return z / (1.0f + expf(-z)); }
 
-// SiLU for the reduced-precision paths: its result is rounded to BF16/FP8,
-// so the hardware exp2 and reciprocal approximations (about 1 ulp of FP32)
-// replace the correctly rounded division.
-__device__ __forceinline__ float silu_fast(float z) {
-    return z * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(z * -1.4426950408889634f));
+// The reduced-precision paths carry every pre-activation and activation of
+// the hidden layers scaled by kSiluScale = -log2(e): with t = kSiluScale z,
+// e^-z = 2^t, so SiLU(z) = z / (1 + e^-z) becomes t / (1 + 2^t) / kSiluScale
+// and the exponential takes the layer's output directly.  The factor is
+// folded into the FP32 parameters the engine keeps in LDS (W1, the biases,
+// and 1 / kSiluScale into W5) and into the FP8 input scales; the MFMA weights
+// are unchanged.  Its result is rounded to BF16/FP8, so the hardware exp2 and
+// reciprocal approximations (about 1 ulp of FP32) replace the correctly
+// rounded division.
+constexpr float kSiluScale = -1.4426950408889634f;
+
+__device__ __forceinline__ float silu_scaled(float t) {
+    return t * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(t));
 }
 
 // Input features: f1 = log10 x mapped from the network's x range onto
@@ -68,7 +76,8 @@ __device__ __forceinline__ uint8_t to_e4m3(float v) {
     return (uint8_t)(packed & 0xFFu);
 }
 
-// Compact copy of the FP32 parameters the MFMA engine reads from LDS.
+// Compact copy of the FP32 parameters the MFMA engine reads from LDS: W1 and
+// the hidden biases times kSiluScale, W5 divided by it, b5 as is.
 constexpr int cW1 = 0, cB1 = 128, cB2 = 192, cB3 = 256, cB4 = 320, cW5 = 384, cB5 = 512, kSmall = 514;
 
 __device__ __forceinline__ void load_small_params(const float* P, float* s) {
@@ -88,7 +97,8 @@ __device__ __forceinline__ void load_small_params(const float* P, float* s) {
             src = kOffW5 + (i - cW5);
         else
             src = kOffB5 + (i - cB5);
-        s[i] = P[src];
+        const float v = P[src];
+        s[i] = i < cW5 ? v * kSiluScale : (i < cB5 ? v / kSiluScale : v);
     }
 }
 
@@ -112,10 +122,15 @@ __device__ __forceinline__ typename FragT<PREC>::type pack_inputs(const float (&
         for (int e = 0; e < 8; ++e) b[e] = (__bf16)h[e];
         return b;
     } else {
-        uint64_t b = 0;
+        // two values per conversion, value e into byte e of the operand
+        float v[8];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) b |= (uint64_t)to_e4m3(h[e] * inv) << (8 * e);
-        return (long)b;
+        for (int e = 0; e < 8; ++e) v[e] = fminf(fmaxf(h[e] * inv, -kE4M3Max), kE4M3Max);  // saturating
+        uint32_t lo = __builtin_amdgcn_cvt_pk_fp8_f32(v[0], v[1], 0u, false);
+        lo = __builtin_amdgcn_cvt_pk_fp8_f32(v[2], v[3], lo, true);
+        uint32_t hi = __builtin_amdgcn_cvt_pk_fp8_f32(v[4], v[5], 0u, false);
+        hi = __builtin_amdgcn_cvt_pk_fp8_f32(v[6], v[7], hi, true);
+        return (long)(((uint64_t)hi << 32) | lo);
     }
 }
 
@@ -139,7 +154,7 @@ __device__ __forceinline__ void mlp_tiles(const typename FragT<PREC>::type* frag
     const int g = lane >> 4;
     FT B0[NTL], B1[NTL];
     {
-        const float inv = PREC == CS_SAMPLER_MLP_FP8 ? 1.0f / scales[3] : 1.0f;
+        const float inv = PREC == CS_SAMPLER_MLP_FP8 ? 1.0f / (kSiluScale * scales[3]) : 1.0f;
 #pragma unroll
         for (int half = 0; half < 2; ++half) {
             float h[NTL][8];
@@ -148,7 +163,7 @@ __device__ __forceinline__ void mlp_tiles(const typename FragT<PREC>::type* frag
                 const int n = 16 * (2 * half + e / 4) + 4 * g + (e & 3);
                 const float w1a = P_lds[cW1 + 2 * n], w1b = P_lds[cW1 + 2 * n + 1], b1 = P_lds[cB1 + n];
 #pragma unroll
-                for (int k = 0; k < NTL; ++k) h[k][e] = silu_fast(fmaf(w1b, f2[k], fmaf(w1a, f1[k], b1)));
+                for (int k = 0; k < NTL; ++k) h[k][e] = silu_scaled(fmaf(w1b, f2[k], fmaf(w1a, f1[k], b1)));
             }
 #pragma unroll
             for (int k = 0; k < NTL; ++k) {
@@ -167,8 +182,10 @@ __device__ __forceinline__ void mlp_tiles(const typename FragT<PREC>::type* frag
     for (int L = 0; L < 3; ++L) {
         float sc = 1.0f, inv_next = 1.0f;
         if constexpr (PREC == CS_SAMPLER_MLP_FP8) {
-            sc = scales[L] * scales[3 + L];
-            if (L < 2) inv_next = 1.0f / scales[4 + L];
+            // the FP8 inputs are h / s (kSiluScale divided out), so the
+            // accumulator takes the factor with the scales
+            sc = kSiluScale * (scales[L] * scales[3 + L]);
+            if (L < 2) inv_next = 1.0f / (kSiluScale * scales[4 + L]);
         }
         FT N0[NTL], N1[NTL];
         float half[NTL][4];  // outputs of an even tile t, packed with tile t + 1
@@ -189,13 +206,13 @@ __device__ __forceinline__ void mlp_tiles(const typename FragT<PREC>::type* frag
                     acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A0, B0[k], acc, 0, 0, 0);
                     acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A1, B1[k], acc, 0, 0, 0);
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) o[r] = silu_fast(acc[r]);
+                    for (int r = 0; r < 4; ++r) o[r] = silu_scaled(acc[r]);
                 } else {
                     acc = {0.0f, 0.0f, 0.0f, 0.0f};
                     acc = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(A0, B0[k], acc, 0, 0, 0);
                     acc = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(A1, B1[k], acc, 0, 0, 0);
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) o[r] = silu_fast(fmaf(acc[r], sc, bias[r]));
+                    for (int r = 0; r < 4; ++r) o[r] = silu_scaled(fmaf(acc[r], sc, bias[r]));
                 }
                 if (L == 2) {
                     // output layer sums, neuron order t ascending then r
@@ -292,18 +309,17 @@ __device__ __forceinline__ float2 mlp_lane_f32(const float* __restrict__ P, floa
 // trusted where its error moves the event least.  With absolute errors e of
 // either output, cos theta gives v to e and the energy ratio r = 1/(1 + x v)
 // gives it to e (1 + x v)^2 / x; the ratio is the better guide iff
-// (1 + x v)^2 < x, i.e. for x > 1 and v < (sqrt(x) - 1) / x.  So: v from the
-// (clamped) ratio where x > 1 and that bound holds, else from the (clamped)
-// cosine.  The energy ratio written back is recomputed from v, so the step
-// conserves energy and momentum exactly whichever output is read.
+// (1 + x v)^2 < x, i.e. iff x > 1 and r > 1/sqrt(x) (r^2 x > 1).  So: v from
+// the ratio (clamped to [1/(1 + 2x), 1]) there, else from the cosine
+// (clamped to [-1, 1]).  The energy ratio written back is recomputed from v,
+// so the step conserves energy and momentum exactly whichever output is read.
 __device__ __forceinline__ double net_reading_v(float x, float y0, float y1) {
     const double xd = (double)x;
-    const double v_mu = 1.0 - (double)fminf(fmaxf(y0, -1.0f), 1.0f);
-    if (!(xd > 1.0)) return v_mu;
-    const double r_lo = 1.0 / (1.0 + 2.0 * xd);
-    const double r = fmin(fmax((double)y1, r_lo), 1.0);
-    const double v_r = (1.0 / r - 1.0) / xd;
-    return v_r < (sqrt(xd) - 1.0) / xd ? v_r : v_mu;
+    if (xd > 1.0) {
+        const double r = fmin(fmax((double)y1, recip_approx(fma(2.0, xd, 1.0))), 1.0);
+        if (r * r * xd > 1.0) return div_normal(1.0 - r, r * xd);
+    }
+    return 1.0 - (double)fminf(fmaxf(y0, -1.0f), 1.0f);
 }
 
 // LDS of the network inside a step kernel (nothing for the plain sampler).

@@ -413,13 +413,20 @@ struct FromArrays {
 template <typename T, int SAMP, typename Src>
 __device__ __forceinline__ void collide_net(const Particles<T>& a, bool active, const Src& src, NetLds<SAMP>& s_net,
                                             const MlpDev& m, uint64_t seed, uint64_t step, CollideSums& sums) {
+    // Three phases, so that little is live while the network runs: (1) x and
+    // the Philox draw from the pair's values, (2) the network for the wave,
+    // (3) the pair's values fetched again (the same source: LDS, a stash entry
+    // in cache, or the particle arrays) for the sampler's fallback and the
+    // scatter.
     double x = 0.0;
     int32_t ie = 0, ig = 0;
-    d3 p = {0.0, 0.0, 0.0}, k = {0.0, 0.0, 0.0};
-    double we = 0.0, wg = 0.0;
-    if (active) {
-        src.get(a, ie, ig, p, k, we, wg);
-        x = pair_invariants(p, k).x;
+    {
+        d3 p = {0.0, 0.0, 0.0}, k = {0.0, 0.0, 0.0};
+        double we = 0.0, wg = 0.0;
+        if (active) {
+            src.get(a, ie, ig, p, k, we, wg);
+            x = pair_invariants(p, k).x;
+        }
     }
     const u32x4 r = draw(seed, (uint64_t)ie, step, kScatter);
     const double u = uniform53(r.a, r.b);
@@ -436,6 +443,9 @@ __device__ __forceinline__ void collide_net(const Particles<T>& a, bool active, 
     }
     if (!active) return;
     if (inside) v = net_reading_v(xf, y.x, y.y);
+    d3 p, k;
+    double we, wg;
+    src.get(a, ie, ig, p, k, we, wg);
     const PairInv inv = pair_invariants(p, k);
     const Scattered s = scatter(p, k, inv, v, uniform53(r.c, r.d));
     write_back<T>(a, ie, ig, we, wg, s, seed, step);

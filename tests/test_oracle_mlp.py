@@ -178,3 +178,22 @@ def test_sample_reading_takes_the_better_conditioned_output():
         if x > 100:
             small = v < 0.01 / np.sqrt(x)
             assert small.any() and err[small].max() <= 2e-5 * e * x, (x, err[small].max())
+
+
+def test_bf16_emulation_by_hand():
+    """One unit per layer: the BF16 network rounds the hidden layer's weight
+    and its input -log2(e) SiLU(z) to bfloat16 (the scale undone after), the
+    first and last layers stay in float64."""
+    widths = (2, 1, 1, 1)
+    params = np.array([0.7, -1.3, 0.2, 1.2345678, -0.1, 2.5, -0.4])  # W1[2], b1, W2, b2, W3, b3
+    x, u = np.array([10.0]), np.array([0.25])
+    f1, f2 = 2.0 / 3.0, -0.5
+    z1 = 0.7 * f1 - 1.3 * f2 + 0.2
+    h1 = z1 / (1.0 + np.exp(-z1))
+    c = -np.log2(np.e)
+    q = M.round_bf16(c * h1)[()] / c
+    z2 = q * M.round_bf16(1.2345678)[()] - 0.1
+    h2 = z2 / (1.0 + np.exp(-z2))
+    y = M.forward_quantized(params, x, u, "bf16", widths=widths)
+    assert abs(y[0, 0] - (2.5 * h2 - 0.4)) < 1e-15
+    assert q != M.round_bf16(h1)[()]  # the scale changes the rounding here
