@@ -16,7 +16,8 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(HERE, "liboracle.so")
+# CS_ORACLE_LIB selects another build of the same source (the sanitized one)
+_LIB_PATH = os.environ.get("CS_ORACLE_LIB") or os.path.join(HERE, "liboracle.so")
 _lib = None
 
 
