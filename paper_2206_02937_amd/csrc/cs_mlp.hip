@@ -28,6 +28,13 @@ constexpr int kMlpThreads = 256;
 constexpr int kMlpSamples = 64;  // samples per FP32 workgroup
 constexpr int kRow = 68;         // LDS row stride (floats), 16-byte aligned rows
 
+// SiLU and its derivative from one exponential and one division (training).
+__device__ __forceinline__ void silu_and_grad(float z, float& h, float& g) {
+    const float sg = 1.0f / (1.0f + expf(-z));
+    h = z * sg;
+    g = sg * (1.0f + z * (1.0f - sg));
+}
+
 __device__ __forceinline__ float silu_grad_f32(float z) {
     const float s = 1.0f / (1.0f + expf(-z));
     return s * (1.0f + z * (1.0f - s));
@@ -197,8 +204,9 @@ struct GradArgs {
 // -- the lane that produced z keeps SiLU'(z) in registers for that --, and
 // the weight gradients dW[16w.., :] = delta[16w.., :] H^T (four 16x16 tiles,
 // K = 16 samples), which stay in MFMA accumulators over the workgroup's tiles
-// and are written once.  The weight operands are staged in LDS once per
-// workgroup in fragment order (conflict-free); activations and deltas are
+// and are written once.  Each lane loads the parameters it uses once, into
+// registers, for all its tiles (its 96 MFMA weight operands among them);
+// activations and deltas are
 // written to LDS in two layouts, [feature][sample] for the operands whose
 // K index is a feature and [sample][feature] (rows of kYRow) for those whose
 // K index is a sample, so that every operand read is conflict-free.  Each
@@ -215,10 +223,6 @@ __device__ __forceinline__ floatx4_t mfma_f32(float a, float b, floatx4_t c) {
 }
 
 __global__ __launch_bounds__(kMlpThreads) void k_mlp_grad_block(const GradArgs a) {
-    // weight fragments: [layer][tile t][k-step][lane]; Wf: A = W[16t + l%16][4ks + l/16],
-    // Wt: A = W^T[16t + l%16][4ks + l/16] = W[4ks + l/16][16t + l%16]
-    __shared__ float Wf[3][4 * 16 * 64];
-    __shared__ float Wt[3][4 * 16 * 64];
     __shared__ float HX[4][kMlpHidden * kTrainTile];      // h1..h4, [feature][sample]
     __shared__ float HY[4][kTrainTile * kYRow];           // h1..h4, [sample][feature]
     __shared__ float DX[kMlpHidden * kTrainTile];         // delta of the current layer, [feature][sample]
@@ -226,31 +230,37 @@ __global__ __launch_bounds__(kMlpThreads) void k_mlp_grad_block(const GradArgs a
     __shared__ float F[kTrainTile][2];                    // features
     __shared__ float dOut[kTrainTile][2];                 // output deltas
     __shared__ float s_loss[2][kTrainTile];
+    __shared__ float yPart[4][2][kTrainTile];             // output-layer sums of each wave's neurons
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int w = wave_uniform(tid >> 6);
     const int li = lane & 15, lg = lane >> 4;  // MFMA operand row / k index of this lane
     const float* P = a.P;
-    {
-        // all of a layer's loads in flight at once (16 + 16 per thread)
-        const int offW[3] = {kOffW2, kOffW3, kOffW4};
-#pragma unroll 1
-        for (int L = 0; L < 3; ++L) {
-            float vf[16], vt[16];
+    // every parameter this lane uses, loaded once for all its tiles: the
+    // hidden layers' MFMA operands A = W[16w + li][4ks + lg] (forward) and
+    // W^T[16w + li][4ks + lg] (backward), and for its neurons
+    // n(r) = 16w + 4 lg + r the first layer, the biases and the output weights
+    const int offW[3] = {kOffW2, kOffW3, kOffW4};
+    const int offB[3] = {kOffB2, kOffB3, kOffB4};
+    float wf[3][16], wt[3][16];
 #pragma unroll
-            for (int it = 0; it < 16; ++it) {
-                const int i = tid + it * kMlpThreads;
-                const int l = i & 63, ks = (i >> 6) & 15, t = i >> 10;
-                const int r = 16 * t + (l & 15), c = 4 * ks + (l >> 4);
-                vf[it] = P[offW[L] + r * kMlpHidden + c];
-                vt[it] = P[offW[L] + c * kMlpHidden + r];
-            }
+    for (int L = 0; L < 3; ++L)
 #pragma unroll
-            for (int it = 0; it < 16; ++it) {
-                Wf[L][tid + it * kMlpThreads] = vf[it];
-                Wt[L][tid + it * kMlpThreads] = vt[it];
-            }
+        for (int ks = 0; ks < 16; ++ks) {
+            wf[L][ks] = P[offW[L] + (16 * w + li) * kMlpHidden + 4 * ks + lg];
+            wt[L][ks] = P[offW[L] + (4 * ks + lg) * kMlpHidden + 16 * w + li];
         }
+    float w1a[4], w1b[4], bias[4][4], w50[4], w51[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int n = 16 * w + 4 * lg + r;
+        w1a[r] = P[kOffW1 + 2 * n];
+        w1b[r] = P[kOffW1 + 2 * n + 1];
+        bias[0][r] = P[kOffB1 + n];
+#pragma unroll
+        for (int L = 0; L < 3; ++L) bias[L + 1][r] = P[offB[L] + n];
+        w50[r] = P[kOffW5 + n];
+        w51[r] = P[kOffW5 + kMlpHidden + n];
     }
     // this lane's neurons of every layer: n(r) = 16w + 4 lg + r, sample li
     floatx4_t gW[3][4];  // dW_{2,3,4}[16w + 4lg + r][16tk + li], accumulated over the tiles
@@ -282,42 +292,55 @@ __global__ __launch_bounds__(kMlpThreads) void k_mlp_grad_block(const GradArgs a
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int n = 16 * w + 4 * lg + r;
-                const float z = fmaf(P[kOffW1 + 2 * n + 1], f2, fmaf(P[kOffW1 + 2 * n], f1, P[kOffB1 + n]));
-                h[r] = silu_f32(z);
-                gp[0][r] = silu_grad_f32(z);
+                const float z = fmaf(w1b[r], f2, fmaf(w1a[r], f1, bias[0][r]));
+                silu_and_grad(z, h[r], gp[0][r]);
                 HX[0][n * kTrainTile + li] = h[r];
             }
             *(float4*)(&HY[0][li * kYRow + 16 * w + 4 * lg]) = make_float4(h[0], h[1], h[2], h[3]);
         }
         __syncthreads();
         // hidden layers 2..4: Z = W H + b on MFMA
-        const int offB[3] = {kOffB2, kOffB3, kOffB4};
 #pragma unroll
         for (int L = 0; L < 3; ++L) {
             floatx4_t acc;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) acc[r] = P[offB[L] + 16 * w + 4 * lg + r];
-            const float* wf = &Wf[L][(w * 16) * 64 + lane];
+            for (int r = 0; r < 4; ++r) acc[r] = bias[L + 1][r];
             const float* hx = &HX[L][lg * kTrainTile + li];
 #pragma unroll
-            for (int ks = 0; ks < 16; ++ks) acc = mfma_f32(wf[ks * 64], hx[4 * ks * kTrainTile], acc);
+            for (int ks = 0; ks < 16; ++ks) acc = mfma_f32(wf[L][ks], hx[4 * ks * kTrainTile], acc);
             float h[4];
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int n = 16 * w + 4 * lg + r;
-                h[r] = silu_f32(acc[r]);
-                gp[L + 1][r] = silu_grad_f32(acc[r]);
+                silu_and_grad(acc[r], h[r], gp[L + 1][r]);
                 HX[L + 1][n * kTrainTile + li] = h[r];
             }
             *(float4*)(&HY[L + 1][li * kYRow + 16 * w + 4 * lg]) = make_float4(h[0], h[1], h[2], h[3]);
+            if (L == 2) {
+                // output layer: this lane's four neurons of h4, then the lane
+                // groups (fixed butterfly), then the waves in order below
+                float q0 = 0.0f, q1 = 0.0f;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    q0 = fmaf(w50[r], h[r], q0);
+                    q1 = fmaf(w51[r], h[r], q1);
+                }
+                q0 += __shfl_xor(q0, 16, 64);
+                q1 += __shfl_xor(q1, 16, 64);
+                q0 += __shfl_xor(q0, 32, 64);
+                q1 += __shfl_xor(q1, 32, 64);
+                if (lg == 0) {
+                    yPart[w][0][li] = q0;
+                    yPart[w][1][li] = q1;
+                }
+            }
             __syncthreads();
         }
         // output layer and loss gradient: one thread per (sample, output)
         if (tid < 2 * kTrainTile) {
             const int sm = tid >> 1, o = tid & 1;
             const int64_t i = tile * kTrainTile + sm;
-            float y = P[kOffB5 + o];
-            for (int k = 0; k < kMlpHidden; ++k) y = fmaf(P[kOffW5 + o * kMlpHidden + k], HY[3][sm * kYRow + k], y);
+            const float y = (((P[kOffB5 + o] + yPart[0][o][sm]) + yPart[1][o][sm]) + yPart[2][o][sm]) + yPart[3][o][sm];
             float d = 0.0f, l = 0.0f;
             if (i < a.n) {
                 const float e = y - (o == 0 ? a.mu_t[i] : a.r_t[i]);
@@ -355,10 +378,7 @@ __global__ __launch_bounds__(kMlpThreads) void k_mlp_grad_block(const GradArgs a
         {
             const float d0 = dOut[li][0], d1 = dOut[li][1];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int n = 16 * w + 4 * lg + r;
-                dl[r] = fmaf(P[kOffW5 + n], d0, P[kOffW5 + kMlpHidden + n] * d1) * gp[3][r];
-            }
+            for (int r = 0; r < 4; ++r) dl[r] = fmaf(w50[r], d0, w51[r] * d1) * gp[3][r];
         }
         // hidden layers 4, 3, 2 (staged matrix L = 2, 1, 0): store the delta,
         // weight gradient delta H^T, delta of the layer below W^T delta
@@ -390,10 +410,9 @@ __global__ __launch_bounds__(kMlpThreads) void k_mlp_grad_block(const GradArgs a
             // delta below: (W^T delta)[16w + 4lg + r][li] * SiLU'(z_L)
             {
                 floatx4_t acc = {0.0f, 0.0f, 0.0f, 0.0f};
-                const float* wt = &Wt[L][(w * 16) * 64 + lane];
                 const float* dx = &DX[lg * kTrainTile + li];
 #pragma unroll
-                for (int ks = 0; ks < 16; ++ks) acc = mfma_f32(wt[ks * 64], dx[4 * ks * kTrainTile], acc);
+                for (int ks = 0; ks < 16; ++ks) acc = mfma_f32(wt[L][ks], dx[4 * ks * kTrainTile], acc);
 #pragma unroll
                 for (int r = 0; r < 4; ++r) dl[r] = acc[r] * gp[L][r];
             }
@@ -421,7 +440,6 @@ __global__ __launch_bounds__(kMlpThreads) void k_mlp_grad_block(const GradArgs a
     }
     // write this workgroup's partial gradient (every entry by its owner)
     float* out = a.partials + (int64_t)blockIdx.x * kMlpParams;
-    const int offW[3] = {kOffW2, kOffW3, kOffW4};
 #pragma unroll
     for (int L = 0; L < 3; ++L)
 #pragma unroll
@@ -454,38 +472,41 @@ struct ReduceArgs {
     float lr, bc1, bc2;
 };
 
-// One workgroup per 64 parameters: its four waves sum the partials of four
-// interleaved quarters of the workgroups (b = 4c + wave, c ascending; 16
-// loads in flight per lane), then wave 0 adds the four quarter sums in order
-// -- a fixed summation order.
-__global__ __launch_bounds__(256) void k_mlp_reduce(const ReduceArgs a) {
-    __shared__ float s_q[4][64];
-    __shared__ float s_lq[4];
+// One workgroup of 16 waves per 64 parameters: wave w sums the partials of
+// workgroups b = 16c + w (c ascending; up to 16 loads in flight per lane),
+// then wave 0 adds the 16 wave sums in order -- a fixed summation order.
+constexpr int kReduceWaves = 16;
+
+__global__ __launch_bounds__(64 * kReduceWaves) void k_mlp_reduce(const ReduceArgs a) {
+    __shared__ float s_q[kReduceWaves][64];
+    __shared__ float s_lq[kReduceWaves];
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
     const int p = blockIdx.x * 64 + lane;
     float g = 0.0f;
     if (p < kMlpParams) {
         int64_t b = w;
-        for (; b + 60 < a.blocks; b += 64) {
+        for (; b + 15 * kReduceWaves < a.blocks; b += 16 * kReduceWaves) {
             float v[16];
 #pragma unroll
-            for (int k = 0; k < 16; ++k) v[k] = a.partials[(b + 4 * k) * kMlpParams + p];
+            for (int k = 0; k < 16; ++k) v[k] = a.partials[(b + kReduceWaves * k) * kMlpParams + p];
 #pragma unroll
             for (int k = 0; k < 16; ++k) g += v[k];
         }
-        for (; b < a.blocks; b += 4) g += a.partials[b * kMlpParams + p];
+        for (; b < a.blocks; b += kReduceWaves) g += a.partials[b * kMlpParams + p];
     }
     s_q[w][lane] = g;
     if (blockIdx.x == 0 && lane == 0) {
         float l = 0.0f;
-        for (int64_t b = w; b < a.blocks; b += 4) l += a.loss_partials[b];
+        for (int64_t b = w; b < a.blocks; b += kReduceWaves) l += a.loss_partials[b];
         s_lq[w] = l;
     }
     __syncthreads();
     if (w != 0) return;
     if (p < kMlpParams) {
-        g = ((s_q[0][lane] + s_q[1][lane]) + s_q[2][lane]) + s_q[3][lane];
+        g = s_q[0][lane];
+#pragma unroll
+        for (int k = 1; k < kReduceWaves; ++k) g += s_q[k][lane];
         if (a.grad_out) a.grad_out[p] = g;
         if (a.params) {
             const float m = 0.9f * a.m[p] + 0.1f * g;
@@ -496,7 +517,11 @@ __global__ __launch_bounds__(256) void k_mlp_reduce(const ReduceArgs a) {
             a.params[p] -= a.lr * mh / (sqrtf(vh) + 1e-8f);
         }
     }
-    if (blockIdx.x == 0 && lane == 0 && a.loss_out) *a.loss_out = ((s_lq[0] + s_lq[1]) + s_lq[2]) + s_lq[3];
+    if (blockIdx.x == 0 && lane == 0 && a.loss_out) {
+        float l = s_lq[0];
+        for (int k = 1; k < kReduceWaves; ++k) l += s_lq[k];
+        *a.loss_out = l;
+    }
 }
 
 __global__ void k_mlp_adam_only(float* params, float* m_, float* v_, const float* grad, float lr, float bc1,
@@ -725,7 +750,7 @@ hipError_t launch_mlp_grad(const MlpDev& m, const float* x, const float* u, cons
         r.bc1 = (float)(1.0 - std::pow(0.9, (double)t));
         r.bc2 = (float)(1.0 - std::pow(0.999, (double)t));
     }
-    k_mlp_reduce<<<(kMlpParams + 63) / 64, 256, 0, st>>>(r);
+    k_mlp_reduce<<<(kMlpParams + 63) / 64, 64 * kReduceWaves, 0, st>>>(r);
     return hipGetLastError();
 }
 
