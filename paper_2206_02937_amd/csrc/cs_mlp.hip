@@ -1,18 +1,15 @@
 // cs_mlp.hip -- kernels of the sampler network (2 -> 64 x4 (SiLU) -> 2).
 //
-// FP32 engine (training, FP32 inference, calibration): one workgroup of 256
-// lanes holds 64 samples; its four waves split every layer's 64 output
-// neurons (wave w computes neurons 16w..16w+15 for all 64 samples), reading
-// the sample's input row from LDS (128-bit loads) and the weights as
-// wave-uniform scalar loads.  Backward keeps SiLU'(z) in registers (the lane
-// that produced z consumes it), the layer outputs in LDS for the weight
-// gradients, and writes one partial gradient per workgroup; a second kernel
-// sums the partials in a fixed order (bitwise reproducible) and applies Adam.
-//
-// MFMA engine (BF16 / FP8 inference): the tile evaluator of cs_net.h on
-// grid-strided 16-sample tiles, the fragments and small parameters in LDS.
-// Preparation kernels build the fragments (BF16 rounding, or per-layer FP8
-// scales from the weight amax and a calibration pass of the FP32 engine).
+// Every engine runs the hidden layers on MFMA:
+//   * BF16 / FP8 inference: the tile evaluator of cs_net.h, 64-sample groups
+//     per wave, the fragments and small parameters in LDS; preparation
+//     kernels build the fragments (BF16 rounding, or per-layer FP8 scales
+//     from the weight amax and a calibration pass of the FP32 engine);
+//   * FP32 inference and calibration: the same walk with FP32 MFMA
+//     (v_mfma_f32_16x16x4_f32) and the correctly rounded FP32 SiLU;
+//   * training: forward and backward of 16-sample tiles on FP32 MFMA, one
+//     partial gradient per workgroup, then a fixed-order sum of the partials
+//     and Adam (bitwise reproducible).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -25,8 +22,6 @@
 namespace cs {
 
 constexpr int kMlpThreads = 256;
-constexpr int kMlpSamples = 64;  // samples per FP32 workgroup
-constexpr int kRow = 68;         // LDS row stride (floats), 16-byte aligned rows
 
 // SiLU and its derivative from one exponential and one division (training).
 __device__ __forceinline__ void silu_and_grad(float z, float& h, float& g) {
@@ -38,90 +33,6 @@ __device__ __forceinline__ void silu_and_grad(float z, float& h, float& g) {
 __device__ __forceinline__ float silu_grad_f32(float z) {
     const float s = 1.0f / (1.0f + expf(-z));
     return s * (1.0f + z * (1.0f - s));
-}
-
-// ---------------------------------------------------------------------------
-// FP32 engine pieces
-// ---------------------------------------------------------------------------
-// Layer 1 (2 -> 64) for this lane's 16 neurons [16w, 16w+16) of sample s.
-__device__ __forceinline__ void fwd_first(const float* P, int w, float f1, float f2, float z[16]) {
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        const int j = 16 * w + i;
-        z[i] = fmaf(P[kOffW1 + 2 * j + 1], f2, fmaf(P[kOffW1 + 2 * j], f1, P[kOffB1 + j]));
-    }
-}
-
-// Hidden layer (64 -> 64): z_j = b_j + sum_k W[j][k] h[k], k ascending.
-__device__ __forceinline__ void fwd_hidden(const float* W, const float* b, int w, const float* hrow, float z[16]) {
-#pragma unroll
-    for (int i = 0; i < 16; ++i) z[i] = b[16 * w + i];
-#pragma unroll 4
-    for (int k = 0; k < kMlpHidden; k += 4) {
-        const float4 hv = *(const float4*)(hrow + k);
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            const float* wr = W + (16 * w + i) * kMlpHidden + k;
-            float a = z[i];
-            a = fmaf(wr[0], hv.x, a);
-            a = fmaf(wr[1], hv.y, a);
-            a = fmaf(wr[2], hv.z, a);
-            a = fmaf(wr[3], hv.w, a);
-            z[i] = a;
-        }
-    }
-}
-
-// Output layer (64 -> 2) for one sample, k ascending.
-__device__ __forceinline__ void fwd_out(const float* P, const float* hrow, float& y0, float& y1) {
-    float a0 = P[kOffB5], a1 = P[kOffB5 + 1];
-#pragma unroll 8
-    for (int k = 0; k < kMlpHidden; ++k) {
-        a0 = fmaf(P[kOffW5 + k], hrow[k], a0);
-        a1 = fmaf(P[kOffW5 + kMlpHidden + k], hrow[k], a1);
-    }
-    y0 = a0;
-    y1 = a1;
-}
-
-__device__ __forceinline__ uint32_t float_bits(float f) { return __float_as_uint(f); }
-
-// Forward pass of one FP32 workgroup; the last hidden output ends in H[1]
-// (ping-pong buffers H[0], H[1]).  amax (nullable): running max |h| of the
-// inputs of hidden layers 2..4, as float bits.
-__device__ __forceinline__ void fwd_block_f32(const float* P, float f1, float f2, bool active, float (*H)[kMlpSamples][kRow],
-                                              uint32_t* amax) {
-    const int tid = threadIdx.x;
-    const int w = wave_uniform(tid >> 6);
-    const int s = tid & 63;
-    float z[16];
-    fwd_first(P, w, f1, f2, z);
-    float m = 0.0f;
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        const float h = silu_f32(z[i]);
-        H[0][s][16 * w + i] = h;
-        m = fmaxf(m, fabsf(h));
-    }
-    if (amax && active) atomicMax(&amax[0], float_bits(m));
-    __syncthreads();
-    const float* Ws[3] = {P + kOffW2, P + kOffW3, P + kOffW4};
-    const float* Bs[3] = {P + kOffB2, P + kOffB3, P + kOffB4};
-#pragma unroll 1
-    for (int L = 0; L < 3; ++L) {
-        const int src = L & 1, dst = src ^ 1;
-        fwd_hidden(Ws[L], Bs[L], w, H[src][s], z);
-        __syncthreads();  // all reads of H[src] done before it is overwritten next layer
-        m = 0.0f;
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            const float h = silu_f32(z[i]);
-            H[dst][s][16 * w + i] = h;
-            m = fmaxf(m, fabsf(h));
-        }
-        if (amax && active && L < 2) atomicMax(&amax[L + 1], float_bits(m));
-        __syncthreads();
-    }
 }
 
 struct FwdArgs {
@@ -158,26 +69,6 @@ __device__ __forceinline__ void sampler_out(const FwdArgs& a, int64_t i, float x
         net_out(a, i, x, y0, y1);
     else
         fallback_out(a, i, x, u);
-}
-
-__global__ __launch_bounds__(kMlpThreads) void k_mlp_fwd_f32(const FwdArgs a) {
-    __shared__ float H[2][kMlpSamples][kRow];
-    const int s = threadIdx.x & 63;
-    const int64_t i = (int64_t)blockIdx.x * kMlpSamples + s;
-    const bool active = i < a.n;
-    const float x = active ? a.x[i] : 1.0f, u = active ? a.u[i] : 0.5f;
-    float f1, f2;
-    features(x, u, a.dom, f1, f2);
-    fwd_block_f32(a.P, f1, f2, active, H, a.amax);
-    if (threadIdx.x < 64 && active) {
-        float y0, y1;
-        fwd_out(a.P, H[1][s], y0, y1);
-        if (a.y) {
-            a.y[2 * i] = y0;
-            a.y[2 * i + 1] = y1;
-        }
-        if (a.mu || a.ratio || a.mask) sampler_out(a, i, x, u, y0, y1);
-    }
 }
 
 // ---------------------------------------------------------------------------
@@ -688,6 +579,207 @@ __global__ __launch_bounds__(kMfmaThreads, kMfmaWavesPerSimd) void k_mlp_mfma(co
 }
 
 // ---------------------------------------------------------------------------
+// FP32 inference on MFMA (v_mfma_f32_16x16x4_f32)
+// ---------------------------------------------------------------------------
+// The layout of the reduced-precision engine (lane l owns sample l % 16 and
+// neurons 16t + 4g + r of a 16-sample tile, g = l / 16), with the K index of
+// each layer's contraction permuted so that every lane's B operand is one of
+// its own outputs of the previous layer: k-step (t, r) pairs lane group g
+// with input neuron 16t + 4g + r, so the A operand of lane l at (output tile
+// T, k-step (t, r)) is W[16T + l % 16][16t + 4 (l / 16) + r].  These
+// fragments (3 layers x 4 x 16 x 64 floats, 48 KB) are built in LDS by each
+// workgroup.  SiLU is the correctly rounded FP32 one; the first and last
+// layers run on the vector ALUs as in the other engine.
+constexpr int kF32Frag = 3 * 4 * 16 * 64;
+
+struct F32Lds {
+    float frag[kF32Frag];
+    float P[kSmall];  // W1, b1..b4, W5, b5 (unscaled)
+};
+
+__device__ __forceinline__ void f32_lds_load(F32Lds& s, const float* P) {
+    const int offW[3] = {kOffW2, kOffW3, kOffW4};
+    for (int i = threadIdx.x; i < kF32Frag; i += blockDim.x) {
+        const int l = i & 63, rr = (i >> 6) & 3, t = (i >> 8) & 3, T = (i >> 10) & 3, L = i >> 12;
+        s.frag[i] = P[offW[L] + (16 * T + (l & 15)) * kMlpHidden + 16 * t + 4 * (l >> 4) + rr];
+    }
+    for (int i = threadIdx.x; i < kSmall; i += blockDim.x) {
+        int src;
+        if (i < cB1)
+            src = kOffW1 + i;
+        else if (i < cB2)
+            src = kOffB1 + (i - cB1);
+        else if (i < cB3)
+            src = kOffB2 + (i - cB2);
+        else if (i < cB4)
+            src = kOffB3 + (i - cB3);
+        else if (i < cW5)
+            src = kOffB4 + (i - cB4);
+        else if (i < cB5)
+            src = kOffW5 + (i - cW5);
+        else
+            src = kOffB5 + (i - cB5);
+        s.P[i] = P[src];
+    }
+}
+
+// NTL tiles side by side; amax (nullable): this lane's running max |h| of the
+// inputs of hidden layers 2..4, over the tiles k whose sample is real[k].
+template <int NTL>
+__device__ __forceinline__ void mlp_tiles_f32(const float* frag, const float* Ps, const float (&f1)[NTL],
+                                              const float (&f2)[NTL], float (&y0)[NTL], float (&y1)[NTL],
+                                              float* amax, const bool (&real)[NTL]) {
+    const int lane = lane_id();
+    const int g = lane >> 4;
+    float h[NTL][16];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int n = 16 * t + 4 * g + r;
+            const float w1a = Ps[cW1 + 2 * n], w1b = Ps[cW1 + 2 * n + 1], b1 = Ps[cB1 + n];
+#pragma unroll
+            for (int k = 0; k < NTL; ++k) {
+                h[k][4 * t + r] = silu_f32(fmaf(w1b, f2[k], fmaf(w1a, f1[k], b1)));
+                if (amax && real[k]) amax[0] = fmaxf(amax[0], fabsf(h[k][4 * t + r]));
+            }
+        }
+    const int offB[3] = {cB2, cB3, cB4};
+#pragma unroll
+    for (int L = 0; L < 3; ++L) {
+        float o[NTL][16];
+#pragma unroll
+        for (int T = 0; T < 4; ++T) {
+            floatx4 acc[NTL];
+#pragma unroll
+            for (int k = 0; k < NTL; ++k)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) acc[k][r] = Ps[offB[L] + 16 * T + 4 * g + r];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const float A = frag[((L * 4 + T) * 16 + q) * 64 + lane];
+#pragma unroll
+                for (int k = 0; k < NTL; ++k) acc[k] = __builtin_amdgcn_mfma_f32_16x16x4f32(A, h[k][q], acc[k], 0, 0, 0);
+            }
+#pragma unroll
+            for (int k = 0; k < NTL; ++k)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) o[k][4 * T + r] = silu_f32(acc[k][r]);
+        }
+#pragma unroll
+        for (int k = 0; k < NTL; ++k)
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                h[k][j] = o[k][j];
+                if (amax && L < 2 && real[k]) amax[L + 1] = fmaxf(amax[L + 1], fabsf(o[k][j]));
+            }
+    }
+#pragma unroll
+    for (int k = 0; k < NTL; ++k) {
+        float p0 = 0.0f, p1 = 0.0f;
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int n = 16 * t + 4 * g + r;
+                p0 = fmaf(Ps[cW5 + n], h[k][4 * t + r], p0);
+                p1 = fmaf(Ps[cW5 + kMlpHidden + n], h[k][4 * t + r], p1);
+            }
+        p0 += __shfl_xor(p0, 16, 64);
+        p1 += __shfl_xor(p1, 16, 64);
+        p0 += __shfl_xor(p0, 32, 64);
+        p1 += __shfl_xor(p1, 32, 64);
+        y0[k] = p0 + Ps[cB5];
+        y1[k] = p1 + Ps[cB5 + 1];
+    }
+}
+
+// FP32 forward / sampler / calibration: the walk of k_mlp_mfma (64-sample
+// groups per wave, the out-of-domain samples in a second walk), two tiles
+// side by side.
+__global__ __launch_bounds__(kMfmaThreads, 2) void k_mlp_f32(const FwdArgs a) {
+    __shared__ F32Lds s_net;
+    __shared__ int64_t s_fb[kMfmaThreads / 64][kFbCap];
+    f32_lds_load(s_net, a.P);
+    __syncthreads();
+    const int lane = lane_id();
+    const int wave = wave_uniform((int)threadIdx.x >> 6);
+    const bool sampling = a.mu || a.ratio || a.mask;
+    const int64_t n_groups = (a.n + 63) / 64;
+    const int64_t first = (int64_t)blockIdx.x * (kMfmaThreads / 64) + wave;
+    const int64_t stride = (int64_t)gridDim.x * (kMfmaThreads / 64);
+    float amax[3] = {0.0f, 0.0f, 0.0f};
+    for (int64_t grp = first; grp < n_groups; grp += stride) {
+        const int64_t i = grp * 64 + lane;
+        const bool active = i < a.n;
+        const float x = active ? a.x[i] : 1.0f, u = active ? a.u[i] : 0.5f;
+        float f1, f2;
+        features(x, u, a.dom, f1, f2);
+        int opaque = 0;
+        asm volatile("" : "+s"(opaque));
+        const float* frag = s_net.frag + opaque;
+        const float* Ps = s_net.P + opaque;
+        float o0 = 0.0f, o1 = 0.0f;
+#pragma unroll
+        for (int t0 = 0; t0 < 4; t0 += 2) {
+            float g1[2], g2[2], y0[2], y1[2];
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                const int src = 16 * (t0 + k) + (lane & 15);
+                g1[k] = __shfl(f1, src, 64);
+                g2[k] = __shfl(f2, src, 64);
+            }
+            // calibration counts only the group's real samples: lane (g, li)
+            // of tile t0 + k evaluates sample 16 (t0 + k) + li of the group
+            const bool real[2] = {grp * 64 + 16 * t0 + (lane & 15) < a.n,
+                                  grp * 64 + 16 * (t0 + 1) + (lane & 15) < a.n};
+            mlp_tiles_f32<2>(frag, Ps, g1, g2, y0, y1, a.amax ? amax : nullptr, real);
+#pragma unroll
+            for (int k = 0; k < 2; ++k)
+                if ((lane >> 4) == t0 + k) {
+                    o0 = y0[k];
+                    o1 = y1[k];
+                }
+        }
+        if (active && a.y) *(float2*)(a.y + 2 * i) = make_float2(o0, o1);
+        if (sampling && active && in_range(x, a.dom)) net_out(a, i, x, o0, o1);
+    }
+    if (a.amax) {
+        // non-negative floats order as their bits
+#pragma unroll
+        for (int L = 0; L < 3; ++L) {
+            float wm = amax[L];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) wm = fmaxf(wm, __shfl_xor(wm, off, 64));
+            if (lane == 0) atomicMax(&a.amax[L], __float_as_uint(wm));
+        }
+    }
+    if (!sampling) return;
+    int64_t* fb = s_fb[wave];
+    int nfb = 0;
+    for (int64_t grp = first; grp < n_groups; grp += stride) {
+        const int64_t i = grp * 64 + lane;
+        const bool defer = i < a.n && !in_range(a.x[i], a.dom);
+        const uint64_t msk = __ballot(defer);
+        if (msk == 0) continue;
+        if (defer) fb[nfb + __popcll(msk & ((1ull << lane) - 1ull))] = i;
+        nfb += __popcll(msk);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        if (nfb >= 64) {
+            fallback_pass(a, fb, 64);
+            const int64_t rest = lane < nfb - 64 ? fb[64 + lane] : 0;
+            __builtin_amdgcn_wave_barrier();
+            if (lane < nfb - 64) fb[lane] = rest;
+            nfb -= 64;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+    if (nfb > 0) fallback_pass(a, fb, nfb);
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 // Feature constants of a network's x range (see NetDomain).
@@ -714,7 +806,10 @@ hipError_t launch_mlp_forward(const MlpDev& m, cs_sampler prec, const float* x, 
     if (n <= 0) return hipSuccess;
     FwdArgs a = {m.params, m.dom, x, u, n, y, mu, ratio, mask, nullptr};
     if (prec == CS_SAMPLER_MLP_F32) {
-        k_mlp_fwd_f32<<<(unsigned)((n + kMlpSamples - 1) / kMlpSamples), kMlpThreads, 0, st>>>(a);
+        const int64_t groups = (n + 63) / 64;
+        int64_t blocks = (groups + kMfmaThreads / 64 - 1) / (kMfmaThreads / 64);
+        if (blocks > 1024) blocks = 1024;
+        k_mlp_f32<<<(unsigned)blocks, kMfmaThreads, 0, st>>>(a);
     } else {
         // one 64-sample group per wave and step of the loop; 2048 workgroups
         // (8 per compute unit) cover the chip
@@ -769,7 +864,10 @@ hipError_t launch_mlp_quantize(float* params, const NetDomain& dom, void* frag_b
     } else {
         k_mlp_zero_amax<<<1, 64, 0, st>>>((uint32_t*)scales + 6);
         FwdArgs a = {params, dom, cx, cu, n, nullptr, nullptr, nullptr, nullptr, (uint32_t*)scales + 6};
-        k_mlp_fwd_f32<<<(unsigned)((n + kMlpSamples - 1) / kMlpSamples), kMlpThreads, 0, st>>>(a);
+        const int64_t groups = (n + 63) / 64;
+        int64_t blocks = (groups + kMfmaThreads / 64 - 1) / (kMfmaThreads / 64);
+        if (blocks > 1024) blocks = 1024;
+        k_mlp_f32<<<(unsigned)blocks, kMfmaThreads, 0, st>>>(a);
         k_mlp_act_scale<<<1, 64, 0, st>>>(scales);
         k_mlp_weight_scale<<<3, 256, 0, st>>>(params, scales);
         k_mlp_build_frag<<<nb, 256, 0, st>>>(params, scales, CS_SAMPLER_MLP_FP8, nullptr, (uint8_t*)frag_fp8);
