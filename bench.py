@@ -170,11 +170,14 @@ def binning_stage(ctx, p, reps=20):
 
 
 def ntc_stage(ctx, p, steps=50, warmup=5):
-    """The step with no-time-counter candidate selection (cs_ntc_step) on the
-    same plasma: milliseconds per step by wall clock around the calls (each
-    call synchronises once), candidates and collisions per step, and the
-    workload's 1:1-pairing pair count per second for comparison with the
-    headline (both advance the same plasma by one step)."""
+    """The step with no-time-counter candidate selection on the same plasma:
+    eager cs_ntc_step calls (milliseconds per step by wall clock around the
+    calls; each call waits for the device's candidate count) and replays of
+    a captured step (cs_ntc_graph_create, sized 1.5x the eager count;
+    milliseconds per replay by HIP events on the replay stream), candidates
+    and collisions per step, and the workload's 1:1-pairing pair count per
+    second for comparison with the headline (both advance the same plasma
+    by one step)."""
     import time
 
     import torch
@@ -191,10 +194,31 @@ def ntc_stage(ctx, p, steps=50, warmup=5):
         ctx.ntc_step(e, g, oe, og, p.dt, p.density_norm, p.seed, s, stats=stats)
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / steps
-    st = stats.cpu().numpy()
-    return {"ms_per_step": ms, "candidates_per_step": int(st[0]), "collisions_per_step": int(st[1]),
-            "candidates_per_s": int(st[0]) / (ms * 1e-3), "pairs_equivalent_per_s": p.n_pairs / (ms * 1e-3),
-            "expected_collisions": float(st.view("float64")[8])}
+    st = compton.decode_stats(stats)
+    out = {"ms_per_step": ms, "candidates_per_step": st["n_pairs"], "collisions_per_step": st["n_collided"],
+           "candidates_per_s": st["n_pairs"] / (ms * 1e-3), "pairs_equivalent_per_s": p.n_pairs / (ms * 1e-3),
+           "expected_collisions": st["sum_prob"]}
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        gr = ctx.ntc_graph(e, g, oe, og, p.dt, p.density_norm, p.seed, (3 * st["n_pairs"]) // 2, stats=stats)
+        try:
+            gr.set_step(warmup + steps)
+            for _ in range(warmup):
+                gr.launch()
+            t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            t0.record(stream)
+            for _ in range(steps):
+                gr.launch()
+            t1.record(stream)
+            stream.synchronize()
+            gms = t0.elapsed_time(t1) / steps
+        finally:
+            gr.close()
+    gst = compton.decode_stats(stats)
+    out["graph"] = {"ms_per_step": gms, "candidates_per_step": gst["n_pairs"], "overflow": gst["overflow"],
+                    "pairs_equivalent_per_s": p.n_pairs / (gms * 1e-3)}
+    return out
 
 
 def training_stage(ctx, batch=4096, steps=200):

@@ -95,7 +95,11 @@ typedef struct {
                           /* range, resolved by the plain sampler                */
     int64_t layout_error; /* 1 when the offsets were not a valid layout; then    */
                           /* no particle was touched                             */
-    int64_t reserved_i[2];
+    int64_t overflow;     /* NTC steps only: 1 when the step drew more           */
+                          /* candidates than it can hold (2^31 - 2, or a NTC     */
+                          /* graph's capacity); then no particle was touched and */
+                          /* n_pairs holds the count (at most 2^31 - 1)          */
+    int64_t reserved_i;
     double sum_prob;      /* sum of P over valid pairs (fixed summation order)   */
     double energy_before; /* sum over collided pairs of gamma + eps before       */
     double energy_after;  /* ... and gamma' + eps' after (pre-storage rounding)  */
@@ -206,14 +210,19 @@ CS_API cs_status cs_check_layout(cs_ctx* ctx, const int64_t* off, int64_t n_cell
  * sum of P / P_max over valid candidates (the expected collision count),
  * energy sums as cs_compton_step.
  *
- * The call synchronises `stream` once (the host needs the step's candidate
- * count to size the launches) and keeps scratch in the context: about
- * 60 bytes per candidate, 300 per cell, and 32 per particle (tags that
- * persist across calls).
+ * The call queues the whole step, then waits until the step's candidate
+ * count is known on the device (the rest of the step runs meanwhile): the
+ * launches are sized for the context's candidate capacity, and a step that
+ * draws more candidates than that changes nothing, so the call grows the
+ * capacity and queues the step again (this happens on the first call and
+ * whenever the count grows past the capacity, which is then set 25% above
+ * the count).  The context keeps the scratch: about 60 bytes per candidate
+ * of capacity, 300 per cell, and 32 per particle (tags that persist
+ * across calls).
  * Errors: CS_ERR_INVALID_ARG (NULL arrays with n > 0, NULL offsets,
  *         n_cells >= 2^31 - 1, dt <= 0 or non-finite, density_norm < 0),
  *         CS_ERR_UNSUPPORTED (a species count >= 2^31, or 2^31 - 1 or more
- *         candidates in the step; nothing was changed),
+ *         candidates in the step; nothing was changed, stats->overflow = 1),
  *         CS_ERR_LAYOUT (offsets not a valid layout; nothing was changed,
  *         stats->layout_error = 1).
  */
@@ -472,6 +481,20 @@ CS_API cs_status cs_graph_create(cs_ctx* ctx, cs_dtype dtype, cs_species electro
                           const int64_t* cell_off_e, const int64_t* cell_off_g, int64_t n_cells, double dt,
                           double density_norm, uint64_t seed, cs_sampler sampler, const cs_mlp* mlp,
                           cs_stats* stats, void* stream, cs_graph** out);
+/* Capture one cs_ntc_step with these arguments into a HIP graph, for callers
+ * that replay the NTC step without host involvement.  The graph's launches
+ * are sized for `max_candidates` candidates per step (1 <= max_candidates <=
+ * 2^31 - 2; about 60 bytes of device memory each, owned by the graph); a
+ * replay whose step draws more changes no particle and writes a stats
+ * record with overflow = 1 and n_pairs = its candidate count.  The step
+ * index works as for cs_graph_create (cs_graph_set_step, advanced by each
+ * replay); cs_graph_launch and cs_graph_destroy apply.  Errors as
+ * cs_ntc_step's argument checks, CS_ERR_LAYOUT for particles without
+ * cells; a bad device layout shows only in the stats record. */
+CS_API cs_status cs_ntc_graph_create(cs_ctx* ctx, cs_dtype dtype, cs_species electrons, cs_species photons,
+                                     const int64_t* cell_off_e, const int64_t* cell_off_g, int64_t n_cells,
+                                     double dt, double density_norm, uint64_t seed, int64_t max_candidates,
+                                     cs_stats* stats, void* stream, cs_graph** out);
 /* Queue the step index of the next replay on `stream`. */
 CS_API cs_status cs_graph_set_step(cs_graph* graph, uint64_t step, void* stream);
 /* Queue one replay (one step) on `stream`. */

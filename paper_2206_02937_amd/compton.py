@@ -42,7 +42,7 @@ class TuneResult(C.Structure):
 
 
 STAGES = ["prep", "pair", "compact", "collide", "finalize"]
-STATS_INT = ["n_pairs", "n_collided", "n_clipped", "n_invalid", "n_fallback", "layout_error"]
+STATS_INT = ["n_pairs", "n_collided", "n_clipped", "n_invalid", "n_fallback", "layout_error", "overflow"]
 STATS_DBL = ["sum_prob", "energy_before", "energy_after"]
 STATS_BYTES = 128
 
@@ -107,6 +107,9 @@ def lib():
     L.cs_graph_create.argtypes = [vp, C.c_int, Species, Species, vp, vp, i64, d, d, u64, C.c_int, vp, vp, vp,
                                   C.POINTER(vp)]
     L.cs_graph_create.restype = st
+    L.cs_ntc_graph_create.argtypes = [vp, C.c_int, Species, Species, vp, vp, i64, d, d, u64, i64, vp, vp,
+                                      C.POINTER(vp)]
+    L.cs_ntc_graph_create.restype = st
     L.cs_graph_set_step.argtypes = [vp, u64, vp]
     L.cs_graph_set_step.restype = st
     L.cs_graph_launch.argtypes = [vp, vp]
@@ -241,7 +244,8 @@ class Context:
 
     def ntc_step(self, e, g, off_e, off_g, dt, density_norm, seed, step, stats=None, stream=None):
         """One Compton step with no-time-counter candidate selection, in place
-        on device tensors (the layout of step); synchronises the stream once."""
+        on device tensors (the layout of step); queues the whole step, then
+        waits for the device's candidate count."""
         code = _dtype_code(e["x"])
         rc = lib().cs_ntc_step(self._h, code, _species(e), _species(g), _ptr(off_e), _ptr(off_g),
                                off_e.numel() - 1, float(dt), float(density_norm), int(seed), int(step), _ptr(stats),
@@ -304,6 +308,13 @@ class Context:
               stream=None):
         """Capture one step into a replayable graph (see Graph)."""
         return Graph(self, e, g, off_e, off_g, dt, density_norm, seed, sampler, mlp, stats, stream)
+
+    def ntc_graph(self, e, g, off_e, off_g, dt, density_norm, seed, max_candidates, stats=None, stream=None):
+        """Capture one NTC step (cs_ntc_graph_create) sized for max_candidates
+        candidates per step; a replay that draws more changes nothing and sets
+        stats' overflow word (see Graph)."""
+        return Graph(self, e, g, off_e, off_g, dt, density_norm, seed, "plain", None, stats, stream,
+                     ntc_max_candidates=max_candidates)
 
     def bin_particles(self, cell, species, n_cells, out=None, off=None, n_invalid=None, stream=None):
         """Group one species by cell (cs_bin_particles).  cell: int32 device
@@ -383,17 +394,24 @@ class Graph:
     stay alive (and in place) while the graph is used; the stream must not be
     the legacy default stream."""
 
-    def __init__(self, ctx, e, g, off_e, off_g, dt, density_norm, seed, sampler, mlp, stats, stream):
+    def __init__(self, ctx, e, g, off_e, off_g, dt, density_norm, seed, sampler, mlp, stats, stream,
+                 ntc_max_candidates=None):
         import torch
 
         self.ctx = ctx
         self.stream = torch.cuda.current_stream() if stream is None else stream
         self._keep = (e, g, off_e, off_g, stats, mlp)
         self._h = C.c_void_p()
-        rc = lib().cs_graph_create(ctx.handle, _dtype_code(e["x"]), _species(e), _species(g), _ptr(off_e),
-                                   _ptr(off_g), off_e.numel() - 1, float(dt), float(density_norm), int(seed),
-                                   SAMPLERS[sampler], None if mlp is None else mlp.handle, _ptr(stats),
-                                   C.c_void_p(self.stream.cuda_stream), C.byref(self._h))
+        if ntc_max_candidates is None:
+            rc = lib().cs_graph_create(ctx.handle, _dtype_code(e["x"]), _species(e), _species(g), _ptr(off_e),
+                                       _ptr(off_g), off_e.numel() - 1, float(dt), float(density_norm), int(seed),
+                                       SAMPLERS[sampler], None if mlp is None else mlp.handle, _ptr(stats),
+                                       C.c_void_p(self.stream.cuda_stream), C.byref(self._h))
+        else:
+            rc = lib().cs_ntc_graph_create(ctx.handle, _dtype_code(e["x"]), _species(e), _species(g), _ptr(off_e),
+                                           _ptr(off_g), off_e.numel() - 1, float(dt), float(density_norm),
+                                           int(seed), int(ntc_max_candidates), _ptr(stats),
+                                           C.c_void_p(self.stream.cuda_stream), C.byref(self._h))
         ctx._check(rc)
 
     def set_step(self, step):

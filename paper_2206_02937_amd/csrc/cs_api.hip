@@ -423,6 +423,8 @@ struct cs_graph {
     cs_ctx* ctx = nullptr;
     int device = 0;
     cs::Workspace ws;  // the graph's own workspace (control block, step counter)
+    bool is_ntc = false;
+    cs::NtcState ntc;  // an NTC graph's own scratch (step word in its head)
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
@@ -447,6 +449,7 @@ void free_graph(cs_graph* g) {
     if (g->exec) (void)hipGraphExecDestroy(g->exec);
     if (g->graph) (void)hipGraphDestroy(g->graph);
     if (g->ws.base) (void)hipFree(g->ws.base);
+    cs::ntc_free(g->ntc);
     delete g;
 }
 
@@ -503,11 +506,70 @@ cs_status cs_graph_create(cs_ctx* ctx, cs_dtype dtype, cs_species electrons, cs_
     return CS_OK;
 }
 
+static cs_status validate_ntc(cs_ctx* ctx, cs_dtype dtype, const cs_species& electrons, const cs_species& photons,
+                              const int64_t* off_e, const int64_t* off_g, int64_t n_cells, double dt,
+                              double density_norm, const char* what);
+
+cs_status cs_ntc_graph_create(cs_ctx* ctx, cs_dtype dtype, cs_species electrons, cs_species photons,
+                              const int64_t* off_e, const int64_t* off_g, int64_t n_cells, double dt,
+                              double density_norm, uint64_t seed, int64_t max_candidates, cs_stats* stats,
+                              void* stream, cs_graph** out) {
+    if (!ctx) return CS_ERR_INVALID_ARG;
+    if (!out) return fail(ctx, CS_ERR_INVALID_ARG, "cs_ntc_graph_create: out is NULL");
+    *out = nullptr;
+    if (!stream)
+        return fail(ctx, CS_ERR_INVALID_ARG, "cs_ntc_graph_create: the legacy (NULL) stream cannot be captured");
+    cs_status s = validate_ntc(ctx, dtype, electrons, photons, off_e, off_g, n_cells, dt, density_norm,
+                               "cs_ntc_graph_create");
+    if (s != CS_OK) return s;
+    if (max_candidates < 1 || max_candidates > ((int64_t)1 << 31) - 2)
+        return fail(ctx, CS_ERR_INVALID_ARG, "cs_ntc_graph_create: max_candidates must be in [1, 2^31 - 2]");
+    if (n_cells == 0 && (electrons.n != 0 || photons.n != 0))
+        return fail(ctx, CS_ERR_LAYOUT, "cs_ntc_graph_create: particles but no cells");
+    DeviceGuard dg(ctx->device);
+    hipStream_t st = (hipStream_t)stream;
+    cs_graph* g = new (std::nothrow) cs_graph();
+    if (!g) return fail(ctx, CS_ERR_INVALID_ARG, "cs_ntc_graph_create: out of host memory");
+    g->ctx = ctx;
+    g->device = ctx->device;
+    g->is_ntc = true;
+    hipError_t e = cs::ntc_prepare_graph(g->ntc, n_cells, max_candidates, electrons.n, photons.n, st);
+    if (e != hipSuccess) {
+        free_graph(g);
+        return hip_fail(ctx, e, "cs_ntc_graph_create: scratch");
+    }
+    e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        free_graph(g);
+        return hip_fail(ctx, e, "cs_ntc_graph_create: hipStreamBeginCapture");
+    }
+    const hipError_t le =
+        cs::ntc_capture(g->ntc, dtype, electrons, photons, off_e, off_g, n_cells, dt, density_norm, seed, stats, st);
+    e = hipStreamEndCapture(st, &g->graph);
+    if (le != hipSuccess || e != hipSuccess) {
+        free_graph(g);
+        return hip_fail(ctx, le != hipSuccess ? le : e, "cs_ntc_graph_create: capture");
+    }
+    e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        free_graph(g);
+        return hip_fail(ctx, e, "cs_ntc_graph_create: hipGraphInstantiate");
+    }
+    *out = g;
+    ctx->last_error.clear();
+    return CS_OK;
+}
+
 cs_status cs_graph_set_step(cs_graph* g, uint64_t step, void* stream) {
     if (!g) return CS_ERR_INVALID_ARG;
     DeviceGuard dg(g->device);
-    k_set_step<<<1, 64, 0, (hipStream_t)stream>>>(cs::ws_control(g->ws), step);
-    const hipError_t e = hipGetLastError();
+    hipError_t e = hipSuccess;
+    if (g->is_ntc) {
+        e = cs::ntc_set_step(g->ntc, step, (hipStream_t)stream);
+    } else {
+        k_set_step<<<1, 64, 0, (hipStream_t)stream>>>(cs::ws_control(g->ws), step);
+        e = hipGetLastError();
+    }
     return e == hipSuccess ? CS_OK : hip_fail(g->ctx, e, "cs_graph_set_step");
 }
 
@@ -826,22 +888,30 @@ cs_status cs_bin_particles(cs_ctx* ctx, cs_dtype dtype, const int32_t* cell, cs_
     return CS_OK;
 }
 
-// Grow a context scratch buffer to `want` bytes (synchronises `stream` first
-// so that no queued kernel still uses the old one).
+static cs_status validate_ntc(cs_ctx* ctx, cs_dtype dtype, const cs_species& electrons, const cs_species& photons,
+                              const int64_t* off_e, const int64_t* off_g, int64_t n_cells, double dt,
+                              double density_norm, const char* what) {
+    const std::string w(what);
+    if (dtype != CS_F32 && dtype != CS_F64) return fail(ctx, CS_ERR_INVALID_ARG, w + ": bad dtype");
+    if (electrons.n < 0 || photons.n < 0 || n_cells < 0 || n_cells >= ((int64_t)1 << 31) - 1)
+        return fail(ctx, CS_ERR_INVALID_ARG, w + ": negative size or n_cells >= 2^31 - 1");
+    if (electrons.n >= ((int64_t)1 << 31) || photons.n >= ((int64_t)1 << 31))
+        return fail(ctx, CS_ERR_UNSUPPORTED, w + ": a species count >= 2^31");
+    if ((electrons.n > 0 && (!electrons.x || !electrons.y || !electrons.z || !electrons.w)) ||
+        (photons.n > 0 && (!photons.x || !photons.y || !photons.z || !photons.w)) || !off_e || !off_g)
+        return fail(ctx, CS_ERR_INVALID_ARG, w + ": NULL array");
+    if (!(dt > 0.0) || !std::isfinite(dt) || !(density_norm >= 0.0) || !std::isfinite(density_norm))
+        return fail(ctx, CS_ERR_INVALID_ARG, w + ": need finite dt > 0 and density_norm >= 0");
+    return CS_OK;
+}
+
 cs_status cs_ntc_step(cs_ctx* ctx, cs_dtype dtype, cs_species electrons, cs_species photons, const int64_t* off_e,
                       const int64_t* off_g, int64_t n_cells, double dt, double density_norm, uint64_t seed,
                       uint64_t step, cs_stats* stats, void* stream) {
     if (!ctx) return CS_ERR_INVALID_ARG;
-    if (dtype != CS_F32 && dtype != CS_F64) return fail(ctx, CS_ERR_INVALID_ARG, "cs_ntc_step: bad dtype");
-    if (electrons.n < 0 || photons.n < 0 || n_cells < 0 || n_cells >= ((int64_t)1 << 31) - 1)
-        return fail(ctx, CS_ERR_INVALID_ARG, "cs_ntc_step: negative size or n_cells >= 2^31 - 1");
-    if (electrons.n >= ((int64_t)1 << 31) || photons.n >= ((int64_t)1 << 31))
-        return fail(ctx, CS_ERR_UNSUPPORTED, "cs_ntc_step: a species count >= 2^31");
-    if ((electrons.n > 0 && (!electrons.x || !electrons.y || !electrons.z || !electrons.w)) ||
-        (photons.n > 0 && (!photons.x || !photons.y || !photons.z || !photons.w)) || !off_e || !off_g)
-        return fail(ctx, CS_ERR_INVALID_ARG, "cs_ntc_step: NULL array");
-    if (!(dt > 0.0) || !std::isfinite(dt) || !(density_norm >= 0.0) || !std::isfinite(density_norm))
-        return fail(ctx, CS_ERR_INVALID_ARG, "cs_ntc_step: need finite dt > 0 and density_norm >= 0");
+    const cs_status vs =
+        validate_ntc(ctx, dtype, electrons, photons, off_e, off_g, n_cells, dt, density_norm, "cs_ntc_step");
+    if (vs != CS_OK) return vs;
     DeviceGuard g(ctx->device);
     hipStream_t st = (hipStream_t)stream;
     cs::NtcOutcome out = cs::NtcOutcome::kOk;
@@ -855,6 +925,8 @@ cs_status cs_ntc_step(cs_ctx* ctx, cs_dtype dtype, cs_species electrons, cs_spec
     return CS_OK;
 }
 
+// Grow a context scratch buffer to `want` bytes (synchronises `stream` first
+// so that no queued kernel still uses the old one).
 static cs_status grow_scratch(cs_ctx* ctx, void** buf, size_t* bytes, size_t want, hipStream_t st,
                               const char* what) {
     if (*bytes >= want) return CS_OK;

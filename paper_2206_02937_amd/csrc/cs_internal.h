@@ -203,22 +203,32 @@ hipError_t launch_sample_plain(cs_dtype dtype, const void* x, const void* u, int
 // and the launch (in/out: x, y, z, w arrays of the dtype)
 size_t bin_workspace_bytes(int64_t n);
 // no-time-counter step (cs_ntc.hip): device scratch and the pinned read-back
-// kept by the context between calls; the touch words (two sets of one
-// 64-bit word per electron and per photon) keep their tags across steps.
+// kept by the context (or a graph) between calls; the touch words (two sets
+// of one 64-bit word per electron and per photon) keep their tags across
+// steps, with the tag epoch and the replay step index in a head before them.
 struct NtcState {
     void* cell_ws = nullptr;
     size_t cell_bytes = 0;
     void* cand_ws = nullptr;
     size_t cand_bytes = 0;
+    int64_t cand_cap = 0;  // candidates the per-candidate launches are sized for
     void* touch = nullptr;
     int64_t cap_e = 0, cap_g = 0;
-    uint32_t epoch = 1;
     void* host = nullptr;
+    hipEvent_t ev = nullptr;
 };
 enum class NtcOutcome { kOk, kLayout, kTooMany };
 hipError_t ntc_step(NtcState& s, cs_dtype dtype, const cs_species& e, const cs_species& g, const int64_t* off_e,
                     const int64_t* off_g, int64_t n_cells, double dt, double dn, uint64_t seed, uint64_t step,
                     cs_stats* stats, hipStream_t st, NtcOutcome* out);
+// graphs: scratch for `cap` candidates (zeroed; synchronises st), the
+// capturable launch sequence (step index from the device word), and the
+// queued write of that word
+hipError_t ntc_prepare_graph(NtcState& s, int64_t n_cells, int64_t cap, int64_t ne, int64_t ng, hipStream_t st);
+hipError_t ntc_capture(const NtcState& s, cs_dtype dtype, const cs_species& e, const cs_species& g,
+                       const int64_t* off_e, const int64_t* off_g, int64_t n_cells, double dt, double dn,
+                       uint64_t seed, cs_stats* stats, hipStream_t st);
+hipError_t ntc_set_step(const NtcState& s, uint64_t step, hipStream_t st);
 void ntc_free(NtcState& s);
 // probability network (cs_pnet.hip)
 size_t pnet_workspace_bytes(int64_t n);

@@ -16,35 +16,50 @@
 // shares a particle with it gives the sequential result.  Rounds:
 //   k_ntc_count    one wave per cell: W (wave max), P_max, the count
 //   k_ntc_scan_*   candidate offsets (int64 exclusive scan over cells, the
-//                  block offsets added by k_ntc_pick); the
-//                  host reads the total (one stream synchronisation)
-//   k_ntc_pick     one wave per cell: its candidates' electrons and
-//                  photons.  A cell of at most 64 candidates is settled in
-//                  the wave: candidates sharing no particle with an earlier
-//                  one are evaluated (probability, accept) and the accepted
-//                  ones listed; the others register for round 1 in the
+//                  block offsets added by k_ntc_pick) and the total, which
+//                  stays on the device: the per-candidate launches are
+//                  sized for a capacity fixed before the step (the context's
+//                  grown capacity, or a graph's) and their workgroups past
+//                  the total return at once; a step whose total exceeds the
+//                  capacity changes nothing and flags its stats record
+//   k_ntc_pick     one wave per cell: its candidates' electrons, photons
+//                  and acceptance uniforms.  In a cell of at most 64
+//                  candidates, those that share no particle with an earlier
+//                  one are ready; the others register for round 1 in the
 //                  particles' "first toucher" words (atomicMax of (round
 //                  tag << 32 | ~candidate): each word ends up holding the
-//                  earliest candidate that touches the particle).  Larger
-//                  cells register every candidate for round 0.
-//   k_ntc_collide_list  the listed accepted candidates, one per lane:
-//                  scattering and write-back (listing them first keeps the
-//                  long collision path off the lanes that only evaluate)
-//   k_ntc_round t  per unresolved candidate: ready when it is the earliest
-//                  unresolved toucher of both its particles; ready ones are
-//                  evaluated; round 0 (run only when a cell has more than
-//                  64 candidates) lists its accepted ones for the dense
-//                  collide, later rounds, with few candidates left, collide
-//                  them in place; the others register for round t + 1 in
+//                  earliest candidate that touches the particle).  Every
+//                  candidate of a larger cell registers for round 0.
+//   k_ntc_eval     round 0, one lane per candidate, one workgroup per
+//                  segment of 1024 candidates (so the FP64 evaluation runs
+//                  on full waves, not on a cell's few dozen lanes): ready
+//                  candidates (a large cell's when it is the earliest
+//                  registered toucher of both its particles) are evaluated
+//                  (probability, accept); the accepted ones are compacted
+//                  into the segment's collide list, the deferred ones (the
+//                  large cells' others register for round 1 here) into its
+//                  round-1 list
+//   k_ntc_collide_list  round 0's accepted candidates, one per lane:
+//                  scattering and write-back
+//   k_ntc_round t  rounds 1 and 2 over the segments' lists: ready
+//                  candidates are evaluated and, when accepted, collide in
+//                  place (few are left); the others register for round 2 in
 //                  the other word set (two sets alternate, so a round never
-//                  reads a word that the same round writes); after the last
-//                  round they mark their cell
+//                  reads a word that the same round writes) and go to the
+//                  segment's round-2 list or, after round 2, mark their cell
 //   k_ntc_serial   one wave per marked cell; its lane 0 resolves the
 //                  cell's remaining candidates in order (long chains: a
 //                  cell with one electron and many candidates)
 //   k_ntc_reduce / k_ntc_final  fixed-order sums into cs_stats
-// Tags grow by one per round and never repeat (a per-context epoch), so the
-// touch words are never cleared between steps.
+// Compaction stays inside a workgroup (a prefix over its waves' ballots):
+// no counter is shared between workgroups, and waves past a segment's list
+// length return at once, so the waves that work are nearly full.
+// Tags grow by one per round and never repeat (an epoch kept on the device
+// beside the touch words and advanced by the last kernel of each step), so
+// the touch words are cleared only when the epoch would wrap.  No kernel
+// depends on a value read back by the host, so a step can be captured in a
+// HIP graph; the step index then comes from a device word that each replay
+// advances.
 //
 // Random numbers: Philox4x32-10 as elsewhere; the count from
 // (cell, kNtcCount), candidate l of cell c from index (c << 32) | l with
@@ -60,23 +75,43 @@
 namespace cs {
 
 constexpr int kNtcThreads = 256;
-constexpr int kNtcRounds = 3;
+constexpr int kNtcRounds = 3;  // round 0 (k_ntc_eval), rounds 1 and 2 (k_ntc_round)
 constexpr int kNtcScanPer = 4;                              // cells per thread in the scan
 constexpr int kNtcScanBlock = kNtcThreads * kNtcScanPer;   // cells per scan workgroup
 constexpr int kNtcRedPer = 2;                               // candidates per thread in the reduction
 constexpr int64_t kNtcMaxCand = 2147483647;                 // candidates per step: below 2^31 - 1
 
-// Control words of a step: flags and the total for the host, the list
-// counts of the rounds.  Zero at the start of every step: zeroed when
-// allocated and by k_ntc_final at the end of the previous step (they sit at
-// the start of the per-cell scratch, whatever the cell count).
+// Control words of a step: the candidate total and flags.  Zero at the
+// start of every step: zeroed when allocated and by k_ntc_final at the end
+// of the previous step (they sit at the start of the per-cell scratch,
+// whatever the cell count).
 struct NtcCtl {
     long long total;
     int32_t layout_bad;
-    int32_t too_many;
-    int32_t has_large;  // a cell with more than 64 candidates
+    int32_t too_many;   // 2^31 - 1 or more candidates
+    int32_t overflow;   // more candidates than the launches were sized for
+    int32_t go;         // none of the above: the step proceeds
     int32_t pad;
 };
+// Status bits before a candidate is resolved (bit 0 clear): registered for
+// round 0 (a candidate of a cell with more than 64), or for round 1 (a
+// small cell's candidate that shares a particle with an earlier one).
+constexpr uint8_t kNtcLarge = 16;
+constexpr uint8_t kNtcLater = 32;
+// Candidates per segment: the evaluation kernel takes one segment per
+// workgroup and compacts the segment's accepted candidates and the ones left
+// for round 1 into the segment's part of two lists (no global counters).
+constexpr int kNtcSeg = 1024;
+constexpr int kNtcSub = kNtcSeg / kNtcThreads;  // collide and round workgroups per segment
+
+// Persistent words at the start of the touch-word allocation (zeroed with
+// the words): the tag epoch and the step index of graph replays.
+struct NtcHead {
+    uint32_t epoch;
+    uint32_t pad;
+    uint64_t step;
+};
+constexpr size_t kNtcHeadBytes = 256;
 
 struct NtcPart {
     double prob, eb, ea;
@@ -87,10 +122,14 @@ template <typename T>
 struct NtcArgs {
     Particles<T> pt;
     const int64_t *off_e, *off_g;
-    int64_t n_cells, total;
+    int64_t n_cells;
+    int64_t total;   // filled on the device by ntc_live
     double dt, dn;
-    uint64_t seed, step;
-    uint32_t epoch;
+    uint64_t seed, step;  // step: the host's, or the device word's (dev_step)
+    uint32_t epoch;       // filled on the device by ntc_live
+    int32_t dev_step;
+    const NtcCtl* ctl;
+    const NtcHead* head;
     const int64_t* cand_off;  // [n_cells + 1] prefixes within each scan block
     int64_t* cand_full;       // [n_cells + 1] candidate offsets (written by k_ntc_pick)
     const double* p_max;      // [n_cells]
@@ -102,11 +141,24 @@ struct NtcArgs {
     unsigned long long *touch_e, *touch_g;  // [2][cap_e], [2][cap_g]
     int64_t cap_e, cap_g;
     uint8_t* pending;    // [n_cells]
-    int32_t* list;       // round 0's accepted candidates, a 256-entry segment per round workgroup
-    int32_t* seg_cnt;    // [round workgroups]: entries of each segment
-    int64_t list_len, n_round_blocks;
-    int32_t *pick_list, *pick_cnt;  // accepted candidates of the pick kernel: 256 per pick workgroup
+    // per segment of kNtcSeg candidates: round 0's accepted candidates and
+    // round 1's list (kNtcSeg entries each) with their lengths; round 2's
+    // list in chunks of kNtcThreads (kNtcSub per segment) with theirs
+    int32_t *lst_c, *lst_1, *lst_2;
+    int32_t *cnt_c, *cnt_1, *cnt_2;
+    int64_t n_seg;  // segments of the capacity
 };
+
+// The step's values that live on the device: the candidate total, the tag
+// epoch and (graph replays) the step index.
+template <typename T>
+__device__ __forceinline__ NtcArgs<T> ntc_live(const NtcArgs<T>& in) {
+    NtcArgs<T> a = in;
+    a.total = in.ctl->total;
+    a.epoch = in.head->epoch;
+    if (in.dev_step) a.step = in.head->step;
+    return a;
+}
 
 __device__ __forceinline__ unsigned long long ntc_tag(uint32_t round_tag, int64_t j) {
     return ((unsigned long long)round_tag << 32) | (unsigned long long)(0xFFFFFFFFu - (uint32_t)j);
@@ -116,11 +168,13 @@ template <typename T>
 __global__ __launch_bounds__(kNtcThreads) void k_ntc_count(const T* ew, const T* gw, const int64_t* off_e,
                                                          const int64_t* off_g, int64_t n_cells, int64_t ne,
                                                          int64_t ng, double dt, double dn, uint64_t seed,
-                                                         uint64_t step, int64_t* count, double* p_max,
-                                                         uint8_t* pending, NtcCtl* ctl) {
+                                                         uint64_t step_host, const NtcHead* head, int dev_step,
+                                                         int64_t* count, double* p_max, uint8_t* pending,
+                                                         NtcCtl* ctl) {
     const int lane = lane_id();
     const int64_t c = (int64_t)blockIdx.x * (kNtcThreads / 64) + (threadIdx.x >> 6);
     if (c >= n_cells) return;
+    const uint64_t step = dev_step ? head->step : step_host;
     if (lane == 0) pending[c] = 0;
     const int64_t e0 = off_e[c], e1 = off_e[c + 1], g0 = off_g[c], g1 = off_g[c + 1];
     const bool bad = e0 < 0 || e1 < e0 || e1 > ne || g0 < 0 || g1 < g0 || g1 > ng ||
@@ -176,7 +230,6 @@ __global__ __launch_bounds__(kNtcThreads) void k_ntc_count(const T* ew, const T*
                 const double fl = floor(n_exp);
                 const u32x4 r = draw(seed, (uint64_t)c, step, kNtcCount);
                 n = (int64_t)fl + (uniform53(r.a, r.b) < n_exp - fl ? 1 : 0);
-                if (n > 64) ctl->has_large = 1;
             }
         }
         count[c] = n;
@@ -233,9 +286,14 @@ __global__ __launch_bounds__(kNtcThreads) void k_ntc_scan_local(const int64_t* c
     if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
 }
 
-// One workgroup: exclusive scan of the block sums (in place), the total.
+// One workgroup: exclusive scan of the block sums (in place), the total, and
+// whether the step proceeds (a valid layout, fewer than 2^31 - 1
+// candidates, at most `cap` of them).  When the tag epoch is about to wrap,
+// the touch words are cleared and the epoch restarts at 0.
 __global__ __launch_bounds__(kNtcThreads) void k_ntc_scan_top(long long* bsum, int64_t n_blocks, int64_t n_cells,
-                                                            int64_t* cand_off, NtcCtl* ctl) {
+                                                            int64_t* cand_off, int64_t cap, NtcCtl* ctl,
+                                                            NtcHead* head, unsigned long long* touch,
+                                                            int64_t n_touch) {
     __shared__ long long s[kNtcThreads / 64];
     long long carry = 0;
     for (int64_t b0 = 0; b0 < n_blocks; b0 += kNtcThreads) {
@@ -246,90 +304,103 @@ __global__ __launch_bounds__(kNtcThreads) void k_ntc_scan_top(long long* bsum, i
         if (b < n_blocks) bsum[b] = carry + ex;
         carry += tot;
     }
+    const bool wrap = head->epoch > 0xFFFFFFFFu - 2 * kNtcRounds;  // (uniform)
+    if (wrap) {
+        for (int64_t i = threadIdx.x; i < n_touch; i += kNtcThreads) touch[i] = 0ull;
+        __syncthreads();  // every thread has read the epoch
+    }
     if (threadIdx.x == 0) {
+        if (wrap) head->epoch = 0;
         cand_off[n_cells] = carry;
         ctl->total = carry;
-        if (carry >= kNtcMaxCand) ctl->too_many = 1;
+        int32_t too_many = ctl->too_many;
+        if (carry >= kNtcMaxCand) too_many = 1;
+        const int32_t overflow = carry > cap ? 1 : 0;
+        ctl->too_many = too_many;
+        ctl->overflow = overflow;
+        ctl->go = (ctl->layout_bad | too_many | overflow) ? 0 : 1;
     }
 }
 
-// One wave per cell: the cell's candidates, 64 at a time.  A cell of at most
-// 64 candidates is settled in the wave: a candidate that shares no particle
-// with an earlier one of its cell is ready, and is evaluated here (the
-// accepted ones listed in the workgroup's segment for the dense collide);
-// the others register for round 1.  Larger cells register every candidate
-// for round 0.
-template <typename T>
-__device__ __forceinline__ bool ntc_evaluate(const NtcArgs<T>& a, int64_t j, int32_t c, int32_t ie, int32_t ig);
-
-template <typename T>
-__global__ __launch_bounds__(kNtcThreads) void k_ntc_pick(const NtcArgs<T> a) {
-    __shared__ int s_cnt[kNtcThreads / 64];
+// Compaction inside a workgroup of THREADS threads: the position of this
+// thread among those with `take` set (in thread order) and their number.
+template <int THREADS>
+__device__ __forceinline__ int compact_slot(bool take, int* lds, int* total) {
     const int lane = lane_id(), wave = threadIdx.x >> 6;
-    const int64_t c = (int64_t)blockIdx.x * (kNtcThreads / 64) + wave;
-    bool acc = false;
-    int64_t j_acc = 0;
-    if (c < a.n_cells) {
-        // cand_off holds prefixes within each scan block: add the block offsets,
-        // and keep the full offsets for the serial pass
-        const int64_t j0 = a.cand_off[c] + a.boff[c / kNtcScanBlock];
-        const int64_t j1 = c + 1 < a.n_cells ? a.cand_off[c + 1] + a.boff[(c + 1) / kNtcScanBlock] : a.total;
-        if (lane == 0) {
-            a.cand_full[c] = j0;
-            if (c + 1 == a.n_cells) a.cand_full[c + 1] = j1;
-        }
-        const int64_t e0 = a.off_e[c], g0 = a.off_g[c];
-        const uint64_t nec = (uint64_t)(a.off_e[c + 1] - e0), ngc = (uint64_t)(a.off_g[c + 1] - g0);
-        const bool small = j1 - j0 <= 64;
-        for (int64_t jb = j0; jb < j1; jb += 64) {
-            const int64_t j = jb + lane;
-            const bool act = j < j1;
-            int32_t ie = -1, ig = -1;
-            if (act) {
-                const u32x4 r = draw(a.seed, ((uint64_t)c << 32) | (uint64_t)(j - j0), a.step, kNtcPick);
-                ie = (int32_t)(e0 + (int64_t)(((uint64_t)r.a * nec) >> 32));
-                ig = (int32_t)(g0 + (int64_t)(((uint64_t)r.b * ngc) >> 32));
-                a.c_local[j] = (int32_t)(j - j0);
-                a.c_u[j] = uniform53(r.c, r.d);
-                a.c_ie[j] = ie;
-                a.c_ig[j] = ig;
-                a.c_cell[j] = (int32_t)c;
-                a.status[j] = 0;
-            }
-            if (small) {
-                const int n = (int)(j1 - j0);
-                bool conflict = false;
-                for (int m = 0; m < n; ++m) {
-                    const int32_t ie_m = __shfl(ie, m, 64), ig_m = __shfl(ig, m, 64);
-                    conflict = conflict || (m < lane && (ie_m == ie || ig_m == ig));
-                }
-                if (act && !conflict) {
-                    acc = ntc_evaluate<T>(a, j, (int32_t)c, ie, ig);
-                    j_acc = j;
-                } else if (act) {
-                    const unsigned long long tag = ntc_tag(a.epoch + 1u, j);
-                    atomicMax(a.touch_e + a.cap_e + ie, tag);
-                    atomicMax(a.touch_g + a.cap_g + ig, tag);
-                }
-            } else if (act) {
-                const unsigned long long tag = ntc_tag(a.epoch, j);
-                atomicMax(a.touch_e + ie, tag);
-                atomicMax(a.touch_g + ig, tag);
-            }
-        }
-    }
-    // the workgroup's accepted candidates (small cells: at most one per lane)
-    const unsigned long long m = __ballot(acc);
-    if (lane == 0) s_cnt[wave] = __popcll(m);
+    const unsigned long long m = __ballot(take);
+    if (lane == 0) lds[wave] = __popcll(m);
     __syncthreads();
     int before = 0, tot = 0;
 #pragma unroll
-    for (int w = 0; w < kNtcThreads / 64; ++w) {
-        before += w < wave ? s_cnt[w] : 0;
-        tot += s_cnt[w];
+    for (int w = 0; w < THREADS / 64; ++w) {
+        before += w < wave ? lds[w] : 0;
+        tot += lds[w];
     }
-    if (acc) a.pick_list[(int64_t)blockIdx.x * kNtcThreads + before + __popcll(m & ((1ull << lane) - 1))] = (int32_t)j_acc;
-    if (threadIdx.x == 0) a.pick_cnt[blockIdx.x] = tot;
+    *total = tot;
+    return before + __popcll(m & ((1ull << lane) - 1));
+}
+__device__ __forceinline__ int seg_slot(bool take, int* lds, int* total) { return compact_slot<kNtcSeg>(take, lds, total); }
+__device__ __forceinline__ int block_slot(bool take, int* lds, int* total) {
+    return compact_slot<kNtcThreads>(take, lds, total);
+}
+
+// One wave per cell: the cell's candidates, 64 at a time: their electrons,
+// photons and acceptance uniforms.  In a cell of at most 64 candidates, a
+// candidate that shares no particle with an earlier one of its cell is
+// ready (status 0); the others register for round 1 (kNtcLater).  Every
+// candidate of a larger cell registers for round 0 (kNtcLarge).
+template <typename T>
+__global__ __launch_bounds__(kNtcThreads) void k_ntc_pick(const NtcArgs<T> a_in) {
+    if (!a_in.ctl->go) return;  // (uniform) the step does not proceed
+    const NtcArgs<T> a = ntc_live(a_in);
+    const int lane = lane_id();
+    const int64_t c = (int64_t)blockIdx.x * (kNtcThreads / 64) + (threadIdx.x >> 6);
+    if (c >= a.n_cells) return;  // (uniform in the wave)
+    // cand_off holds prefixes within each scan block: add the block offsets,
+    // and keep the full offsets for the serial pass
+    const int64_t j0 = a.cand_off[c] + a.boff[c / kNtcScanBlock];
+    const int64_t j1 = c + 1 < a.n_cells ? a.cand_off[c + 1] + a.boff[(c + 1) / kNtcScanBlock] : a.total;
+    if (lane == 0) {
+        a.cand_full[c] = j0;
+        if (c + 1 == a.n_cells) a.cand_full[c + 1] = j1;
+    }
+    const int64_t e0 = a.off_e[c], g0 = a.off_g[c];
+    const uint64_t nec = (uint64_t)(a.off_e[c + 1] - e0), ngc = (uint64_t)(a.off_g[c + 1] - g0);
+    const bool small = j1 - j0 <= 64;
+    for (int64_t jb = j0; jb < j1; jb += 64) {
+        const int64_t j = jb + lane;
+        const bool act = j < j1;
+        int32_t ie = -1, ig = -1;
+        if (act) {
+            const u32x4 r = draw(a.seed, ((uint64_t)c << 32) | (uint64_t)(j - j0), a.step, kNtcPick);
+            ie = (int32_t)(e0 + (int64_t)(((uint64_t)r.a * nec) >> 32));
+            ig = (int32_t)(g0 + (int64_t)(((uint64_t)r.b * ngc) >> 32));
+            a.c_local[j] = (int32_t)(j - j0);
+            a.c_u[j] = uniform53(r.c, r.d);
+            a.c_ie[j] = ie;
+            a.c_ig[j] = ig;
+            a.c_cell[j] = (int32_t)c;
+        }
+        if (small) {
+            const int n = (int)(j1 - j0);
+            bool conflict = false;
+            for (int m = 0; m < n; ++m) {  // (m uniform: a lane read, not a permute)
+                const int32_t ie_m = __builtin_amdgcn_readlane(ie, m), ig_m = __builtin_amdgcn_readlane(ig, m);
+                conflict = conflict || (m < lane && (ie_m == ie || ig_m == ig));
+            }
+            if (act) a.status[j] = conflict ? kNtcLater : 0;
+            if (act && conflict) {
+                const unsigned long long tag = ntc_tag(a.epoch + 1u, j);
+                atomicMax(a.touch_e + a.cap_e + ie, tag);
+                atomicMax(a.touch_g + a.cap_g + ig, tag);
+            }
+        } else if (act) {
+            a.status[j] = kNtcLarge;
+            const unsigned long long tag = ntc_tag(a.epoch, j);
+            atomicMax(a.touch_e + ie, tag);
+            atomicMax(a.touch_g + ig, tag);
+        }
+    }
 }
 
 // The probability of candidate j (cell c, particles ie, ig) on the current
@@ -392,70 +463,126 @@ __device__ __forceinline__ void ntc_collide(const NtcArgs<T>& a, int64_t j, int3
     a.r_ea[j] = sc.e_after;
 }
 
-// Round t: ready candidates (earliest unresolved toucher of both their
-// particles) are evaluated, and the accepted ones listed in the workgroup's
-// segment for k_ntc_collide_list (round 0) or collide in place (later
-// rounds); the others register for round t + 1, or
-// after the last round mark their cell.
+// Round 0, one workgroup per segment of kNtcSeg candidates, one lane per
+// candidate: ready candidates (status 0, or a large cell's candidate that
+// is the earliest registered toucher of both its particles) are evaluated,
+// and the accepted ones compacted into the segment's collide list; the
+// large cells' other candidates register for round 1, and they and the
+// small cells' deferred ones are compacted into the segment's round-1 list.
 template <typename T>
-__global__ __launch_bounds__(kNtcThreads) void k_ntc_round(const NtcArgs<T> a, int t) {
-    __shared__ int s_cnt[kNtcThreads / 64];
-    const int64_t j = (int64_t)blockIdx.x * kNtcThreads + threadIdx.x;
-    const int lane = lane_id(), wave = threadIdx.x >> 6;
-    bool acc = false;
-    const uint8_t st = j < a.total ? a.status[j] : (uint8_t)1;
-    if (!(st & 1)) {
+__global__ __launch_bounds__(kNtcSeg) void k_ntc_eval(const NtcArgs<T> a_in) {
+    __shared__ int s_acc[kNtcSeg / 64], s_later[kNtcSeg / 64];
+    if (!a_in.ctl->go) return;  // (uniform)
+    const NtcArgs<T> a = ntc_live(a_in);
+    const int64_t base = (int64_t)blockIdx.x * kNtcSeg;
+    if (base >= a.total) return;  // (uniform) past the candidates
+    const int64_t j = base + threadIdx.x;
+    bool acc = false, later = false;
+    if (j < a.total) {
+        const uint8_t st = a.status[j];
         const int32_t ie = a.c_ie[j], ig = a.c_ig[j];
+        bool ready = st == 0;
+        if (st & kNtcLarge) {
+            const unsigned long long mine = ntc_tag(a.epoch, j);
+            ready = a.touch_e[ie] == mine && a.touch_g[ig] == mine;
+            if (!ready) {
+                const unsigned long long next = ntc_tag(a.epoch + 1u, j);
+                atomicMax(a.touch_e + a.cap_e + ie, next);
+                atomicMax(a.touch_g + a.cap_g + ig, next);
+                later = true;
+            }
+        } else if (st & kNtcLater) {
+            later = true;
+        }
+        if (ready) acc = ntc_evaluate<T>(a, j, a.c_cell[j], ie, ig);
+    }
+    int n_acc, n_later;
+    const int pa = seg_slot(acc, s_acc, &n_acc);
+    const int pl = seg_slot(later, s_later, &n_later);
+    if (acc) a.lst_c[base + pa] = (int32_t)j;
+    if (later) a.lst_1[base + pl] = (int32_t)j;
+    if (threadIdx.x == 0) {
+        a.cnt_c[blockIdx.x] = n_acc;
+        a.cnt_1[blockIdx.x] = n_later;
+    }
+}
+
+// Round 0's accepted candidates, one per lane (they share no particle, so
+// their order does not matter).  Workgroups of kNtcThreads, kNtcSub per
+// segment: a small workgroup whose waves have nothing to do frees its
+// place at once, so the few waves that work spread over the chip.
+// Workgroup b takes part b / n_seg of segment b % n_seg: the first parts
+// (the ones most often busy, as lists fill from their start) are
+// consecutive workgroups, which the dispatcher deals out over all XCDs.
+template <typename T>
+__global__ __launch_bounds__(kNtcThreads) void k_ntc_collide_list(const NtcArgs<T> a_in) {
+    if (!a_in.ctl->go) return;  // (uniform)
+    const int64_t seg = blockIdx.x % a_in.n_seg;
+    const int i = (int)(blockIdx.x / a_in.n_seg) * kNtcThreads + (int)threadIdx.x;
+    if (seg * kNtcSeg >= a_in.ctl->total || i >= a_in.cnt_c[seg]) return;
+    const NtcArgs<T> a = ntc_live(a_in);
+    const int64_t j = a.lst_c[seg * kNtcSeg + i];
+    ntc_collide<T>(a, j, a.c_cell[j], a.c_ie[j], a.c_ig[j]);
+}
+
+// Round t (1 or 2), one lane per list entry, workgroups of kNtcThreads:
+// round 1 over the segments' round-1 lists (kNtcSub workgroups per
+// segment, mapped as in k_ntc_collide_list), round 2 over the chunks of
+// kNtcThreads entries that round 1 wrote.  A candidate that is the earliest registered toucher of both its
+// particles is evaluated and, when accepted, collides in place (few
+// candidates are left after round 0); in round 1 the others register for
+// round 2 and are compacted into the workgroup's chunk of the round-2 list,
+// in round 2 they mark their cell for the serial pass.
+template <typename T>
+__global__ __launch_bounds__(kNtcThreads) void k_ntc_round(const NtcArgs<T> a_in, int t) {
+    __shared__ int s_later[kNtcThreads / 64];
+    if (!a_in.ctl->go) return;  // (uniform)
+    const int64_t seg = blockIdx.x % a_in.n_seg;
+    if (seg * kNtcSeg >= a_in.ctl->total) return;  // (uniform) past the candidates
+    const int sub = (int)(blockIdx.x / a_in.n_seg) * kNtcThreads;
+    // entries of this workgroup: round 1, the part [sub, sub + kNtcThreads)
+    // of the segment's list; round 2, its own chunk
+    const int n = t == 1 ? min(a_in.cnt_1[seg] - sub, kNtcThreads) : a_in.cnt_2[blockIdx.x];
+    if (n <= 0) {
+        if (t == 1 && threadIdx.x == 0) a_in.cnt_2[blockIdx.x] = 0;
+        return;  // (uniform)
+    }
+    const NtcArgs<T> a = ntc_live(a_in);
+    const int64_t chunk = (int64_t)blockIdx.x * kNtcThreads;  // this workgroup's chunk of the lists
+    bool later = false;
+    int64_t j = 0;
+    if ((int)threadIdx.x < n) {
+        j = t == 1 ? a.lst_1[seg * kNtcSeg + sub + threadIdx.x] : a.lst_2[chunk + threadIdx.x];
+        const int32_t ie = a.c_ie[j], ig = a.c_ig[j], c = a.c_cell[j];
         const unsigned long long* te = a.touch_e + (t & 1) * a.cap_e;
         const unsigned long long* tg = a.touch_g + (t & 1) * a.cap_g;
         const unsigned long long mine = ntc_tag(a.epoch + (uint32_t)t, j);
         if (te[ie] == mine && tg[ig] == mine) {
-            acc = ntc_evaluate<T>(a, j, a.c_cell[j], ie, ig);
-            // after round 0 few candidates are left: they collide here
-            if (t > 0 && acc) {
-                ntc_collide<T>(a, j, a.c_cell[j], ie, ig);
-                acc = false;
-            }
+            if (ntc_evaluate<T>(a, j, c, ie, ig)) ntc_collide<T>(a, j, c, ie, ig);
         } else if (t + 1 < kNtcRounds) {
             const unsigned long long next = ntc_tag(a.epoch + (uint32_t)(t + 1), j);
             atomicMax(a.touch_e + ((t + 1) & 1) * a.cap_e + ie, next);
             atomicMax(a.touch_g + ((t + 1) & 1) * a.cap_g + ig, next);
+            later = true;
         } else {
-            a.pending[a.c_cell[j]] = 1;
+            a.pending[c] = 1;
         }
     }
-    if (t != 0) return;  // (uniform) only round 0 lists its accepted candidates
-    const unsigned long long m = __ballot(acc);
-    if (lane == 0) s_cnt[wave] = __popcll(m);
-    __syncthreads();
-    int before = 0, tot = 0;
-#pragma unroll
-    for (int w = 0; w < kNtcThreads / 64; ++w) {
-        before += w < wave ? s_cnt[w] : 0;
-        tot += s_cnt[w];
+    if (t + 1 < kNtcRounds) {  // (uniform: t == 1)
+        int n_later;
+        const int pl = block_slot(later, s_later, &n_later);
+        if (later) a.lst_2[chunk + pl] = (int32_t)j;
+        if (threadIdx.x == 0) a.cnt_2[blockIdx.x] = n_later;
     }
-    int32_t* seg = a.list + (int64_t)blockIdx.x * kNtcThreads;
-    if (acc) seg[before + __popcll(m & ((1ull << lane) - 1))] = (int32_t)j;
-    if (threadIdx.x == 0) a.seg_cnt[blockIdx.x] = tot;
-}
-
-// Accepted candidates listed in segments of 256 (one per listing
-// workgroup): workgroup b collides segment b, one entry per lane.
-template <typename T>
-__global__ __launch_bounds__(kNtcThreads) void k_ntc_collide_list(const NtcArgs<T> a, const int32_t* list,
-                                                                const int32_t* cnt) {
-    const int n = cnt[blockIdx.x];
-    if ((int)threadIdx.x >= n) return;
-    const int64_t j = list[(int64_t)blockIdx.x * kNtcThreads + threadIdx.x];
-    ntc_collide<T>(a, j, a.c_cell[j], a.c_ie[j], a.c_ig[j]);
 }
 
 // One wave per marked cell: the wave reads the statuses of 64 candidates at
 // a time and lane 0 resolves the unresolved ones among them in order.
 template <typename T>
-__global__ __launch_bounds__(kNtcThreads) void k_ntc_serial(const NtcArgs<T> a) {
+__global__ __launch_bounds__(kNtcThreads) void k_ntc_serial(const NtcArgs<T> a_in) {
     const int64_t c = (int64_t)blockIdx.x * (kNtcThreads / 64) + (threadIdx.x >> 6);
-    if (c >= a.n_cells || !a.pending[c]) return;  // (uniform in the wave)
+    if (!a_in.ctl->go || c >= a_in.n_cells || !a_in.pending[c]) return;  // (uniform in the wave)
+    const NtcArgs<T> a = ntc_live(a_in);
     const int lane = lane_id();
     const int64_t j0 = a.cand_full[c], j1 = a.cand_full[c + 1];
     for (int64_t jb = j0; jb < j1; jb += 64) {
@@ -510,9 +637,12 @@ __device__ __forceinline__ NtcPart block_sum_part(NtcPart v, NtcPart* lds) {
 }
 
 __global__ __launch_bounds__(kNtcThreads) void k_ntc_reduce(const uint8_t* status, const double* ratio,
-                                                          const double* eb, const double* ea, int64_t total,
+                                                          const double* eb, const double* ea, const NtcCtl* ctl,
                                                           NtcPart* part) {
     __shared__ NtcPart s[kNtcThreads / 64];
+    const int64_t total = ctl->total;
+    // (uniform) the step did not proceed, or a workgroup past the candidates
+    if (!ctl->go || (int64_t)blockIdx.x * kNtcThreads * kNtcRedPer >= total) return;
     NtcPart v = {0.0, 0.0, 0.0, 0, 0, 0};
     const int64_t base = (int64_t)blockIdx.x * kNtcThreads * kNtcRedPer + threadIdx.x;
     for (int q = 0; q < kNtcRedPer; ++q) {
@@ -535,9 +665,14 @@ __global__ __launch_bounds__(kNtcThreads) void k_ntc_reduce(const uint8_t* statu
     if (threadIdx.x == 0) part[blockIdx.x] = r;
 }
 
-__global__ __launch_bounds__(kNtcThreads) void k_ntc_final(const NtcPart* part, int64_t n_part, int64_t total,
-                                                         cs_stats* stats, NtcCtl* ctl) {
+// The stats record from the reduction's partials, the control words
+// cleared for the next step, the epoch and the step word advanced.
+__global__ __launch_bounds__(kNtcThreads) void k_ntc_final(const NtcPart* part, cs_stats* stats, NtcCtl* ctl,
+                                                         NtcHead* head) {
     __shared__ NtcPart s[kNtcThreads / 64];
+    const NtcCtl c = *ctl;
+    const int64_t total = c.total;
+    const int64_t n_part = c.go ? (total + kNtcThreads * kNtcRedPer - 1) / (kNtcThreads * kNtcRedPer) : 0;
     NtcPart v = {0.0, 0.0, 0.0, 0, 0, 0};
     for (int64_t b = threadIdx.x; b < n_part; b += kNtcThreads) {
         const NtcPart p = part[b];
@@ -552,16 +687,25 @@ __global__ __launch_bounds__(kNtcThreads) void k_ntc_final(const NtcPart* part, 
     if (threadIdx.x == 0) {
         NtcCtl z = {};
         *ctl = z;
+        head->epoch += kNtcRounds;
+        head->step += 1;
     }
     if (threadIdx.x == 0 && stats) {
         cs_stats o = {};
-        o.n_pairs = total;
-        o.n_collided = r.coll;
-        o.n_clipped = r.clip;
-        o.n_invalid = r.inv;
-        o.sum_prob = r.prob;
-        o.energy_before = r.eb;
-        o.energy_after = r.ea;
+        if (c.layout_bad) {
+            o.layout_error = 1;
+        } else if (!c.go) {  // too many candidates: nothing was changed
+            o.n_pairs = c.too_many ? kNtcMaxCand : total;
+            o.overflow = 1;
+        } else {
+            o.n_pairs = total;
+            o.n_collided = r.coll;
+            o.n_clipped = r.clip;
+            o.n_invalid = r.inv;
+            o.sum_prob = r.prob;
+            o.energy_before = r.eb;
+            o.energy_after = r.ea;
+        }
         *stats = o;
     }
 }
@@ -576,6 +720,41 @@ __global__ void k_ntc_stats_layout(cs_stats* stats) {
 // host side
 // ---------------------------------------------------------------------------
 static inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Device scratch of a step, laid out from sizes the host knows before the
+// step: the cell count, the candidate capacity and the particle counts.
+struct NtcLayout {
+    int64_t nb, n_pb, n_seg, n_part;  // scan, pick, segment and reduction workgroups
+    size_t b_count, b_off, b_pmax, b_pend, b_bsum, b_ctl, cell;
+    size_t b_i32, b_u8, b_d, b_part, b_lst, b_cnt, cand;
+};
+
+static NtcLayout ntc_layout(int64_t n_cells, int64_t cap) {
+    NtcLayout l;
+    l.nb = (n_cells + kNtcScanBlock - 1) / kNtcScanBlock;
+    l.n_pb = (n_cells + kNtcThreads / 64 - 1) / (kNtcThreads / 64);
+    l.n_seg = (cap + kNtcSeg - 1) / kNtcSeg;
+    l.n_part = (cap + kNtcThreads * kNtcRedPer - 1) / (kNtcThreads * kNtcRedPer);
+    const size_t nc = (size_t)(n_cells > 0 ? n_cells : 1);
+    l.b_count = align256(8 * nc);
+    l.b_off = align256(8 * (nc + 1));
+    l.b_pmax = l.b_count;
+    l.b_pend = align256(nc);
+    l.b_bsum = align256(8 * (size_t)(l.nb > 0 ? l.nb : 1));
+    l.b_ctl = align256(sizeof(NtcCtl));
+    l.cell = l.b_ctl + l.b_count + 2 * l.b_off + l.b_pmax + l.b_pend + l.b_bsum;
+    const size_t tc = (size_t)(cap > 0 ? cap : 1);
+    l.b_i32 = align256(4 * tc);
+    l.b_u8 = align256(tc);
+    l.b_d = align256(8 * tc);
+    l.b_part = align256(sizeof(NtcPart) * (size_t)(l.n_part > 0 ? l.n_part : 1));
+    l.b_lst = align256(4 * (size_t)(l.n_seg > 0 ? l.n_seg : 1) * kNtcSeg);
+    l.b_cnt = align256(4 * (size_t)(l.n_seg > 0 ? l.n_seg : 1) * kNtcSub);
+    l.cand = 4 * l.b_i32 + l.b_u8 + 4 * l.b_d + l.b_part + 3 * l.b_lst + 3 * l.b_cnt;
+    return l;
+}
+
+static size_t touch_bytes(int64_t cap_e, int64_t cap_g) { return kNtcHeadBytes + 2 * 8 * (size_t)(cap_e + cap_g); }
 
 static hipError_t grow(void** buf, size_t* bytes, size_t want, hipStream_t st, bool* fresh = nullptr) {
     if (fresh) *fresh = false;
@@ -604,7 +783,139 @@ void ntc_free(NtcState& s) {
     if (s.cand_ws) (void)hipFree(s.cand_ws);
     if (s.touch) (void)hipFree(s.touch);
     if (s.host) (void)hipHostFree(s.host);
+    if (s.ev) (void)hipEventDestroy(s.ev);
     s = NtcState{};
+}
+
+// Scratch for a step of n_cells cells, `cap` candidates and ne / ng
+// particles: the per-cell area (zeroed when fresh: its control words start
+// at zero), the per-candidate area, and the touch words with their head
+// (zeroed when (re)allocated).  Synchronises `st` when a buffer grows.
+static hipError_t ntc_reserve(NtcState& s, int64_t n_cells, int64_t cap, int64_t ne, int64_t ng, hipStream_t st) {
+    const NtcLayout l = ntc_layout(n_cells, cap);
+    bool fresh = false;
+    hipError_t err = grow(&s.cell_ws, &s.cell_bytes, l.cell, st, &fresh);
+    if (err != hipSuccess) return err;
+    if (fresh) {
+        err = hipMemsetAsync(s.cell_ws, 0, s.cell_bytes, st);
+        if (err != hipSuccess) return err;
+    }
+    if (cap > 0 || s.cand_ws == nullptr) {
+        err = grow(&s.cand_ws, &s.cand_bytes, l.cand, st);
+        if (err != hipSuccess) return err;
+    }
+    if (cap > s.cand_cap) s.cand_cap = cap;
+    if (s.cap_e < ne || s.cap_g < ng || s.touch == nullptr) {
+        err = hipStreamSynchronize(st);
+        if (err != hipSuccess) return err;
+        if (s.touch) (void)hipFree(s.touch);
+        s.touch = nullptr;
+        s.cap_e = ne > s.cap_e ? ne + ne / 4 : s.cap_e;
+        s.cap_g = ng > s.cap_g ? ng + ng / 4 : s.cap_g;
+        if (s.cap_e < 1) s.cap_e = 1;
+        if (s.cap_g < 1) s.cap_g = 1;
+        err = hipMalloc(&s.touch, touch_bytes(s.cap_e, s.cap_g));
+        if (err != hipSuccess) {
+            s.touch = nullptr;
+            s.cap_e = s.cap_g = 0;
+            return err;
+        }
+        err = hipMemsetAsync(s.touch, 0, touch_bytes(s.cap_e, s.cap_g), st);
+        if (err != hipSuccess) return err;
+    }
+    return hipSuccess;
+}
+
+// Queue one whole step for the candidate capacity s.cand_cap (no host
+// synchronisation, no allocation, no memset: capturable).  With `host`
+// set, the control words are copied there after the scan and `ev` is
+// recorded behind the copy.
+template <typename T>
+static hipError_t ntc_enqueue(const NtcState& s, const cs_species& e, const cs_species& g, const int64_t* off_e,
+                              const int64_t* off_g, int64_t n_cells, double dt, double dn, uint64_t seed,
+                              uint64_t step, bool dev_step, cs_stats* stats, hipStream_t st, void* host,
+                              hipEvent_t ev) {
+    const int64_t cap = s.cand_cap;
+    const NtcLayout l = ntc_layout(n_cells, cap);
+    char* cw = (char*)s.cell_ws;
+    NtcCtl* ctl = (NtcCtl*)cw;
+    int64_t* count = (int64_t*)(cw += l.b_ctl);
+    int64_t* cand_off = (int64_t*)(cw += l.b_count);
+    double* p_max = (double*)(cw += l.b_off);
+    uint8_t* pending = (uint8_t*)(cw += l.b_pmax);
+    long long* bsum = (long long*)(cw += l.b_pend);
+    int64_t* cand_full = (int64_t*)(cw += l.b_bsum);
+    NtcHead* head = (NtcHead*)s.touch;
+    unsigned long long* touch = (unsigned long long*)((char*)s.touch + kNtcHeadBytes);
+    if (n_cells > 0) {
+        k_ntc_count<T><<<(unsigned)((n_cells + 3) / 4), kNtcThreads, 0, st>>>(
+            (const T*)e.w, (const T*)g.w, off_e, off_g, n_cells, e.n, g.n, dt, dn, seed, step, head, dev_step ? 1 : 0,
+            count, p_max, pending, ctl);
+        k_ntc_scan_local<<<(unsigned)l.nb, kNtcThreads, 0, st>>>(count, n_cells, cand_off, bsum);
+    }
+    k_ntc_scan_top<<<1, kNtcThreads, 0, st>>>(bsum, l.nb, n_cells, cand_off, cap, ctl, head, touch,
+                                              2 * (s.cap_e + s.cap_g));
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    if (host) {
+        err = hipMemcpyAsync(host, ctl, sizeof(NtcCtl), hipMemcpyDeviceToHost, st);
+        if (err == hipSuccess) err = hipEventRecord(ev, st);
+        if (err != hipSuccess) return err;
+    }
+    NtcArgs<T> a;
+    a.pt = {(T*)e.x, (T*)e.y, (T*)e.z, (T*)e.w, (T*)g.x, (T*)g.y, (T*)g.z, (T*)g.w};
+    a.off_e = off_e;
+    a.off_g = off_g;
+    a.n_cells = n_cells;
+    a.total = 0;
+    a.dt = dt;
+    a.dn = dn;
+    a.seed = seed;
+    a.step = step;
+    a.epoch = 0;
+    a.dev_step = dev_step ? 1 : 0;
+    a.ctl = ctl;
+    a.head = head;
+    a.cand_off = cand_off;
+    a.boff = bsum;
+    a.cand_full = cand_full;
+    a.p_max = p_max;
+    char* q = (char*)s.cand_ws;
+    a.c_ie = (int32_t*)q;
+    a.c_ig = (int32_t*)(q += l.b_i32);
+    a.c_cell = (int32_t*)(q += l.b_i32);
+    a.c_local = (int32_t*)(q += l.b_i32);
+    a.status = (uint8_t*)(q += l.b_i32);
+    a.r_ratio = (double*)(q += l.b_u8);
+    a.r_eb = (double*)(q += l.b_d);
+    a.r_ea = (double*)(q += l.b_d);
+    a.c_u = (double*)(q += l.b_d);
+    NtcPart* part = (NtcPart*)(q += l.b_d);
+    a.lst_c = (int32_t*)(q += l.b_part);
+    a.lst_1 = (int32_t*)(q += l.b_lst);
+    a.lst_2 = (int32_t*)(q += l.b_lst);
+    a.cnt_c = (int32_t*)(q += l.b_lst);
+    a.cnt_1 = (int32_t*)(q += l.b_cnt);
+    a.cnt_2 = (int32_t*)(q += l.b_cnt);
+    a.n_seg = l.n_seg > 0 ? l.n_seg : 1;
+    a.touch_e = touch;
+    a.touch_g = touch + 2 * s.cap_e;
+    a.cap_e = s.cap_e;
+    a.cap_g = s.cap_g;
+    a.pending = pending;
+    if (n_cells > 0) k_ntc_pick<T><<<(unsigned)l.n_pb, kNtcThreads, 0, st>>>(a);
+    if (cap > 0) {
+        // one workgroup per segment, up to the capacity; kNtcSub smaller ones per segment
+        k_ntc_eval<T><<<(unsigned)l.n_seg, kNtcSeg, 0, st>>>(a);
+        const unsigned grid = (unsigned)(l.n_seg * kNtcSub);
+        k_ntc_collide_list<T><<<grid, kNtcThreads, 0, st>>>(a);
+        for (int t = 1; t < kNtcRounds; ++t) k_ntc_round<T><<<grid, kNtcThreads, 0, st>>>(a, t);
+    }
+    if (n_cells > 0) k_ntc_serial<T><<<(unsigned)l.n_pb, kNtcThreads, 0, st>>>(a);
+    if (cap > 0)
+        k_ntc_reduce<<<(unsigned)l.n_part, kNtcThreads, 0, st>>>(a.status, a.r_ratio, a.r_eb, a.r_ea, ctl, part);
+    k_ntc_final<<<1, kNtcThreads, 0, st>>>(part, stats, ctl, head);
+    return hipGetLastError();
 }
 
 template <typename T>
@@ -612,31 +923,13 @@ static hipError_t ntc_launch(NtcState& s, const cs_species& e, const cs_species&
                              const int64_t* off_g, int64_t n_cells, double dt, double dn, uint64_t seed,
                              uint64_t step, cs_stats* stats, hipStream_t st, NtcOutcome* out) {
     *out = NtcOutcome::kOk;
-    // per-cell area: counts, offsets, P_max, marks, block sums, control
-    const int64_t nb = (n_cells + kNtcScanBlock - 1) / kNtcScanBlock;
-    const size_t b_count = align256(8 * (size_t)(n_cells > 0 ? n_cells : 1));
-    const size_t b_off = align256(8 * (size_t)(n_cells + 1));
-    const size_t b_pmax = b_count;
-    const size_t b_pend = align256((size_t)(n_cells > 0 ? n_cells : 1));
-    const size_t b_bsum = align256(8 * (size_t)(nb > 0 ? nb : 1));
-    const size_t b_ctl = align256(sizeof(NtcCtl));
-    bool fresh = false;
-    hipError_t err =
-        grow(&s.cell_ws, &s.cell_bytes, b_count + 2 * b_off + b_pmax + b_pend + b_bsum + b_ctl, st, &fresh);
-    if (err != hipSuccess) return err;
-    if (fresh) {  // the control words start at zero
-        err = hipMemsetAsync(s.cell_ws, 0, s.cell_bytes, st);
-        if (err != hipSuccess) return err;
+    if (n_cells == 0 && (e.n != 0 || g.n != 0)) {
+        *out = NtcOutcome::kLayout;
+        if (stats) k_ntc_stats_layout<<<1, 1, 0, st>>>(stats);
+        return hipGetLastError();
     }
-    // the control words first: their place does not depend on the cell count
-    char* cw = (char*)s.cell_ws;
-    NtcCtl* ctl = (NtcCtl*)cw;
-    int64_t* count = (int64_t*)(cw += b_ctl);
-    int64_t* cand_off = (int64_t*)(cw += b_count);
-    double* p_max = (double*)(cw += b_off);
-    uint8_t* pending = (uint8_t*)(cw += b_pmax);
-    long long* bsum = (long long*)(cw += b_pend);
-    int64_t* cand_full = (int64_t*)(cw += b_bsum);
+    hipError_t err = ntc_reserve(s, n_cells, s.cand_cap, e.n, g.n, st);
+    if (err != hipSuccess) return err;
     if (!s.host) {
         err = hipHostMalloc(&s.host, sizeof(NtcCtl), hipHostMallocDefault);
         if (err != hipSuccess) {
@@ -644,123 +937,36 @@ static hipError_t ntc_launch(NtcState& s, const cs_species& e, const cs_species&
             return err;
         }
     }
-    // touch words: two sets per species, zero when (re)allocated
-    if (s.cap_e < e.n || s.cap_g < g.n || s.touch == nullptr) {
-        err = hipStreamSynchronize(st);
-        if (err != hipSuccess) return err;
-        if (s.touch) (void)hipFree(s.touch);
-        s.touch = nullptr;
-        s.cap_e = e.n > s.cap_e ? e.n + e.n / 4 : s.cap_e;
-        s.cap_g = g.n > s.cap_g ? g.n + g.n / 4 : s.cap_g;
-        if (s.cap_e < 1) s.cap_e = 1;
-        if (s.cap_g < 1) s.cap_g = 1;
-        const size_t tb = 2 * 8 * (size_t)(s.cap_e + s.cap_g);
-        err = hipMalloc(&s.touch, tb);
+    if (!s.ev) {
+        err = hipEventCreateWithFlags(&s.ev, hipEventDisableTiming);
         if (err != hipSuccess) {
-            s.touch = nullptr;
-            s.cap_e = s.cap_g = 0;
+            s.ev = nullptr;
             return err;
         }
-        err = hipMemsetAsync(s.touch, 0, tb, st);
-        if (err != hipSuccess) return err;
-        s.epoch = 1;
     }
-    if (s.epoch > 0xFFFFFFFFu - 2 * kNtcRounds) {  // tags would wrap: clear and restart
-        err = hipMemsetAsync(s.touch, 0, 2 * 8 * (size_t)(s.cap_e + s.cap_g), st);
-        if (err != hipSuccess) return err;
-        s.epoch = 1;
-    }
-    if (n_cells > 0) {
-        k_ntc_count<T><<<(unsigned)((n_cells + 3) / 4), kNtcThreads, 0, st>>>(
-            (const T*)e.w, (const T*)g.w, off_e, off_g, n_cells, e.n, g.n, dt, dn, seed, step, count, p_max, pending, ctl);
-        k_ntc_scan_local<<<(unsigned)nb, kNtcThreads, 0, st>>>(count, n_cells, cand_off, bsum);
-    }
-    k_ntc_scan_top<<<1, kNtcThreads, 0, st>>>(bsum, nb, n_cells, cand_off, ctl);
-    err = hipGetLastError();
-    if (err == hipSuccess) err = hipMemcpyAsync(s.host, ctl, sizeof(NtcCtl), hipMemcpyDeviceToHost, st);
-    if (err == hipSuccess) err = hipStreamSynchronize(st);
+    // The whole step is queued at once; the host then waits only for the
+    // scan's control words (the rest of the step runs meanwhile).  A step
+    // with more candidates than the capacity changed nothing: the scratch
+    // grows and the step is queued again (same inputs, same candidates).
+    err = ntc_enqueue<T>(s, e, g, off_e, off_g, n_cells, dt, dn, seed, step, false, stats, st, s.host, s.ev);
+    if (err == hipSuccess) err = hipEventSynchronize(s.ev);
     if (err != hipSuccess) return err;
     const NtcCtl h = *(const NtcCtl*)s.host;
-    if (h.layout_bad || (n_cells == 0 && (e.n != 0 || g.n != 0))) {
+    if (h.layout_bad) {
         *out = NtcOutcome::kLayout;
-        if (stats) k_ntc_stats_layout<<<1, 1, 0, st>>>(stats);
-        err = hipGetLastError();
-        return err == hipSuccess ? hipMemsetAsync(ctl, 0, sizeof(NtcCtl), st) : err;
+        return hipSuccess;
     }
     if (h.too_many) {
         *out = NtcOutcome::kTooMany;
-        return hipMemsetAsync(ctl, 0, sizeof(NtcCtl), st);
+        return hipSuccess;
     }
-    const int64_t total = h.total;
-    // per-candidate area
-    const int64_t n_part = (total + kNtcThreads * kNtcRedPer - 1) / (kNtcThreads * kNtcRedPer);
-    const size_t tc = (size_t)(total > 0 ? total : 1);
-    const size_t b_i32 = align256(4 * tc), b_u8 = align256(tc), b_d = align256(8 * tc);
-    const size_t b_part = align256(sizeof(NtcPart) * (size_t)(n_part > 0 ? n_part : 1));
-    const int64_t n_rb = (total + kNtcThreads - 1) / kNtcThreads;
-    const int64_t list_len = (n_rb > 0 ? n_rb : 1) * kNtcThreads;
-    const int64_t n_pb = (n_cells + kNtcThreads / 64 - 1) / (kNtcThreads / 64);  // pick workgroups
-    const size_t b_list = align256(4 * (size_t)list_len);
-    const size_t b_seg = align256(4 * (size_t)(n_rb > 0 ? n_rb : 1));
-    const size_t b_plist = align256(4 * (size_t)(n_pb > 0 ? n_pb : 1) * kNtcThreads);
-    const size_t b_pcnt = align256(4 * (size_t)(n_pb > 0 ? n_pb : 1));
-    err = grow(&s.cand_ws, &s.cand_bytes, 4 * b_i32 + b_u8 + 4 * b_d + b_part + b_list + b_seg + b_plist + b_pcnt,
-               st);
-    if (err != hipSuccess) return err;
-    NtcArgs<T> a;
-    a.pt = {(T*)e.x, (T*)e.y, (T*)e.z, (T*)e.w, (T*)g.x, (T*)g.y, (T*)g.z, (T*)g.w};
-    a.off_e = off_e;
-    a.off_g = off_g;
-    a.n_cells = n_cells;
-    a.total = total;
-    a.dt = dt;
-    a.dn = dn;
-    a.seed = seed;
-    a.step = step;
-    a.epoch = s.epoch;
-    a.cand_off = cand_off;
-    a.boff = bsum;
-    a.cand_full = cand_full;
-    a.p_max = p_max;
-    char* q = (char*)s.cand_ws;
-    a.c_ie = (int32_t*)q;
-    a.c_ig = (int32_t*)(q += b_i32);
-    a.c_cell = (int32_t*)(q += b_i32);
-    a.c_local = (int32_t*)(q += b_i32);
-    a.status = (uint8_t*)(q += b_i32);
-    a.r_ratio = (double*)(q += b_u8);
-    a.r_eb = (double*)(q += b_d);
-    a.r_ea = (double*)(q += b_d);
-    a.c_u = (double*)(q += b_d);
-    NtcPart* part = (NtcPart*)(q += b_d);
-    a.list = (int32_t*)(q += b_part);
-    a.seg_cnt = (int32_t*)(q += b_list);
-    a.pick_list = (int32_t*)(q += b_seg);
-    a.pick_cnt = (int32_t*)(q += b_plist);
-    a.list_len = list_len;
-    a.n_round_blocks = n_rb;
-    a.touch_e = (unsigned long long*)s.touch;
-    a.touch_g = a.touch_e + 2 * s.cap_e;
-    a.cap_e = s.cap_e;
-    a.cap_g = s.cap_g;
-    a.pending = pending;
-    s.epoch += kNtcRounds;
-    if (total > 0) {
-        const unsigned grid = (unsigned)((total + kNtcThreads - 1) / kNtcThreads);
-        k_ntc_pick<T><<<(unsigned)n_pb, kNtcThreads, 0, st>>>(a);
-        k_ntc_collide_list<T><<<(unsigned)n_pb, kNtcThreads, 0, st>>>(a, a.pick_list, a.pick_cnt);
-        // round 0 only for cells of more than 64 candidates (the others were
-        // settled in the pick kernel and registered for round 1)
-        if (h.has_large) {
-            k_ntc_round<T><<<grid, kNtcThreads, 0, st>>>(a, 0);
-            k_ntc_collide_list<T><<<grid, kNtcThreads, 0, st>>>(a, a.list, a.seg_cnt);
-        }
-        for (int t = 1; t < kNtcRounds; ++t) k_ntc_round<T><<<grid, kNtcThreads, 0, st>>>(a, t);
-        k_ntc_serial<T><<<(unsigned)n_pb, kNtcThreads, 0, st>>>(a);
-        k_ntc_reduce<<<(unsigned)n_part, kNtcThreads, 0, st>>>(a.status, a.r_ratio, a.r_eb, a.r_ea, total, part);
+    if (h.overflow) {
+        err = ntc_reserve(s, n_cells, h.total + h.total / 4, e.n, g.n, st);
+        if (err == hipSuccess)
+            err = ntc_enqueue<T>(s, e, g, off_e, off_g, n_cells, dt, dn, seed, step, false, stats, st, nullptr,
+                                 nullptr);
     }
-    k_ntc_final<<<1, kNtcThreads, 0, st>>>(part, n_part, total, stats, ctl);
-    return hipGetLastError();
+    return err;
 }
 
 hipError_t ntc_step(NtcState& s, cs_dtype dtype, const cs_species& e, const cs_species& g, const int64_t* off_e,
@@ -768,6 +974,29 @@ hipError_t ntc_step(NtcState& s, cs_dtype dtype, const cs_species& e, const cs_s
                     cs_stats* stats, hipStream_t st, NtcOutcome* out) {
     if (dtype == CS_F64) return ntc_launch<double>(s, e, g, off_e, off_g, n_cells, dt, dn, seed, step, stats, st, out);
     return ntc_launch<float>(s, e, g, off_e, off_g, n_cells, dt, dn, seed, step, stats, st, out);
+}
+
+hipError_t ntc_prepare_graph(NtcState& s, int64_t n_cells, int64_t cap, int64_t ne, int64_t ng, hipStream_t st) {
+    hipError_t err = ntc_reserve(s, n_cells, cap, ne, ng, st);
+    if (err == hipSuccess) err = hipStreamSynchronize(st);
+    return err;
+}
+
+hipError_t ntc_capture(const NtcState& s, cs_dtype dtype, const cs_species& e, const cs_species& g,
+                       const int64_t* off_e, const int64_t* off_g, int64_t n_cells, double dt, double dn,
+                       uint64_t seed, cs_stats* stats, hipStream_t st) {
+    if (dtype == CS_F64)
+        return ntc_enqueue<double>(s, e, g, off_e, off_g, n_cells, dt, dn, seed, 0, true, stats, st, nullptr, nullptr);
+    return ntc_enqueue<float>(s, e, g, off_e, off_g, n_cells, dt, dn, seed, 0, true, stats, st, nullptr, nullptr);
+}
+
+__global__ void k_ntc_set_step(NtcHead* head, uint64_t step) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) head->step = step;
+}
+
+hipError_t ntc_set_step(const NtcState& s, uint64_t step, hipStream_t st) {
+    k_ntc_set_step<<<1, 64, 0, st>>>((NtcHead*)s.touch, step);
+    return hipGetLastError();
 }
 
 }  // namespace cs

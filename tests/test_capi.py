@@ -54,6 +54,8 @@ def test_null_context_and_create_errors():
         compton.CS_ERR_INVALID_ARG
     assert L.cs_compton_step_noalloc(None, 0, sp, sp, None, None, 0, 0.1, 1.0, 0, 0, 0, None, None, None) == \
         compton.CS_ERR_INVALID_ARG
+    assert L.cs_ntc_graph_create(None, 0, sp, sp, None, None, 0, 0.1, 1.0, 0, 1, None, None, None) == \
+        compton.CS_ERR_INVALID_ARG
     assert L.cs_create(None, 0) == compton.CS_ERR_INVALID_ARG
     assert b"NULL" in L.cs_last_error(None)
     import torch

@@ -247,3 +247,88 @@ def test_uneven_cells_match_oracle(ctx, orc):
     st, gst, diag = res[0]
     per_cell = np.bincount(diag["cell"], minlength=p.n_cells)
     assert per_cell.max() > 64 and st["n_collided"] > 1000, (per_cell.max(), st)
+
+
+def test_graph_replays_equal_eager_steps(ctx):
+    """cs_ntc_graph_create: replays of the captured step (step index from
+    the graph's device word, advanced by each replay) leave the particles and
+    the stats record bitwise equal to eager cs_ntc_step calls with the same
+    step indices, with eager work and synchronisations between the replays;
+    a graph sized below the step's candidate count changes nothing and flags
+    the overflow."""
+    import torch
+
+    from paper_2206_02937_amd import compton
+
+    p = plasma.grid(seed=3, nx=128, ny=128, per_cell=256, dtype=np.float32)
+    steps = [5, 6, 7]
+    eager = []
+    e, g, oe, og = compton.to_device(p)
+    for s in steps:
+        buf = ctx.stats_buffer()
+        ctx.ntc_step(e, g, oe, og, p.dt, p.density_norm, p.seed, s, stats=buf)
+        torch.cuda.synchronize()
+        eager.append((compton.to_host(e), compton.to_host(g), compton.decode_stats(buf)))
+    n_cand = max(st["n_pairs"] for _, _, st in eager)
+    assert n_cand > 100000
+    e, g, oe, og = compton.to_device(p)
+    stats = ctx.stats_buffer()
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        gr = ctx.ntc_graph(e, g, oe, og, p.dt, p.density_norm, p.seed, n_cand + n_cand // 2, stats=stats)
+        try:
+            gr.set_step(steps[0])
+            for k, (ee, ge, se) in enumerate(eager):
+                gr.launch()
+                stream.synchronize()
+                st = compton.decode_stats(stats)
+                print(f"  replay {k}: {st['n_pairs']} candidates, {st['n_collided']} collisions", flush=True)
+                assert st == se, (st, se)
+                he, hg = compton.to_host(e), compton.to_host(g)
+                for key in "xyzw":
+                    assert np.array_equal(he[key], ee[key]) and np.array_equal(hg[key], ge[key]), (k, key)
+                torch.zeros(1 << 20, device="cuda").sum().item()  # unrelated eager work between replays
+        finally:
+            gr.close()
+        # too small a capacity: the replay changes nothing, stats flag it
+        before_e, before_g = compton.to_host(e), compton.to_host(g)
+        small = ctx.ntc_graph(e, g, oe, og, p.dt, p.density_norm, p.seed, 1000, stats=stats)
+        try:
+            small.set_step(steps[0])
+            small.launch()
+            stream.synchronize()
+        finally:
+            small.close()
+    st = compton.decode_stats(stats)
+    assert st["overflow"] == 1 and st["n_pairs"] > 1000 and st["n_collided"] == 0
+    he, hg = compton.to_host(e), compton.to_host(g)
+    for key in "xyzw":
+        assert np.array_equal(he[key], before_e[key]) and np.array_equal(hg[key], before_g[key])
+
+
+def test_capacity_grows_between_calls(ctx):
+    """A context that stepped a small plasma (small candidate capacity) then
+    steps a larger one: the larger step overflows the capacity, changes
+    nothing, and is queued again on grown scratch; the result equals a fresh
+    context's."""
+    import torch
+
+    from paper_2206_02937_amd import compton
+
+    small = plasma.grid(seed=4, nx=2, ny=2, per_cell=32, dtype=np.float32)
+    big = plasma.grid(seed=4, nx=32, ny=32, per_cell=256, dtype=np.float32)
+    c1 = compton.Context(0)
+    c2 = compton.Context(0)
+    try:
+        _gpu_steps(c1, small, [0])
+        a = _gpu_steps(c1, big, [0])
+        b = _gpu_steps(c2, big, [0])
+    finally:
+        c1.close()
+        c2.close()
+    torch.cuda.synchronize()
+    (ea, ga, sa), = a
+    (eb, gb, sb), = b
+    assert sa == sb and sa["n_pairs"] > 1000
+    assert all(np.array_equal(ea[k], eb[k]) and np.array_equal(ga[k], gb[k]) for k in "xyzw")
