@@ -95,9 +95,14 @@ struct GradArgs {
 // -- the lane that produced z keeps SiLU'(z) in registers for that --, and
 // the weight gradients dW[16w.., :] = delta[16w.., :] H^T (four 16x16 tiles,
 // K = 16 samples), which stay in MFMA accumulators over the workgroup's tiles
-// and are written once.  Each lane loads the parameters it uses once, into
-// registers, for all its tiles (its 96 MFMA weight operands among them);
-// activations and deltas are
+// and are written once.  The workgroup first issues the loads of its first
+// tile's inputs and targets (vector-memory loads complete in issue order,
+// so a wait for them must not sit behind the parameter loads), then copies
+// the parameters into LDS with coalesced 16-byte loads, and each lane takes
+// the parameters it uses from there into registers, once for all its tiles
+// (its 96 MFMA weight operands among them); each tile issues the next
+// tile's input loads as soon as it has consumed its own.  Activations and
+// deltas are
 // written to LDS in two layouts, [feature][sample] for the operands whose
 // K index is a feature and [sample][feature] (rows of kYRow) for those whose
 // K index is a sample, so that every operand read is conflict-free.  Each
@@ -106,6 +111,26 @@ struct GradArgs {
 // in a fixed order.
 constexpr int kTrainTile = 16;
 constexpr int kYRow = 80;  // [sample][feature] rows: 64 + 16 floats
+// The parameters in LDS: the three 64x64 hidden matrices with rows of 68
+// floats (so that the operand reads, 16 rows by 4 columns, spread over the
+// banks), then the other 514 parameters packed: W1, b1, b2, b3, b4, W5, b5.
+constexpr int kParRow = 68;
+constexpr int kParMat = kMlpHidden * kParRow;
+constexpr int kParSmall = 3 * kParMat;
+constexpr int kParSW1 = 0, kParSB1 = 128, kParSB2 = 192, kParSW5 = 384, kParSB5 = 512;
+constexpr int kParFloats = kParSmall + 516;
+
+// LDS position of the 4-aligned parameter index f (below kOffB5).
+__device__ __forceinline__ int par_slot(int f) {
+    if (f < kOffW2) return kParSmall + f;  // W1, b1
+    if (f < kOffB2) return ((f - kOffW2) >> 6) * kParRow + ((f - kOffW2) & 63);
+    if (f < kOffW3) return kParSmall + kParSB2 + (f - kOffB2);
+    if (f < kOffB3) return kParMat + ((f - kOffW3) >> 6) * kParRow + ((f - kOffW3) & 63);
+    if (f < kOffW4) return kParSmall + kParSB2 + 64 + (f - kOffB3);
+    if (f < kOffB4) return 2 * kParMat + ((f - kOffW4) >> 6) * kParRow + ((f - kOffW4) & 63);
+    if (f < kOffW5) return kParSmall + kParSB2 + 128 + (f - kOffB4);
+    return kParSmall + kParSW5 + (f - kOffW5);  // W5
+}
 
 typedef float floatx4_t __attribute__((ext_vector_type(4)));
 
@@ -114,6 +139,7 @@ __device__ __forceinline__ floatx4_t mfma_f32(float a, float b, floatx4_t c) {
 }
 
 __global__ __launch_bounds__(kMlpThreads) void k_mlp_grad_block(const GradArgs a) {
+    __shared__ float4 s_par4[kParFloats / 4];             // the parameters (layout: par_slot)
     __shared__ float HX[4][kMlpHidden * kTrainTile];      // h1..h4, [feature][sample]
     __shared__ float HY[4][kTrainTile * kYRow];           // h1..h4, [sample][feature]
     __shared__ float DX[kMlpHidden * kTrainTile];         // delta of the current layer, [feature][sample]
@@ -126,32 +152,66 @@ __global__ __launch_bounds__(kMlpThreads) void k_mlp_grad_block(const GradArgs a
     const int lane = tid & 63;
     const int w = wave_uniform(tid >> 6);
     const int li = lane & 15, lg = lane >> 4;  // MFMA operand row / k index of this lane
-    const float* P = a.P;
-    // every parameter this lane uses, loaded once for all its tiles: the
+    const int64_t n_tiles = (a.n + kTrainTile - 1) / kTrainTile;
+    // this thread's inputs of the first tile: features (tid < kTrainTile),
+    // target (tid < 2 kTrainTile: sample tid / 2, output tid % 2)
+    float in_x = 0.0f, in_u = 0.0f, in_t = 0.0f;
+    auto load_inputs = [&](int64_t tile) {
+        const int64_t i = tile * kTrainTile + tid;
+        if (tid < kTrainTile && i < a.n) {
+            in_x = a.x[i];
+            in_u = a.u[i];
+        }
+        const int64_t it = tile * kTrainTile + (tid >> 1);
+        if (tid < 2 * kTrainTile && it < a.n) in_t = (tid & 1) == 0 ? a.mu_t[it] : a.r_t[it];
+    };
+    if ((int64_t)blockIdx.x < n_tiles) load_inputs(blockIdx.x);
+    // the parameters into LDS (12802 floats: 3200 16-byte loads and two floats)
+    {
+        constexpr int kN4 = kMlpParams / 4;              // 3200 16-byte pieces
+        constexpr int kFull = kN4 / kMlpThreads;         // 12 rounds for every thread
+        constexpr int kRest = kN4 - kFull * kMlpThreads;  // then 128 threads once more
+        const float4* P4 = (const float4*)a.P;
+        float4 v[kFull + 1];
+        // all issued before the first store; in the last round the threads
+        // past kRest repeat the piece of thread 0 (same value, same place)
+        const int last = kFull * kMlpThreads + (tid < kRest ? tid : 0);
+#pragma unroll
+        for (int q = 0; q < kFull; ++q) v[q] = P4[tid + q * kMlpThreads];
+        v[kFull] = P4[last];
+        const float tail = a.P[kN4 * 4 + (tid & 1)];
+#pragma unroll
+        for (int q = 0; q < kFull; ++q) s_par4[par_slot(4 * (tid + q * kMlpThreads)) / 4] = v[q];
+        s_par4[par_slot(4 * last) / 4] = v[kFull];
+        if (tid < kMlpParams % 4) ((float*)s_par4)[kParSmall + kParSB5 + tid] = tail;
+    }
+    __syncthreads();
+    const float* P = (const float*)s_par4;
+    // every parameter this lane uses, taken once for all its tiles: the
     // hidden layers' MFMA operands A = W[16w + li][4ks + lg] (forward) and
     // W^T[16w + li][4ks + lg] (backward), and for its neurons
     // n(r) = 16w + 4 lg + r the first layer, the biases and the output weights
     const int offW[3] = {kOffW2, kOffW3, kOffW4};
-    const int offB[3] = {kOffB2, kOffB3, kOffB4};
     float wf[3][16], wt[3][16];
 #pragma unroll
     for (int L = 0; L < 3; ++L)
 #pragma unroll
         for (int ks = 0; ks < 16; ++ks) {
-            wf[L][ks] = P[offW[L] + (16 * w + li) * kMlpHidden + 4 * ks + lg];
-            wt[L][ks] = P[offW[L] + (4 * ks + lg) * kMlpHidden + 16 * w + li];
+            wf[L][ks] = P[L * kParMat + (16 * w + li) * kParRow + 4 * ks + lg];
+            wt[L][ks] = P[L * kParMat + (4 * ks + lg) * kParRow + 16 * w + li];
         }
+    const float* Ps = P + kParSmall;
     float w1a[4], w1b[4], bias[4][4], w50[4], w51[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int n = 16 * w + 4 * lg + r;
-        w1a[r] = P[kOffW1 + 2 * n];
-        w1b[r] = P[kOffW1 + 2 * n + 1];
-        bias[0][r] = P[kOffB1 + n];
+        w1a[r] = Ps[kParSW1 + 2 * n];
+        w1b[r] = Ps[kParSW1 + 2 * n + 1];
+        bias[0][r] = Ps[kParSB1 + n];
 #pragma unroll
-        for (int L = 0; L < 3; ++L) bias[L + 1][r] = P[offB[L] + n];
-        w50[r] = P[kOffW5 + n];
-        w51[r] = P[kOffW5 + kMlpHidden + n];
+        for (int L = 0; L < 3; ++L) bias[L + 1][r] = Ps[kParSB2 + 64 * L + n];
+        w50[r] = Ps[kParSW5 + n];
+        w51[r] = Ps[kParSW5 + kMlpHidden + n];
     }
     // this lane's neurons of every layer: n(r) = 16w + 4 lg + r, sample li
     floatx4_t gW[3][4];  // dW_{2,3,4}[16w + 4lg + r][16tk + li], accumulated over the tiles
@@ -164,16 +224,17 @@ __global__ __launch_bounds__(kMlpThreads) void k_mlp_grad_block(const GradArgs a
     float gW5 = 0.0f;                        // tid < 128: dW5[tid / 64][tid % 64]
     float gB5 = 0.0f, g_loss = 0.0f;         // tid < 2: db5[tid]; tid == 2: the loss
     const float inv_n = 1.0f / (float)a.n;
-    const int64_t n_tiles = (a.n + kTrainTile - 1) / kTrainTile;
     for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-        __syncthreads();  // the previous tile's LDS reads are done (and the weights are staged)
+        __syncthreads();  // the previous tile's LDS reads are done
         if (tid < kTrainTile) {
             const int64_t i = tile * kTrainTile + tid;
             float f1 = 0.0f, f2 = 0.0f;
-            if (i < a.n) features(a.x[i], a.u[i], a.dom, f1, f2);
+            if (i < a.n) features(in_x, in_u, a.dom, f1, f2);
             F[tid][0] = f1;
             F[tid][1] = f2;
         }
+        const float target = in_t;
+        if (tile + gridDim.x < n_tiles) load_inputs(tile + gridDim.x);
         __syncthreads();
         float gp[4][4];  // SiLU'(z) of layers 1..4 at this lane's (neuron, sample)
         // layer 1 (2 -> 64) on the vector ALUs, in the MFMA output layout
@@ -231,10 +292,10 @@ __global__ __launch_bounds__(kMlpThreads) void k_mlp_grad_block(const GradArgs a
         if (tid < 2 * kTrainTile) {
             const int sm = tid >> 1, o = tid & 1;
             const int64_t i = tile * kTrainTile + sm;
-            const float y = (((P[kOffB5 + o] + yPart[0][o][sm]) + yPart[1][o][sm]) + yPart[2][o][sm]) + yPart[3][o][sm];
+            const float y = (((Ps[kParSB5 + o] + yPart[0][o][sm]) + yPart[1][o][sm]) + yPart[2][o][sm]) + yPart[3][o][sm];
             float d = 0.0f, l = 0.0f;
             if (i < a.n) {
-                const float e = y - (o == 0 ? a.mu_t[i] : a.r_t[i]);
+                const float e = y - target;
                 if (a.loss == 0) {
                     d = e * inv_n;
                     l = 0.5f * e * e * inv_n;
