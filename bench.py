@@ -29,6 +29,8 @@ WEIGHTS = os.path.join(ROOT, "paper_2206_02937_amd", "weights", "sampler_2x64x4.
 PEAK_HBM_GBS = 8000.0
 PEAK_MFMA_TFLOPS = {"mlp_bf16": 2500.0, "mlp_fp8": 5000.0}
 PEAK_FP32_TFLOPS = 157.3
+SIMD_COUNT = 256 * 4
+CLOCK_HZ = 2.4e9
 MLP_MFMA_FLOPS = 3 * 64 * 64 * 2  # hidden 64x64 layers per sample
 WORKLOADS = ["grid_large", "grid", "single_cell", "uneven", "power_law"]
 METRIC = "scattering pairs/s, MLP vs plain sampler, 1 MI355X at KS≤2e-3 vs FP64 oracle"
@@ -76,23 +78,49 @@ def source_digest():
     return h.hexdigest()[:16]
 
 
-def traffic_record(kernel, workload):
-    """HBM bytes per launch of `kernel` on `workload` from the FETCH_SIZE /
-    WRITE_SIZE counter summaries under profiles/ ("traffic-record:" lines),
-    scaled by the copy-kernel calibration recorded there; None when no record
-    matches or the kernel sources changed since the counters were taken."""
+def counter_record(tag, kernel, workload):
+    """The fields of the `tag` line ("traffic-record:", "valu-record:") for
+    `kernel` on `workload` in the counter summaries under profiles/; None
+    when no record matches or the kernel sources changed since the counters
+    were taken."""
     import glob
 
     digest = source_digest()
     for f in sorted(glob.glob(os.path.join(ROOT, "profiles", "counters_*.md"))):
         with open(f) as fh:
             for line in fh:
-                if not line.startswith("traffic-record:"):
+                if not line.startswith(tag):
                     continue
                 kv = dict(t.split("=", 1) for t in line.split()[1:] if "=" in t)
                 if kv.get("kernel") == kernel and kv.get("workload") == workload and kv.get("source_sha") == digest:
-                    return int(kv["bytes_per_launch"])
+                    return kv
     return None
+
+
+def traffic_record(kernel, workload):
+    """HBM bytes per launch of `kernel` on `workload` from the FETCH_SIZE /
+    WRITE_SIZE counters, each scaled by what it reads for a plain device copy
+    of known size (the calibration recorded with them); None as above."""
+    kv = counter_record("traffic-record:", kernel, workload)
+    return int(kv["bytes_per_launch"]) if kv else None
+
+
+def valu_roofline(kernel, workload, avg_ms, units):
+    """VALU-issue roofline of `kernel` on `workload`: the SIMD cycles spent
+    issuing VALU instructions per launch (4 x SQ_ACTIVE_INST_VALU, summed
+    over the chip, from the counter summaries) against every SIMD's cycles
+    over the launch's live average duration (1024 SIMDs at 2.4 GHz); with
+    the VALU instructions per unit of work.  None without a current record."""
+    kv = counter_record("valu-record:", kernel, workload)
+    if kv is None:
+        return None
+    busy = float(kv["valu_busy_cycles"])
+    avail = avg_ms * 1e-3 * SIMD_COUNT * CLOCK_HZ
+    return {"kernel": kernel, "bound": "valu", "achieved": busy / avail, "peak": 1.0,
+            "unit": "fraction of SIMD cycles issuing VALU", "frac": busy / avail,
+            "valu_busy_cycles_per_launch": busy, "wave_valu_insts_per_launch": float(kv["valu_insts"]),
+            "valu_insts_per_unit": float(kv["valu_insts"]) * 64 / units, "unit_of_work": "pair (per lane)",
+            "avg_ms": avg_ms}
 
 
 def storage_bytes(dtype):
@@ -221,36 +249,44 @@ def ntc_stage(ctx, p, steps=50, warmup=5):
     return out
 
 
-def training_stage(ctx, batch=4096, steps=200):
+def training_stage(ctx, batch=4096, steps=200, more_batches=(16384, 65536)):
     """One optimiser step of the sampler network (cs_mlp_train_step: forward,
     backward, fixed-order gradient sum, Adam) at the training driver's batch
     of 4096 samples, on a separate copy of the network: samples/s and the
-    FP32 rate at 75 k flops per sample (forward 25 k, backward 50 k)."""
+    FP32 rate at 75 k flops per sample (forward 25 k, backward 50 k); the
+    same at larger batches, which fill more of the chip (the driver keeps
+    4096: its optimisation is tuned at that batch)."""
     import numpy as np
     import torch
 
     from paper_2206_02937_amd import compton, plasma
 
     net = compton.MLP.load(ctx, WEIGHTS)
-    x, u = plasma.sampler_inputs(batch, seed=11)
-    xd = torch.from_numpy(x.astype(np.float32)).cuda()
-    ud = torch.from_numpy(u.astype(np.float32)).cuda()
-    mu, r = ctx.sample_plain(xd, ud)
-    loss = torch.zeros((), dtype=torch.float32, device="cuda")
-    for _ in range(10):
-        net.train_step(xd, ud, mu, r, lr=1e-4, loss_out=loss)
-    torch.cuda.synchronize()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record()
-    for _ in range(steps):
-        net.train_step(xd, ud, mu, r, lr=1e-4, loss_out=loss)
-    ev1.record()
-    torch.cuda.synchronize()
-    ms = ev0.elapsed_time(ev1) / steps
+
+    def timed(b, n_steps):
+        x, u = plasma.sampler_inputs(b, seed=11)
+        xd = torch.from_numpy(x.astype(np.float32)).cuda()
+        ud = torch.from_numpy(u.astype(np.float32)).cuda()
+        mu, r = ctx.sample_plain(xd, ud)
+        loss = torch.zeros((), dtype=torch.float32, device="cuda")
+        for _ in range(10):
+            net.train_step(xd, ud, mu, r, lr=1e-4, loss_out=loss)
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(n_steps):
+            net.train_step(xd, ud, mu, r, lr=1e-4, loss_out=loss)
+        ev1.record()
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / n_steps
+        tfs = 75e3 * b / (ms * 1e-3) / 1e12
+        return {"batch": b, "ms_per_step": ms, "samples_per_s": b / (ms * 1e-3), "fp32_tflops": tfs,
+                "fp32_frac": tfs / PEAK_FP32_TFLOPS}
+
+    out = timed(batch, steps)
+    out["larger_batches"] = [timed(b, max(20, steps // 4)) for b in more_batches]
     net.close()
-    tfs = 75e3 * batch / (ms * 1e-3) / 1e12
-    return {"batch": batch, "ms_per_step": ms, "samples_per_s": batch / (ms * 1e-3), "fp32_tflops": tfs,
-            "fp32_frac": tfs / PEAK_FP32_TFLOPS}
+    return out
 
 
 def beam_gas_stage(ctx, net, sampler, steps=10, n_cells=4096):
@@ -459,7 +495,8 @@ def pair_roofline(p, run, strategy):
     return {"kernel": "k_pair_compact", "bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": gbs / PEAK_HBM_GBS, "traffic": traffic_record("k_pair_compact", p.name), "bytes_per_launch": b,
             "avg_ms": ms, "units_per_launch": f"{p.n_pairs} pairs, {st['n_collided']} collisions",
-            "working_set_mib": p.nbytes() / 2**20}
+            "working_set_mib": p.nbytes() / 2**20,
+            "valu": valu_roofline("k_pair_compact", p.name, ms, p.n_pairs)}
 
 
 def workload_stage(ctx, p, net, samplers, steps, warmup, autotune_sampler="mlp_bf16", baseline=None,
@@ -664,7 +701,8 @@ def main():
             "frac": achieved / PEAK_HBM_GBS, "traffic": traffic_record(kern, p.name),
             "bytes_per_launch": bytes_launch, "avg_ms": ms, "avg_ms_events": ms_events,
             "event_overhead_ms": overhead,
-            "units_per_launch": f"{n_pairs} pairs, {acc_per_step} collisions"}
+            "units_per_launch": f"{n_pairs} pairs, {acc_per_step} collisions",
+            "valu": valu_roofline(kern, p.name, ms, n_pairs) if kern == "k_pair_compact" else None}
     roof_mlp = mfma_roofline("mlp_bf16", stage, ks)
     roof_mlp_fp8 = mfma_roofline("mlp_fp8", stage, ks)
     uneven = power = None
