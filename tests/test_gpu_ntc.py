@@ -332,3 +332,91 @@ def test_capacity_grows_between_calls(ctx):
     (eb, gb, sb), = b
     assert sa == sb and sa["n_pairs"] > 1000
     assert all(np.array_equal(ea[k], eb[k]) and np.array_equal(ga[k], gb[k]) for k in "xyzw")
+
+
+def _unequal_plasma(dtype):
+    rng = np.random.default_rng(21)
+    counts_e = np.array([5, 0, 17, 300, 3, 1, 0, 40, 513, 1, 64])
+    counts_g = np.array([9, 4, 17, 10, 3, 0, 0, 600, 2, 64, 1])
+    ne, ng = int(counts_e.sum()), int(counts_g.sum())
+    pm = plasma.maxwell_juttner_momentum(rng, ne, 0.5)
+    ux, uy, uz = plasma.isotropic(rng, ne)
+    eps = plasma.log_uniform(rng, ng, 1e-3, 1.0)
+    vx, vy, vz = plasma.isotropic(rng, ng)
+    e = {k: v.astype(dtype) for k, v in {"x": pm * ux, "y": pm * uy, "z": pm * uz,
+                                         "w": rng.uniform(0.5, 2.0, ne)}.items()}
+    g = {k: v.astype(dtype) for k, v in {"x": eps * vx, "y": eps * vy, "z": eps * vz,
+                                         "w": rng.uniform(0.5, 2.0, ng)}.items()}
+    off_e = np.concatenate([[0], np.cumsum(counts_e)]).astype(np.int64)
+    off_g = np.concatenate([[0], np.cumsum(counts_g)]).astype(np.int64)
+    return plasma.Plasma("unequal", e, g, off_e, off_g, 0.5, 0.2, 13)
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_graph_replays_on_uneven_cells_and_chains(ctx, dtype):
+    """Graph replays equal eager steps where every path of the step runs:
+    empty cells, cells of more than 64 candidates (tagged rounds), cells of a
+    lone particle (the serial pass), unequal weights; FP32 and FP64
+    storage; the capacity exactly the largest candidate count."""
+    import torch
+
+    from paper_2206_02937_amd import compton
+
+    p = _unequal_plasma(dtype)
+    steps = [0, 1, 2]
+    eager = _gpu_steps(ctx, p, steps)
+    n_max = max(st["n_pairs"] for _, _, st in eager)
+    assert n_max > 1000
+    e, g, oe, og = compton.to_device(p)
+    stats = ctx.stats_buffer()
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        gr = ctx.ntc_graph(e, g, oe, og, p.dt, p.density_norm, p.seed, n_max, stats=stats)
+        try:
+            gr.set_step(steps[0])
+            for k, (ee, ge, se) in enumerate(eager):
+                gr.launch()
+                stream.synchronize()
+                st = _stats(stats)
+                assert st == se, (k, st, se)
+                he, hg = compton.to_host(e), compton.to_host(g)
+                for key in "xyzw":
+                    assert np.array_equal(he[key], ee[key], equal_nan=True), (k, key)
+                    assert np.array_equal(hg[key], ge[key], equal_nan=True), (k, key)
+        finally:
+            gr.close()
+
+
+def test_graph_layout_errors(ctx):
+    """A graph over offsets that are not a valid layout changes nothing and
+    flags its stats record on every replay; creation refuses particles
+    without cells and a capacity outside [1, 2^31 - 2]."""
+    import torch
+
+    from paper_2206_02937_amd import compton
+
+    q = plasma.grid(seed=2, nx=2, ny=2, per_cell=64, dtype=np.float64)
+    e, g, oe, og = compton.to_device(q)
+    bad = oe.clone()
+    bad[2] = bad[1] - 1
+    stats = ctx.stats_buffer()
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        gr = ctx.ntc_graph(e, g, bad, og, q.dt, q.density_norm, q.seed, 4096, stats=stats)
+        try:
+            for _ in range(2):
+                gr.launch()
+                stream.synchronize()
+                st = _stats(stats)
+                assert st["layout_error"] == 1 and st["n_pairs"] == 0
+        finally:
+            gr.close()
+        assert all(np.array_equal(compton.to_host(e)[k], q.e[k]) for k in "xyzw")
+        for cap in (0, 1 << 31):
+            with pytest.raises(RuntimeError):
+                ctx.ntc_graph(e, g, oe, og, q.dt, q.density_norm, q.seed, cap, stats=stats)
+        no_cells = torch.zeros(1, dtype=torch.int64, device="cuda")
+        with pytest.raises(RuntimeError):
+            ctx.ntc_graph(e, g, no_cells, no_cells, q.dt, q.density_norm, q.seed, 16, stats=stats)
