@@ -420,3 +420,34 @@ def test_graph_layout_errors(ctx):
         no_cells = torch.zeros(1, dtype=torch.int64, device="cuda")
         with pytest.raises(RuntimeError):
             ctx.ntc_graph(e, g, no_cells, no_cells, q.dt, q.density_norm, q.seed, 16, stats=stats)
+
+
+def test_too_many_candidates(ctx):
+    """A cell whose expected candidate count N_e N_g P_max reaches 2^31 - 1
+    (2^16 x 2^16 particles, P_max = 2): the call fails with
+    CS_ERR_UNSUPPORTED before any candidate is drawn, no particle changes,
+    and the stats record is flagged (overflow = 1, n_pairs = 2^31 - 1)."""
+    import torch
+
+    from paper_2206_02937_amd import compton
+
+    rng = np.random.default_rng(31)
+    n = 1 << 16
+    ux, uy, uz = plasma.isotropic(rng, n)
+    vx, vy, vz = plasma.isotropic(rng, n)
+    e = {"x": (2 * ux).astype(np.float32), "y": (2 * uy).astype(np.float32), "z": (2 * uz).astype(np.float32),
+         "w": np.ones(n, np.float32)}
+    g = {"x": (0.1 * vx).astype(np.float32), "y": (0.1 * vy).astype(np.float32),
+         "z": (0.1 * vz).astype(np.float32), "w": np.ones(n, np.float32)}
+    off = np.array([0, n], dtype=np.int64)
+    p = plasma.Plasma("too_many", e, g, off, off.copy(), 1.0, 1.0, 3)
+    de, dg, oe, og = compton.to_device(p)
+    buf = ctx.stats_buffer()
+    with pytest.raises(RuntimeError) as info:
+        ctx.ntc_step(de, dg, oe, og, p.dt, p.density_norm, p.seed, 0, stats=buf)
+    assert "candidates" in str(info.value)
+    torch.cuda.synchronize()
+    st = compton.decode_stats(buf)
+    assert st["overflow"] == 1 and st["n_pairs"] == (1 << 31) - 1 and st["n_collided"] == 0
+    assert all(np.array_equal(compton.to_host(de)[k], e[k]) for k in "xyzw")
+    assert all(np.array_equal(compton.to_host(dg)[k], g[k]) for k in "xyzw")
