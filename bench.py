@@ -31,6 +31,12 @@ PEAK_MFMA_TFLOPS = {"mlp_bf16": 2500.0, "mlp_fp8": 5000.0}
 PEAK_FP32_TFLOPS = 157.3
 SIMD_COUNT = 256 * 4
 CLOCK_HZ = 2.4e9
+# the network's SiLU issues two transcendental instructions (exp2, reciprocal)
+# per activation, 256 activations per sample; one wavefront transcendental
+# instruction takes ~11.7 cycles on this part (measured), so at most
+# SIMD_COUNT x CLOCK_HZ x 64 / (512 x 11.7) samples/s
+TRANS_CYCLES = 11.7
+SILU_CEILING = SIMD_COUNT * CLOCK_HZ * 64 / (512 * TRANS_CYCLES)
 MLP_MFMA_FLOPS = 3 * 64 * 64 * 2  # hidden 64x64 layers per sample
 WORKLOADS = ["grid_large", "grid", "single_cell", "uneven", "power_law"]
 METRIC = "scattering pairs/s, MLP vs plain sampler, 1 MI355X at KS≤2e-3 vs FP64 oracle"
@@ -121,6 +127,32 @@ def valu_roofline(kernel, workload, avg_ms, units):
             "valu_busy_cycles_per_launch": busy, "wave_valu_insts_per_launch": float(kv["valu_insts"]),
             "valu_insts_per_unit": float(kv["valu_insts"]) * 64 / units, "unit_of_work": "pair (per lane)",
             "avg_ms": avg_ms}
+
+
+def hbm_copy_stage(mib=512, reps=20):
+    """The HBM bandwidth a plain device-to-device copy reaches on this machine: a
+    512 MiB buffer (twice the Infinity Cache) copied `reps` times, timed with
+    HIP events; bytes moved = read + written.  Context for the HBM rooflines,
+    whose peak stays the published 8 TB/s."""
+    import torch
+
+    src = torch.ones((mib << 20) // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / reps
+    moved = 2 * src.numel() * 4
+    del src, dst
+    torch.cuda.empty_cache()
+    gbs = moved / (ms * 1e-3) / 1e9
+    return {"gbs": gbs, "bytes_per_copy": moved, "ms_per_copy": ms, "frac_of_peak": gbs / PEAK_HBM_GBS}
 
 
 def storage_bytes(dtype):
@@ -475,9 +507,11 @@ def mfma_roofline(prec, stage, ks):
         return None
     t = ks[prec]["t"]
     tf = stage["n"] * MLP_MFMA_FLOPS / t / 1e12
+    rate = stage["n"] / t
     return {"kernel": f"k_mlp_mfma<{prec[4:]}>", "bound": "mfma", "achieved": tf, "peak": PEAK_MFMA_TFLOPS[prec],
             "unit": "TFLOP/s", "frac": tf / PEAK_MFMA_TFLOPS[prec], "traffic": None,
-            "flops_per_launch": stage["n"] * MLP_MFMA_FLOPS, "avg_ms": t * 1e3}
+            "flops_per_launch": stage["n"] * MLP_MFMA_FLOPS, "avg_ms": t * 1e3,
+            "silu_ceiling_samples_per_s": SILU_CEILING, "samples_per_s": rate, "silu_frac": rate / SILU_CEILING}
 
 
 def pair_roofline(p, run, strategy):
@@ -625,6 +659,8 @@ def main():
 
     from paper_2206_02937_amd import compton, plasma
 
+    copy_bw = hbm_copy_stage()
+    print(json.dumps({"progress": "hbm copy", **copy_bw}), flush=True)
     p = plasma.make(args.workload, seed=0)
     n_pairs = p.n_pairs
     ctx = compton.Context(0)
@@ -773,6 +809,7 @@ def main():
                                              "vs_plain": None if plain_run is None else
                                              fp8_run["pairs_per_s"] / plain_run["pairs_per_s"]},
         "roofline": roof,
+        "hbm_copy": copy_bw,
         "roofline_mlp": roof_mlp,
         "roofline_mlp_fp8": roof_mlp_fp8,
         "error_vs_oracle": parity,
@@ -786,6 +823,10 @@ def main():
         "cpu_baseline": cpu,
         "last_stats": st,
     }
+    for r in (roof, (uneven or {}).get("roofline"), (power or {}).get("roofline"), (binned or {}).get("roofline"),
+              (pnet or {}).get("roofline")):
+        if r and r.get("bound") == "hbm":
+            r["frac_of_copy"] = r["achieved"] / copy_bw["gbs"]
     print(json.dumps(line), flush=True)
     if args.traffic_calibration:
         # a plain copy kernel of known size: its FETCH_SIZE / WRITE_SIZE
