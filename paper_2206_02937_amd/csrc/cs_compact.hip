@@ -303,25 +303,39 @@ __global__ __launch_bounds__(kChunk) void k_pair_compact(const CompactArgs<T> a)
 // Segmented list: prefix sums over the pair workgroups' counts, computed by
 // every collide workgroup instead of a look-back chain in the pair kernel
 // (whose workgroups, finishing together, would wait for one another).
-// Thread t of NT takes counts [P t, P (t + 1)), P = kSegMax / NT; s receives
-// the n <= kSegMax exclusive prefixes.  Called by every thread; returns the
-// total.
+// Thread t of NT takes counts [P t, P (t + 1)), P = kSegMax / NT: seg_load
+// reads them (issued only, so that other reads can join them), seg_scan
+// writes the n <= kSegMax exclusive prefixes to s and returns the total.
+// Both are called by every thread.
 constexpr int kSegMax = 4096;
 
 template <int NT>
-__device__ __forceinline__ int32_t seg_prefix(const int32_t* cnt, int n, int32_t* s, int32_t* s_wtot) {
+struct SegCounts {
+    int32_t v[kSegMax / NT];
+};
+
+template <int NT>
+__device__ __forceinline__ SegCounts<NT> seg_load(const int32_t* cnt, int n) {
+    constexpr int kSegPerThread = kSegMax / NT;
+    const int k0 = (int)threadIdx.x * kSegPerThread;
+    SegCounts<NT> c;
+#pragma unroll
+    for (int i = 0; i < kSegPerThread; ++i) c.v[i] = k0 + i < n ? cnt[k0 + i] : 0;
+    return c;
+}
+
+template <int NT>
+__device__ __forceinline__ int32_t seg_scan(SegCounts<NT> c, int n, int32_t* s, int32_t* s_wtot) {
     constexpr int kSegPerThread = kSegMax / NT;
     const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
     const int k0 = tid * kSegPerThread;
-    int32_t v[kSegPerThread];
-#pragma unroll
-    for (int i = 0; i < kSegPerThread; ++i) v[i] = k0 + i < n ? cnt[k0 + i] : 0;
+    int32_t* v = c.v;
     int32_t run = 0;
 #pragma unroll
     for (int i = 0; i < kSegPerThread; ++i) {
-        const int32_t c = v[i];
+        const int32_t x = v[i];
         v[i] = run;
-        run += c;
+        run += x;
     }
     int32_t incl = run;  // inclusive scan of the thread totals over the wave
 #pragma unroll
@@ -398,8 +412,11 @@ __global__ __launch_bounds__(SAMP == CS_SAMPLER_PLAIN ? kDenseThreads : kDenseNe
     const int tid = threadIdx.x;
     const int lane = lane_id();
     const int wave = tid >> 6;
-    net_load<SAMP>(s_net, a.mlp);
-    if constexpr (NET) __syncthreads();
+    // the network's copy, the control block and the segment counts are read
+    // together (the counts whatever the layout), then the copy is stored
+    // while the counts are still in flight; the scan's barriers publish it
+    NetFetch<SAMP, NT> nf;
+    nf.fetch(a.mlp);
     StepControl* ctrl = a.ctrl;
     const uint32_t E = ctrl->epoch;
     const uint64_t step = ctrl->step;
@@ -407,12 +424,14 @@ __global__ __launch_bounds__(SAMP == CS_SAMPLER_PLAIN ? kDenseThreads : kDenseNe
     const bool seg = a.n_seg > 0;  // uniform
     int64_t A;
     if (seg) {
-        // (the counts are read whatever the layout, so that their reads need
-        // not wait for the control block's)
-        const int32_t total = seg_prefix<NT>(a.seg_count, a.n_seg, s_seg, s_wtot);
+        const SegCounts<NT> cnt = seg_load<NT>(a.seg_count, a.n_seg);
+        nf.store(s_net);
+        const int32_t total = seg_scan<NT>(cnt, a.n_seg, s_seg, s_wtot);
         A = layout_ok ? (int64_t)total : 0;
         if (blockIdx.x == 0 && tid == 0) ctrl->n_accepted = (uint32_t)A;
     } else {
+        nf.store(s_net);
+        if constexpr (NET) __syncthreads();
         A = layout_ok ? (int64_t)ctrl->n_accepted : 0;
     }
     const int64_t seg_len = (int64_t)kChunk * a.chunks_per_block;

@@ -80,26 +80,23 @@ __device__ __forceinline__ uint8_t to_e4m3(float v) {
 // the hidden biases times kSiluScale, W5 divided by it, b5 as is.
 constexpr int cW1 = 0, cB1 = 128, cB2 = 192, cB3 = 256, cB4 = 320, cW5 = 384, cB5 = 512, kSmall = 514;
 
+// Entry i of the compact copy: where it comes from in the parameter block,
+// and its value there scaled as the engine keeps it.
+__device__ __forceinline__ int small_param_src(int i) {
+    if (i < cB1) return kOffW1 + i;
+    if (i < cB2) return kOffB1 + (i - cB1);
+    if (i < cB3) return kOffB2 + (i - cB2);
+    if (i < cB4) return kOffB3 + (i - cB3);
+    if (i < cW5) return kOffB4 + (i - cB4);
+    if (i < cB5) return kOffW5 + (i - cW5);
+    return kOffB5 + (i - cB5);
+}
+__device__ __forceinline__ float small_param_value(int i, float v) {
+    return i < cW5 ? v * kSiluScale : (i < cB5 ? v / kSiluScale : v);
+}
+
 __device__ __forceinline__ void load_small_params(const float* P, float* s) {
-    for (int i = threadIdx.x; i < kSmall; i += blockDim.x) {
-        int src;
-        if (i < cB1)
-            src = kOffW1 + i;
-        else if (i < cB2)
-            src = kOffB1 + (i - cB1);
-        else if (i < cB3)
-            src = kOffB2 + (i - cB2);
-        else if (i < cB4)
-            src = kOffB3 + (i - cB3);
-        else if (i < cW5)
-            src = kOffB4 + (i - cB4);
-        else if (i < cB5)
-            src = kOffW5 + (i - cW5);
-        else
-            src = kOffB5 + (i - cB5);
-        const float v = P[src];
-        s[i] = i < cW5 ? v * kSiluScale : (i < cB5 ? v / kSiluScale : v);
-    }
+    for (int i = threadIdx.x; i < kSmall; i += blockDim.x) s[i] = small_param_value(i, P[small_param_src(i)]);
 }
 
 template <int PREC>
@@ -356,6 +353,53 @@ __device__ __forceinline__ void net_load(NetLds<SAMP>& s, const MlpDev& m) {
         if (threadIdx.x < 6) s.sc[threadIdx.x] = SAMP == CS_SAMPLER_MLP_FP8 ? m.fp8_scales[threadIdx.x] : 1.0f;
     }
 }
+
+// The same copy in two phases for a workgroup of NT threads, so that a
+// kernel can issue its global reads together with its own and wait once:
+// fetch reads this thread's share into registers (every read unconditional,
+// clamped into the arrays), store writes it to LDS; a barrier must follow
+// before the copy is read.  Nothing to do for the other samplers.
+template <int SAMP, int NT, bool MFMA = SAMP == CS_SAMPLER_MLP_BF16 || SAMP == CS_SAMPLER_MLP_FP8>
+struct NetFetch {
+    __device__ __forceinline__ void fetch(const MlpDev&) {}
+    __device__ __forceinline__ void store(NetLds<SAMP>&) const {}
+};
+template <int SAMP, int NT>
+struct NetFetch<SAMP, NT, true> {
+    typedef typename FragT<SAMP>::type FT;
+    static constexpr int kF = (kFragCount + NT - 1) / NT;
+    static constexpr int kP = (kSmall + NT - 1) / NT;
+    FT f[kF];
+    float p[kP];
+    float sc;
+    __device__ __forceinline__ void fetch(const MlpDev& m) {
+        const FT* src = (const FT*)(SAMP == CS_SAMPLER_MLP_BF16 ? m.frag_bf16 : m.frag_fp8);
+#pragma unroll
+        for (int q = 0; q < kF; ++q) {
+            const int i = (int)threadIdx.x + q * NT;
+            f[q] = src[i < kFragCount ? i : kFragCount - 1];
+        }
+#pragma unroll
+        for (int q = 0; q < kP; ++q) {
+            const int i = (int)threadIdx.x + q * NT;
+            p[q] = m.params[small_param_src(i < kSmall ? i : kSmall - 1)];
+        }
+        sc = SAMP == CS_SAMPLER_MLP_FP8 ? m.fp8_scales[threadIdx.x < 6 ? threadIdx.x : 0] : 1.0f;
+    }
+    __device__ __forceinline__ void store(NetLds<SAMP>& s) const {
+#pragma unroll
+        for (int q = 0; q < kF; ++q) {
+            const int i = (int)threadIdx.x + q * NT;
+            if (i < kFragCount) s.frag[i] = f[q];
+        }
+#pragma unroll
+        for (int q = 0; q < kP; ++q) {
+            const int i = (int)threadIdx.x + q * NT;
+            if (i < kSmall) s.P[i] = small_param_value(i, p[q]);
+        }
+        if (threadIdx.x < 6) s.sc[threadIdx.x] = sc;
+    }
+};
 
 // The network's two outputs for every lane of the wave with need == true
 // (features f1, f2 of the lane's own sample); other lanes get 0.  Must be

@@ -147,7 +147,15 @@ struct NtcArgs {
     int32_t *lst_c, *lst_1, *lst_2;
     int32_t *cnt_c, *cnt_1, *cnt_2;
     int64_t n_seg;  // segments of the capacity
+    int64_t cap;    // candidates the arrays hold
 };
+
+// The kernels below issue every read that does not depend on another one
+// (the control words, the live values, their own inputs -- speculatively,
+// clamped into the arrays) before they wait for any, and only then test
+// whether the step proceeds: each read chain costs a memory round trip, and
+// the waves of a launch run in few generations, so the round trips, not the
+// arithmetic, set the kernels' length.
 
 // The step's values that live on the device: the candidate total, the tag
 // epoch and (graph replays) the step index.
@@ -351,21 +359,25 @@ __device__ __forceinline__ int block_slot(bool take, int* lds, int* total) {
 // candidate of a larger cell registers for round 0 (kNtcLarge).
 template <typename T>
 __global__ __launch_bounds__(kNtcThreads) void k_ntc_pick(const NtcArgs<T> a_in) {
-    if (!a_in.ctl->go) return;  // (uniform) the step does not proceed
-    const NtcArgs<T> a = ntc_live(a_in);
     const int lane = lane_id();
     const int64_t c = (int64_t)blockIdx.x * (kNtcThreads / 64) + (threadIdx.x >> 6);
-    if (c >= a.n_cells) return;  // (uniform in the wave)
+    if (c >= a_in.n_cells) return;  // (uniform in the wave)
+    const int32_t go = a_in.ctl->go;
+    const NtcArgs<T> a = ntc_live(a_in);
+    const bool last = c + 1 == a.n_cells;
     // cand_off holds prefixes within each scan block: add the block offsets,
     // and keep the full offsets for the serial pass
-    const int64_t j0 = a.cand_off[c] + a.boff[c / kNtcScanBlock];
-    const int64_t j1 = c + 1 < a.n_cells ? a.cand_off[c + 1] + a.boff[(c + 1) / kNtcScanBlock] : a.total;
+    const int64_t co0 = a.cand_off[c], bo0 = a.boff[c / kNtcScanBlock];
+    const int64_t co1 = last ? 0 : a.cand_off[c + 1], bo1 = last ? 0 : a.boff[(c + 1) / kNtcScanBlock];
+    const int64_t e0 = a.off_e[c], e1 = a.off_e[c + 1], g0 = a.off_g[c], g1 = a.off_g[c + 1];
+    if (!go) return;  // (uniform) the step does not proceed
+    const int64_t j0 = co0 + bo0;
+    const int64_t j1 = last ? a.total : co1 + bo1;
     if (lane == 0) {
         a.cand_full[c] = j0;
-        if (c + 1 == a.n_cells) a.cand_full[c + 1] = j1;
+        if (last) a.cand_full[c + 1] = j1;
     }
-    const int64_t e0 = a.off_e[c], g0 = a.off_g[c];
-    const uint64_t nec = (uint64_t)(a.off_e[c + 1] - e0), ngc = (uint64_t)(a.off_g[c + 1] - g0);
+    const uint64_t nec = (uint64_t)(e1 - e0), ngc = (uint64_t)(g1 - g0);
     const bool small = j1 - j0 <= 64;
     for (int64_t jb = j0; jb < j1; jb += 64) {
         const int64_t j = jb + lane;
@@ -472,15 +484,16 @@ __device__ __forceinline__ void ntc_collide(const NtcArgs<T>& a, int64_t j, int3
 template <typename T>
 __global__ __launch_bounds__(kNtcSeg) void k_ntc_eval(const NtcArgs<T> a_in) {
     __shared__ int s_acc[kNtcSeg / 64], s_later[kNtcSeg / 64];
-    if (!a_in.ctl->go) return;  // (uniform)
-    const NtcArgs<T> a = ntc_live(a_in);
     const int64_t base = (int64_t)blockIdx.x * kNtcSeg;
-    if (base >= a.total) return;  // (uniform) past the candidates
     const int64_t j = base + threadIdx.x;
+    const int64_t jc = j < a_in.cap ? j : a_in.cap - 1;
+    const int32_t go = a_in.ctl->go;
+    const NtcArgs<T> a = ntc_live(a_in);
+    const uint8_t st = a.status[jc];
+    const int32_t ie = a.c_ie[jc], ig = a.c_ig[jc], cell = a.c_cell[jc];
+    if (!go || base >= a.total) return;  // (uniform) no step, or past the candidates
     bool acc = false, later = false;
     if (j < a.total) {
-        const uint8_t st = a.status[j];
-        const int32_t ie = a.c_ie[j], ig = a.c_ig[j];
         bool ready = st == 0;
         if (st & kNtcLarge) {
             const unsigned long long mine = ntc_tag(a.epoch, j);
@@ -494,7 +507,7 @@ __global__ __launch_bounds__(kNtcSeg) void k_ntc_eval(const NtcArgs<T> a_in) {
         } else if (st & kNtcLater) {
             later = true;
         }
-        if (ready) acc = ntc_evaluate<T>(a, j, a.c_cell[j], ie, ig);
+        if (ready) acc = ntc_evaluate<T>(a, j, cell, ie, ig);
     }
     int n_acc, n_later;
     const int pa = seg_slot(acc, s_acc, &n_acc);
@@ -516,12 +529,13 @@ __global__ __launch_bounds__(kNtcSeg) void k_ntc_eval(const NtcArgs<T> a_in) {
 // consecutive workgroups, which the dispatcher deals out over all XCDs.
 template <typename T>
 __global__ __launch_bounds__(kNtcThreads) void k_ntc_collide_list(const NtcArgs<T> a_in) {
-    if (!a_in.ctl->go) return;  // (uniform)
     const int64_t seg = blockIdx.x % a_in.n_seg;
     const int i = (int)(blockIdx.x / a_in.n_seg) * kNtcThreads + (int)threadIdx.x;
-    if (seg * kNtcSeg >= a_in.ctl->total || i >= a_in.cnt_c[seg]) return;
+    const int32_t go = a_in.ctl->go;
     const NtcArgs<T> a = ntc_live(a_in);
-    const int64_t j = a.lst_c[seg * kNtcSeg + i];
+    const int32_t n = a.cnt_c[seg];
+    const int64_t j = a.lst_c[seg * kNtcSeg + i];  // (read whatever the count: i < kNtcSeg)
+    if (!go || seg * kNtcSeg >= a.total || i >= n) return;
     ntc_collide<T>(a, j, a.c_cell[j], a.c_ie[j], a.c_ig[j]);
 }
 
@@ -536,23 +550,25 @@ __global__ __launch_bounds__(kNtcThreads) void k_ntc_collide_list(const NtcArgs<
 template <typename T>
 __global__ __launch_bounds__(kNtcThreads) void k_ntc_round(const NtcArgs<T> a_in, int t) {
     __shared__ int s_later[kNtcThreads / 64];
-    if (!a_in.ctl->go) return;  // (uniform)
     const int64_t seg = blockIdx.x % a_in.n_seg;
-    if (seg * kNtcSeg >= a_in.ctl->total) return;  // (uniform) past the candidates
     const int sub = (int)(blockIdx.x / a_in.n_seg) * kNtcThreads;
+    const int64_t chunk = (int64_t)blockIdx.x * kNtcThreads;  // this workgroup's chunk of the lists
+    const int32_t go = a_in.ctl->go;
+    const NtcArgs<T> a = ntc_live(a_in);
     // entries of this workgroup: round 1, the part [sub, sub + kNtcThreads)
-    // of the segment's list; round 2, its own chunk
-    const int n = t == 1 ? min(a_in.cnt_1[seg] - sub, kNtcThreads) : a_in.cnt_2[blockIdx.x];
+    // of the segment's list; round 2, its own chunk (read whatever the count)
+    const int32_t cnt = t == 1 ? a.cnt_1[seg] : a.cnt_2[blockIdx.x];
+    const int64_t j_l = t == 1 ? a.lst_1[seg * kNtcSeg + sub + threadIdx.x] : a.lst_2[chunk + threadIdx.x];
+    if (!go || seg * kNtcSeg >= a.total) return;  // (uniform) no step, or past the candidates
+    const int n = t == 1 ? min(cnt - sub, kNtcThreads) : cnt;
     if (n <= 0) {
-        if (t == 1 && threadIdx.x == 0) a_in.cnt_2[blockIdx.x] = 0;
+        if (t == 1 && threadIdx.x == 0) a.cnt_2[blockIdx.x] = 0;
         return;  // (uniform)
     }
-    const NtcArgs<T> a = ntc_live(a_in);
-    const int64_t chunk = (int64_t)blockIdx.x * kNtcThreads;  // this workgroup's chunk of the lists
     bool later = false;
     int64_t j = 0;
     if ((int)threadIdx.x < n) {
-        j = t == 1 ? a.lst_1[seg * kNtcSeg + sub + threadIdx.x] : a.lst_2[chunk + threadIdx.x];
+        j = j_l;
         const int32_t ie = a.c_ie[j], ig = a.c_ig[j], c = a.c_cell[j];
         const unsigned long long* te = a.touch_e + (t & 1) * a.cap_e;
         const unsigned long long* tg = a.touch_g + (t & 1) * a.cap_g;
@@ -581,7 +597,10 @@ __global__ __launch_bounds__(kNtcThreads) void k_ntc_round(const NtcArgs<T> a_in
 template <typename T>
 __global__ __launch_bounds__(kNtcThreads) void k_ntc_serial(const NtcArgs<T> a_in) {
     const int64_t c = (int64_t)blockIdx.x * (kNtcThreads / 64) + (threadIdx.x >> 6);
-    if (!a_in.ctl->go || c >= a_in.n_cells || !a_in.pending[c]) return;  // (uniform in the wave)
+    if (c >= a_in.n_cells) return;  // (uniform in the wave)
+    const int32_t go = a_in.ctl->go;
+    const uint8_t pend = a_in.pending[c];
+    if (!go || !pend) return;  // (uniform in the wave)
     const NtcArgs<T> a = ntc_live(a_in);
     const int lane = lane_id();
     const int64_t j0 = a.cand_full[c], j1 = a.cand_full[c + 1];
@@ -638,27 +657,39 @@ __device__ __forceinline__ NtcPart block_sum_part(NtcPart v, NtcPart* lds) {
 
 __global__ __launch_bounds__(kNtcThreads) void k_ntc_reduce(const uint8_t* status, const double* ratio,
                                                           const double* eb, const double* ea, const NtcCtl* ctl,
-                                                          NtcPart* part) {
+                                                          int64_t cap, NtcPart* part) {
     __shared__ NtcPart s[kNtcThreads / 64];
-    const int64_t total = ctl->total;
-    // (uniform) the step did not proceed, or a workgroup past the candidates
-    if (!ctl->go || (int64_t)blockIdx.x * kNtcThreads * kNtcRedPer >= total) return;
-    NtcPart v = {0.0, 0.0, 0.0, 0, 0, 0};
     const int64_t base = (int64_t)blockIdx.x * kNtcThreads * kNtcRedPer + threadIdx.x;
+    const int64_t total = ctl->total;
+    const int32_t go = ctl->go;
+    uint8_t st[kNtcRedPer];
+    double rt[kNtcRedPer], b[kNtcRedPer], e[kNtcRedPer];
+#pragma unroll
+    for (int q = 0; q < kNtcRedPer; ++q) {  // (clamped into the arrays; used below the total only)
+        const int64_t j = base + (int64_t)q * kNtcThreads;
+        const int64_t jc = j < cap ? j : cap - 1;
+        st[q] = status[jc];
+        rt[q] = ratio[jc];
+        b[q] = eb[jc];
+        e[q] = ea[jc];
+    }
+    // (uniform) the step did not proceed, or a workgroup past the candidates
+    if (!go || (int64_t)blockIdx.x * kNtcThreads * kNtcRedPer >= total) return;
+    NtcPart v = {0.0, 0.0, 0.0, 0, 0, 0};
+#pragma unroll
     for (int q = 0; q < kNtcRedPer; ++q) {
         const int64_t j = base + (int64_t)q * kNtcThreads;
         if (j >= total) break;
-        const uint8_t st = status[j];
-        if (st & 4) {
+        if (st[q] & 4) {
             v.inv += 1;
             continue;
         }
-        v.prob += ratio[j];
-        v.clip += (st & 8) ? 1 : 0;
-        if (st & 2) {
+        v.prob += rt[q];
+        v.clip += (st[q] & 8) ? 1 : 0;
+        if (st[q] & 2) {
             v.coll += 1;
-            v.eb += eb[j];
-            v.ea += ea[j];
+            v.eb += b[q];
+            v.ea += e[q];
         }
     }
     const NtcPart r = block_sum_part(v, s);
@@ -898,6 +929,7 @@ static hipError_t ntc_enqueue(const NtcState& s, const cs_species& e, const cs_s
     a.cnt_1 = (int32_t*)(q += l.b_cnt);
     a.cnt_2 = (int32_t*)(q += l.b_cnt);
     a.n_seg = l.n_seg > 0 ? l.n_seg : 1;
+    a.cap = cap > 0 ? cap : 1;
     a.touch_e = touch;
     a.touch_g = touch + 2 * s.cap_e;
     a.cap_e = s.cap_e;
@@ -913,7 +945,8 @@ static hipError_t ntc_enqueue(const NtcState& s, const cs_species& e, const cs_s
     }
     if (n_cells > 0) k_ntc_serial<T><<<(unsigned)l.n_pb, kNtcThreads, 0, st>>>(a);
     if (cap > 0)
-        k_ntc_reduce<<<(unsigned)l.n_part, kNtcThreads, 0, st>>>(a.status, a.r_ratio, a.r_eb, a.r_ea, ctl, part);
+        k_ntc_reduce<<<(unsigned)l.n_part, kNtcThreads, 0, st>>>(a.status, a.r_ratio, a.r_eb, a.r_ea, ctl, a.cap,
+                                                                 part);
     k_ntc_final<<<1, kNtcThreads, 0, st>>>(part, stats, ctl, head);
     return hipGetLastError();
 }
