@@ -340,6 +340,53 @@ def test_strategies_agree_with_network(ctx, mo, precision):
     net.close()
 
 
+@pytest.mark.parametrize("precision", ["mlp_bf16", "mlp_fp8"])
+def test_network_list_modes_identical(ctx, mo, precision):
+    """The compact strategy's collide kernel with a network sampler, in both
+    of its accepted-pair list layouts: one pair chunk per pair workgroup on
+    a 68x68-cell grid (4624 workgroups, more than the 4096 whose segment
+    counts a collide workgroup scans: the look-back list) and 16 chunks per
+    workgroup (the segments).  Both give the fused strategy's bits."""
+    import torch
+
+    from paper_2206_02937_amd import compton
+
+    p = plasma.grid(seed=23, nx=68, ny=68, per_cell=256)
+    p.dt *= 4.0
+    assert int(np.minimum(np.diff(p.off_e), np.diff(p.off_g)).sum()) // 256 > 4096
+    net = compton.MLP(ctx, _net_params(mo))
+    if precision == "mlp_bf16":
+        net.quantize(precision)
+    else:
+        cx, cu = plasma.sampler_inputs(4096, seed=7)
+        net.quantize(precision, _dev(cx.astype(np.float32)), _dev(cu.astype(np.float32)))
+    outs = []
+    try:
+        for strategy, chunks in (("fused", 0), ("compact", 1), ("compact", 16)):
+            _log(f"  {precision} {strategy} chunks per workgroup {chunks}")
+            ctx.set_strategy(strategy)
+            ctx.set_chunks_per_block(chunks)
+            ctx.set_pairs_per_lane(1 if strategy == "compact" else 0)
+            e, g, oe, og = compton.to_device(p)
+            stats = ctx.stats_buffer()
+            for s in range(2):
+                ctx.step(e, g, oe, og, p.dt, p.density_norm, p.seed, s, sampler=precision, mlp=net, stats=stats)
+            torch.cuda.synchronize()
+            outs.append((compton.to_host(e), compton.to_host(g), compton.decode_stats(stats)))
+    finally:
+        ctx.set_strategy("fused")
+        ctx.set_chunks_per_block(0)
+        ctx.set_pairs_per_lane(0)
+    e0, g0, s0 = outs[0]
+    assert s0["n_collided"] > 0
+    for e1, g1, s1 in outs[1:]:
+        for c in "xyzw":
+            assert np.array_equal(e0[c], e1[c]) and np.array_equal(g0[c], g1[c])
+        for k in ("n_pairs", "n_collided", "n_clipped", "n_invalid", "n_fallback"):
+            assert s0[k] == s1[k]
+    net.close()
+
+
 def test_network_sampler_errors(ctx, mo):
     import torch
 
