@@ -131,6 +131,10 @@ __device__ __forceinline__ typename FragT<PREC>::type pack_inputs(const float (&
     }
 }
 
+// Four consecutive parameters of the compact copy (f a multiple of 4: every
+// group below starts on a 16-byte boundary) in one LDS read.
+__device__ __forceinline__ float4 ld4(const float* P_lds, int f) { return *(const float4*)(P_lds + f); }
+
 // NTL tiles of 16 samples each on one wave, evaluated side by side (their
 // MFMA and SiLU chains are independent, so each hides the others' latency).
 // For tile k every lane passes the features of sample (lane % 16) in f1[k],
@@ -156,11 +160,17 @@ __device__ __forceinline__ void mlp_tiles(const typename FragT<PREC>::type* frag
         for (int half = 0; half < 2; ++half) {
             float h[NTL][8];
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const int n = 16 * (2 * half + e / 4) + 4 * g + (e & 3);
-                const float w1a = P_lds[cW1 + 2 * n], w1b = P_lds[cW1 + 2 * n + 1], b1 = P_lds[cB1 + n];
+            for (int q = 0; q < 2; ++q) {
+                // neurons nb .. nb + 3: their (W1 row, b1) as three 16-byte reads
+                const int nb = 16 * (2 * half + q) + 4 * g;
+                const float4 wa = ld4(P_lds, cW1 + 2 * nb), wb = ld4(P_lds, cW1 + 2 * nb + 4), b1 = ld4(P_lds, cB1 + nb);
+                const float w1a[4] = {wa.x, wa.z, wb.x, wb.z}, w1b[4] = {wa.y, wa.w, wb.y, wb.w};
+                const float b1v[4] = {b1.x, b1.y, b1.z, b1.w};
 #pragma unroll
-                for (int k = 0; k < NTL; ++k) h[k][e] = silu_scaled(fmaf(w1b, f2[k], fmaf(w1a, f1[k], b1)));
+                for (int e = 0; e < 4; ++e)
+#pragma unroll
+                    for (int k = 0; k < NTL; ++k)
+                        h[k][4 * q + e] = silu_scaled(fmaf(w1b[e], f2[k], fmaf(w1a[e], f1[k], b1v[e])));
             }
 #pragma unroll
             for (int k = 0; k < NTL; ++k) {
@@ -190,9 +200,8 @@ __device__ __forceinline__ void mlp_tiles(const typename FragT<PREC>::type* frag
         for (int t = 0; t < 4; ++t) {
             const FT A0 = frag[((L * 4 + t) * 2 + 0) * 64 + lane];
             const FT A1 = frag[((L * 4 + t) * 2 + 1) * 64 + lane];
-            float bias[4];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) bias[r] = P_lds[offB[L] + 16 * t + 4 * g + r];
+            const float4 b4 = ld4(P_lds, offB[L] + 16 * t + 4 * g);
+            const float bias[4] = {b4.x, b4.y, b4.z, b4.w};
 #pragma unroll
             for (int k = 0; k < NTL; ++k) {
                 floatx4 acc;
@@ -213,11 +222,12 @@ __device__ __forceinline__ void mlp_tiles(const typename FragT<PREC>::type* frag
                 }
                 if (L == 2) {
                     // output layer sums, neuron order t ascending then r
+                    const float4 v0 = ld4(P_lds, cW5 + 16 * t + 4 * g), v1 = ld4(P_lds, cW5 + kMlpHidden + 16 * t + 4 * g);
+                    const float w50[4] = {v0.x, v0.y, v0.z, v0.w}, w51[4] = {v1.x, v1.y, v1.z, v1.w};
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
-                        const int n = 16 * t + 4 * g + r;
-                        p0[k] = fmaf(P_lds[cW5 + n], o[r], p0[k]);
-                        p1[k] = fmaf(P_lds[cW5 + kMlpHidden + n], o[r], p1[k]);
+                        p0[k] = fmaf(w50[r], o[r], p0[k]);
+                        p1[k] = fmaf(w51[r], o[r], p1[k]);
                     }
                 } else if ((t & 1) == 0) {
 #pragma unroll
@@ -331,13 +341,13 @@ struct NetLds<CS_SAMPLER_MLP_F32> {
 template <>
 struct NetLds<CS_SAMPLER_MLP_BF16> {
     bf16x8 frag[kFragCount];
-    float P[kSmall];
+    alignas(16) float P[kSmall];  // read in 16-byte groups
     float sc[6];
 };
 template <>
 struct NetLds<CS_SAMPLER_MLP_FP8> {
     long frag[kFragCount];
-    float P[kSmall];
+    alignas(16) float P[kSmall];  // read in 16-byte groups
     float sc[6];
 };
 
