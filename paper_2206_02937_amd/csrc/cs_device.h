@@ -141,9 +141,10 @@ __device__ __forceinline__ uint32_t shuffle_index(uint32_t i, uint32_t M, const 
 // cancellation at small x (where the closed form loses about 1/x^2 of its
 // precision); they converge like sigma^k with sigma < 1/4 for z < 2.  The
 // series branch serves x < 1; kTailTerms terms reach round-off at sigma
-// just below 1/4, and a wave whose lanes all have a smaller sigma takes
-// fewer (see tail_series).
-constexpr int kTailTerms = 28;
+// just below 1/4, and a lane with a smaller sigma takes fewer (see
+// tail_series).
+constexpr int kTailChunk = 6;   // terms per Horner chunk
+constexpr int kTailTerms = 30;  // five chunks
 constexpr double kSeriesSwitch = 1.0;
 
 struct TailCoeffs {
@@ -187,33 +188,6 @@ __device__ __forceinline__ double ipow(double t) {
     }
 }
 
-// sum_{k = N0}^{N1 - 1} c_k t^(k - N0): chunks of CH terms by Horner (the
-// chunks are independent, so their dependency chains overlap), combined in
-// powers of t^CH.  Coefficients are read from scalar registers.
-template <int N0, int N1, int CH>
-__device__ __forceinline__ double poly_chunked(cdptr c, double t) {
-    constexpr int NC = (N1 - N0 + CH - 1) / CH;
-    double part[NC];
-#pragma unroll
-    for (int i = 0; i < NC; ++i) {
-        const int lo = N0 + i * CH;
-        const int hi = lo + CH < N1 ? lo + CH : N1;
-        double acc = c[hi - 1];
-#pragma unroll
-        for (int k = hi - 2; k >= lo; --k) acc = fma_sgpr(acc, t, c[k]);
-        part[i] = acc;
-    }
-    if constexpr (NC == 1) {
-        return part[0];
-    } else {
-        const double tc = ipow<CH>(t);
-        double r = part[NC - 1];
-#pragma unroll
-        for (int i = NC - 2; i >= 0; --i) r = fma(r, tc, part[i]);
-        return r;
-    }
-}
-
 // 1/a to about an ulp (hardware estimate and two Newton steps).
 __device__ __forceinline__ double recip_approx(double a) {
     double r = __builtin_amdgcn_rcp(a);
@@ -221,36 +195,71 @@ __device__ __forceinline__ double recip_approx(double a) {
     return fma(fma(-a, r, 1.0), r, r);
 }
 
-// T(v) from the three series with N terms each.  The coefficient pointers
-// pass through an empty asm so that the compiler reads the coefficients with
-// scalar loads at each use instead of hoisting whole tables into vector
-// registers across the sampler's iteration.
-template <int N, int CH>
-__device__ __forceinline__ double tail_terms(double v, double z, double A, double s, double q, double sig) {
+// sum_{k < 6 nch} c_k t^k for this lane's nch <= NC chunks of kTailChunk
+// terms: the wave evaluates NC chunks (Horner each, from scalar registers),
+// the lane zeroes those at or beyond its nch, and the chunks are combined
+// from the top in powers of t^6.  A zeroed chunk leaves the combination at
+// exactly 0 and fma(0, t^6, p) = p, so the lane's result is bit for bit its
+// own nch-chunk sum, whatever NC its wave needs.
+template <int NC>
+__device__ __forceinline__ double poly_lane_chunks(cdptr c, double t, int nch) {
+    double part[NC];
+#pragma unroll
+    for (int i = 0; i < NC; ++i) {
+        const int lo = i * kTailChunk;
+        double acc = c[lo + kTailChunk - 1];
+#pragma unroll
+        for (int k = lo + kTailChunk - 2; k >= lo; --k) acc = fma_sgpr(acc, t, c[k]);
+        part[i] = i == 0 || i < nch ? acc : 0.0;
+    }
+    if constexpr (NC == 1) {
+        return part[0];
+    } else {
+        const double tc = ipow<kTailChunk>(t);
+        double r = part[NC - 1];
+#pragma unroll
+        for (int i = NC - 2; i >= 0; --i) r = fma(r, tc, part[i]);
+        return r;
+    }
+}
+
+// T(v) from the three series, each with this lane's nch chunks (the wave's
+// NC >= nch evaluated).  The coefficient pointers pass through an empty asm
+// so that the compiler reads the coefficients with scalar loads at each use
+// instead of hoisting whole tables into vector registers across the
+// sampler's iteration.
+template <int NC>
+__device__ __forceinline__ double tail_terms(double v, double z, double A, double s, double q, double sig,
+                                             int nch) {
     cdptr S1 = (cdptr)kTail.s1, S2 = (cdptr)kTail.s2, S3 = (cdptr)kTail.s3;
     asm volatile("" : "+s"(S1), "+s"(S2), "+s"(S3));
-    const double p1 = poly_chunked<0, N, CH>(S1, sig);
-    const double p2 = poly_chunked<0, N, CH>(S2, sig);
-    const double p3 = poly_chunked<0, N, CH>(S3, sig);
+    const double p1 = poly_lane_chunks<NC>(S1, sig, nch);
+    const double p2 = poly_lane_chunks<NC>(S2, sig, nch);
+    const double p3 = poly_lane_chunks<NC>(S3, sig, nch);
     const double iA = recip_approx(A);
     const double first = 0.5 * v * (2.0 + z) * iA * iA;
     const double inner = fma(s, p2, 2.0 * recip_approx(1.0 + s));
     return first + 2.0 * q * p1 - 2.0 * q * q * inner + q * q * q * p3;
 }
 
-// Series branch of T(v) for x < kSeriesSwitch.  The wave takes as many terms
-// as its largest sigma needs for the truncated remainder to stay below
+// Series branch of T(v) for x < kSeriesSwitch.  Each lane takes as many
+// terms as its own sigma needs for the truncated remainder to stay below
 // 1e-17 of the sum: 6 terms up to sigma = 1.5e-3, 12 up to 0.035, 18 up to
-// 0.112, else kTailTerms (sigma < 1/4).
+// 0.112, else kTailTerms (sigma < 1/4).  The wave evaluates the chunks its
+// largest need requires; a lane's result depends on its own sigma only
+// (poly_lane_chunks), so it is the same whichever lanes share its wave --
+// every kernel strategy, whose waves group the collisions differently,
+// gives the same bits.
 __device__ __forceinline__ double tail_series(double x, double v) {
     const double z = x * v;
     const double r = recip_approx(2.0 + z);
     const double s = z * r, q = v * r, sig = s * s;
     const double A = 1.0 + z;
-    if (__all(sig <= 1.5e-3)) return tail_terms<6, 6>(v, z, A, s, q, sig);
-    if (__all(sig <= 0.035)) return tail_terms<12, 6>(v, z, A, s, q, sig);
-    if (__all(sig <= 0.112)) return tail_terms<18, 9>(v, z, A, s, q, sig);
-    return tail_terms<kTailTerms, 14>(v, z, A, s, q, sig);
+    const int nch = sig <= 1.5e-3 ? 1 : (sig <= 0.035 ? 2 : (sig <= 0.112 ? 3 : kTailTerms / kTailChunk));
+    if (__all(nch <= 1)) return tail_terms<1>(v, z, A, s, q, sig, nch);
+    if (__all(nch <= 2)) return tail_terms<2>(v, z, A, s, q, sig, nch);
+    if (__all(nch <= 3)) return tail_terms<3>(v, z, A, s, q, sig, nch);
+    return tail_terms<kTailTerms / kTailChunk>(v, z, A, s, q, sig, nch);
 }
 
 // s(x) = sigma_KN(x) / sigma_T.  Below 2: the per-segment Taylor polynomial
