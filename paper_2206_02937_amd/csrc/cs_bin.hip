@@ -13,8 +13,10 @@
 // every run.  Ids outside [0, n_cells) get the key n_cells, which sorts them
 // after every valid particle.
 //
-//   per pass:
-//   k_bin_hist    per 4096-key tile, the digit counts (LDS atomics)
+//   per pass (tiles of 16 waves x 1024 keys = 16384 keys for FP32 values,
+//   8 waves x 1024 = 8192 for FP64, so that a tile and one value array fit
+//   in LDS together):
+//   k_bin_hist    per tile, the digit counts (LDS atomics)
 //   k_bin_scan    one workgroup per digit: exclusive prefix over the tiles of
 //                 that digit's counts, and the digit's total
 //   k_bin_scatter per tile: digit bases from the totals and the tile
@@ -31,16 +33,32 @@
 // arrays so that the last one writes the output.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "cs_block.h"
 #include "cs_internal.h"
 
 namespace cs {
 
-constexpr int kBinThreads = 256;
+constexpr int kBinThreads = 256;                          // scans and offsets
 constexpr int kBinChunks = 16;                             // 64-key chunks per wave
 constexpr int kBinWaveKeys = 64 * kBinChunks;             // 1024
-constexpr int kBinTile = kBinWaveKeys * (kBinThreads / 64);  // 4096
 constexpr int kBinDigits = 512;  // at most: a 9-bit digit
+
+// Tile shape per value type: the larger the tile, the longer each digit's
+// run of consecutive output positions (8-bit digits: ~64 keys per digit and
+// FP32 tile, 256 bytes per value array instead of 64 with 4096-key tiles),
+// so the scattered writes fill whole lines.  A tile's keys and one value
+// array are staged in LDS together with the source indices and per-wave
+// counts: 132 KB for FP32, 100 KB for FP64.
+template <typename T>
+struct BinShape {
+    static constexpr int kThreads = sizeof(T) == 4 ? 1024 : 512;
+    static constexpr int kWaves = kThreads / 64;
+    static constexpr int kTile = kWaves * kBinWaveKeys;
+    typedef typename std::conditional<sizeof(T) == 4, uint32_t, uint64_t>::type Word;  // a key or a value
+};
+constexpr int kBinTileMin = 8192;  // the smaller tile (FP64): sizes the per-tile counts of the scratch
 
 template <typename T>
 struct BinArrays {
@@ -59,25 +77,26 @@ __device__ __forceinline__ uint32_t bin_key(const uint32_t* keys, const int32_t*
     return c >= 0 && (int64_t)c < n_cells ? (uint32_t)c : (uint32_t)n_cells;
 }
 
-// hist[d * n_tiles + t] = keys of tile t whose digit is d
-__global__ __launch_bounds__(kBinThreads) void k_bin_hist(const uint32_t* keys, const int32_t* cell, int64_t n,
-                                                          int64_t n_cells, int shift, int dbits, int64_t n_tiles,
-                                                          uint32_t* hist) {
+// hist[d * n_tiles + t] = keys of tile t (TILE keys, THREADS threads) whose
+// digit is d
+template <int THREADS, int TILE>
+__global__ __launch_bounds__(THREADS) void k_bin_hist(const uint32_t* keys, const int32_t* cell, int64_t n,
+                                                      int64_t n_cells, int shift, int dbits, int64_t n_tiles,
+                                                      uint32_t* hist) {
     __shared__ uint32_t s_cnt[kBinDigits];
     const int tid = threadIdx.x;
     const uint32_t mask = (1u << dbits) - 1u;
     const int nd = 1 << dbits;
-    s_cnt[tid] = 0;
-    s_cnt[tid + kBinThreads] = 0;
+    for (int d = tid; d < kBinDigits; d += THREADS) s_cnt[d] = 0;
     __syncthreads();
-    const int64_t t0 = (int64_t)blockIdx.x * kBinTile;
+    const int64_t t0 = (int64_t)blockIdx.x * TILE;
 #pragma unroll 4
-    for (int j = 0; j < kBinTile / kBinThreads; ++j) {
-        const int64_t i = t0 + (int64_t)j * kBinThreads + tid;
+    for (int j = 0; j < TILE / THREADS; ++j) {
+        const int64_t i = t0 + (int64_t)j * THREADS + tid;
         if (i < n) atomicAdd(&s_cnt[(bin_key(keys, cell, n_cells, i) >> shift) & mask], 1u);
     }
     __syncthreads();
-    for (int d = tid; d < nd; d += kBinThreads) hist[(int64_t)d * n_tiles + blockIdx.x] = s_cnt[d];
+    for (int d = tid; d < nd; d += THREADS) hist[(int64_t)d * n_tiles + blockIdx.x] = s_cnt[d];
 }
 
 // Workgroup d: exclusive prefix of hist[d][0 .. n_tiles) in place, the sum to
@@ -119,42 +138,50 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_scan(uint32_t* hist, int64_
 // LDS the same way (read in order, written in digit order), so every global
 // access is coalesced.
 template <typename T>
-__global__ __launch_bounds__(kBinThreads) void k_bin_scatter(const uint32_t* keys_in, const int32_t* cell,
-                                                             int64_t n, int64_t n_cells, int shift, int dbits,
-                                                             int64_t n_tiles, const uint32_t* hist,
-                                                             const uint32_t* totals, BinArrays<T> src,
-                                                             uint32_t* keys_out, BinOut<T> dst) {
-    constexpr int kPer = kBinTile / kBinThreads;               // 16 outputs per thread
-    __shared__ uint32_t s_cnt[kBinThreads / 64][kBinDigits];  // per wave counts, then running local bases
-    __shared__ uint32_t s_toff[kBinDigits];                    // tile-local start of each digit's run
-    __shared__ uint32_t s_gbase[kBinDigits];                   // global start of each digit's run
-    __shared__ uint64_t s_buf[kBinTile];                       // the tile's keys, then each value array
-    __shared__ uint16_t s_src[kBinTile];                       // tile-local source of each output
-    __shared__ int s_scan[kBinThreads / 64 + 1];
+__global__ __launch_bounds__(BinShape<T>::kThreads) void k_bin_scatter(const uint32_t* keys_in, const int32_t* cell,
+                                                                       int64_t n, int64_t n_cells, int shift,
+                                                                       int dbits, int64_t n_tiles,
+                                                                       const uint32_t* hist, const uint32_t* totals,
+                                                                       BinArrays<T> src, uint32_t* keys_out,
+                                                                       BinOut<T> dst) {
+    constexpr int kThreads = BinShape<T>::kThreads, kTile = BinShape<T>::kTile, kWaves = BinShape<T>::kWaves;
+    typedef typename BinShape<T>::Word Word;
+    constexpr int kPer = kTile / kThreads;            // 16 outputs per thread
+    __shared__ uint32_t s_cnt[kWaves][kBinDigits];    // per wave counts, then running local bases
+    __shared__ uint32_t s_toff[kBinDigits];           // tile-local start of each digit's run
+    __shared__ uint32_t s_gbase[kBinDigits];          // global start of each digit's run
+    __shared__ Word s_buf[kTile];                     // the tile's keys, then each value array
+    __shared__ uint16_t s_src[kTile];                 // tile-local source of each output
+    __shared__ int s_scan[kWaves + 1];
+    static_assert(kTile <= 65536, "tile-local indices are 16-bit");
     uint32_t* s_key = (uint32_t*)s_buf;
     T* s_val = (T*)s_buf;
     const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
     const int64_t t = blockIdx.x;
-    const int64_t t0 = t * kBinTile;
+    const int64_t t0 = t * kTile;
     const int64_t rem = n - t0;
-    const int len = rem < kBinTile ? (int)rem : kBinTile;
+    const int len = rem < kTile ? (int)rem : kTile;
     const int wl0 = wave * kBinWaveKeys;  // this wave's first key in the tile
     const uint32_t mask = (1u << dbits) - 1u;
     const int nd = 1 << dbits;
-    // thread t looks after digits 2t and 2t + 1 in the scans below
-    const int d0 = 2 * tid, d1 = 2 * tid + 1;
+    // thread t < kBinDigits / 2 looks after digits 2t and 2t + 1 in the scans
+    // below; the others add nothing to them
+    const bool dig = tid < kBinDigits / 2;
+    const int d0 = dig ? 2 * tid : 0, d1 = d0 + 1;
+    if (dig) {
 #pragma unroll
-    for (int w = 0; w < kBinThreads / 64; ++w) {
-        s_cnt[w][d0] = 0;
-        s_cnt[w][d1] = 0;
+        for (int w = 0; w < kWaves; ++w) {
+            s_cnt[w][d0] = 0;
+            s_cnt[w][d1] = 0;
+        }
     }
     // digit base over all tiles: exclusive prefix of the totals
     {
-        const uint32_t t0v = d0 < nd ? totals[d0] : 0u, t1v = d1 < nd ? totals[d1] : 0u;
+        const uint32_t t0v = dig && d0 < nd ? totals[d0] : 0u, t1v = dig && d1 < nd ? totals[d1] : 0u;
         int unused;
         const uint32_t ex = (uint32_t)block_exclusive_scan((int)(t0v + t1v), s_scan, &unused);
-        if (d0 < nd) s_gbase[d0] = ex + hist[(int64_t)d0 * n_tiles + t];
-        if (d1 < nd) s_gbase[d1] = ex + t0v + hist[(int64_t)d1 * n_tiles + t];
+        if (dig && d0 < nd) s_gbase[d0] = ex + hist[(int64_t)d0 * n_tiles + t];
+        if (dig && d1 < nd) s_gbase[d1] = ex + t0v + hist[(int64_t)d1 * n_tiles + t];
     }
     uint32_t key[kBinChunks];
 #pragma unroll
@@ -168,23 +195,27 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_scatter(const uint32_t* key
     // base inside it (waves in key order)
     {
         uint32_t tc0 = 0, tc1 = 0;
+        if (dig) {
 #pragma unroll
-        for (int w = 0; w < kBinThreads / 64; ++w) {
-            tc0 += s_cnt[w][d0];
-            tc1 += s_cnt[w][d1];
+            for (int w = 0; w < kWaves; ++w) {
+                tc0 += s_cnt[w][d0];
+                tc1 += s_cnt[w][d1];
+            }
         }
         int unused2;
         uint32_t run0 = (uint32_t)block_exclusive_scan((int)(tc0 + tc1), s_scan, &unused2);
         uint32_t run1 = run0 + tc0;
-        s_toff[d0] = run0;
-        s_toff[d1] = run1;
+        if (dig) {
+            s_toff[d0] = run0;
+            s_toff[d1] = run1;
 #pragma unroll
-        for (int w = 0; w < kBinThreads / 64; ++w) {
-            const uint32_t c0 = s_cnt[w][d0], c1 = s_cnt[w][d1];
-            s_cnt[w][d0] = run0;
-            s_cnt[w][d1] = run1;
-            run0 += c0;
-            run1 += c1;
+            for (int w = 0; w < kWaves; ++w) {
+                const uint32_t c0 = s_cnt[w][d0], c1 = s_cnt[w][d1];
+                s_cnt[w][d0] = run0;
+                s_cnt[w][d1] = run1;
+                run0 += c0;
+                run1 += c1;
+            }
         }
     }
     __syncthreads();
@@ -215,7 +246,7 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_scatter(const uint32_t* key
     uint32_t pos[kPer];
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
-        const int j = tid + q * kBinThreads;
+        const int j = tid + q * kThreads;
         pos[q] = 0;
         if (j < len) {
             const uint32_t k = s_key[j];
@@ -231,13 +262,13 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_scatter(const uint32_t* key
         __syncthreads();  // s_buf free
 #pragma unroll
         for (int q = 0; q < kPer; ++q) {
-            const int j = tid + q * kBinThreads;
+            const int j = tid + q * kThreads;
             if (j < len) s_val[j] = srcs[a][t0 + j];
         }
         __syncthreads();
 #pragma unroll
         for (int q = 0; q < kPer; ++q) {
-            const int j = tid + q * kBinThreads;
+            const int j = tid + q * kThreads;
             if (j < len) dsts[a][pos[q]] = s_val[s_src[j]];
         }
     }
@@ -261,7 +292,9 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_offsets(const uint32_t* key
     if (c == n_cells && n_invalid) *n_invalid = n - lo;
 }
 
-int64_t bin_tiles(int64_t n) { return (n + kBinTile - 1) / kBinTile; }
+// tiles of a pass (per value type); the scratch is sized for the smaller
+// tile, which gives the more tiles
+int64_t bin_tiles(int64_t n, int64_t tile = kBinTileMin) { return (n + tile - 1) / tile; }
 
 // scratch: two key arrays (uint32), one copy of the four value arrays (8 B
 // elements, enough for either storage type), digit counts of every tile and
@@ -277,7 +310,9 @@ template <typename T>
 static void launch_passes(const int32_t* cell, int64_t n, int64_t n_cells, const void* const in[4],
                           void* const out[4], uint32_t* const keys[2], void* const tmp[4], uint32_t* hist,
                           uint32_t* totals, int passes, int low_bits, hipStream_t st) {
-    const int64_t n_tiles = bin_tiles(n);
+    constexpr int kThreads = BinShape<T>::kThreads, kTile = BinShape<T>::kTile;
+    static_assert(kTile >= kBinTileMin, "the scratch holds counts for kBinTileMin tiles");
+    const int64_t n_tiles = bin_tiles(n, kTile);
     const BinArrays<T> in_a = {(const T*)in[0], (const T*)in[1], (const T*)in[2], (const T*)in[3]};
     const BinOut<T> out_a = {(T*)out[0], (T*)out[1], (T*)out[2], (T*)out[3]};
     const BinOut<T> tmp_a = {(T*)tmp[0], (T*)tmp[1], (T*)tmp[2], (T*)tmp[3]};
@@ -291,10 +326,11 @@ static void launch_passes(const int32_t* cell, int64_t n, int64_t n_cells, const
         const BinOut<T> dst = ((passes - 1 - ps) & 1) == 0 ? out_a : tmp_a;
         const BinOut<T> prev = ((passes - ps) & 1) == 0 ? out_a : tmp_a;
         const BinArrays<T> src = ps == 0 ? in_a : BinArrays<T>{prev.x, prev.y, prev.z, prev.w};
-        k_bin_hist<<<(unsigned)n_tiles, kBinThreads, 0, st>>>(kin, cell, n, n_cells, shift, dbits, n_tiles, hist);
+        k_bin_hist<kThreads, kTile><<<(unsigned)n_tiles, kThreads, 0, st>>>(kin, cell, n, n_cells, shift, dbits,
+                                                                             n_tiles, hist);
         k_bin_scan<<<1u << dbits, kBinThreads, 0, st>>>(hist, n_tiles, totals);
-        k_bin_scatter<T><<<(unsigned)n_tiles, kBinThreads, 0, st>>>(kin, cell, n, n_cells, shift, dbits, n_tiles,
-                                                                    hist, totals, src, keys[ps & 1], dst);
+        k_bin_scatter<T><<<(unsigned)n_tiles, kThreads, 0, st>>>(kin, cell, n, n_cells, shift, dbits, n_tiles, hist,
+                                                                 totals, src, keys[ps & 1], dst);
     }
 }
 
