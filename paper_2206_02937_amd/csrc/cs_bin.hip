@@ -183,6 +183,17 @@ __global__ __launch_bounds__(BinShape<T>::kThreads) void k_bin_scatter(const uin
         if (dig && d0 < nd) s_gbase[d0] = ex + hist[(int64_t)d0 * n_tiles + t];
         if (dig && d1 < nd) s_gbase[d1] = ex + t0v + hist[(int64_t)d1 * n_tiles + t];
     }
+    // the tile's four value arrays, read in order (coalesced) into registers
+    // first, so that their reads are in flight while the keys are ranked
+    const T* srcs[4] = {src.x, src.y, src.z, src.w};
+    T val[4][kPer];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            const int j = tid + q * kThreads;
+            val[a][q] = j < len ? srcs[a][t0 + j] : (T)0;
+        }
     uint32_t key[kBinChunks];
 #pragma unroll
     for (int c = 0; c < kBinChunks; ++c) {
@@ -255,7 +266,6 @@ __global__ __launch_bounds__(BinShape<T>::kThreads) void k_bin_scatter(const uin
             keys_out[pos[q]] = k;
         }
     }
-    const T* srcs[4] = {src.x, src.y, src.z, src.w};
     T* dsts[4] = {dst.x, dst.y, dst.z, dst.w};
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
@@ -263,7 +273,7 @@ __global__ __launch_bounds__(BinShape<T>::kThreads) void k_bin_scatter(const uin
 #pragma unroll
         for (int q = 0; q < kPer; ++q) {
             const int j = tid + q * kThreads;
-            if (j < len) s_val[j] = srcs[a][t0 + j];
+            if (j < len) s_val[j] = val[a][q];
         }
         __syncthreads();
 #pragma unroll
