@@ -95,7 +95,11 @@ struct GradArgs {
 // -- the lane that produced z keeps SiLU'(z) in registers for that --, and
 // the weight gradients dW[16w.., :] = delta[16w.., :] H^T (four 16x16 tiles,
 // K = 16 samples), which stay in MFMA accumulators over the workgroup's tiles
-// and are written once.  The workgroup first issues the loads of its first
+// and are written once: on the workgroup's last tile, right after the layer's
+// backward pass (the stores then drain while the layers below run), and
+// non-temporal (they are read once, by the reduction kernel, so they skip the
+// cache rather than wait in it for the end-of-kernel write-back; with a
+// 4096-sample batch, 13 MB of partials).  The workgroup first issues the loads of its first
 // tile's inputs and targets (vector-memory loads complete in issue order,
 // so a wait for them must not sit behind the parameter loads), then copies
 // the parameters into LDS with coalesced 16-byte loads, and each lane takes
@@ -354,6 +358,16 @@ __global__ __launch_bounds__(kMlpThreads) void k_mlp_grad_block(const GradArgs a
                     for (int tk = 0; tk < 4; ++tk) gW[L][tk] = mfma_f32(aop, hy[sm * kYRow + 16 * tk + li], gW[L][tk]);
                 }
             }
+            if (tile + gridDim.x >= n_tiles) {
+                // the workgroup's last tile: this layer's partial is final
+                float* out = a.partials + (int64_t)blockIdx.x * kMlpParams;
+#pragma unroll
+                for (int tk = 0; tk < 4; ++tk)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        __builtin_nontemporal_store(gW[L][tk][r],
+                                                    &out[offW[L] + (16 * w + 4 * lg + r) * kMlpHidden + 16 * tk + li]);
+            }
             if (w == 0) {
                 float db = 0.0f;
                 for (int sm = 0; sm < kTrainTile; ++sm) db += dy[sm * kYRow + lane];
@@ -390,14 +404,18 @@ __global__ __launch_bounds__(kMlpThreads) void k_mlp_grad_block(const GradArgs a
             }
         }
     }
-    // write this workgroup's partial gradient (every entry by its owner)
+    // the rest of this workgroup's partial gradient (every entry by its
+    // owner; the hidden matrices were written with the last tile, or here
+    // as zeros by a workgroup that had no tile)
     float* out = a.partials + (int64_t)blockIdx.x * kMlpParams;
+    if ((int64_t)blockIdx.x >= n_tiles) {
 #pragma unroll
-    for (int L = 0; L < 3; ++L)
+        for (int L = 0; L < 3; ++L)
 #pragma unroll
-        for (int tk = 0; tk < 4; ++tk)
+            for (int tk = 0; tk < 4; ++tk)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) out[offW[L] + (16 * w + 4 * lg + r) * kMlpHidden + 16 * tk + li] = gW[L][tk][r];
+                for (int r = 0; r < 4; ++r) out[offW[L] + (16 * w + 4 * lg + r) * kMlpHidden + 16 * tk + li] = gW[L][tk][r];
+    }
     if (w == 0) {
         out[kOffW1 + 2 * lane] = gW1a;
         out[kOffW1 + 2 * lane + 1] = gW1b;
