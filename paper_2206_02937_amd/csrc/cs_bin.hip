@@ -184,7 +184,10 @@ __global__ __launch_bounds__(BinShape<T>::kThreads) void k_bin_scatter(const uin
         if (dig && d1 < nd) s_gbase[d1] = ex + t0v + hist[(int64_t)d1 * n_tiles + t];
     }
     // the tile's four value arrays, read in order (coalesced) into registers
-    // first, so that their reads are in flight while the keys are ranked
+    // first, so that their reads are in flight while the keys are ranked;
+    // non-temporal, as every value is read once per pass (the stores stay
+    // ordinary: a digit's run rarely fills whole lines, and the cache
+    // merges the pieces that neighbouring tiles write)
     const T* srcs[4] = {src.x, src.y, src.z, src.w};
     T val[4][kPer];
 #pragma unroll
@@ -192,7 +195,7 @@ __global__ __launch_bounds__(BinShape<T>::kThreads) void k_bin_scatter(const uin
 #pragma unroll
         for (int q = 0; q < kPer; ++q) {
             const int j = tid + q * kThreads;
-            val[a][q] = j < len ? srcs[a][t0 + j] : (T)0;
+            val[a][q] = j < len ? __builtin_nontemporal_load(&srcs[a][t0 + j]) : (T)0;
         }
     uint32_t key[kBinChunks];
 #pragma unroll
