@@ -124,16 +124,18 @@ constexpr int kParSmall = 3 * kParMat;
 constexpr int kParSW1 = 0, kParSB1 = 128, kParSB2 = 192, kParSW5 = 384, kParSB5 = 512;
 constexpr int kParFloats = kParSmall + 516;
 
-// LDS position of the 4-aligned parameter index f (below kOffB5).
+// LDS position of the 4-aligned parameter index f (below kOffB5).  Written
+// with selects only: with branches, the compiler moves each of the copy's
+// global loads down to its LDS store and waits for it there, fourteen memory
+// round trips in a row instead of one.
 __device__ __forceinline__ int par_slot(int f) {
-    if (f < kOffW2) return kParSmall + f;  // W1, b1
-    if (f < kOffB2) return ((f - kOffW2) >> 6) * kParRow + ((f - kOffW2) & 63);
-    if (f < kOffW3) return kParSmall + kParSB2 + (f - kOffB2);
-    if (f < kOffB3) return kParMat + ((f - kOffW3) >> 6) * kParRow + ((f - kOffW3) & 63);
-    if (f < kOffW4) return kParSmall + kParSB2 + 64 + (f - kOffB3);
-    if (f < kOffB4) return 2 * kParMat + ((f - kOffW4) >> 6) * kParRow + ((f - kOffW4) & 63);
-    if (f < kOffW5) return kParSmall + kParSB2 + 128 + (f - kOffB4);
-    return kParSmall + kParSW5 + (f - kOffW5);  // W5
+    const int m = (f >= kOffW3) + (f >= kOffW4);       // hidden matrix W_{m+2} and its bias b_{m+2}
+    const int rel = f - (kOffW2 + m * (kOffW3 - kOffW2));  // offset from the start of W_{m+2}
+    const bool hidden = f >= kOffW2 && f < kOffW5;
+    const int mat = m * kParMat + (rel >> 6) * kParRow + (rel & 63);
+    const int bias = kParSmall + kParSB2 + kMlpHidden * m + (rel - kMlpHidden * kMlpHidden);
+    const int small = f < kOffW2 ? kParSmall + f : kParSmall + kParSW5 + (f - kOffW5);  // W1, b1 | W5
+    return hidden ? (rel < kMlpHidden * kMlpHidden ? mat : bias) : small;
 }
 
 typedef float floatx4_t __attribute__((ext_vector_type(4)));
@@ -178,7 +180,8 @@ __global__ __launch_bounds__(kMlpThreads) void k_mlp_grad_block(const GradArgs a
         const float4* P4 = (const float4*)a.P;
         float4 v[kFull + 1];
         // all issued before the first store; in the last round the threads
-        // past kRest repeat the piece of thread 0 (same value, same place)
+        // past kRest repeat the piece of thread 0, and every thread stores
+        // one of the two tail floats (same value, same place)
         const int last = kFull * kMlpThreads + (tid < kRest ? tid : 0);
 #pragma unroll
         for (int q = 0; q < kFull; ++q) v[q] = P4[tid + q * kMlpThreads];
@@ -187,7 +190,11 @@ __global__ __launch_bounds__(kMlpThreads) void k_mlp_grad_block(const GradArgs a
 #pragma unroll
         for (int q = 0; q < kFull; ++q) s_par4[par_slot(4 * (tid + q * kMlpThreads)) / 4] = v[q];
         s_par4[par_slot(4 * last) / 4] = v[kFull];
-        if (tid < kMlpParams % 4) ((float*)s_par4)[kParSmall + kParSB5 + tid] = tail;
+        static_assert(kMlpParams % 4 == 2, "two tail floats");
+        ((float*)s_par4)[kParSmall + kParSB5 + (tid & 1)] = tail;
+        // scheduling: the fifteen global loads first, then the LDS stores
+        __builtin_amdgcn_sched_group_barrier(0x0020, kFull + 2, 0);
+        __builtin_amdgcn_sched_group_barrier(0x0200, kFull + 2, 0);
     }
     __syncthreads();
     const float* P = (const float*)s_par4;
