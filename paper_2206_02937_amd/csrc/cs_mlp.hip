@@ -450,8 +450,11 @@ struct ReduceArgs {
 };
 
 // One workgroup of 16 waves per 64 parameters: wave w sums the partials of
-// workgroups b = 16c + w (c ascending; up to 16 loads in flight per lane),
-// then wave 0 adds the 16 wave sums in order -- a fixed summation order.
+// workgroups b = 16c + w (c ascending; 16 loads in flight per lane), then
+// wave 0 adds the 16 wave sums in order -- a fixed summation order.  The
+// loss partials the same way (lane j of wave w holds entry w + 16j, lane 0
+// adds them in order).  Every global read is issued before the first sum
+// that needs it, so that each costs one memory round trip.
 constexpr int kReduceWaves = 16;
 
 __global__ __launch_bounds__(64 * kReduceWaves) void k_mlp_reduce(const ReduceArgs a) {
@@ -460,6 +463,9 @@ __global__ __launch_bounds__(64 * kReduceWaves) void k_mlp_reduce(const ReduceAr
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
     const int p = blockIdx.x * 64 + lane;
+    // this wave's loss partials, one per lane (blockIdx.x == 0)
+    const int64_t lb = w + (int64_t)kReduceWaves * lane;
+    const float lv = blockIdx.x == 0 && lb < a.blocks ? a.loss_partials[lb] : 0.0f;
     float g = 0.0f;
     if (p < kMlpParams) {
         int64_t b = w;
@@ -467,16 +473,17 @@ __global__ __launch_bounds__(64 * kReduceWaves) void k_mlp_reduce(const ReduceAr
             float v[16];
 #pragma unroll
             for (int k = 0; k < 16; ++k) v[k] = a.partials[(b + kReduceWaves * k) * kMlpParams + p];
+            __builtin_amdgcn_sched_group_barrier(0x0020, 16, 0);  // the sixteen loads first
 #pragma unroll
             for (int k = 0; k < 16; ++k) g += v[k];
         }
         for (; b < a.blocks; b += kReduceWaves) g += a.partials[b * kMlpParams + p];
     }
     s_q[w][lane] = g;
-    if (blockIdx.x == 0 && lane == 0) {
+    if (blockIdx.x == 0) {
         float l = 0.0f;
-        for (int64_t b = w; b < a.blocks; b += kReduceWaves) l += a.loss_partials[b];
-        s_lq[w] = l;
+        for (int j = 0; w + (int64_t)kReduceWaves * j < a.blocks; ++j) l += __shfl(lv, j, 64);
+        if (lane == 0) s_lq[w] = l;
     }
     __syncthreads();
     if (w != 0) return;
@@ -881,6 +888,7 @@ NetDomain net_domain(double x_min, double x_max) {
 }
 
 constexpr int64_t kMaxGradBlocks = 512;
+static_assert(kMaxGradBlocks <= 64 * kReduceWaves, "k_mlp_reduce holds one loss partial per lane");
 
 int64_t mlp_grad_blocks(int64_t n) {
     const int64_t t = (n + kTrainTile - 1) / kTrainTile;
