@@ -208,16 +208,28 @@ __global__ __launch_bounds__(kChunk) void k_pair_compact(const CompactArgs<T> a)
     const int wave = tid >> 6;
     const int64_t blk = blockIdx.x;
     const int G = a.chunks_per_block;
-    for (int i = tid; i < kSigTabSegments * kSigTabTerms; i += kChunk) s_sig[i] = kSigTab[i];
-    StepControl* ctrl = a.ctrl;
-    const uint32_t E = ctrl->epoch;
-    const uint64_t step = ctrl->step;
-    const bool layout_ok = ctrl->layout_epoch != E && ctrl->scan_fault_epoch != E;
-    const int32_t T_total = layout_ok ? a.pair_off[a.n_cells] : 0;
+    // the s(x) table into LDS: every thread's reads issued before anything
+    // waits, and stored below (a loop of read, wait, store would wait once
+    // per round)
+    constexpr int kSigRounds = kSigTabSegments * kSigTabTerms / kChunk;
+    static_assert(kSigRounds * kChunk == kSigTabSegments * kSigTabTerms, "whole rounds");
+    double sig_v[kSigRounds];
+#pragma unroll
+    for (int r = 0; r < kSigRounds; ++r) sig_v[r] = kSigTab[tid + r * kChunk];
     // chunk_cell of the workgroup's chunks and of the one after them, lane i
     // holding entry blk G + i (G < 64)
     const int64_t jc = blk * G + lane;
     const int cc = lane <= G && jc <= a.n_chunks ? a.chunk_cell[jc] : 0;
+    const int32_t T_read = a.pair_off[a.n_cells];  // read with the control block, not after it
+    StepControl* ctrl = a.ctrl;
+    const CtrlView cv = ctrl_view(ctrl);
+    const uint32_t E = cv.epoch;
+    const uint64_t step = cv.step;
+    const bool layout_ok = cv.layout_ok;
+    const int32_t T_total = layout_ok ? T_read : 0;
+    // (the s(x) table's reads, issued first, stored here)
+#pragma unroll
+    for (int r = 0; r < kSigRounds; ++r) s_sig[tid + r * kChunk] = sig_v[r];
     // steps of this workgroup: its chunks below min(n_chunks, ceil(T / kChunk))
     int64_t n_used = ((int64_t)T_total + kChunk - 1) / kChunk;
     if (n_used > a.n_chunks) n_used = a.n_chunks;
@@ -306,7 +318,10 @@ __global__ __launch_bounds__(kChunk) void k_pair_compact(const CompactArgs<T> a)
 // Thread t of NT takes counts [P t, P (t + 1)), P = kSegMax / NT: seg_load
 // reads them (issued only, so that other reads can join them), seg_scan
 // writes the n <= kSegMax exclusive prefixes to s and returns the total.
-// Both are called by every thread.
+// Both are called by every thread.  The count array has room for kSegMax
+// entries whatever n, so that a thread reads its P counts with 16-byte loads
+// and zeroes those past n (element by element, the reads sat in branches of
+// their own, each waiting for the array's address).
 constexpr int kSegMax = 4096;
 
 template <int NT>
@@ -317,10 +332,25 @@ struct SegCounts {
 template <int NT>
 __device__ __forceinline__ SegCounts<NT> seg_load(const int32_t* cnt, int n) {
     constexpr int kSegPerThread = kSegMax / NT;
+    static_assert(kSegPerThread % 4 == 0, "16-byte reads");
     const int k0 = (int)threadIdx.x * kSegPerThread;
+    int4 q[kSegPerThread / 4];
+    if (k0 < n) {
+#pragma unroll
+        for (int j = 0; j < kSegPerThread / 4; ++j) q[j] = ((const int4*)(cnt + k0))[j];
+    } else {
+#pragma unroll
+        for (int j = 0; j < kSegPerThread / 4; ++j) q[j] = make_int4(0, 0, 0, 0);
+    }
     SegCounts<NT> c;
 #pragma unroll
-    for (int i = 0; i < kSegPerThread; ++i) c.v[i] = k0 + i < n ? cnt[k0 + i] : 0;
+    for (int j = 0; j < kSegPerThread / 4; ++j) {
+        const int i = 4 * j;
+        c.v[i] = k0 + i < n ? q[j].x : 0;
+        c.v[i + 1] = k0 + i + 1 < n ? q[j].y : 0;
+        c.v[i + 2] = k0 + i + 2 < n ? q[j].z : 0;
+        c.v[i + 3] = k0 + i + 3 < n ? q[j].w : 0;
+    }
     return c;
 }
 
@@ -418,9 +448,9 @@ __global__ __launch_bounds__(SAMP == CS_SAMPLER_PLAIN ? kDenseThreads : kDenseNe
     NetFetch<SAMP, NT> nf;
     nf.fetch(a.mlp);
     StepControl* ctrl = a.ctrl;
-    const uint32_t E = ctrl->epoch;
-    const uint64_t step = ctrl->step;
-    const bool layout_ok = ctrl->layout_epoch != E && ctrl->scan_fault_epoch != E;
+    const CtrlView cv = ctrl_view(ctrl);
+    const uint64_t step = cv.step;
+    const bool layout_ok = cv.layout_ok;
     const bool seg = a.n_seg > 0;  // uniform
     int64_t A;
     if (seg) {
@@ -432,7 +462,7 @@ __global__ __launch_bounds__(SAMP == CS_SAMPLER_PLAIN ? kDenseThreads : kDenseNe
     } else {
         nf.store(s_net);
         if constexpr (NET) __syncthreads();
-        A = layout_ok ? (int64_t)ctrl->n_accepted : 0;
+        A = layout_ok ? (int64_t)cv.n_accepted : 0;
     }
     const int64_t seg_len = (int64_t)kChunk * a.chunks_per_block;
     const int64_t stride = (int64_t)gridDim.x * NT;
@@ -502,13 +532,20 @@ static size_t compact_stash_bytes(const StepShape& s) {
     return sizeof(StashPair<double>) * (size_t)compact_pair_blocks(s) * kChunk * (size_t)s.chunks_per_block;
 }
 
+// per pair workgroup its accepted count, with room for the kSegMax counts
+// that seg_load reads
+static int64_t seg_count_len(const StepShape& s) {
+    const int64_t n = compact_pair_blocks(s) + 1;
+    return n > kSegMax ? n : kSegMax;
+}
+
 size_t compact_workspace_bytes(const StepShape& s) {
     size_t b = 0;
     b += al(sizeof(int32_t) * (s.n_cells + 1));
     b += al(sizeof(uint32_t) * 4 * (s.n_cells > 0 ? s.n_cells : 1));
     b += al(sizeof(int32_t) * (s.n_chunks + 1));
     b += al(sizeof(int32_t) * compact_list_len(s) + 8);
-    b += al(sizeof(int32_t) * (compact_pair_blocks(s) + 1));
+    b += al(sizeof(int32_t) * seg_count_len(s));
     b += al(compact_stash_bytes(s) + 16);
     b += 3 * al(8 * (s.n_chunks > 0 ? s.n_chunks : 1));
     b += 3 * al(8 * s.n_collide_blocks);
@@ -528,7 +565,7 @@ void carve_compact_buffers(const Workspace& w, const StepShape& s, CompactBuffer
     b->cell_keys = (uint32_t*)take(sizeof(uint32_t) * 4 * (s.n_cells > 0 ? s.n_cells : 1));
     b->chunk_cell = (int32_t*)take(sizeof(int32_t) * (s.n_chunks + 1));
     b->list = (int32_t*)take(sizeof(int32_t) * compact_list_len(s) + 8);
-    b->seg_count = (int32_t*)take(sizeof(int32_t) * (compact_pair_blocks(s) + 1));
+    b->seg_count = (int32_t*)take(sizeof(int32_t) * seg_count_len(s));
     b->stash = take(compact_stash_bytes(s) + 16);
     b->chunk_prob = (double*)take(8 * (s.n_chunks > 0 ? s.n_chunks : 1));
     b->chunk_clip = (int64_t*)take(8 * (s.n_chunks > 0 ? s.n_chunks : 1));

@@ -50,8 +50,9 @@ struct PrepArgs {
 __global__ __launch_bounds__(kPrepThreads) void k_prep_scan(const PrepArgs a) {
     __shared__ int s_scan[kPrepThreads / 64 + 1];
     __shared__ int s_prefix;
-    const uint32_t E = a.ctrl->epoch;
-    const uint64_t step = a.use_device_step ? a.ctrl->step : a.step;
+    const CtrlView cv = ctrl_view(a.ctrl);
+    const uint32_t E = cv.epoch;
+    const uint64_t step = a.use_device_step ? cv.step : a.step;
     const int64_t base = (int64_t)blockIdx.x * kPrepCells + (int64_t)threadIdx.x * kPrepPerThread;
     int cnt[kPrepPerThread];
     bool bad = false;
@@ -185,9 +186,10 @@ __global__ __launch_bounds__(kChunk) void k_step(const FusedArgs<T> a) {
     const int lane = lane_id();
     const int wave = tid >> 6;
     StepControl* ctrl = a.ctrl;
-    const uint32_t E = ctrl->epoch;
-    const uint64_t step = ctrl->step;
-    const bool layout_ok = ctrl->layout_epoch != E && ctrl->scan_fault_epoch != E;
+    const CtrlView cv = ctrl_view(ctrl);
+    const uint32_t E = cv.epoch;
+    const uint64_t step = cv.step;
+    const bool layout_ok = cv.layout_ok;
     double sum_p = 0.0;
     long long n_clip = 0, n_inv = 0, n_coll = 0;
     CollideSums sums;
@@ -327,10 +329,12 @@ __global__ __launch_bounds__(kFinalThreads) void k_finalize_step(const FinalArgs
     __shared__ long long s_i[4][kFinalThreads / 64];
     const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
     StepControl* ctrl = a.ctrl;
-    const uint32_t E = ctrl->epoch;
-    const uint64_t step = ctrl->step;
-    const int32_t n_pairs_raw = a.n_cells > 0 ? a.pair_off[a.n_cells] : 0;
-    const uint32_t n_acc_raw = ctrl->n_accepted;
+    const CtrlView cv = ctrl_view(ctrl);
+    const uint32_t E = cv.epoch;
+    const uint64_t step = cv.step;
+    const int32_t np_read = a.pair_off[a.n_cells];  // (allocated for n_cells = 0 too)
+    const int32_t n_pairs_raw = a.n_cells > 0 ? np_read : 0;
+    const uint32_t n_acc_raw = cv.n_accepted;
     double sp = 0.0, eb = 0.0, ea = 0.0;
     long long cl = 0, in = 0, co = 0, fb = 0;
     // both partial sets in one pass, four entries of each per thread at a
@@ -364,7 +368,7 @@ __global__ __launch_bounds__(kFinalThreads) void k_finalize_step(const FinalArgs
             fb += vf[k];
         }
     }
-    const bool layout_ok = ctrl->layout_epoch != E && ctrl->scan_fault_epoch != E;
+    const bool layout_ok = cv.layout_ok;
     sp = wave_sum(sp);
     eb = wave_sum(eb);
     ea = wave_sum(ea);
@@ -555,9 +559,9 @@ __global__ __launch_bounds__(kChunk) void k_cell_baseline(const FusedArgs<T> a) 
     const int wave = tid >> 6;
     const int64_t c = blockIdx.x;
     StepControl* ctrl = a.ctrl;
-    const uint32_t E = ctrl->epoch;
-    const uint64_t step = ctrl->step;
-    const bool layout_ok = ctrl->layout_epoch != E && ctrl->scan_fault_epoch != E;
+    const CtrlView cv = ctrl_view(ctrl);
+    const uint64_t step = cv.step;
+    const bool layout_ok = cv.layout_ok;
     double sum_p = 0.0;
     long long n_clip = 0, n_inv = 0, n_coll = 0;
     CollideSums sums;

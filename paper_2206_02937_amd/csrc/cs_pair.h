@@ -17,6 +17,27 @@ struct Particles {
     T *gx, *gy, *gz, *gw;
 };
 
+// The step's control block as a kernel reads it: one copy at the start, so
+// that every field comes back in the same memory round trip (read field by
+// field, with the layout test's short-circuit between the reads, they took
+// several round trips in a row).  Fields that the kernel's own workgroups
+// update later keep the values they had when it started.
+struct CtrlView {
+    uint32_t epoch, n_accepted;
+    uint64_t step;
+    bool layout_ok;  // no layout error and no scan time-out in this step
+};
+
+__device__ __forceinline__ CtrlView ctrl_view(const StepControl* ctrl) {
+    const StepControl c = *ctrl;
+    CtrlView v;
+    v.epoch = c.epoch;
+    v.n_accepted = c.n_accepted;
+    v.step = c.step;
+    v.layout_ok = (c.layout_epoch != c.epoch) & (c.scan_fault_epoch != c.epoch);
+    return v;
+}
+
 struct PairOutcome {
     int32_t ie, ig;  // electron / photon index of the pair
     double x;        // rest-frame photon energy (0 when invalid)
