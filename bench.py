@@ -84,11 +84,12 @@ def source_digest():
     return h.hexdigest()[:16]
 
 
-def counter_record(tag, kernel, workload):
+def counter_record(tag, kernel, workload, launch=None):
     """The fields of the `tag` line ("traffic-record:", "valu-record:") for
-    `kernel` on `workload` in the counter summaries under profiles/; None
-    when no record matches or the kernel sources changed since the counters
-    were taken."""
+    `kernel` on `workload` (and, when given, the launch configuration
+    `launch`, e.g. "ppl1_g16": pairs per lane and chunks per pair block) in
+    the counter summaries under profiles/; None when no record matches or the
+    kernel sources changed since the counters were taken."""
     import glob
 
     digest = source_digest()
@@ -98,26 +99,36 @@ def counter_record(tag, kernel, workload):
                 if not line.startswith(tag):
                     continue
                 kv = dict(t.split("=", 1) for t in line.split()[1:] if "=" in t)
-                if kv.get("kernel") == kernel and kv.get("workload") == workload and kv.get("source_sha") == digest:
+                if (kv.get("kernel") == kernel and kv.get("workload") == workload and kv.get("source_sha") == digest
+                        and (launch is None or kv.get("launch") == launch)):
                     return kv
     return None
 
 
-def traffic_record(kernel, workload):
+def traffic_record(kernel, workload, launch=None):
     """HBM bytes per launch of `kernel` on `workload` from the FETCH_SIZE /
     WRITE_SIZE counters, each scaled by what it reads for a plain device copy
     of known size (the calibration recorded with them); None as above."""
-    kv = counter_record("traffic-record:", kernel, workload)
+    kv = counter_record("traffic-record:", kernel, workload, launch)
     return int(kv["bytes_per_launch"]) if kv else None
 
 
-def valu_roofline(kernel, workload, avg_ms, units):
+def launch_tag(ctx):
+    """The pair kernel's launch configuration as the counter records name it:
+    pairs per lane and chunks per pair block, as the context holds them."""
+    from paper_2206_02937_amd import compton
+
+    return (f"ppl{ctx.get_option(compton.OPT_PAIRS_PER_LANE)}"
+            f"_g{ctx.get_option(compton.OPT_CHUNKS_PER_BLOCK)}")
+
+
+def valu_roofline(kernel, workload, avg_ms, units, launch=None):
     """VALU-issue roofline of `kernel` on `workload`: the SIMD cycles spent
     issuing VALU instructions per launch (4 x SQ_ACTIVE_INST_VALU, summed
     over the chip, from the counter summaries) against every SIMD's cycles
     over the launch's live average duration (1024 SIMDs at 2.4 GHz); with
     the VALU instructions per unit of work.  None without a current record."""
-    kv = counter_record("valu-record:", kernel, workload)
+    kv = counter_record("valu-record:", kernel, workload, launch)
     if kv is None:
         return None
     busy = float(kv["valu_busy_cycles"])
@@ -514,7 +525,7 @@ def mfma_roofline(prec, stage, ks):
             "silu_ceiling_samples_per_s": SILU_CEILING, "samples_per_s": rate, "silu_frac": rate / SILU_CEILING}
 
 
-def pair_roofline(p, run, strategy):
+def pair_roofline(p, run, strategy, launch=None):
     """HBM roofline of the pair kernel from a stage-timed (eager) run:
     algorithmic bytes = every pair's 8 particle values read + per collision
     its stash entry (8 values, 2 indices) and list slot written."""
@@ -527,10 +538,10 @@ def pair_roofline(p, run, strategy):
     b = p.n_pairs * 8 * sb + st["n_collided"] * (8 * sb + 12)
     gbs = b / (ms * 1e-3) / 1e9
     return {"kernel": "k_pair_compact", "bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": gbs / PEAK_HBM_GBS, "traffic": traffic_record("k_pair_compact", p.name), "bytes_per_launch": b,
-            "avg_ms": ms, "units_per_launch": f"{p.n_pairs} pairs, {st['n_collided']} collisions",
-            "working_set_mib": p.nbytes() / 2**20,
-            "valu": valu_roofline("k_pair_compact", p.name, ms, p.n_pairs)}
+            "frac": gbs / PEAK_HBM_GBS, "traffic": traffic_record("k_pair_compact", p.name, launch),
+            "bytes_per_launch": b, "avg_ms": ms, "units_per_launch": f"{p.n_pairs} pairs, {st['n_collided']} collisions",
+            "launch": launch, "working_set_mib": p.nbytes() / 2**20,
+            "valu": valu_roofline("k_pair_compact", p.name, ms, p.n_pairs, launch)}
 
 
 def workload_stage(ctx, p, net, samplers, steps, warmup, autotune_sampler="mlp_bf16", baseline=None,
@@ -560,7 +571,7 @@ def workload_stage(ctx, p, net, samplers, steps, warmup, autotune_sampler="mlp_b
                         "collisions_per_step": r["last_stats"]["n_collided"],
                         "fallback_per_step": r["last_stats"]["n_fallback"]}
     eager = run_steps(ctx, p, "plain", None, steps, warmup)
-    out["roofline"] = pair_roofline(p, eager, strategy)
+    out["roofline"] = pair_roofline(p, eager, strategy, launch_tag(ctx))
     if baseline:
         ctx.set_strategy(baseline)
         ctx.set_chunks_per_block(0)
@@ -677,6 +688,7 @@ def main():
         del e, g, oe, og
     if compton.STRATEGY_NAMES[ctx.get_option(compton.OPT_STRATEGY)] not in ("fused", "compact"):
         args.graph = False  # graphs capture the fused or compact strategy only
+    launch = launch_tag(ctx)  # the pair kernel's configuration, for the counter records
     print(json.dumps({"progress": "timing", "sampler": args.sampler}), flush=True)
     # per-stage timing (eager) for the roofline, then the measured run
     eager = run_steps(ctx, p, args.sampler, net, args.steps, args.warmup)
@@ -734,11 +746,11 @@ def main():
     ms = ms_events - overhead
     achieved = bytes_launch / (ms * 1e-3) / 1e9
     roof = {"kernel": kern, "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": achieved / PEAK_HBM_GBS, "traffic": traffic_record(kern, p.name),
+            "frac": achieved / PEAK_HBM_GBS, "traffic": traffic_record(kern, p.name, launch),
             "bytes_per_launch": bytes_launch, "avg_ms": ms, "avg_ms_events": ms_events,
             "event_overhead_ms": overhead,
-            "units_per_launch": f"{n_pairs} pairs, {acc_per_step} collisions",
-            "valu": valu_roofline(kern, p.name, ms, n_pairs) if kern == "k_pair_compact" else None}
+            "units_per_launch": f"{n_pairs} pairs, {acc_per_step} collisions", "launch": launch,
+            "valu": valu_roofline(kern, p.name, ms, n_pairs, launch) if kern == "k_pair_compact" else None}
     roof_mlp = mfma_roofline("mlp_bf16", stage, ks)
     roof_mlp_fp8 = mfma_roofline("mlp_fp8", stage, ks)
     uneven = power = None

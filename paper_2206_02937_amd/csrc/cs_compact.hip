@@ -462,7 +462,7 @@ __global__ __launch_bounds__(SAMP == CS_SAMPLER_PLAIN ? kDenseThreads : kDenseNe
     } else {
         nf.store(s_net);
         if constexpr (NET) __syncthreads();
-        A = layout_ok ? (int64_t)cv.n_accepted : 0;
+        A = layout_ok ? (int64_t)ctrl->n_accepted : 0;
     }
     const int64_t seg_len = (int64_t)kChunk * a.chunks_per_block;
     const int64_t stride = (int64_t)gridDim.x * NT;

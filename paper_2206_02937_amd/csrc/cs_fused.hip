@@ -50,9 +50,9 @@ struct PrepArgs {
 __global__ __launch_bounds__(kPrepThreads) void k_prep_scan(const PrepArgs a) {
     __shared__ int s_scan[kPrepThreads / 64 + 1];
     __shared__ int s_prefix;
-    const CtrlView cv = ctrl_view(a.ctrl);
-    const uint32_t E = cv.epoch;
-    const uint64_t step = a.use_device_step ? cv.step : a.step;
+    // (not ctrl_view: block 0 may write the step word during this kernel)
+    const uint32_t E = a.ctrl->epoch;
+    const uint64_t step = a.use_device_step ? a.ctrl->step : a.step;
     const int64_t base = (int64_t)blockIdx.x * kPrepCells + (int64_t)threadIdx.x * kPrepPerThread;
     int cnt[kPrepPerThread];
     bool bad = false;
@@ -334,7 +334,7 @@ __global__ __launch_bounds__(kFinalThreads) void k_finalize_step(const FinalArgs
     const uint64_t step = cv.step;
     const int32_t np_read = a.pair_off[a.n_cells];  // (allocated for n_cells = 0 too)
     const int32_t n_pairs_raw = a.n_cells > 0 ? np_read : 0;
-    const uint32_t n_acc_raw = cv.n_accepted;
+    const uint32_t n_acc_raw = ctrl->n_accepted;
     double sp = 0.0, eb = 0.0, ea = 0.0;
     long long cl = 0, in = 0, co = 0, fb = 0;
     // both partial sets in one pass, four entries of each per thread at a

@@ -17,24 +17,23 @@ struct Particles {
     T *gx, *gy, *gz, *gw;
 };
 
-// The step's control block as a kernel reads it: one copy at the start, so
-// that every field comes back in the same memory round trip (read field by
-// field, with the layout test's short-circuit between the reads, they took
-// several round trips in a row).  Fields that the kernel's own workgroups
-// update later keep the values they had when it started.
+// The step's control words that every kernel after the scan reads at its
+// start (epoch, step counter, layout and scan-fault epochs), all in one
+// memory round trip: read one by one, with the layout test's short-circuit
+// between two of them, they took several round trips in a row.
 struct CtrlView {
-    uint32_t epoch, n_accepted;
+    uint32_t epoch;
     uint64_t step;
     bool layout_ok;  // no layout error and no scan time-out in this step
 };
 
 __device__ __forceinline__ CtrlView ctrl_view(const StepControl* ctrl) {
-    const StepControl c = *ctrl;
+    const uint32_t epoch = ctrl->epoch, layout_epoch = ctrl->layout_epoch, fault_epoch = ctrl->scan_fault_epoch;
+    const uint64_t step = ctrl->step;
     CtrlView v;
-    v.epoch = c.epoch;
-    v.n_accepted = c.n_accepted;
-    v.step = c.step;
-    v.layout_ok = (c.layout_epoch != c.epoch) & (c.scan_fault_epoch != c.epoch);
+    v.epoch = epoch;
+    v.step = step;
+    v.layout_ok = (layout_epoch != epoch) & (fault_epoch != epoch);
     return v;
 }
 

@@ -69,6 +69,34 @@ def test_records_are_matched_to_the_kernel_sources(tmp_path, monkeypatch):
     assert bench.traffic_record("k_a", "w1") is None
 
 
+def test_records_are_matched_to_the_launch_configuration(tmp_path, monkeypatch):
+    """A record that names a launch configuration (pairs per lane, chunks
+    per pair block) counts only for that configuration: the autotuner may
+    pick another one, whose traffic the record does not describe."""
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    _fake_tree(tmp_path, "")
+    d = bench.source_digest()
+    (tmp_path / "profiles" / "counters_x.md").write_text(
+        f"traffic-record: kernel=k_a launch=ppl1_g16 workload=w bytes_per_launch=111 source_sha={d}\n"
+        f"traffic-record: kernel=k_a launch=ppl2_g16 workload=w bytes_per_launch=222 source_sha={d}\n"
+        f"valu-record: kernel=k_a launch=ppl2_g16 workload=w valu_busy_cycles=10 valu_insts=5 waves=1 "
+        f"source_sha={d}\n")
+    assert bench.traffic_record("k_a", "w", "ppl1_g16") == 111
+    assert bench.traffic_record("k_a", "w", "ppl2_g16") == 222
+    assert bench.traffic_record("k_a", "w", "ppl1_g32") is None
+    assert bench.valu_roofline("k_a", "w", 1.0, 1, "ppl1_g16") is None
+    assert bench.valu_roofline("k_a", "w", 1.0, 1, "ppl2_g16")["valu_busy_cycles_per_launch"] == 10
+    ctx = SimpleNamespace(get_option=lambda o: {bench_opt("OPT_PAIRS_PER_LANE"): 2,
+                                                bench_opt("OPT_CHUNKS_PER_BLOCK"): 16}[o])
+    assert bench.launch_tag(ctx) == "ppl2_g16"
+
+
+def bench_opt(name):
+    from paper_2206_02937_amd import compton
+
+    return getattr(compton, name)
+
+
 def test_valu_roofline_arithmetic(tmp_path, monkeypatch):
     """Busy SIMD cycles per launch against 1024 SIMDs x 2.4 GHz x the live
     duration; instructions per unit = wavefront instructions x 64 / units."""
@@ -108,7 +136,7 @@ def test_pair_roofline_bytes(monkeypatch):
     """Algorithmic bytes of the pair kernel: 8 particle values per pair,
     plus per collision its stash entry's 8 values and 12 bytes of indices
     and list slot; the time is the pair stage minus an empty bracket."""
-    monkeypatch.setattr(bench, "traffic_record", lambda k, w: None)
+    monkeypatch.setattr(bench, "traffic_record", lambda *a: None)
     monkeypatch.setattr(bench, "valu_roofline", lambda *a: None)
     p = SimpleNamespace(e={"x": np.zeros(1, np.float32)}, n_pairs=1 << 22, name="w", nbytes=lambda: 2**27)
     run = {"last_stats": {"n_collided": 100000}, "stage_ms": {"pair": 0.046, "compact": 0.005}}
